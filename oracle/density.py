@@ -1,0 +1,138 @@
+"""Oracle: reconstruction, extraction and the whole density-matrix pipeline.
+
+Test infrastructure only: see the package docstring.
+
+Definitions followed:
+* Eq.(3): rho~ = X r^T, so the estimate of P_mn is X[m, :] r[n, :]^T =
+  s_n X[m, c(n)] (only the probe of n's colour is nonzero at n);
+* Eq.(6): X = Phi F = sum_j Q_j F_j, F_j the j-th block of rows of F;
+* the text around Eq.(2) and Fig.1(a): P is read off only on the pairs closer
+  than the cutoff (the colouring's conflict graph plus the diagonal);
+* the orbital energy sum E = Tr(H rho) quoted with Fig.2(a).
+
+Readings:
+* the raw estimate is not symmetric; by default P <- (P + P^T)/2 on the
+  (symmetric) pattern. The largest raw asymmetry is reported;
+* E_band = sum over entries (m, n) present in both H and the pattern of
+  H_mn P_mn; trace = sum_m P_mm; no value is dropped by a threshold.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .lanczos import REORTH_FULL, assemble_T, block_lanczos
+from .subspace import contraction, eig_subspace, fermi
+
+
+def reconstruct_X(Q: list, F: np.ndarray) -> np.ndarray:
+    b = Q[0].shape[1]
+    X = np.zeros_like(Q[0])
+    for j, Qj in enumerate(Q):
+        X += Qj @ F[j * b:(j + 1) * b, :]
+    return X
+
+
+def pattern_rows(p_row_ptr: np.ndarray) -> np.ndarray:
+    n = p_row_ptr.shape[0] - 1
+    return np.repeat(np.arange(n), np.diff(p_row_ptr))
+
+
+def gather_raw(X: np.ndarray, color, sign, p_row_ptr, p_col) -> np.ndarray:
+    rows = pattern_rows(p_row_ptr)
+    cols = p_col.astype(np.int64)
+    return sign[cols].astype(np.float64) * X[rows, color[cols]]
+
+
+def symmetrize(p_raw: np.ndarray, p_row_ptr, p_col) -> np.ndarray:
+    """(P + P^T)/2 on a symmetric pattern (looked up by binary search)."""
+    rows = pattern_rows(p_row_ptr)
+    cols = p_col.astype(np.int64)
+    n = p_row_ptr.shape[0] - 1
+    key = rows * n + cols
+    tkey = cols * n + rows
+    pos = np.searchsorted(key, tkey)       # rows sorted, cols sorted within rows
+    if np.any(pos >= key.size) or np.any(key[np.minimum(pos, key.size - 1)] != tkey):
+        raise ValueError("pattern is not symmetric")
+    return 0.5 * (p_raw + p_raw[pos])
+
+
+def trace_of(p_val, p_row_ptr, p_col) -> float:
+    rows = pattern_rows(p_row_ptr)
+    return float(np.sum(p_val[rows == p_col]))
+
+
+def band_energy(H, p_val, p_row_ptr, p_col) -> float:
+    """sum over (m,n) in both patterns of H_mn P_mn."""
+    Hc = H.tocsr()
+    rows = pattern_rows(p_row_ptr)
+    h = np.asarray(Hc[rows, p_col.astype(np.int64)]).ravel()
+    return float(np.sum(h * p_val))
+
+
+def density_matrix(H, color, sign, n_colors, mu, kT, depth, p_row_ptr, p_col,
+                   spin_deg=2.0, reorth=REORTH_FULL, cholqr2=True, symmetrize_p=True,
+                   eig_driver="evd"):
+    """The whole CSS estimate of P on the pattern; returns a dict of results."""
+    color = np.asarray(color)
+    sign = np.asarray(sign)
+    lz = block_lanczos(H, color, sign, n_colors, depth, reorth=reorth, cholqr2=cholqr2)
+    T = assemble_T(lz.A, lz.B)
+    lam, U = eig_subspace(T, driver=eig_driver)
+    F, trace_k, e_k = contraction(lam, U, lz.b0, mu, kT, spin_deg)
+    X = reconstruct_X(lz.Q, F)
+    p_raw = gather_raw(X, color, sign, p_row_ptr, p_col)
+    p_sym = symmetrize(p_raw, p_row_ptr, p_col)
+    p_val = p_sym if symmetrize_p else p_raw
+    return {
+        "p_val": p_val, "p_raw": p_raw, "X": X, "F": F, "lam": lam, "T": T,
+        "lanczos": lz, "v_eff": lz.v_eff, "breakdown": lz.breakdown,
+        "trace": trace_of(p_val, p_row_ptr, p_col),
+        "e_band": band_energy(H, p_val, p_row_ptr, p_col),
+        "trace_krylov": trace_k, "e_band_krylov": e_k,
+        "asym_max": float(np.max(np.abs(p_raw - p_sym))) if p_raw.size else 0.0,
+    }
+
+
+# ---- references used to separate the method error from the parity error ----
+
+def dense_fermi_dm(H, mu, kT, spin_deg=2.0) -> np.ndarray:
+    """g f(H) from dense diagonalisation (Eq.(1) with S = I)."""
+    Hd = H.toarray() if hasattr(H, "toarray") else np.asarray(H)
+    lam, U = np.linalg.eigh(Hd)
+    return (U * (spin_deg * fermi(lam, mu, kT))[None, :]) @ U.T
+
+
+def css_exact_X(P_dense: np.ndarray, color, sign, n_colors) -> np.ndarray:
+    """X = g f(H) r with no Krylov truncation (Eq.(2)-(3) alone)."""
+    from .probes import probe_block
+    return P_dense @ probe_block(np.asarray(color), np.asarray(sign), n_colors)
+
+
+def mu_midgap_dense(H, n_electrons: int, spin_deg=2.0) -> float:
+    Hd = H.toarray() if hasattr(H, "toarray") else np.asarray(H)
+    eps = np.linalg.eigvalsh(Hd)
+    K = int(round(n_electrons / spin_deg))
+    return 0.5 * (eps[K - 1] + eps[K])
+
+
+def krylov_weights(U: np.ndarray, b0: np.ndarray) -> np.ndarray:
+    b = b0.shape[0]
+    return (b0[:, None] ** 2 * U[:b, :] ** 2).sum(axis=0)
+
+
+def mu_krylov_bisection(lam: np.ndarray, w: np.ndarray, n_electrons: float, kT: float,
+                        spin_deg=2.0, tol=1e-13) -> float:
+    """mu at which the Krylov quadrature trace sum_k g f(lambda_k) w_k equals N_e.
+
+    Used to choose mu for systems too large for dense diagonalisation; the
+    trace is monotone in mu, so plain bisection on [min lambda - 50 kT,
+    max lambda + 50 kT] converges.
+    """
+    lo, hi = float(lam.min()) - 50 * kT, float(lam.max()) + 50 * kT
+    while hi - lo > tol * max(1.0, abs(lo), abs(hi)):
+        mid = 0.5 * (lo + hi)
+        if np.sum(spin_deg * fermi(lam, mid, kT) * w) < n_electrons:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)

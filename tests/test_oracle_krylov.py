@@ -1,0 +1,250 @@
+"""Pins of the oracle's probes, block Lanczos, subspace solve and pipeline (CPU only)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import density as D
+from oracle.coloring import greedy_color
+from oracle.lanczos import assemble_T, block_lanczos
+from oracle.pattern import conflict_pattern
+from oracle.probes import color_counts, first_block, probe_block, probe_signs, splitmix64
+from oracle.subspace import contraction, eig_subspace, fermi
+from paper_2605_20918_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- probes
+
+def test_splitmix64_published_outputs():
+    with open(os.path.join(GOLDEN, "splitmix64.json")) as f:
+        g = json.load(f)
+    for vec in g["vectors"]:
+        outs = vec.get("outputs") or [int(h, 16) for h in vec["outputs_hex"]]
+        got = splitmix64(vec["seed"], np.arange(len(outs), dtype=np.uint64))
+        assert [int(x) for x in got] == outs
+
+
+def test_signs_balanced_and_ones_flag():
+    s = probe_signs(100000, seed=99)
+    assert set(np.unique(s)) == {-1, 1}
+    assert abs(int(s.sum())) < 2000
+    assert np.all(probe_signs(10, 99, all_ones=True) == 1)
+
+
+def test_first_block_exact_qr():
+    rng = np.random.default_rng(0)
+    color = rng.integers(0, 7, size=200).astype(np.int32)
+    color[:7] = np.arange(7)
+    sign = probe_signs(200, 5)
+    Q1, b0 = first_block(color, sign, 7)
+    assert np.array_equal(Q1.T @ Q1 == np.eye(7), np.ones((7, 7), bool)) or np.allclose(Q1.T @ Q1, np.eye(7), atol=1e-15)
+    assert np.allclose(Q1 * b0[None, :], probe_block(color, sign, 7), atol=1e-15)
+    assert color_counts(color, 7).sum() == 200
+
+
+# ---------------------------------------------------------------- helpers
+
+def small_water(M=27, seed=11, r_cut=6.0):
+    ws = synth.water_system(M, seed)
+    H = ws.H.to_scipy()
+    rp, col, deg = conflict_pattern(ws.orb_xyz, ws.box, r_cut)
+    color, b = greedy_color(rp, col, deg)
+    sign = probe_signs(ws.n, seed)
+    return ws, H, rp, col, color, b, sign
+
+
+# ---------------------------------------------------------------- Lanczos
+
+@pytest.mark.parametrize("reorth", ["full", "local", "none"])
+def test_krylov_polynomial_exactness(reorth):
+    # Phi T^p E_1 B_0 = H^p r for every p <= v_eff - 1 (exact arithmetic)
+    ws, H, rp, col, color, b, sign = small_water(M=64, seed=20919)
+    lz = block_lanczos(H, color, sign, b, depth=4, reorth=reorth)
+    assert lz.v_eff == 4
+    Phi = np.hstack(lz.Q)
+    T = assemble_T(lz.A, lz.B)
+    r = probe_block(color, sign, b)
+    E1B0 = np.zeros((T.shape[0], b))
+    E1B0[:b, :] = np.diag(lz.b0)
+    Hp_r, Tp = r.copy(), E1B0.copy()
+    for p in range(lz.v_eff):
+        ref = Hp_r
+        got = Phi @ Tp
+        assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref)), p
+        Hp_r = H @ Hp_r
+        Tp = T @ Tp
+
+
+def test_three_term_relation_and_orthonormality():
+    ws, H, rp, col, color, b, sign = small_water(M=64, seed=20919)
+    lz = block_lanczos(H, color, sign, b, depth=5)
+    Phi = np.hstack(lz.Q)
+    T = assemble_T(lz.A, lz.B)
+    assert np.max(np.abs(Phi.T @ Phi - np.eye(Phi.shape[1]))) < 1e-13
+    assert np.max(np.abs(Phi.T @ (H @ Phi) - T)) < 1e-12
+    assert np.allclose(T, T.T, atol=0)
+    for B in lz.B:
+        assert np.allclose(B, np.triu(B)) and np.all(np.diag(B) > 0)
+    lam = np.linalg.eigvalsh(T)
+    ev = np.linalg.eigvalsh(H.toarray())
+    assert lam.min() >= ev.min() - 1e-12 and lam.max() <= ev.max() + 1e-12
+
+
+def test_one_block_when_every_orbital_has_its_own_colour():
+    # b = N: Q_1 = diag(s) (colour(i) = i), so T = A_1 = S H S and depth is capped at 1
+    n = 30
+    rng = np.random.default_rng(1)
+    xyz = rng.uniform(0, 1, size=(n, 3))
+    H = synth.random_symmetric_csr(xyz, np.zeros(3), 10.0, seed=2).to_scipy()
+    rp, col, deg = conflict_pattern(xyz, np.zeros(3), 10.0)
+    color, b = greedy_color(rp, col, deg)
+    sign = probe_signs(n, 4)
+    lz = block_lanczos(H, color, sign, b, depth=5)
+    assert lz.v_eff == 1
+    S = np.diag(sign.astype(float))
+    assert np.allclose(lz.A[0], S @ H.toarray() @ S, atol=1e-15)
+
+
+def test_breakdown_on_scaled_identity():
+    n = 40
+    xyz, box = synth.chain_1d(n, 1.0)
+    rp, col, deg = conflict_pattern(xyz, box, 1.5)
+    color, b = greedy_color(rp, col, deg)
+    H = sp.identity(n, format="csr") * -0.3
+    lz = block_lanczos(H, color, probe_signs(n, 1), b, depth=6)
+    assert lz.v_eff == 1 and lz.breakdown
+
+
+# ---------------------------------------------------------------- subspace
+
+def test_fermi_closed_forms():
+    mu, kT = -0.4, 0.01
+    assert fermi(np.array([mu]), mu, kT)[0] == 0.5
+    x = np.array([mu + 50, mu - 50, mu + 1e5, mu - 1e5])
+    f = fermi(x, mu, kT)
+    assert np.all(np.isfinite(f)) and f[1] == 1.0 and f[3] == 1.0 and f[2] == 0.0
+    assert 0 < f[0] < 1e-300 or f[0] == 0.0
+    t = np.linspace(-0.3, 0.3, 101)
+    assert np.allclose(fermi(mu + t, mu, kT) + fermi(mu - t, mu, kT), 1.0, atol=1e-15)
+    assert np.allclose(fermi(mu + t, mu, kT), 1.0 / (np.exp(t / kT) + 1.0), rtol=1e-14)
+
+
+def test_contraction_basis_invariant_and_trace():
+    ws, H, rp, col, color, b, sign = small_water(M=64, seed=20919)
+    lz = block_lanczos(H, color, sign, b, depth=5)
+    T = assemble_T(lz.A, lz.B)
+    mu, kT = -0.41, 0.01
+    F1, tr1, e1 = contraction(*eig_subspace(T, "evd"), lz.b0, mu, kT)
+    F2, tr2, e2 = contraction(*eig_subspace(T, "evr"), lz.b0, mu, kT)
+    assert np.max(np.abs(F1 - F2)) < 1e-12
+    assert abs(tr1 - tr2) < 1e-10 and abs(e1 - e2) < 1e-10
+    # Tr(B_0 F_1) is the Krylov trace
+    assert abs(np.trace(np.diag(lz.b0) @ F1[:b, :]) - tr1) < 1e-10
+
+
+# ---------------------------------------------------------------- pipeline
+
+def test_pipeline_reduces_to_dense_when_b_equals_n():
+    n = 24
+    rng = np.random.default_rng(8)
+    xyz = rng.uniform(0, 1, size=(n, 3))
+    H = synth.random_symmetric_csr(xyz, np.zeros(3), 10.0, seed=9).to_scipy()
+    rp, col, deg = conflict_pattern(xyz, np.zeros(3), 10.0)
+    color, b = greedy_color(rp, col, deg)
+    sign = probe_signs(n, 3)
+    mu, kT = 0.05, 0.2
+    r = D.density_matrix(H, color, sign, b, mu, kT, 3, rp, col)
+    P = D.dense_fermi_dm(H, mu, kT)
+    assert np.max(np.abs(r["p_val"] - P[D.pattern_rows(rp), col])) < 1e-12
+    assert np.max(np.abs(r["p_raw"] - r["p_val"])) < 1e-12
+
+
+def test_pipeline_equals_css_exact_when_krylov_space_is_exhausted():
+    # 1D chain with b = 3 colours and N = 3 * 8: depth 8 spans the whole space
+    n, a, r_cut = 24, 1.0, 2.0
+    xyz, box = synth.chain_1d(n, a)
+    H = synth.random_symmetric_csr(xyz, box, 1.0, seed=21, off_scale=0.3).to_scipy()
+    rp, col, deg = conflict_pattern(xyz, box, r_cut)
+    color, b = greedy_color(rp, col, deg)
+    assert b == 3
+    sign = probe_signs(n, 12)
+    mu, kT = 0.0, 0.1
+    r = D.density_matrix(H, color, sign, b, mu, kT, 8, rp, col, reorth="full")
+    assert r["v_eff"] == 8
+    P = D.dense_fermi_dm(H, mu, kT)
+    Xe = D.css_exact_X(P, color, sign, b)
+    pe = D.gather_raw(Xe, color, sign, rp, col)
+    assert np.max(np.abs(r["p_raw"] - pe)) < 1e-11
+
+
+def test_pipeline_closed_form_for_scaled_identity():
+    n, c = 36, -0.37
+    xyz, box = synth.chain_1d(n, 1.0)
+    rp, col, deg = conflict_pattern(xyz, box, 2.0)
+    color, b = greedy_color(rp, col, deg)
+    H = sp.identity(n, format="csr") * c
+    mu, kT = -0.4, 0.01
+    r = D.density_matrix(H, color, probe_signs(n, 2), b, mu, kT, 5, rp, col)
+    expect = np.where(D.pattern_rows(rp) == col, 2.0 * fermi(np.array([c]), mu, kT)[0], 0.0)
+    assert r["v_eff"] == 1
+    assert np.max(np.abs(r["p_val"] - expect)) < 1e-14
+
+
+def test_pipeline_invariants_on_water():
+    ws, H, rp, col, color, b, sign = small_water(M=64, seed=20919)
+    mu = D.mu_midgap_dense(H, ws.n_electrons)
+    r = D.density_matrix(H, color, sign, b, mu, 0.01, 40, rp, col)
+    assert r["v_eff"] == ws.n // b
+    # exact-arithmetic identities survive symmetrisation
+    assert abs(r["trace"] - r["trace_krylov"]) < 1e-10 * ws.n
+    assert abs(r["e_band"] - r["e_band_krylov"]) < 1e-10 * ws.n
+    # symmetric after symmetrisation (bitwise)
+    key = {(i, j): v for i, j, v in zip(D.pattern_rows(rp).tolist(), col.tolist(), r["p_val"].tolist())}
+    assert all(key[(j, i)] == v for (i, j), v in key.items())
+    # trace close to the electron count (mu mid-gap, warm electrons)
+    assert abs(r["trace"] - ws.n_electrons) < 0.01 * ws.n_electrons
+
+
+def test_mu_bisection_on_krylov_trace():
+    ws, H, rp, col, color, b, sign = small_water(M=64, seed=20919)
+    mu_d = D.mu_midgap_dense(H, ws.n_electrons)
+    lz = block_lanczos(H, color, sign, b, 40)
+    lam, U = eig_subspace(assemble_T(lz.A, lz.B))
+    w = D.krylov_weights(U, lz.b0)
+    assert abs(w.sum() - ws.n) < 1e-9 * ws.n          # sum_k w_k = sum_c n_c = N
+    mu_k = D.mu_krylov_bisection(lam, w, ws.n_electrons, 0.01)
+    _, tr, _ = contraction(lam, U, lz.b0, mu_k, 0.01)
+    assert abs(tr - ws.n_electrons) < 1e-8
+    ev = np.linalg.eigvalsh(H.toarray())
+    K = ws.n_electrons // 2
+    assert ev[K - 1] - 0.05 < mu_k < ev[K] + 0.05 and abs(mu_k - mu_d) < 0.05
+
+
+# ---------------------------------------------------------------- planted mistakes
+
+def test_planted_mistakes_are_caught(monkeypatch):
+    """Each pin above must fail for a plausible slip in the oracle."""
+    import oracle.lanczos as L
+    import oracle.subspace as S
+    ws, H, rp, col, color, b, sign = small_water(M=64, seed=20919)
+
+    # (1) dropped Q_{j-1} B_{j-1}^T term: three-term relation breaks
+    lz = L.block_lanczos(H, color, sign, b, 4, reorth="none", cholqr2=False)
+    T = assemble_T(lz.A, lz.B)
+    Tbad = T.copy()
+    Tbad[:b, b:2 * b] = 0.0
+    Phi = np.hstack(lz.Q)
+    assert np.max(np.abs(Phi.T @ (H @ Phi) - Tbad)) > 1e-3
+
+    # (2) transposed B in T: Phi^T H Phi no longer matches
+    Tt = assemble_T(lz.A, [B.T for B in lz.B])
+    assert np.max(np.abs(Phi.T @ (H @ Phi) - Tt)) > 1e-3
+
+    # (3) wrong sign in the Fermi function: closed form f(mu+t)=1/(e^{t/kT}+1) fails
+    monkeypatch.setattr(S, "fermi", lambda x, mu, kT: 1.0 / (1.0 + np.exp(-(np.asarray(x) - mu) / kT)))
+    t = np.linspace(-0.1, 0.1, 5)
+    assert not np.allclose(S.fermi(-0.4 + t, -0.4, 0.01), 1.0 / (np.exp(t / 0.01) + 1.0))
