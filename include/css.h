@@ -1,0 +1,209 @@
+/*
+ * css.h -- C ABI of the chromatic-superposition-state (CSS) density-matrix
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * The method (arXiv 2605.20918) estimates the sparse finite-temperature
+ * density matrix P = g f(H), f the Fermi-Dirac function of Eq.(1), on the
+ * pairs of orbitals closer than a cutoff:
+ *   1. colour the orbitals so that orbitals closer than the cutoff differ
+ *      (greedy Welsh-Powell multicolouring, text around Eq.(2), Fig.1(b));
+ *   2. build one +-1 probe per colour (Eq.(2), Fig.1(c));
+ *   3. project H onto the block Krylov space of the probes by block Lanczos
+ *      (text after Eq.(4));
+ *   4. evaluate f exactly in that small space by diagonalisation (Eqs.(5)-(7))
+ *      and read P_mn = s_n X[m, colour(n)] off X = f(H) r (Eqs.(3), (6)).
+ *
+ * Conventions for every entry point
+ *   - Arrays documented "device" are device memory the caller owns (for
+ *     example torch tensors); the library never allocates, frees or keeps them.
+ *     Arrays documented "host" are ordinary host memory.
+ *   - Scratch memory comes only from the caller's workspace `ws` of
+ *     `ws_bytes` bytes (device, 256-byte aligned); query its size with
+ *     css_workspace_size. The library keeps no allocation between calls.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued on it in order; entry points that return host scalars
+ *     synchronise that stream before returning.
+ *   - Every entry point returns a css_status and never throws or aborts. On an
+ *     error the outputs are unspecified. A Lanczos breakdown after the first
+ *     block is not an error: it is reported through css_info.
+ *   - Results are deterministic: the same inputs give bitwise identical
+ *     outputs (no floating-point atomics in any reduction).
+ */
+#ifndef CSS_H
+#define CSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t css_status;
+enum {
+    CSS_OK = 0,
+    CSS_E_ARG = 1,            /* bad scalar argument or NULL pointer */
+    CSS_E_CSR = 2,            /* malformed CSR (row pointers, column range) or colours */
+    CSS_E_WORKSPACE = 3,      /* ws_bytes smaller than css_workspace_size reports */
+    CSS_E_DEVICE = 4,         /* HIP runtime error */
+    CSS_E_BREAKDOWN_AT_1 = 5, /* the first Lanczos block already degenerates */
+    CSS_E_NONFINITE = 6,      /* NaN or Inf in H or in the projected matrix */
+    CSS_E_EIG = 7,            /* the subspace eigensolver failed */
+    CSS_E_UNSUPPORTED = 8,    /* option or size outside what is implemented */
+    CSS_E_CAPACITY = 9        /* an output array is smaller than the result */
+};
+
+/* value types of css_csr.val */
+enum { CSS_F64 = 0, CSS_F32 = 1 };
+
+/* flags (bitwise or) for css_block_lanczos / css_density_matrix / css_build_probes */
+#define CSS_PREC_FP64      0x0u   /* SpMM and block products in FP64 */
+#define CSS_PREC_FP32      0x1u   /* SpMM and block products in FP32 (FP32 accumulation) */
+#define CSS_PREC_BF16X3    0x2u   /* reserved: split bf16 hi+lo products */
+#define CSS_PREC_MASK      0x3u
+#define CSS_BASIS_STORED   0x0u   /* keep every Krylov block for the reconstruction */
+#define CSS_BASIS_TWOPASS  0x4u   /* store no basis; regenerate it in a second pass */
+#define CSS_REORTH_NONE    0x0u
+#define CSS_REORTH_LOCAL   0x8u   /* second Gram-Schmidt pass against Q_{j-1}, Q_j */
+#define CSS_REORTH_FULL    0x10u  /* second Gram-Schmidt pass against Q_1..Q_j */
+#define CSS_REORTH_MASK    0x18u
+#define CSS_CHOLQR2        0x20u  /* repeat the Cholesky QR once */
+#define CSS_SYMMETRIZE     0x40u  /* return (P + P^T)/2 instead of the raw estimate */
+#define CSS_SIGNS_ONES     0x80u  /* probes with all signs +1 instead of random signs */
+
+/* workspace query selectors */
+enum { CSS_ENTRY_COLOR = 0, CSS_ENTRY_LANCZOS = 1, CSS_ENTRY_DENSITY = 2, CSS_ENTRY_SPMM = 3 };
+
+/* Sparse symmetric H in CSR form; all pointers device. Column indices must be
+ * sorted within each row; row_ptr[0] = 0, row_ptr[n] = nnz < 2^31. */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int32_t* row_ptr;   /* device, n+1 */
+    const int32_t* col;       /* device, nnz */
+    const void* val;          /* device, nnz, of type val_dtype */
+    int32_t val_dtype;        /* CSS_F64 or CSS_F32 */
+} css_csr;
+
+/* Diagnostics filled by css_block_lanczos / css_density_matrix (host struct). */
+typedef struct {
+    int32_t depth_eff;        /* Krylov blocks actually built (v_eff) */
+    int32_t n_colors;         /* b */
+    int32_t breakdown;        /* 1 if the recurrence stopped early on a degenerate block */
+    int32_t reserved;
+    double min_diag_r;        /* smallest diagonal of the Cholesky factors of W^T W */
+    double asym_max;          /* max |P_raw - (P_raw + P_raw^T)/2| on the pattern */
+    double trace_krylov;      /* sum_k g f(lambda_k) w_k (Krylov quadrature of Tr P) */
+    double e_band_krylov;     /* sum_k lambda_k g f(lambda_k) w_k */
+    double t_phase_ms[6];     /* lanczos, eig, contraction, reconstruction, gather, total */
+} css_info;
+
+/*
+ * css_color -- conflict graph and greedy colouring (text around Eq.(2), Fig.1(b)).
+ *   Orbitals m, n conflict when the minimum-image distance between their
+ *   centres is within r_cut: d^2 = (dx*dx + dy*dy) + dz*dz <= r_cut*r_cut with
+ *   dx -= L*rint(dx/L) in periodic directions (L = box[k] > 0), rounded
+ *   without fused multiply-add. The pattern of P is this graph plus the
+ *   diagonal. Colours follow first fit along the Welsh-Powell order (degree
+ *   descending, index ascending); they are bitwise equal to the sequential
+ *   greedy colouring.
+ *   xyz        device, n x 3 doubles, row-major orbital centres
+ *   n          number of orbitals (>= 1)
+ *   box        host, 3 doubles: periodic box edges, 0 = open direction
+ *   r_cut      cutoff distance (> 0)
+ *   color      device int32[n] out (may be NULL in a size query)
+ *   n_colors   host out: number of colours b
+ *   p_row_ptr  device int64[n+1] out: pattern row pointers
+ *   p_col      device int32[*p_nnz] out: sorted pattern columns; NULL = size query
+ *              (then only p_row_ptr and *p_nnz are produced)
+ *   p_nnz      host in/out: in = capacity of p_col, out = nnz of the pattern;
+ *              CSS_E_CAPACITY if the capacity is too small
+ *   rounds     host out (may be NULL): parallel colouring rounds used
+ */
+css_status css_color(const double* xyz, int32_t n, const double box[3], double r_cut,
+                     int32_t* color, int32_t* n_colors,
+                     int64_t* p_row_ptr, int32_t* p_col, int64_t* p_nnz, int32_t* rounds,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * css_build_probes -- signs and colour counts of the CSS probes (Eq.(2), Fig.1(c)).
+ *   Probe c is r_c[m] = sign[m] for colour(m) = c, 0 otherwise. sign[m] = +1
+ *   when the top bit of the (m+1)-th SplitMix64 output from state `seed` is 0,
+ *   else -1 (all +1 with CSS_SIGNS_ONES).
+ *   color        device int32[n], values in [0, n_colors)
+ *   sign         device int8[n] out
+ *   color_count  device int32[n_colors] out: orbitals per colour
+ *   Returns CSS_E_CSR if a colour is out of range or a colour owns no orbital
+ *   (synchronises the stream to check).
+ */
+css_status css_build_probes(const int32_t* color, int32_t n, int32_t n_colors, uint64_t seed,
+                            uint32_t flags, int8_t* sign, int32_t* color_count, void* stream);
+
+/*
+ * css_spmm -- W = H V for a dense block V of b columns (the sparse-dense
+ *   product the whole method reduces to, text after Eq.(10)).
+ *   V, W  device, n x ld row-major, element type = H's value type; ld >= b,
+ *         ld a multiple of 16 (css_block_ld(b) gives the library's choice)
+ *   Columns b..ld-1 of W are H times those columns of V (zero when V's are).
+ *   H is not validated here (css_block_lanczos and css_density_matrix do).
+ */
+css_status css_spmm(const css_csr* H, const void* V, void* W, int32_t b, int32_t ld,
+                    void* stream);
+
+/*
+ * css_block_lanczos -- block Lanczos projection (text after Eq.(4)).
+ *   Builds Q_1 = r B_0^-1 from the probes and runs the block recurrence
+ *   H Q_j = Q_{j-1} B_{j-1}^T + Q_j A_j + Q_{j+1} B_j for
+ *   j = 1..min(depth, floor(n/b)), stopping early if W^T W is not positive
+ *   definite or min diag R <= 1e-10 ||H||_inf.
+ *   A  device, depth*b*b doubles out: A_j row-major at A + (j-1)*b*b
+ *   B  device, (depth-1)*b*b doubles out: B_j (upper triangular) at B + (j-1)*b*b
+ *   info host out (may be NULL).
+ *   Only the first info->depth_eff blocks of A (depth_eff-1 of B) are defined.
+ */
+css_status css_block_lanczos(const css_csr* H, const int32_t* color, const int8_t* sign,
+                             int32_t n_colors, int32_t depth, uint32_t flags,
+                             double* A, double* B, css_info* info,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * css_density_matrix -- the CSS estimate of P = g f(H) on a pattern
+ *   (Eqs.(1)-(7) with S = I). Block Lanczos, exact diagonalisation of the
+ *   block-tridiagonal projected H, F = U diag(g f(lambda)) U[0:b,:]^T B_0,
+ *   X = [Q_1..Q_k] F, then P_mn = sign[n] X[m, colour(n)] on the pattern,
+ *   symmetrised with CSS_SYMMETRIZE.
+ *   mu, kT      chemical potential and temperature (kT > 0), units of H
+ *   spin_deg    g (2 for closed shells)
+ *   p_row_ptr, p_col, p_nnz  device pattern (e.g. from css_color); must be
+ *               symmetric with sorted rows when CSS_SYMMETRIZE is set
+ *   p_val       device double[p_nnz] out
+ *   e_band      host out: sum over entries in both H and the pattern of H_mn P_mn
+ *   trace       host out: sum_m P_mm
+ *   info        host out (may be NULL)
+ */
+css_status css_density_matrix(const css_csr* H, const int32_t* color, const int8_t* sign,
+                              int32_t n_colors, double mu, double kT, int32_t depth,
+                              double spin_deg, const int64_t* p_row_ptr, const int32_t* p_col,
+                              int64_t p_nnz, uint32_t flags, double* p_val,
+                              double* e_band, double* trace, css_info* info,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * css_workspace_size -- bytes of workspace an entry point needs.
+ *   entry  CSS_ENTRY_*; the other arguments as they will be passed
+ *   (nnz = H's nnz, or for CSS_ENTRY_COLOR unused).
+ */
+css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, int32_t n_colors,
+                              int32_t depth, uint32_t flags, size_t* bytes);
+
+/* Leading dimension the library uses for blocks of b columns. */
+int32_t css_block_ld(int32_t n_colors);
+
+/* Static text for a status code. */
+const char* css_status_string(css_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSS_H */

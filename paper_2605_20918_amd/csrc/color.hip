@@ -1,0 +1,460 @@
+// Conflict graph (= sparsity pattern of P) and greedy multicolouring on the GPU.
+//
+// Method: the text around Eq.(2) colours orbitals greedily in the manner of
+// Welsh and Powell so that any two orbitals closer than the cutoff differ
+// (Fig.1(b)). The sequential algorithm visits orbitals by degree descending
+// (ties: smaller index first) and gives each the smallest colour not used by
+// its already coloured neighbours. That result is reproduced exactly in
+// parallel by Jones-Plassmann rounds with the Welsh-Powell rank as priority:
+// an orbital is coloured as soon as all its higher-priority neighbours are,
+// taking the smallest colour they do not use -- exactly the set the
+// sequential sweep would have seen at that point.
+//
+// The distance predicate is evaluated with separately rounded products and
+// sums (no fused multiply-add) so that every conflict decision is identical
+// to a plain IEEE evaluation of ((dx*dx + dy*dy) + dz*dz) <= r_cut*r_cut.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <vector>
+
+#include "css_common.h"
+
+namespace css {
+namespace {
+
+constexpr int kMaxRowLds = 8192;     // longest pattern row the LDS row sort handles
+
+struct Grid {
+    int nc[3];          // cells per dimension
+    double w[3];        // cell width (>= r_cut)
+    double lo[3];       // origin (open directions) / 0 (periodic)
+    double L[3];        // box edge, 0 = open
+};
+
+__device__ __forceinline__ int cell_coord(double x, int k, const Grid& g) {
+    double t;
+    if (g.L[k] > 0.0) {
+        t = x - g.L[k] * floor(x / g.L[k]);
+    } else {
+        t = x - g.lo[k];
+    }
+    int c = static_cast<int>(floor(t / g.w[k]));
+    return c < 0 ? 0 : (c >= g.nc[k] ? g.nc[k] - 1 : c);
+}
+
+__device__ __forceinline__ bool conflict(const double* __restrict__ xyz, int64_t m, int64_t n,
+                                         const Grid& g, double rc2) {
+#pragma clang fp contract(off)
+    double d[3];
+    for (int k = 0; k < 3; ++k) {
+        double dk = xyz[3 * n + k] - xyz[3 * m + k];
+        if (g.L[k] > 0.0) {
+            double q = rint(dk / g.L[k]);
+            double s = g.L[k] * q;
+            dk = dk - s;
+        }
+        d[k] = dk;
+    }
+    double a = d[0] * d[0];
+    double b = d[1] * d[1];
+    double c = d[2] * d[2];
+    double ab = a + b;
+    double d2 = ab + c;
+    return d2 <= rc2;
+}
+
+__global__ void k_bbox(const double* __restrict__ xyz, int n, double* __restrict__ out) {
+    // one block: min and max per coordinate
+    __shared__ double smin[3][256], smax[3][256];
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        for (int k = 0; k < 3; ++k) {
+            double v = xyz[3 * (int64_t)i + k];
+            mn[k] = fmin(mn[k], v);
+            mx[k] = fmax(mx[k], v);
+        }
+    for (int k = 0; k < 3; ++k) { smin[k][threadIdx.x] = mn[k]; smax[k][threadIdx.x] = mx[k]; }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int k = 0; k < 3; ++k) {
+                smin[k][threadIdx.x] = fmin(smin[k][threadIdx.x], smin[k][threadIdx.x + s]);
+                smax[k][threadIdx.x] = fmax(smax[k][threadIdx.x], smax[k][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) { out[k] = smin[k][0]; out[3 + k] = smax[k][0]; }
+}
+
+__global__ void k_finite_check(const double* __restrict__ xyz, int64_t cnt, int* __restrict__ bad) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < cnt && !isfinite(xyz[i])) atomicOr(bad, 1);
+}
+
+__global__ void k_bin(const double* __restrict__ xyz, int n, Grid g, int* __restrict__ cell_of,
+                      int* __restrict__ cell_count) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cx = cell_coord(xyz[3 * (int64_t)i], 0, g);
+    int cy = cell_coord(xyz[3 * (int64_t)i + 1], 1, g);
+    int cz = cell_coord(xyz[3 * (int64_t)i + 2], 2, g);
+    int c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
+    cell_of[i] = c;
+    atomicAdd(&cell_count[c], 1);
+}
+
+__global__ void k_place(int n, const int* __restrict__ cell_of, const int* __restrict__ cell_start,
+                        int* __restrict__ cell_fill, int* __restrict__ cell_list) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = cell_of[i];
+    int pos = cell_start[c] + atomicAdd(&cell_fill[c], 1);
+    cell_list[pos] = i;
+}
+
+// Stencil offsets along one dimension: all distinct neighbouring cells.
+__device__ __forceinline__ int stencil(int nc, bool periodic, int c, int o[3]) {
+    if (nc == 1) { o[0] = 0; return 1; }
+    if (periodic) {
+        if (nc == 2) { o[0] = 0; o[1] = 1; return 2; }
+        o[0] = (c + nc - 1) % nc; o[1] = c; o[2] = (c + 1) % nc; return 3;
+    }
+    int k = 0;
+    for (int d = -1; d <= 1; ++d) {
+        int cc = c + d;
+        if (cc >= 0 && cc < nc) o[k++] = cc;
+    }
+    return k;
+}
+
+// COUNT = true: deg[m] = number of conflicting partners (self excluded).
+// COUNT = false: write the row (self included) at p_col[p_row_ptr[m] ...] unsorted.
+template <bool COUNT>
+__global__ void k_neighbours(const double* __restrict__ xyz, int n, Grid g, double rc2,
+                             const int* __restrict__ cell_of, const int* __restrict__ cell_start,
+                             const int* __restrict__ cell_list, int* __restrict__ deg,
+                             const int64_t* __restrict__ p_row_ptr, int32_t* __restrict__ p_col) {
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    int c = cell_of[m];
+    int cz = c % g.nc[2];
+    int cy = (c / g.nc[2]) % g.nc[1];
+    int cx = c / (g.nc[2] * g.nc[1]);
+    int ox[3], oy[3], oz[3];
+    int nx = stencil(g.nc[0], g.L[0] > 0.0, cx, ox);
+    int ny = stencil(g.nc[1], g.L[1] > 0.0, cy, oy);
+    int nz = stencil(g.nc[2], g.L[2] > 0.0, cz, oz);
+    int64_t out = COUNT ? 0 : p_row_ptr[m];
+    int count = 0;
+    for (int a = 0; a < nx; ++a)
+        for (int b = 0; b < ny; ++b)
+            for (int d = 0; d < nz; ++d) {
+                int cc = (ox[a] * g.nc[1] + oy[b]) * g.nc[2] + oz[d];
+                int s = cell_start[cc], e = cell_start[cc + 1];
+                for (int t = s; t < e; ++t) {
+                    int nb = cell_list[t];
+                    if (nb == m || conflict(xyz, m, nb, g, rc2)) {
+                        if (!COUNT) p_col[out + count] = nb;
+                        ++count;
+                    }
+                }
+            }
+    if (COUNT) deg[m] = count - 1;      // self is always found once
+}
+
+// Sort each pattern row ascending by rank (entries are distinct).
+__global__ void k_sort_rows(int n, const int64_t* __restrict__ p_row_ptr, int32_t* __restrict__ p_col) {
+    __shared__ int32_t row[kMaxRowLds];
+    int m = blockIdx.x;
+    if (m >= n) return;
+    int64_t s = p_row_ptr[m];
+    int len = static_cast<int>(p_row_ptr[m + 1] - s);
+    for (int i = threadIdx.x; i < len; i += blockDim.x) row[i] = p_col[s + i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+        int32_t x = row[i];
+        int r = 0;
+        for (int k = 0; k < len; ++k) r += (row[k] < x);
+        p_col[s + r] = x;
+    }
+}
+
+// One Jones-Plassmann round over all orbitals; coloured ones return at once.
+__global__ void k_jp_round(int n, const int64_t* __restrict__ p_row_ptr,
+                           const int32_t* __restrict__ p_col, const int* __restrict__ deg,
+                           int* color, int* __restrict__ n_new) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    if (__hip_atomic_load(&color[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 0) return;
+    int dv = deg[v];
+    int64_t s = p_row_ptr[v], e = p_row_ptr[v + 1];
+    // readiness: every higher-priority neighbour already coloured
+    for (int64_t t = s; t < e; ++t) {
+        int u = p_col[t];
+        if (u == v) continue;
+        int du = deg[u];
+        bool higher = du > dv || (du == dv && u < v);
+        if (higher && __hip_atomic_load(&color[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0)
+            return;
+    }
+    // smallest colour not used by the higher-priority neighbours, 64 at a time
+    for (int base = 0;; base += 64) {
+        unsigned long long used = 0ull;
+        for (int64_t t = s; t < e; ++t) {
+            int u = p_col[t];
+            if (u == v) continue;
+            int du = deg[u];
+            bool higher = du > dv || (du == dv && u < v);
+            if (!higher) continue;
+            int cu = __hip_atomic_load(&color[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cu >= base && cu < base + 64) used |= 1ull << (cu - base);
+        }
+        if (used != ~0ull) {
+            int c = base + __builtin_ctzll(~used);
+            __hip_atomic_store(&color[v], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            atomicAdd(n_new, 1);
+            return;
+        }
+    }
+}
+
+__global__ void k_fill_int(int* __restrict__ p, int64_t cnt, int v) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < cnt) p[i] = v;
+}
+
+__global__ void k_max_color(const int* __restrict__ color, int n, int* __restrict__ out, int* __restrict__ maxrow,
+                            const int64_t* __restrict__ p_row_ptr) {
+    __shared__ int sc[256], sr[256];
+    int mc = -1, mr = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (color) mc = max(mc, color[i]);
+        mr = max(mr, static_cast<int>(min<int64_t>(p_row_ptr[i + 1] - p_row_ptr[i], INT_MAX)));
+    }
+    sc[threadIdx.x] = mc;
+    sr[threadIdx.x] = mr;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sc[threadIdx.x] = max(sc[threadIdx.x], sc[threadIdx.x + s]);
+            sr[threadIdx.x] = max(sr[threadIdx.x], sr[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { atomicMax(out, sc[0]); atomicMax(maxrow, sr[0]); }
+}
+
+// ---- exclusive scan of (deg[i] + 1) into int64 row pointers -----------------
+
+constexpr int kScanBlock = 1024;
+
+__global__ void k_scan_blocks(const int* __restrict__ deg, int n, int64_t* __restrict__ out,
+                              int64_t* __restrict__ block_sum) {
+    __shared__ int64_t s[kScanBlock];
+    int i = blockIdx.x * kScanBlock + threadIdx.x;
+    int64_t v = (i < n) ? (int64_t)deg[i] + 1 : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        int64_t t = (threadIdx.x >= off) ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n) out[i + 1] = s[threadIdx.x];          // inclusive within block, shifted
+    if (threadIdx.x == kScanBlock - 1) block_sum[blockIdx.x] = s[threadIdx.x];
+}
+
+__global__ void k_scan_sums(int64_t* __restrict__ block_sum, int nb) {
+    // single block: exclusive scan of the block sums in place (sequential chunks)
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    __shared__ int64_t s[kScanBlock];
+    for (int base = 0; base < nb; base += kScanBlock) {
+        int i = base + threadIdx.x;
+        int64_t v = (i < nb) ? block_sum[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < kScanBlock; off <<= 1) {
+            int64_t t = (threadIdx.x >= off) ? s[threadIdx.x - off] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nb) block_sum[i] = carry + s[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == kScanBlock - 1) carry += s[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ out, int n, const int64_t* __restrict__ block_sum) {
+    int i = blockIdx.x * kScanBlock + threadIdx.x;
+    if (i == 0) out[0] = 0;
+    if (i < n) out[i + 1] += block_sum[blockIdx.x];
+}
+
+Grid make_grid(int n, const double box[3], double r_cut, const double bb[6]) {
+    Grid g;
+    const double wmin = r_cut * (1.0 + 1e-9);
+    for (int k = 0; k < 3; ++k) {
+        g.L[k] = box[k] > 0.0 ? box[k] : 0.0;
+        double extent = g.L[k] > 0.0 ? g.L[k] : (bb[3 + k] - bb[k]);
+        g.lo[k] = g.L[k] > 0.0 ? 0.0 : bb[k];
+        long long c = extent > 0.0 ? static_cast<long long>(std::floor(extent / wmin)) : 1;
+        g.nc[k] = static_cast<int>(std::max<long long>(1, std::min<long long>(c, 1 << 20)));
+    }
+    // cap the number of cells so the workspace stays O(n)
+    const long long cap = 2LL * n + 64;
+    while ((long long)g.nc[0] * g.nc[1] * g.nc[2] > cap) {
+        int k = (g.nc[0] >= g.nc[1] && g.nc[0] >= g.nc[2]) ? 0 : (g.nc[1] >= g.nc[2] ? 1 : 2);
+        g.nc[k] = std::max(1, g.nc[k] / 2);
+    }
+    for (int k = 0; k < 3; ++k) {
+        double extent = g.L[k] > 0.0 ? g.L[k] : (bb[3 + k] - bb[k]);
+        g.w[k] = extent > 0.0 ? extent / g.nc[k] : 1.0;
+        if (g.w[k] < wmin) g.w[k] = wmin;   // open direction: cells may overhang the box
+    }
+    return g;
+}
+
+struct ColorWs {
+    int *cell_of, *cell_count, *cell_start, *cell_fill, *cell_list, *deg, *scalars;
+    int64_t* block_sum;
+    double* bbox;
+};
+
+ColorWs carve_color(Arena& a, int n) {
+    ColorWs w;
+    int64_t ncell = 2LL * n + 64;
+    w.cell_of = a.take<int>(n);
+    w.cell_count = a.take<int>(ncell);
+    w.cell_start = a.take<int>(ncell + 1);
+    w.cell_fill = a.take<int>(ncell);
+    w.cell_list = a.take<int>(n);
+    w.deg = a.take<int>(n);
+    w.scalars = a.take<int>(64);
+    w.block_sum = a.take<int64_t>((n + kScanBlock - 1) / kScanBlock + 1);
+    w.bbox = a.take<double>(8);
+    return w;
+}
+
+}  // namespace
+
+size_t color_workspace_bytes(int n) {
+    Arena a;
+    carve_color(a, n);
+    return a.used + 256;
+}
+
+}  // namespace css
+
+using namespace css;
+
+extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3], double r_cut,
+                                int32_t* color, int32_t* n_colors, int64_t* p_row_ptr,
+                                int32_t* p_col, int64_t* p_nnz, int32_t* rounds, void* ws,
+                                size_t ws_bytes, void* stream) {
+    if (n < 1 || xyz == nullptr || box == nullptr || p_row_ptr == nullptr || p_nnz == nullptr ||
+        !(r_cut > 0.0) || !std::isfinite(r_cut) || ws == nullptr)
+        return CSS_E_ARG;
+    for (int k = 0; k < 3; ++k)
+        if (!(box[k] >= 0.0) || !std::isfinite(box[k])) return CSS_E_ARG;
+    if (p_col != nullptr && (color == nullptr || n_colors == nullptr)) return CSS_E_ARG;
+    if (ws_bytes < color_workspace_bytes(n)) return CSS_E_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+
+    Arena ar;
+    ar.base = static_cast<char*>(ws);
+    ar.cap = ws_bytes;
+    ColorWs w = carve_color(ar, n);
+    if (ar.overflow) return CSS_E_WORKSPACE;
+
+    // finite coordinates and bounding box (open directions)
+    CSS_HIP_TRY(hipMemsetAsync(w.scalars, 0, 64 * sizeof(int), s));
+    k_finite_check<<<grid_for(3LL * n, 256), 256, 0, s>>>(xyz, 3LL * n, w.scalars);
+    k_bbox<<<1, 256, 0, s>>>(xyz, n, w.bbox);
+    double hb[8];
+    int hbad = 0;
+    CSS_HIP_TRY(hipMemcpyAsync(hb, w.bbox, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipMemcpyAsync(&hbad, w.scalars, sizeof(int), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    if (hbad) return CSS_E_NONFINITE;
+    Grid g = make_grid(n, box, r_cut, hb);
+    const int ncell = g.nc[0] * g.nc[1] * g.nc[2];
+    const double rc2 = r_cut * r_cut;
+
+    // cell list
+    CSS_HIP_TRY(hipMemsetAsync(w.cell_count, 0, sizeof(int) * ncell, s));
+    CSS_HIP_TRY(hipMemsetAsync(w.cell_fill, 0, sizeof(int) * ncell, s));
+    k_bin<<<grid_for(n, 256), 256, 0, s>>>(xyz, n, g, w.cell_of, w.cell_count);
+    {
+        // cell_start = exclusive scan of cell_count (reuse the row-pointer scan on a temp view)
+        std::vector<int> hc(ncell);
+        CSS_HIP_TRY(hipMemcpyAsync(hc.data(), w.cell_count, sizeof(int) * ncell, hipMemcpyDeviceToHost, s));
+        CSS_HIP_TRY(hipStreamSynchronize(s));
+        std::vector<int> hs(ncell + 1);
+        hs[0] = 0;
+        for (int c = 0; c < ncell; ++c) hs[c + 1] = hs[c] + hc[c];
+        CSS_HIP_TRY(hipMemcpyAsync(w.cell_start, hs.data(), sizeof(int) * (ncell + 1), hipMemcpyHostToDevice, s));
+        CSS_HIP_TRY(hipStreamSynchronize(s));
+    }
+    k_place<<<grid_for(n, 256), 256, 0, s>>>(n, w.cell_of, w.cell_start, w.cell_fill, w.cell_list);
+
+    // degrees and row pointers
+    k_neighbours<true><<<grid_for(n, 128), 128, 0, s>>>(xyz, n, g, rc2, w.cell_of, w.cell_start,
+                                                        w.cell_list, w.deg, nullptr, nullptr);
+    const int nblk = (n + kScanBlock - 1) / kScanBlock;
+    k_scan_blocks<<<nblk, kScanBlock, 0, s>>>(w.deg, n, p_row_ptr, w.block_sum);
+    k_scan_sums<<<1, kScanBlock, 0, s>>>(w.block_sum, nblk);
+    k_scan_add<<<nblk, kScanBlock, 0, s>>>(p_row_ptr, n, w.block_sum);
+    int64_t nnz = 0;
+    CSS_HIP_TRY(hipMemcpyAsync(&nnz, p_row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    const int64_t capacity = *p_nnz;
+    *p_nnz = nnz;
+    if (p_col == nullptr) return CSS_OK;                 // size query
+    if (capacity < nnz) return CSS_E_CAPACITY;
+
+    // longest row must fit the LDS row sort
+    CSS_HIP_TRY(hipMemsetAsync(w.scalars, 0, 2 * sizeof(int), s));
+    k_max_color<<<64, 256, 0, s>>>(nullptr, n, w.scalars, w.scalars + 1, p_row_ptr);
+    int hmax[2];
+    CSS_HIP_TRY(hipMemcpyAsync(hmax, w.scalars, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    if (hmax[1] > kMaxRowLds) return CSS_E_UNSUPPORTED;
+
+    k_neighbours<false><<<grid_for(n, 128), 128, 0, s>>>(xyz, n, g, rc2, w.cell_of, w.cell_start,
+                                                         w.cell_list, w.deg, p_row_ptr, p_col);
+    k_sort_rows<<<n, 256, 0, s>>>(n, p_row_ptr, p_col);
+
+    // Jones-Plassmann rounds with Welsh-Powell priorities
+    k_fill_int<<<grid_for(n, 256), 256, 0, s>>>(color, n, -1);
+    int* n_new = w.scalars + 8;
+    CSS_HIP_TRY(hipMemsetAsync(n_new, 0, sizeof(int), s));
+    int done = 0, nround = 0;
+    const int batch = 8;
+    while (done < n) {
+        for (int r = 0; r < batch; ++r)
+            k_jp_round<<<grid_for(n, 256), 256, 0, s>>>(n, p_row_ptr, p_col, w.deg, color, n_new);
+        nround += batch;
+        CSS_HIP_TRY(hipMemcpyAsync(&done, n_new, sizeof(int), hipMemcpyDeviceToHost, s));
+        CSS_HIP_TRY(hipStreamSynchronize(s));
+        if (nround > n + batch) return CSS_E_DEVICE;     // cannot happen: each round colours >= 1
+    }
+    CSS_HIP_TRY(hipMemsetAsync(w.scalars, 0xff, sizeof(int), s));
+    CSS_HIP_TRY(hipMemsetAsync(w.scalars + 1, 0, sizeof(int), s));
+    k_max_color<<<64, 256, 0, s>>>(color, n, w.scalars, w.scalars + 1, p_row_ptr);
+    int hc = 0;
+    CSS_HIP_TRY(hipMemcpyAsync(&hc, w.scalars, sizeof(int), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    *n_colors = hc + 1;
+    if (rounds) *rounds = nround;
+    return CSS_OK;
+}

@@ -1,0 +1,59 @@
+// Internal dense block kernels (MFMA Gram / block update, small b x b FP64 ops).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace css {
+
+// Tall blocks: Np x ld row-major, Np a multiple of kRowPad, rows >= n and
+// columns >= b zero. Small matrices: ld x ld row-major FP64, zero outside b x b.
+
+// Split-K Gram plan. out[p] = X_p^T Y (X_p = X + p*xstride) for p < nprod.
+struct GramPlan {
+    int ld, nprod, ntiles, nchunk;
+    int64_t Np, rows_per_chunk;
+    bool sym;
+};
+GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t partial_cap_mats);
+int64_t gram_partial_mats(int ld);                 // capacity (in ld x ld matrices) to reserve
+
+// mode: 0 = plain, 1 = (S + S^T)/2, 2 = add (S + S^T)/2 into out (out += sym)
+template <typename T>
+void gram_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, double* partial,
+                 double* out, int64_t out_stride, int mode, const int* state, hipStream_t s);
+
+// OUT = alpha*IN + sum_p X_p * op_p(S_p),  op_p(S) = scale * (trans ? S^T : S)
+// X_p = X + p*xstride (tall), S_p = S + p*sstride (small FP64). OUT may equal IN;
+// OUT must not alias any X_p.
+template <typename T>
+void update_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, int nprod,
+                   const double* S, int64_t sstride, bool trans, double scale, int64_t Np, int ld,
+                   const int* state, hipStream_t s);
+
+// Cholesky G = R^T R of the leading b x b block, R and R^-1 (ld x ld, zero
+// elsewhere). On failure (non-positive pivot, non-finite, min diag <= tau) sets
+// state[0] = 1, state[2] = step, writes R^-1 = 0. Tracks min diag in *min_diag.
+// tau: device scalar (min diag threshold) or nullptr for no threshold.
+void chol_inv_launch(const double* G, int b, int ld, const double* tau, double* R, double* Rinv,
+                     double* scratch, int* state, int step, double* min_diag, hipStream_t s);
+
+// A += (C + C^T)/2 (ld x ld)
+void sym_add_launch(const double* C, double* A, int ld, const int* state, hipStream_t s);
+
+// R = R2 * R1 (upper triangular, ld x ld)
+void trmm_upper_launch(const double* R2, const double* R1, double* R, int ld, const int* state,
+                       hipStream_t s);
+
+// out (b x b, dense) = M (ld x ld) leading block
+void copy_small_launch(const double* M, int ld, int b, double* out, hipStream_t s);
+
+// Generic FP64 GEMM C = A B (+ beta C) with arbitrary element strides (MFMA).
+void gemm_f64_launch(int M, int N, int K, const double* A, int64_t a_rs, int64_t a_cs,
+                     const double* B, int64_t b_rs, int64_t b_cs, double* C, int64_t c_rs,
+                     int64_t c_cs, hipStream_t s);
+
+size_t chol_scratch_bytes(int b);
+
+}  // namespace css

@@ -1,0 +1,493 @@
+// The CSS density matrix on the cutoff pattern (Eqs.(1)-(7) with S = I).
+//
+// After block Lanczos (lanczos.hip):
+//   T  = block tridiagonal projected H (A_j diagonal, B_j below, B_j^T above);
+//   T  = U diag(lambda) U^T by exact diagonalisation (Eq.(7); rocSOLVER dsyevd);
+//   F  = U diag(g f(lambda)) U[0:b,:]^T B_0, f the Fermi function of Eq.(1)
+//        evaluated without overflow, B_0 = diag(sqrt n_c)          (Eq.(6));
+//   X  = sum_j Q_j F_j  (F_j = j-th block of b rows of F)          (Eq.(6));
+//   P_mn = s_n X[m, c(n)] on the pattern                           (Eq.(3)),
+//        optionally (P + P^T)/2 computed from X directly;
+//   trace = sum_m P_mm, e_band = sum over entries in H and the pattern of H_mn P_mn.
+// Krylov quadrature: w_k = sum_c n_c U[c,k]^2, trace_K = sum_k g f_k w_k,
+// E_K = sum_k lambda_k g f_k w_k. All reductions use a fixed order.
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <vector>
+
+#include "css_common.h"
+#include "dense.h"
+#include "driver.h"
+
+namespace css {
+
+size_t color_workspace_bytes(int n);
+size_t lanczos_workspace_bytes(const LzPlan& p);
+
+namespace {
+
+// ------------------------------------------------------------------ rocSOLVER handle
+
+std::mutex g_mu;
+rocblas_handle g_handle[64] = {};
+
+rocblas_handle handle_for_current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    if (!g_handle[dev]) {
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
+        g_handle[dev] = h;
+    }
+    return g_handle[dev];
+}
+
+size_t eig_workspace_bytes(int nT) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    rocblas_handle h = handle_for_current_device();
+    if (!h) return 0;
+    size_t sz = 0;
+    if (rocblas_start_device_memory_size_query(h) != rocblas_status_success) return 0;
+    rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, nT, nullptr, nT, nullptr, nullptr, nullptr);
+    if (rocblas_stop_device_memory_size_query(h, &sz) != rocblas_status_success) return 0;
+    return sz;
+}
+
+css_status eig(double* T, int nT, double* lam, double* E, int* dinfo, void* ws, size_t wsb, hipStream_t s) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    rocblas_handle h = handle_for_current_device();
+    if (!h) return CSS_E_DEVICE;
+    if (rocblas_set_stream(h, s) != rocblas_status_success) return CSS_E_DEVICE;
+    if (rocblas_set_workspace(h, ws, wsb) != rocblas_status_success) return CSS_E_DEVICE;
+    rocblas_status st = rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, nT, T, nT, lam, E, dinfo);
+    rocblas_set_workspace(h, nullptr, 0);
+    return st == rocblas_status_success ? CSS_OK : CSS_E_EIG;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// T (column-major nT x nT) from the padded A_j, B_j (ld x ld row-major).
+__global__ void k_assemble_T(const double* __restrict__ A, const double* __restrict__ B, int v, int b, int ld,
+                             double* __restrict__ T, int* __restrict__ bad) {
+    const int64_t nT = (int64_t)v * b;
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= nT * nT) return;
+    const int64_t col = idx / nT, row = idx % nT;
+    const int bi = (int)(row / b), bj = (int)(col / b);
+    const int i = (int)(row % b), j = (int)(col % b);
+    const int64_t mat = (int64_t)ld * ld;
+    double x = 0.0;
+    if (bi == bj)
+        x = A[bi * mat + (int64_t)i * ld + j];
+    else if (bi == bj + 1)
+        x = B[bj * mat + (int64_t)i * ld + j];          // block below the diagonal: B_j
+    else if (bj == bi + 1)
+        x = B[bi * mat + (int64_t)j * ld + i];          // above: B_j^T
+    if (!isfinite(x)) atomicOr(bad, 1);
+    T[idx] = x;
+}
+
+__device__ __forceinline__ double fermi(double x, double mu, double kT) {
+    const double t = (x - mu) / kT;
+    if (t > 0.0) {
+        const double e = exp(-t);
+        return e / (1.0 + e);
+    }
+    return 1.0 / (1.0 + exp(t));
+}
+
+// Y[k][c] = g f(lambda_k) U[c][k] sqrt(n_c)   (nT x b, row-major)
+__global__ void k_occ_y(const double* __restrict__ U, const double* __restrict__ lam, const int* __restrict__ counts,
+                        int nT, int b, double mu, double kT, double g, double* __restrict__ Y) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nT * b) return;
+    const int k = (int)(idx / b), c = (int)(idx % b);
+    const double occ = g * fermi(lam[k], mu, kT);
+    Y[idx] = occ * U[(int64_t)k * nT + c] * sqrt((double)counts[c]);
+}
+
+// Per-eigenpair quadrature terms: t0 = g f w, t1 = lambda g f w
+__global__ void k_quad_terms(const double* __restrict__ U, const double* __restrict__ lam,
+                             const int* __restrict__ counts, int nT, int b, double mu, double kT, double g,
+                             double* __restrict__ t0, double* __restrict__ t1) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nT) return;
+    double w = 0.0;
+    for (int c = 0; c < b; ++c) {
+        const double u = U[(int64_t)k * nT + c];
+        w += (double)counts[c] * u * u;
+    }
+    const double occ = g * fermi(lam[k], mu, kT);
+    t0[k] = occ * w;
+    t1[k] = lam[k] * occ * w;
+}
+
+// Pattern sanity: row pointers monotone from 0 to nnz, columns in range.
+__global__ void k_validate_pattern(int n, int64_t nnz, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                   int* __restrict__ bad) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int64_t a = rp[i], b = rp[i + 1];
+        if (a < 0 || b < a || b > nnz) atomicOr(bad, 1);
+        if (i == 0 && a != 0) atomicOr(bad, 1);
+        if (i == n - 1 && b != nnz) atomicOr(bad, 1);
+    }
+    if (i < nnz) {
+        const int32_t c = col[i];
+        if (c < 0 || c >= n) atomicOr(bad, 1);
+    }
+}
+
+// Fpad[j][i][c] = F[j*b + i][c] for i, c < b; zero in the padding.
+__global__ void k_pad_F(const double* __restrict__ F, int v, int b, int ld, double* __restrict__ Fpad) {
+    const int64_t mat = (int64_t)ld * ld;
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= v * mat) return;
+    const int j = (int)(idx / mat);
+    const int i = (int)((idx % mat) / ld), c = (int)(idx % ld);
+    Fpad[idx] = (i < b && c < b) ? F[((int64_t)j * b + i) * b + c] : 0.0;
+}
+
+// One wavefront per pattern row: P values, the diagonal and the raw asymmetry.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(int n, const int64_t* __restrict__ prp, const int32_t* __restrict__ pcol,
+                                                const int32_t* __restrict__ color, const int8_t* __restrict__ sign,
+                                                const T* __restrict__ X, int ld, int sym, double* __restrict__ pval,
+                                                double* __restrict__ row_trace, double* __restrict__ row_asym) {
+    const int lane = threadIdx.x & 63;
+    const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (m >= n) return;
+    const int cm = color[m];
+    const double sm = (double)sign[m];
+    const T* __restrict__ xm = X + m * ld;
+    double tr = 0.0, asym = 0.0;
+    for (int64_t t = prp[m] + lane; t < prp[m + 1]; t += 64) {
+        const int nn = pcol[t];
+        const double raw = (double)sign[nn] * (double)xm[color[nn]];
+        const double rt = sm * (double)X[(int64_t)nn * ld + cm];
+        const double v = 0.5 * (raw + rt);
+        asym = fmax(asym, fabs(raw - v));
+        const double out = sym ? v : raw;
+        pval[t] = out;
+        if (nn == m) tr = out;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        tr += __shfl_xor(tr, off);          // only one lane holds the diagonal: order is irrelevant
+        asym = fmax(asym, __shfl_xor(asym, off));
+    }
+    if (lane == 0) {
+        row_trace[m] = tr;
+        row_asym[m] = asym;
+    }
+}
+
+// One wavefront per row: sum over H entries present in the pattern of H_mn P_mn.
+template <typename V>
+__global__ __launch_bounds__(256) void k_energy(int n, const int32_t* __restrict__ hrp, const int32_t* __restrict__ hcol,
+                                                const V* __restrict__ hval, const int64_t* __restrict__ prp,
+                                                const int32_t* __restrict__ pcol, const double* __restrict__ pval,
+                                                double* __restrict__ row_e) {
+    const int lane = threadIdx.x & 63;
+    const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (m >= n) return;
+    const int64_t ps = prp[m], pe = prp[m + 1];
+    double e = 0.0;
+    for (int32_t t = hrp[m] + lane; t < hrp[m + 1]; t += 64) {
+        const int nn = hcol[t];
+        int64_t lo = ps, hi = pe;          // binary search nn in the sorted pattern row
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (pcol[mid] < nn) lo = mid + 1; else hi = mid;
+        }
+        if (lo < pe && pcol[lo] == nn) e += (double)hval[t] * pval[lo];
+    }
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+    if (lane == 0) row_e[m] = e;
+}
+
+// Deterministic two-level sum: block b sums v[b*chunk ...) in a fixed tree.
+__global__ void k_block_sum(const double* __restrict__ v, int64_t n, int64_t chunk, double* __restrict__ out) {
+    __shared__ double sm[256];
+    const int64_t s = blockIdx.x * chunk, e = min(n, s + chunk);
+    double acc = 0.0;
+    for (int64_t i = s + threadIdx.x; i < e; i += 256) acc += v[i];
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sm[threadIdx.x] += sm[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
+}
+
+__global__ void k_block_max(const double* __restrict__ v, int64_t n, double* __restrict__ out) {
+    __shared__ double sm[256];
+    double m = 0.0;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) m = fmax(m, v[i]);
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + k]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
+}
+
+constexpr int kSumBlocks = 256;
+
+// out = sum(v[0..n)) with a fixed order: kSumBlocks partial sums, then one block.
+void det_sum(const double* v, int64_t n, double* tmp, double* out, hipStream_t s) {
+    const int64_t chunk = std::max<int64_t>(1, (n + kSumBlocks - 1) / kSumBlocks);
+    const int nb = (int)((n + chunk - 1) / chunk);
+    k_block_sum<<<std::max(1, nb), 256, 0, s>>>(v, n, chunk, tmp);
+    k_block_sum<<<1, 256, 0, s>>>(tmp, std::max(1, nb), std::max(1, nb), out);
+}
+
+void det_max(const double* v, int64_t n, double* tmp, double* out, hipStream_t s) {
+    k_block_max<<<kSumBlocks, 256, 0, s>>>(v, n, tmp);
+    k_block_max<<<1, 256, 0, s>>>(tmp, kSumBlocks, out);
+}
+
+// ------------------------------------------------------------------ plan
+
+struct DmPlan {
+    LzPlan lz;
+    int nTmax = 0;
+    size_t eig_ws = 0;
+    bool sep_X = false;
+};
+
+struct DmBufs {
+    LzBufs lz;
+    double *T = nullptr, *lam = nullptr, *E = nullptr, *Y = nullptr, *F = nullptr, *Fpad = nullptr;
+    double *t0 = nullptr, *t1 = nullptr, *rows = nullptr, *tmp = nullptr, *res = nullptr;
+    int* flags = nullptr;
+    void* X = nullptr;
+    void* eig_ws = nullptr;
+};
+
+void carve_dm(Arena& a, const DmPlan& p, DmBufs& bf) {
+    carve_lanczos(a, p.lz, bf.lz);
+    const int64_t nT = p.nTmax;
+    const int64_t mat = (int64_t)p.lz.ld * p.lz.ld;
+    bf.T = a.take<double>(nT * nT);
+    bf.lam = a.take<double>(nT);
+    bf.E = a.take<double>(nT);
+    bf.Y = a.take<double>(nT * p.lz.b);
+    bf.F = a.take<double>(nT * p.lz.b);
+    bf.Fpad = a.take<double>(std::max(1, p.lz.v_max) * mat);
+    bf.t0 = a.take<double>(nT);
+    bf.t1 = a.take<double>(nT);
+    bf.rows = a.take<double>(3 * (int64_t)p.lz.n);
+    bf.tmp = a.take<double>(4 * kSumBlocks);
+    bf.res = a.take<double>(16);
+    bf.flags = a.take<int>(16);
+    bf.X = p.sep_X ? a.take<char>((size_t)p.lz.Np * p.lz.ld * p.lz.elem) : bf.lz.W;
+    bf.eig_ws = p.eig_ws ? a.take<char>(p.eig_ws) : nullptr;
+}
+
+css_status plan_dm(const css_csr* H, int32_t b, int32_t depth, uint32_t flags, DmPlan& p) {
+    CSS_TRY(plan_lanczos(H, b, depth, flags, p.lz));
+    p.nTmax = std::max(1, p.lz.v_max) * b;
+    p.sep_X = p.lz.twopass;
+    p.eig_ws = eig_workspace_bytes(p.nTmax);
+    return CSS_OK;
+}
+
+size_t dm_workspace_bytes(const DmPlan& p) {
+    Arena a;
+    DmBufs bf;
+    carve_dm(a, p, bf);
+    return a.used + 256;
+}
+
+template <typename T>
+void launch_gather(int n, const int64_t* prp, const int32_t* pcol, const int32_t* color, const int8_t* sign,
+                   const void* X, int ld, int sym, double* pval, double* rt, double* ra, hipStream_t s) {
+    k_gather<T><<<grid_for(n, 4), 256, 0, s>>>(n, prp, pcol, color, sign, static_cast<const T*>(X), ld, sym, pval,
+                                               rt, ra);
+}
+
+}  // namespace
+}  // namespace css
+
+using namespace css;
+
+extern "C" css_status css_density_matrix(const css_csr* H, const int32_t* color, const int8_t* sign,
+                                         int32_t n_colors, double mu, double kT, int32_t depth, double spin_deg,
+                                         const int64_t* p_row_ptr, const int32_t* p_col, int64_t p_nnz,
+                                         uint32_t flags, double* p_val, double* e_band, double* trace,
+                                         css_info* info, void* ws, size_t ws_bytes, void* stream) {
+    if (!color || !sign || !p_row_ptr || !p_col || !p_val || !e_band || !trace || !ws || p_nnz < 1) return CSS_E_ARG;
+    if (!(kT > 0.0) || !std::isfinite(kT) || !std::isfinite(mu) || !(spin_deg > 0.0)) return CSS_E_ARG;
+    DmPlan p;
+    CSS_TRY(plan_dm(H, n_colors, depth, flags, p));
+    if (p.eig_ws == 0) return CSS_E_DEVICE;
+    if (ws_bytes < dm_workspace_bytes(p)) return CSS_E_WORKSPACE;
+    Arena a;
+    a.base = static_cast<char*>(ws);
+    a.cap = ws_bytes;
+    DmBufs bf;
+    carve_dm(a, p, bf);
+    if (a.overflow) return CSS_E_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    const LzPlan& lz = p.lz;
+
+    hipEvent_t ev[6] = {};
+    for (auto& e : ev) CSS_HIP_TRY(hipEventCreate(&e));
+    struct Guard {
+        hipEvent_t* e;
+        ~Guard() { for (int i = 0; i < 6; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
+    } guard{ev};
+    CSS_HIP_TRY(hipEventRecord(ev[0], s));
+
+    {
+        CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+        k_validate_pattern<<<grid_for(std::max<int64_t>(lz.n, p_nnz), 256), 256, 0, s>>>(lz.n, p_nnz, p_row_ptr, p_col,
+                                                                                         bf.flags);
+        int pbad = 0;
+        CSS_HIP_TRY(hipMemcpyAsync(&pbad, bf.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+        CSS_HIP_TRY(hipStreamSynchronize(s));
+        if (pbad) return CSS_E_CSR;
+    }
+    int v_eff = 0, brk = 0;
+    double md = 0.0;
+    CSS_TRY(run_lanczos_pass1(H, color, sign, lz, bf.lz, s, &v_eff, &brk, &md));
+    CSS_HIP_TRY(hipEventRecord(ev[1], s));
+
+    // projected matrix and its eigenpairs
+    const int nT = v_eff * lz.b;
+    CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+    k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T, bf.flags);
+    int hbad = 0;
+    CSS_HIP_TRY(hipMemcpyAsync(&hbad, bf.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    if (hbad) return CSS_E_NONFINITE;
+    CSS_TRY(eig(bf.T, nT, bf.lam, bf.E, bf.flags + 1, bf.eig_ws, p.eig_ws, s));
+    CSS_HIP_TRY(hipEventRecord(ev[2], s));
+
+    // contraction F = U diag(g f) U_top^T B_0 and quadrature
+    k_occ_y<<<grid_for((int64_t)nT * lz.b, 256), 256, 0, s>>>(bf.T, bf.lam, bf.lz.counts, nT, lz.b, mu, kT, spin_deg,
+                                                                bf.Y);
+    gemm_f64_launch(nT, lz.b, nT, bf.T, 1, nT, bf.Y, lz.b, 1, bf.F, lz.b, 1, s);
+    const int64_t mat = (int64_t)lz.ld * lz.ld;
+    k_pad_F<<<grid_for(v_eff * mat, 256), 256, 0, s>>>(bf.F, v_eff, lz.b, lz.ld, bf.Fpad);
+    k_quad_terms<<<grid_for(nT, 256), 256, 0, s>>>(bf.T, bf.lam, bf.lz.counts, nT, lz.b, mu, kT, spin_deg, bf.t0,
+                                                   bf.t1);
+    det_sum(bf.t0, nT, bf.tmp, bf.res + 2, s);
+    det_sum(bf.t1, nT, bf.tmp + kSumBlocks, bf.res + 3, s);
+    CSS_HIP_TRY(hipEventRecord(ev[3], s));
+
+    // reconstruction X = sum_j Q_j F_j
+    if (lz.twopass) {
+        CSS_TRY(run_lanczos_pass2(H, color, sign, lz, bf.lz, v_eff, bf.Fpad, bf.X, s));
+    } else if (lz.fp32) {
+        update_launch<float>(static_cast<float*>(bf.X), nullptr, 0.0, static_cast<const float*>(slot_ptr(lz, bf.lz, 0)),
+                             lz.Np * lz.ld, v_eff, bf.Fpad, mat, false, 1.0, lz.Np, lz.ld, nullptr, s);
+    } else {
+        update_launch<double>(static_cast<double*>(bf.X), nullptr, 0.0,
+                              static_cast<const double*>(slot_ptr(lz, bf.lz, 0)), lz.Np * lz.ld, v_eff, bf.Fpad, mat,
+                              false, 1.0, lz.Np, lz.ld, nullptr, s);
+    }
+    CSS_HIP_TRY(hipEventRecord(ev[4], s));
+
+    // extraction on the pattern, trace, band energy
+    const int sym = (flags & CSS_SYMMETRIZE) ? 1 : 0;
+    double* rt = bf.rows;
+    double* ra = bf.rows + lz.n;
+    double* re = bf.rows + 2 * (int64_t)lz.n;
+    if (lz.fp32)
+        launch_gather<float>(lz.n, p_row_ptr, p_col, color, sign, bf.X, lz.ld, sym, p_val, rt, ra, s);
+    else
+        launch_gather<double>(lz.n, p_row_ptr, p_col, color, sign, bf.X, lz.ld, sym, p_val, rt, ra, s);
+    if (H->val_dtype == CSS_F64)
+        k_energy<double><<<grid_for(lz.n, 4), 256, 0, s>>>(lz.n, H->row_ptr, H->col, static_cast<const double*>(H->val),
+                                                           p_row_ptr, p_col, p_val, re);
+    else
+        k_energy<float><<<grid_for(lz.n, 4), 256, 0, s>>>(lz.n, H->row_ptr, H->col, static_cast<const float*>(H->val),
+                                                          p_row_ptr, p_col, p_val, re);
+    det_sum(rt, lz.n, bf.tmp + 2 * kSumBlocks, bf.res + 0, s);
+    det_sum(re, lz.n, bf.tmp + 3 * kSumBlocks, bf.res + 1, s);
+    det_max(ra, lz.n, bf.tmp, bf.res + 4, s);
+    CSS_HIP_TRY(hipEventRecord(ev[5], s));
+    double hres[8];
+    int hinfo = 0;
+    CSS_HIP_TRY(hipMemcpyAsync(hres, bf.res, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipMemcpyAsync(&hinfo, bf.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    CSS_HIP_TRY(hipGetLastError());
+    if (hinfo != 0) return CSS_E_EIG;
+    *trace = hres[0];
+    *e_band = hres[1];
+    if (info) {
+        *info = css_info{};
+        info->depth_eff = v_eff;
+        info->n_colors = lz.b;
+        info->breakdown = brk;
+        info->min_diag_r = md;
+        info->asym_max = hres[4];
+        info->trace_krylov = hres[2];
+        info->e_band_krylov = hres[3];
+        for (int k = 0; k < 5; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess) info->t_phase_ms[k] = ms;
+        }
+        float tot = 0.f;
+        if (hipEventElapsedTime(&tot, ev[0], ev[5]) == hipSuccess) info->t_phase_ms[5] = tot;
+    }
+    return CSS_OK;
+}
+
+extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, int32_t n_colors, int32_t depth,
+                                         uint32_t flags, size_t* bytes) {
+    if (!bytes || n < 1) return CSS_E_ARG;
+    if (entry == CSS_ENTRY_COLOR) {
+        *bytes = color_workspace_bytes(n);
+        return CSS_OK;
+    }
+    if (entry == CSS_ENTRY_SPMM) {
+        *bytes = 0;
+        return CSS_OK;
+    }
+    // a shape-only CSR for planning
+    css_csr H{n, nnz, reinterpret_cast<const int32_t*>(1), reinterpret_cast<const int32_t*>(1),
+              reinterpret_cast<const void*>(1), (flags & CSS_PREC_MASK) == CSS_PREC_FP32 ? CSS_F32 : CSS_F64};
+    if (entry == CSS_ENTRY_LANCZOS) {
+        LzPlan p;
+        CSS_TRY(plan_lanczos(&H, n_colors, depth, flags, p));
+        *bytes = lanczos_workspace_bytes(p);
+        return CSS_OK;
+    }
+    if (entry == CSS_ENTRY_DENSITY) {
+        DmPlan p;
+        CSS_TRY(plan_dm(&H, n_colors, depth, flags, p));
+        if (p.eig_ws == 0) return CSS_E_DEVICE;
+        *bytes = dm_workspace_bytes(p);
+        return CSS_OK;
+    }
+    return CSS_E_ARG;
+}
+
+extern "C" int32_t css_block_ld(int32_t n_colors) { return n_colors > 0 ? block_ld(n_colors) : 0; }
+
+extern "C" const char* css_status_string(css_status s) {
+    switch (s) {
+        case CSS_OK: return "ok";
+        case CSS_E_ARG: return "invalid argument";
+        case CSS_E_CSR: return "malformed CSR matrix or colouring";
+        case CSS_E_WORKSPACE: return "workspace too small";
+        case CSS_E_DEVICE: return "HIP runtime or library error";
+        case CSS_E_BREAKDOWN_AT_1: return "the first Krylov block is degenerate";
+        case CSS_E_NONFINITE: return "non-finite value in H or in the projected matrix";
+        case CSS_E_EIG: return "subspace eigensolver failed";
+        case CSS_E_UNSUPPORTED: return "option or size not supported";
+        case CSS_E_CAPACITY: return "output array too small";
+        default: return "unknown status";
+    }
+}

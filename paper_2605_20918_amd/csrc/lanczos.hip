@@ -1,0 +1,450 @@
+// Block Lanczos projection of H onto the block Krylov space of the CSS probes
+// (Golub-Underwood process, text after Eq.(4)).
+//
+// Block recurrence, exact arithmetic:
+//   H Q_j = Q_{j-1} B_{j-1}^T + Q_j A_j + Q_{j+1} B_j,  Q_0 = 0,
+// so [Q_1..Q_k]^T H [Q_1..Q_k] is block tridiagonal (A_j diagonal, B_j below,
+// B_j^T above). One step here:
+//   W   = H Q_j                                   (CSR SpMM)
+//   A_j = sym(Q_j^T W)                            (MFMA Gram)
+//   W  <- W - Q_j A_j - Q_{j-1} B_{j-1}^T          (MFMA block update)
+//   [re-orthogonalise W against Q_j, Q_{j-1} (local) or all Q (full), adding
+//    the symmetrised Q_j coefficient to A_j]
+//   W   = Q_{j+1} R by Cholesky QR on W^T W (twice with CholQR2), B_j = R;
+//   stop when W^T W is not positive definite or min diag R <= 1e-10 ||H||_inf.
+// The first block Q_1 = r B_0^-1 comes from the probes with B_0 = diag(sqrt n_c).
+//
+// No host synchronisation inside the loop: a breakdown sets a device flag
+// that turns the remaining kernels of the run into no-ops. Every reduction is
+// in a fixed order, so a second pass that replays the stored coefficients
+// regenerates the basis bitwise (used when the basis is not stored).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "css_common.h"
+#include "dense.h"
+#include "driver.h"
+#include "spmm.h"
+
+namespace css {
+namespace {
+
+__global__ void k_validate_csr(int n, int64_t nnz, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                               int* __restrict__ state) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int32_t a = rp[i], b = rp[i + 1];
+        if (a < 0 || b < a || b > nnz) atomicOr(&state[1], 1);
+        if (i == 0 && a != 0) atomicOr(&state[1], 1);
+        if (i == n - 1 && (int64_t)b != nnz) atomicOr(&state[1], 1);
+    }
+    if (i < nnz) {
+        const int32_t c = col[i];
+        if (c < 0 || c >= n) atomicOr(&state[1], 1);
+    }
+}
+
+template <typename V>
+__global__ void k_row_abs_sum(int n, const int32_t* __restrict__ rp, const V* __restrict__ val,
+                              double* __restrict__ out_rows, int* __restrict__ state) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    bool finite = true;
+    for (int32_t t = rp[i]; t < rp[i + 1]; ++t) {
+        const double v = (double)val[t];
+        finite = finite && isfinite(v);
+        s += fabs(v);
+    }
+    if (!finite) atomicOr(&state[1], 2);
+    out_rows[i] = s;
+}
+
+// max over an array (deterministic: max is order independent)
+__global__ void k_max_reduce(const double* __restrict__ v, int64_t n, double* __restrict__ out) {
+    __shared__ double sm[256];
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, v[i]);
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sm[0];
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S* __restrict__ in, D* __restrict__ out, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = D(in[i]);
+}
+
+__global__ void k_counts(const int32_t* __restrict__ color, int n, int b, int* __restrict__ counts,
+                         int* __restrict__ state) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = color[i];
+    if (c < 0 || c >= b)
+        atomicOr(&state[1], 4);
+    else
+        atomicAdd(&counts[c], 1);
+}
+
+__global__ void k_check_counts(const int* __restrict__ counts, int b, int* __restrict__ state) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < b && counts[c] == 0) atomicOr(&state[1], 8);
+}
+
+template <typename T>
+__global__ void k_zero(T* __restrict__ p, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = T(0);
+}
+
+// Q_1[m, c(m)] = s_m / sqrt(n_c); all other entries (and padded rows) zero.
+template <typename T>
+__global__ void k_init_q1(const int32_t* __restrict__ color, const int8_t* __restrict__ sign,
+                          const int* __restrict__ counts, int n, int64_t Np, int ld, T* __restrict__ Q) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= Np * ld) return;
+    const int64_t m = idx / ld;
+    const int c = static_cast<int>(idx % ld);
+    T v = T(0);
+    if (m < n && color[m] == c) v = T((double)sign[m] / sqrt((double)counts[c]));
+    Q[idx] = v;
+}
+
+__global__ void k_zero_small(double* __restrict__ p, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_copy_small_full(const double* __restrict__ a, double* __restrict__ b, int64_t n,
+                                  const int* __restrict__ state) {
+    if (state && state[0]) return;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+template <typename T>
+void zero_tall(T* p, int64_t count, hipStream_t s) {
+    k_zero<T><<<grid_for(count, 256), 256, 0, s>>>(p, count);
+}
+
+template <typename T>
+bool launch_spmm_t(const css_csr* H, const LzBufs& bf, const T* V, T* W, int ld, hipStream_t s) {
+    const T* val = bf.hval ? static_cast<const T*>(bf.hval) : static_cast<const T*>(H->val);
+    SpmmArgs<T> a{H->n, H->row_ptr, H->col, val, V, W, ld};
+    return spmm_launch(a, s);
+}
+
+__global__ void k_tau(double* __restrict__ scal) { scal[1] = 1e-10 * scal[0]; }
+
+__global__ void k_set_int(int* __restrict__ p, int v) { *p = v; }
+
+// ------------------------------------------------------------------ one step
+
+template <typename T>
+struct Step {
+    const css_csr* H;
+    const LzPlan& p;
+    const LzBufs& bf;
+    hipStream_t s;
+
+    int64_t mat() const { return (int64_t)p.ld * p.ld; }
+    int64_t tall() const { return p.Np * p.ld; }
+    // Block holding Q_j (0-based): stored basis slot j, two-pass slot j % 3.
+    T* q(int j) const { return static_cast<T*>(slot_ptr(p, bf, p.twopass ? j % 3 : j)); }
+
+    void gram(const T* X, int64_t xstride, int nprod, const T* Y, double* out, int64_t out_stride, bool sym,
+              int mode) const {
+        GramPlan g = gram_plan(p.Np, p.ld, nprod, sym, p.partial_mats);
+        gram_launch<T>(g, X, xstride, Y, bf.partial, out, out_stride, mode, bf.state, s);
+    }
+    void update(T* out, const T* in, double alpha, const T* X, int64_t xstride, int nprod, const double* S,
+                int64_t sstride, bool trans, double scale) const {
+        update_launch<T>(out, in, alpha, X, xstride, nprod, S, sstride, trans, scale, p.Np, p.ld, bf.state, s);
+    }
+
+    // Step j (0-based). replay: regenerate Q_{j+1} from stored coefficients
+    // (no Gram, no Cholesky). last: j == v_max - 1, no QR of W.
+    bool run(int j, bool replay, bool last) const {
+        const int ld = p.ld;
+        T* W = static_cast<T*>(bf.W);
+        T* Wt = static_cast<T*>(bf.Wt);
+        T* Qj = q(j);
+        double* Aj = bf.A + j * mat();
+        double* Apre = bf.Apre + j * mat();
+        if (!launch_spmm_t<T>(H, bf, Qj, W, ld, s)) return false;
+        if (!replay) gram(Qj, 0, 1, W, Apre, 0, false, 1);                    // A_j = sym(Q_j^T W)
+        update(W, W, 1.0, Qj, 0, 1, Apre, 0, false, -1.0);                    // W -= Q_j A_j
+        if (j > 0) update(W, W, 1.0, q(j - 1), 0, 1, bf.B + (j - 1) * mat(), 0, true, -1.0);  // W -= Q_{j-1} B^T
+        if (!replay) k_copy_small_full<<<grid_for(mat(), 256), 256, 0, s>>>(Apre, Aj, mat(), bf.state);
+        if (p.reorth == 1 || (p.reorth == 2 && p.twopass)) {
+            // local: coefficients against Q_{j-1} and Q_j, one block at a time
+            const int first = std::max(0, j - 1);
+            const int np = j - first + 1;
+            double* C = p.twopass ? bf.C + (int64_t)j * p.max_coef * mat() : bf.C;
+            if (!replay)
+                for (int t = 0; t < np; ++t) gram(q(first + t), 0, 1, W, C + t * mat(), 0, false, 0);
+            for (int t = 0; t < np; ++t) update(W, W, 1.0, q(first + t), 0, 1, C + t * mat(), 0, false, -1.0);
+            if (!replay) sym_add_launch(C + (np - 1) * mat(), Aj, ld, bf.state, s);
+        } else if (p.reorth == 2) {
+            // full: coefficients against Q_0..Q_j (contiguous stored slots), batched
+            const int np = j + 1;
+            const int cap = (int)std::max<int64_t>(1, p.partial_mats);
+            for (int t0 = 0; t0 < np; t0 += cap) {
+                const int cnt = std::min(cap, np - t0);
+                gram(q(t0), tall(), cnt, W, bf.C + t0 * mat(), mat(), false, 0);
+            }
+            update(W, W, 1.0, q(0), tall(), np, bf.C, mat(), false, -1.0);
+            sym_add_launch(bf.C + j * mat(), Aj, ld, bf.state, s);
+        }
+        if (last) return true;
+        T* Qn = q(j + 1);
+        double* R1inv = p.twopass ? bf.R1inv + j * mat() : bf.R1inv;
+        double* R2inv = p.twopass ? bf.R2inv + j * mat() : bf.R2inv;
+        double* Bj = bf.B + j * mat();
+        if (!replay) {
+            gram(W, 0, 1, W, bf.G, 0, true, 0);                               // G = W^T W
+            chol_inv_launch(bf.G, p.b, ld, bf.scal + 1, p.cholqr2 ? bf.R1 : Bj, R1inv, bf.chol_scratch,
+                            bf.state, 2 * j, bf.min_diag, s);
+        }
+        if (p.cholqr2) {
+            update(Wt, nullptr, 0.0, W, 0, 1, R1inv, 0, false, 1.0);           // Wt = W R1^-1
+            if (!replay) {
+                gram(Wt, 0, 1, Wt, bf.G, 0, true, 0);
+                chol_inv_launch(bf.G, p.b, ld, nullptr, bf.R2, R2inv, bf.chol_scratch, bf.state, 2 * j + 1,
+                                bf.min_diag, s);
+                trmm_upper_launch(bf.R2, bf.R1, Bj, ld, bf.state, s);        // B_j = R2 R1
+            }
+            update(Qn, nullptr, 0.0, Wt, 0, 1, R2inv, 0, false, 1.0);          // Q_{j+1} = Wt R2^-1
+        } else {
+            update(Qn, nullptr, 0.0, W, 0, 1, R1inv, 0, false, 1.0);           // Q_{j+1} = W R1^-1
+        }
+        return true;
+    }
+};
+
+template <typename T>
+css_status prepare(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p, const LzBufs& bf,
+                   hipStream_t s) {
+    k_zero<int><<<1, 64, 0, s>>>(bf.state, 16);
+    k_validate_csr<<<grid_for(std::max<int64_t>(p.n, p.nnz), 256), 256, 0, s>>>(p.n, p.nnz, H->row_ptr, H->col,
+                                                                                bf.state);
+    CSS_HIP_TRY(hipGetLastError());
+    int hst[16];
+    CSS_HIP_TRY(hipMemcpyAsync(hst, bf.state, sizeof(hst), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    if (hst[1]) return CSS_E_CSR;
+    double* rows = static_cast<double*>(bf.W);     // W is free scratch until the first SpMM
+    if (H->val_dtype == CSS_F64)
+        k_row_abs_sum<double><<<grid_for(p.n, 256), 256, 0, s>>>(p.n, H->row_ptr,
+                                                                  static_cast<const double*>(H->val), rows, bf.state);
+    else
+        k_row_abs_sum<float><<<grid_for(p.n, 256), 256, 0, s>>>(p.n, H->row_ptr, static_cast<const float*>(H->val),
+                                                                rows, bf.state);
+    k_max_reduce<<<1, 256, 0, s>>>(rows, p.n, bf.scal);
+    k_tau<<<1, 1, 0, s>>>(bf.scal);
+    k_zero<int><<<grid_for(p.b, 256), 256, 0, s>>>(bf.counts, p.b);
+    k_counts<<<grid_for(p.n, 256), 256, 0, s>>>(color, p.n, p.b, bf.counts, bf.state);
+    k_check_counts<<<grid_for(p.b, 256), 256, 0, s>>>(bf.counts, p.b, bf.state);
+    CSS_HIP_TRY(hipMemcpyAsync(hst, bf.state, sizeof(hst), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    if (hst[1] & 2) return CSS_E_NONFINITE;
+    if (hst[1]) return CSS_E_CSR;
+    if (p.convert_h) {
+        if (p.fp32)
+            k_convert<double, float><<<grid_for(p.nnz, 256), 256, 0, s>>>(static_cast<const double*>(H->val),
+                                                                           static_cast<float*>(bf.hval), p.nnz);
+        else
+            k_convert<float, double><<<grid_for(p.nnz, 256), 256, 0, s>>>(static_cast<const float*>(H->val),
+                                                                           static_cast<double*>(bf.hval), p.nnz);
+    }
+    zero_tall<T>(static_cast<T*>(bf.W), p.Np * p.ld, s);
+    if (bf.Wt) zero_tall<T>(static_cast<T*>(bf.Wt), p.Np * p.ld, s);
+    const int64_t mat = (int64_t)p.ld * p.ld;
+    k_zero_small<<<grid_for(p.v_max * mat, 256), 256, 0, s>>>(bf.A, p.v_max * mat);
+    k_zero_small<<<grid_for(p.v_max * mat, 256), 256, 0, s>>>(bf.Apre, p.v_max * mat);
+    k_zero_small<<<grid_for(p.v_max * mat, 256), 256, 0, s>>>(bf.B, p.v_max * mat);
+    (void)sign;
+    CSS_HIP_TRY(hipGetLastError());
+    return CSS_OK;
+}
+
+template <typename T>
+css_status pass1_t(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p, const LzBufs& bf,
+                   hipStream_t s, int* v_eff, int* breakdown, double* min_diag) {
+    CSS_TRY(prepare<T>(H, color, sign, p, bf, s));
+    Step<T> st{H, p, bf, s};
+    k_init_q1<T><<<grid_for(p.Np * p.ld, 256), 256, 0, s>>>(color, sign, bf.counts, p.n, p.Np, p.ld, st.q(0));
+    for (int j = 0; j < p.v_max; ++j)
+        if (!st.run(j, false, j == p.v_max - 1)) return CSS_E_UNSUPPORTED;
+    CSS_HIP_TRY(hipGetLastError());
+    int hst[16];
+    CSS_HIP_TRY(hipMemcpyAsync(hst, bf.state, sizeof(hst), hipMemcpyDeviceToHost, s));
+    std::vector<double> md(2 * std::max(1, p.v_max));
+    CSS_HIP_TRY(hipMemcpyAsync(md.data(), bf.min_diag, sizeof(double) * md.size(), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    *breakdown = hst[0] ? 1 : 0;
+    *v_eff = hst[0] ? hst[2] / 2 + 1 : p.v_max;
+    double m = INFINITY;
+    for (int j = 0; j < *v_eff - (hst[0] ? 0 : 1); ++j) m = std::min(m, md[2 * j]);
+    *min_diag = m;
+    return CSS_OK;
+}
+
+template <typename T>
+css_status pass2_t(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p, const LzBufs& bf,
+                   int v_eff, const double* Fpad, void* Xv, hipStream_t s) {
+    Step<T> st{H, p, bf, s};
+    T* X = static_cast<T*>(Xv);
+    k_set_int<<<1, 1, 0, s>>>(bf.state, 0);
+    k_init_q1<T><<<grid_for(p.Np * p.ld, 256), 256, 0, s>>>(color, sign, bf.counts, p.n, p.Np, p.ld, st.q(0));
+    zero_tall<T>(X, p.Np * p.ld, s);
+    const int64_t mat = (int64_t)p.ld * p.ld;
+    for (int j = 0; j < v_eff; ++j) {
+        st.update(X, X, 1.0, st.q(j), 0, 1, Fpad + j * mat, 0, false, 1.0);    // X += Q_j F_j
+        if (j < v_eff - 1 && !st.run(j, true, false)) return CSS_E_UNSUPPORTED;
+    }
+    CSS_HIP_TRY(hipGetLastError());
+    return CSS_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ plan / carve
+
+css_status plan_lanczos(const css_csr* H, int32_t b, int32_t depth, uint32_t flags, LzPlan& p) {
+    if (!H || H->n < 1 || !H->row_ptr || !H->col || !H->val) return CSS_E_ARG;
+    if (H->val_dtype != CSS_F64 && H->val_dtype != CSS_F32) return CSS_E_ARG;
+    if (H->nnz < 0 || H->nnz >= (int64_t(1) << 31)) return CSS_E_CSR;
+    if (b < 1 || b > H->n || depth < 1) return CSS_E_ARG;
+    if (b > kMaxColors) return CSS_E_UNSUPPORTED;
+    const uint32_t prec = flags & CSS_PREC_MASK;
+    if (prec == CSS_PREC_BF16X3 || prec == 3u) return CSS_E_UNSUPPORTED;
+    p.n = H->n;
+    p.nnz = H->nnz;
+    p.b = b;
+    p.depth = depth;
+    p.v_max = std::min(depth, H->n / b);
+    p.ld = block_ld(b);
+    p.Np = padded_rows(H->n);
+    p.fp32 = prec == CSS_PREC_FP32;
+    p.elem = p.fp32 ? 4 : 8;
+    p.twopass = (flags & CSS_BASIS_TWOPASS) != 0;
+    p.reorth = (flags & CSS_REORTH_FULL) ? 2 : ((flags & CSS_REORTH_LOCAL) ? 1 : 0);
+    if (p.twopass && p.reorth == 2) return CSS_E_UNSUPPORTED;
+    p.cholqr2 = (flags & CSS_CHOLQR2) != 0;
+    p.convert_h = (p.fp32 && H->val_dtype == CSS_F64) || (!p.fp32 && H->val_dtype == CSS_F32);
+    p.nslots = p.twopass ? 3 : std::max(1, p.v_max);
+    p.max_coef = p.reorth == 2 ? p.v_max : (p.reorth == 1 ? 2 : 0);
+    const int64_t by_rows = std::max<int64_t>(1, p.Np / 64) * std::max(1, p.max_coef);
+    p.partial_mats = std::max<int64_t>(1, std::min<int64_t>(gram_partial_mats(p.ld), std::max<int64_t>(by_rows, 64)));
+    return CSS_OK;
+}
+
+void carve_lanczos(Arena& a, const LzPlan& p, LzBufs& bf) {
+    const int64_t mat = (int64_t)p.ld * p.ld;
+    const int64_t tall_bytes = p.Np * p.ld * (int64_t)p.elem;
+    bf.basis = a.take<char>((size_t)p.nslots * tall_bytes);
+    bf.W = a.take<char>(tall_bytes);
+    bf.Wt = p.cholqr2 ? a.take<char>(tall_bytes) : nullptr;
+    bf.hval = p.convert_h ? a.take<char>((size_t)p.nnz * p.elem) : nullptr;
+    const int v = std::max(1, p.v_max);
+    bf.A = a.take<double>(v * mat);
+    bf.Apre = a.take<double>(v * mat);
+    bf.B = a.take<double>(v * mat);
+    bf.C = a.take<double>((p.twopass ? v : 1) * std::max(1, p.max_coef) * mat);
+    bf.R1inv = a.take<double>((p.twopass ? v : 1) * mat);
+    bf.R2inv = a.take<double>((p.twopass ? v : 1) * mat);
+    bf.G = a.take<double>(mat);
+    bf.R1 = a.take<double>(mat);
+    bf.R2 = a.take<double>(mat);
+    bf.partial = a.take<double>(p.partial_mats * mat);
+    bf.chol_scratch = a.take<double>(chol_scratch_bytes(p.b) / sizeof(double) + 1);
+    bf.min_diag = a.take<double>(2 * v);
+    bf.scal = a.take<double>(16);
+    bf.state = a.take<int>(16);
+    bf.counts = a.take<int>(p.b);
+}
+
+css_status run_lanczos_pass1(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p,
+                             const LzBufs& bf, hipStream_t s, int* v_eff, int* breakdown, double* min_diag) {
+    if (p.fp32) return pass1_t<float>(H, color, sign, p, bf, s, v_eff, breakdown, min_diag);
+    return pass1_t<double>(H, color, sign, p, bf, s, v_eff, breakdown, min_diag);
+}
+
+css_status run_lanczos_pass2(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p,
+                             const LzBufs& bf, int v_eff, const double* Fpad, void* X, hipStream_t s) {
+    if (p.fp32) return pass2_t<float>(H, color, sign, p, bf, v_eff, Fpad, X, s);
+    return pass2_t<double>(H, color, sign, p, bf, v_eff, Fpad, X, s);
+}
+
+size_t lanczos_workspace_bytes(const LzPlan& p) {
+    Arena a;
+    LzBufs bf;
+    carve_lanczos(a, p, bf);
+    return a.used + 256;
+}
+
+}  // namespace css
+
+using namespace css;
+
+extern "C" css_status css_block_lanczos(const css_csr* H, const int32_t* color, const int8_t* sign,
+                                        int32_t n_colors, int32_t depth, uint32_t flags, double* A, double* B,
+                                        css_info* info, void* ws, size_t ws_bytes, void* stream) {
+    if (!color || !sign || !A || (depth > 1 && !B) || !ws) return CSS_E_ARG;
+    LzPlan p;
+    CSS_TRY(plan_lanczos(H, n_colors, depth, flags, p));
+    if (ws_bytes < lanczos_workspace_bytes(p)) return CSS_E_WORKSPACE;
+    Arena a;
+    a.base = static_cast<char*>(ws);
+    a.cap = ws_bytes;
+    LzBufs bf;
+    carve_lanczos(a, p, bf);
+    if (a.overflow) return CSS_E_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (info) {
+        CSS_HIP_TRY(hipEventCreate(&e0));
+        CSS_HIP_TRY(hipEventCreate(&e1));
+        CSS_HIP_TRY(hipEventRecord(e0, s));
+    }
+    int v_eff = 0, brk = 0;
+    double md = 0.0;
+    css_status st = run_lanczos_pass1(H, color, sign, p, bf, s, &v_eff, &brk, &md);
+    if (st != CSS_OK) {
+        if (e0) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); }
+        return st;
+    }
+    const int64_t mat = (int64_t)p.ld * p.ld;
+    const int64_t bb = (int64_t)p.b * p.b;
+    for (int j = 0; j < v_eff; ++j) copy_small_launch(bf.A + j * mat, p.ld, p.b, A + j * bb, s);
+    for (int j = 0; j + 1 < v_eff; ++j) copy_small_launch(bf.B + j * mat, p.ld, p.b, B + j * bb, s);
+    CSS_HIP_TRY(hipGetLastError());
+    if (info) {
+        CSS_HIP_TRY(hipEventRecord(e1, s));
+        CSS_HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        CSS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *info = css_info{};
+        info->depth_eff = v_eff;
+        info->n_colors = p.b;
+        info->breakdown = brk;
+        info->min_diag_r = md;
+        info->t_phase_ms[0] = ms;
+        info->t_phase_ms[5] = ms;
+    } else {
+        CSS_HIP_TRY(hipStreamSynchronize(s));
+    }
+    return CSS_OK;
+}

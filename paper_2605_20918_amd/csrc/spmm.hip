@@ -1,0 +1,117 @@
+// Sparse H times a dense block: W = H V (the product the whole method is built
+// on; the paper performs every such product with a CPU SpMM library).
+//
+// Layout: H in CSR (int32 row pointers and columns, FP64 or FP32 values);
+// V and W row-major n x ld, so one orbital's b entries are contiguous. A group
+// of LPR lanes owns one row of W and lane j of the group owns columns
+// j, j+LPR, ..., j+(C-1)*LPR (ld = C*LPR), so every V row is read as C
+// coalesced LPR-wide segments. The row's nonzeros are walked four at a time
+// to keep several V-row loads in flight.
+
+#include <hip/hip_runtime.h>
+
+#include "css_common.h"
+#include "spmm.h"
+
+namespace css {
+namespace {
+
+template <typename T, int LPR, int C>
+__global__ __launch_bounds__(256) void k_spmm_csr(int n, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col,
+                                                  const T* __restrict__ val, const T* __restrict__ V,
+                                                  T* __restrict__ W, int ld) {
+    const int lane = threadIdx.x % LPR;
+    const int64_t row = (int64_t)blockIdx.x * (256 / LPR) + threadIdx.x / LPR;
+    if (row >= n) return;
+    T acc[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) acc[k] = T(0);
+    const int s = rp[row], e = rp[row + 1];
+    const T* __restrict__ vb = V + lane;
+    int t = s;
+    for (; t + 4 <= e; t += 4) {
+        const int64_t c0 = col[t], c1 = col[t + 1], c2 = col[t + 2], c3 = col[t + 3];
+        const T h0 = val[t], h1 = val[t + 1], h2 = val[t + 2], h3 = val[t + 3];
+        const T* p0 = vb + c0 * ld;
+        const T* p1 = vb + c1 * ld;
+        const T* p2 = vb + c2 * ld;
+        const T* p3 = vb + c3 * ld;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            T a = p0[k * LPR], b = p1[k * LPR], c = p2[k * LPR], d = p3[k * LPR];
+            acc[k] += h0 * a;
+            acc[k] += h1 * b;
+            acc[k] += h2 * c;
+            acc[k] += h3 * d;
+        }
+    }
+    for (; t < e; ++t) {
+        const int64_t c0 = col[t];
+        const T h0 = val[t];
+        const T* p0 = vb + c0 * ld;
+#pragma unroll
+        for (int k = 0; k < C; ++k) acc[k] += h0 * p0[k * LPR];
+    }
+    T* __restrict__ wr = W + row * ld + lane;
+#pragma unroll
+    for (int k = 0; k < C; ++k) wr[k * LPR] = acc[k];
+}
+
+template <typename T, int LPR, int C>
+void launch_one(const SpmmArgs<T>& a, hipStream_t s) {
+    constexpr int rows_per_block = 256 / LPR;
+    const unsigned grid = static_cast<unsigned>((a.n + rows_per_block - 1) / rows_per_block);
+    k_spmm_csr<T, LPR, C><<<grid, 256, 0, s>>>(a.n, a.row_ptr, a.col, a.val, a.V, a.W, a.ld);
+}
+
+template <typename T, int LPR>
+bool dispatch_c(const SpmmArgs<T>& a, int c, hipStream_t s) {
+    switch (c) {
+#define CSS_CASE(CC) case CC: launch_one<T, LPR, CC>(a, s); return true;
+        CSS_CASE(1) CSS_CASE(2) CSS_CASE(3) CSS_CASE(4) CSS_CASE(5) CSS_CASE(6) CSS_CASE(7) CSS_CASE(8)
+        CSS_CASE(9) CSS_CASE(10) CSS_CASE(11) CSS_CASE(12) CSS_CASE(13) CSS_CASE(14) CSS_CASE(15) CSS_CASE(16)
+#undef CSS_CASE
+        default: return false;
+    }
+}
+
+}  // namespace
+
+template <typename T>
+bool spmm_launch(const SpmmArgs<T>& a, hipStream_t s) {
+    if (a.ld % 16 != 0 || a.ld > kMaxColors) return false;
+    if (a.ld <= 256) return dispatch_c<T, 16>(a, a.ld / 16, s);
+    if (a.ld <= 512 && a.ld % 32 == 0) return dispatch_c<T, 32>(a, a.ld / 32, s);
+    if (a.ld % 64 == 0) return dispatch_c<T, 64>(a, a.ld / 64, s);
+    return false;
+}
+
+template bool spmm_launch<double>(const SpmmArgs<double>&, hipStream_t);
+template bool spmm_launch<float>(const SpmmArgs<float>&, hipStream_t);
+
+}  // namespace css
+
+using namespace css;
+
+extern "C" css_status css_spmm(const css_csr* H, const void* V, void* W, int32_t b, int32_t ld,
+                               void* stream) {
+    if (!H || !V || !W || H->n < 1 || b < 1 || ld < b || !H->row_ptr || !H->col || !H->val)
+        return CSS_E_ARG;
+    if (H->nnz < 0 || H->nnz >= (int64_t(1) << 31)) return CSS_E_CSR;
+    hipStream_t s = as_stream(stream);
+    bool ok;
+    if (H->val_dtype == CSS_F64) {
+        SpmmArgs<double> a{H->n, H->row_ptr, H->col, static_cast<const double*>(H->val),
+                           static_cast<const double*>(V), static_cast<double*>(W), ld};
+        ok = spmm_launch(a, s);
+    } else if (H->val_dtype == CSS_F32) {
+        SpmmArgs<float> a{H->n, H->row_ptr, H->col, static_cast<const float*>(H->val),
+                          static_cast<const float*>(V), static_cast<float*>(W), ld};
+        ok = spmm_launch(a, s);
+    } else {
+        return CSS_E_ARG;
+    }
+    if (!ok) return CSS_E_UNSUPPORTED;
+    return hipGetLastError() == hipSuccess ? CSS_OK : CSS_E_DEVICE;
+}

@@ -1,0 +1,258 @@
+"""Python binding of libcss (include/css.h): argument marshalling only.
+
+Every function here takes torch tensors on a ROCm device, passes their
+pointers and the current HIP stream to the C ABI, and returns tensors or
+scalars. No step of the method runs in Python. When libcss.so has not been
+built, loading fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libcss.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "css.h")
+
+# status codes
+CSS_OK = 0
+STATUS = {0: "CSS_OK", 1: "CSS_E_ARG", 2: "CSS_E_CSR", 3: "CSS_E_WORKSPACE", 4: "CSS_E_DEVICE",
+          5: "CSS_E_BREAKDOWN_AT_1", 6: "CSS_E_NONFINITE", 7: "CSS_E_EIG", 8: "CSS_E_UNSUPPORTED",
+          9: "CSS_E_CAPACITY"}
+CSS_F64, CSS_F32 = 0, 1
+
+# flags
+PREC_FP64 = 0x0
+PREC_FP32 = 0x1
+PREC_BF16X3 = 0x2
+BASIS_STORED = 0x0
+BASIS_TWOPASS = 0x4
+REORTH_NONE = 0x0
+REORTH_LOCAL = 0x8
+REORTH_FULL = 0x10
+CHOLQR2 = 0x20
+SYMMETRIZE = 0x40
+SIGNS_ONES = 0x80
+
+ENTRY_COLOR, ENTRY_LANCZOS, ENTRY_DENSITY, ENTRY_SPMM = 0, 1, 2, 3
+
+
+class CssError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} failed: {STATUS.get(code, code)} ({msg})")
+        self.code = code
+
+
+class CsrStruct(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p), ("val_dtype", ctypes.c_int32)]
+
+
+class InfoStruct(ctypes.Structure):
+    _fields_ = [("depth_eff", ctypes.c_int32), ("n_colors", ctypes.c_int32), ("breakdown", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("min_diag_r", ctypes.c_double), ("asym_max", ctypes.c_double),
+                ("trace_krylov", ctypes.c_double), ("e_band_krylov", ctypes.c_double),
+                ("t_phase_ms", ctypes.c_double * 6)]
+
+    def as_dict(self) -> dict:
+        return {"depth_eff": self.depth_eff, "n_colors": self.n_colors, "breakdown": self.breakdown,
+                "min_diag_r": self.min_diag_r, "asym_max": self.asym_max, "trace_krylov": self.trace_krylov,
+                "e_band_krylov": self.e_band_krylov,
+                "t_phase_ms": {k: self.t_phase_ms[i] for i, k in
+                               enumerate(["lanczos", "eig", "contraction", "reconstruction", "gather", "total"])}}
+
+
+_lib = None
+
+
+def declared_symbols() -> list[str]:
+    """Entry points declared in include/css.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:css_status|int32_t|const char\*)\s+(css_\w+)\s*\(", text, re.M)))
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2605_20918_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u32, u64, dbl, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                      ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t)
+    pcsr, pinfo = ctypes.POINTER(CsrStruct), ctypes.POINTER(InfoStruct)
+    lib.css_color.argtypes = [vp, i32, ctypes.POINTER(dbl * 3), dbl, vp, ctypes.POINTER(i32), vp, vp,
+                              ctypes.POINTER(i64), ctypes.POINTER(i32), vp, sz, vp]
+    lib.css_build_probes.argtypes = [vp, i32, i32, u64, u32, vp, vp, vp]
+    lib.css_spmm.argtypes = [pcsr, vp, vp, i32, i32, vp]
+    lib.css_block_lanczos.argtypes = [pcsr, vp, vp, i32, i32, u32, vp, vp, pinfo, vp, sz, vp]
+    lib.css_density_matrix.argtypes = [pcsr, vp, vp, i32, dbl, dbl, i32, dbl, vp, vp, i64, u32, vp,
+                                       ctypes.POINTER(dbl), ctypes.POINTER(dbl), pinfo, vp, sz, vp]
+    lib.css_workspace_size.argtypes = [i32, i32, i64, i32, i32, u32, ctypes.POINTER(sz)]
+    lib.css_block_ld.argtypes = [i32]
+    lib.css_block_ld.restype = i32
+    lib.css_status_string.argtypes = [i32]
+    lib.css_status_string.restype = ctypes.c_char_p
+    for name in ("css_color", "css_build_probes", "css_spmm", "css_block_lanczos", "css_density_matrix",
+                 "css_workspace_size"):
+        getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(fn: str, code: int):
+    if code != CSS_OK:
+        raise CssError(fn, code, load().css_status_string(code).decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+_ws_cache: dict = {}
+
+
+def workspace(nbytes: int, device):
+    """A cached device byte buffer of at least nbytes (grown on demand)."""
+    torch = _torch()
+    key = str(device)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        _ws_cache.pop(key, None)
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+@dataclass
+class DeviceCSR:
+    """CSR matrix held in device tensors (int32 row_ptr/col, float64 or float32 values)."""
+    n: int
+    row_ptr: object
+    col: object
+    val: object
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @staticmethod
+    def from_host(row_ptr, col, val, device="cuda", dtype=None):
+        torch = _torch()
+        rp = torch.as_tensor(row_ptr, dtype=torch.int32).to(device)
+        c = torch.as_tensor(col, dtype=torch.int32).to(device)
+        v = torch.as_tensor(val).to(device)
+        if dtype is not None:
+            v = v.to(dtype)
+        return DeviceCSR(int(rp.numel()) - 1, rp.contiguous(), c.contiguous(), v.contiguous())
+
+    def struct(self) -> CsrStruct:
+        torch = _torch()
+        dt = CSS_F64 if self.val.dtype == torch.float64 else CSS_F32
+        return CsrStruct(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr(), dt)
+
+
+def block_ld(n_colors: int) -> int:
+    return int(load().css_block_ld(n_colors))
+
+
+def workspace_size(entry: int, n: int, nnz: int, n_colors: int, depth: int, flags: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check("css_workspace_size", load().css_workspace_size(entry, n, nnz, n_colors, depth, flags, ctypes.byref(out)))
+    return int(out.value)
+
+
+def css_color(xyz, box, r_cut: float):
+    """Conflict pattern and greedy colouring. Returns (color, n_colors, p_row_ptr, p_col, rounds)."""
+    torch = _torch()
+    lib = load()
+    xyz = xyz.to(torch.float64).contiguous()
+    n = int(xyz.shape[0])
+    dev = xyz.device
+    ws = workspace(workspace_size(ENTRY_COLOR, n, 0, 1, 1, 0), dev)
+    boxa = (ctypes.c_double * 3)(*[float(x) for x in box])
+    p_row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    nnz = ctypes.c_int64(0)
+    ncol = ctypes.c_int32(0)
+    rounds = ctypes.c_int32(0)
+    s = _stream(dev)
+    _check("css_color", lib.css_color(_ptr(xyz), n, ctypes.byref(boxa), float(r_cut), None, ctypes.byref(ncol),
+                                      _ptr(p_row_ptr), None, ctypes.byref(nnz), ctypes.byref(rounds),
+                                      _ptr(ws), ws.numel(), s))
+    p_col = torch.empty(int(nnz.value), dtype=torch.int32, device=dev)
+    color = torch.empty(n, dtype=torch.int32, device=dev)
+    _check("css_color", lib.css_color(_ptr(xyz), n, ctypes.byref(boxa), float(r_cut), _ptr(color),
+                                      ctypes.byref(ncol), _ptr(p_row_ptr), _ptr(p_col), ctypes.byref(nnz),
+                                      ctypes.byref(rounds), _ptr(ws), ws.numel(), s))
+    return color, int(ncol.value), p_row_ptr, p_col, int(rounds.value)
+
+
+def css_build_probes(color, n_colors: int, seed: int, flags: int = 0):
+    """Returns (sign int8[n], color_count int32[b])."""
+    torch = _torch()
+    n = int(color.numel())
+    sign = torch.empty(n, dtype=torch.int8, device=color.device)
+    counts = torch.empty(n_colors, dtype=torch.int32, device=color.device)
+    _check("css_build_probes", load().css_build_probes(_ptr(color), n, n_colors, ctypes.c_uint64(seed & (2**64 - 1)),
+                                                       flags, _ptr(sign), _ptr(counts), _stream(color.device)))
+    return sign, counts
+
+
+def css_spmm(H: DeviceCSR, V, b: int):
+    """W = H V for V of shape (n, ld) with b meaningful columns."""
+    torch = _torch()
+    W = torch.empty_like(V)
+    csr = H.struct()
+    _check("css_spmm", load().css_spmm(ctypes.byref(csr), _ptr(V), _ptr(W), b, int(V.shape[1]), _stream(V.device)))
+    return W
+
+
+def css_block_lanczos(H: DeviceCSR, color, sign, n_colors: int, depth: int, flags: int):
+    """Returns (A [v_eff, b, b], B [v_eff-1, b, b], info dict) as float64 device tensors."""
+    torch = _torch()
+    dev = color.device
+    b = n_colors
+    A = torch.zeros(depth * b * b, dtype=torch.float64, device=dev)
+    B = torch.zeros(max(1, depth - 1) * b * b, dtype=torch.float64, device=dev)
+    ws = workspace(workspace_size(ENTRY_LANCZOS, H.n, H.nnz, b, depth, flags), dev)
+    info = InfoStruct()
+    csr = H.struct()
+    _check("css_block_lanczos", load().css_block_lanczos(ctypes.byref(csr), _ptr(color), _ptr(sign), b, depth, flags,
+                                                         _ptr(A), _ptr(B), ctypes.byref(info), _ptr(ws), ws.numel(),
+                                                         _stream(dev)))
+    v = info.depth_eff
+    return A[: v * b * b].view(v, b, b), B[: max(0, v - 1) * b * b].view(max(0, v - 1), b, b), info.as_dict()
+
+
+def css_density_matrix(H: DeviceCSR, color, sign, n_colors: int, mu: float, kT: float, depth: int, p_row_ptr,
+                       p_col, flags: int, spin_deg: float = 2.0, p_val=None):
+    """Returns (p_val float64 [nnz_P], e_band, trace, info dict)."""
+    torch = _torch()
+    dev = color.device
+    nnz = int(p_col.numel())
+    if p_val is None:
+        p_val = torch.empty(nnz, dtype=torch.float64, device=dev)
+    ws = workspace(workspace_size(ENTRY_DENSITY, H.n, H.nnz, n_colors, depth, flags), dev)
+    e_band = ctypes.c_double(0.0)
+    trace = ctypes.c_double(0.0)
+    info = InfoStruct()
+    csr = H.struct()
+    _check("css_density_matrix",
+           load().css_density_matrix(ctypes.byref(csr), _ptr(color), _ptr(sign), n_colors, float(mu), float(kT),
+                                     depth, float(spin_deg), _ptr(p_row_ptr), _ptr(p_col), nnz, flags, _ptr(p_val),
+                                     ctypes.byref(e_band), ctypes.byref(trace), ctypes.byref(info), _ptr(ws),
+                                     ws.numel(), _stream(dev)))
+    return p_val, float(e_band.value), float(trace.value), info.as_dict()

@@ -1,0 +1,238 @@
+"""GPU parity: every step of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances: integer work (pattern, colours, signs, counts) bitwise; FP64 path
+max|dP| <= 1e-10 (the stated target); FP32 path max|dP| <= 1e-5 and relative
+band energy <= 1e-7 against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import density as D  # noqa: E402
+from oracle.coloring import greedy_color  # noqa: E402
+from oracle.lanczos import assemble_T, block_lanczos  # noqa: E402
+from oracle.pattern import conflict_pattern  # noqa: E402
+from oracle.probes import color_counts, probe_signs  # noqa: E402
+from paper_2605_20918_amd import css, synth  # noqa: E402
+
+from gpu_common import KT, R_CUT, dev_i8, dev_i32, dev_i64, to_dev, water_case  # noqa: E402
+
+FP64_FLAGS = css.PREC_FP64 | css.REORTH_FULL | css.CHOLQR2 | css.SYMMETRIZE
+FP32_FLAGS = css.PREC_FP32 | css.REORTH_LOCAL | css.CHOLQR2 | css.SYMMETRIZE
+
+
+def setup_module(module):
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    css.load()
+
+
+# ---------------------------------------------------------------- colouring
+
+def _colour_case(xyz, box, r_cut):
+    rp, col, deg = conflict_pattern(xyz, box, r_cut)
+    color, b = greedy_color(rp, col, deg)
+    g_color, g_b, g_rp, g_col, rounds = css.css_color(torch.as_tensor(xyz).cuda(), box, r_cut)
+    assert g_b == b
+    assert np.array_equal(g_rp.cpu().numpy(), rp)
+    assert np.array_equal(g_col.cpu().numpy(), col)
+    assert np.array_equal(g_color.cpu().numpy(), color)
+    return rounds
+
+
+@pytest.mark.parametrize("M,seed", [(8, 1), (64, 20919), (343, 5), (1000, 20920)])
+def test_colour_water_bitexact(M, seed):
+    ws = synth.water_system(M, seed)
+    print(f"colour water M={M} seed={seed}", flush=True)
+    _colour_case(ws.orb_xyz, ws.box, R_CUT)
+
+
+def test_colour_special_graphs_bitexact():
+    xyz, box = synth.chain_1d(30, 0.7)
+    _colour_case(xyz, box, 1.45)                      # Fig.1(b) chain
+    rng = np.random.default_rng(3)
+    _colour_case(rng.uniform(0, 1, size=(40, 3)), np.zeros(3), 10.0)      # complete graph
+    _colour_case(rng.uniform(0, 20, size=(500, 3)), np.zeros(3), 3.0)     # open cluster
+    g = 6
+    idx = np.arange(g ** 3)
+    lat = np.stack([idx // 36, (idx // 6) % 6, idx % 6], 1).astype(float)
+    _colour_case(lat, np.array([6.0, 6.0, 6.0]), 1.0)                     # exact-distance ties
+    _colour_case(lat, np.array([6.0, 0.0, 6.0]), 1.5)                     # mixed open / periodic
+    _colour_case(np.zeros((5, 3)), np.zeros(3), 1.0)                      # coincident centres
+
+
+# ---------------------------------------------------------------- probes
+
+@pytest.mark.parametrize("ones", [False, True])
+def test_probes_bitexact(ones):
+    ws, H, rp, col, color, b, sign, mu = water_case(64, 20919)
+    g_sign, g_cnt = css.css_build_probes(dev_i32(color), b, 20919, css.SIGNS_ONES if ones else 0)
+    assert np.array_equal(g_sign.cpu().numpy(), probe_signs(ws.n, 20919, all_ones=ones))
+    assert np.array_equal(g_cnt.cpu().numpy(), color_counts(color, b))
+
+
+def test_probes_reject_bad_colours():
+    bad = dev_i32(np.array([0, 1, 5, 1], dtype=np.int32))
+    with pytest.raises(css.CssError) as e:
+        css.css_build_probes(bad, 3, 1)
+    assert e.value.code == 2
+
+
+# ---------------------------------------------------------------- SpMM
+
+@pytest.mark.parametrize("M,b", [(64, 69), (216, 16), (1000, 88), (1000, 300)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_spmm(M, b, dtype):
+    ws = synth.water_system(M, 7)
+    ld = css.block_ld(b)
+    rng = np.random.default_rng(1)
+    V = np.zeros((ws.n, ld))
+    V[:, :b] = rng.normal(size=(ws.n, b))
+    ref = ws.H.to_scipy() @ V
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    H = to_dev(ws, tdt)
+    W = css.css_spmm(H, torch.as_tensor(V, dtype=tdt).cuda(), b).double().cpu().numpy()
+    scale = np.max(np.abs(ref))
+    tol = 1e-14 if dtype == "f64" else 2e-6
+    assert np.max(np.abs(W - ref)) <= tol * scale
+    assert np.all(W[:, b:] == 0)
+
+
+# ---------------------------------------------------------------- Lanczos
+
+@pytest.mark.parametrize("M,seed,depth", [(64, 20919, 40), (216, 3, 4)])
+def test_lanczos_blocks_fp64(M, seed, depth):
+    ws, H, rp, col, color, b, sign, mu = water_case(M, seed)
+    ref = block_lanczos(H, color, sign, b, depth, reorth="full", cholqr2=True)
+    A, B, info = css.css_block_lanczos(to_dev(ws), dev_i32(color), dev_i8(sign), b, depth,
+                                       css.PREC_FP64 | css.REORTH_FULL | css.CHOLQR2)
+    assert info["depth_eff"] == ref.v_eff and info["breakdown"] == int(ref.breakdown)
+    for j in range(ref.v_eff):
+        assert np.max(np.abs(A[j].cpu().numpy() - ref.A[j])) < 1e-11, j
+    for j in range(ref.v_eff - 1):
+        assert np.max(np.abs(B[j].cpu().numpy() - ref.B[j])) < 1e-11, j
+    lam_g = np.linalg.eigvalsh(assemble_T([a.cpu().numpy() for a in A], [x.cpu().numpy() for x in B]))
+    lam_o = np.linalg.eigvalsh(assemble_T(ref.A, ref.B))
+    assert np.max(np.abs(lam_g - lam_o)) < 1e-11
+
+
+# ---------------------------------------------------------------- whole path
+
+def _dm_case(M, seed, depth, flags, reorth):
+    ws, H, rp, col, color, b, sign, mu = water_case(M, seed)
+    ref = D.density_matrix(H, color, sign, b, mu, KT, depth, rp, col, reorth=reorth, cholqr2=True)
+    p_val, e_band, trace, info = css.css_density_matrix(to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, depth,
+                                                        dev_i64(rp), dev_i32(col), flags)
+    return ws, ref, p_val.cpu().numpy(), e_band, trace, info
+
+
+@pytest.mark.parametrize("M,seed,depth", [(64, 20919, 40), (125, 11, 6), (216, 3, 40)])
+def test_density_fp64_parity(M, seed, depth):
+    print(f"density fp64 M={M} seed={seed} depth={depth}", flush=True)
+    ws, ref, p, e_band, trace, info = _dm_case(M, seed, depth, FP64_FLAGS, "full")
+    assert info["depth_eff"] == ref["v_eff"]
+    assert np.max(np.abs(p - ref["p_val"])) <= 1e-10
+    assert abs(e_band - ref["e_band"]) <= 1e-10 * abs(ref["e_band"])
+    assert abs(trace - ref["trace"]) <= 1e-10 * abs(ref["trace"])
+    assert abs(info["trace_krylov"] - ref["trace_krylov"]) <= 1e-9
+    assert abs(info["e_band_krylov"] - ref["e_band_krylov"]) <= 1e-9
+    assert abs(info["asym_max"] - ref["asym_max"]) <= 1e-10
+
+
+def test_density_fp64_cfg2_parity():
+    # 1000 molecules, 6000 orbitals, depth 40 (the 1000-H2O FP64 configuration)
+    print("density fp64 cfg2", flush=True)
+    ws, ref, p, e_band, trace, info = _dm_case(1000, 20920, 40, FP64_FLAGS, "full")
+    assert info["depth_eff"] == 40
+    assert np.max(np.abs(p - ref["p_val"])) <= 1e-10
+    assert abs(e_band - ref["e_band"]) <= 1e-10 * abs(ref["e_band"])
+
+
+@pytest.mark.parametrize("M,seed,depth", [(64, 20919, 40), (216, 3, 40)])
+def test_density_fp32_parity(M, seed, depth):
+    print(f"density fp32 M={M}", flush=True)
+    ws, ref, p, e_band, trace, info = _dm_case(M, seed, depth, FP32_FLAGS, "local")
+    err = np.max(np.abs(p - ref["p_val"]))
+    rel_e = abs(e_band - ref["e_band"]) / abs(ref["e_band"])
+    print(f"  fp32 max|dP|={err:.3e} rel dE={rel_e:.3e}", flush=True)
+    assert err <= 1e-5
+    assert rel_e <= 1e-7
+
+
+def test_twopass_matches_stored_basis():
+    ws, H, rp, col, color, b, sign, mu = water_case(216, 3)
+    args = (to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, 12, dev_i64(rp), dev_i32(col))
+    base = css.PREC_FP64 | css.REORTH_LOCAL | css.CHOLQR2 | css.SYMMETRIZE
+    p1, e1, t1, i1 = css.css_density_matrix(*args, base)
+    p2, e2, t2, i2 = css.css_density_matrix(*args, base | css.BASIS_TWOPASS)
+    assert i1["depth_eff"] == i2["depth_eff"]
+    assert torch.max(torch.abs(p1 - p2)).item() <= 1e-13
+    assert abs(e1 - e2) <= 1e-12 * abs(e1)
+
+
+def test_deterministic_bitwise():
+    ws, H, rp, col, color, b, sign, mu = water_case(216, 3)
+    args = (to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, 10, dev_i64(rp), dev_i32(col), FP64_FLAGS)
+    p1, e1, t1, _ = css.css_density_matrix(*args)
+    p1 = p1.clone()
+    p2, e2, t2, _ = css.css_density_matrix(*args)
+    assert torch.equal(p1, p2) and e1 == e2 and t1 == t2
+
+
+# ---------------------------------------------------------------- special cases and errors
+
+def test_scaled_identity_breaks_down_to_closed_form():
+    n, c = 48, -0.37
+    xyz, box = synth.chain_1d(n, 1.0)
+    rp, col, deg = conflict_pattern(xyz, box, 2.0)
+    color, b = greedy_color(rp, col, deg)
+    Hd = css.DeviceCSR.from_host(np.arange(n + 1), np.arange(n), np.full(n, c), "cuda", torch.float64)
+    sign = probe_signs(n, 2)
+    p, e, t, info = css.css_density_matrix(Hd, dev_i32(color), dev_i8(sign), b, -0.4, KT, 6, dev_i64(rp),
+                                           dev_i32(col), FP64_FLAGS)
+    f = 2.0 / (np.exp((c + 0.4) / KT) + 1.0)
+    expect = np.where(D.pattern_rows(rp) == col, f, 0.0)
+    assert info["depth_eff"] == 1 and info["breakdown"] == 1
+    assert np.max(np.abs(p.cpu().numpy() - expect)) < 1e-14
+
+
+def test_every_orbital_its_own_colour_gives_dense_fermi():
+    n = 40
+    rng = np.random.default_rng(8)
+    xyz = rng.uniform(0, 1, size=(n, 3))
+    Hs = synth.random_symmetric_csr(xyz, np.zeros(3), 10.0, seed=9)
+    rp, col, deg = conflict_pattern(xyz, np.zeros(3), 10.0)
+    color, b = greedy_color(rp, col, deg)
+    sign = probe_signs(n, 3)
+    Hd = css.DeviceCSR.from_host(Hs.row_ptr, Hs.col, Hs.val, "cuda", torch.float64)
+    p, e, t, info = css.css_density_matrix(Hd, dev_i32(color), dev_i8(sign), b, 0.05, 0.2, 3, dev_i64(rp),
+                                           dev_i32(col), FP64_FLAGS)
+    P = D.dense_fermi_dm(Hs.to_scipy(), 0.05, 0.2)
+    assert np.max(np.abs(p.cpu().numpy() - P[D.pattern_rows(rp), col])) < 1e-12
+
+
+def test_errors_are_reported():
+    ws, H, rp, col, color, b, sign, mu = water_case(64, 20919)
+    good = (to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, 4, dev_i64(rp), dev_i32(col), FP64_FLAGS)
+    with pytest.raises(css.CssError) as e:
+        css.css_density_matrix(*good[:5], 0.0, *good[6:])          # kT = 0
+    assert e.value.code == 1
+    bad_rp = ws.H.row_ptr.copy()
+    bad_rp[5] = bad_rp[6] + 3
+    Hb = css.DeviceCSR.from_host(bad_rp, ws.H.col, ws.H.val, "cuda", torch.float64)
+    with pytest.raises(css.CssError) as e:
+        css.css_density_matrix(Hb, *good[1:])
+    assert e.value.code == 2
+    vals = ws.H.val.copy()
+    vals[10] = np.nan
+    Hn = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, vals, "cuda", torch.float64)
+    with pytest.raises(css.CssError) as e:
+        css.css_density_matrix(Hn, *good[1:])
+    assert e.value.code == 6
+    bad_color = color.copy()
+    bad_color[3] = b + 2
+    with pytest.raises(css.CssError) as e:
+        css.css_density_matrix(good[0], dev_i32(bad_color), *good[2:])
+    assert e.value.code == 2
