@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the CSS density-matrix path on one MI355X.
+
+One step = the whole hot path on device-resident inputs: conflict pattern and
+greedy colouring (css_color), probes (css_build_probes) and the density
+matrix (css_density_matrix: block Lanczos, subspace diagonalisation, Fermi
+contraction, reconstruction, gather). The metric is orbital*Krylov-steps per
+second, N * v_eff / step time.
+
+Workloads (seeded synthetic water, 6 orbitals per molecule, R_c = 6 A,
+kT = 0.01 Ha, depth 40):
+  10k   10 000 molecules (60 000 orbitals), mixed precision (FP32 blocks with
+        full re-orthogonalisation, FP64 small matrices / eigensolve / sums)
+  1k    1 000 molecules, FP64
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+KT = 0.01
+R_CUT = 6.0
+MU_WATER = -0.41      # mid-gap of the water model (dense spectrum of the 1000-molecule box: -0.4095)
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    "10k": dict(n_mol=10000, seed=20921, depth=40, prec="fp32"),
+    "1k": dict(n_mol=1000, seed=20920, depth=40, prec="fp64"),
+}
+
+
+def flags_for(prec: str):
+    from paper_2605_20918_amd import css
+    if prec == "fp32":
+        return css.PREC_FP32 | css.REORTH_FULL | css.CHOLQR2 | css.SYMMETRIZE
+    return css.PREC_FP64 | css.REORTH_LOCAL | css.CHOLQR2 | css.SYMMETRIZE
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(ws, depth_sample: int, mu: float):
+    """The oracle, as it stands, on a bounded sample of the same workload (reduced depth)."""
+    from threadpoolctl import threadpool_info
+    from oracle import density as D
+    from oracle.coloring import greedy_color
+    from oracle.pattern import conflict_pattern
+    from oracle.probes import probe_signs
+    H = ws.H.to_scipy()
+    t0 = time.perf_counter()
+    rp, col, deg = conflict_pattern(ws.orb_xyz, ws.box, R_CUT)
+    color, b = greedy_color(rp, col, deg)
+    sign = probe_signs(ws.n, ws.seed)
+    r = D.density_matrix(H, color, sign, b, mu, KT, depth_sample, rp, col, reorth="full")
+    dt = time.perf_counter() - t0
+    threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    return {"value": ws.n * r["v_eff"] / dt, "unit": "orbital*steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"same {ws.n_mol}-molecule input at depth {depth_sample} (v_eff={r['v_eff']}): pattern, "
+                      f"colouring, block Lanczos (full reorth), eigensolve, contraction, gather; {dt:.1f} s; "
+                      f"BLAS threads {threads}, SciPy SpMM single-threaded; host {cpu_model()}, nproc {os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="10k", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_20918_amd import css, synth
+    if not torch.cuda.is_available():
+        print("no ROCm device visible", file=sys.stderr)
+        sys.exit(1)
+    css.load()
+    wl = WORKLOADS[args.workload]
+    print(f"[bench] generating {wl['n_mol']} molecules", file=sys.stderr, flush=True)
+    ws = synth.water_system(wl["n_mol"], wl["seed"])
+    dev = torch.device("cuda:0")
+    tdt = torch.float32 if wl["prec"] == "fp32" else torch.float64
+    H = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, dev, tdt)
+    xyz = torch.as_tensor(ws.orb_xyz, dtype=torch.float64, device=dev)
+    box = [float(x) for x in ws.box]
+    flags = flags_for(wl["prec"])
+    depth = wl["depth"]
+    mu = MU_WATER
+    state = {}
+
+    def step(fl=flags):
+        color, b, p_rp, p_col, rounds = css.css_color(xyz, box, R_CUT)
+        sign, _ = css.css_build_probes(color, b, wl["seed"])
+        p_val, e_band, trace, info = css.css_density_matrix(H, color, sign, b, mu, KT, depth, p_rp, p_col, fl)
+        state.update(b=b, nnz_p=int(p_col.numel()), rounds=rounds, e_band=e_band, trace=trace, info=info,
+                     p_val=p_val)
+
+    for i in range(args.warmup):
+        step()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    info = state["info"]
+    v_eff = info["depth_eff"]
+    b = state["b"]
+    print(f"[bench] timed {args.steps} steps: {dt * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # colouring alone (css_color) for the phase table
+    torch.cuda.synchronize()
+    tc = time.perf_counter()
+    css.css_color(xyz, box, R_CUT)
+    torch.cuda.synchronize()
+    t_color = time.perf_counter() - tc
+
+    # SpMM roofline: the same kernel and launch shape as inside the Lanczos loop,
+    # timed with events on the stream it runs on
+    ld = css.block_ld(b)
+    V = torch.zeros((ws.n, ld), dtype=tdt, device=dev)
+    V[:, :b] = torch.randn((ws.n, b), dtype=tdt, device=dev)
+    for _ in range(3):
+        css.css_spmm(H, V, b)
+    reps = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        css.css_spmm(H, V, b)
+    e1.record()
+    torch.cuda.synchronize()
+    t_spmm = e0.elapsed_time(e1) / reps * 1e-3
+    s_val = 4 if tdt == torch.float32 else 8
+    nnz = ws.H.nnz
+    bytes_alg = nnz * (s_val + 4) + 4 * (ws.n + 1) + 2 * ws.n * b * s_val
+    achieved = bytes_alg / t_spmm / 1e9
+
+    out = {
+        "metric": "orbital*Krylov-steps/s (P-build incl. colouring)",
+        "value": ws.n * v_eff / dt,
+        "unit": "orbital*steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if wl["prec"] == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"water {wl['n_mol']} H2O ({ws.n} orbitals), {wl['prec']} blocks, depth {depth}",
+                   "n_orbitals": ws.n, "nnz_H": nnz, "nnz_P": state["nnz_p"], "n_colors": b,
+                   "depth": depth, "depth_eff": v_eff, "kT": KT, "mu": mu, "r_cut": R_CUT,
+                   "flags": flags},
+        "phases_ms": {**info["t_phase_ms"], "colour_probe_total": t_color * 1e3,
+                      "colour_rounds": state["rounds"]},
+        "trace": state["trace"], "e_band": state["e_band"], "trace_krylov": info["trace_krylov"],
+        "roofline": {"bound": "hbm", "kernel": "k_spmm_csr", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "bytes_per_launch": bytes_alg, "avg_launch_us": t_spmm * 1e6},
+    }
+
+    if wl["prec"] == "fp32" and not args.no_fp64:
+        H64 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, dev, torch.float64)
+        Hsave = H
+
+        def step64():
+            color, bb, p_rp, p_col, _ = css.css_color(xyz, box, R_CUT)
+            sign, _ = css.css_build_probes(color, bb, wl["seed"])
+            css.css_density_matrix(H64, color, sign, bb, mu, KT, depth, p_rp, p_col, flags_for("fp64"))
+        step64()
+        torch.cuda.synchronize()
+        t64 = time.perf_counter()
+        step64()
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t64
+        out["fp64_ms_per_step"] = t64 * 1e3
+        out["mixed_vs_fp64_speedup"] = t64 / dt
+        del H64, Hsave
+
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the CPU sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(ws, 6, mu)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
