@@ -70,6 +70,8 @@ enum { CSS_F64 = 0, CSS_F32 = 1 };
 #define CSS_CHOLQR2        0x20u  /* repeat the Cholesky QR once */
 #define CSS_SYMMETRIZE     0x40u  /* return (P + P^T)/2 instead of the raw estimate */
 #define CSS_SIGNS_ONES     0x80u  /* probes with all signs +1 instead of random signs */
+#define CSS_SUBSPACE_EIG   0x100u /* subspace Fermi operator by dense diagonalisation (rocSOLVER)
+                                     instead of the default pole expansion of Eq.(7) */
 
 /* workspace query selectors */
 enum { CSS_ENTRY_COLOR = 0, CSS_ENTRY_LANCZOS = 1, CSS_ENTRY_DENSITY = 2, CSS_ENTRY_SPMM = 3 };
@@ -90,12 +92,12 @@ typedef struct {
     int32_t depth_eff;        /* Krylov blocks actually built (v_eff) */
     int32_t n_colors;         /* b */
     int32_t breakdown;        /* 1 if the recurrence stopped early on a degenerate block */
-    int32_t reserved;
+    int32_t n_poles;          /* poles of the Fermi expansion (0 with CSS_SUBSPACE_EIG) */
     double min_diag_r;        /* smallest diagonal of the Cholesky factors of W^T W */
     double asym_max;          /* max |P_raw - (P_raw + P_raw^T)/2| on the pattern */
     double trace_krylov;      /* sum_k g f(lambda_k) w_k (Krylov quadrature of Tr P) */
     double e_band_krylov;     /* sum_k lambda_k g f(lambda_k) w_k */
-    double t_phase_ms[6];     /* lanczos, eig, contraction, reconstruction, gather, total */
+    double t_phase_ms[6];     /* lanczos, subspace solve, F padding, reconstruction, gather, total */
 } css_info;
 
 /*
@@ -195,6 +197,16 @@ css_status css_density_matrix(const css_csr* H, const int32_t* color, const int8
  */
 css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, int32_t n_colors,
                               int32_t depth, uint32_t flags, size_t* bytes);
+
+/*
+ * css_fermi_poles -- the rational approximation of the Fermi function used for
+ *   the subspace step (host only, no device work). With y = (x - mu)/(2 kT),
+ *   f(x) = 1/2 - (1/2) sum_p c_p y / (1 + kappa_p^2 y^2): the Lambert continued
+ *   fraction of tanh truncated at `depth` (even, 2..512) levels. Returns the
+ *   positive kappa_p and weight_p = c_p / (2 kappa_p) (arrays of depth/2, host,
+ *   either may be NULL) and their count.
+ */
+css_status css_fermi_poles(int32_t depth, double* kappa, double* weight, int32_t* npoles);
 
 /* Leading dimension the library uses for blocks of b columns. */
 int32_t css_block_ld(int32_t n_colors);

@@ -184,42 +184,85 @@ __global__ void k_sort_rows(int n, const int64_t* __restrict__ p_row_ptr, int32_
     }
 }
 
-// One Jones-Plassmann round over all orbitals; coloured ones return at once.
-__global__ void k_jp_round(int n, const int64_t* __restrict__ p_row_ptr,
-                           const int32_t* __restrict__ p_col, const int* __restrict__ deg,
-                           int* color, int* __restrict__ n_new) {
-    int v = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ bool higher_priority(int du, int u, int dv, int v) {
+    return du > dv || (du == dv && u < v);
+}
+
+// Dependency counts: cnt[v] = higher-priority neighbours of v; orbitals with none
+// form the first frontier. One wavefront per orbital.
+__global__ __launch_bounds__(256) void k_jp_init(int n, const int64_t* __restrict__ p_row_ptr,
+                                                 const int32_t* __restrict__ p_col, const int* __restrict__ deg,
+                                                 int* __restrict__ cnt, int* __restrict__ color,
+                                                 int* __restrict__ frontier, int* __restrict__ fsize) {
+    const int lane = threadIdx.x & 63;
+    const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (v >= n) return;
-    if (__hip_atomic_load(&color[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 0) return;
-    int dv = deg[v];
-    int64_t s = p_row_ptr[v], e = p_row_ptr[v + 1];
-    // readiness: every higher-priority neighbour already coloured
-    for (int64_t t = s; t < e; ++t) {
-        int u = p_col[t];
-        if (u == v) continue;
-        int du = deg[u];
-        bool higher = du > dv || (du == dv && u < v);
-        if (higher && __hip_atomic_load(&color[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0)
-            return;
+    const int dv = deg[v];
+    int c = 0;
+    for (int64_t t = p_row_ptr[v] + lane; t < p_row_ptr[v + 1]; t += 64) {
+        const int u = p_col[t];
+        if (u != v && higher_priority(deg[u], u, dv, v)) ++c;
     }
-    // smallest colour not used by the higher-priority neighbours, 64 at a time
-    for (int base = 0;; base += 64) {
-        unsigned long long used = 0ull;
-        for (int64_t t = s; t < e; ++t) {
-            int u = p_col[t];
-            if (u == v) continue;
-            int du = deg[u];
-            bool higher = du > dv || (du == dv && u < v);
-            if (!higher) continue;
-            int cu = __hip_atomic_load(&color[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (cu >= base && cu < base + 64) used |= 1ull << (cu - base);
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if (lane == 0) {
+        cnt[v] = c;
+        color[v] = -1;
+        if (c == 0) frontier[atomicAdd(fsize, 1)] = v;
+    }
+}
+
+// One round: every frontier orbital takes the smallest colour its (all coloured)
+// higher-priority neighbours do not use, then releases its lower-priority
+// neighbours; those whose count drops to zero form the next frontier.
+// sizes[r % 3] is this round's frontier size, sizes[(r+1) % 3] the next one,
+// sizes[(r+2) % 3] is cleared for the round after.
+__global__ __launch_bounds__(256) void k_jp_round(const int64_t* __restrict__ p_row_ptr,
+                                                  const int32_t* __restrict__ p_col, const int* __restrict__ deg,
+                                                  int* __restrict__ cnt, int* color, const int* __restrict__ fin,
+                                                  int* __restrict__ fout, int* sizes, int r, int* __restrict__ done,
+                                                  int* __restrict__ nonempty) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int size_in = sizes[r % 3];
+    if (blockIdx.x == 0 && threadIdx.x == 0) sizes[(r + 2) % 3] = 0;
+    if (size_in == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(nonempty, 1);
+    int* size_out = sizes + (r + 1) % 3;
+    const int nwaves = gridDim.x * 4;
+    for (int i = blockIdx.x * 4 + w; i < size_in; i += nwaves) {
+        const int v = fin[i];
+        const int dv = deg[v];
+        const int64_t s = p_row_ptr[v], e = p_row_ptr[v + 1];
+        int chosen = -1;
+        for (int base = 0; chosen < 0; base += 256) {
+            unsigned long long m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+            for (int64_t t = s + lane; t < e; t += 64) {
+                const int u = p_col[t];
+                if (u == v || !higher_priority(deg[u], u, dv, v)) continue;
+                const int cu = color[u] - base;
+                if (cu >= 0 && cu < 256) {
+                    const unsigned long long bit = 1ull << (cu & 63);
+                    if (cu < 64) m0 |= bit; else if (cu < 128) m1 |= bit; else if (cu < 192) m2 |= bit; else m3 |= bit;
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                m0 |= __shfl_xor(m0, off);
+                m1 |= __shfl_xor(m1, off);
+                m2 |= __shfl_xor(m2, off);
+                m3 |= __shfl_xor(m3, off);
+            }
+            if (~m0) chosen = base + __builtin_ctzll(~m0);
+            else if (~m1) chosen = base + 64 + __builtin_ctzll(~m1);
+            else if (~m2) chosen = base + 128 + __builtin_ctzll(~m2);
+            else if (~m3) chosen = base + 192 + __builtin_ctzll(~m3);
         }
-        if (used != ~0ull) {
-            int c = base + __builtin_ctzll(~used);
-            __hip_atomic_store(&color[v], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            atomicAdd(n_new, 1);
-            return;
+        if (lane == 0) color[v] = chosen;
+        __threadfence();
+        for (int64_t t = s + lane; t < e; t += 64) {
+            const int u = p_col[t];
+            if (u == v || higher_priority(deg[u], u, dv, v)) continue;
+            if (atomicSub(&cnt[u], 1) == 1) fout[atomicAdd(size_out, 1)] = u;
         }
+        if (lane == 0) atomicAdd(done, 1);
     }
 }
 
@@ -325,7 +368,7 @@ Grid make_grid(int n, const double box[3], double r_cut, const double bb[6]) {
 }
 
 struct ColorWs {
-    int *cell_of, *cell_count, *cell_start, *cell_fill, *cell_list, *deg, *scalars;
+    int *cell_of, *cell_count, *cell_start, *cell_fill, *cell_list, *deg, *scalars, *jp_cnt;
     int64_t* block_sum;
     double* bbox;
 };
@@ -339,6 +382,7 @@ ColorWs carve_color(Arena& a, int n) {
     w.cell_fill = a.take<int>(ncell);
     w.cell_list = a.take<int>(n);
     w.deg = a.take<int>(n);
+    w.jp_cnt = a.take<int>(n);
     w.scalars = a.take<int>(64);
     w.block_sum = a.take<int64_t>((n + kScanBlock - 1) / kScanBlock + 1);
     w.bbox = a.take<double>(8);
@@ -434,20 +478,25 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
                                                          w.cell_list, w.deg, p_row_ptr, p_col);
     k_sort_rows<<<n, 256, 0, s>>>(n, p_row_ptr, p_col);
 
-    // Jones-Plassmann rounds with Welsh-Powell priorities
-    k_fill_int<<<grid_for(n, 256), 256, 0, s>>>(color, n, -1);
-    int* n_new = w.scalars + 8;
-    CSS_HIP_TRY(hipMemsetAsync(n_new, 0, sizeof(int), s));
+    // Jones-Plassmann rounds with Welsh-Powell priorities, frontier by frontier
+    int* sizes = w.scalars + 8;      // three rotating frontier sizes
+    int* n_done = w.scalars + 12;
+    CSS_HIP_TRY(hipMemsetAsync(w.scalars + 8, 0, 8 * sizeof(int), s));
+    int* fr[2] = {w.cell_fill, w.cell_list};     // cell arrays are free once the pattern exists
+    k_jp_init<<<grid_for(n, 4), 256, 0, s>>>(n, p_row_ptr, p_col, w.deg, w.jp_cnt, color, fr[0], sizes);
     int done = 0, nround = 0;
-    const int batch = 8;
+    const int batch = 32;
+    const unsigned rgrid = static_cast<unsigned>(std::min<int64_t>(1024, std::max<int64_t>(1, (n + 3) / 4)));
     while (done < n) {
-        for (int r = 0; r < batch; ++r)
-            k_jp_round<<<grid_for(n, 256), 256, 0, s>>>(n, p_row_ptr, p_col, w.deg, color, n_new);
-        nround += batch;
-        CSS_HIP_TRY(hipMemcpyAsync(&done, n_new, sizeof(int), hipMemcpyDeviceToHost, s));
+        for (int r = 0; r < batch; ++r, ++nround)
+            k_jp_round<<<rgrid, 256, 0, s>>>(p_row_ptr, p_col, w.deg, w.jp_cnt, color, fr[nround & 1],
+                                             fr[(nround + 1) & 1], sizes, nround % 3, n_done, n_done + 1);
+        CSS_HIP_TRY(hipMemcpyAsync(&done, n_done, sizeof(int), hipMemcpyDeviceToHost, s));
         CSS_HIP_TRY(hipStreamSynchronize(s));
-        if (nround > n + batch) return CSS_E_DEVICE;     // cannot happen: each round colours >= 1
+        if (nround > n + batch) return CSS_E_DEVICE;     // cannot happen: every round colours >= 1
     }
+    int real_rounds = 0;
+    CSS_HIP_TRY(hipMemcpyAsync(&real_rounds, n_done + 1, sizeof(int), hipMemcpyDeviceToHost, s));
     CSS_HIP_TRY(hipMemsetAsync(w.scalars, 0xff, sizeof(int), s));
     CSS_HIP_TRY(hipMemsetAsync(w.scalars + 1, 0, sizeof(int), s));
     k_max_color<<<64, 256, 0, s>>>(color, n, w.scalars, w.scalars + 1, p_row_ptr);
@@ -455,6 +504,6 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
     CSS_HIP_TRY(hipMemcpyAsync(&hc, w.scalars, sizeof(int), hipMemcpyDeviceToHost, s));
     CSS_HIP_TRY(hipStreamSynchronize(s));
     *n_colors = hc + 1;
-    if (rounds) *rounds = nround;
+    if (rounds) *rounds = real_rounds;
     return CSS_OK;
 }

@@ -26,11 +26,11 @@ void gram_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, dou
 
 // OUT = alpha*IN + sum_p X_p * op_p(S_p),  op_p(S) = scale * (trans ? S^T : S)
 // X_p = X + p*xstride (tall), S_p = S + p*sstride (small FP64). OUT may equal IN;
-// OUT must not alias any X_p.
+// OUT must not alias any X_p. stage: nprod*ld*ld elements of T (scratch).
 template <typename T>
 void update_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, int nprod,
                    const double* S, int64_t sstride, bool trans, double scale, int64_t Np, int ld,
-                   const int* state, hipStream_t s);
+                   void* stage, const int* state, hipStream_t s);
 
 // Cholesky G = R^T R of the leading b x b block, R and R^-1 (ld x ld, zero
 // elsewhere). On failure (non-positive pivot, non-finite, min diag <= tau) sets

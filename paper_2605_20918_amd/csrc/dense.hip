@@ -49,119 +49,196 @@ struct MF<float> {
 
 // ------------------------------------------------------------------ Gram
 
-template <typename T>
-__global__ __launch_bounds__(64) void k_gram(const T* __restrict__ X, int64_t xstride,
-                                             const T* __restrict__ Y, int64_t Np, int64_t rpc, int ld,
-                                             int tpd, int sym, double* __restrict__ partial, int nchunk,
-                                             const int* __restrict__ state) {
+// One workgroup (2 x 2 waves) computes a (32 TW) x (32 TW) tile of X_p^T Y over a
+// chunk of rows for product p = blockIdx.z, writing one partial per (p, chunk).
+// Wave (wi, wj) owns the 16TW x 16TW sub-tile; with sym the strictly lower
+// wave tile is skipped (mirrored by the reduction).
+template <typename T, typename PT, int TW>
+__global__ __launch_bounds__(256) void k_gram(const T* __restrict__ X, int64_t xstride,
+                                              const T* __restrict__ Y, int64_t Np, int64_t rpc, int ld, int ntw,
+                                              int sym, PT* __restrict__ partial, int nchunk,
+                                              const int* __restrict__ state) {
     if (state && state[0]) return;
     typedef MF<T> M;
-    const int l = threadIdx.x, lr = l >> 4, lc = l & 15;
-    const int chunk = blockIdx.x, p = blockIdx.z;
-    int ti, tj;
-    if (sym) {
-        int rem = blockIdx.y, cnt = tpd;
-        ti = 0;
-        while (rem >= cnt) { rem -= cnt; ++ti; --cnt; }
-        tj = ti + rem;
-    } else {
-        ti = blockIdx.y / tpd;
-        tj = blockIdx.y % tpd;
-    }
-    const int i0 = ti * 32, j0 = tj * 32;
-    const bool vi1 = i0 + 16 < ld, vj1 = j0 + 16 < ld;
-    typename M::acc c00 = M::zero(), c01 = M::zero(), c10 = M::zero(), c11 = M::zero();
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, lr = l >> 4, lc = l & 15;
+    const int wi = w & 1, wj = w >> 1;
+    const int I0 = (blockIdx.y / ntw) * 32 * TW, J0 = (blockIdx.y % ntw) * 32 * TW;
+    const int i0 = I0 + wi * 16 * TW, j0 = J0 + wj * 16 * TW;
+    if (i0 >= ld || j0 >= ld) return;
+    if (sym && i0 > j0 + 16 * TW - 16) return;          // wave tile entirely below the diagonal
+    const int chunk = blockIdx.x;
     const int64_t r0 = (int64_t)chunk * rpc;
     const int64_t r1 = r0 + rpc < Np ? r0 + rpc : Np;
-    const T* xa = X + (int64_t)p * xstride + (r0 + lr) * ld + i0 + lc;
-    const T* ya = Y + (r0 + lr) * ld + j0 + lc;
-    const int64_t step = 4 * (int64_t)ld;
-#pragma unroll 4
-    for (int64_t r = r0; r < r1; r += 4, xa += step, ya += step) {
-        const T a0 = xa[0], b0 = ya[0];
-        const T a1 = vi1 ? xa[16] : T(0);
-        const T b1 = vj1 ? ya[16] : T(0);
-        c00 = M::mma(a0, b0, c00);
-        c01 = M::mma(a0, b1, c01);
-        c10 = M::mma(a1, b0, c10);
-        c11 = M::mma(a1, b1, c11);
-    }
-    double* out = partial + ((int64_t)p * nchunk + chunk) * ld * ld;
+    bool vi[TW], vj[TW];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int ra = i0 + M::row(l, r), rb = ra + 16, ca = j0 + lc, cb = ca + 16;
-        out[(int64_t)ra * ld + ca] = c00[r];
-        if (vj1) out[(int64_t)ra * ld + cb] = c01[r];
-        if (vi1) out[(int64_t)rb * ld + ca] = c10[r];
-        if (vi1 && vj1) out[(int64_t)rb * ld + cb] = c11[r];
+    for (int a = 0; a < TW; ++a) { vi[a] = i0 + 16 * a < ld; vj[a] = j0 + 16 * a < ld; }
+    const int64_t step = 4 * (int64_t)ld;
+    {
+        const int p = blockIdx.z;
+        typename M::acc c[TW][TW];
+#pragma unroll
+        for (int a = 0; a < TW; ++a)
+#pragma unroll
+            for (int b = 0; b < TW; ++b) c[a][b] = M::zero();
+        const T* xa = X + (int64_t)p * xstride + (r0 + lr) * ld + i0 + lc;
+        const T* ya = Y + (r0 + lr) * ld + j0 + lc;
+        for (int64_t r = r0; r < r1; r += 4, xa += step, ya += step) {
+            T av[TW], bv[TW];
+#pragma unroll
+            for (int a = 0; a < TW; ++a) {
+                av[a] = vi[a] ? xa[16 * a] : T(0);
+                bv[a] = vj[a] ? ya[16 * a] : T(0);
+            }
+#pragma unroll
+            for (int a = 0; a < TW; ++a)
+#pragma unroll
+                for (int b = 0; b < TW; ++b) c[a][b] = M::mma(av[a], bv[b], c[a][b]);
+        }
+        PT* out = partial + ((int64_t)p * nchunk + chunk) * ld * ld;
+#pragma unroll
+        for (int a = 0; a < TW; ++a)
+#pragma unroll
+            for (int b = 0; b < TW; ++b)
+                if (vi[a] && vj[b]) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = i0 + 16 * a + M::row(l, r), col = j0 + 16 * b + lc;
+                        out[(int64_t)row * ld + col] = PT(c[a][b][r]);
+                    }
+                }
     }
 }
 
-__global__ void k_gram_reduce(const double* __restrict__ partial, int nchunk, int ld, int sym, int mode,
-                              double* __restrict__ out, int64_t out_stride, const int* __restrict__ state) {
+// Sum of the chunk partials in a fixed order: thread group g (of 4) adds chunks
+// g, g+4, ... for 64 consecutive entries, then the four group sums are added
+// in order. mode 0: plain; 1: (S + S^T)/2; 2: out += (S + S^T)/2.
+template <typename PT>
+__global__ __launch_bounds__(256) void k_gram_reduce(const PT* __restrict__ partial, int nchunk, int ld, int sym,
+                                                     int mode, double* __restrict__ out, int64_t out_stride,
+                                                     const int* __restrict__ state) {
     if (state && state[0]) return;
+    __shared__ double s1s[4][64], s2s[4][64];
     const int p = blockIdx.y;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ld * ld) return;
-    const int i = idx / ld, j = idx % ld;
+    const int g = threadIdx.x >> 6, e = threadIdx.x & 63;
+    const int idx = blockIdx.x * 64 + e;
     const int64_t mat = (int64_t)ld * ld;
-    const double* base = partial + (int64_t)p * nchunk * mat;
-    const int64_t sij = (sym && (i >> 5) > (j >> 5)) ? (int64_t)j * ld + i : (int64_t)i * ld + j;
-    double s1 = 0.0;
-    for (int c = 0; c < nchunk; ++c) s1 += base[c * mat + sij];
-    double v = s1;
-    if (mode != 0) {
-        const int64_t sji = (sym && (j >> 5) > (i >> 5)) ? (int64_t)i * ld + j : (int64_t)j * ld + i;
-        double s2 = 0.0;
-        for (int c = 0; c < nchunk; ++c) s2 += base[c * mat + sji];
-        v = 0.5 * (s1 + s2);
+    const bool valid = idx < ld * ld;
+    const int i = valid ? idx / ld : 0, j = valid ? idx % ld : 0;
+    const int64_t sij = (sym && i > j) ? (int64_t)j * ld + i : (int64_t)i * ld + j;
+    const int64_t sji = (sym && j > i) ? (int64_t)i * ld + j : (int64_t)j * ld + i;
+    const PT* base = partial + (int64_t)p * nchunk * mat;
+    double s1 = 0.0, s2 = 0.0;
+    if (valid) {
+        for (int c = g; c < nchunk; c += 4) s1 += (double)base[c * mat + sij];
+        if (mode != 0)
+            for (int c = g; c < nchunk; c += 4) s2 += (double)base[c * mat + sji];
     }
-    double* o = out + p * out_stride + idx;
-    if (mode == 2)
-        *o += v;
-    else
-        *o = v;
+    s1s[g][e] = s1;
+    s2s[g][e] = s2;
+    __syncthreads();
+    if (g == 0 && valid) {
+        const double t1 = ((s1s[0][e] + s1s[1][e]) + s1s[2][e]) + s1s[3][e];
+        double v = t1;
+        if (mode != 0) {
+            const double t2 = ((s2s[0][e] + s2s[1][e]) + s2s[2][e]) + s2s[3][e];
+            v = 0.5 * (t1 + t2);
+        }
+        double* o = out + p * out_stride + idx;
+        if (mode == 2)
+            *o += v;
+        else
+            *o = v;
+    }
 }
 
 // ------------------------------------------------------------------ update
 
+// OUT = alpha IN + sum_p X_p S'_p with S'_p already in the block precision (and
+// transposed / scaled by the caller's staging kernel). A workgroup owns 64*MT
+// rows (4 waves x 16*MT) and up to 16*NTW columns; S'_p is staged through LDS
+// 32 rows of K at a time, double buffered, and the X fragments of a K chunk
+// are fetched before the chunk's LDS barrier.
+constexpr int kKC = 32;
+
 template <typename T, int MT, int NTW>
 __global__ __launch_bounds__(256) void k_update(T* OUT, const T* IN, double alpha, const T* __restrict__ X,
-                                                int64_t xstride, int nprod, const double* __restrict__ S,
-                                                int64_t sstride, int trans, double scale, int64_t Np, int ld,
-                                                const int* __restrict__ state) {
+                                                int64_t xstride, int nprod, const T* __restrict__ S,
+                                                int64_t Np, int ld, const int* __restrict__ state) {
     if (state && state[0]) return;
     typedef MF<T> M;
+    constexpr int NC = 16 * NTW;                              // columns per workgroup
+    constexpr int SP = NC + (sizeof(T) == 8 ? 8 : 16);        // padded LDS row
+    constexpr int PER = (kKC * NC + 255) / 256;               // staged elements per thread
+    __shared__ T sS[2][kKC * SP];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, lr = l >> 4, lc = l & 15;
     const int64_t m0 = ((int64_t)blockIdx.x * 4 + w) * (16 * MT);
-    if (m0 >= Np) return;
-    const int jt0 = blockIdx.y * NTW;
-    const int ntw = min(NTW, ld / 16 - jt0);
+    const int jc0 = blockIdx.y * NC;
+    const int ntw = min(NTW, (ld - jc0) / 16);
+    const bool active = m0 < Np;
+    const int64_t mat = (int64_t)ld * ld;
+    const int nkc = (ld + kKC - 1) / kKC;
+    const int total = nprod * nkc;
     typename M::acc c[MT][NTW];
 #pragma unroll
     for (int a = 0; a < MT; ++a)
 #pragma unroll
         for (int b = 0; b < NTW; ++b) c[a][b] = M::zero();
-    for (int p = 0; p < nprod; ++p) {
-        const T* __restrict__ Xp = X + (int64_t)p * xstride + (m0 + lc) * ld + lr;
-        const double* __restrict__ Sp = S + (int64_t)p * sstride;
-        for (int k0 = 0; k0 < ld; k0 += 4) {
-            T a[MT];
+
+    auto fetch_s = [&](int it, T (&reg)[PER]) {
+        const int p = it / nkc, kc = (it % nkc) * kKC;
+        const T* Sp = S + (int64_t)p * mat;
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) a[mt] = Xp[(int64_t)16 * mt * ld + k0];
-            const int k = k0 + lr;
+        for (int q = 0; q < PER; ++q) {
+            const int t = threadIdx.x + 256 * q;
+            const int kk = t / NC, jj = t % NC;
+            const int k = kc + kk, j = jc0 + jj;
+            reg[q] = (t < kKC * NC && k < ld && j < ld) ? Sp[(int64_t)k * ld + j] : T(0);
+        }
+    };
+    auto store_s = [&](int buf, const T (&reg)[PER]) {
 #pragma unroll
-            for (int nt = 0; nt < NTW; ++nt) {
-                if (nt < ntw) {
-                    const int j = (jt0 + nt) * 16 + lc;
-                    const double sv = trans ? Sp[(int64_t)j * ld + k] : Sp[(int64_t)k * ld + j];
-                    const T bv = T(scale * sv);
+        for (int q = 0; q < PER; ++q) {
+            const int t = threadIdx.x + 256 * q;
+            if (t < kKC * NC) sS[buf][(t / NC) * SP + t % NC] = reg[q];
+        }
+    };
+    T sreg[PER];
+    fetch_s(0, sreg);
+    store_s(0, sreg);
+    for (int it = 0; it < total; ++it) {
+        const int buf = it & 1;
+        const int p = it / nkc, kc = (it % nkc) * kKC;
+        const int kend = min(kKC, ld - kc);
+        // X fragments of this chunk (issued before the barrier)
+        T xa[kKC / 4][MT];
+        if (active) {
+            const T* __restrict__ Xp = X + (int64_t)p * xstride + (m0 + lc) * ld + kc + lr;
 #pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) c[mt][nt] = M::mma(a[mt], bv, c[mt][nt]);
+            for (int k4 = 0; k4 < kKC / 4; ++k4)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    xa[k4][mt] = (4 * k4 < kend) ? Xp[(int64_t)16 * mt * ld + 4 * k4] : T(0);
+        }
+        if (it + 1 < total) fetch_s(it + 1, sreg);
+        __syncthreads();                                  // chunk `it` staged in sS[buf]
+        if (active) {
+#pragma unroll
+            for (int k4 = 0; k4 < kKC / 4; ++k4) {
+                if (4 * k4 < kend) {
+#pragma unroll
+                    for (int nt = 0; nt < NTW; ++nt) {
+                        if (nt < ntw) {
+                            const T bv = sS[buf][(4 * k4 + lr) * SP + nt * 16 + lc];
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt) c[mt][nt] = M::mma(xa[k4][mt], bv, c[mt][nt]);
+                        }
+                    }
                 }
             }
         }
+        if (it + 1 < total) store_s(buf ^ 1, sreg);       // other buffer: last read before the barrier above
     }
+    if (!active) return;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -170,7 +247,7 @@ __global__ __launch_bounds__(256) void k_update(T* OUT, const T* IN, double alph
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int64_t row = m0 + 16 * mt + M::row(l, r);
-                    const int col = (jt0 + nt) * 16 + lc;
+                    const int col = jc0 + nt * 16 + lc;
                     const int64_t idx = row * ld + col;
                     double v = (double)c[mt][nt][r];
                     if (IN != nullptr && alpha != 0.0) v += alpha * (double)IN[idx];
@@ -180,8 +257,182 @@ __global__ __launch_bounds__(256) void k_update(T* OUT, const T* IN, double alph
         }
 }
 
+// S'_p = scale * (trans ? S_p^T : S_p) in the block precision.
+template <typename T>
+__global__ void k_stage_s(const double* __restrict__ S, int64_t sstride, int nprod, int ld, int trans,
+                          double scale, T* __restrict__ out) {
+    const int64_t mat = (int64_t)ld * ld;
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= nprod * mat) return;
+    const int64_t p = idx / mat;
+    const int k = (int)((idx % mat) / ld), j = (int)(idx % ld);
+    const double* Sp = S + p * sstride;
+    out[idx] = T(scale * (trans ? Sp[(int64_t)j * ld + k] : Sp[(int64_t)k * ld + j]));
+}
+
 // ------------------------------------------------------------------ small FP64
 
+// Cholesky G = R^T R (R upper) and R^-1 for b <= 16*NB with a 16 x 16 thread grid;
+// thread (ty, tx) keeps entries (ty + 16a, tx + 16c) in registers.
+template <int NB>
+__global__ __launch_bounds__(256) void k_chol_inv_reg(const double* __restrict__ G, int b, int ld,
+                                                      const double* __restrict__ tau_p, double* __restrict__ R,
+                                                      double* __restrict__ Rinv, int* state, int step,
+                                                      double* __restrict__ min_diag) {
+    __shared__ double rowk[16 * NB];
+    __shared__ double colk[16 * NB];
+    __shared__ double rdiag[16 * NB];
+    __shared__ double rinvd[16 * NB];
+    __shared__ int fail;
+    __shared__ double dmin;
+    if (state[0]) return;
+    const double tau = tau_p ? *tau_p : 0.0;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double m[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            const int i = ty + 16 * a, j = tx + 16 * c;
+            m[a][c] = (i < b && j < b && j >= i) ? G[(int64_t)i * ld + j] : 0.0;
+        }
+    if (threadIdx.x == 0) { fail = 0; dmin = INFINITY; }
+    __syncthreads();
+    for (int k = 0; k < b; ++k) {
+        const int ka = k >> 4, kt = k & 15;
+        if (ty == kt && tx == kt) {                 // owner of (k, k) takes the pivot
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+                if (a == ka) {
+                    const double piv = m[a][a];
+                    if (!(piv > 0.0) || !isfinite(piv)) {
+                        fail = 1;
+                    } else {
+                        const double d = sqrt(piv);
+                        dmin = fmin(dmin, d);
+                        if (!(d > tau)) fail = 1;
+                        rdiag[k] = d;
+                        rinvd[k] = 1.0 / d;
+                    }
+                }
+        }
+        __syncthreads();
+        if (fail) break;
+        const double d = rdiag[k], dinv = rinvd[k];
+        if (ty == kt) {                             // owners of row k scale it and publish it
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+                if (a == ka) {
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) {
+                        const int j = tx + 16 * c;
+                        if (j > k && j < b) {
+                            m[a][c] *= dinv;
+                            rowk[j] = m[a][c];
+                        } else if (j == k) {
+                            m[a][c] = d;
+                        }
+                    }
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {              // trailing update of the upper triangle
+            const int i = ty + 16 * a;
+            if (i > k && i < b) {
+                const double rki = rowk[i];
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    const int j = tx + 16 * c;
+                    if (j >= i && j < b) m[a][c] -= rki * rowk[j];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) min_diag[step] = dmin;
+    if (fail) {
+        for (int idx = threadIdx.x; idx < ld * ld; idx += 256) { Rinv[idx] = 0.0; R[idx] = 0.0; }
+        __syncthreads();
+        if (threadIdx.x == 0) { state[2] = step; state[0] = 1; }
+        return;
+    }
+    // R to global (zero outside the upper b x b triangle)
+    for (int idx = threadIdx.x; idx < ld * ld; idx += 256) {
+        const int i = idx / ld, j = idx % ld;
+        if (i >= 16 * NB || j >= 16 * NB || i >= b || j >= b || j < i) R[idx] = 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            const int i = ty + 16 * a, j = tx + 16 * c;
+            if (i < b && j < b && j >= i) R[(int64_t)i * ld + j] = m[a][c];
+        }
+    // R^-1 = X by back substitution, X initialised to the identity: row i of X is
+    // final once divided by R[i][i]; then X[i'][:] -= R[i'][i] X[i][:] for i' < i
+    double x[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) x[a][c] = ((ty + 16 * a) == (tx + 16 * c)) ? 1.0 : 0.0;
+    for (int i = b - 1; i >= 0; --i) {
+        const int ia = i >> 4, it = i & 15;
+        if (ty == it) {
+            const double rii = rinvd[i];
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+                if (a == ia) {
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) {
+                        const int j = tx + 16 * c;
+                        if (j < b) {
+                            x[a][c] *= rii;
+                            rowk[j] = x[a][c];
+                        }
+                    }
+                }
+        }
+        if (tx == it) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+                if (c == ia) {
+#pragma unroll
+                    for (int a = 0; a < NB; ++a) {
+                        const int ip = ty + 16 * a;
+                        if (ip < i) colk[ip] = m[a][c];
+                    }
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+            const int ip = ty + 16 * a;
+            if (ip < i) {
+                const double r = colk[ip];
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    const int j = tx + 16 * c;
+                    if (j >= i && j < b) x[a][c] -= r * rowk[j];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < ld * ld; idx += 256) {
+        const int i = idx / ld, j = idx % ld;
+        if (i >= 16 * NB || j >= 16 * NB || i >= b || j >= b || j < i) Rinv[idx] = 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            const int i = ty + 16 * a, j = tx + 16 * c;
+            if (i < b && j < b && j >= i) Rinv[(int64_t)i * ld + j] = x[a][c];
+        }
+}
+
+// General-size fallback (global-memory working set).
 __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, int b, int ld,
                                                   const double* __restrict__ tau_p,
                                                   double* __restrict__ R, double* __restrict__ Rinv,
@@ -338,16 +589,21 @@ int64_t gram_partial_mats(int ld) {
     return std::min<int64_t>(1024, std::max<int64_t>(64, m));
 }
 
+namespace {
+int gram_tw(int ld) { return ld <= 64 ? 2 : (ld <= 96 ? 3 : 4); }
+}
+
 GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t cap_mats) {
     GramPlan g;
     g.ld = ld;
     g.nprod = nprod;
     g.Np = Np;
     g.sym = sym;
-    const int tpd = (ld + 31) / 32;
-    g.ntiles = sym ? tpd * (tpd + 1) / 2 : tpd * tpd;
-    int64_t want = (4096 + (int64_t)g.ntiles * nprod - 1) / ((int64_t)g.ntiles * nprod);
-    int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(want, cap_mats / std::max(1, nprod)));
+    const int tile = 32 * gram_tw(ld);
+    const int ntw = (ld + tile - 1) / tile;
+    g.ntiles = ntw * ntw;
+    int64_t nchunk = (1024 + (int64_t)g.ntiles * nprod - 1) / ((int64_t)g.ntiles * nprod);
+    nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, cap_mats / std::max(1, nprod)));
     nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, Np / 64));
     int64_t rpc = (Np + nchunk - 1) / nchunk;
     rpc = (rpc + 3) / 4 * 4;
@@ -359,33 +615,65 @@ GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t cap_mats) {
 template <typename T>
 void gram_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, double* partial, double* out,
                  int64_t out_stride, int mode, const int* state, hipStream_t s) {
-    const int tpd = (g.ld + 31) / 32;
+    const int tw = gram_tw(g.ld);
+    const int ntw = (g.ld + 32 * tw - 1) / (32 * tw);
+    T* part = reinterpret_cast<T*>(partial);      // partials in the block precision
     dim3 grid(g.nchunk, g.ntiles, g.nprod);
-    k_gram<T><<<grid, 64, 0, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, tpd, g.sym ? 1 : 0, partial,
-                                  g.nchunk, state);
-    dim3 rgrid(grid_for((int64_t)g.ld * g.ld, 256), g.nprod);
-    k_gram_reduce<<<rgrid, 256, 0, s>>>(partial, g.nchunk, g.ld, g.sym ? 1 : 0, mode, out, out_stride, state);
+    if (tw == 2)
+        k_gram<T, T, 2><<<grid, 256, 0, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw, g.sym ? 1 : 0,
+                                             part, g.nchunk, state);
+    else if (tw == 3)
+        k_gram<T, T, 3><<<grid, 256, 0, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw, g.sym ? 1 : 0,
+                                             part, g.nchunk, state);
+    else
+        k_gram<T, T, 4><<<grid, 256, 0, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw, g.sym ? 1 : 0,
+                                             part, g.nchunk, state);
+    dim3 rgrid(grid_for((int64_t)g.ld * g.ld, 64), g.nprod);
+    k_gram_reduce<T><<<rgrid, 256, 0, s>>>(part, g.nchunk, g.ld, g.sym ? 1 : 0, mode, out, out_stride, state);
+}
+
+template <typename T, int NTW>
+void update_one(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, int nprod, const T* S, int64_t Np,
+                int ld, const int* state, hipStream_t s) {
+    constexpr int MT = 2;
+    const int64_t rows_per_block = 4 * 16 * MT;
+    dim3 grid(static_cast<unsigned>((Np + rows_per_block - 1) / rows_per_block), (ld + 16 * NTW - 1) / (16 * NTW));
+    k_update<T, MT, NTW><<<grid, 256, 0, s>>>(OUT, IN, alpha, X, xstride, nprod, S, Np, ld, state);
 }
 
 template <typename T>
 void update_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, int nprod, const double* S,
-                   int64_t sstride, bool trans, double scale, int64_t Np, int ld, const int* state,
+                   int64_t sstride, bool trans, double scale, int64_t Np, int ld, void* stage, const int* state,
                    hipStream_t s) {
-    constexpr int MT = 2, NTW = 8;
-    const int64_t rows_per_block = 4 * 16 * MT;
-    dim3 grid(static_cast<unsigned>((Np + rows_per_block - 1) / rows_per_block), (ld / 16 + NTW - 1) / NTW);
-    k_update<T, MT, NTW><<<grid, 256, 0, s>>>(OUT, IN, alpha, X, xstride, nprod, S, sstride, trans ? 1 : 0, scale,
-                                               Np, ld, state);
+    T* st = static_cast<T*>(stage);
+    const int64_t cnt = (int64_t)nprod * ld * ld;
+    k_stage_s<T><<<grid_for(cnt, 256), 256, 0, s>>>(S, sstride, nprod, ld, trans ? 1 : 0, scale, st);
+    const int nt = ld / 16;
+    if (nt <= 2)
+        update_one<T, 2>(OUT, IN, alpha, X, xstride, nprod, st, Np, ld, state, s);
+    else if (nt <= 4)
+        update_one<T, 4>(OUT, IN, alpha, X, xstride, nprod, st, Np, ld, state, s);
+    else if (nt <= 6)
+        update_one<T, 6>(OUT, IN, alpha, X, xstride, nprod, st, Np, ld, state, s);
+    else
+        update_one<T, 8>(OUT, IN, alpha, X, xstride, nprod, st, Np, ld, state, s);
 }
 
 size_t chol_scratch_bytes(int b) { return sizeof(double) * ((size_t)b * (b + 1) + b + 8); }
 
-void chol_inv_launch(const double* G, int b, int ld, const double* tau, double* R, double* Rinv,
-                     double* scratch, int* state, int step, double* min_diag, hipStream_t s) {
+void chol_inv_launch(const double* G, int b, int ld, const double* tau, double* R, double* Rinv, double* scratch,
+                     int* state, int step, double* min_diag, hipStream_t s) {
+    if (b <= 128) {
+        switch ((b + 15) / 16) {
+#define CSS_CHOL(NB) case NB: k_chol_inv_reg<NB><<<1, 256, 0, s>>>(G, b, ld, tau, R, Rinv, state, step, min_diag); return;
+            CSS_CHOL(1) CSS_CHOL(2) CSS_CHOL(3) CSS_CHOL(4) CSS_CHOL(5) CSS_CHOL(6) CSS_CHOL(7) CSS_CHOL(8)
+#undef CSS_CHOL
+            default: break;
+        }
+    }
     const size_t bytes = chol_scratch_bytes(b);
     const bool lds = bytes + 64 <= (size_t)max_lds_bytes();
-    k_chol_inv<<<1, 256, lds ? bytes : 0, s>>>(G, b, ld, tau, R, Rinv, scratch, state, step, min_diag,
-                                               lds ? 1 : 0);
+    k_chol_inv<<<1, 256, lds ? bytes : 0, s>>>(G, b, ld, tau, R, Rinv, scratch, state, step, min_diag, lds ? 1 : 0);
 }
 
 void trmm_upper_launch(const double* R2, const double* R1, double* R, int ld, const int* state, hipStream_t s) {
@@ -411,8 +699,8 @@ template void gram_launch<double>(const GramPlan&, const double*, int64_t, const
 template void gram_launch<float>(const GramPlan&, const float*, int64_t, const float*, double*, double*, int64_t,
                                  int, const int*, hipStream_t);
 template void update_launch<double>(double*, const double*, double, const double*, int64_t, int, const double*,
-                                    int64_t, bool, double, int64_t, int, const int*, hipStream_t);
+                                    int64_t, bool, double, int64_t, int, void*, const int*, hipStream_t);
 template void update_launch<float>(float*, const float*, double, const float*, int64_t, int, const double*,
-                                   int64_t, bool, double, int64_t, int, const int*, hipStream_t);
+                                   int64_t, bool, double, int64_t, int, void*, const int*, hipStream_t);
 
 }  // namespace css

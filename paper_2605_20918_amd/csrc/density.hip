@@ -24,6 +24,7 @@
 #include "css_common.h"
 #include "dense.h"
 #include "driver.h"
+#include "subspace.h"
 
 namespace css {
 
@@ -259,13 +260,16 @@ void det_max(const double* v, int64_t n, double* tmp, double* out, hipStream_t s
 struct DmPlan {
     LzPlan lz;
     int nTmax = 0;
+    bool use_eig = false;     // dense diagonalisation (rocSOLVER) instead of the pole expansion
     size_t eig_ws = 0;
+    size_t pole_ws = 0;
     bool sep_X = false;
 };
 
 struct DmBufs {
     LzBufs lz;
     double *T = nullptr, *lam = nullptr, *E = nullptr, *Y = nullptr, *F = nullptr, *Fpad = nullptr;
+    void* pole_ws = nullptr;
     double *t0 = nullptr, *t1 = nullptr, *rows = nullptr, *tmp = nullptr, *res = nullptr;
     int* flags = nullptr;
     void* X = nullptr;
@@ -276,10 +280,10 @@ void carve_dm(Arena& a, const DmPlan& p, DmBufs& bf) {
     carve_lanczos(a, p.lz, bf.lz);
     const int64_t nT = p.nTmax;
     const int64_t mat = (int64_t)p.lz.ld * p.lz.ld;
-    bf.T = a.take<double>(nT * nT);
+    bf.T = p.use_eig ? a.take<double>(nT * nT) : nullptr;
     bf.lam = a.take<double>(nT);
     bf.E = a.take<double>(nT);
-    bf.Y = a.take<double>(nT * p.lz.b);
+    bf.Y = p.use_eig ? a.take<double>(nT * p.lz.b) : nullptr;
     bf.F = a.take<double>(nT * p.lz.b);
     bf.Fpad = a.take<double>(std::max(1, p.lz.v_max) * mat);
     bf.t0 = a.take<double>(nT);
@@ -290,13 +294,21 @@ void carve_dm(Arena& a, const DmPlan& p, DmBufs& bf) {
     bf.flags = a.take<int>(16);
     bf.X = p.sep_X ? a.take<char>((size_t)p.lz.Np * p.lz.ld * p.lz.elem) : bf.lz.W;
     bf.eig_ws = p.eig_ws ? a.take<char>(p.eig_ws) : nullptr;
+    bf.pole_ws = p.pole_ws ? a.take<char>(p.pole_ws) : nullptr;
 }
 
 css_status plan_dm(const css_csr* H, int32_t b, int32_t depth, uint32_t flags, DmPlan& p) {
     CSS_TRY(plan_lanczos(H, b, depth, flags, p.lz));
     p.nTmax = std::max(1, p.lz.v_max) * b;
     p.sep_X = p.lz.twopass;
-    p.eig_ws = eig_workspace_bytes(p.nTmax);
+    p.use_eig = (flags & CSS_SUBSPACE_EIG) != 0;
+    if (p.use_eig) {
+        p.eig_ws = eig_workspace_bytes(p.nTmax);
+        if (p.eig_ws == 0) return CSS_E_DEVICE;
+    } else {
+        if (b > 128) return CSS_E_UNSUPPORTED;
+        p.pole_ws = pole_workspace_bytes(std::max(1, p.lz.v_max), b);
+    }
     return CSS_OK;
 }
 
@@ -328,7 +340,6 @@ extern "C" css_status css_density_matrix(const css_csr* H, const int32_t* color,
     if (!(kT > 0.0) || !std::isfinite(kT) || !std::isfinite(mu) || !(spin_deg > 0.0)) return CSS_E_ARG;
     DmPlan p;
     CSS_TRY(plan_dm(H, n_colors, depth, flags, p));
-    if (p.eig_ws == 0) return CSS_E_DEVICE;
     if (ws_bytes < dm_workspace_bytes(p)) return CSS_E_WORKSPACE;
     Arena a;
     a.base = static_cast<char*>(ws);
@@ -361,27 +372,34 @@ extern "C" css_status css_density_matrix(const css_csr* H, const int32_t* color,
     CSS_TRY(run_lanczos_pass1(H, color, sign, lz, bf.lz, s, &v_eff, &brk, &md));
     CSS_HIP_TRY(hipEventRecord(ev[1], s));
 
-    // projected matrix and its eigenpairs
+    // Fermi operator in the Krylov subspace: F = g f(T) E_1 B_0 and the quadrature sums
     const int nT = v_eff * lz.b;
-    CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
-    k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T, bf.flags);
-    int hbad = 0;
-    CSS_HIP_TRY(hipMemcpyAsync(&hbad, bf.flags, sizeof(int), hipMemcpyDeviceToHost, s));
-    CSS_HIP_TRY(hipStreamSynchronize(s));
-    if (hbad) return CSS_E_NONFINITE;
-    CSS_TRY(eig(bf.T, nT, bf.lam, bf.E, bf.flags + 1, bf.eig_ws, p.eig_ws, s));
-    CSS_HIP_TRY(hipEventRecord(ev[2], s));
-
-    // contraction F = U diag(g f) U_top^T B_0 and quadrature
-    k_occ_y<<<grid_for((int64_t)nT * lz.b, 256), 256, 0, s>>>(bf.T, bf.lam, bf.lz.counts, nT, lz.b, mu, kT, spin_deg,
-                                                                bf.Y);
-    gemm_f64_launch(nT, lz.b, nT, bf.T, 1, nT, bf.Y, lz.b, 1, bf.F, lz.b, 1, s);
     const int64_t mat = (int64_t)lz.ld * lz.ld;
+    int npoles = 0;
+    if (p.use_eig) {
+        CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+        k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T,
+                                                                     bf.flags);
+        int hbad = 0;
+        CSS_HIP_TRY(hipMemcpyAsync(&hbad, bf.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+        CSS_HIP_TRY(hipStreamSynchronize(s));
+        if (hbad) return CSS_E_NONFINITE;
+        CSS_TRY(eig(bf.T, nT, bf.lam, bf.E, bf.flags + 1, bf.eig_ws, p.eig_ws, s));
+        CSS_HIP_TRY(hipEventRecord(ev[2], s));
+        k_occ_y<<<grid_for((int64_t)nT * lz.b, 256), 256, 0, s>>>(bf.T, bf.lam, bf.lz.counts, nT, lz.b, mu, kT,
+                                                                    spin_deg, bf.Y);
+        gemm_f64_launch(nT, lz.b, nT, bf.T, 1, nT, bf.Y, lz.b, 1, bf.F, lz.b, 1, s);
+        k_quad_terms<<<grid_for(nT, 256), 256, 0, s>>>(bf.T, bf.lam, bf.lz.counts, nT, lz.b, mu, kT, spin_deg, bf.t0,
+                                                       bf.t1);
+        det_sum(bf.t0, nT, bf.tmp, bf.res + 2, s);
+        det_sum(bf.t1, nT, bf.tmp + kSumBlocks, bf.res + 3, s);
+    } else {
+        CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+        CSS_TRY(subspace_fermi_poles(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.lz.counts, mu, kT, spin_deg, bf.F,
+                                     bf.res + 2, bf.pole_ws, p.pole_ws, &npoles, s));
+        CSS_HIP_TRY(hipEventRecord(ev[2], s));
+    }
     k_pad_F<<<grid_for(v_eff * mat, 256), 256, 0, s>>>(bf.F, v_eff, lz.b, lz.ld, bf.Fpad);
-    k_quad_terms<<<grid_for(nT, 256), 256, 0, s>>>(bf.T, bf.lam, bf.lz.counts, nT, lz.b, mu, kT, spin_deg, bf.t0,
-                                                   bf.t1);
-    det_sum(bf.t0, nT, bf.tmp, bf.res + 2, s);
-    det_sum(bf.t1, nT, bf.tmp + kSumBlocks, bf.res + 3, s);
     CSS_HIP_TRY(hipEventRecord(ev[3], s));
 
     // reconstruction X = sum_j Q_j F_j
@@ -389,11 +407,11 @@ extern "C" css_status css_density_matrix(const css_csr* H, const int32_t* color,
         CSS_TRY(run_lanczos_pass2(H, color, sign, lz, bf.lz, v_eff, bf.Fpad, bf.X, s));
     } else if (lz.fp32) {
         update_launch<float>(static_cast<float*>(bf.X), nullptr, 0.0, static_cast<const float*>(slot_ptr(lz, bf.lz, 0)),
-                             lz.Np * lz.ld, v_eff, bf.Fpad, mat, false, 1.0, lz.Np, lz.ld, nullptr, s);
+                             lz.Np * lz.ld, v_eff, bf.Fpad, mat, false, 1.0, lz.Np, lz.ld, bf.lz.stage, nullptr, s);
     } else {
         update_launch<double>(static_cast<double*>(bf.X), nullptr, 0.0,
                               static_cast<const double*>(slot_ptr(lz, bf.lz, 0)), lz.Np * lz.ld, v_eff, bf.Fpad, mat,
-                              false, 1.0, lz.Np, lz.ld, nullptr, s);
+                              false, 1.0, lz.Np, lz.ld, bf.lz.stage, nullptr, s);
     }
     CSS_HIP_TRY(hipEventRecord(ev[4], s));
 
@@ -432,6 +450,7 @@ extern "C" css_status css_density_matrix(const css_csr* H, const int32_t* color,
         info->breakdown = brk;
         info->min_diag_r = md;
         info->asym_max = hres[4];
+        info->n_poles = npoles;
         info->trace_krylov = hres[2];
         info->e_band_krylov = hres[3];
         for (int k = 0; k < 5; ++k) {
@@ -467,7 +486,6 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
     if (entry == CSS_ENTRY_DENSITY) {
         DmPlan p;
         CSS_TRY(plan_dm(&H, n_colors, depth, flags, p));
-        if (p.eig_ws == 0) return CSS_E_DEVICE;
         *bytes = dm_workspace_bytes(p);
         return CSS_OK;
     }

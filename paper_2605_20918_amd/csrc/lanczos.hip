@@ -168,7 +168,8 @@ struct Step {
     }
     void update(T* out, const T* in, double alpha, const T* X, int64_t xstride, int nprod, const double* S,
                 int64_t sstride, bool trans, double scale) const {
-        update_launch<T>(out, in, alpha, X, xstride, nprod, S, sstride, trans, scale, p.Np, p.ld, bf.state, s);
+        update_launch<T>(out, in, alpha, X, xstride, nprod, S, sstride, trans, scale, p.Np, p.ld, bf.stage, bf.state,
+                         s);
     }
 
     // Step j (0-based). replay: regenerate Q_{j+1} from stored coefficients
@@ -344,8 +345,11 @@ css_status plan_lanczos(const css_csr* H, int32_t b, int32_t depth, uint32_t fla
     p.convert_h = (p.fp32 && H->val_dtype == CSS_F64) || (!p.fp32 && H->val_dtype == CSS_F32);
     p.nslots = p.twopass ? 3 : std::max(1, p.v_max);
     p.max_coef = p.reorth == 2 ? p.v_max : (p.reorth == 1 ? 2 : 0);
-    const int64_t by_rows = std::max<int64_t>(1, p.Np / 64) * std::max(1, p.max_coef);
-    p.partial_mats = std::max<int64_t>(1, std::min<int64_t>(gram_partial_mats(p.ld), std::max<int64_t>(by_rows, 64)));
+    // partial Gram buffers: enough chunks for a single product, and at least 32
+    // chunks per product for the batched full re-orthogonalisation Gram
+    const int64_t single = std::min<int64_t>(gram_partial_mats(p.ld), std::max<int64_t>(1, p.Np / 64));
+    const int64_t batched = std::min<int64_t>(32, std::max<int64_t>(1, p.Np / 64)) * std::max(1, p.max_coef);
+    p.partial_mats = std::max<int64_t>(1, std::max(single, batched));
     return CSS_OK;
 }
 
@@ -367,6 +371,7 @@ void carve_lanczos(Arena& a, const LzPlan& p, LzBufs& bf) {
     bf.R1 = a.take<double>(mat);
     bf.R2 = a.take<double>(mat);
     bf.partial = a.take<double>(p.partial_mats * mat);
+    bf.stage = a.take<double>((int64_t)std::max({2, p.v_max, p.max_coef}) * mat);
     bf.chol_scratch = a.take<double>(chol_scratch_bytes(p.b) / sizeof(double) + 1);
     bf.min_diag = a.take<double>(2 * v);
     bf.scal = a.take<double>(16);

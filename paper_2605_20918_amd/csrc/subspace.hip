@@ -1,0 +1,428 @@
+// Fermi-Dirac operator inside the Krylov subspace by a pole expansion of Eq.(7).
+//
+// Eq.(7) writes rho^K as a contour integral of f(z) times the resolvent
+// (z - H^K)^-1. Only F = g f(T) E_1 B_0 (T = H^K, block tridiagonal with v
+// blocks of b) is needed. This file evaluates it as a finite sum of
+// resolvents instead of diagonalising T:
+//
+//   f(x) = (1 - tanh(y))/2,  y = (x - mu)/(2 kT),
+//   tanh(y) ~ sum_p c_p y / (1 + kappa_p^2 y^2)      (truncated Lambert continued fraction)
+//
+// The truncation at depth M equals y [(D + i y E)^-1]_11 with D = diag(1,3,5,..)
+// and E the tridiagonal of ones; with K = D^-1/2 E D^-1/2 = W diag(kappa) W^T
+// the poles are y = +-i/kappa_p and c_p = 2 W[0,p]^2 (kappa_p > 0). Each term
+// is  Y (I + kappa^2 Y^2)^-1 = Im[(I - i kappa Y)^-1] / kappa, so with Y = (T - mu)/(2kT)
+//
+//   F = g [ E_1 B_0 / 2 - sum_p (c_p / (2 kappa_p)) Im Z_p ],
+//   (I - i kappa_p Y) Z_p = E_1 B_0.
+//
+// I - i kappa Y has all singular values >= 1 and positive definite Hermitian
+// part, so its block elimination needs no pivoting and is well conditioned.
+// Each Z_p comes from Schur complements taken from the last block upward,
+//   S_v = D_v,  S_j = D_j - U_j S_{j+1}^-1 L_{j+1},  G_j = S_j^-1 L_j,
+//   Z_1 = S_1^-1 R_1,  Z_{j+1} = -G_{j+1} Z_j,
+// with D_j = I - i a (A_j - mu), L_{j+1} = -i a B_j, U_j = -i a B_j^T, a = kappa/(2kT).
+// The truncation depth is chosen from a Gershgorin bound of T so that the
+// rational approximation error stays near double-precision rounding.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "css_common.h"
+#include "subspace.h"
+
+namespace css {
+namespace {
+
+// ------------------------------------------------------------------ host: pole table
+
+// Eigenvalues of a symmetric tridiagonal matrix (diagonal d, off-diagonal e[i] between
+// i and i+1) and the first component of each eigenvector, by implicit QL with
+// Wilkinson-type shifts, rotating only the first row of the eigenvector matrix.
+void tridiag_eig_first_row(std::vector<double>& d, std::vector<double> e, std::vector<double>& z) {
+    const int n = static_cast<int>(d.size());
+    z.assign(n, 0.0);
+    z[0] = 1.0;
+    e.push_back(0.0);
+    for (int l = 0; l < n; ++l) {
+        for (int iter = 0; iter < 200; ++iter) {
+            int m = l;
+            for (; m < n - 1; ++m) {
+                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) <= 1e-300 + 2.2e-16 * dd) break;
+            }
+            if (m == l) break;
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+            double s = 1.0, c = 1.0, p = 0.0;
+            int i = m - 1;
+            for (; i >= l; --i) {
+                const double f = s * e[i], b = c * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {
+                    d[i + 1] -= p;
+                    e[m] = 0.0;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2.0 * c * b;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - b;
+                const double zf = z[i + 1];
+                z[i + 1] = s * z[i] + c * zf;
+                z[i] = c * z[i] - s * zf;
+            }
+            if (r == 0.0 && i >= l) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[m] = 0.0;
+        }
+    }
+}
+
+struct PoleTable {
+    std::vector<double> kappa, weight;   // weight = c_p / (2 kappa_p)
+};
+
+std::mutex g_pole_mu;
+std::map<int, PoleTable> g_poles;
+
+const PoleTable& pole_table(int M) {
+    std::lock_guard<std::mutex> lock(g_pole_mu);
+    auto it = g_poles.find(M);
+    if (it != g_poles.end()) return it->second;
+    std::vector<double> d(M, 0.0), e(M - 1), z;
+    for (int k = 0; k + 1 < M; ++k) e[k] = 1.0 / std::sqrt((2.0 * k + 1.0) * (2.0 * k + 3.0));
+    tridiag_eig_first_row(d, e, z);
+    PoleTable t;
+    for (int p = 0; p < M; ++p)
+        if (d[p] > 1e-12) {
+            t.kappa.push_back(d[p]);
+            t.weight.push_back(2.0 * z[p] * z[p] / (2.0 * d[p]));
+        }
+    return g_poles.emplace(M, std::move(t)).first->second;
+}
+
+// Truncation depth for |y| <= ymax with error near 1e-15 (measured: 26 poles reach
+// |y| = 80, 40 poles 160, 54 poles 320); a margin of 10 poles is added.
+int depth_for(double ymax) {
+    const int M = 52 + static_cast<int>(std::ceil(0.35 * std::min(1e6, std::max(0.0, ymax))));
+    return (M + 1) / 2 * 2;
+}
+constexpr int kMaxDepth = 512;       // at most 256 poles (|y| up to about 1300)
+
+// ------------------------------------------------------------------ device
+
+// Gershgorin interval of T, one thread per row: lo[row], hi[row].
+__global__ void k_gersh(const double* __restrict__ A, const double* __restrict__ B, int v, int b, int ld,
+                        double* __restrict__ lo, double* __restrict__ hi) {
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= v * b) return;
+    const int j = row / b, r = row % b;
+    const int64_t mat = (int64_t)ld * ld;
+    double rad = 0.0;
+    for (int c = 0; c < b; ++c)
+        if (c != r) rad += fabs(A[j * mat + (int64_t)r * ld + c]);
+    if (j > 0)
+        for (int c = 0; c < b; ++c) rad += fabs(B[(j - 1) * mat + (int64_t)r * ld + c]);
+    if (j + 1 < v)
+        for (int c = 0; c < b; ++c) rad += fabs(B[j * mat + (int64_t)c * ld + r]);
+    const double dg = A[j * mat + (int64_t)r * ld + r];
+    lo[row] = dg - rad;
+    hi[row] = dg + rad;
+}
+
+__global__ void k_minmax(const double* __restrict__ lo, const double* __restrict__ hi, int n, double* __restrict__ out) {
+    __shared__ double smin[256], smax[256];
+    double a = INFINITY, z = -INFINITY;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        a = fmin(a, lo[i]);
+        z = fmax(z, hi[i]);
+    }
+    smin[threadIdx.x] = a;
+    smax[threadIdx.x] = z;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = smin[0]; out[1] = smax[0]; }
+}
+
+constexpr int kPoleThreads = 1024;
+constexpr int kMaxPer = 16;          // b*b / kPoleThreads entries per thread (b <= 128)
+
+// One workgroup per pole: backward Schur sweep with in-place Gauss-Jordan inversion
+// of each complex b x b Schur complement (no pivoting), then the forward sweep.
+// Writes W_p = weight_p * Im Z_p (nT x b, row-major) for pole p = blockIdx.x.
+__global__ __launch_bounds__(kPoleThreads) void k_pole_solve(const double* __restrict__ A, const double* __restrict__ B,
+                                                             int v, int b, int ld, double mu, double inv2kT,
+                                                             const double* __restrict__ kappa,
+                                                             const double* __restrict__ weight,
+                                                             const int* __restrict__ counts, double* Gbuf,
+                                                             double* Sglob, int use_lds, double* __restrict__ Wout) {
+    extern __shared__ double lds[];
+    __shared__ double colr[128], coli[128], pinv[2];
+    const int p = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int bb = b * b;
+    const int64_t mat = (int64_t)ld * ld;
+    const double a = kappa[p] * inv2kT;
+    const double wgt = weight[p];
+    double* Sr = use_lds ? lds : Sglob + (int64_t)p * 2 * bb;
+    double* Si = Sr + bb;
+    double* Gp = Gbuf + (int64_t)p * v * 2 * bb;          // G_j at Gp + j*2bb (Re, then Im)
+    double* Wp = Wout + (int64_t)p * v * bb;
+    const int per = (bb + kPoleThreads - 1) / kPoleThreads;
+
+    for (int j = v - 1; j >= 0; --j) {
+        // S = I - i a (A_j - mu) + i a B_j^T G_{j+1}
+        const double* Aj = A + j * mat;
+        for (int q = 0; q < per; ++q) {
+            const int e = tid + kPoleThreads * q;
+            if (e >= bb) break;
+            const int r = e / b, c = e % b;
+            double sr = (r == c) ? 1.0 : 0.0;
+            double si = -a * (Aj[(int64_t)r * ld + c] - (r == c ? mu : 0.0));
+            if (j + 1 < v) {
+                const double* Bj = B + j * mat;
+                const double* Gr = Gp + (int64_t)(j + 1) * 2 * bb;
+                const double* Gi = Gr + bb;
+                double tr = 0.0, ti = 0.0;
+                for (int k = 0; k < b; ++k) {
+                    const double bk = Bj[(int64_t)k * ld + r];
+                    tr += bk * Gr[k * b + c];
+                    ti += bk * Gi[k * b + c];
+                }
+                sr -= a * ti;
+                si += a * tr;
+            }
+            Sr[e] = sr;
+            Si[e] = si;
+        }
+        __syncthreads();
+        // Gauss-Jordan inverse in place
+        for (int k = 0; k < b; ++k) {
+            if (tid == 0) {
+                const double xr = Sr[k * b + k], xi = Si[k * b + k];
+                const double den = 1.0 / (xr * xr + xi * xi);
+                pinv[0] = xr * den;
+                pinv[1] = -xi * den;
+            }
+            if (tid < b) {
+                colr[tid] = Sr[tid * b + k];
+                coli[tid] = Si[tid * b + k];
+            }
+            __syncthreads();
+            const double qr = pinv[0], qi = pinv[1];
+            // scaled pivot row: row k * pinv (entry k becomes pinv)
+            for (int c = tid; c < b; c += kPoleThreads) {
+                const double xr = (c == k) ? 1.0 : Sr[k * b + c], xi = (c == k) ? 0.0 : Si[k * b + c];
+                Sr[k * b + c] = xr * qr - xi * qi;
+                Si[k * b + c] = xr * qi + xi * qr;
+            }
+            __syncthreads();
+            for (int q = 0; q < per; ++q) {
+                const int e = tid + kPoleThreads * q;
+                if (e >= bb) break;
+                const int r = e / b, c = e % b;
+                if (r == k) continue;
+                const double fr = colr[r], fi = coli[r];
+                const double xr = (c == k) ? 0.0 : Sr[e], xi = (c == k) ? 0.0 : Si[e];
+                const double pr = Sr[k * b + c], pi = Si[k * b + c];
+                Sr[e] = xr - (fr * pr - fi * pi);
+                Si[e] = xi - (fr * pi + fi * pr);
+            }
+            __syncthreads();
+        }
+        if (j > 0) {
+            // G_j = S^-1 L_j = -i a S^-1 B_{j-1}
+            const double* Bm = B + (j - 1) * mat;
+            double* Gr = Gp + (int64_t)j * 2 * bb;
+            double* Gi = Gr + bb;
+            for (int q = 0; q < per; ++q) {
+                const int e = tid + kPoleThreads * q;
+                if (e >= bb) break;
+                const int r = e / b, c = e % b;
+                double tr = 0.0, ti = 0.0;
+                for (int k = 0; k < b; ++k) {
+                    const double bk = Bm[(int64_t)k * ld + c];
+                    tr += Sr[r * b + k] * bk;
+                    ti += Si[r * b + k] * bk;
+                }
+                Gr[e] = a * ti;
+                Gi[e] = -a * tr;
+            }
+            __syncthreads();
+        }
+    }
+    // forward sweep: Z_1 = S_1^-1 B_0 (column scaling by sqrt(n_c)), Z_{j+1} = -G_{j+1} Z_j
+    for (int q = 0; q < per; ++q) {
+        const int e = tid + kPoleThreads * q;
+        if (e >= bb) break;
+        const double sc = sqrt((double)counts[e % b]);
+        Sr[e] *= sc;
+        Si[e] *= sc;
+        Wp[e] = wgt * Si[e];
+    }
+    __syncthreads();
+    for (int j = 1; j < v; ++j) {
+        const double* Gr = Gp + (int64_t)j * 2 * bb;
+        const double* Gi = Gr + bb;
+        double nr[kMaxPer], ni[kMaxPer];
+        for (int q = 0; q < per; ++q) {
+            const int e = tid + kPoleThreads * q;
+            nr[q] = 0.0;
+            ni[q] = 0.0;
+            if (e >= bb) continue;
+            const int r = e / b, c = e % b;
+            double tr = 0.0, ti = 0.0;
+            for (int k = 0; k < b; ++k) {
+                const double gr = Gr[r * b + k], gi = Gi[r * b + k];
+                const double zr = Sr[k * b + c], zi = Si[k * b + c];
+                tr += gr * zr - gi * zi;
+                ti += gr * zi + gi * zr;
+            }
+            nr[q] = -tr;
+            ni[q] = -ti;
+        }
+        __syncthreads();
+        for (int q = 0; q < per; ++q) {
+            const int e = tid + kPoleThreads * q;
+            if (e >= bb) break;
+            Sr[e] = nr[q];
+            Si[e] = ni[q];
+            Wp[(int64_t)j * bb + e] = wgt * ni[q];
+        }
+        __syncthreads();
+    }
+}
+
+// F = g (E_1 B_0 / 2 - sum_p W_p), poles summed in order.
+__global__ void k_pole_sum(const double* __restrict__ Wout, int npole, int64_t nTb, int b,
+                           const int* __restrict__ counts, double g, double* __restrict__ F) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= nTb) return;
+    double s = 0.0;
+    for (int p = 0; p < npole; ++p) s += Wout[(int64_t)p * nTb + idx];
+    const int64_t row = idx / b;
+    const int c = (int)(idx % b);
+    const double e1b0 = (row == c) ? sqrt((double)counts[c]) : 0.0;
+    F[idx] = g * (0.5 * e1b0 - s);
+}
+
+// trace_K = sum_c sqrt(n_c) F[c][c];  E_K = sum_c sqrt(n_c) (A_1 F_1 + B_1^T F_2)[c][c]
+__global__ void k_krylov_sums(const double* __restrict__ A, const double* __restrict__ B, const double* __restrict__ F,
+                              const int* __restrict__ counts, int v, int b, int ld, double* __restrict__ out) {
+    __shared__ double st[256], se[256];
+    double t = 0.0, e = 0.0;
+    for (int c = threadIdx.x; c < b; c += 256) {
+        const double sc = sqrt((double)counts[c]);
+        t += sc * F[(int64_t)c * b + c];
+        double tf = 0.0;
+        for (int k = 0; k < b; ++k) tf += A[(int64_t)c * ld + k] * F[(int64_t)k * b + c];
+        if (v > 1)
+            for (int k = 0; k < b; ++k) tf += B[(int64_t)k * ld + c] * F[(int64_t)(b + k) * b + c];
+        e += sc * tf;
+    }
+    st[threadIdx.x] = t;
+    se[threadIdx.x] = e;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            st[threadIdx.x] += st[threadIdx.x + s];
+            se[threadIdx.x] += se[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = st[0]; out[1] = se[0]; }
+}
+
+int max_lds() {
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0, val = 65536;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&val, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+            cached = val;
+        else
+            cached = 65536;
+    }
+    return cached;
+}
+
+}  // namespace
+
+size_t pole_workspace_bytes(int v, int b) {
+    const int64_t np = kMaxDepth / 2 + 1;
+    const int64_t bb = (int64_t)b * b;
+    return sizeof(double) * (size_t)(np * (v * 2 * bb + v * bb + 2 * bb) + 2 * np + 2 * (int64_t)v * b + 16) + 4096;
+}
+
+css_status subspace_fermi_poles(const double* A, const double* B, int v, int b, int ld, const int* counts,
+                                double mu, double kT, double g, double* F, double* sums, void* ws, size_t ws_bytes,
+                                int* npoles_out, hipStream_t s) {
+    if (b > 128) return CSS_E_UNSUPPORTED;
+    const int nT = v * b;
+    const int64_t bb = (int64_t)b * b;
+    Arena ar;
+    ar.base = static_cast<char*>(ws);
+    ar.cap = ws_bytes;
+    double* glo = ar.take<double>(nT);
+    double* ghi = ar.take<double>(nT);
+    double* range = ar.take<double>(16);
+    k_gersh<<<grid_for(nT, 256), 256, 0, s>>>(A, B, v, b, ld, glo, ghi);
+    k_minmax<<<1, 256, 0, s>>>(glo, ghi, nT, range);
+    double hr[2];
+    CSS_HIP_TRY(hipMemcpyAsync(hr, range, sizeof(hr), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    if (!std::isfinite(hr[0]) || !std::isfinite(hr[1])) return CSS_E_NONFINITE;
+    const double ymax = std::max(std::fabs(hr[0] - mu), std::fabs(hr[1] - mu)) / (2.0 * kT);
+    const int M = depth_for(ymax);
+    if (M > kMaxDepth) return CSS_E_UNSUPPORTED;       // spectrum too wide for kT: more than 256 poles
+    const PoleTable& pt = pole_table(M);
+    const int np = static_cast<int>(pt.kappa.size());
+    double* kap = ar.take<double>(np);
+    double* wgt = ar.take<double>(np);
+    double* Gbuf = ar.take<double>((int64_t)np * v * 2 * bb);
+    double* Wout = ar.take<double>((int64_t)np * v * bb);
+    const size_t lds_bytes = sizeof(double) * 2 * bb;
+    const bool use_lds = lds_bytes + 4096 <= (size_t)max_lds();
+    double* Sg = use_lds ? nullptr : ar.take<double>((int64_t)np * 2 * bb);
+    if (ar.overflow) return CSS_E_WORKSPACE;
+    CSS_HIP_TRY(hipMemcpyAsync(kap, pt.kappa.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+    CSS_HIP_TRY(hipMemcpyAsync(wgt, pt.weight.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+    k_pole_solve<<<np, kPoleThreads, use_lds ? lds_bytes : 0, s>>>(A, B, v, b, ld, mu, 1.0 / (2.0 * kT), kap, wgt,
+                                                                    counts, Gbuf, Sg, use_lds ? 1 : 0, Wout);
+    k_pole_sum<<<grid_for((int64_t)nT * b, 256), 256, 0, s>>>(Wout, np, (int64_t)nT * b, b, counts, g, F);
+    k_krylov_sums<<<1, 256, 0, s>>>(A, B, F, counts, v, b, ld, sums);
+    if (npoles_out) *npoles_out = np;
+    CSS_HIP_TRY(hipGetLastError());
+    return CSS_OK;
+}
+
+}  // namespace css
+
+extern "C" css_status css_fermi_poles(int32_t depth, double* kappa, double* weight, int32_t* npoles) {
+    if (depth < 2 || depth > css::kMaxDepth || (depth & 1) || !npoles) return CSS_E_ARG;
+    const css::PoleTable& t = css::pole_table(depth);
+    *npoles = static_cast<int32_t>(t.kappa.size());
+    for (size_t i = 0; i < t.kappa.size(); ++i) {
+        if (kappa) kappa[i] = t.kappa[i];
+        if (weight) weight[i] = t.weight[i];
+    }
+    return CSS_OK;
+}

@@ -35,6 +35,7 @@ REORTH_FULL = 0x10
 CHOLQR2 = 0x20
 SYMMETRIZE = 0x40
 SIGNS_ONES = 0x80
+SUBSPACE_EIG = 0x100
 
 ENTRY_COLOR, ENTRY_LANCZOS, ENTRY_DENSITY, ENTRY_SPMM = 0, 1, 2, 3
 
@@ -52,16 +53,17 @@ class CsrStruct(ctypes.Structure):
 
 class InfoStruct(ctypes.Structure):
     _fields_ = [("depth_eff", ctypes.c_int32), ("n_colors", ctypes.c_int32), ("breakdown", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("min_diag_r", ctypes.c_double), ("asym_max", ctypes.c_double),
+                ("n_poles", ctypes.c_int32), ("min_diag_r", ctypes.c_double), ("asym_max", ctypes.c_double),
                 ("trace_krylov", ctypes.c_double), ("e_band_krylov", ctypes.c_double),
                 ("t_phase_ms", ctypes.c_double * 6)]
 
     def as_dict(self) -> dict:
         return {"depth_eff": self.depth_eff, "n_colors": self.n_colors, "breakdown": self.breakdown,
+                "n_poles": self.n_poles,
                 "min_diag_r": self.min_diag_r, "asym_max": self.asym_max, "trace_krylov": self.trace_krylov,
                 "e_band_krylov": self.e_band_krylov,
                 "t_phase_ms": {k: self.t_phase_ms[i] for i, k in
-                               enumerate(["lanczos", "eig", "contraction", "reconstruction", "gather", "total"])}}
+                               enumerate(["lanczos", "subspace", "f_pad", "reconstruction", "gather", "total"])}}
 
 
 _lib = None
@@ -92,6 +94,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.css_density_matrix.argtypes = [pcsr, vp, vp, i32, dbl, dbl, i32, dbl, vp, vp, i64, u32, vp,
                                        ctypes.POINTER(dbl), ctypes.POINTER(dbl), pinfo, vp, sz, vp]
     lib.css_workspace_size.argtypes = [i32, i32, i64, i32, i32, u32, ctypes.POINTER(sz)]
+    lib.css_fermi_poles.argtypes = [i32, vp, vp, ctypes.POINTER(i32)]
+    lib.css_fermi_poles.restype = i32
     lib.css_block_ld.argtypes = [i32]
     lib.css_block_ld.restype = i32
     lib.css_status_string.argtypes = [i32]
@@ -163,6 +167,19 @@ class DeviceCSR:
         torch = _torch()
         dt = CSS_F64 if self.val.dtype == torch.float64 else CSS_F32
         return CsrStruct(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr(), dt)
+
+
+def fermi_poles(depth: int):
+    """(kappa, weight) of the truncated continued-fraction Fermi expansion (host only)."""
+    import numpy as np
+    lib = load()
+    n = ctypes.c_int32(0)
+    _check("css_fermi_poles", lib.css_fermi_poles(depth, None, None, ctypes.byref(n)))
+    kap = np.zeros(n.value)
+    wgt = np.zeros(n.value)
+    _check("css_fermi_poles", lib.css_fermi_poles(depth, kap.ctypes.data_as(ctypes.c_void_p),
+                                                  wgt.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+    return kap, wgt
 
 
 def block_ld(n_colors: int) -> int:

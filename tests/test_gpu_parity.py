@@ -123,6 +123,7 @@ def test_lanczos_blocks_fp64(M, seed, depth):
 # ---------------------------------------------------------------- whole path
 
 def _dm_case(M, seed, depth, flags, reorth):
+    """GPU path with the given flags against the oracle (exact diagonalisation of T)."""
     ws, H, rp, col, color, b, sign, mu = water_case(M, seed)
     ref = D.density_matrix(H, color, sign, b, mu, KT, depth, rp, col, reorth=reorth, cholqr2=True)
     p_val, e_band, trace, info = css.css_density_matrix(to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, depth,
@@ -130,10 +131,12 @@ def _dm_case(M, seed, depth, flags, reorth):
     return ws, ref, p_val.cpu().numpy(), e_band, trace, info
 
 
+@pytest.mark.parametrize("subspace", ["poles", "eig"])
 @pytest.mark.parametrize("M,seed,depth", [(64, 20919, 40), (125, 11, 6), (216, 3, 40)])
-def test_density_fp64_parity(M, seed, depth):
-    print(f"density fp64 M={M} seed={seed} depth={depth}", flush=True)
-    ws, ref, p, e_band, trace, info = _dm_case(M, seed, depth, FP64_FLAGS, "full")
+def test_density_fp64_parity(M, seed, depth, subspace):
+    print(f"density fp64 M={M} seed={seed} depth={depth} subspace={subspace}", flush=True)
+    flags = FP64_FLAGS | (css.SUBSPACE_EIG if subspace == "eig" else 0)
+    ws, ref, p, e_band, trace, info = _dm_case(M, seed, depth, flags, "full")
     assert info["depth_eff"] == ref["v_eff"]
     assert np.max(np.abs(p - ref["p_val"])) <= 1e-10
     assert abs(e_band - ref["e_band"]) <= 1e-10 * abs(ref["e_band"])
@@ -143,10 +146,12 @@ def test_density_fp64_parity(M, seed, depth):
     assert abs(info["asym_max"] - ref["asym_max"]) <= 1e-10
 
 
-def test_density_fp64_cfg2_parity():
+@pytest.mark.parametrize("subspace", ["poles", "eig"])
+def test_density_fp64_cfg2_parity(subspace):
     # 1000 molecules, 6000 orbitals, depth 40 (the 1000-H2O FP64 configuration)
-    print("density fp64 cfg2", flush=True)
-    ws, ref, p, e_band, trace, info = _dm_case(1000, 20920, 40, FP64_FLAGS, "full")
+    print(f"density fp64 cfg2 subspace={subspace}", flush=True)
+    flags = FP64_FLAGS | (css.SUBSPACE_EIG if subspace == "eig" else 0)
+    ws, ref, p, e_band, trace, info = _dm_case(1000, 20920, 40, flags, "full")
     assert info["depth_eff"] == 40
     assert np.max(np.abs(p - ref["p_val"])) <= 1e-10
     assert abs(e_band - ref["e_band"]) <= 1e-10 * abs(ref["e_band"])
