@@ -16,7 +16,7 @@ struct GramPlan {
     int64_t Np, rows_per_chunk;
     bool sym;
 };
-GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t partial_cap_mats);
+GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t partial_cap_mats, int elem);
 int64_t gram_partial_mats(int ld);                 // capacity (in ld x ld matrices) to reserve
 
 // mode: 0 = plain, 1 = (S + S^T)/2, 2 = add (S + S^T)/2 into out (out += sym)

@@ -49,75 +49,104 @@ struct MF<float> {
 
 // ------------------------------------------------------------------ Gram
 
-// One workgroup (2 x 2 waves) computes a (32 TW) x (32 TW) tile of X_p^T Y over a
-// chunk of rows for product p = blockIdx.z, writing one partial per (p, chunk).
-// Wave (wi, wj) owns the 16TW x 16TW sub-tile; with sym the strictly lower
-// wave tile is skipped (mirrored by the reduction).
-template <typename T, typename PT, int TW>
-__global__ __launch_bounds__(256) void k_gram(const T* __restrict__ X, int64_t xstride,
-                                              const T* __restrict__ Y, int64_t Np, int64_t rpc, int ld, int ntw,
-                                              int sym, PT* __restrict__ partial, int nchunk,
-                                              const int* __restrict__ state) {
+// One workgroup computes a (32 TW) x (32 TW) tile of X_p^T Y over a chunk of rows
+// for product p = blockIdx.z, writing one partial per (p, chunk). The workgroup
+// has KS groups of 2 x 2 waves; group g takes the 4-row steps g, g+KS, ... of the
+// chunk, and the KS group tiles are added in order through LDS. Wave (wi, wj)
+// of a group owns a 16TW x 16TW sub-tile; with sym the strictly lower wave tile
+// is skipped (the reduction mirrors it).
+template <typename T, typename PT, int TW, int KS>
+__global__ __launch_bounds__(256 * KS) void k_gram(const T* __restrict__ X, int64_t xstride,
+                                                   const T* __restrict__ Y, int64_t Np, int64_t rpc, int ld,
+                                                   int ntw, int sym, PT* __restrict__ partial, int nchunk,
+                                                   const int* __restrict__ state) {
     if (state && state[0]) return;
     typedef MF<T> M;
+    extern __shared__ char gram_lds[];
+    PT* buf = reinterpret_cast<PT*>(gram_lds);            // KS tiles of (32TW)^2
+    constexpr int TILE = 32 * TW;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, lr = l >> 4, lc = l & 15;
-    const int wi = w & 1, wj = w >> 1;
-    const int I0 = (blockIdx.y / ntw) * 32 * TW, J0 = (blockIdx.y % ntw) * 32 * TW;
+    const int grp = w >> 2, wl = w & 3;
+    const int wi = wl & 1, wj = wl >> 1;
+    const int I0 = (blockIdx.y / ntw) * TILE, J0 = (blockIdx.y % ntw) * TILE;
     const int i0 = I0 + wi * 16 * TW, j0 = J0 + wj * 16 * TW;
-    if (i0 >= ld || j0 >= ld) return;
-    if (sym && i0 > j0 + 16 * TW - 16) return;          // wave tile entirely below the diagonal
-    const int chunk = blockIdx.x;
+    const bool skip = (i0 >= ld || j0 >= ld) || (sym && i0 > j0 + 16 * TW - 16);
+    const int chunk = blockIdx.x, p = blockIdx.z;
     const int64_t r0 = (int64_t)chunk * rpc;
     const int64_t r1 = r0 + rpc < Np ? r0 + rpc : Np;
     bool vi[TW], vj[TW];
 #pragma unroll
     for (int a = 0; a < TW; ++a) { vi[a] = i0 + 16 * a < ld; vj[a] = j0 + 16 * a < ld; }
-    const int64_t step = 4 * (int64_t)ld;
-    {
-        const int p = blockIdx.z;
-        typename M::acc c[TW][TW];
+    typename M::acc c[TW][TW];
 #pragma unroll
-        for (int a = 0; a < TW; ++a)
+    for (int a = 0; a < TW; ++a)
 #pragma unroll
-            for (int b = 0; b < TW; ++b) c[a][b] = M::zero();
-        const T* xa = X + (int64_t)p * xstride + (r0 + lr) * ld + i0 + lc;
-        const T* ya = Y + (r0 + lr) * ld + j0 + lc;
-        for (int64_t r = r0; r < r1; r += 4, xa += step, ya += step) {
-            T av[TW], bv[TW];
+        for (int b = 0; b < TW; ++b) c[a][b] = M::zero();
+    if (!skip) {
+        const int64_t step = 4 * (int64_t)KS * ld;
+        const T* xa = X + (int64_t)p * xstride + (r0 + 4 * grp + lr) * ld + i0 + lc;
+        const T* ya = Y + (r0 + 4 * grp + lr) * ld + j0 + lc;
+        T av[TW], bv[TW];
+        int64_t r = r0 + 4 * grp;
+        if (r < r1) {
 #pragma unroll
             for (int a = 0; a < TW; ++a) {
                 av[a] = vi[a] ? xa[16 * a] : T(0);
                 bv[a] = vj[a] ? ya[16 * a] : T(0);
             }
+        }
+        for (; r < r1; r += 4 * KS) {
+            xa += step;
+            ya += step;
+            T an[TW], bn[TW];
+            const bool more = r + 4 * KS < r1;
+#pragma unroll
+            for (int a = 0; a < TW; ++a) {                 // prefetch the next step
+                an[a] = (more && vi[a]) ? xa[16 * a] : T(0);
+                bn[a] = (more && vj[a]) ? ya[16 * a] : T(0);
+            }
 #pragma unroll
             for (int a = 0; a < TW; ++a)
 #pragma unroll
                 for (int b = 0; b < TW; ++b) c[a][b] = M::mma(av[a], bv[b], c[a][b]);
+#pragma unroll
+            for (int a = 0; a < TW; ++a) { av[a] = an[a]; bv[a] = bn[a]; }
         }
-        PT* out = partial + ((int64_t)p * nchunk + chunk) * ld * ld;
+    }
+    // group tiles to LDS (tile-local coordinates), then add them in group order
+    PT* mine = buf + (int64_t)grp * TILE * TILE;
 #pragma unroll
-        for (int a = 0; a < TW; ++a)
+    for (int a = 0; a < TW; ++a)
 #pragma unroll
-            for (int b = 0; b < TW; ++b)
-                if (vi[a] && vj[b]) {
+        for (int b = 0; b < TW; ++b)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = i0 + 16 * a + M::row(l, r), col = j0 + 16 * b + lc;
-                        out[(int64_t)row * ld + col] = PT(c[a][b][r]);
-                    }
-                }
+            for (int r = 0; r < 4; ++r) {
+                const int row = wi * 16 * TW + 16 * a + M::row(l, r), col = wj * 16 * TW + 16 * b + lc;
+                mine[row * TILE + col] = PT(c[a][b][r]);
+            }
+    __syncthreads();
+    PT* out = partial + ((int64_t)p * nchunk + chunk) * ld * ld;
+    for (int e = threadIdx.x; e < TILE * TILE; e += 256 * KS) {
+        const int row = e / TILE, col = e % TILE;
+        const int gi = I0 + row, gj = J0 + col;
+        if (gi >= ld || gj >= ld) continue;
+        PT acc = buf[e];
+        for (int g = 1; g < KS; ++g) acc += buf[(int64_t)g * TILE * TILE + e];
+        out[(int64_t)gi * ld + gj] = acc;
     }
 }
 
-// Sum of the chunk partials in a fixed order: thread group g (of 4) adds chunks
-// g, g+4, ... for 64 consecutive entries, then the four group sums are added
-// in order. mode 0: plain; 1: (S + S^T)/2; 2: out += (S + S^T)/2.
+// Sum of the chunk partials in a fixed order: thread group g (of 16) adds chunks
+// g, g+16, ... for 64 consecutive entries, then the group sums are added in
+// order. mode 0: plain; 1: (S + S^T)/2; 2: out += (S + S^T)/2.
+constexpr int kRedGroups = 16;
+
 template <typename PT>
-__global__ __launch_bounds__(256) void k_gram_reduce(const PT* __restrict__ partial, int nchunk, int ld, int sym,
-                                                     int mode, double* __restrict__ out, int64_t out_stride,
-                                                     const int* __restrict__ state) {
+__global__ __launch_bounds__(64 * kRedGroups) void k_gram_reduce(const PT* __restrict__ partial, int nchunk, int ld,
+                                                                int sym, int mode, double* __restrict__ out,
+                                                                int64_t out_stride, const int* __restrict__ state) {
     if (state && state[0]) return;
-    __shared__ double s1s[4][64], s2s[4][64];
+    __shared__ double s1s[kRedGroups][64], s2s[kRedGroups][64];
     const int p = blockIdx.y;
     const int g = threadIdx.x >> 6, e = threadIdx.x & 63;
     const int idx = blockIdx.x * 64 + e;
@@ -129,18 +158,19 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const PT* __restrict__ part
     const PT* base = partial + (int64_t)p * nchunk * mat;
     double s1 = 0.0, s2 = 0.0;
     if (valid) {
-        for (int c = g; c < nchunk; c += 4) s1 += (double)base[c * mat + sij];
+        for (int c = g; c < nchunk; c += kRedGroups) s1 += (double)base[c * mat + sij];
         if (mode != 0)
-            for (int c = g; c < nchunk; c += 4) s2 += (double)base[c * mat + sji];
+            for (int c = g; c < nchunk; c += kRedGroups) s2 += (double)base[c * mat + sji];
     }
     s1s[g][e] = s1;
     s2s[g][e] = s2;
     __syncthreads();
     if (g == 0 && valid) {
-        const double t1 = ((s1s[0][e] + s1s[1][e]) + s1s[2][e]) + s1s[3][e];
+        double t1 = 0.0, t2 = 0.0;
+        for (int q = 0; q < kRedGroups; ++q) t1 += s1s[q][e];
         double v = t1;
         if (mode != 0) {
-            const double t2 = ((s2s[0][e] + s2s[1][e]) + s2s[2][e]) + s2s[3][e];
+            for (int q = 0; q < kRedGroups; ++q) t2 += s2s[q][e];
             v = 0.5 * (t1 + t2);
         }
         double* o = out + p * out_stride + idx;
@@ -593,7 +623,16 @@ namespace {
 int gram_tw(int ld) { return ld <= 64 ? 2 : (ld <= 96 ? 3 : 4); }
 }
 
-GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t cap_mats) {
+// groups of 4 waves per Gram workgroup: as many as fit the LDS combine (<= 4)
+template <typename T>
+int gram_ks(int ld) {
+    const size_t tile = 32 * gram_tw(ld);
+    const size_t per = tile * tile * sizeof(T);
+    int ks = static_cast<int>((150u * 1024u) / per);
+    return std::max(1, std::min(4, ks));
+}
+
+GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t cap_mats, int elem) {
     GramPlan g;
     g.ld = ld;
     g.nprod = nprod;
@@ -602,14 +641,43 @@ GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t cap_mats) {
     const int tile = 32 * gram_tw(ld);
     const int ntw = (ld + tile - 1) / tile;
     g.ntiles = ntw * ntw;
-    int64_t nchunk = (1024 + (int64_t)g.ntiles * nprod - 1) / ((int64_t)g.ntiles * nprod);
+    // about 2048 waves in flight (2 per SIMD); a workgroup holds 4*KS waves
+    const int ks = elem == 4 ? gram_ks<float>(ld) : gram_ks<double>(ld);
+    const int64_t target_wg = std::max<int64_t>(16, 2048 / (4 * ks * std::max(1, g.ntiles)));
+    int64_t nchunk = (target_wg + nprod - 1) / nprod;
     nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, cap_mats / std::max(1, nprod)));
-    nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, Np / 64));
+    nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, Np / 256));
     int64_t rpc = (Np + nchunk - 1) / nchunk;
-    rpc = (rpc + 3) / 4 * 4;
+    rpc = (rpc + 15) / 16 * 16;
     g.rows_per_chunk = rpc;
     g.nchunk = static_cast<int>((Np + rpc - 1) / rpc);
     return g;
+}
+
+template <typename T, int TW>
+void gram_tw_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, T* part, int ntw, const int* state,
+                    hipStream_t s) {
+    dim3 grid(g.nchunk, g.ntiles, g.nprod);
+    const int ks = gram_ks<T>(g.ld);
+    const size_t lds = (size_t)ks * (32 * TW) * (32 * TW) * sizeof(T);
+    switch (ks) {
+        case 4:
+            k_gram<T, T, TW, 4><<<grid, 256 * 4, lds, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw,
+                                                            g.sym ? 1 : 0, part, g.nchunk, state);
+            break;
+        case 3:
+            k_gram<T, T, TW, 3><<<grid, 256 * 3, lds, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw,
+                                                            g.sym ? 1 : 0, part, g.nchunk, state);
+            break;
+        case 2:
+            k_gram<T, T, TW, 2><<<grid, 256 * 2, lds, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw,
+                                                            g.sym ? 1 : 0, part, g.nchunk, state);
+            break;
+        default:
+            k_gram<T, T, TW, 1><<<grid, 256, lds, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw,
+                                                        g.sym ? 1 : 0, part, g.nchunk, state);
+            break;
+    }
 }
 
 template <typename T>
@@ -618,18 +686,15 @@ void gram_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, dou
     const int tw = gram_tw(g.ld);
     const int ntw = (g.ld + 32 * tw - 1) / (32 * tw);
     T* part = reinterpret_cast<T*>(partial);      // partials in the block precision
-    dim3 grid(g.nchunk, g.ntiles, g.nprod);
     if (tw == 2)
-        k_gram<T, T, 2><<<grid, 256, 0, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw, g.sym ? 1 : 0,
-                                             part, g.nchunk, state);
+        gram_tw_launch<T, 2>(g, X, xstride, Y, part, ntw, state, s);
     else if (tw == 3)
-        k_gram<T, T, 3><<<grid, 256, 0, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw, g.sym ? 1 : 0,
-                                             part, g.nchunk, state);
+        gram_tw_launch<T, 3>(g, X, xstride, Y, part, ntw, state, s);
     else
-        k_gram<T, T, 4><<<grid, 256, 0, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw, g.sym ? 1 : 0,
-                                             part, g.nchunk, state);
+        gram_tw_launch<T, 4>(g, X, xstride, Y, part, ntw, state, s);
     dim3 rgrid(grid_for((int64_t)g.ld * g.ld, 64), g.nprod);
-    k_gram_reduce<T><<<rgrid, 256, 0, s>>>(part, g.nchunk, g.ld, g.sym ? 1 : 0, mode, out, out_stride, state);
+    k_gram_reduce<T><<<rgrid, 64 * kRedGroups, 0, s>>>(part, g.nchunk, g.ld, g.sym ? 1 : 0, mode, out, out_stride,
+                                                        state);
 }
 
 template <typename T, int NTW>

@@ -163,7 +163,7 @@ struct Step {
 
     void gram(const T* X, int64_t xstride, int nprod, const T* Y, double* out, int64_t out_stride, bool sym,
               int mode) const {
-        GramPlan g = gram_plan(p.Np, p.ld, nprod, sym, p.partial_mats);
+        GramPlan g = gram_plan(p.Np, p.ld, nprod, sym, p.partial_mats, (int)sizeof(T));
         gram_launch<T>(g, X, xstride, Y, bf.partial, out, out_stride, mode, bf.state, s);
     }
     void update(T* out, const T* in, double alpha, const T* X, int64_t xstride, int nprod, const double* S,

@@ -163,12 +163,20 @@ __global__ void k_minmax(const double* __restrict__ lo, const double* __restrict
 }
 
 constexpr int kPoleThreads = 1024;
-constexpr int kMaxPer = 16;          // b*b / kPoleThreads entries per thread (b <= 128)
+constexpr int kPoleWaves = kPoleThreads / 64;
+
+typedef double pd4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ pd4 mfma64(double a, double b, pd4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 // One workgroup per pole: backward Schur sweep with in-place Gauss-Jordan inversion
 // of each complex b x b Schur complement (no pivoting), then the forward sweep.
+// The b x b products run on FP64 MFMA 16x16x4 tiles, one tile at a time per wave
+// (lane l supplies A[l%16][l/16], B[l/16][l%16]; result r of lane l is D[l/16+4r][l%16]).
 // Writes W_p = weight_p * Im Z_p (nT x b, row-major) for pole p = blockIdx.x.
-__global__ __launch_bounds__(kPoleThreads) void k_pole_solve(const double* __restrict__ A, const double* __restrict__ B,
+__global__ __launch_bounds__(kPoleThreads) void k_pole_solve_generic(const double* __restrict__ A, const double* __restrict__ B,
                                                              int v, int b, int ld, double mu, double inv2kT,
                                                              const double* __restrict__ kappa,
                                                              const double* __restrict__ weight,
@@ -178,7 +186,10 @@ __global__ __launch_bounds__(kPoleThreads) void k_pole_solve(const double* __res
     __shared__ double colr[128], coli[128], pinv[2];
     const int p = blockIdx.x;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, lr = lane >> 4, lc = lane & 15;
     const int bb = b * b;
+    const int nt = (b + 15) / 16;          // output tiles per dimension
+    const int ntiles = nt * nt;
     const int64_t mat = (int64_t)ld * ld;
     const double a = kappa[p] * inv2kT;
     const double wgt = weight[p];
@@ -189,29 +200,35 @@ __global__ __launch_bounds__(kPoleThreads) void k_pole_solve(const double* __res
     const int per = (bb + kPoleThreads - 1) / kPoleThreads;
 
     for (int j = v - 1; j >= 0; --j) {
-        // S = I - i a (A_j - mu) + i a B_j^T G_{j+1}
+        // S = I - i a (A_j - mu) + i a B_j^T G_{j+1}: tile products into registers, then LDS
         const double* Aj = A + j * mat;
-        for (int q = 0; q < per; ++q) {
-            const int e = tid + kPoleThreads * q;
-            if (e >= bb) break;
-            const int r = e / b, c = e % b;
-            double sr = (r == c) ? 1.0 : 0.0;
-            double si = -a * (Aj[(int64_t)r * ld + c] - (r == c ? mu : 0.0));
+        const double* Bj = B + j * mat;
+        const double* Gr1 = Gp + (int64_t)(j + 1) * 2 * bb;
+        const double* Gi1 = Gr1 + bb;
+        for (int t = wave; t < ntiles; t += kPoleWaves) {
+            const int m0 = (t / nt) * 16, c0 = (t % nt) * 16;
+            pd4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
             if (j + 1 < v) {
-                const double* Bj = B + j * mat;
-                const double* Gr = Gp + (int64_t)(j + 1) * 2 * bb;
-                const double* Gi = Gr + bb;
-                double tr = 0.0, ti = 0.0;
-                for (int k = 0; k < b; ++k) {
-                    const double bk = Bj[(int64_t)k * ld + r];
-                    tr += bk * Gr[k * b + c];
-                    ti += bk * Gi[k * b + c];
+                const int mr = m0 + lc, cc = c0 + lc;
+                for (int k0 = 0; k0 < b; k0 += 4) {
+                    const int k = k0 + lr;
+                    const bool kv = k < b;
+                    const double av = (kv && mr < b) ? Bj[(int64_t)k * ld + mr] : 0.0;     // (B_j^T)[m][k]
+                    const double gr = (kv && cc < b) ? Gr1[k * b + cc] : 0.0;
+                    const double gi = (kv && cc < b) ? Gi1[k * b + cc] : 0.0;
+                    tr = mfma64(av, gr, tr);
+                    ti = mfma64(av, gi, ti);
                 }
-                sr -= a * ti;
-                si += a * tr;
             }
-            Sr[e] = sr;
-            Si[e] = si;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + lr + 4 * r, col = c0 + lc;
+                if (row < b && col < b) {
+                    const double dg = (row == col) ? 1.0 : 0.0;
+                    Sr[row * b + col] = dg - a * ti[r];
+                    Si[row * b + col] = -a * (Aj[(int64_t)row * ld + col] - (row == col ? mu : 0.0)) + a * tr[r];
+                }
+            }
         }
         __syncthreads();
         // Gauss-Jordan inverse in place
@@ -228,7 +245,6 @@ __global__ __launch_bounds__(kPoleThreads) void k_pole_solve(const double* __res
             }
             __syncthreads();
             const double qr = pinv[0], qi = pinv[1];
-            // scaled pivot row: row k * pinv (entry k becomes pinv)
             for (int c = tid; c < b; c += kPoleThreads) {
                 const double xr = (c == k) ? 1.0 : Sr[k * b + c], xi = (c == k) ? 0.0 : Si[k * b + c];
                 Sr[k * b + c] = xr * qr - xi * qi;
@@ -253,18 +269,27 @@ __global__ __launch_bounds__(kPoleThreads) void k_pole_solve(const double* __res
             const double* Bm = B + (j - 1) * mat;
             double* Gr = Gp + (int64_t)j * 2 * bb;
             double* Gi = Gr + bb;
-            for (int q = 0; q < per; ++q) {
-                const int e = tid + kPoleThreads * q;
-                if (e >= bb) break;
-                const int r = e / b, c = e % b;
-                double tr = 0.0, ti = 0.0;
-                for (int k = 0; k < b; ++k) {
-                    const double bk = Bm[(int64_t)k * ld + c];
-                    tr += Sr[r * b + k] * bk;
-                    ti += Si[r * b + k] * bk;
+            for (int t = wave; t < ntiles; t += kPoleWaves) {
+                const int m0 = (t / nt) * 16, c0 = (t % nt) * 16;
+                const int mr = m0 + lc, cc = c0 + lc;
+                pd4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+                for (int k0 = 0; k0 < b; k0 += 4) {
+                    const int k = k0 + lr;
+                    const bool kv = k < b;
+                    const double sr = (kv && mr < b) ? Sr[mr * b + k] : 0.0;
+                    const double si = (kv && mr < b) ? Si[mr * b + k] : 0.0;
+                    const double bv = (kv && cc < b) ? Bm[(int64_t)k * ld + cc] : 0.0;
+                    tr = mfma64(sr, bv, tr);
+                    ti = mfma64(si, bv, ti);
                 }
-                Gr[e] = a * ti;
-                Gi[e] = -a * tr;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = m0 + lr + 4 * r, col = c0 + lc;
+                    if (row < b && col < b) {
+                        Gr[row * b + col] = a * ti[r];
+                        Gi[row * b + col] = -a * tr[r];
+                    }
+                }
             }
             __syncthreads();
         }
@@ -279,33 +304,290 @@ __global__ __launch_bounds__(kPoleThreads) void k_pole_solve(const double* __res
         Wp[e] = wgt * Si[e];
     }
     __syncthreads();
+    constexpr int kMaxTilesPerWave = 4;    // (128/16)^2 / 16 waves
     for (int j = 1; j < v; ++j) {
         const double* Gr = Gp + (int64_t)j * 2 * bb;
         const double* Gi = Gr + bb;
-        double nr[kMaxPer], ni[kMaxPer];
-        for (int q = 0; q < per; ++q) {
-            const int e = tid + kPoleThreads * q;
-            nr[q] = 0.0;
-            ni[q] = 0.0;
-            if (e >= bb) continue;
-            const int r = e / b, c = e % b;
-            double tr = 0.0, ti = 0.0;
-            for (int k = 0; k < b; ++k) {
-                const double gr = Gr[r * b + k], gi = Gi[r * b + k];
-                const double zr = Sr[k * b + c], zi = Si[k * b + c];
-                tr += gr * zr - gi * zi;
-                ti += gr * zi + gi * zr;
+        pd4 nr[kMaxTilesPerWave], ni[kMaxTilesPerWave];
+        int q = 0;
+        for (int t = wave; t < ntiles; t += kPoleWaves, ++q) {
+            const int m0 = (t / nt) * 16, c0 = (t % nt) * 16;
+            const int mr = m0 + lc, cc = c0 + lc;
+            pd4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+            for (int k0 = 0; k0 < b; k0 += 4) {
+                const int k = k0 + lr;
+                const bool kv = k < b;
+                const double gr = (kv && mr < b) ? Gr[mr * b + k] : 0.0;
+                const double gi = (kv && mr < b) ? Gi[mr * b + k] : 0.0;
+                const double zr = (kv && cc < b) ? Sr[k * b + cc] : 0.0;
+                const double zi = (kv && cc < b) ? Si[k * b + cc] : 0.0;
+                re = mfma64(gr, zr, re);
+                re = mfma64(-gi, zi, re);
+                im = mfma64(gr, zi, im);
+                im = mfma64(gi, zr, im);
             }
-            nr[q] = -tr;
-            ni[q] = -ti;
+            nr[q] = re;
+            ni[q] = im;
         }
         __syncthreads();
-        for (int q = 0; q < per; ++q) {
-            const int e = tid + kPoleThreads * q;
-            if (e >= bb) break;
-            Sr[e] = nr[q];
-            Si[e] = ni[q];
-            Wp[(int64_t)j * bb + e] = wgt * ni[q];
+        q = 0;
+        for (int t = wave; t < ntiles; t += kPoleWaves, ++q) {
+            const int m0 = (t / nt) * 16, c0 = (t % nt) * 16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + lr + 4 * r, col = c0 + lc;
+                if (row < b && col < b) {
+                    Sr[row * b + col] = -nr[q][r];
+                    Si[row * b + col] = -ni[q][r];
+                    Wp[(int64_t)j * bb + row * b + col] = -wgt * ni[q][r];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Register-tiled Gauss-Jordan inverse (no pivoting) of the complex b x b matrix
+// (Sr, Si) in LDS, b <= 96: thread (ty, tx) of a 32 x 32 grid keeps entries
+// (ty + 32a, tx + 32c); the pivot row and column are broadcast through
+// double-buffered LDS vectors, one barrier per pivot.
+__device__ void gj_inverse_reg(double* Sr, double* Si, int b, double (*vec)[4][96]) {
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    double xr[3][3], xi[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int i = ty + 32 * a, j = tx + 32 * c;
+            const bool in = i < b && j < b;
+            xr[a][c] = in ? Sr[i * b + j] : 0.0;
+            xi[a][c] = in ? Si[i * b + j] : 0.0;
+        }
+    __syncthreads();
+    for (int k = 0; k < b; ++k) {
+        double(*v)[96] = vec[k & 1];      // [0] col re, [1] col im, [2] row re, [3] row im
+        const int kb = k >> 5, kt = k & 31;
+        if (tx == kt) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (c == kb) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const int i = ty + 32 * a;
+                        if (i < b) { v[0][i] = xr[a][c]; v[1][i] = xi[a][c]; }
+                    }
+                }
+        }
+        if (ty == kt) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (a == kb) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int j = tx + 32 * c;
+                        if (j < b) { v[2][j] = xr[a][c]; v[3][j] = xi[a][c]; }
+                    }
+                }
+        }
+        __syncthreads();
+        const double pr = v[2][k], pi = v[3][k];
+        const double den = 1.0 / (pr * pr + pi * pi);
+        const double qr = pr * den, qi = -pi * den;              // 1 / pivot
+        double rr[3], ri[3], cr[3], ci[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int j = tx + 32 * c;
+            const double mr = j < b ? v[2][j] : 0.0, mi = j < b ? v[3][j] : 0.0;
+            rr[c] = mr * qr - mi * qi;                          // pivot row / pivot
+            ri[c] = mr * qi + mi * qr;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int i = ty + 32 * a;
+            cr[a] = i < b ? v[0][i] : 0.0;
+            ci[a] = i < b ? v[1][i] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int i = ty + 32 * a;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int j = tx + 32 * c;
+                double nr, ni;
+                if (i == k) {
+                    nr = (j == k) ? qr : rr[c];
+                    ni = (j == k) ? qi : ri[c];
+                } else if (j == k) {
+                    nr = -(cr[a] * qr - ci[a] * qi);
+                    ni = -(cr[a] * qi + ci[a] * qr);
+                } else {
+                    nr = xr[a][c] - (cr[a] * rr[c] - ci[a] * ri[c]);
+                    ni = xi[a][c] - (cr[a] * ri[c] + ci[a] * rr[c]);
+                }
+                xr[a][c] = nr;
+                xi[a][c] = ni;
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int i = ty + 32 * a, j = tx + 32 * c;
+            if (i < b && j < b) { Sr[i * b + j] = xr[a][c]; Si[i * b + j] = xi[a][c]; }
+        }
+    __syncthreads();
+}
+
+// b <= 96: one workgroup per pole with the Schur complement in LDS.
+//   S_{v-1} = D_{v-1};  for j = v-1 .. 0:  S_j <- S_j^-1 (Gauss-Jordan);
+//   G_j = -i a S_j^-1 B_{j-1} (kept in global for the forward sweep and staged in LDS);
+//   S_{j-1} = D_{j-1} + i a B_{j-1}^T G_j.
+// Forward: Z_0 = S_0^-1 B_0, Z_j = -G_j Z_{j-1}; W_p rows j*b.. = weight_p Im Z_j.
+constexpr int kMaxTiles96 = 3;     // (96/16)^2 tiles over 16 waves
+
+__global__ __launch_bounds__(kPoleThreads) void k_pole_solve(const double* __restrict__ A, const double* __restrict__ B,
+                                                             int v, int b, int ld, double mu, double inv2kT,
+                                                             const double* __restrict__ kappa,
+                                                             const double* __restrict__ weight,
+                                                             const int* __restrict__ counts, double* Gbuf,
+                                                             double* __restrict__ Wout) {
+    extern __shared__ double lds[];
+    __shared__ double vec[2][4][96];
+    const int p = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, lr = lane >> 4, lc = lane & 15;
+    const int bb = b * b;
+    const int nt = (b + 15) / 16;
+    const int ntiles = nt * nt;
+    const int64_t mat = (int64_t)ld * ld;
+    const double a = kappa[p] * inv2kT;
+    const double wgt = weight[p];
+    double* Sr = lds;
+    double* Si = lds + bb;
+    double* Gp = Gbuf + (int64_t)p * v * 2 * bb;
+    double* Wp = Wout + (int64_t)p * v * bb;
+
+    // S_{v-1} = I - i a (A_{v-1} - mu)
+    {
+        const double* Aj = A + (v - 1) * mat;
+        for (int e = tid; e < bb; e += kPoleThreads) {
+            const int r = e / b, c = e % b;
+            Sr[e] = (r == c) ? 1.0 : 0.0;
+            Si[e] = -a * (Aj[(int64_t)r * ld + c] - (r == c ? mu : 0.0));
+        }
+    }
+    __syncthreads();
+    for (int j = v - 1; j >= 0; --j) {
+        gj_inverse_reg(Sr, Si, b, vec);
+        if (j == 0) break;
+        // G_j = -i a S^-1 B_{j-1}: A operand S^-1 (LDS), B operand B_{j-1} (global); tiles go
+        // straight to global (S^-1 is not overwritten before the barrier)
+        const double* Bm = B + (j - 1) * mat;
+        double* Gr = Gp + (int64_t)j * 2 * bb;
+        double* Gi = Gr + bb;
+        for (int t = wave; t < ntiles; t += kPoleWaves) {
+            const int m0 = (t / nt) * 16, c0 = (t % nt) * 16;
+            const int mr = m0 + lc, cc = c0 + lc;
+            pd4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+            for (int k0 = 0; k0 < b; k0 += 4) {
+                const int k = k0 + lr;
+                const bool kv = k < b;
+                const double sr = (kv && mr < b) ? Sr[mr * b + k] : 0.0;
+                const double si = (kv && mr < b) ? Si[mr * b + k] : 0.0;
+                const double bv = (kv && cc < b) ? Bm[(int64_t)k * ld + cc] : 0.0;
+                tr = mfma64(sr, bv, tr);
+                ti = mfma64(si, bv, ti);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + lr + 4 * r, col = c0 + lc;
+                if (row < b && col < b) {
+                    Gr[row * b + col] = a * ti[r];      // Re(-i a (tr + i ti)) = a ti
+                    Gi[row * b + col] = -a * tr[r];     // Im = -a tr
+                }
+            }
+        }
+        __syncthreads();
+        // S_{j-1} = I - i a (A_{j-1} - mu) + i a B_{j-1}^T G_j: operands B_{j-1}^T and G_j (global);
+        // the result overwrites the LDS matrix directly
+        const double* Aj = A + (j - 1) * mat;
+        for (int t = wave; t < ntiles; t += kPoleWaves) {
+            const int m0 = (t / nt) * 16, c0 = (t % nt) * 16;
+            const int mr = m0 + lc, cc = c0 + lc;
+            pd4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+            for (int k0 = 0; k0 < b; k0 += 4) {
+                const int k = k0 + lr;
+                const bool kv = k < b;
+                const double av = (kv && mr < b) ? Bm[(int64_t)k * ld + mr] : 0.0;
+                const double zr = (kv && cc < b) ? Gr[k * b + cc] : 0.0;
+                const double zi = (kv && cc < b) ? Gi[k * b + cc] : 0.0;
+                tr = mfma64(av, zr, tr);
+                ti = mfma64(av, zi, ti);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + lr + 4 * r, col = c0 + lc;
+                if (row < b && col < b) {
+                    const double dg = (row == col) ? 1.0 : 0.0;
+                    Sr[row * b + col] = dg - a * ti[r];
+                    Si[row * b + col] = -a * (Aj[(int64_t)row * ld + col] - (row == col ? mu : 0.0)) + a * tr[r];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // forward sweep
+    for (int e = tid; e < bb; e += kPoleThreads) {
+        const double sc = sqrt((double)counts[e % b]);
+        Sr[e] *= sc;
+        Si[e] *= sc;
+        Wp[e] = wgt * Si[e];
+    }
+    __syncthreads();
+    for (int j = 1; j < v; ++j) {
+        const double* Gr = Gp + (int64_t)j * 2 * bb;
+        const double* Gi = Gr + bb;
+        pd4 nr[kMaxTiles96], ni[kMaxTiles96];
+#pragma unroll
+        for (int q = 0; q < kMaxTiles96; ++q) {
+            const int t = wave + kPoleWaves * q;
+            nr[q] = pd4{0, 0, 0, 0};
+            ni[q] = pd4{0, 0, 0, 0};
+            if (t >= ntiles) continue;
+            const int m0 = (t / nt) * 16, c0 = (t % nt) * 16;
+            const int mr = m0 + lc, cc = c0 + lc;
+            pd4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+            for (int k0 = 0; k0 < b; k0 += 4) {
+                const int k = k0 + lr;
+                const bool kv = k < b;
+                const double g_r = (kv && mr < b) ? Gr[mr * b + k] : 0.0;
+                const double g_i = (kv && mr < b) ? Gi[mr * b + k] : 0.0;
+                const double zr = (kv && cc < b) ? Sr[k * b + cc] : 0.0;
+                const double zi = (kv && cc < b) ? Si[k * b + cc] : 0.0;
+                re = mfma64(g_r, zr, re);
+                re = mfma64(-g_i, zi, re);
+                im = mfma64(g_r, zi, im);
+                im = mfma64(g_i, zr, im);
+            }
+            nr[q] = re;
+            ni[q] = im;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kMaxTiles96; ++q) {
+            const int t = wave + kPoleWaves * q;
+            if (t >= ntiles) continue;
+            const int m0 = (t / nt) * 16, c0 = (t % nt) * 16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + lr + 4 * r, col = c0 + lc;
+                if (row < b && col < b) {
+                    Sr[row * b + col] = -nr[q][r];
+                    Si[row * b + col] = -ni[q][r];
+                    Wp[(int64_t)j * bb + row * b + col] = -wgt * ni[q][r];
+                }
+            }
         }
         __syncthreads();
     }
@@ -400,13 +682,18 @@ css_status subspace_fermi_poles(const double* A, const double* B, int v, int b, 
     double* Gbuf = ar.take<double>((int64_t)np * v * 2 * bb);
     double* Wout = ar.take<double>((int64_t)np * v * bb);
     const size_t lds_bytes = sizeof(double) * 2 * bb;
-    const bool use_lds = lds_bytes + 4096 <= (size_t)max_lds();
+    const bool use_lds = lds_bytes + 8192 <= (size_t)max_lds();
     double* Sg = use_lds ? nullptr : ar.take<double>((int64_t)np * 2 * bb);
     if (ar.overflow) return CSS_E_WORKSPACE;
     CSS_HIP_TRY(hipMemcpyAsync(kap, pt.kappa.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
     CSS_HIP_TRY(hipMemcpyAsync(wgt, pt.weight.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
-    k_pole_solve<<<np, kPoleThreads, use_lds ? lds_bytes : 0, s>>>(A, B, v, b, ld, mu, 1.0 / (2.0 * kT), kap, wgt,
-                                                                    counts, Gbuf, Sg, use_lds ? 1 : 0, Wout);
+    if (b <= 96 && use_lds)
+        k_pole_solve<<<np, kPoleThreads, lds_bytes, s>>>(A, B, v, b, ld, mu, 1.0 / (2.0 * kT), kap, wgt, counts, Gbuf,
+                                                         Wout);
+    else
+        k_pole_solve_generic<<<np, kPoleThreads, use_lds ? lds_bytes : 0, s>>>(A, B, v, b, ld, mu, 1.0 / (2.0 * kT),
+                                                                                kap, wgt, counts, Gbuf, Sg,
+                                                                                use_lds ? 1 : 0, Wout);
     k_pole_sum<<<grid_for((int64_t)nT * b, 256), 256, 0, s>>>(Wout, np, (int64_t)nT * b, b, counts, g, F);
     k_krylov_sums<<<1, 256, 0, s>>>(A, B, F, counts, v, b, ld, sums);
     if (npoles_out) *npoles_out = np;
