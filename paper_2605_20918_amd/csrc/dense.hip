@@ -49,25 +49,26 @@ struct MF<float> {
 
 // ------------------------------------------------------------------ Gram
 
-// One workgroup computes a (32 TW) x (32 TW) tile of X_p^T Y over a chunk of rows
-// for product p = blockIdx.z, writing one partial per (p, chunk). The workgroup
-// has KS groups of 2 x 2 waves; group g takes the 4-row steps g, g+KS, ... of the
-// chunk, and the KS group tiles are added in order through LDS. Wave (wi, wj)
-// of a group owns a 16TW x 16TW sub-tile; with sym the strictly lower wave tile
-// is skipped (the reduction mirrors it).
-template <typename T, typename PT, int TW, int KS>
-__global__ __launch_bounds__(256 * KS) void k_gram(const T* __restrict__ X, int64_t xstride,
-                                                   const T* __restrict__ Y, int64_t Np, int64_t rpc, int ld,
-                                                   int ntw, int sym, PT* __restrict__ partial, int nchunk,
-                                                   const int* __restrict__ state) {
+// One workgroup computes a TILE x TILE tile of X_p^T Y over a chunk of rows for
+// product p = blockIdx.z, writing one partial per (p, chunk). The workgroup has
+// KS groups of WPG waves; group g takes the 4-row steps g, g+KS, ... of the chunk
+// and the KS group tiles are added in order through LDS. WPG = 1: one wave owns
+// the whole (16 TW)^2 tile (no duplicated operand loads); WPG = 4: 2 x 2 waves of
+// (16 TW)^2 each. With sym, wave tiles strictly below the diagonal are skipped
+// (the reduction mirrors them).
+template <typename T, typename PT, int TW, int KS, int WPG>
+__global__ __launch_bounds__(64 * WPG * KS) void k_gram(const T* __restrict__ X, int64_t xstride,
+                                                        const T* __restrict__ Y, int64_t Np, int64_t rpc, int ld,
+                                                        int ntw, int sym, PT* __restrict__ partial, int nchunk,
+                                                        const int* __restrict__ state) {
     if (state && state[0]) return;
     typedef MF<T> M;
     extern __shared__ char gram_lds[];
-    PT* buf = reinterpret_cast<PT*>(gram_lds);            // KS tiles of (32TW)^2
-    constexpr int TILE = 32 * TW;
+    PT* buf = reinterpret_cast<PT*>(gram_lds);            // KS tiles of TILE^2
+    constexpr int TILE = (WPG == 1 ? 16 : 32) * TW;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, lr = l >> 4, lc = l & 15;
-    const int grp = w >> 2, wl = w & 3;
-    const int wi = wl & 1, wj = wl >> 1;
+    const int grp = w / WPG, wl = w % WPG;
+    const int wi = (WPG == 1) ? 0 : (wl & 1), wj = (WPG == 1) ? 0 : (wl >> 1);
     const int I0 = (blockIdx.y / ntw) * TILE, J0 = (blockIdx.y % ntw) * TILE;
     const int i0 = I0 + wi * 16 * TW, j0 = J0 + wj * 16 * TW;
     const bool skip = (i0 >= ld || j0 >= ld) || (sym && i0 > j0 + 16 * TW - 16);
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(256 * KS) void k_gram(const T* __restrict__ X, int6
             }
     __syncthreads();
     PT* out = partial + ((int64_t)p * nchunk + chunk) * ld * ld;
-    for (int e = threadIdx.x; e < TILE * TILE; e += 256 * KS) {
+    for (int e = threadIdx.x; e < TILE * TILE; e += 64 * WPG * KS) {
         const int row = e / TILE, col = e % TILE;
         const int gi = I0 + row, gj = J0 + col;
         if (gi >= ld || gj >= ld) continue;
@@ -620,13 +621,18 @@ int64_t gram_partial_mats(int ld) {
 }
 
 namespace {
-int gram_tw(int ld) { return ld <= 64 ? 2 : (ld <= 96 ? 3 : 4); }
+// Gram layout: FP32 with ld <= 96 -> one wave per 96-wide tile (TW = 6, WPG = 1:
+// 36 accumulators of 4 floats); FP64 with ld <= 96 -> 2 x 2 waves of TW = 3;
+// ld > 96 -> 2 x 2 waves of TW = 4 (128-wide tiles).
+int gram_tw(int ld, int elem) { return ld <= 96 ? (elem == 4 ? 6 : 3) : 4; }
+int gram_wpg(int ld, int elem) { return (ld <= 96 && elem == 4) ? 1 : 4; }
+int gram_tile(int ld, int elem) { return (gram_wpg(ld, elem) == 1 ? 16 : 32) * gram_tw(ld, elem); }
 }
 
-// groups of 4 waves per Gram workgroup: as many as fit the LDS combine (<= 4)
+// groups per Gram workgroup: as many as fit the LDS combine (<= 4)
 template <typename T>
 int gram_ks(int ld) {
-    const size_t tile = 32 * gram_tw(ld);
+    const size_t tile = gram_tile(ld, (int)sizeof(T));
     const size_t per = tile * tile * sizeof(T);
     int ks = static_cast<int>((150u * 1024u) / per);
     return std::max(1, std::min(4, ks));
@@ -638,12 +644,14 @@ GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t cap_mats, in
     g.nprod = nprod;
     g.Np = Np;
     g.sym = sym;
-    const int tile = 32 * gram_tw(ld);
+    const int tile = gram_tile(ld, elem);
     const int ntw = (ld + tile - 1) / tile;
     g.ntiles = ntw * ntw;
-    // about 2048 waves in flight (2 per SIMD); a workgroup holds 4*KS waves
+    // about 1024 waves in flight (1 per SIMD; each wave holds a large tile);
+    // a workgroup holds WPG*KS waves
     const int ks = elem == 4 ? gram_ks<float>(ld) : gram_ks<double>(ld);
-    const int64_t target_wg = std::max<int64_t>(16, 2048 / (4 * ks * std::max(1, g.ntiles)));
+    const int64_t target_wg =
+        std::max<int64_t>(16, 1024 / (gram_wpg(ld, elem) * ks * std::max(1, g.ntiles)));
     int64_t nchunk = (target_wg + nprod - 1) / nprod;
     nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, cap_mats / std::max(1, nprod)));
     nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, Np / 256));
@@ -654,44 +662,35 @@ GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t cap_mats, in
     return g;
 }
 
-template <typename T, int TW>
+template <typename T, int TW, int WPG>
 void gram_tw_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, T* part, int ntw, const int* state,
                     hipStream_t s) {
+    constexpr int TILE = (WPG == 1 ? 16 : 32) * TW;
+    constexpr int KS0 = (150 * 1024) / (TILE * TILE * (int)sizeof(T));
+    constexpr int KS = KS0 < 1 ? 1 : (KS0 > 4 ? 4 : KS0);
     dim3 grid(g.nchunk, g.ntiles, g.nprod);
-    const int ks = gram_ks<T>(g.ld);
-    const size_t lds = (size_t)ks * (32 * TW) * (32 * TW) * sizeof(T);
-    switch (ks) {
-        case 4:
-            k_gram<T, T, TW, 4><<<grid, 256 * 4, lds, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw,
-                                                            g.sym ? 1 : 0, part, g.nchunk, state);
-            break;
-        case 3:
-            k_gram<T, T, TW, 3><<<grid, 256 * 3, lds, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw,
-                                                            g.sym ? 1 : 0, part, g.nchunk, state);
-            break;
-        case 2:
-            k_gram<T, T, TW, 2><<<grid, 256 * 2, lds, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw,
-                                                            g.sym ? 1 : 0, part, g.nchunk, state);
-            break;
-        default:
-            k_gram<T, T, TW, 1><<<grid, 256, lds, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw,
-                                                        g.sym ? 1 : 0, part, g.nchunk, state);
-            break;
-    }
+    const size_t lds = (size_t)KS * TILE * TILE * sizeof(T);
+    k_gram<T, T, TW, KS, WPG><<<grid, 64 * WPG * KS, lds, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw,
+                                                                g.sym ? 1 : 0, part, g.nchunk, state);
 }
 
 template <typename T>
 void gram_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, double* partial, double* out,
                  int64_t out_stride, int mode, const int* state, hipStream_t s) {
-    const int tw = gram_tw(g.ld);
-    const int ntw = (g.ld + 32 * tw - 1) / (32 * tw);
+    const int elem = (int)sizeof(T);
+    const int tile = gram_tile(g.ld, elem);
+    const int ntw = (g.ld + tile - 1) / tile;
     T* part = reinterpret_cast<T*>(partial);      // partials in the block precision
-    if (tw == 2)
-        gram_tw_launch<T, 2>(g, X, xstride, Y, part, ntw, state, s);
-    else if (tw == 3)
-        gram_tw_launch<T, 3>(g, X, xstride, Y, part, ntw, state, s);
+    if constexpr (sizeof(T) == 4) {
+        if (gram_wpg(g.ld, elem) == 1) {
+            gram_tw_launch<T, 6, 1>(g, X, xstride, Y, part, ntw, state, s);
+        } else {
+            gram_tw_launch<T, 4, 4>(g, X, xstride, Y, part, ntw, state, s);
+        }
+    } else if (g.ld <= 96)
+        gram_tw_launch<T, 3, 4>(g, X, xstride, Y, part, ntw, state, s);
     else
-        gram_tw_launch<T, 4>(g, X, xstride, Y, part, ntw, state, s);
+        gram_tw_launch<T, 4, 4>(g, X, xstride, Y, part, ntw, state, s);
     dim3 rgrid(grid_for((int64_t)g.ld * g.ld, 64), g.nprod);
     k_gram_reduce<T><<<rgrid, 64 * kRedGroups, 0, s>>>(part, g.nchunk, g.ld, g.sym ? 1 : 0, mode, out, out_stride,
                                                         state);
