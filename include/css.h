@@ -72,6 +72,9 @@ enum { CSS_F64 = 0, CSS_F32 = 1 };
 #define CSS_SIGNS_ONES     0x80u  /* probes with all signs +1 instead of random signs */
 #define CSS_SUBSPACE_EIG   0x100u /* subspace Fermi operator by dense diagonalisation (rocSOLVER)
                                      instead of the default pole expansion of Eq.(7) */
+#define CSS_SPMM_CSR       0x200u /* always use the row-parallel CSR SpMM kernel; by default the
+                                     16-row grouped MFMA kernel is used where H's row groups
+                                     are dense enough (see css_spmm_prepare) */
 
 /* workspace query selectors */
 enum { CSS_ENTRY_COLOR = 0, CSS_ENTRY_LANCZOS = 1, CSS_ENTRY_DENSITY = 2, CSS_ENTRY_SPMM = 3 };
@@ -93,6 +96,8 @@ typedef struct {
     int32_t n_colors;         /* b */
     int32_t breakdown;        /* 1 if the recurrence stopped early on a degenerate block */
     int32_t n_poles;          /* poles of the Fermi expansion (0 with CSS_SUBSPACE_EIG) */
+    int32_t spmm_kernel;      /* 1: the 16-row grouped MFMA SpMM ran, 0: the CSR kernel */
+    int32_t reserved;
     double min_diag_r;        /* smallest diagonal of the Cholesky factors of W^T W */
     double asym_max;          /* max |P_raw - (P_raw + P_raw^T)/2| on the pattern */
     double trace_krylov;      /* sum_k g f(lambda_k) w_k (Krylov quadrature of Tr P) */
@@ -142,15 +147,36 @@ css_status css_build_probes(const int32_t* color, int32_t n, int32_t n_colors, u
                             uint32_t flags, int8_t* sign, int32_t* color_count, void* stream);
 
 /*
+ * css_spmm_prepare -- column unions for the grouped SpMM kernel (a layout of
+ *   the sparse-dense product of css_spmm; no arithmetic of the method).
+ *   For every group of 16 consecutive rows: the sorted union U of their column
+ *   indices, and H's values of those rows as a dense 16 x |U| block.
+ *   ws    device, css_workspace_size(CSS_ENTRY_SPMM, n, nnz, ...) bytes, owned
+ *         by the caller; pass it to css_spmm while H (structure and values)
+ *         stays unchanged.
+ *   Validates H's structure and synchronises the stream. Returns CSS_E_CSR for
+ *   a malformed H, CSS_E_UNSUPPORTED if a group of 16 rows holds more than 8192
+ *   nonzeros or the blocks would hold more than 4 times H's nonzeros (rows whose
+ *   neighbours share few columns; css_spmm then needs ws = NULL).
+ */
+css_status css_spmm_prepare(const css_csr* H, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * css_spmm -- W = H V for a dense block V of b columns (the sparse-dense
  *   product the whole method reduces to, text after Eq.(10)).
  *   V, W  device, n x ld row-major, element type = H's value type; ld >= b,
  *         ld a multiple of 16 (css_block_ld(b) gives the library's choice)
+ *   ws    NULL: row-parallel CSR kernel. Else a workspace filled by
+ *         css_spmm_prepare for this H: the grouped MFMA kernel when ld <= 128
+ *         and V, W are 16-byte aligned, the CSR kernel otherwise. The grouped
+ *         kernel needs a finite V (a block's zeros multiply every V row of
+ *         its union).
  *   Columns b..ld-1 of W are H times those columns of V (zero when V's are).
- *   H is not validated here (css_block_lanczos and css_density_matrix do).
+ *   H is not validated here (css_spmm_prepare, css_block_lanczos and
+ *   css_density_matrix do).
  */
 css_status css_spmm(const css_csr* H, const void* V, void* W, int32_t b, int32_t ld,
-                    void* stream);
+                    const void* ws, size_t ws_bytes, void* stream);
 
 /*
  * css_block_lanczos -- block Lanczos projection (text after Eq.(4)).
@@ -193,7 +219,8 @@ css_status css_density_matrix(const css_csr* H, const int32_t* color, const int8
 /*
  * css_workspace_size -- bytes of workspace an entry point needs.
  *   entry  CSS_ENTRY_*; the other arguments as they will be passed
- *   (nnz = H's nnz, or for CSS_ENTRY_COLOR unused).
+ *   (nnz = H's nnz, or for CSS_ENTRY_COLOR unused; CSS_ENTRY_SPMM uses n and
+ *   nnz only).
  */
 css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, int32_t n_colors,
                               int32_t depth, uint32_t flags, size_t* bytes);

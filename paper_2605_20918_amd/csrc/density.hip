@@ -24,6 +24,7 @@
 #include "css_common.h"
 #include "dense.h"
 #include "driver.h"
+#include "spmm.h"
 #include "subspace.h"
 
 namespace css {
@@ -448,6 +449,7 @@ extern "C" css_status css_density_matrix(const css_csr* H, const int32_t* color,
         info->depth_eff = v_eff;
         info->n_colors = lz.b;
         info->breakdown = brk;
+        info->spmm_kernel = bf.lz.use_grp ? 1 : 0;
         info->min_diag_r = md;
         info->asym_max = hres[4];
         info->n_poles = npoles;
@@ -471,7 +473,8 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
         return CSS_OK;
     }
     if (entry == CSS_ENTRY_SPMM) {
-        *bytes = 0;
+        if (nnz < 0 || nnz >= (int64_t(1) << 31)) return CSS_E_ARG;
+        *bytes = spmm_workspace_bytes(n, nnz);
         return CSS_OK;
     }
     // a shape-only CSR for planning

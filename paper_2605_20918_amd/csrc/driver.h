@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "css_common.h"
+#include "spmm.h"
 
 namespace css {
 
@@ -22,6 +23,7 @@ struct LzPlan {
     int max_coef = 0;         // reorthogonalisation products per step
     int64_t partial_mats = 0;
     size_t elem = 8;
+    bool grp_ok = false;      // grouped MFMA SpMM allowed (ld <= 128, not CSS_SPMM_CSR)
 };
 
 struct LzBufs {
@@ -45,6 +47,8 @@ struct LzBufs {
     double* scal = nullptr;       // 16 doubles: [0] ||H||_inf
     int* state = nullptr;         // 16 ints: [0] broken, [1] bad input, [2] fail step
     int* counts = nullptr;        // b colour counts
+    SpmmGroups grp{};             // row-group unions (grp_ok)
+    bool use_grp = false;         // host decision taken when H is validated
 };
 
 css_status plan_lanczos(const css_csr* H, int32_t n_colors, int32_t depth, uint32_t flags, LzPlan& p);
@@ -52,8 +56,9 @@ void carve_lanczos(Arena& a, const LzPlan& p, LzBufs& bf);
 
 // Validates H (and colours), converts H if needed, builds Q_1 in slot 0 and
 // runs pass 1. On return (stream synchronised) *v_eff and *breakdown are set.
+// Also decides bf.use_grp.
 css_status run_lanczos_pass1(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p,
-                             const LzBufs& bf, hipStream_t s, int* v_eff, int* breakdown, double* min_diag);
+                             LzBufs& bf, hipStream_t s, int* v_eff, int* breakdown, double* min_diag);
 
 // Pointer to the tall block holding Q_{j} (0-based j) after pass 1 with a stored basis.
 inline void* slot_ptr(const LzPlan& p, const LzBufs& bf, int j) {

@@ -33,21 +33,6 @@
 namespace css {
 namespace {
 
-__global__ void k_validate_csr(int n, int64_t nnz, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                               int* __restrict__ state) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) {
-        const int32_t a = rp[i], b = rp[i + 1];
-        if (a < 0 || b < a || b > nnz) atomicOr(&state[1], 1);
-        if (i == 0 && a != 0) atomicOr(&state[1], 1);
-        if (i == n - 1 && (int64_t)b != nnz) atomicOr(&state[1], 1);
-    }
-    if (i < nnz) {
-        const int32_t c = col[i];
-        if (c < 0 || c >= n) atomicOr(&state[1], 1);
-    }
-}
-
 template <typename V>
 __global__ void k_row_abs_sum(int n, const int32_t* __restrict__ rp, const V* __restrict__ val,
                               double* __restrict__ out_rows, int* __restrict__ state) {
@@ -140,6 +125,7 @@ template <typename T>
 bool launch_spmm_t(const css_csr* H, const LzBufs& bf, const T* V, T* W, int ld, hipStream_t s) {
     const T* val = bf.hval ? static_cast<const T*>(bf.hval) : static_cast<const T*>(H->val);
     SpmmArgs<T> a{H->n, H->row_ptr, H->col, val, V, W, ld};
+    if (bf.use_grp && spmm_grp_launch(a, bf.grp, s)) return true;
     return spmm_launch(a, s);
 }
 
@@ -233,16 +219,16 @@ struct Step {
 };
 
 template <typename T>
-css_status prepare(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p, const LzBufs& bf,
+css_status prepare(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p, LzBufs& bf,
                    hipStream_t s) {
     k_zero<int><<<1, 64, 0, s>>>(bf.state, 16);
-    k_validate_csr<<<grid_for(std::max<int64_t>(p.n, p.nnz), 256), 256, 0, s>>>(p.n, p.nnz, H->row_ptr, H->col,
-                                                                                bf.state);
+    csr_validate_launch(p.n, p.nnz, H->row_ptr, H->col, bf.state, s);
     CSS_HIP_TRY(hipGetLastError());
     int hst[16];
     CSS_HIP_TRY(hipMemcpyAsync(hst, bf.state, sizeof(hst), hipMemcpyDeviceToHost, s));
     CSS_HIP_TRY(hipStreamSynchronize(s));
     if (hst[1]) return CSS_E_CSR;
+    if (p.grp_ok) spmm_grp_prepare(p.n, H->row_ptr, H->col, bf.grp, bf.state + 4, s);
     double* rows = static_cast<double*>(bf.W);     // W is free scratch until the first SpMM
     if (H->val_dtype == CSS_F64)
         k_row_abs_sum<double><<<grid_for(p.n, 256), 256, 0, s>>>(p.n, H->row_ptr,
@@ -259,6 +245,8 @@ css_status prepare(const css_csr* H, const int32_t* color, const int8_t* sign, c
     CSS_HIP_TRY(hipStreamSynchronize(s));
     if (hst[1] & 2) return CSS_E_NONFINITE;
     if (hst[1]) return CSS_E_CSR;
+    // grouped SpMM where the 16 x |U_g| blocks hold at most kGroupFill times the nonzeros
+    bf.use_grp = p.grp_ok && spmm_grp_worthwhile(p.nnz, hst[4], hst[5]);
     if (p.convert_h) {
         if (p.fp32)
             k_convert<double, float><<<grid_for(p.nnz, 256), 256, 0, s>>>(static_cast<const double*>(H->val),
@@ -267,6 +255,9 @@ css_status prepare(const css_csr* H, const int32_t* color, const int8_t* sign, c
             k_convert<float, double><<<grid_for(p.nnz, 256), 256, 0, s>>>(static_cast<const float*>(H->val),
                                                                            static_cast<double*>(bf.hval), p.nnz);
     }
+    if (bf.use_grp)
+        spmm_grp_fill<T>(p.n, H->row_ptr, bf.hval ? static_cast<const T*>(bf.hval) : static_cast<const T*>(H->val),
+                         bf.grp, s);
     zero_tall<T>(static_cast<T*>(bf.W), p.Np * p.ld, s);
     if (bf.Wt) zero_tall<T>(static_cast<T*>(bf.Wt), p.Np * p.ld, s);
     const int64_t mat = (int64_t)p.ld * p.ld;
@@ -279,7 +270,7 @@ css_status prepare(const css_csr* H, const int32_t* color, const int8_t* sign, c
 }
 
 template <typename T>
-css_status pass1_t(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p, const LzBufs& bf,
+css_status pass1_t(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p, LzBufs& bf,
                    hipStream_t s, int* v_eff, int* breakdown, double* min_diag) {
     CSS_TRY(prepare<T>(H, color, sign, p, bf, s));
     Step<T> st{H, p, bf, s};
@@ -350,6 +341,7 @@ css_status plan_lanczos(const css_csr* H, int32_t b, int32_t depth, uint32_t fla
     const int64_t single = std::min<int64_t>(gram_partial_mats(p.ld), std::max<int64_t>(1, p.Np / 64));
     const int64_t batched = std::min<int64_t>(32, std::max<int64_t>(1, p.Np / 64)) * std::max(1, p.max_coef);
     p.partial_mats = std::max<int64_t>(1, std::max(single, batched));
+    p.grp_ok = (flags & CSS_SPMM_CSR) == 0 && p.ld <= 128;
     return CSS_OK;
 }
 
@@ -377,10 +369,11 @@ void carve_lanczos(Arena& a, const LzPlan& p, LzBufs& bf) {
     bf.scal = a.take<double>(16);
     bf.state = a.take<int>(16);
     bf.counts = a.take<int>(p.b);
+    if (p.grp_ok) carve_groups(a, p.n, p.nnz, p.elem, bf.grp);
 }
 
 css_status run_lanczos_pass1(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p,
-                             const LzBufs& bf, hipStream_t s, int* v_eff, int* breakdown, double* min_diag) {
+                             LzBufs& bf, hipStream_t s, int* v_eff, int* breakdown, double* min_diag) {
     if (p.fp32) return pass1_t<float>(H, color, sign, p, bf, s, v_eff, breakdown, min_diag);
     return pass1_t<double>(H, color, sign, p, bf, s, v_eff, breakdown, min_diag);
 }
@@ -445,6 +438,7 @@ extern "C" css_status css_block_lanczos(const css_csr* H, const int32_t* color, 
         info->depth_eff = v_eff;
         info->n_colors = p.b;
         info->breakdown = brk;
+        info->spmm_kernel = bf.use_grp ? 1 : 0;
         info->min_diag_r = md;
         info->t_phase_ms[0] = ms;
         info->t_phase_ms[5] = ms;

@@ -76,7 +76,33 @@ bool dispatch_c(const SpmmArgs<T>& a, int c, hipStream_t s) {
     }
 }
 
+// state[1] |= 1 for a malformed CSR structure.
+__global__ void k_validate_csr(int n, int64_t nnz, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                               int* __restrict__ state) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int32_t a = rp[i], b = rp[i + 1];
+        if (a < 0 || b < a || b > nnz) atomicOr(&state[1], 1);
+        if (i == 0 && a != 0) atomicOr(&state[1], 1);
+        if (i == n - 1 && (int64_t)b != nnz) atomicOr(&state[1], 1);
+    }
+    if (i < nnz) {
+        const int32_t c = col[i];
+        if (c < 0 || c >= n) atomicOr(&state[1], 1);
+    }
+}
+
+__global__ void k_zero_ints(int* __restrict__ p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
 }  // namespace
+
+void csr_validate_launch(int n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, int* state,
+                         hipStream_t s) {
+    k_validate_csr<<<grid_for(std::max<int64_t>(n, nnz), 256), 256, 0, s>>>(n, nnz, row_ptr, col, state);
+}
 
 template <typename T>
 bool spmm_launch(const SpmmArgs<T>& a, hipStream_t s) {
@@ -90,27 +116,80 @@ bool spmm_launch(const SpmmArgs<T>& a, hipStream_t s) {
 template bool spmm_launch<double>(const SpmmArgs<double>&, hipStream_t);
 template bool spmm_launch<float>(const SpmmArgs<float>&, hipStream_t);
 
+namespace {
+
+constexpr size_t kSpmmHeader = 256;     // 16 status ints ahead of the group arrays
+
+SpmmGroups groups_in(void* ws, int n, int64_t nnz, size_t elem) {
+    Arena a;
+    a.base = static_cast<char*>(ws) + kSpmmHeader;
+    a.cap = ~size_t(0);
+    SpmmGroups g;
+    carve_groups(a, n, nnz, elem, g);
+    return g;
+}
+
+bool csr_shape_ok(const css_csr* H) {
+    return H && H->n >= 1 && H->row_ptr && H->col && H->val && H->nnz >= 0 && H->nnz < (int64_t(1) << 31) &&
+           (H->val_dtype == CSS_F64 || H->val_dtype == CSS_F32);
+}
+
+size_t elem_of(const css_csr* H) { return H->val_dtype == CSS_F32 ? 4 : 8; }
+
+}  // namespace
+
+size_t spmm_workspace_bytes(int n, int64_t nnz) {
+    Arena a;
+    SpmmGroups g;
+    carve_groups(a, n, nnz, 8, g);
+    return kSpmmHeader + a.used;
+}
+
 }  // namespace css
 
 using namespace css;
 
-extern "C" css_status css_spmm(const css_csr* H, const void* V, void* W, int32_t b, int32_t ld,
-                               void* stream) {
-    if (!H || !V || !W || H->n < 1 || b < 1 || ld < b || !H->row_ptr || !H->col || !H->val)
-        return CSS_E_ARG;
-    if (H->nnz < 0 || H->nnz >= (int64_t(1) << 31)) return CSS_E_CSR;
+extern "C" css_status css_spmm_prepare(const css_csr* H, void* ws, size_t ws_bytes, void* stream) {
+    if (!csr_shape_ok(H) || !ws) return CSS_E_ARG;
+    if (ws_bytes < spmm_workspace_bytes(H->n, H->nnz)) return CSS_E_WORKSPACE;
     hipStream_t s = as_stream(stream);
+    int* state = static_cast<int*>(ws);
+    const SpmmGroups g = groups_in(ws, H->n, H->nnz, elem_of(H));
+    k_zero_ints<<<1, 64, 0, s>>>(state, 16);
+    csr_validate_launch(H->n, H->nnz, H->row_ptr, H->col, state, s);
+    int hst[16];
+    CSS_HIP_TRY(hipGetLastError());
+    CSS_HIP_TRY(hipMemcpyAsync(hst, state, sizeof(hst), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    if (hst[1]) return CSS_E_CSR;
+    spmm_grp_prepare(H->n, H->row_ptr, H->col, g, state + 4, s);
+    CSS_HIP_TRY(hipGetLastError());
+    CSS_HIP_TRY(hipMemcpyAsync(hst, state, sizeof(hst), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    if (!spmm_grp_worthwhile(H->nnz, hst[4], hst[5])) return CSS_E_UNSUPPORTED;
+    if (H->val_dtype == CSS_F64)
+        spmm_grp_fill<double>(H->n, H->row_ptr, static_cast<const double*>(H->val), g, s);
+    else
+        spmm_grp_fill<float>(H->n, H->row_ptr, static_cast<const float*>(H->val), g, s);
+    CSS_HIP_TRY(hipGetLastError());
+    return CSS_OK;
+}
+
+extern "C" css_status css_spmm(const css_csr* H, const void* V, void* W, int32_t b, int32_t ld, const void* ws,
+                               size_t ws_bytes, void* stream) {
+    if (!csr_shape_ok(H) || !V || !W || b < 1 || ld < b) return CSS_E_ARG;
+    if (ws && ws_bytes < spmm_workspace_bytes(H->n, H->nnz)) return CSS_E_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    const SpmmGroups g = ws ? groups_in(const_cast<void*>(ws), H->n, H->nnz, elem_of(H)) : SpmmGroups{};
     bool ok;
     if (H->val_dtype == CSS_F64) {
         SpmmArgs<double> a{H->n, H->row_ptr, H->col, static_cast<const double*>(H->val),
                            static_cast<const double*>(V), static_cast<double*>(W), ld};
-        ok = spmm_launch(a, s);
-    } else if (H->val_dtype == CSS_F32) {
+        ok = (ws && spmm_grp_launch(a, g, s)) || spmm_launch(a, s);
+    } else {
         SpmmArgs<float> a{H->n, H->row_ptr, H->col, static_cast<const float*>(H->val),
                           static_cast<const float*>(V), static_cast<float*>(W), ld};
-        ok = spmm_launch(a, s);
-    } else {
-        return CSS_E_ARG;
+        ok = (ws && spmm_grp_launch(a, g, s)) || spmm_launch(a, s);
     }
     if (!ok) return CSS_E_UNSUPPORTED;
     return hipGetLastError() == hipSuccess ? CSS_OK : CSS_E_DEVICE;

@@ -36,6 +36,7 @@ CHOLQR2 = 0x20
 SYMMETRIZE = 0x40
 SIGNS_ONES = 0x80
 SUBSPACE_EIG = 0x100
+SPMM_CSR = 0x200
 
 ENTRY_COLOR, ENTRY_LANCZOS, ENTRY_DENSITY, ENTRY_SPMM = 0, 1, 2, 3
 
@@ -53,13 +54,14 @@ class CsrStruct(ctypes.Structure):
 
 class InfoStruct(ctypes.Structure):
     _fields_ = [("depth_eff", ctypes.c_int32), ("n_colors", ctypes.c_int32), ("breakdown", ctypes.c_int32),
-                ("n_poles", ctypes.c_int32), ("min_diag_r", ctypes.c_double), ("asym_max", ctypes.c_double),
+                ("n_poles", ctypes.c_int32), ("spmm_kernel", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("min_diag_r", ctypes.c_double), ("asym_max", ctypes.c_double),
                 ("trace_krylov", ctypes.c_double), ("e_band_krylov", ctypes.c_double),
                 ("t_phase_ms", ctypes.c_double * 6)]
 
     def as_dict(self) -> dict:
         return {"depth_eff": self.depth_eff, "n_colors": self.n_colors, "breakdown": self.breakdown,
-                "n_poles": self.n_poles,
+                "n_poles": self.n_poles, "spmm_kernel": "grouped" if self.spmm_kernel else "csr",
                 "min_diag_r": self.min_diag_r, "asym_max": self.asym_max, "trace_krylov": self.trace_krylov,
                 "e_band_krylov": self.e_band_krylov,
                 "t_phase_ms": {k: self.t_phase_ms[i] for i, k in
@@ -89,7 +91,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.css_color.argtypes = [vp, i32, ctypes.POINTER(dbl * 3), dbl, vp, ctypes.POINTER(i32), vp, vp,
                               ctypes.POINTER(i64), ctypes.POINTER(i32), vp, sz, vp]
     lib.css_build_probes.argtypes = [vp, i32, i32, u64, u32, vp, vp, vp]
-    lib.css_spmm.argtypes = [pcsr, vp, vp, i32, i32, vp]
+    lib.css_spmm_prepare.argtypes = [pcsr, vp, sz, vp]
+    lib.css_spmm.argtypes = [pcsr, vp, vp, i32, i32, vp, sz, vp]
     lib.css_block_lanczos.argtypes = [pcsr, vp, vp, i32, i32, u32, vp, vp, pinfo, vp, sz, vp]
     lib.css_density_matrix.argtypes = [pcsr, vp, vp, i32, dbl, dbl, i32, dbl, vp, vp, i64, u32, vp,
                                        ctypes.POINTER(dbl), ctypes.POINTER(dbl), pinfo, vp, sz, vp]
@@ -100,7 +103,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.css_block_ld.restype = i32
     lib.css_status_string.argtypes = [i32]
     lib.css_status_string.restype = ctypes.c_char_p
-    for name in ("css_color", "css_build_probes", "css_spmm", "css_block_lanczos", "css_density_matrix",
+    for name in ("css_color", "css_build_probes", "css_spmm_prepare", "css_spmm", "css_block_lanczos",
+                 "css_density_matrix",
                  "css_workspace_size"):
         getattr(lib, name).restype = i32
     _lib = lib
@@ -228,12 +232,26 @@ def css_build_probes(color, n_colors: int, seed: int, flags: int = 0):
     return sign, counts
 
 
-def css_spmm(H: DeviceCSR, V, b: int):
-    """W = H V for V of shape (n, ld) with b meaningful columns."""
+def css_spmm_prepare(H: DeviceCSR):
+    """Row-group column unions of H for the grouped SpMM; returns the workspace tensor."""
     torch = _torch()
-    W = torch.empty_like(V)
+    nbytes = workspace_size(ENTRY_SPMM, H.n, H.nnz, 1, 1, 0)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=H.row_ptr.device)
     csr = H.struct()
-    _check("css_spmm", load().css_spmm(ctypes.byref(csr), _ptr(V), _ptr(W), b, int(V.shape[1]), _stream(V.device)))
+    _check("css_spmm_prepare", load().css_spmm_prepare(ctypes.byref(csr), _ptr(ws), nbytes,
+                                                       _stream(H.row_ptr.device)))
+    return ws
+
+
+def css_spmm(H: DeviceCSR, V, b: int, ws=None, out=None):
+    """W = H V for V of shape (n, ld) with b meaningful columns. ws from css_spmm_prepare
+    selects the grouped kernel; None the CSR kernel."""
+    torch = _torch()
+    W = torch.empty_like(V) if out is None else out
+    csr = H.struct()
+    _check("css_spmm", load().css_spmm(ctypes.byref(csr), _ptr(V), _ptr(W), b, int(V.shape[1]),
+                                       None if ws is None else _ptr(ws), 0 if ws is None else ws.numel(),
+                                       _stream(V.device)))
     return W
 
 

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(css.LIB_PATH), reason="libcss
 def test_every_declared_symbol_is_exported():
     names = css.declared_symbols()
     assert {"css_color", "css_build_probes", "css_block_lanczos", "css_density_matrix", "css_spmm",
-            "css_workspace_size", "css_status_string", "css_block_ld"} <= set(names)
+            "css_spmm_prepare", "css_workspace_size", "css_status_string", "css_block_ld"} <= set(names)
     lib = ctypes.CDLL(css.LIB_PATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
@@ -29,9 +29,18 @@ def test_host_only_entry_points():
 def test_argument_errors_before_any_device_work():
     lib = css.load()
     assert lib.css_build_probes(None, 0, 1, 0, 0, None, None, None) == 1
-    assert lib.css_spmm(None, None, None, 1, 16, None) == 1
+    assert lib.css_spmm(None, None, None, 1, 16, None, 0, None) == 1
+    assert lib.css_spmm_prepare(None, None, 0, None) == 1
     out = ctypes.c_size_t(0)
     assert lib.css_workspace_size(0, 0, 0, 1, 1, 0, ctypes.byref(out)) == 1
+    # shape-only CSR with placeholder pointers: the size checks come before any device work
+    csr = css.CsrStruct(1000, 5000, 8, 8, 8, css.CSS_F64)
+    assert lib.css_workspace_size(css.ENTRY_SPMM, 1000, 5000, 1, 1, 0, ctypes.byref(out)) == 0
+    need = out.value
+    assert need >= 2 * 4 * 5000 + 4 * 63
+    assert lib.css_spmm_prepare(ctypes.byref(csr), ctypes.c_void_p(256), need - 1, None) == 3
+    assert lib.css_spmm(ctypes.byref(csr), ctypes.c_void_p(256), ctypes.c_void_p(256), 8, 16,
+                        ctypes.c_void_p(256), need - 1, None) == 3
 
 
 def test_oracle_not_imported_by_product_path():

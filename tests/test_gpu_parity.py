@@ -84,22 +84,97 @@ def test_probes_reject_bad_colours():
 
 # ---------------------------------------------------------------- SpMM
 
-@pytest.mark.parametrize("M,b", [(64, 69), (216, 16), (1000, 88), (1000, 300)])
+def _spmm_check(Hs, V, b, dtype, kernel):
+    """css_spmm (CSR or grouped kernel) against the plain sparse product in FP64."""
+    ref = Hs.to_scipy() @ V
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    H = css.DeviceCSR.from_host(Hs.row_ptr, Hs.col, Hs.val, "cuda", tdt)
+    ws = css.css_spmm_prepare(H) if kernel == "grp" else None
+    W = css.css_spmm(H, torch.as_tensor(V, dtype=tdt).cuda(), b, ws=ws).double().cpu().numpy()
+    scale = max(np.max(np.abs(ref)), 1e-300)
+    # FP32: products rounded once and summed over at most ~120 terms of similar size
+    tol = 1e-14 if dtype == "f64" else 2e-6
+    assert np.max(np.abs(W - ref)) <= tol * scale
+    assert np.all(W[:, b:] == 0)
+
+
+@pytest.mark.parametrize("M,b", [(64, 69), (63, 37), (216, 16), (1000, 88), (1000, 300)])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_spmm(M, b, dtype):
+@pytest.mark.parametrize("kernel", ["csr", "grp"])
+def test_spmm(M, b, dtype, kernel):
+    print(f"spmm M={M} b={b} {dtype} {kernel}", flush=True)
     ws = synth.water_system(M, 7)
     ld = css.block_ld(b)
     rng = np.random.default_rng(1)
     V = np.zeros((ws.n, ld))
     V[:, :b] = rng.normal(size=(ws.n, b))
-    ref = ws.H.to_scipy() @ V
-    tdt = torch.float64 if dtype == "f64" else torch.float32
-    H = to_dev(ws, tdt)
-    W = css.css_spmm(H, torch.as_tensor(V, dtype=tdt).cuda(), b).double().cpu().numpy()
-    scale = np.max(np.abs(ref))
-    tol = 1e-14 if dtype == "f64" else 2e-6
-    assert np.max(np.abs(W - ref)) <= tol * scale
-    assert np.all(W[:, b:] == 0)
+    _spmm_check(ws.H, V, b, dtype, kernel)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_spmm_grouped_every_tile_count_ragged_and_empty_rows(dtype):
+    """Banded H with n = 1007 (ragged last group), rows 32..63 empty (two whole
+    empty groups), a few long rows and a chunked union (> 256 columns in the
+    groups of rows 5 and 700); every ld from 16 to 128."""
+    n = 1007
+    rng = np.random.default_rng(5)
+    rows = []
+    for i in range(n):
+        if 32 <= i < 64:
+            rows.append(np.zeros(0, dtype=np.int64))
+            continue
+        if i in (5, 700):
+            rows.append(np.sort(rng.choice(n, size=400, replace=False)))
+            continue
+        lo, hi = max(0, i - 24), min(n, i + 25)
+        k = int(rng.integers(1, hi - lo))
+        rows.append(np.sort(rng.choice(np.arange(lo, hi), size=k, replace=False)))
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    col = np.concatenate(rows).astype(np.int32)
+    val = rng.normal(size=col.size)
+    Hs = synth.CSR(n, rp.astype(np.int32), col, val)
+    for b in (1, 17, 33, 49, 64, 80, 100, 128):
+        ld = css.block_ld(b)
+        V = np.zeros((n, ld))
+        V[:, :b] = rng.normal(size=(n, b))
+        print(f"  ragged spmm {dtype} b={b} ld={ld}", flush=True)
+        _spmm_check(Hs, V, b, dtype, "grp")
+
+
+def test_spmm_prepare_rejects_oversized_sparse_and_bad_csr():
+    n = 1000
+    rng = np.random.default_rng(6)
+    rows = [np.sort(rng.choice(n, size=600, replace=False)) if i < 16 else np.array([i]) for i in range(n)]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    col = np.concatenate(rows).astype(np.int32)
+    H = css.DeviceCSR.from_host(rp, col, np.ones(col.size), "cuda", torch.float64)
+    with pytest.raises(css.CssError) as e:                   # 9600 nonzeros in rows 0..15
+        css.css_spmm_prepare(H)
+    assert e.value.code == 8
+    Hd = css.DeviceCSR.from_host(np.arange(n + 1), np.arange(n), np.ones(n), "cuda", torch.float64)
+    with pytest.raises(css.CssError) as e:                   # diagonal: blocks 16 times the nonzeros
+        css.css_spmm_prepare(Hd)
+    assert e.value.code == 8
+    bad = col.copy()
+    bad[7] = n + 3
+    Hb = css.DeviceCSR.from_host(rp, bad, np.ones(col.size), "cuda", torch.float64)
+    with pytest.raises(css.CssError) as e:
+        css.css_spmm_prepare(Hb)
+    assert e.value.code == 2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_density_same_with_either_spmm_kernel(prec):
+    ws, H, rp, col, color, b, sign, mu = water_case(216, 3)
+    flags = FP64_FLAGS if prec == "fp64" else FP32_FLAGS
+    args = (to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, 20, dev_i64(rp), dev_i32(col))
+    p1, e1, _, _ = css.css_density_matrix(*args, flags)
+    p2, e2, _, _ = css.css_density_matrix(*args, flags | css.SPMM_CSR)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert torch.max(torch.abs(p1 - p2)).item() <= tol
+    assert abs(e1 - e2) <= (1e-12 if prec == "fp64" else 1e-7) * abs(e1)
 
 
 # ---------------------------------------------------------------- Lanczos
