@@ -19,52 +19,54 @@
 
 #include "css_common.h"
 #include "dense.h"
+#include "mfma_util.h"
 
 namespace css {
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
 template <typename T>
-struct MF;
-template <>
-struct MF<double> {
-    typedef d4 acc;
-    __device__ static acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
-    __device__ static acc mma(double a, double b, acc c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    __device__ static int row(int l, int r) { return (l >> 4) + 4 * r; }
-};
-template <>
-struct MF<float> {
-    typedef f4 acc;
-    __device__ static acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
-    __device__ static acc mma(float a, float b, acc c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
-};
+using MF = Mfma<T>;
 
 // ------------------------------------------------------------------ Gram
 
 // One workgroup computes a TILE x TILE tile of X_p^T Y over a chunk of rows for
 // product p = blockIdx.z, writing one partial per (p, chunk). The workgroup has
-// KS groups of WPG waves; group g takes the 4-row steps g, g+KS, ... of the chunk
-// and the KS group tiles are added in order through LDS. WPG = 1: one wave owns
-// the whole (16 TW)^2 tile (no duplicated operand loads); WPG = 4: 2 x 2 waves of
-// (16 TW)^2 each. With sym, wave tiles strictly below the diagonal are skipped
-// (the reduction mirrors them).
-template <typename T, typename PT, int TW, int KS, int WPG>
+// KS groups of WPG waves; group g takes the 4-row steps g, g+KS, ... of the chunk,
+// and the group tiles are added into one LDS tile in group order. WPG = 1: one
+// wave owns the whole (16 TW)^2 tile; WPG = 4: 2 x 2 waves of (16 TW)^2 each.
+// With sym, wave tiles strictly below the diagonal are skipped (the reduction
+// mirrors them). The operands of each step are fetched kGramDepth steps ahead of
+// their use. RUN: every wave tile lies inside ld, and each lane reads runs of
+// adjacent columns (seg_col order); otherwise one column per lane and tile,
+// masked beyond ld.
+constexpr int kGramDepth = 4;
+
+template <typename T, int TW, bool RUN>
+__device__ inline void gram_load(const T* __restrict__ p, int lc, const bool (&valid)[TW], T (&x)[TW]) {
+    if constexpr (RUN) {
+        load_run<T, TW>(p, lc, x);
+    } else {
+#pragma unroll
+        for (int a = 0; a < TW; ++a) x[a] = valid[a] ? p[16 * a + lc] : T(0);
+    }
+}
+
+template <typename T, int TW, bool RUN>
+__device__ constexpr int gram_col(int a, int x) {
+    if constexpr (RUN) return seg_col<TW, MF<T>::VW>(a, x);
+    return 16 * a + x;
+}
+
+template <typename T, typename PT, int TW, int KS, int WPG, bool RUN>
 __global__ __launch_bounds__(64 * WPG * KS) void k_gram(const T* __restrict__ X, int64_t xstride,
                                                         const T* __restrict__ Y, int64_t Np, int64_t rpc, int ld,
                                                         int ntw, int sym, PT* __restrict__ partial, int nchunk,
                                                         const int* __restrict__ state) {
     if (state && state[0]) return;
     typedef MF<T> M;
+    constexpr int D = kGramDepth;
     extern __shared__ char gram_lds[];
-    PT* buf = reinterpret_cast<PT*>(gram_lds);            // KS tiles of TILE^2
+    PT* buf = reinterpret_cast<PT*>(gram_lds);            // one TILE^2 tile
     constexpr int TILE = (WPG == 1 ? 16 : 32) * TW;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, lr = l >> 4, lc = l & 15;
     const int grp = w / WPG, wl = w % WPG;
@@ -75,6 +77,9 @@ __global__ __launch_bounds__(64 * WPG * KS) void k_gram(const T* __restrict__ X,
     const int chunk = blockIdx.x, p = blockIdx.z;
     const int64_t r0 = (int64_t)chunk * rpc;
     const int64_t r1 = r0 + rpc < Np ? r0 + rpc : Np;
+    // r1 - r0 is a multiple of 64, so nst is a multiple of D (4 KS D divides 64)
+    static_assert((64 % (4 * KS * D)) == 0, "chunks must hold whole rounds of D steps");
+    const int nst = (int)((r1 - r0) / (4 * KS));
     bool vi[TW], vj[TW];
 #pragma unroll
     for (int a = 0; a < TW; ++a) { vi[a] = i0 + 16 * a < ld; vj[a] = j0 + 16 * a < ld; }
@@ -83,57 +88,58 @@ __global__ __launch_bounds__(64 * WPG * KS) void k_gram(const T* __restrict__ X,
     for (int a = 0; a < TW; ++a)
 #pragma unroll
         for (int b = 0; b < TW; ++b) c[a][b] = M::zero();
-    if (!skip) {
+    // WPG = 1: the single wave tile always lies inside ld and chunks hold rows, so
+    // there is no branch (keeps the accumulators in one register class)
+    if (WPG == 1 || (!skip && nst > 0)) {
         const int64_t step = 4 * (int64_t)KS * ld;
-        const T* xa = X + (int64_t)p * xstride + (r0 + 4 * grp + lr) * ld + i0 + lc;
-        const T* ya = Y + (r0 + 4 * grp + lr) * ld + j0 + lc;
-        T av[TW], bv[TW];
-        int64_t r = r0 + 4 * grp;
-        if (r < r1) {
+        const T* xa = X + (int64_t)p * xstride + (r0 + 4 * grp + lr) * ld + i0;
+        const T* ya = Y + (r0 + 4 * grp + lr) * ld + j0;
+        T xr[D][TW], yr[D][TW];
 #pragma unroll
-            for (int a = 0; a < TW; ++a) {
-                av[a] = vi[a] ? xa[16 * a] : T(0);
-                bv[a] = vj[a] ? ya[16 * a] : T(0);
+        for (int d = 0; d < D; ++d) {
+            const int64_t o = (int64_t)min(d, nst - 1) * step;
+            gram_load<T, TW, RUN>(xa + o, lc, vi, xr[d]);
+            gram_load<T, TW, RUN>(ya + o, lc, vj, yr[d]);
+        }
+        for (int s0 = 0; s0 < nst; s0 += D) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+#pragma unroll
+                for (int a = 0; a < TW; ++a)
+#pragma unroll
+                    for (int b = 0; b < TW; ++b) c[a][b] = M::mma(xr[d][a], yr[d][b], c[a][b]);
+                const int64_t o = (int64_t)min(s0 + d + D, nst - 1) * step;
+                gram_load<T, TW, RUN>(xa + o, lc, vi, xr[d]);
+                gram_load<T, TW, RUN>(ya + o, lc, vj, yr[d]);
+                __builtin_amdgcn_sched_barrier(0);       // keep each step's loads D steps ahead of their use
             }
         }
-        for (; r < r1; r += 4 * KS) {
-            xa += step;
-            ya += step;
-            T an[TW], bn[TW];
-            const bool more = r + 4 * KS < r1;
+    }
+    // group tiles added into LDS in group order (tile-local coordinates)
 #pragma unroll
-            for (int a = 0; a < TW; ++a) {                 // prefetch the next step
-                an[a] = (more && vi[a]) ? xa[16 * a] : T(0);
-                bn[a] = (more && vj[a]) ? ya[16 * a] : T(0);
-            }
+    for (int g = 0; g < KS; ++g) {
+        if (grp == g) {
 #pragma unroll
             for (int a = 0; a < TW; ++a)
 #pragma unroll
-                for (int b = 0; b < TW; ++b) c[a][b] = M::mma(av[a], bv[b], c[a][b]);
+                for (int b = 0; b < TW; ++b)
 #pragma unroll
-            for (int a = 0; a < TW; ++a) { av[a] = an[a]; bv[a] = bn[a]; }
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = wi * 16 * TW + gram_col<T, TW, RUN>(a, M::row(l, r));
+                        const int col = wj * 16 * TW + gram_col<T, TW, RUN>(b, lc);
+                        const PT v = PT(c[a][b][r]);
+                        PT& e = buf[row * TILE + col];
+                        e = (g == 0) ? v : e + v;
+                        if (r == 3) __builtin_amdgcn_sched_barrier(0);   // one tile's values live at a time
+                    }
         }
+        __syncthreads();
     }
-    // group tiles to LDS (tile-local coordinates), then add them in group order
-    PT* mine = buf + (int64_t)grp * TILE * TILE;
-#pragma unroll
-    for (int a = 0; a < TW; ++a)
-#pragma unroll
-        for (int b = 0; b < TW; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = wi * 16 * TW + 16 * a + M::row(l, r), col = wj * 16 * TW + 16 * b + lc;
-                mine[row * TILE + col] = PT(c[a][b][r]);
-            }
-    __syncthreads();
     PT* out = partial + ((int64_t)p * nchunk + chunk) * ld * ld;
     for (int e = threadIdx.x; e < TILE * TILE; e += 64 * WPG * KS) {
         const int row = e / TILE, col = e % TILE;
         const int gi = I0 + row, gj = J0 + col;
-        if (gi >= ld || gj >= ld) continue;
-        PT acc = buf[e];
-        for (int g = 1; g < KS; ++g) acc += buf[(int64_t)g * TILE * TILE + e];
-        out[(int64_t)gi * ld + gj] = acc;
+        if (gi < ld && gj < ld) out[(int64_t)gi * ld + gj] = buf[e];
     }
 }
 
@@ -186,9 +192,12 @@ __global__ __launch_bounds__(64 * kRedGroups) void k_gram_reduce(const PT* __res
 
 // OUT = alpha IN + sum_p X_p S'_p with S'_p already in the block precision (and
 // transposed / scaled by the caller's staging kernel). A workgroup owns 64*MT
-// rows (4 waves x 16*MT) and up to 16*NTW columns; S'_p is staged through LDS
-// 32 rows of K at a time, double buffered, and the X fragments of a K chunk
-// are fetched before the chunk's LDS barrier.
+// rows (4 waves x 16*MT) and up to 16*NTW columns. K (the ld columns of every
+// X_p) is walked in chunks of 32: S'_p's chunk rows are staged in LDS (double
+// buffered) and each lane reads its X row's chunk as vector runs. K is permuted
+// inside a chunk: lane row lr of MFMA step (j, e) stands for k = 4 VW j + VW lr + e
+// (VW = elements per 16 bytes), so a lane's VW values of one run feed VW steps.
+// The next chunk's X runs and S' rows are fetched while the current one is used.
 constexpr int kKC = 32;
 
 template <typename T, int MT, int NTW>
@@ -197,6 +206,8 @@ __global__ __launch_bounds__(256) void k_update(T* OUT, const T* IN, double alph
                                                 int64_t Np, int ld, const int* __restrict__ state) {
     if (state && state[0]) return;
     typedef MF<T> M;
+    constexpr int VW = M::VW;
+    constexpr int NJ = kKC / (4 * VW);                        // runs per lane and row tile in a chunk
     constexpr int NC = 16 * NTW;                              // columns per workgroup
     constexpr int SP = NC + (sizeof(T) == 8 ? 8 : 16);        // padded LDS row
     constexpr int PER = (kKC * NC + 255) / 256;               // staged elements per thread
@@ -233,41 +244,61 @@ __global__ __launch_bounds__(256) void k_update(T* OUT, const T* IN, double alph
             if (t < kKC * NC) sS[buf][(t / NC) * SP + t % NC] = reg[q];
         }
     };
-    T sreg[PER];
-    fetch_s(0, sreg);
-    store_s(0, sreg);
-    for (int it = 0; it < total; ++it) {
-        const int buf = it & 1;
+    // this lane's runs of chunk it: x[mt][j][e] = X_p[m0 + 16 mt + lc][kc + 4 VW j + VW lr + e]
+    auto fetch_x = [&](int it, T (&x)[MT][NJ][VW]) {
         const int p = it / nkc, kc = (it % nkc) * kKC;
         const int kend = min(kKC, ld - kc);
-        // X fragments of this chunk (issued before the barrier)
-        T xa[kKC / 4][MT];
-        if (active) {
-            const T* __restrict__ Xp = X + (int64_t)p * xstride + (m0 + lc) * ld + kc + lr;
+        const T* Xp = X + (int64_t)p * xstride + (m0 + lc) * ld + kc + VW * lr;
 #pragma unroll
-            for (int k4 = 0; k4 < kKC / 4; ++k4)
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-                    xa[k4][mt] = (4 * k4 < kend) ? Xp[(int64_t)16 * mt * ld + 4 * k4] : T(0);
-        }
-        if (it + 1 < total) fetch_s(it + 1, sreg);
-        __syncthreads();                                  // chunk `it` staged in sS[buf]
-        if (active) {
+            for (int j = 0; j < NJ; ++j) {
+                if (active && 4 * VW * j < kend) {
+                    load_q<T, VW>(Xp + (int64_t)16 * mt * ld + 4 * VW * j, x[mt][j]);
+                } else {
 #pragma unroll
-            for (int k4 = 0; k4 < kKC / 4; ++k4) {
-                if (4 * k4 < kend) {
+                    for (int e = 0; e < VW; ++e) x[mt][j][e] = T(0);
+                }
+            }
+    };
+    auto compute = [&](int buf, const T (&x)[MT][NJ][VW]) {
 #pragma unroll
-                    for (int nt = 0; nt < NTW; ++nt) {
-                        if (nt < ntw) {
-                            const T bv = sS[buf][(4 * k4 + lr) * SP + nt * 16 + lc];
+        for (int j = 0; j < NJ; ++j)
 #pragma unroll
-                            for (int mt = 0; mt < MT; ++mt) c[mt][nt] = M::mma(xa[k4][mt], bv, c[mt][nt]);
-                        }
+            for (int e = 0; e < VW; ++e) {
+                const int k = 4 * VW * j + VW * lr + e;
+#pragma unroll
+                for (int nt = 0; nt < NTW; ++nt) {
+                    if (nt < ntw) {
+                        const T bv = sS[buf][k * SP + nt * 16 + lc];
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) c[mt][nt] = M::mma(x[mt][j][e], bv, c[mt][nt]);
                     }
                 }
             }
+    };
+    T sreg[PER];
+    T xa[MT][NJ][VW], xb[MT][NJ][VW];
+    fetch_x(0, xa);
+    fetch_s(0, sreg);
+    store_s(0, sreg);
+    // chunk `it` lives in sS[it & 1] and in xa (even it) / xb (odd it)
+    for (int it = 0; it < total; it += 2) {
+        if (it + 1 < total) {
+            fetch_x(it + 1, xb);
+            fetch_s(it + 1, sreg);
         }
-        if (it + 1 < total) store_s(buf ^ 1, sreg);       // other buffer: last read before the barrier above
+        __syncthreads();                                  // sS[0] holds chunk it
+        compute(0, xa);
+        if (it + 1 < total) store_s(1, sreg);
+        if (it + 1 >= total) break;
+        if (it + 2 < total) {
+            fetch_x(it + 2, xa);
+            fetch_s(it + 2, sreg);
+        }
+        __syncthreads();                                  // sS[1] holds chunk it + 1
+        compute(1, xb);
+        if (it + 2 < total) store_s(0, sreg);
     }
     if (!active) return;
 #pragma unroll
@@ -624,18 +655,13 @@ namespace {
 // Gram layout: FP32 with ld <= 96 -> one wave per 96-wide tile (TW = 6, WPG = 1:
 // 36 accumulators of 4 floats); FP64 with ld <= 96 -> 2 x 2 waves of TW = 3;
 // ld > 96 -> 2 x 2 waves of TW = 4 (128-wide tiles).
-int gram_tw(int ld, int elem) { return ld <= 96 ? (elem == 4 ? 6 : 3) : 4; }
+// Wave tiles: FP32 with ld <= 96 -> one wave per ld x ld tile (TW = ld/16, up to
+// 36 accumulators of 4 floats); otherwise 2 x 2 waves of TW = 3 (FP64, ld <= 96)
+// or TW = 4 (ld > 96).
+int gram_tw(int ld, int elem) { return (ld <= 96 && elem == 4) ? ld / 16 : (ld <= 96 ? 3 : 4); }
 int gram_wpg(int ld, int elem) { return (ld <= 96 && elem == 4) ? 1 : 4; }
 int gram_tile(int ld, int elem) { return (gram_wpg(ld, elem) == 1 ? 16 : 32) * gram_tw(ld, elem); }
-}
-
-// groups per Gram workgroup: as many as fit the LDS combine (<= 4)
-template <typename T>
-int gram_ks(int ld) {
-    const size_t tile = gram_tile(ld, (int)sizeof(T));
-    const size_t per = tile * tile * sizeof(T);
-    int ks = static_cast<int>((150u * 1024u) / per);
-    return std::max(1, std::min(4, ks));
+int gram_ks(int ld, int elem) { return gram_wpg(ld, elem) == 1 ? 4 : 2; }
 }
 
 GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t cap_mats, int elem) {
@@ -647,31 +673,29 @@ GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t cap_mats, in
     const int tile = gram_tile(ld, elem);
     const int ntw = (ld + tile - 1) / tile;
     g.ntiles = ntw * ntw;
-    // about 1024 waves in flight (1 per SIMD; each wave holds a large tile);
-    // a workgroup holds WPG*KS waves
-    const int ks = elem == 4 ? gram_ks<float>(ld) : gram_ks<double>(ld);
+    // about 1024 waves in flight; a workgroup holds WPG*KS waves
+    const int ks = gram_ks(ld, elem);
     const int64_t target_wg =
         std::max<int64_t>(16, 1024 / (gram_wpg(ld, elem) * ks * std::max(1, g.ntiles)));
     int64_t nchunk = (target_wg + nprod - 1) / nprod;
     nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, cap_mats / std::max(1, nprod)));
     nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, Np / 256));
     int64_t rpc = (Np + nchunk - 1) / nchunk;
-    rpc = (rpc + 15) / 16 * 16;
+    rpc = (rpc + 63) / 64 * 64;                   // whole prefetch rounds per chunk (Np is a multiple of 256)
     g.rows_per_chunk = rpc;
     g.nchunk = static_cast<int>((Np + rpc - 1) / rpc);
     return g;
 }
 
-template <typename T, int TW, int WPG>
+template <typename T, int TW, int WPG, bool RUN>
 void gram_tw_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, T* part, int ntw, const int* state,
                     hipStream_t s) {
     constexpr int TILE = (WPG == 1 ? 16 : 32) * TW;
-    constexpr int KS0 = (150 * 1024) / (TILE * TILE * (int)sizeof(T));
-    constexpr int KS = KS0 < 1 ? 1 : (KS0 > 4 ? 4 : KS0);
+    constexpr int KS = WPG == 1 ? 4 : 2;
     dim3 grid(g.nchunk, g.ntiles, g.nprod);
-    const size_t lds = (size_t)KS * TILE * TILE * sizeof(T);
-    k_gram<T, T, TW, KS, WPG><<<grid, 64 * WPG * KS, lds, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, ntw,
-                                                                g.sym ? 1 : 0, part, g.nchunk, state);
+    const size_t lds = (size_t)TILE * TILE * sizeof(T);
+    k_gram<T, T, TW, KS, WPG, RUN><<<grid, 64 * WPG * KS, lds, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld,
+                                                                     ntw, g.sym ? 1 : 0, part, g.nchunk, state);
 }
 
 template <typename T>
@@ -682,15 +706,30 @@ void gram_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, dou
     const int ntw = (g.ld + tile - 1) / tile;
     T* part = reinterpret_cast<T*>(partial);      // partials in the block precision
     if constexpr (sizeof(T) == 4) {
-        if (gram_wpg(g.ld, elem) == 1) {
-            gram_tw_launch<T, 6, 1>(g, X, xstride, Y, part, ntw, state, s);
+        if (g.ld <= 96) {
+            switch (g.ld / 16) {
+                case 1: gram_tw_launch<T, 1, 1, true>(g, X, xstride, Y, part, ntw, state, s); break;
+                case 2: gram_tw_launch<T, 2, 1, true>(g, X, xstride, Y, part, ntw, state, s); break;
+                case 3: gram_tw_launch<T, 3, 1, true>(g, X, xstride, Y, part, ntw, state, s); break;
+                case 4: gram_tw_launch<T, 4, 1, true>(g, X, xstride, Y, part, ntw, state, s); break;
+                case 5: gram_tw_launch<T, 5, 1, true>(g, X, xstride, Y, part, ntw, state, s); break;
+                default: gram_tw_launch<T, 6, 1, true>(g, X, xstride, Y, part, ntw, state, s); break;
+            }
+        } else if (g.ld % 64 == 0) {
+            gram_tw_launch<T, 4, 4, true>(g, X, xstride, Y, part, ntw, state, s);
         } else {
-            gram_tw_launch<T, 4, 4>(g, X, xstride, Y, part, ntw, state, s);
+            gram_tw_launch<T, 4, 4, false>(g, X, xstride, Y, part, ntw, state, s);
         }
-    } else if (g.ld <= 96)
-        gram_tw_launch<T, 3, 4>(g, X, xstride, Y, part, ntw, state, s);
-    else
-        gram_tw_launch<T, 4, 4>(g, X, xstride, Y, part, ntw, state, s);
+    } else if (g.ld <= 96) {
+        if (g.ld % 48 == 0)
+            gram_tw_launch<T, 3, 4, true>(g, X, xstride, Y, part, ntw, state, s);
+        else
+            gram_tw_launch<T, 3, 4, false>(g, X, xstride, Y, part, ntw, state, s);
+    } else if (g.ld % 64 == 0) {
+        gram_tw_launch<T, 4, 4, true>(g, X, xstride, Y, part, ntw, state, s);
+    } else {
+        gram_tw_launch<T, 4, 4, false>(g, X, xstride, Y, part, ntw, state, s);
+    }
     dim3 rgrid(grid_for((int64_t)g.ld * g.ld, 64), g.nprod);
     k_gram_reduce<T><<<rgrid, 64 * kRedGroups, 0, s>>>(part, g.nchunk, g.ld, g.sym ? 1 : 0, mode, out, out_stride,
                                                         state);
@@ -699,7 +738,7 @@ void gram_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, dou
 template <typename T, int NTW>
 void update_one(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, int nprod, const T* S, int64_t Np,
                 int ld, const int* state, hipStream_t s) {
-    constexpr int MT = 2;
+    constexpr int MT = sizeof(T) == 4 ? 2 : 1;   // FP64: one row tile per wave keeps two waves per SIMD
     const int64_t rows_per_block = 4 * 16 * MT;
     dim3 grid(static_cast<unsigned>((Np + rows_per_block - 1) / rows_per_block), (ld + 16 * NTW - 1) / (16 * NTW));
     k_update<T, MT, NTW><<<grid, 256, 0, s>>>(OUT, IN, alpha, X, xstride, nprod, S, Np, ld, state);

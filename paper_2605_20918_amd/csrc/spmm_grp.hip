@@ -22,65 +22,14 @@
 #include <algorithm>
 
 #include "css_common.h"
+#include "mfma_util.h"
 #include "spmm.h"
 
 namespace css {
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
 template <typename T>
-struct GMF;
-template <>
-struct GMF<double> {
-    typedef d4 acc;
-    static constexpr int VW = 2;      // elements per 16-byte access
-    __device__ static acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
-    __device__ static acc mma(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-    __device__ static int row(int l, int r) { return (l >> 4) + 4 * r; }
-};
-template <>
-struct GMF<float> {
-    typedef f4 acc;
-    static constexpr int VW = 4;
-    __device__ static acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
-    __device__ static acc mma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-    __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
-};
-
-template <typename T, int Q>
-__device__ inline void load_q(const T* p, T (&o)[Q]) {
-    if constexpr (Q == 1) {
-        o[0] = *p;
-    } else {
-        typedef T vt __attribute__((ext_vector_type(Q)));
-        const vt v = *reinterpret_cast<const vt*>(p);
-#pragma unroll
-        for (int e = 0; e < Q; ++e) o[e] = v[e];
-    }
-}
-
-template <typename T, int Q>
-__device__ inline void store_q(T* p, const T (&o)[Q]) {
-    if constexpr (Q == 1) {
-        *p = o[0];
-    } else {
-        typedef T vt __attribute__((ext_vector_type(Q)));
-        vt v;
-#pragma unroll
-        for (int e = 0; e < Q; ++e) v[e] = o[e];
-        *reinterpret_cast<vt*>(p) = v;
-    }
-}
-
-// Segment widths: tiles [0, NT) are split into runs of VW, then 2, then 1.
-template <int NT, int VW>
-struct Seg {
-    static constexpr int full = NT / VW * VW;
-    static constexpr int two = (VW > 2 && NT - full >= 2) ? 2 : 0;
-    static constexpr int one = NT - full - two;
-};
+using GMF = Mfma<T>;
 
 // Per group: U_g (sorted unique columns) at U[rp[16g] ..], |U_g| in ucount[g], and for
 // every CSR entry t of the group pos[t] = (row - 16g) << 16 | (position of col[t] in U_g).
@@ -209,24 +158,8 @@ __global__ __launch_bounds__(256) void k_grp_fill(int n, const int32_t* __restri
 template <typename T, int NT>
 __device__ inline void load_step(const T* __restrict__ Hb, const T* __restrict__ V, const int32_t* uidx, int ld,
                                  int st, int lane, int lr, int lc, T& a, T (&x)[NT]) {
-    typedef GMF<T> M;
-    typedef Seg<NT, M::VW> S;
     a = Hb[64 * st + lane];
-    const T* vr = V + (int64_t)uidx[4 * st + lr] * ld;
-#pragma unroll
-    for (int t = 0; t < S::full; t += M::VW) {
-        T y[M::VW];
-        load_q<T, M::VW>(vr + 16 * t + lc * M::VW, y);
-#pragma unroll
-        for (int e = 0; e < M::VW; ++e) x[t + e] = y[e];
-    }
-    if constexpr (S::two) {
-        T y[2];
-        load_q<T, 2>(vr + 16 * S::full + lc * 2, y);
-        x[S::full] = y[0];
-        x[S::full + 1] = y[1];
-    }
-    if constexpr (S::one) x[NT - 1] = vr[16 * (NT - 1) + lc];
+    load_run<T, NT>(V + (int64_t)uidx[4 * st + lr] * ld, lc, x);
 }
 
 // One wavefront per group of 16 rows: W rows = Hg * V[U_g]. The union is walked in
@@ -242,7 +175,6 @@ __global__ __launch_bounds__(64) void k_spmm_grp(int n, int ngroups, int per_xcd
                                                  const int64_t* __restrict__ boff, const T* __restrict__ hblk,
                                                  const T* __restrict__ V, T* __restrict__ W, int ld) {
     typedef GMF<T> M;
-    typedef Seg<NT, M::VW> S;
     __shared__ int32_t uidx[UC];
     const int lane = threadIdx.x, lr = lane >> 4, lc = lane & 15;
     const int g = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
@@ -284,19 +216,10 @@ __global__ __launch_bounds__(64) void k_spmm_grp(int n, int ngroups, int per_xcd
     for (int r = 0; r < 4; ++r) {
         const int row = r0 + M::row(lane, r);
         if (row >= r1) continue;
-        T* wr = W + (int64_t)row * ld;
+        T y[NT];
 #pragma unroll
-        for (int t = 0; t < S::full; t += M::VW) {
-            T y[M::VW];
-#pragma unroll
-            for (int e = 0; e < M::VW; ++e) y[e] = c[t + e][r];
-            store_q<T, M::VW>(wr + 16 * t + lc * M::VW, y);
-        }
-        if constexpr (S::two) {
-            const T y[2] = {c[S::full][r], c[S::full + 1][r]};
-            store_q<T, 2>(wr + 16 * S::full + lc * 2, y);
-        }
-        if constexpr (S::one) wr[16 * (NT - 1) + lc] = c[NT - 1][r];
+        for (int t = 0; t < NT; ++t) y[t] = c[t][r];
+        store_run<T, NT>(W + (int64_t)row * ld, lc, y);
     }
 }
 
