@@ -494,6 +494,173 @@ __global__ __launch_bounds__(256) void k_chol_inv_reg(const double* __restrict__
         }
 }
 
+// One wavefront, blocks of 16 (NB blocks, b <= 16 NB): Cholesky G = R^T R of the
+// leading b x b block and X = R^-1, with no workgroup barrier on the critical path.
+// LDS holds the 16NB x 16NB matrix M (row stride W): G's upper triangle, then R;
+// rows/columns b..16NB-1 are padded with the identity. Diagonal blocks are factored
+// and inverted in registers (MFMA D layout: lane l holds rows (l>>4)+4r, column l&15)
+// with cross-lane broadcasts; panel solves R_kj = R_kk^-T A_kj, trailing updates
+// A_ij -= R_ki^T R_kj and the blocked inverse X_ij = -X_ii sum_{k=i+1..j} R_ik X_kj
+// run on FP64 MFMA. The X_jj are kept in XD (D layout); the X_ij (i < j) are stored
+// transposed in the strictly lower block triangle of M.
+__device__ inline double lane_bcast(double v, int src) { return __shfl(v, src, 64); }
+
+template <int NB>
+__global__ __launch_bounds__(64) void k_chol_inv_blk(const double* __restrict__ G, int b, int ld,
+                                                     const double* __restrict__ tau_p, double* __restrict__ R,
+                                                     double* __restrict__ Rinv, int* state, int step,
+                                                     double* __restrict__ min_diag) {
+    constexpr int N = 16 * NB, W = N + 1;
+    extern __shared__ double chol_lds[];
+    double* M = chol_lds;                 // N x W
+    double* XD = chol_lds + N * W;        // NB x 256 (D layout)
+    if (state[0]) return;
+    typedef MF<double> Mf;
+    const int l = threadIdx.x, lr = l >> 4, lc = l & 15;
+    const double tau = tau_p ? *tau_p : 0.0;
+    // rows in batches of 12 with every load issued before the LDS stores (N*N/64 = 4 N elements per lane)
+    for (int e0 = 0; e0 < N * N; e0 += 64 * 12) {
+        double v[12];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            const int e = e0 + 64 * q + l;
+            const int i = e / N, j = e % N;
+            v[q] = (e < N * N && i < b && j < b && j >= i) ? G[(int64_t)i * ld + j] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            const int e = e0 + 64 * q + l;
+            const int i = e / N, j = e % N;
+            if (e < N * N) M[i * W + j] = (i >= b && i == j) ? 1.0 : v[q];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    bool fail = false;
+    double dmin = INFINITY;
+    for (int kb = 0; kb < NB && !fail; ++kb) {
+        const int o = 16 * kb;
+        // (a)-(b) diagonal block: unblocked Cholesky in registers
+        double a[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = M[(o + lr + 4 * r) * W + o + lc];
+        double dinv[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int rk = k >> 2, sl = 16 * (k & 3);
+            const double piv = lane_bcast(a[rk], sl + k);
+            double d = 1.0;
+            if (o + k < b && !fail) {                   // uniform: piv is the same in every lane
+                if (!(piv > 0.0) || !isfinite(piv)) {
+                    fail = true;
+                } else {
+                    d = sqrt(piv);
+                    dmin = fmin(dmin, d);
+                    if (!(d > tau)) fail = true;
+                }
+            }
+            dinv[k] = 1.0 / d;                          // after a failure the block is discarded
+            if (lr == (k & 3)) a[rk] = lc > k ? a[rk] * dinv[k] : (lc == k ? d : 0.0);
+            const double vj = lane_bcast(a[rk], sl + lc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double vi = lane_bcast(a[rk], sl + lr + 4 * r);
+                if (lr + 4 * r > k && lc >= lr + 4 * r) a[r] -= vi * vj;
+            }
+        }
+        if (fail) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) M[(o + lr + 4 * r) * W + o + lc] = a[r];
+        // (c) X_kk = R_kk^-1 by backward substitution: row i of X is final once scaled
+        double x[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = (lr + 4 * r == lc) ? 1.0 : 0.0;
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+            const int ri = i >> 2, si = 16 * (i & 3);
+            if (lr == (i & 3)) x[ri] *= dinv[i];
+            const double xij = lane_bcast(x[ri], si + lc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double rii = lane_bcast(a[r], 16 * lr + i);     // R_kk[lr + 4r][i]
+                if (lr + 4 * r < i) x[r] -= rii * xij;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) XD[kb * 256 + r * 64 + l] = x[r];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // (d) panel R_kj = X_kk^T A_kj
+        for (int jb = kb + 1; jb < NB; ++jb) {
+            Mf::acc c = Mf::zero();
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) c = Mf::mma(x[s4], M[(o + 4 * s4 + lr) * W + 16 * jb + lc], c);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) M[(o + lr + 4 * r) * W + 16 * jb + lc] = c[r];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // (e) trailing update A_ij -= R_ki^T R_kj, kb < i <= j
+        for (int ib = kb + 1; ib < NB; ++ib)
+            for (int jb = ib; jb < NB; ++jb) {
+                Mf::acc c;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) c[r] = M[(16 * ib + lr + 4 * r) * W + 16 * jb + lc];
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4)
+                    c = Mf::mma(-M[(o + 4 * s4 + lr) * W + 16 * ib + lc], M[(o + 4 * s4 + lr) * W + 16 * jb + lc], c);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) M[(16 * ib + lr + 4 * r) * W + 16 * jb + lc] = c[r];
+            }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    if (l == 0) min_diag[step] = dmin;
+    if (fail) {
+        for (int idx = l; idx < ld * ld; idx += 64) { Rinv[idx] = 0.0; R[idx] = 0.0; }
+        if (l == 0) { state[2] = step; state[0] = 1; }
+        return;
+    }
+    // blocked inverse, block column by block column
+    for (int jb = 1; jb < NB; ++jb)
+        for (int ib = jb - 1; ib >= 0; --ib) {
+            Mf::acc t = Mf::zero();
+            for (int kb = ib + 1; kb <= jb; ++kb) {
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    const double av = M[(16 * ib + lc) * W + 16 * kb + 4 * s4 + lr];          // R_ik[lc][4s+lr]
+                    const double bv = kb == jb ? XD[jb * 256 + s4 * 64 + l]                    // X_jj[4s+lr][lc]
+                                               : M[(16 * jb + lc) * W + 16 * kb + 4 * s4 + lr];  // X_kj^T
+                    t = Mf::mma(av, bv, t);
+                }
+            }
+            Mf::acc c = Mf::zero();
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int li = lc, lj = 4 * s4 + lr;                   // X_ii[lc][4s+lr]
+                const double av = XD[ib * 256 + (li >> 2) * 64 + 16 * (li & 3) + lj];
+                c = Mf::mma(-av, t[s4], c);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) M[(16 * jb + lc) * W + 16 * ib + lr + 4 * r] = c[r];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll 4
+    for (int i = 0; i < ld; ++i)
+        for (int j = l; j < ld; j += 64) {
+            double rv = 0.0, xv = 0.0;
+            if (i < b && j < b && j >= i) {
+                rv = M[i * W + j];
+                const int bi = i >> 4, bj = j >> 4;
+                if (bi == bj) {
+                    const int li = i & 15, lj = j & 15;
+                    xv = XD[bi * 256 + (li >> 2) * 64 + 16 * (li & 3) + lj];
+                } else {
+                    xv = M[j * W + i];
+                }
+            }
+            R[(int64_t)i * ld + j] = rv;
+            Rinv[(int64_t)i * ld + j] = xv;
+        }
+}
+
 // General-size fallback (global-memory working set).
 __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, int b, int ld,
                                                   const double* __restrict__ tau_p,
@@ -767,8 +934,10 @@ size_t chol_scratch_bytes(int b) { return sizeof(double) * ((size_t)b * (b + 1) 
 void chol_inv_launch(const double* G, int b, int ld, const double* tau, double* R, double* Rinv, double* scratch,
                      int* state, int step, double* min_diag, hipStream_t s) {
     if (b <= 128) {
-        switch ((b + 15) / 16) {
-#define CSS_CHOL(NB) case NB: k_chol_inv_reg<NB><<<1, 256, 0, s>>>(G, b, ld, tau, R, Rinv, state, step, min_diag); return;
+        const int nb = (b + 15) / 16;
+        const size_t lds = sizeof(double) * ((size_t)16 * nb * (16 * nb + 1) + 256 * (size_t)nb);
+        switch (nb) {
+#define CSS_CHOL(NB) case NB: k_chol_inv_blk<NB><<<1, 64, lds, s>>>(G, b, ld, tau, R, Rinv, state, step, min_diag); return;
             CSS_CHOL(1) CSS_CHOL(2) CSS_CHOL(3) CSS_CHOL(4) CSS_CHOL(5) CSS_CHOL(6) CSS_CHOL(7) CSS_CHOL(8)
 #undef CSS_CHOL
             default: break;
