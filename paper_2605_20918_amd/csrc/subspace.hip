@@ -593,6 +593,277 @@ __global__ __launch_bounds__(kPoleThreads) void k_pole_solve(const double* __res
     }
 }
 
+// b <= 96, blocks of 16 (N = 16 NB rows, padded with the identity beyond b):
+// one workgroup per pole, the complex Schur complement S (N x N, row stride
+// N + 1) in LDS. Each S_j is inverted in place by block Gauss-Jordan without
+// pivoting: wave 0 inverts the 16 x 16 diagonal block P = S_kk^-1 in registers,
+// then the row block (S_kj <- P S_kj), the trailing blocks (S_ij -= S_ik S_kj)
+// and the column block (S_ik <- -S_ik P) are updated on FP64 MFMA, four
+// barriers per block step instead of one per pivot. G_j (N x N, global) and the
+// forward sweep are as in k_pole_solve_generic.
+constexpr int kBlkThreads = 512;     // 8 waves: 256 registers per lane, no spills
+constexpr int kBlkWaves = kBlkThreads / 64;
+
+__device__ inline double pole_bcast(double v, int src) { return __shfl(v, src, 64); }
+
+template <int NB>
+__device__ void gj_inverse_blk(double* Sr, double* Si, double* Pr, double* Pi) {
+    constexpr int SW = 16 * NB + 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane >> 4, lc = lane & 15;
+    for (int kb = 0; kb < NB; ++kb) {
+        const int o = 16 * kb;
+        if (wave == 0) {
+            double xr[4], xi[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                xr[r] = Sr[(o + lr + 4 * r) * SW + o + lc];
+                xi[r] = Si[(o + lr + 4 * r) * SW + o + lc];
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int rk = k >> 2, sk = 16 * (k & 3);
+                const double pr = pole_bcast(xr[rk], sk + k), pi = pole_bcast(xi[rk], sk + k);
+                const double den = 1.0 / (pr * pr + pi * pi);
+                const double qr = pr * den, qi = -pi * den;                       // 1 / pivot
+                const double mr = pole_bcast(xr[rk], sk + lc), mi = pole_bcast(xi[rk], sk + lc);
+                const double rr = mr * qr - mi * qi, ri = mr * qi + mi * qr;      // pivot row / pivot
+                double cr[4], ci[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {                                     // column k, my rows
+                    cr[r] = pole_bcast(xr[r], 16 * lr + k);
+                    ci[r] = pole_bcast(xi[r], 16 * lr + k);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = lr + 4 * r;
+                    double nr, ni;
+                    if (i == k) {
+                        nr = (lc == k) ? qr : rr;
+                        ni = (lc == k) ? qi : ri;
+                    } else if (lc == k) {
+                        nr = -(cr[r] * qr - ci[r] * qi);
+                        ni = -(cr[r] * qi + ci[r] * qr);
+                    } else {
+                        nr = xr[r] - (cr[r] * rr - ci[r] * ri);
+                        ni = xi[r] - (cr[r] * ri + ci[r] * rr);
+                    }
+                    xr[r] = nr;
+                    xi[r] = ni;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Pr[(lr + 4 * r) * 17 + lc] = xr[r];
+                Pi[(lr + 4 * r) * 17 + lc] = xi[r];
+            }
+        }
+        __syncthreads();
+        if (wave < NB - 1) {                                  // row block: S_kj <- P S_kj
+            const int jb = wave < kb ? wave : wave + 1;
+            pd4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int k = 4 * s4 + lr;
+                const double ar = Pr[lc * 17 + k], ai = Pi[lc * 17 + k];
+                const double br = Sr[(o + k) * SW + 16 * jb + lc], bi = Si[(o + k) * SW + 16 * jb + lc];
+                cr = mfma64(ar, br, cr);
+                cr = mfma64(-ai, bi, cr);
+                ci = mfma64(ar, bi, ci);
+                ci = mfma64(ai, br, ci);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Sr[(o + lr + 4 * r) * SW + 16 * jb + lc] = cr[r];
+                Si[(o + lr + 4 * r) * SW + 16 * jb + lc] = ci[r];
+            }
+        }
+        __syncthreads();
+        for (int t = wave; t < (NB - 1) * (NB - 1); t += kBlkWaves) {   // trailing: S_ij -= S_ik S_kj
+            int ib = t / (NB - 1), jb = t % (NB - 1);
+            ib += ib >= kb;
+            jb += jb >= kb;
+            pd4 cr, ci;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                cr[r] = Sr[(16 * ib + lr + 4 * r) * SW + 16 * jb + lc];
+                ci[r] = Si[(16 * ib + lr + 4 * r) * SW + 16 * jb + lc];
+            }
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int k = o + 4 * s4 + lr;
+                const double ar = Sr[(16 * ib + lc) * SW + k], ai = Si[(16 * ib + lc) * SW + k];
+                const double br = Sr[k * SW + 16 * jb + lc], bi = Si[k * SW + 16 * jb + lc];
+                cr = mfma64(-ar, br, cr);
+                cr = mfma64(ai, bi, cr);
+                ci = mfma64(-ar, bi, ci);
+                ci = mfma64(-ai, br, ci);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Sr[(16 * ib + lr + 4 * r) * SW + 16 * jb + lc] = cr[r];
+                Si[(16 * ib + lr + 4 * r) * SW + 16 * jb + lc] = ci[r];
+            }
+        }
+        __syncthreads();
+        if (wave < NB - 1) {                                  // column block: S_ik <- -S_ik P
+            const int ib = wave < kb ? wave : wave + 1;
+            pd4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int k = 4 * s4 + lr;
+                const double ar = Sr[(16 * ib + lc) * SW + o + k], ai = Si[(16 * ib + lc) * SW + o + k];
+                const double br = Pr[k * 17 + lc], bi = Pi[k * 17 + lc];
+                cr = mfma64(-ar, br, cr);
+                cr = mfma64(ai, bi, cr);
+                ci = mfma64(-ar, bi, ci);
+                ci = mfma64(-ai, br, ci);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Sr[(16 * ib + lr + 4 * r) * SW + o + lc] = cr[r];
+                Si[(16 * ib + lr + 4 * r) * SW + o + lc] = ci[r];
+            }
+        } else if (wave == NB - 1) {                          // S_kk <- P
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Sr[(o + lr + 4 * r) * SW + o + lc] = Pr[(lr + 4 * r) * 17 + lc];
+                Si[(o + lr + 4 * r) * SW + o + lc] = Pi[(lr + 4 * r) * 17 + lc];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __restrict__ A,
+                                                                 const double* __restrict__ B, int v, int b, int ld,
+                                                                 double mu, double inv2kT,
+                                                                 const double* __restrict__ kappa,
+                                                                 const double* __restrict__ weight,
+                                                                 const int* __restrict__ counts, double* Gbuf,
+                                                                 double* __restrict__ Wout) {
+    constexpr int N = 16 * NB, SW = N + 1, NTL = NB * NB;
+    constexpr int MAXQ = (NTL + kBlkWaves - 1) / kBlkWaves;
+    extern __shared__ double lds[];
+    double* Sr = lds;
+    double* Si = lds + N * SW;
+    double* Pr = lds + 2 * N * SW;
+    double* Pi = Pr + 16 * 17;
+    const int p = blockIdx.x, tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, lr = lane >> 4, lc = lane & 15;
+    const int64_t mat = (int64_t)ld * ld, nn = (int64_t)N * N;
+    const double a = kappa[p] * inv2kT;
+    const double wgt = weight[p];
+    double* Gp = Gbuf + (int64_t)p * v * 2 * nn;
+    double* Wp = Wout + (int64_t)p * v * b * b;
+    // S = D_{v-1} = I - i a (A_{v-1} - mu) on the leading b x b block, identity beyond
+    {
+        const double* Aj = A + (int64_t)(v - 1) * mat;
+        for (int e = tid; e < N * N; e += kBlkThreads) {
+            const int r = e / N, c = e % N;
+            Sr[r * SW + c] = (r == c) ? 1.0 : 0.0;
+            Si[r * SW + c] = (r < b && c < b) ? -a * (Aj[(int64_t)r * ld + c] - (r == c ? mu : 0.0)) : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int j = v - 1; j >= 0; --j) {
+        gj_inverse_blk<NB>(Sr, Si, Pr, Pi);
+        if (j == 0) break;
+        // G_j = -i a S_j^-1 B_{j-1} (B zero beyond b)
+        const double* Bm = B + (int64_t)(j - 1) * mat;
+        double* Gr = Gp + (int64_t)j * 2 * nn;
+        double* Gi = Gr + nn;
+        for (int t = wave; t < NTL; t += kBlkWaves) {
+            const int m0 = (t / NB) * 16, c0 = (t % NB) * 16;
+            pd4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+#pragma unroll 4
+            for (int k0 = 0; k0 < N; k0 += 4) {
+                const int k = k0 + lr;
+                const double bv = Bm[(int64_t)k * ld + c0 + lc];
+                tr = mfma64(Sr[(m0 + lc) * SW + k], bv, tr);
+                ti = mfma64(Si[(m0 + lc) * SW + k], bv, ti);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + lr + 4 * r, col = c0 + lc;
+                Gr[row * N + col] = a * ti[r];        // Re(-i a (tr + i ti)) = a ti
+                Gi[row * N + col] = -a * tr[r];       // Im = -a tr
+            }
+        }
+        __syncthreads();
+        // S_{j-1} = I - i a (A_{j-1} - mu) + i a B_{j-1}^T G_j
+        const double* Aj = A + (int64_t)(j - 1) * mat;
+        for (int t = wave; t < NTL; t += kBlkWaves) {
+            const int m0 = (t / NB) * 16, c0 = (t % NB) * 16;
+            pd4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+#pragma unroll 4
+            for (int k0 = 0; k0 < N; k0 += 4) {
+                const int k = k0 + lr;
+                const double av = Bm[(int64_t)k * ld + m0 + lc];
+                tr = mfma64(av, Gr[k * N + c0 + lc], tr);
+                ti = mfma64(av, Gi[k * N + c0 + lc], ti);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + lr + 4 * r, col = c0 + lc;
+                const double am = (row < b && col < b) ? Aj[(int64_t)row * ld + col] - (row == col ? mu : 0.0) : 0.0;
+                Sr[row * SW + col] = (row == col ? 1.0 : 0.0) - a * ti[r];
+                Si[row * SW + col] = -a * am + a * tr[r];
+            }
+        }
+        __syncthreads();
+    }
+    // forward sweep: Z_0 = S_0^-1 diag(sqrt(n_c)), Z_j = -G_j Z_{j-1}; W_p block j = weight_p Im Z_j
+    for (int e = tid; e < N * N; e += kBlkThreads) {
+        const int r = e / N, c = e % N;
+        const double sc = c < b ? sqrt((double)counts[c]) : 0.0;
+        Sr[r * SW + c] *= sc;
+        Si[r * SW + c] *= sc;
+        if (r < b && c < b) Wp[r * b + c] = wgt * Si[r * SW + c];
+    }
+    __syncthreads();
+    for (int j = 1; j < v; ++j) {
+        const double* Gr = Gp + (int64_t)j * 2 * nn;
+        const double* Gi = Gr + nn;
+        pd4 nr[MAXQ], ni[MAXQ];
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+            const int t = wave + kBlkWaves * q;
+            nr[q] = pd4{0, 0, 0, 0};
+            ni[q] = pd4{0, 0, 0, 0};
+            if (t >= NTL) continue;
+            const int m0 = (t / NB) * 16, c0 = (t % NB) * 16;
+#pragma unroll 4
+            for (int k0 = 0; k0 < N; k0 += 4) {
+                const int k = k0 + lr;
+                const double g_r = Gr[(m0 + lc) * N + k], g_i = Gi[(m0 + lc) * N + k];
+                const double zr = Sr[k * SW + c0 + lc], zi = Si[k * SW + c0 + lc];
+                nr[q] = mfma64(g_r, zr, nr[q]);
+                nr[q] = mfma64(-g_i, zi, nr[q]);
+                ni[q] = mfma64(g_r, zi, ni[q]);
+                ni[q] = mfma64(g_i, zr, ni[q]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+            const int t = wave + kBlkWaves * q;
+            if (t >= NTL) continue;
+            const int m0 = (t / NB) * 16, c0 = (t % NB) * 16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + lr + 4 * r, col = c0 + lc;
+                Sr[row * SW + col] = -nr[q][r];
+                Si[row * SW + col] = -ni[q][r];
+                if (row < b && col < b) Wp[(int64_t)j * b * b + row * b + col] = -wgt * ni[q][r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+size_t pole_blk_lds_bytes(int nb) { return sizeof(double) * (2 * (size_t)16 * nb * (16 * nb + 1) + 2 * 16 * 17); }
+
 // F = g (E_1 B_0 / 2 - sum_p W_p), poles summed in order.
 __global__ void k_pole_sum(const double* __restrict__ Wout, int npole, int64_t nTb, int b,
                            const int* __restrict__ counts, double g, double* __restrict__ F) {
@@ -651,7 +922,9 @@ int max_lds() {
 size_t pole_workspace_bytes(int v, int b) {
     const int64_t np = kMaxDepth / 2 + 1;
     const int64_t bb = (int64_t)b * b;
-    return sizeof(double) * (size_t)(np * (v * 2 * bb + v * bb + 2 * bb) + 2 * np + 2 * (int64_t)v * b + 16) + 4096;
+    const int64_t n16 = 16 * (int64_t)((b + 15) / 16);
+    const int64_t gmat = std::max(bb, n16 * n16);          // G blocks (padded for the blocked solver)
+    return sizeof(double) * (size_t)(np * (v * 2 * gmat + v * bb + 2 * bb) + 2 * np + 2 * (int64_t)v * b + 16) + 4096;
 }
 
 css_status subspace_fermi_poles(const double* A, const double* B, int v, int b, int ld, const int* counts,
@@ -679,7 +952,9 @@ css_status subspace_fermi_poles(const double* A, const double* B, int v, int b, 
     const int np = static_cast<int>(pt.kappa.size());
     double* kap = ar.take<double>(np);
     double* wgt = ar.take<double>(np);
-    double* Gbuf = ar.take<double>((int64_t)np * v * 2 * bb);
+    const int nb16 = (b + 15) / 16;
+    const int64_t gmat = std::max<int64_t>(bb, (int64_t)256 * nb16 * nb16);
+    double* Gbuf = ar.take<double>((int64_t)np * v * 2 * gmat);
     double* Wout = ar.take<double>((int64_t)np * v * bb);
     const size_t lds_bytes = sizeof(double) * 2 * bb;
     const bool use_lds = lds_bytes + 8192 <= (size_t)max_lds();
@@ -687,7 +962,19 @@ css_status subspace_fermi_poles(const double* A, const double* B, int v, int b, 
     if (ar.overflow) return CSS_E_WORKSPACE;
     CSS_HIP_TRY(hipMemcpyAsync(kap, pt.kappa.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
     CSS_HIP_TRY(hipMemcpyAsync(wgt, pt.weight.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
-    if (b <= 96 && use_lds)
+    const size_t blk_lds = pole_blk_lds_bytes(nb16);
+    if (b <= 96 && ld == 16 * nb16 && blk_lds <= (size_t)max_lds()) {
+        switch (nb16) {
+#define CSS_POLE(NB)                                                                                              \
+    case NB:                                                                                                      \
+        k_pole_solve_blk<NB><<<np, kBlkThreads, blk_lds, s>>>(A, B, v, b, ld, mu, 1.0 / (2.0 * kT), kap, wgt,    \
+                                                               counts, Gbuf, Wout);                               \
+        break;
+            CSS_POLE(1) CSS_POLE(2) CSS_POLE(3) CSS_POLE(4) CSS_POLE(5) CSS_POLE(6)
+#undef CSS_POLE
+            default: return CSS_E_UNSUPPORTED;
+        }
+    } else if (b <= 96 && use_lds)
         k_pole_solve<<<np, kPoleThreads, lds_bytes, s>>>(A, B, v, b, ld, mu, 1.0 / (2.0 * kT), kap, wgt, counts, Gbuf,
                                                          Wout);
     else

@@ -196,8 +196,15 @@ def workspace_size(entry: int, n: int, nnz: int, n_colors: int, depth: int, flag
     return int(out.value)
 
 
+_color_capacity: dict = {}
+
+
 def css_color(xyz, box, r_cut: float):
-    """Conflict pattern and greedy colouring. Returns (color, n_colors, p_row_ptr, p_col, rounds)."""
+    """Conflict pattern and greedy colouring. Returns (color, n_colors, p_row_ptr, p_col, rounds).
+
+    The pattern's column array is allocated from the last size seen for this orbital
+    count (+5%), so a repeated call does the work once; a first call (or one that
+    outgrows the capacity) asks for the exact size first."""
     torch = _torch()
     lib = load()
     xyz = xyz.to(torch.float64).contiguous()
@@ -210,14 +217,28 @@ def css_color(xyz, box, r_cut: float):
     ncol = ctypes.c_int32(0)
     rounds = ctypes.c_int32(0)
     s = _stream(dev)
+    color = torch.empty(n, dtype=torch.int32, device=dev)
+    cap = _color_capacity.get((n, str(dev)))
+    if cap is not None:
+        p_col = torch.empty(cap, dtype=torch.int32, device=dev)
+        nnz.value = cap
+        code = lib.css_color(_ptr(xyz), n, ctypes.byref(boxa), float(r_cut), _ptr(color), ctypes.byref(ncol),
+                             _ptr(p_row_ptr), _ptr(p_col), ctypes.byref(nnz), ctypes.byref(rounds), _ptr(ws),
+                             ws.numel(), s)
+        if code == CSS_OK:
+            return color, int(ncol.value), p_row_ptr, p_col[:int(nnz.value)], int(rounds.value)
+        if code != 9:                                   # anything but "capacity too small"
+            _check("css_color", code)
+    nnz.value = 0
     _check("css_color", lib.css_color(_ptr(xyz), n, ctypes.byref(boxa), float(r_cut), None, ctypes.byref(ncol),
                                       _ptr(p_row_ptr), None, ctypes.byref(nnz), ctypes.byref(rounds),
                                       _ptr(ws), ws.numel(), s))
-    p_col = torch.empty(int(nnz.value), dtype=torch.int32, device=dev)
-    color = torch.empty(n, dtype=torch.int32, device=dev)
+    need = int(nnz.value)
+    p_col = torch.empty(need, dtype=torch.int32, device=dev)
     _check("css_color", lib.css_color(_ptr(xyz), n, ctypes.byref(boxa), float(r_cut), _ptr(color),
                                       ctypes.byref(ncol), _ptr(p_row_ptr), _ptr(p_col), ctypes.byref(nnz),
                                       ctypes.byref(rounds), _ptr(ws), ws.numel(), s))
+    _color_capacity[(n, str(dev))] = need + need // 20 + 64
     return color, int(ncol.value), p_row_ptr, p_col, int(rounds.value)
 
 

@@ -65,6 +65,21 @@ def test_colour_special_graphs_bitexact():
     _colour_case(np.zeros((5, 3)), np.zeros(3), 1.0)                      # coincident centres
 
 
+def test_colour_large_frontiers_bitexact():
+    """6000 isolated orbitals (all in the first round, a frontier larger than one
+    workgroup keeps) beside a dense 1-d chain (one orbital per round), colouring
+    and pattern identical to the oracle's; repeated, so the second call reuses the
+    pattern capacity of the first."""
+    rng = np.random.default_rng(11)
+    g = np.arange(6000)
+    iso = np.stack([g % 20, (g // 20) % 20, g // 400], 1).astype(float) * 3.0 + 100.0
+    chain = np.stack([np.arange(300) * 0.1, np.zeros(300), np.zeros(300)], 1)
+    xyz = np.concatenate([chain, iso])[rng.permutation(6300)]
+    r1 = _colour_case(xyz, np.zeros(3), 1.0)
+    r2 = _colour_case(xyz, np.zeros(3), 1.0)
+    assert r1 == r2
+
+
 # ---------------------------------------------------------------- probes
 
 @pytest.mark.parametrize("ones", [False, True])
