@@ -10,9 +10,15 @@ second, N * v_eff / step time.
 Workloads (seeded synthetic water, 6 orbitals per molecule, R_c = 6 A,
 kT = 0.01 Ha, depth 40):
   10k   10 000 molecules (60 000 orbitals), mixed precision (FP32 blocks with
-        full re-orthogonalisation, FP64 small matrices / eigensolve / sums)
+        full re-orthogonalisation, FP64 small matrices / eigensolve / sums);
+        the FP64 path (local re-orthogonalisation) is timed beside it
+  1m    1 000 000 molecules (6 000 000 orbitals), mixed precision with a stored
+        basis; FP64 beside it with the two-pass (no stored basis) variant
   1k    1 000 molecules, FP64
 Prints one JSON line.
+
+--copy-calibration copies 1 GiB device to device three times and prints its
+size: the reference for scaling the HBM byte counters of a profiler run.
 """
 from __future__ import annotations
 
@@ -34,16 +40,52 @@ MU_WATER = -0.41      # mid-gap of the water model (dense spectrum of the 1000-m
 PEAK_HBM_GBS = 8000.0
 
 WORKLOADS = {
-    "10k": dict(n_mol=10000, seed=20921, depth=40, prec="fp32"),
-    "1k": dict(n_mol=1000, seed=20920, depth=40, prec="fp64"),
+    "10k": dict(n_mol=10000, seed=20921, depth=40, prec="fp32", fp64_twopass=False),
+    "1m": dict(n_mol=1000000, seed=20923, depth=40, prec="fp32", fp64_twopass=True),
+    "1k": dict(n_mol=1000, seed=20920, depth=40, prec="fp64", fp64_twopass=False),
 }
 
+# HBM bytes per launch of the grouped SpMM from FETCH_SIZE + WRITE_SIZE counter runs
+# (scaled by a 1 GiB copy), valid while the kernel source hashes to the recorded value
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmm_grp_traffic_10k.json")
 
-def flags_for(prec: str):
+
+def flags_for(prec: str, twopass: bool = False):
     from paper_2605_20918_amd import css
     if prec == "fp32":
         return css.PREC_FP32 | css.REORTH_FULL | css.CHOLQR2 | css.SYMMETRIZE
-    return css.PREC_FP64 | css.REORTH_LOCAL | css.CHOLQR2 | css.SYMMETRIZE
+    return (css.PREC_FP64 | css.REORTH_LOCAL | css.CHOLQR2 | css.SYMMETRIZE |
+            (css.BASIS_TWOPASS if twopass else 0))
+
+
+def kernel_hash() -> str:
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2605_20918_amd", "csrc", "spmm_grp.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch from the committed counter summary, or None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha256_16") != kernel_hash() or t.get("workload") != workload:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 30
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
 
 
 def cpu_model() -> str:
@@ -86,6 +128,7 @@ def main():
     ap.add_argument("--workload", default="10k", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -98,6 +141,9 @@ def main():
         print("no ROCm device visible", file=sys.stderr)
         sys.exit(1)
     css.load()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     wl = WORKLOADS[args.workload]
     print(f"[bench] generating {wl['n_mol']} molecules", file=sys.stderr, flush=True)
     ws = synth.water_system(wl["n_mol"], wl["seed"])
@@ -178,29 +224,43 @@ def main():
         "phases_ms": {**info["t_phase_ms"], "colour_probe_total": t_color * 1e3,
                       "colour_rounds": state["rounds"]},
         "trace": state["trace"], "e_band": state["e_band"], "trace_krylov": info["trace_krylov"],
-        "roofline": {"bound": "hbm", "kernel": "k_spmm_grp" if grouped else "k_spmm_csr", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "bytes_per_launch": bytes_alg, "avg_launch_us": t_spmm * 1e6},
+        "roofline": {"bound": "hbm", "kernel": "k_spmm_grp" if grouped else "k_spmm_csr", "achieved": achieved,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": measured_traffic(args.workload) if grouped else None,
+                     "bytes_per_launch": bytes_alg, "avg_launch_us": t_spmm * 1e6,
+                     "kernel_sha256_16": kernel_hash()},
     }
 
     if wl["prec"] == "fp32" and not args.no_fp64:
-        H64 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, dev, torch.float64)
-        Hsave = H
+        p_mixed = state["p_val"].double().cpu()
+        e_mixed = state["e_band"]
+        del state["p_val"]
+        H = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, dev, torch.float64)
+        f64 = flags_for("fp64", wl["fp64_twopass"])
+        res = {}
 
         def step64():
             color, bb, p_rp, p_col, _ = css.css_color(xyz, box, R_CUT)
             sign, _ = css.css_build_probes(color, bb, wl["seed"])
-            css.css_density_matrix(H64, color, sign, bb, mu, KT, depth, p_rp, p_col, flags_for("fp64"))
+            res["p"], res["e"], _, res["info"] = css.css_density_matrix(H, color, sign, bb, mu, KT, depth, p_rp,
+                                                                         p_col, f64)
         step64()
         torch.cuda.synchronize()
         t64 = time.perf_counter()
         step64()
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t64
+        dp = float(torch.max(torch.abs(res["p"].cpu() - p_mixed)))
         out["fp64_ms_per_step"] = t64 * 1e3
+        out["fp64_flags"] = f64
+        out["fp64_phases_ms"] = res["info"]["t_phase_ms"]
         out["mixed_vs_fp64_speedup"] = t64 / dt
-        del H64, Hsave
+        out["mixed_vs_fp64_max_abs_dP"] = dp
+        out["mixed_vs_fp64_rel_dE"] = abs(e_mixed - res["e"]) / abs(res["e"])
+        del H, res
 
+    if args.workload == "1m":
+        args.no_cpu_baseline = True        # the oracle at this size takes hours; the default run reports it
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the CPU sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(ws, 6, mu)

@@ -767,6 +767,10 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
     }
     __syncthreads();
     for (int j = v - 1; j >= 0; --j) {
+        int zoff = 0;                                          // as in the forward sweep below
+        asm volatile("" : "+v"(zoff));
+        double* Sr = lds + zoff;
+        double* Si = lds + zoff + N * SW;
         gj_inverse_blk<NB>(Sr, Si, Pr, Pi);
         if (j == 0) break;
         // G_j = -i a S_j^-1 B_{j-1} (B zero beyond b)
@@ -776,12 +780,24 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
         for (int t = wave; t < NTL; t += kBlkWaves) {
             const int m0 = (t / NB) * 16, c0 = (t % NB) * 16;
             pd4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
-#pragma unroll 4
-            for (int k0 = 0; k0 < N; k0 += 4) {
-                const int k = k0 + lr;
-                const double bv = Bm[(int64_t)k * ld + c0 + lc];
-                tr = mfma64(Sr[(m0 + lc) * SW + k], bv, tr);
-                ti = mfma64(Si[(m0 + lc) * SW + k], bv, ti);
+            constexpr int H = 8, NH = (N / 4 + H - 1) / H;      // K in chunks of 8 steps of global operands
+#pragma unroll
+            for (int h = 0; h < NH; ++h) {
+                double bv[H];
+#pragma unroll
+                for (int q = 0; q < H; ++q) {
+                    const int s4 = h * H + q;
+                    bv[q] = s4 < N / 4 ? Bm[(int64_t)(4 * s4 + lr) * ld + c0 + lc] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < H; ++q) {
+                    const int s4 = h * H + q;
+                    if (s4 >= N / 4) break;
+                    const int k = 4 * s4 + lr;
+                    tr = mfma64(Sr[(m0 + lc) * SW + k], bv[q], tr);
+                    ti = mfma64(Si[(m0 + lc) * SW + k], bv[q], ti);
+                }
+                __builtin_amdgcn_sched_barrier(0);             // one chunk of operands live at a time
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -796,12 +812,25 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
         for (int t = wave; t < NTL; t += kBlkWaves) {
             const int m0 = (t / NB) * 16, c0 = (t % NB) * 16;
             pd4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
-#pragma unroll 4
-            for (int k0 = 0; k0 < N; k0 += 4) {
-                const int k = k0 + lr;
-                const double av = Bm[(int64_t)k * ld + m0 + lc];
-                tr = mfma64(av, Gr[k * N + c0 + lc], tr);
-                ti = mfma64(av, Gi[k * N + c0 + lc], ti);
+            constexpr int H = 8, NH = (N / 4 + H - 1) / H;      // K in chunks of 8 steps of global operands
+#pragma unroll
+            for (int h = 0; h < NH; ++h) {
+                double av[H], zr[H], zi[H];
+#pragma unroll
+                for (int q = 0; q < H; ++q) {
+                    const int s4 = h * H + q;
+                    const int k = 4 * s4 + lr;
+                    const bool in = s4 < N / 4;
+                    av[q] = in ? Bm[(int64_t)k * ld + m0 + lc] : 0.0;
+                    zr[q] = in ? Gr[k * N + c0 + lc] : 0.0;
+                    zi[q] = in ? Gi[k * N + c0 + lc] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < H; ++q) {
+                    tr = mfma64(av[q], zr[q], tr);
+                    ti = mfma64(av[q], zi[q], ti);
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -825,6 +854,12 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
     for (int j = 1; j < v; ++j) {
         const double* Gr = Gp + (int64_t)j * 2 * nn;
         const double* Gi = Gr + nn;
+        // an opaque zero keeps the per-tile LDS addresses from being hoisted out of this
+        // loop (they would exceed the register budget and be spilled)
+        int zoff = 0;
+        asm volatile("" : "+v"(zoff));
+        double* Sr = lds + zoff;
+        double* Si = lds + zoff + N * SW;
         pd4 nr[MAXQ], ni[MAXQ];
 #pragma unroll
         for (int q = 0; q < MAXQ; ++q) {
@@ -833,15 +868,29 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
             ni[q] = pd4{0, 0, 0, 0};
             if (t >= NTL) continue;
             const int m0 = (t / NB) * 16, c0 = (t % NB) * 16;
-#pragma unroll 4
-            for (int k0 = 0; k0 < N; k0 += 4) {
-                const int k = k0 + lr;
-                const double g_r = Gr[(m0 + lc) * N + k], g_i = Gi[(m0 + lc) * N + k];
-                const double zr = Sr[k * SW + c0 + lc], zi = Si[k * SW + c0 + lc];
-                nr[q] = mfma64(g_r, zr, nr[q]);
-                nr[q] = mfma64(-g_i, zi, nr[q]);
-                ni[q] = mfma64(g_r, zi, ni[q]);
-                ni[q] = mfma64(g_i, zr, ni[q]);
+            constexpr int H = 8, NH = (N / 4 + H - 1) / H;      // K in chunks of 8 steps of global operands
+#pragma unroll
+            for (int h = 0; h < NH; ++h) {
+                double g_r[H], g_i[H];
+#pragma unroll
+                for (int qq = 0; qq < H; ++qq) {
+                    const int s4 = h * H + qq;
+                    const bool in = s4 < N / 4;
+                    g_r[qq] = in ? Gr[(m0 + lc) * N + 4 * s4 + lr] : 0.0;
+                    g_i[qq] = in ? Gi[(m0 + lc) * N + 4 * s4 + lr] : 0.0;
+                }
+#pragma unroll
+                for (int qq = 0; qq < H; ++qq) {
+                    const int s4 = h * H + qq;
+                    if (s4 >= N / 4) break;
+                    const int k = 4 * s4 + lr;
+                    const double zr = Sr[k * SW + c0 + lc], zi = Si[k * SW + c0 + lc];
+                    nr[q] = mfma64(g_r[qq], zr, nr[q]);
+                    nr[q] = mfma64(-g_i[qq], zi, nr[q]);
+                    ni[q] = mfma64(g_r[qq], zi, ni[q]);
+                    ni[q] = mfma64(g_i[qq], zr, ni[q]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         __syncthreads();

@@ -208,16 +208,18 @@ def tight_binding_h(atoms: np.ndarray, L: float, rng, n_mol: int) -> CSR:
                     cols += [n, m]
                     vals += [v, v]
 
-    row = np.concatenate(rows).astype(np.int64)
-    col = np.concatenate(cols).astype(np.int64)
+    row = np.concatenate(rows).astype(np.int32)
+    col = np.concatenate(cols).astype(np.int32)
     val = np.concatenate(vals).astype(np.float64)
-    order = np.lexsort((col, row))
-    row, col, val = row[order], col[order], val[order]
-    row_ptr = np.zeros(N + 1, dtype=np.int64)
-    np.cumsum(np.bincount(row, minlength=N), out=row_ptr[1:])
-    if row_ptr[-1] >= 2 ** 31:
+    if row.size >= 2 ** 31:
         raise ValueError("H has too many nonzeros for int32 row pointers")
-    return CSR(N, row_ptr.astype(np.int32), col.astype(np.int32), val)
+    # CSR with sorted columns; every (row, col) occurs once, so nothing is summed
+    import scipy.sparse as sp
+    m = sp.csr_matrix((val, (row, col)), shape=(N, N))
+    m.sort_indices()
+    if m.nnz != row.size:
+        raise AssertionError("duplicate orbital pair in H")
+    return CSR(N, m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.astype(np.float64))
 
 
 def water_system(n_mol: int, seed: int, edge: float | None = None) -> WaterSystem:
