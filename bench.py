@@ -146,7 +146,9 @@ def main():
         return
     wl = WORKLOADS[args.workload]
     print(f"[bench] generating {wl['n_mol']} molecules", file=sys.stderr, flush=True)
-    ws = synth.water_system(wl["n_mol"], wl["seed"])
+    t_gen = time.perf_counter()
+    ws = synth.water_system(wl["n_mol"], wl["seed"], progress=lambda m: print(
+        f"[bench] generator: {m} ({time.perf_counter() - t_gen:.0f} s)", file=sys.stderr, flush=True))
     dev = torch.device("cuda:0")
     tdt = torch.float32 if wl["prec"] == "fp32" else torch.float64
     H = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, dev, tdt)

@@ -18,6 +18,9 @@ struct GramPlan {
 };
 GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t partial_cap_mats, int elem);
 int64_t gram_partial_mats(int ld);                 // capacity (in ld x ld matrices) to reserve
+// Chunks (partials per product) a Gram of Np rows needs so that no FP32 running sum
+// is longer than a fixed row count (1 for FP64); reserve nprod times this.
+int64_t gram_min_chunks(int64_t Np, int ld, int elem);
 
 // mode: 0 = plain, 1 = (S + S^T)/2, 2 = add (S + S^T)/2 into out (out += sym)
 template <typename T>

@@ -831,6 +831,16 @@ int gram_tile(int ld, int elem) { return (gram_wpg(ld, elem) == 1 ? 16 : 32) * g
 int gram_ks(int ld, int elem) { return gram_wpg(ld, elem) == 1 ? 4 : 2; }
 }
 
+// FP32 Grams: a wave adds at most this many rows in FP32 before its partial is
+// summed in FP64 (rounding of an FP32 running sum grows with its length).
+constexpr int64_t kGramFp32Rows = 512;
+
+int64_t gram_min_chunks(int64_t Np, int ld, int elem) {
+    if (elem != 4) return 1;
+    const int64_t rows = (int64_t)gram_ks(ld, elem) * kGramFp32Rows;     // rows of one chunk
+    return (Np + rows - 1) / rows;
+}
+
 GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t cap_mats, int elem) {
     GramPlan g;
     g.ld = ld;
@@ -845,8 +855,9 @@ GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t cap_mats, in
     const int64_t target_wg =
         std::max<int64_t>(16, 1024 / (gram_wpg(ld, elem) * ks * std::max(1, g.ntiles)));
     int64_t nchunk = (target_wg + nprod - 1) / nprod;
-    nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, cap_mats / std::max(1, nprod)));
     nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, Np / 256));
+    nchunk = std::max<int64_t>(nchunk, gram_min_chunks(Np, ld, elem));
+    nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, cap_mats / std::max(1, nprod)));
     int64_t rpc = (Np + nchunk - 1) / nchunk;
     rpc = (rpc + 63) / 64 * 64;                   // whole prefetch rounds per chunk (Np is a multiple of 256)
     g.rows_per_chunk = rpc;

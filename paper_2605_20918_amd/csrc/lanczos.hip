@@ -340,7 +340,9 @@ css_status plan_lanczos(const css_csr* H, int32_t b, int32_t depth, uint32_t fla
     // chunks per product for the batched full re-orthogonalisation Gram
     const int64_t single = std::min<int64_t>(gram_partial_mats(p.ld), std::max<int64_t>(1, p.Np / 64));
     const int64_t batched = std::min<int64_t>(32, std::max<int64_t>(1, p.Np / 64)) * std::max(1, p.max_coef);
-    p.partial_mats = std::max<int64_t>(1, std::max(single, batched));
+    // FP32: enough chunks that no wave keeps an FP32 running sum over more than a few hundred rows
+    const int64_t bounded = gram_min_chunks(p.Np, p.ld, (int)p.elem) * std::max(1, p.max_coef);
+    p.partial_mats = std::max<int64_t>(1, std::max({single, batched, bounded}));
     p.grp_ok = (flags & CSS_SPMM_CSR) == 0 && p.ld <= 128;
     return CSS_OK;
 }

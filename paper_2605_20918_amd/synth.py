@@ -151,7 +151,7 @@ def _atom_pairs(atoms: np.ndarray, L: float, cut: float):
     return pairs.astype(np.int64)
 
 
-def tight_binding_h(atoms: np.ndarray, L: float, rng, n_mol: int) -> CSR:
+def tight_binding_h(atoms: np.ndarray, L: float, rng, n_mol: int, progress=None) -> CSR:
     n_atoms = atoms.shape[0]
     is_o = (np.arange(n_atoms) % 3) == 0
     n_orb_atom = np.where(is_o, 4, 1)
@@ -181,6 +181,8 @@ def tight_binding_h(atoms: np.ndarray, L: float, rng, n_mol: int) -> CSR:
 
     # inter-atomic hopping, each pair computed once and mirrored
     pairs = _atom_pairs(atoms, L, HOP_CUT)
+    if progress:
+        progress(f"{pairs.shape[0]} atom pairs within {HOP_CUT} A")
     A, B = pairs[:, 0], pairs[:, 1]
     d = atoms[B] - atoms[A]
     d -= L * np.rint(d / L)
@@ -193,6 +195,8 @@ def tight_binding_h(atoms: np.ndarray, L: float, rng, n_mol: int) -> CSR:
         return [np.ones(uvec.shape[0])] + ([uvec[:, 0], uvec[:, 1], uvec[:, 2]] if is_oxygen else [])
 
     for oa in (True, False):
+        if progress:
+            progress(f"hopping blocks from {'O' if oa else 'H'} atoms")
         for ob in (True, False):
             sel = (is_o[A] == oa) & (is_o[B] == ob)
             if not np.any(sel):
@@ -215,6 +219,8 @@ def tight_binding_h(atoms: np.ndarray, L: float, rng, n_mol: int) -> CSR:
         raise ValueError("H has too many nonzeros for int32 row pointers")
     # CSR with sorted columns; every (row, col) occurs once, so nothing is summed
     import scipy.sparse as sp
+    if progress:
+        progress(f"CSR of {row.size} entries")
     m = sp.csr_matrix((val, (row, col)), shape=(N, N))
     m.sort_indices()
     if m.nnz != row.size:
@@ -222,10 +228,15 @@ def tight_binding_h(atoms: np.ndarray, L: float, rng, n_mol: int) -> CSR:
     return CSR(N, m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.astype(np.float64))
 
 
-def water_system(n_mol: int, seed: int, edge: float | None = None) -> WaterSystem:
-    """A periodic water-like box of n_mol molecules with its tight-binding H."""
+def water_system(n_mol: int, seed: int, edge: float | None = None, progress=None) -> WaterSystem:
+    """A periodic water-like box of n_mol molecules with its tight-binding H.
+
+    progress: optional callable taking a short text, called between the stages
+    of a long generation (it does not change the result)."""
     atoms, box, rng = water_geometry(n_mol, seed, edge)
-    H = tight_binding_h(atoms, float(box[0]), rng, n_mol)
+    if progress:
+        progress(f"{3 * n_mol} atoms placed")
+    H = tight_binding_h(atoms, float(box[0]), rng, n_mol, progress)
     orb_atom = np.repeat(np.arange(3 * n_mol), np.tile([4, 1, 1], n_mol)).astype(np.int32)
     orb_xyz = atoms[orb_atom]
     return WaterSystem(n_mol, box, atoms, np.ascontiguousarray(orb_xyz), orb_atom, H, seed,
