@@ -15,6 +15,9 @@ kT = 0.01 Ha, depth 40):
   1m    1 000 000 molecules (6 000 000 orbitals), mixed precision with a stored
         basis; FP64 beside it with the two-pass (no stored basis) variant
   1k    1 000 molecules, FP64
+  batch48  48 independent boxes of 200..8000 molecules (log-uniform sizes, seed
+        20922), mixed precision: every box coloured, then all densities in one
+        css_density_matrix_batched call; compared with one call per box
 Prints one JSON line.
 
 --copy-calibration copies 1 GiB device to device three times and prints its
@@ -43,7 +46,96 @@ WORKLOADS = {
     "10k": dict(n_mol=10000, seed=20921, depth=40, prec="fp32", fp64_twopass=False),
     "1m": dict(n_mol=1000000, seed=20923, depth=40, prec="fp32", fp64_twopass=True),
     "1k": dict(n_mol=1000, seed=20920, depth=40, prec="fp64", fp64_twopass=False),
+    "batch48": dict(n_mol=0, seed=20922, depth=40, prec="fp32", fp64_twopass=False),
 }
+BATCH_SIZE_SEED = 20922
+BATCH_COUNT = 48
+
+
+def batch_sizes():
+    rng = np.random.default_rng(BATCH_SIZE_SEED)
+    return np.round(np.exp(rng.uniform(np.log(200.0), np.log(8000.0), BATCH_COUNT))).astype(int)
+
+
+def run_batch(args):
+    """48 uneven water boxes: colouring per box, then one batched density call."""
+    import torch
+    from paper_2605_20918_amd import css, synth
+    wl = WORKLOADS["batch48"]
+    sizes = batch_sizes()
+    dev = torch.device("cuda:0")
+    boxes = []
+    t_gen = time.perf_counter()
+    for k, M in enumerate(sizes):
+        w = synth.water_system(int(M), BATCH_SIZE_SEED * 100 + k)
+        H = css.DeviceCSR.from_host(w.H.row_ptr, w.H.col, w.H.val, dev, torch.float32)
+        boxes.append((w, H, torch.as_tensor(w.orb_xyz, dtype=torch.float64, device=dev),
+                      [float(x) for x in w.box]))
+    print(f"[bench] generated {len(boxes)} boxes, {int(sizes.sum())} molecules "
+          f"({time.perf_counter() - t_gen:.0f} s)", file=sys.stderr, flush=True)
+    flags = flags_for(wl["prec"])
+    depth = wl["depth"]
+    state = {}
+
+    def colour_all():
+        systems = []
+        for k, (w, H, xyz, box) in enumerate(boxes):
+            color, b, p_rp, p_col, _ = css.css_color(xyz, box, R_CUT)
+            sign, _ = css.css_build_probes(color, b, BATCH_SIZE_SEED * 100 + k)
+            systems.append(dict(H=H, color=color, sign=sign, n_colors=b, mu=MU_WATER, p_row_ptr=p_rp, p_col=p_col))
+        return systems
+
+    def step():
+        t0 = time.perf_counter()
+        systems = colour_all()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = css.css_density_matrix_batched(systems, KT, depth, flags, concurrency=4)
+        torch.cuda.synchronize()
+        state.update(systems=systems, res=res, t_colour=t1 - t0, t_density=time.perf_counter() - t1)
+
+    for i in range(args.warmup):
+        step()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tc = td = 0.0
+    for i in range(args.steps):
+        step()
+        tc += state["t_colour"]
+        td += state["t_density"]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    systems, res = state["systems"], state["res"]
+    work = sum(int(d["H"].n) * r[3]["depth_eff"] for d, r in zip(systems, res))
+    # the same densities, one call per box
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    seq = []
+    for d in systems:
+        seq.append(css.css_density_matrix(d["H"], d["color"], d["sign"], d["n_colors"], d["mu"], KT, depth,
+                                          d["p_row_ptr"], d["p_col"], flags))
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - ts
+    same = all(torch.equal(a[0], b[0]) and a[1] == b[1] for a, b in zip(res, seq))
+    out = {
+        "metric": "aggregate orbital*Krylov-steps/s (48 boxes: colouring + batched P-build)",
+        "value": work / dt, "unit": "orbital*steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{BATCH_COUNT} water boxes of {int(sizes.min())}..{int(sizes.max())} molecules "
+                               f"({int(sizes.sum())} in all, {sum(int(d['H'].n) for d in systems)} orbitals), "
+                               f"fp32 blocks, depth {depth}",
+                   "sizes": [int(x) for x in sizes], "flags": flags, "concurrency": 4},
+        "colour_ms_per_step": tc / args.steps * 1e3,
+        "batched_density_ms": td / args.steps * 1e3,
+        "sequential_density_ms": ts * 1e3,
+        "batched_vs_sequential_density": ts / (td / args.steps),
+        "density_rate_batched": work / (td / args.steps),
+        "density_rate_sequential": work / ts,
+        "batched_equals_sequential_bitwise": same,
+    }
+    print(json.dumps(out), flush=True)
 
 # HBM bytes per launch of the grouped SpMM from FETCH_SIZE + WRITE_SIZE counter runs
 # (scaled by a 1 GiB copy), valid while the kernel source hashes to the recorded value
@@ -143,6 +235,9 @@ def main():
     css.load()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "batch48":
+        run_batch(args)
         return
     wl = WORKLOADS[args.workload]
     print(f"[bench] generating {wl['n_mol']} molecules", file=sys.stderr, flush=True)

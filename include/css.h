@@ -216,6 +216,45 @@ css_status css_density_matrix(const css_csr* H, const int32_t* color, const int8
                               double* e_band, double* trace, css_info* info,
                               void* ws, size_t ws_bytes, void* stream);
 
+/* One system of a batch (all arrays device, as for css_density_matrix). */
+typedef struct {
+    css_csr H;                    /* the system's Hamiltonian */
+    const int32_t* color;         /* int32[H.n], colours 0..n_colors-1 */
+    const int8_t* sign;           /* int8[H.n], probe signs */
+    int32_t n_colors;
+    double mu;                    /* the system's chemical potential */
+    const int64_t* p_row_ptr;     /* pattern, as css_density_matrix */
+    const int32_t* p_col;
+    int64_t p_nnz;
+    double* p_val;                /* out: double[p_nnz] */
+    double e_band, trace;         /* out */
+    css_info info;                /* out */
+    css_status status;            /* out: this system's status */
+} css_system;
+
+#define CSS_MAX_BATCH_STREAMS 16
+
+/*
+ * css_density_matrix_batched -- css_density_matrix for `count` independent
+ *   systems of uneven size (clusters, fragments, snapshots) in one call. Each
+ *   system's result (p_val, e_band, trace, info) is bitwise the one the single-
+ *   system call gives; kT, depth, spin_deg and flags are shared. The systems run
+ *   side by side on `concurrency` (1..16) library-created streams of default
+ *   priority, largest first, so that the N-independent, latency-bound phases of
+ *   small systems overlap. Work starts after the work already queued on
+ *   `stream`; all of it is complete when the call returns.
+ *   ws        device, css_batched_workspace_size(...) bytes: one slice per stream.
+ *   Returns the first failing system's status (every system's own status is in
+ *   its struct), CSS_E_UNSUPPORTED with CSS_SUBSPACE_EIG.
+ */
+css_status css_density_matrix_batched(css_system* systems, int32_t count, double kT, int32_t depth,
+                                      double spin_deg, uint32_t flags, int32_t concurrency,
+                                      void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for css_density_matrix_batched (host only). */
+css_status css_batched_workspace_size(const css_system* systems, int32_t count, int32_t depth,
+                                      uint32_t flags, int32_t concurrency, size_t* bytes);
+
 /*
  * css_workspace_size -- bytes of workspace an entry point needs.
  *   entry  CSS_ENTRY_*; the other arguments as they will be passed

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 
 #include "css_common.h"
@@ -797,16 +798,17 @@ __global__ __launch_bounds__(64) void k_gemm_f64(int Mr, int Nc, int K, const do
 }
 
 int max_lds_bytes() {
-    static int cached = -1;
-    if (cached < 0) {
+    static std::atomic<int> cached{-1};        // same value from any thread
+    int c = cached.load(std::memory_order_relaxed);
+    if (c < 0) {
         int dev = 0, v = 65536;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
-            cached = v;
-        else
-            cached = 65536;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 65536;
+        cached.store(v, std::memory_order_relaxed);
+        c = v;
     }
-    return cached;
+    return c;
 }
 
 }  // namespace

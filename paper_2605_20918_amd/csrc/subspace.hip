@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -954,16 +955,17 @@ __global__ void k_krylov_sums(const double* __restrict__ A, const double* __rest
 }
 
 int max_lds() {
-    static int cached = -1;
-    if (cached < 0) {
+    static std::atomic<int> cached{-1};        // same value from any thread
+    int c = cached.load(std::memory_order_relaxed);
+    if (c < 0) {
         int dev = 0, val = 65536;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&val, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
-            cached = val;
-        else
-            cached = 65536;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&val, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            val = 65536;
+        cached.store(val, std::memory_order_relaxed);
+        c = val;
     }
-    return cached;
+    return c;
 }
 
 }  // namespace

@@ -68,6 +68,14 @@ class InfoStruct(ctypes.Structure):
                                enumerate(["lanczos", "subspace", "f_pad", "reconstruction", "gather", "total"])}}
 
 
+class SystemStruct(ctypes.Structure):
+    _fields_ = [("H", CsrStruct), ("color", ctypes.c_void_p), ("sign", ctypes.c_void_p),
+                ("n_colors", ctypes.c_int32), ("mu", ctypes.c_double), ("p_row_ptr", ctypes.c_void_p),
+                ("p_col", ctypes.c_void_p), ("p_nnz", ctypes.c_int64), ("p_val", ctypes.c_void_p),
+                ("e_band", ctypes.c_double), ("trace", ctypes.c_double), ("info", InfoStruct),
+                ("status", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -91,6 +99,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.css_color.argtypes = [vp, i32, ctypes.POINTER(dbl * 3), dbl, vp, ctypes.POINTER(i32), vp, vp,
                               ctypes.POINTER(i64), ctypes.POINTER(i32), vp, sz, vp]
     lib.css_build_probes.argtypes = [vp, i32, i32, u64, u32, vp, vp, vp]
+    psys = ctypes.POINTER(SystemStruct)
+    lib.css_density_matrix_batched.argtypes = [psys, i32, dbl, i32, dbl, u32, i32, vp, sz, vp]
+    lib.css_batched_workspace_size.argtypes = [psys, i32, i32, u32, i32, ctypes.POINTER(sz)]
     lib.css_spmm_prepare.argtypes = [pcsr, vp, sz, vp]
     lib.css_spmm.argtypes = [pcsr, vp, vp, i32, i32, vp, sz, vp]
     lib.css_block_lanczos.argtypes = [pcsr, vp, vp, i32, i32, u32, vp, vp, pinfo, vp, sz, vp]
@@ -104,7 +115,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.css_status_string.argtypes = [i32]
     lib.css_status_string.restype = ctypes.c_char_p
     for name in ("css_color", "css_build_probes", "css_spmm_prepare", "css_spmm", "css_block_lanczos",
-                 "css_density_matrix",
+                 "css_density_matrix", "css_density_matrix_batched", "css_batched_workspace_size",
                  "css_workspace_size"):
         getattr(lib, name).restype = i32
     _lib = lib
@@ -312,3 +323,39 @@ def css_density_matrix(H: DeviceCSR, color, sign, n_colors: int, mu: float, kT: 
                                      ctypes.byref(e_band), ctypes.byref(trace), ctypes.byref(info), _ptr(ws),
                                      ws.numel(), _stream(dev)))
     return p_val, float(e_band.value), float(trace.value), info.as_dict()
+
+
+def css_density_matrix_batched(systems, kT: float, depth: int, flags: int, concurrency: int = 4,
+                               spin_deg: float = 2.0, check: bool = True):
+    """Independent systems in one call. `systems`: list of dicts with keys H (DeviceCSR),
+    color, sign, n_colors, mu, p_row_ptr, p_col. Returns a list of (p_val, e_band, trace,
+    info, status) in input order; with check, raises if any system failed."""
+    torch = _torch()
+    lib = load()
+    n = len(systems)
+    arr = (SystemStruct * n)()
+    outs = []
+    dev = systems[0]["color"].device
+    for k, d in enumerate(systems):
+        nnz_p = int(d["p_col"].numel())
+        p_val = torch.empty(nnz_p, dtype=torch.float64, device=dev)
+        outs.append(p_val)
+        arr[k].H = d["H"].struct()
+        arr[k].color = _ptr(d["color"])
+        arr[k].sign = _ptr(d["sign"])
+        arr[k].n_colors = int(d["n_colors"])
+        arr[k].mu = float(d["mu"])
+        arr[k].p_row_ptr = _ptr(d["p_row_ptr"])
+        arr[k].p_col = _ptr(d["p_col"])
+        arr[k].p_nnz = nnz_p
+        arr[k].p_val = _ptr(p_val)
+    need = ctypes.c_size_t(0)
+    _check("css_batched_workspace_size",
+           lib.css_batched_workspace_size(arr, n, depth, flags, concurrency, ctypes.byref(need)))
+    ws = workspace(int(need.value), dev)
+    code = lib.css_density_matrix_batched(arr, n, float(kT), depth, float(spin_deg), flags, concurrency, _ptr(ws),
+                                          ws.numel(), _stream(dev))
+    res = [(outs[k], arr[k].e_band, arr[k].trace, arr[k].info.as_dict(), arr[k].status) for k in range(n)]
+    if check:
+        _check("css_density_matrix_batched", code)
+    return res

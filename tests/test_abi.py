@@ -12,7 +12,8 @@ pytestmark = pytest.mark.skipif(not os.path.exists(css.LIB_PATH), reason="libcss
 def test_every_declared_symbol_is_exported():
     names = css.declared_symbols()
     assert {"css_color", "css_build_probes", "css_block_lanczos", "css_density_matrix", "css_spmm",
-            "css_spmm_prepare", "css_workspace_size", "css_status_string", "css_block_ld"} <= set(names)
+            "css_spmm_prepare", "css_workspace_size", "css_status_string", "css_block_ld",
+            "css_density_matrix_batched", "css_batched_workspace_size"} <= set(names)
     lib = ctypes.CDLL(css.LIB_PATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
@@ -31,6 +32,9 @@ def test_argument_errors_before_any_device_work():
     assert lib.css_build_probes(None, 0, 1, 0, 0, None, None, None) == 1
     assert lib.css_spmm(None, None, None, 1, 16, None, 0, None) == 1
     assert lib.css_spmm_prepare(None, None, 0, None) == 1
+    assert lib.css_density_matrix_batched(None, 0, 0.01, 4, 2.0, 0, 4, None, 0, None) == 1
+    out_b = ctypes.c_size_t(0)
+    assert lib.css_batched_workspace_size(None, 0, 4, 0, 4, ctypes.byref(out_b)) == 1
     out = ctypes.c_size_t(0)
     assert lib.css_workspace_size(0, 0, 0, 1, 1, 0, ctypes.byref(out)) == 1
     # shape-only CSR with placeholder pointers: the size checks come before any device work
@@ -53,3 +57,30 @@ def test_oracle_not_imported_by_product_path():
                 with open(src) as f:
                     text = f.read()
                 assert "import oracle" not in text and "from oracle" not in text, src
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """ctypes mirrors of css_csr, css_info and css_system have the C header's field offsets."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    structs = {"css_csr": css.CsrStruct, "css_info": css.InfoStruct, "css_system": css.SystemStruct}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "css.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -278,6 +278,48 @@ def test_deterministic_bitwise():
     assert torch.equal(p1, p2) and e1 == e2 and t1 == t2
 
 
+# ---------------------------------------------------------------- batched systems
+
+def _system(M, seed, dtype=None):
+    ws, H, rp, col, color, b, sign, mu = water_case(M, seed)
+    return dict(H=to_dev(ws, dtype), color=dev_i32(color), sign=dev_i8(sign), n_colors=b, mu=mu,
+                p_row_ptr=dev_i64(rp), p_col=dev_i32(col))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_equals_single_bitwise(prec):
+    """Uneven systems (8..216 molecules, different b and v_eff) in one batched call give
+    bitwise the results of one call per system."""
+    print(f"batched {prec}", flush=True)
+    flags = FP64_FLAGS if prec == "fp64" else FP32_FLAGS
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    cases = [(125, 11), (8, 1), (64, 20919), (216, 3), (27, 5)]
+    systems = [_system(M, sd, dt) for M, sd in cases]
+    res = css.css_density_matrix_batched(systems, KT, 12, flags, concurrency=3)
+    effs = set()
+    for d, (p, e, t, info, st) in zip(systems, res):
+        assert st == 0
+        p1, e1, t1, i1 = css.css_density_matrix(d["H"], d["color"], d["sign"], d["n_colors"], d["mu"], KT, 12,
+                                                d["p_row_ptr"], d["p_col"], flags)
+        assert torch.equal(p, p1) and e == e1 and t == t1
+        assert info["depth_eff"] == i1["depth_eff"] and info["n_colors"] == d["n_colors"]
+        effs.add(info["depth_eff"])
+    assert len(effs) > 1
+
+
+def test_batched_reports_each_systems_status():
+    systems = [_system(64, 20919), _system(27, 5)]
+    ws, H, rp, col, color, b, sign, mu = water_case(27, 5)
+    bad_rp = ws.H.row_ptr.copy()
+    bad_rp[3] = bad_rp[4] + 2
+    systems[1]["H"] = css.DeviceCSR.from_host(bad_rp, ws.H.col, ws.H.val, "cuda", torch.float64)
+    res = css.css_density_matrix_batched(systems, KT, 6, FP64_FLAGS, concurrency=2, check=False)
+    assert res[0][4] == 0 and res[1][4] == 2
+    with pytest.raises(css.CssError) as e:
+        css.css_density_matrix_batched(systems, KT, 6, FP64_FLAGS, concurrency=2)
+    assert e.value.code == 2
+
+
 # ---------------------------------------------------------------- special cases and errors
 
 def test_scaled_identity_breaks_down_to_closed_form():
