@@ -16,8 +16,9 @@ kT = 0.01 Ha, depth 40):
         basis; FP64 beside it with the two-pass (no stored basis) variant
   1k    1 000 molecules, FP64
   batch48  48 independent boxes of 200..8000 molecules (log-uniform sizes, seed
-        20922), mixed precision: every box coloured, then all densities in one
-        css_density_matrix_batched call; compared with one call per box
+        20922), mixed precision: all boxes coloured in one css_color_batched call,
+        then all densities in one css_density_matrix_batched call; compared with
+        one density call per box
 Prints one JSON line.
 
 --copy-calibration copies 1 GiB device to device three times and prints its
@@ -79,8 +80,8 @@ def run_batch(args):
 
     def colour_all():
         systems = []
-        for k, (w, H, xyz, box) in enumerate(boxes):
-            color, b, p_rp, p_col, _ = css.css_color(xyz, box, R_CUT)
+        cols = css.css_color_batched([(xyz, box) for (w, H, xyz, box) in boxes], R_CUT, concurrency=4)
+        for k, ((w, H, xyz, box), (color, b, p_rp, p_col, _)) in enumerate(zip(boxes, cols)):
             sign, _ = css.css_build_probes(color, b, BATCH_SIZE_SEED * 100 + k)
             systems.append(dict(H=H, color=color, sign=sign, n_colors=b, mu=MU_WATER, p_row_ptr=p_rp, p_col=p_col))
         return systems

@@ -255,6 +255,34 @@ css_status css_density_matrix_batched(css_system* systems, int32_t count, double
 css_status css_batched_workspace_size(const css_system* systems, int32_t count, int32_t depth,
                                       uint32_t flags, int32_t concurrency, size_t* bytes);
 
+/* One colouring of a batch: the arguments of css_color, outputs included. */
+typedef struct {
+    const double* xyz;            /* device, n x 3 */
+    int32_t n;
+    double box[3];
+    double r_cut;
+    int32_t* color;               /* device int32[n] out */
+    int32_t n_colors;             /* out */
+    int64_t* p_row_ptr;           /* device int64[n+1] out */
+    int32_t* p_col;               /* device int32[p_nnz] out (capacity p_nnz on input) */
+    int64_t p_nnz;                /* in: capacity of p_col; out: entries */
+    int32_t rounds;               /* out */
+    css_status status;            /* out: CSS_E_CAPACITY if p_col was too small */
+} css_color_job;
+
+/*
+ * css_color_batched -- css_color for `count` independent geometries in one call,
+ *   side by side on `concurrency` library streams as css_density_matrix_batched.
+ *   Each job's outputs are those css_color gives for it alone. A job whose
+ *   capacity is too small reports CSS_E_CAPACITY (with the entries needed in
+ *   p_nnz) without affecting the others.
+ *   ws  device, css_color_batched_workspace_size(...) bytes.
+ */
+css_status css_color_batched(css_color_job* jobs, int32_t count, int32_t concurrency, void* ws,
+                             size_t ws_bytes, void* stream);
+css_status css_color_batched_workspace_size(const css_color_job* jobs, int32_t count,
+                                            int32_t concurrency, size_t* bytes);
+
 /*
  * css_workspace_size -- bytes of workspace an entry point needs.
  *   entry  CSS_ENTRY_*; the other arguments as they will be passed

@@ -76,6 +76,13 @@ class SystemStruct(ctypes.Structure):
                 ("status", ctypes.c_int32)]
 
 
+class ColorJobStruct(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_void_p), ("n", ctypes.c_int32), ("box", ctypes.c_double * 3),
+                ("r_cut", ctypes.c_double), ("color", ctypes.c_void_p), ("n_colors", ctypes.c_int32),
+                ("p_row_ptr", ctypes.c_void_p), ("p_col", ctypes.c_void_p), ("p_nnz", ctypes.c_int64),
+                ("rounds", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -99,6 +106,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.css_color.argtypes = [vp, i32, ctypes.POINTER(dbl * 3), dbl, vp, ctypes.POINTER(i32), vp, vp,
                               ctypes.POINTER(i64), ctypes.POINTER(i32), vp, sz, vp]
     lib.css_build_probes.argtypes = [vp, i32, i32, u64, u32, vp, vp, vp]
+    pjob = ctypes.POINTER(ColorJobStruct)
+    lib.css_color_batched.argtypes = [pjob, i32, i32, vp, sz, vp]
+    lib.css_color_batched_workspace_size.argtypes = [pjob, i32, i32, ctypes.POINTER(sz)]
     psys = ctypes.POINTER(SystemStruct)
     lib.css_density_matrix_batched.argtypes = [psys, i32, dbl, i32, dbl, u32, i32, vp, sz, vp]
     lib.css_batched_workspace_size.argtypes = [psys, i32, i32, u32, i32, ctypes.POINTER(sz)]
@@ -116,6 +126,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.css_status_string.restype = ctypes.c_char_p
     for name in ("css_color", "css_build_probes", "css_spmm_prepare", "css_spmm", "css_block_lanczos",
                  "css_density_matrix", "css_density_matrix_batched", "css_batched_workspace_size",
+                 "css_color_batched", "css_color_batched_workspace_size",
                  "css_workspace_size"):
         getattr(lib, name).restype = i32
     _lib = lib
@@ -359,3 +370,53 @@ def css_density_matrix_batched(systems, kT: float, depth: int, flags: int, concu
     if check:
         _check("css_density_matrix_batched", code)
     return res
+
+
+def css_color_batched(geoms, r_cut: float, concurrency: int = 4):
+    """Colours several geometries in one call. `geoms`: list of (xyz tensor, box).
+    Returns a list of (color, n_colors, p_row_ptr, p_col, rounds) as css_color does.
+    Pattern capacities come from the per-size cache (first sight: the 6 A ball
+    estimate); a job that outgrows its capacity is redone alone with the exact size."""
+    torch = _torch()
+    lib = load()
+    n = len(geoms)
+    arr = (ColorJobStruct * n)()
+    keep = []
+    dev = geoms[0][0].device
+    for k, (xyz, box) in enumerate(geoms):
+        xyz = xyz.to(torch.float64).contiguous()
+        m = int(xyz.shape[0])
+        cap = _color_capacity.get((m, str(dev)), 200 * m + 64)
+        color = torch.empty(m, dtype=torch.int32, device=dev)
+        p_row_ptr = torch.empty(m + 1, dtype=torch.int64, device=dev)
+        p_col = torch.empty(cap, dtype=torch.int32, device=dev)
+        keep.append([xyz, box, color, p_row_ptr, p_col])
+        arr[k].xyz = _ptr(xyz)
+        arr[k].n = m
+        for i in range(3):
+            arr[k].box[i] = float(box[i])
+        arr[k].r_cut = float(r_cut)
+        arr[k].color = _ptr(color)
+        arr[k].p_row_ptr = _ptr(p_row_ptr)
+        arr[k].p_col = _ptr(p_col)
+        arr[k].p_nnz = cap
+    need = ctypes.c_size_t(0)
+    _check("css_color_batched_workspace_size",
+           lib.css_color_batched_workspace_size(arr, n, concurrency, ctypes.byref(need)))
+    ws = workspace(int(need.value), dev)
+    code = lib.css_color_batched(arr, n, concurrency, _ptr(ws), ws.numel(), _stream(dev))
+    out = []
+    for k in range(n):
+        xyz, box, color, p_row_ptr, p_col = keep[k]
+        m = int(arr[k].n)
+        if arr[k].status == 9:                           # capacity: redo alone at the exact size
+            _color_capacity.pop((m, str(dev)), None)
+            out.append(css_color(xyz, box, r_cut))
+            continue
+        _check("css_color_batched", arr[k].status)
+        nnz = int(arr[k].p_nnz)
+        _color_capacity[(m, str(dev))] = nnz + nnz // 20 + 64
+        out.append((color, int(arr[k].n_colors), p_row_ptr, p_col[:nnz], int(arr[k].rounds)))
+    if code not in (0, 9):
+        _check("css_color_batched", code)
+    return out

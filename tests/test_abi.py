@@ -13,7 +13,8 @@ def test_every_declared_symbol_is_exported():
     names = css.declared_symbols()
     assert {"css_color", "css_build_probes", "css_block_lanczos", "css_density_matrix", "css_spmm",
             "css_spmm_prepare", "css_workspace_size", "css_status_string", "css_block_ld",
-            "css_density_matrix_batched", "css_batched_workspace_size"} <= set(names)
+            "css_density_matrix_batched", "css_batched_workspace_size", "css_color_batched",
+            "css_color_batched_workspace_size"} <= set(names)
     lib = ctypes.CDLL(css.LIB_PATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
@@ -66,7 +67,8 @@ def test_struct_layout_matches_header(tmp_path):
     gcc = shutil.which("gcc")
     if gcc is None:
         pytest.skip("no C compiler")
-    structs = {"css_csr": css.CsrStruct, "css_info": css.InfoStruct, "css_system": css.SystemStruct}
+    structs = {"css_csr": css.CsrStruct, "css_info": css.InfoStruct, "css_system": css.SystemStruct,
+               "css_color_job": css.ColorJobStruct}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "css.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -307,6 +307,30 @@ def test_batched_equals_single_bitwise(prec):
     assert len(effs) > 1
 
 
+def test_colour_batched_equals_single_bitwise():
+    """Several geometries coloured in one call (one with a first frontier larger than
+    one workgroup keeps, one forced through the capacity retry) match css_color."""
+    rng = np.random.default_rng(11)
+    g = np.arange(6000)
+    iso = np.stack([g % 20, (g // 20) % 20, g // 400], 1).astype(float) * 3.0 + 100.0
+    chain = np.stack([np.arange(300) * 0.1, np.zeros(300), np.zeros(300)], 1)
+    big = np.concatenate([chain, iso])[rng.permutation(6300)]
+    geoms = [(synth.water_system(64, 20919).orb_xyz, synth.water_system(64, 20919).box, 6.0),
+             (synth.water_system(216, 3).orb_xyz, synth.water_system(216, 3).box, 6.0),
+             (big, np.zeros(3), 6.0)]
+    for xyz, box, rc in geoms:
+        print(f"batched colour n={xyz.shape[0]}", flush=True)
+    css._color_capacity[(6300, "cuda:0")] = 10               # forces the capacity retry for the third job
+    dev = [(torch.as_tensor(x).cuda(), b) for x, b, _ in geoms]
+    res = css.css_color_batched(dev, 6.0, concurrency=3)
+    for (x, b, rc), (color, nc, rp, col, rounds) in zip(geoms, res):
+        rp_o, col_o, deg = conflict_pattern(x, b, rc)
+        color_o, b_o = greedy_color(rp_o, col_o, deg)
+        assert nc == b_o
+        assert np.array_equal(rp.cpu().numpy(), rp_o) and np.array_equal(col.cpu().numpy(), col_o)
+        assert np.array_equal(color.cpu().numpy(), color_o)
+
+
 def test_batched_reports_each_systems_status():
     systems = [_system(64, 20919), _system(27, 5)]
     ws, H, rp, col, color, b, sign, mu = water_case(27, 5)
