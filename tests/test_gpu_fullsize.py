@@ -1,0 +1,100 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times.
+
+10 000 molecules: the oracle runs the whole path (about a minute on the host) and the
+GPU results are compared element by element. 10^6 molecules: the oracle cannot run, so
+the GPU results are checked against identities that hold at any size and the mixed
+path against the FP64 path.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from oracle import density as D  # noqa: E402
+from oracle.coloring import greedy_color  # noqa: E402
+from oracle.pattern import conflict_pattern  # noqa: E402
+from oracle.probes import probe_signs  # noqa: E402
+from paper_2605_20918_amd import css, synth  # noqa: E402
+
+KT, R_CUT, MU = bench.KT, bench.R_CUT, bench.MU_WATER
+
+
+def setup_module(module):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    css.load()
+
+
+def _gpu_step(ws, seed, H, flags, depth=40):
+    xyz = torch.as_tensor(ws.orb_xyz, dtype=torch.float64, device="cuda")
+    color, b, p_rp, p_col, _ = css.css_color(xyz, [float(x) for x in ws.box], R_CUT)
+    sign, _ = css.css_build_probes(color, b, seed)
+    p, e, t, info = css.css_density_matrix(H, color, sign, b, MU, KT, depth, p_rp, p_col, flags)
+    return color, b, p_rp, p_col, sign, p, e, t, info
+
+
+def test_10k_against_the_oracle():
+    wl = bench.WORKLOADS["10k"]
+    ws = synth.water_system(wl["n_mol"], wl["seed"])
+    print("10k: oracle pattern, colouring and density", flush=True)
+    rp, col, deg = conflict_pattern(ws.orb_xyz, ws.box, R_CUT)
+    color, b = greedy_color(rp, col, deg)
+    sign = probe_signs(ws.n, wl["seed"])
+    ref = D.density_matrix(ws.H.to_scipy(), color, sign, b, MU, KT, wl["depth"], rp, col, reorth="full",
+                           cholqr2=True)
+    print(f"10k: oracle done (b={b}, v_eff={ref['v_eff']})", flush=True)
+    H32 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, "cuda", torch.float32)
+    H64 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, "cuda", torch.float64)
+    runs = {"mixed (bench)": (H32, bench.flags_for("fp32")),
+            "fp64 full": (H64, css.PREC_FP64 | css.REORTH_FULL | css.CHOLQR2 | css.SYMMETRIZE),
+            "fp64 local (bench comparator)": (H64, bench.flags_for("fp64"))}
+    errs = {}
+    for name, (H, flags) in runs.items():
+        g_color, g_b, g_rp, g_col, g_sign, p, e, t, info = _gpu_step(ws, wl["seed"], H, flags)
+        assert g_b == b and np.array_equal(g_color.cpu().numpy(), color)
+        assert np.array_equal(g_rp.cpu().numpy(), rp) and np.array_equal(g_col.cpu().numpy(), col)
+        assert np.array_equal(g_sign.cpu().numpy(), sign)
+        assert info["depth_eff"] == ref["v_eff"]
+        dp = float(np.max(np.abs(p.cpu().numpy() - ref["p_val"])))
+        de = abs(e - ref["e_band"]) / abs(ref["e_band"])
+        errs[name] = (dp, de)
+        print(f"10k {name}: max|dP| {dp:.3e}  rel dE {de:.3e}", flush=True)
+    assert errs["mixed (bench)"][0] <= 1e-5 and errs["mixed (bench)"][1] <= 1e-7
+    assert errs["fp64 full"][0] <= 1e-10 and errs["fp64 full"][1] <= 1e-10
+    assert errs["fp64 local (bench comparator)"][0] <= 1e-8 and errs["fp64 local (bench comparator)"][1] <= 1e-10
+
+
+def test_1m_identities_and_mixed_against_fp64():
+    """Tr P = sum_k g f(l_k) w_k and sum H.P = sum_k l_k g f(l_k) w_k hold exactly for the
+    Lanczos relation; P is symmetric; the mixed path agrees with the FP64 two-pass path."""
+    wl = bench.WORKLOADS["1m"]
+    print("1m: generating", flush=True)
+    ws = synth.water_system(wl["n_mol"], wl["seed"])
+    print("1m: mixed path", flush=True)
+    H32 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, "cuda", torch.float32)
+    *_, p32, e32, t32, i32 = _gpu_step(ws, wl["seed"], H32, bench.flags_for("fp32"))
+    p32 = p32.cpu()
+    del H32
+    torch.cuda.empty_cache()
+    print("1m: fp64 two-pass path", flush=True)
+    H64 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, "cuda", torch.float64)
+    *_, p64, e64, t64, i64 = _gpu_step(ws, wl["seed"], H64, bench.flags_for("fp64", True))
+    assert i32["depth_eff"] == i64["depth_eff"] == wl["depth"]
+    for name, e, t, info, tol in (("fp64", e64, t64, i64, 1e-10), ("mixed", e32, t32, i32, 1e-7)):
+        rt = abs(t - info["trace_krylov"]) / abs(t)
+        re = abs(e - info["e_band_krylov"]) / abs(e)
+        print(f"1m {name}: trace identity {rt:.2e}  energy identity {re:.2e}  asym {info['asym_max']:.2e}",
+              flush=True)
+        assert rt <= tol and re <= tol
+    dp = float(torch.max(torch.abs(p64.cpu() - p32)))
+    de = abs(e32 - e64) / abs(e64)
+    print(f"1m mixed vs fp64: max|dP| {dp:.3e}  rel dE {de:.3e}", flush=True)
+    assert dp <= 2e-5 and de <= 1e-7
