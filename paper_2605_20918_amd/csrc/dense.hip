@@ -36,11 +36,14 @@ using MF = Mfma<T>;
 // and the group tiles are added into one LDS tile in group order. WPG = 1: one
 // wave owns the whole (16 TW)^2 tile; WPG = 4: 2 x 2 waves of (16 TW)^2 each.
 // With sym, wave tiles strictly below the diagonal are skipped (the reduction
-// mirrors them). The operands of each step are fetched kGramDepth steps ahead of
+// mirrors them). The operands of each step are fetched gram_depth() steps ahead of
 // their use. RUN: every wave tile lies inside ld, and each lane reads runs of
 // adjacent columns (seg_col order); otherwise one column per lane and tile,
 // masked beyond ld.
-constexpr int kGramDepth = 4;
+// operand steps in flight: 8 for the single-wave FP32 tiles (one wave per SIMD),
+// 4 for the 2 x 2-wave tiles
+template <typename T, int WPG>
+constexpr int gram_depth() { return (WPG == 1 && sizeof(T) == 4) ? 8 : 4; }
 
 template <typename T, int TW, bool RUN>
 __device__ inline void gram_load(const T* __restrict__ p, int lc, const bool (&valid)[TW], T (&x)[TW]) {
@@ -65,7 +68,7 @@ __global__ __launch_bounds__(64 * WPG * KS) void k_gram(const T* __restrict__ X,
                                                         const int* __restrict__ state) {
     if (state && state[0]) return;
     typedef MF<T> M;
-    constexpr int D = kGramDepth;
+    constexpr int D = gram_depth<T, WPG>();
     extern __shared__ char gram_lds[];
     PT* buf = reinterpret_cast<PT*>(gram_lds);            // one TILE^2 tile
     constexpr int TILE = (WPG == 1 ? 16 : 32) * TW;
@@ -78,8 +81,8 @@ __global__ __launch_bounds__(64 * WPG * KS) void k_gram(const T* __restrict__ X,
     const int chunk = blockIdx.x, p = blockIdx.z;
     const int64_t r0 = (int64_t)chunk * rpc;
     const int64_t r1 = r0 + rpc < Np ? r0 + rpc : Np;
-    // r1 - r0 is a multiple of 64, so nst is a multiple of D (4 KS D divides 64)
-    static_assert((64 % (4 * KS * D)) == 0, "chunks must hold whole rounds of D steps");
+    // r1 - r0 is a multiple of 128, so nst is a multiple of D (4 KS D divides 128)
+    static_assert((128 % (4 * KS * D)) == 0, "chunks must hold whole rounds of D steps");
     const int nst = (int)((r1 - r0) / (4 * KS));
     bool vi[TW], vj[TW];
 #pragma unroll
@@ -166,9 +169,17 @@ __global__ __launch_bounds__(64 * kRedGroups) void k_gram_reduce(const PT* __res
     const PT* base = partial + (int64_t)p * nchunk * mat;
     double s1 = 0.0, s2 = 0.0;
     if (valid) {
-        for (int c = g; c < nchunk; c += kRedGroups) s1 += (double)base[c * mat + sij];
-        if (mode != 0)
-            for (int c = g; c < nchunk; c += kRedGroups) s2 += (double)base[c * mat + sji];
+        // chunks g, g+16, ... added in that order; unrolled so the loads are issued together
+        if (mode != 0) {
+#pragma unroll 8
+            for (int c = g; c < nchunk; c += kRedGroups) {
+                s1 += (double)base[c * mat + sij];
+                s2 += (double)base[c * mat + sji];
+            }
+        } else {
+#pragma unroll 8
+            for (int c = g; c < nchunk; c += kRedGroups) s1 += (double)base[c * mat + sij];
+        }
     }
     s1s[g][e] = s1;
     s2s[g][e] = s2;
@@ -861,7 +872,7 @@ GramPlan gram_plan(int64_t Np, int ld, int nprod, bool sym, int64_t cap_mats, in
     nchunk = std::max<int64_t>(nchunk, gram_min_chunks(Np, ld, elem));
     nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, cap_mats / std::max(1, nprod)));
     int64_t rpc = (Np + nchunk - 1) / nchunk;
-    rpc = (rpc + 63) / 64 * 64;                   // whole prefetch rounds per chunk (Np is a multiple of 256)
+    rpc = (rpc + 127) / 128 * 128;                // whole prefetch rounds per chunk (Np is a multiple of 256)
     g.rows_per_chunk = rpc;
     g.nchunk = static_cast<int>((Np + rpc - 1) / rpc);
     return g;
@@ -932,10 +943,14 @@ void update_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstrid
     const int64_t cnt = (int64_t)nprod * ld * ld;
     k_stage_s<T><<<grid_for(cnt, 256), 256, 0, s>>>(S, sstride, nprod, ld, trans ? 1 : 0, scale, st);
     const int nt = ld / 16;
+    // fewer than ~4 row workgroups per CU: split the columns in two blocks for parallelism
+    const bool few = Np / (sizeof(T) == 4 ? 128 : 64) < 1024;
     if (nt <= 2)
         update_one<T, 2>(OUT, IN, alpha, X, xstride, nprod, st, Np, ld, state, s);
     else if (nt <= 4)
         update_one<T, 4>(OUT, IN, alpha, X, xstride, nprod, st, Np, ld, state, s);
+    else if (nt <= 6 && few)
+        update_one<T, 3>(OUT, IN, alpha, X, xstride, nprod, st, Np, ld, state, s);
     else if (nt <= 6)
         update_one<T, 6>(OUT, IN, alpha, X, xstride, nprod, st, Np, ld, state, s);
     else
