@@ -125,7 +125,8 @@ typedef struct {
  *              (then only p_row_ptr and *p_nnz are produced)
  *   p_nnz      host in/out: in = capacity of p_col, out = nnz of the pattern;
  *              CSS_E_CAPACITY if the capacity is too small
- *   rounds     host out (may be NULL): parallel colouring rounds used
+ *   rounds     host out (may be NULL): fixed-point colouring sweeps used (the
+ *              last one found no change)
  */
 css_status css_color(const double* xyz, int32_t n, const double box[3], double r_cut,
                      int32_t* color, int32_t* n_colors,

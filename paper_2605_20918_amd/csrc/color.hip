@@ -4,11 +4,14 @@
 // Welsh and Powell so that any two orbitals closer than the cutoff differ
 // (Fig.1(b)). The sequential algorithm visits orbitals by degree descending
 // (ties: smaller index first) and gives each the smallest colour not used by
-// its already coloured neighbours. That result is reproduced exactly in
-// parallel by Jones-Plassmann rounds with the Welsh-Powell rank as priority:
-// an orbital is coloured as soon as all its higher-priority neighbours are,
-// taking the smallest colour they do not use -- exactly the set the
-// sequential sweep would have seen at that point.
+// its already coloured neighbours. Those are exactly its higher-priority
+// neighbours (Welsh-Powell rank), so the greedy colours are the unique solution
+// of c(v) = mex{ c(u) : u a higher-priority neighbour of v }. It is found here by
+// in-place fixed-point sweeps that re-evaluate only orbitals whose inputs
+// changed; the first sweep without a change certifies the solution. On water
+// the sweeps needed stay near a hundred at any size, while the dependency depth
+// that a round-by-round (Jones-Plassmann) colouring has to walk grows with the
+// system (about a thousand levels at 60 000 orbitals, ten thousand at 6 million).
 //
 // The distance predicate is evaluated with separately rounded products and
 // sums (no fused multiply-add) so that every conflict decision is identical
@@ -188,82 +191,192 @@ __device__ __forceinline__ bool higher_priority(int du, int u, int dv, int v) {
     return du > dv || (du == dv && u < v);
 }
 
-// Dependency counts: cnt[v] = higher-priority neighbours of v; orbitals with none
-// form the first frontier. One wavefront per orbital.
-__global__ __launch_bounds__(256) void k_jp_init(int n, const int64_t* __restrict__ p_row_ptr,
-                                                 const int32_t* __restrict__ p_col, const int* __restrict__ deg,
-                                                 int* __restrict__ cnt, int* __restrict__ color,
-                                                 int* __restrict__ frontier, int* __restrict__ fsize) {
+// Pattern entries of higher-priority neighbours carry this flag in the sign bit of
+// their column index while the colouring runs; k_clear_flags removes it.
+constexpr int32_t kHpFlag = int32_t(0x80000000u);
+
+// Flags every row's higher-priority entries, starts every colour at 0 and makes
+// every orbital due in sweep 0 (stamp 0). One wavefront per orbital.
+__global__ __launch_bounds__(256) void k_fp_init(int n, const int64_t* __restrict__ p_row_ptr,
+                                                 int32_t* __restrict__ p_col, const int* __restrict__ deg,
+                                                 int* __restrict__ color, int* __restrict__ stamp) {
     const int lane = threadIdx.x & 63;
     const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (v >= n) return;
     const int dv = deg[v];
-    int c = 0;
     for (int64_t t = p_row_ptr[v] + lane; t < p_row_ptr[v + 1]; t += 64) {
         const int u = p_col[t];
-        if (u != v && higher_priority(deg[u], u, dv, v)) ++c;
+        if (u != v && higher_priority(deg[u], u, dv, v)) p_col[t] = u | kHpFlag;
     }
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
     if (lane == 0) {
-        cnt[v] = c;
-        color[v] = -1;
-        if (c == 0) frontier[atomicAdd(fsize, 1)] = v;
+        color[v] = 0;
+        stamp[v] = 0;
     }
 }
 
-// One round: every frontier orbital takes the smallest colour its (all coloured)
-// higher-priority neighbours do not use, then releases its lower-priority
-// neighbours; those whose count drops to zero form the next frontier.
-// sizes[r % 3] is this round's frontier size, sizes[(r+1) % 3] the next one,
-// sizes[(r+2) % 3] is cleared for the round after.
-__global__ __launch_bounds__(256) void k_jp_round(const int64_t* __restrict__ p_row_ptr,
+__global__ void k_clear_flags(int32_t* __restrict__ p_col, int64_t nnz) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < nnz) p_col[t] &= ~kHpFlag;
+}
+
+// One sweep k of the fixed-point iteration c(v) = mex{ c(u) : u a higher-priority
+// neighbour of v }. Its solution is unique (the priority relation is acyclic,
+// so it is fixed level by level) and it is the sequential greedy colouring:
+// there, v receives the smallest colour absent from its already coloured
+// neighbours, which are exactly its higher-priority ones. Only orbitals with
+// stamp k are evaluated; one whose colour changes stamps its lower-priority
+// neighbours k + 1 (plain stores: every writer writes the same value, and a
+// stamp only grows). Updates are in place; an orbital read before a neighbour's
+// change in the same sweep is stamped and evaluated again in the next one, so
+// the first sweep in which nothing changes leaves every orbital satisfying its
+// equation: the iteration has converged to the greedy colouring.
+// A wavefront owns kFpChunk consecutive orbitals (one load per lane brings their
+// stamps, colours, degrees and row bounds) and evaluates the due ones one after
+// the other in priority order, so that an orbital can already see the new colour
+// of a higher-priority neighbour of the same chunk (consecutive orbitals are
+// mostly on one molecule). A row is read kFpLoads entries per lane at a time; the
+// first batch of every due orbital's row is requested before the first is used.
+constexpr int kFpChunk = 8;
+constexpr int kFpLoads = 4;
+constexpr int kFpSpan = 64 * kFpLoads;               // row entries per batch
+
+__device__ __forceinline__ void mex_mark(int cu, int base, unsigned long long (&m)[4]) {
+    const int cc = cu - base;
+    const bool in = cu >= 0 && cc >= 0 && cc < 256;
+    const unsigned long long bit = in ? 1ull << (cc & 63) : 0ull;
+    const int word = cc >> 6;
+    m[0] |= word == 0 ? bit : 0ull;
+    m[1] |= word == 1 ? bit : 0ull;
+    m[2] |= word == 2 ? bit : 0ull;
+    m[3] |= word == 3 ? bit : 0ull;
+}
+
+// Smallest colour >= base absent from the wave's masks (-1 if all 256 are present).
+__device__ __forceinline__ int mex_of(unsigned long long (&m)[4], int base) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int wd = 0; wd < 4; ++wd) m[wd] |= __shfl_xor(m[wd], off);
+    if (~m[0]) return base + __builtin_ctzll(~m[0]);
+    if (~m[1]) return base + 64 + __builtin_ctzll(~m[1]);
+    if (~m[2]) return base + 128 + __builtin_ctzll(~m[2]);
+    if (~m[3]) return base + 192 + __builtin_ctzll(~m[3]);
+    return -1;
+}
+
+// Stamps the lower-priority neighbours among a batch of row entries (entry q of
+// this lane at index t + 64 q) with `next`. Most are stamped already by another
+// changed neighbour: the stamp is read first and written only if it differs (a
+// stale read costs a redundant store, never a missed one, since only this sweep
+// writes `next`).
+__device__ __forceinline__ void mark_lower(const int (&u)[kFpLoads], int v, int64_t t, int64_t e, int next,
+                                           int* stamp) {
+    int old[kFpLoads];
+#pragma unroll
+    for (int q = 0; q < kFpLoads; ++q) {
+        const bool lp = u[q] >= 0 && u[q] != v && t + 64 * q < e;
+        old[q] = lp ? stamp[u[q]] : next;
+    }
+#pragma unroll
+    for (int q = 0; q < kFpLoads; ++q)
+        if (old[q] != next) stamp[u[q]] = next;
+}
+
+__global__ __launch_bounds__(256) void k_fp_sweep(int n, const int64_t* __restrict__ p_row_ptr,
                                                   const int32_t* __restrict__ p_col, const int* __restrict__ deg,
-                                                  int* __restrict__ cnt, int* color, const int* __restrict__ fin,
-                                                  int* __restrict__ fout, int* sizes, int r, int* __restrict__ done,
-                                                  int* __restrict__ nonempty) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int size_in = sizes[r % 3];
-    if (blockIdx.x == 0 && threadIdx.x == 0) sizes[(r + 2) % 3] = 0;
-    if (size_in == 0) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(nonempty, 1);
-    int* size_out = sizes + (r + 1) % 3;
-    const int nwaves = gridDim.x * 4;
-    for (int i = blockIdx.x * 4 + w; i < size_in; i += nwaves) {
-        const int v = fin[i];
-        const int dv = deg[v];
-        const int64_t s = p_row_ptr[v], e = p_row_ptr[v + 1];
-        int chosen = -1;
-        for (int base = 0; chosen < 0; base += 256) {
-            unsigned long long m0 = 0, m1 = 0, m2 = 0, m3 = 0;
-            for (int64_t t = s + lane; t < e; t += 64) {
-                const int u = p_col[t];
-                if (u == v || !higher_priority(deg[u], u, dv, v)) continue;
-                const int cu = color[u] - base;
-                if (cu >= 0 && cu < 256) {
-                    const unsigned long long bit = 1ull << (cu & 63);
-                    if (cu < 64) m0 |= bit; else if (cu < 128) m1 |= bit; else if (cu < 192) m2 |= bit; else m3 |= bit;
+                                                  int* color, int* stamp, int k, int* __restrict__ changed) {
+    // changed: set to 1 if this sweep changed a colour (cleared by the host before)
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    int nchanged = 0;
+    for (int64_t v0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kFpChunk; v0 < n; v0 += nwaves * kFpChunk) {
+        const int64_t vl = min<int64_t>(v0 + lane % kFpChunk, n - 1);
+        const int st = stamp[vl], cl = color[vl], dl = deg[vl];
+        __builtin_amdgcn_sched_barrier(0);
+        const bool due = lane < kFpChunk && v0 + lane < n && st == k;
+        const unsigned long long dm = __ballot(due);
+        if (!dm) continue;
+        const int64_t rs = p_row_ptr[vl], re = p_row_ptr[vl + 1];
+        // rank among the due orbitals of the chunk: the number of higher-priority ones
+        int rank = 0;
+#pragma unroll
+        for (int j = 0; j < kFpChunk; ++j) {
+            const int dj = __shfl(dl, j);
+            rank += ((dm >> j) & 1) && (dj > dl || (dj == dl && j < lane));
+        }
+        const int ndue = __popcll(dm);
+        // first batch of every due orbital's row, in evaluation order, all in flight at once
+        int src[kFpChunk];
+        int u[kFpChunk][kFpLoads];
+#pragma unroll
+        for (int r = 0; r < kFpChunk; ++r) {
+            const unsigned long long b = __ballot(due && rank == r);
+            src[r] = b ? __builtin_ctzll(b) : 0;
+            const int64_t sr = __shfl(rs, src[r]), er = __shfl(re, src[r]);
+#pragma unroll
+            for (int q = 0; q < kFpLoads; ++q) u[r][q] = p_col[min(sr + lane + 64 * q, er - 1)];
+        }
+        for (int r = 0; r < ndue; ++r) {
+            const int v = static_cast<int>(v0) + src[0];
+            const int cur = __shfl(cl, src[0]);
+            const int64_t s = __shfl(rs, src[0]), e = __shfl(re, src[0]);
+            int cu[kFpLoads];
+#pragma unroll
+            for (int q = 0; q < kFpLoads; ++q) {
+                const bool hp = u[0][q] < 0 && s + lane + 64 * q < e;
+                cu[q] = hp ? color[u[0][q] & ~kHpFlag] : -1;
+            }
+            unsigned long long m[4] = {0ull, 0ull, 0ull, 0ull};
+#pragma unroll
+            for (int q = 0; q < kFpLoads; ++q) mex_mark(cu[q], 0, m);
+            // the rest of a long row
+            for (int64_t tb = s + lane + kFpSpan; __ballot(tb < e); tb += kFpSpan) {
+                int w[kFpLoads], cw[kFpLoads];
+#pragma unroll
+                for (int q = 0; q < kFpLoads; ++q) w[q] = p_col[min(tb + 64 * q, e - 1)];
+#pragma unroll
+                for (int q = 0; q < kFpLoads; ++q) cw[q] = (w[q] < 0 && tb + 64 * q < e) ? color[w[q] & ~kHpFlag] : -1;
+#pragma unroll
+                for (int q = 0; q < kFpLoads; ++q) mex_mark(cw[q], 0, m);
+            }
+            int chosen = mex_of(m, 0);
+            // colours beyond 255: further windows over the whole row
+            for (int base = 256; chosen < 0; base += 256) {
+                unsigned long long mb[4] = {0ull, 0ull, 0ull, 0ull};
+                for (int64_t tb = s + lane; __ballot(tb < e); tb += kFpSpan) {
+                    int w[kFpLoads], cw[kFpLoads];
+#pragma unroll
+                    for (int q = 0; q < kFpLoads; ++q) w[q] = p_col[min(tb + 64 * q, e - 1)];
+#pragma unroll
+                    for (int q = 0; q < kFpLoads; ++q) cw[q] = (w[q] < 0 && tb + 64 * q < e) ? color[w[q] & ~kHpFlag] : -1;
+#pragma unroll
+                    for (int q = 0; q < kFpLoads; ++q) mex_mark(cw[q], base, mb);
+                }
+                chosen = mex_of(mb, base);
+            }
+            if (chosen != cur) {
+                if (lane == 0) color[v] = chosen;
+                ++nchanged;
+                mark_lower(u[0], v, s + lane, e, k + 1, stamp);
+                for (int64_t tb = s + lane + kFpSpan; __ballot(tb < e); tb += kFpSpan) {
+                    int w[kFpLoads];
+#pragma unroll
+                    for (int q = 0; q < kFpLoads; ++q) w[q] = p_col[min(tb + 64 * q, e - 1)];
+                    mark_lower(w, v, tb, e, k + 1, stamp);
                 }
             }
-            for (int off = 32; off > 0; off >>= 1) {
-                m0 |= __shfl_xor(m0, off);
-                m1 |= __shfl_xor(m1, off);
-                m2 |= __shfl_xor(m2, off);
-                m3 |= __shfl_xor(m3, off);
+            // next orbital's row to the front
+#pragma unroll
+            for (int i = 0; i + 1 < kFpChunk; ++i) {
+                src[i] = src[i + 1];
+#pragma unroll
+                for (int q = 0; q < kFpLoads; ++q) u[i][q] = u[i + 1][q];
             }
-            if (~m0) chosen = base + __builtin_ctzll(~m0);
-            else if (~m1) chosen = base + 64 + __builtin_ctzll(~m1);
-            else if (~m2) chosen = base + 128 + __builtin_ctzll(~m2);
-            else if (~m3) chosen = base + 192 + __builtin_ctzll(~m3);
         }
-        if (lane == 0) color[v] = chosen;
-        __threadfence();
-        for (int64_t t = s + lane; t < e; t += 64) {
-            const int u = p_col[t];
-            if (u == v || higher_priority(deg[u], u, dv, v)) continue;
-            if (atomicSub(&cnt[u], 1) == 1) fout[atomicAdd(size_out, 1)] = u;
-        }
-        if (lane == 0) atomicAdd(done, 1);
     }
+    // a plain store of the same value by every wave that changed something: device-wide
+    // atomics on one address would serialise thousands of waves
+    if (lane == 0 && nchanged > 0) *changed = 1;
 }
 
 __global__ void k_fill_int(int* __restrict__ p, int64_t cnt, int v) {
@@ -368,7 +481,7 @@ Grid make_grid(int n, const double box[3], double r_cut, const double bb[6]) {
 }
 
 struct ColorWs {
-    int *cell_of, *cell_count, *cell_start, *cell_fill, *cell_list, *deg, *scalars, *jp_cnt;
+    int *cell_of, *cell_count, *cell_start, *cell_fill, *cell_list, *deg, *scalars, *stamp;
     int64_t* block_sum;
     double* bbox;
 };
@@ -382,7 +495,7 @@ ColorWs carve_color(Arena& a, int n) {
     w.cell_fill = a.take<int>(ncell);
     w.cell_list = a.take<int>(n);
     w.deg = a.take<int>(n);
-    w.jp_cnt = a.take<int>(n);
+    w.stamp = a.take<int>(n);
     w.scalars = a.take<int>(64);
     w.block_sum = a.take<int64_t>((n + kScanBlock - 1) / kScanBlock + 1);
     w.bbox = a.take<double>(8);
@@ -478,25 +591,25 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
                                                          w.cell_list, w.deg, p_row_ptr, p_col);
     k_sort_rows<<<n, 256, 0, s>>>(n, p_row_ptr, p_col);
 
-    // Jones-Plassmann rounds with Welsh-Powell priorities, frontier by frontier
-    int* sizes = w.scalars + 8;      // three rotating frontier sizes
-    int* n_done = w.scalars + 12;
-    CSS_HIP_TRY(hipMemsetAsync(w.scalars + 8, 0, 8 * sizeof(int), s));
-    int* fr[2] = {w.cell_fill, w.cell_list};     // cell arrays are free once the pattern exists
-    k_jp_init<<<grid_for(n, 4), 256, 0, s>>>(n, p_row_ptr, p_col, w.deg, w.jp_cnt, color, fr[0], sizes);
-    int done = 0, nround = 0;
-    const int batch = 32;
-    const unsigned rgrid = static_cast<unsigned>(std::min<int64_t>(1024, std::max<int64_t>(1, (n + 3) / 4)));
-    while (done < n) {
-        for (int r = 0; r < batch; ++r, ++nround)
-            k_jp_round<<<rgrid, 256, 0, s>>>(p_row_ptr, p_col, w.deg, w.jp_cnt, color, fr[nround & 1],
-                                             fr[(nround + 1) & 1], sizes, nround % 3, n_done, n_done + 1);
-        CSS_HIP_TRY(hipMemcpyAsync(&done, n_done, sizeof(int), hipMemcpyDeviceToHost, s));
+    // fixed-point sweeps, kFpBatch per host check of the change counters
+    constexpr int kFpBatch = 16;
+    int* stamp = w.stamp;
+    int* changed = w.scalars + 16;                // kFpBatch change counters
+    k_fp_init<<<grid_for(n, 4), 256, 0, s>>>(n, p_row_ptr, p_col, w.deg, color, stamp);
+    const unsigned sgrid = static_cast<unsigned>(std::min<int64_t>(16384, (n + 4 * kFpChunk - 1) / (4 * kFpChunk)));
+    int sweeps = 0;
+    for (int k0 = 0; sweeps == 0; k0 += kFpBatch) {
+        if (k0 > n + kFpBatch) return CSS_E_DEVICE;       // cannot happen: sweep k fixes priority level k
+        CSS_HIP_TRY(hipMemsetAsync(changed, 0, kFpBatch * sizeof(int), s));
+        for (int r = 0; r < kFpBatch; ++r)
+            k_fp_sweep<<<sgrid, 256, 0, s>>>(n, p_row_ptr, p_col, w.deg, color, stamp, k0 + r, changed + r);
+        int hch[kFpBatch];
+        CSS_HIP_TRY(hipMemcpyAsync(hch, changed, sizeof(hch), hipMemcpyDeviceToHost, s));
         CSS_HIP_TRY(hipStreamSynchronize(s));
-        if (nround > n + batch) return CSS_E_DEVICE;     // cannot happen: every round colours >= 1
+        for (int r = 0; r < kFpBatch && sweeps == 0; ++r)
+            if (hch[r] == 0) sweeps = k0 + r + 1;
     }
-    int real_rounds = 0;
-    CSS_HIP_TRY(hipMemcpyAsync(&real_rounds, n_done + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    k_clear_flags<<<grid_for(nnz, 256), 256, 0, s>>>(p_col, nnz);
     CSS_HIP_TRY(hipMemsetAsync(w.scalars, 0xff, sizeof(int), s));
     CSS_HIP_TRY(hipMemsetAsync(w.scalars + 1, 0, sizeof(int), s));
     k_max_color<<<64, 256, 0, s>>>(color, n, w.scalars, w.scalars + 1, p_row_ptr);
@@ -504,6 +617,6 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
     CSS_HIP_TRY(hipMemcpyAsync(&hc, w.scalars, sizeof(int), hipMemcpyDeviceToHost, s));
     CSS_HIP_TRY(hipStreamSynchronize(s));
     *n_colors = hc + 1;
-    if (rounds) *rounds = real_rounds;
+    if (rounds) *rounds = sweeps;
     return CSS_OK;
 }
