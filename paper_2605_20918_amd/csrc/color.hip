@@ -70,15 +70,19 @@ __device__ __forceinline__ bool conflict(const double* __restrict__ xyz, int64_t
     return d2 <= rc2;
 }
 
-__global__ void k_bbox(const double* __restrict__ xyz, int n, double* __restrict__ out) {
-    // one block: min and max per coordinate
+// Bounding box in two levels: every work-group's min and max per coordinate to
+// part[6 blockIdx.x ..], then one work-group over the parts (min and max are
+// order independent).
+constexpr int kBboxBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_bbox(const double* __restrict__ xyz, int64_t n, int stride,
+                                              double* __restrict__ out) {
     __shared__ double smin[3][256], smax[3][256];
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         for (int k = 0; k < 3; ++k) {
-            double v = xyz[3 * (int64_t)i + k];
-            mn[k] = fmin(mn[k], v);
-            mx[k] = fmax(mx[k], v);
+            mn[k] = fmin(mn[k], xyz[stride * i + k]);
+            mx[k] = fmax(mx[k], xyz[stride * i + (stride == 3 ? k : 3 + k)]);
         }
     for (int k = 0; k < 3; ++k) { smin[k][threadIdx.x] = mn[k]; smax[k][threadIdx.x] = mx[k]; }
     __syncthreads();
@@ -91,7 +95,7 @@ __global__ void k_bbox(const double* __restrict__ xyz, int n, double* __restrict
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int k = 0; k < 3; ++k) { out[k] = smin[k][0]; out[3 + k] = smax[k][0]; }
+        for (int k = 0; k < 3; ++k) { out[6 * blockIdx.x + k] = smin[k][0]; out[6 * blockIdx.x + 3 + k] = smax[k][0]; }
 }
 
 __global__ void k_finite_check(const double* __restrict__ xyz, int64_t cnt, int* __restrict__ bad) {
@@ -137,13 +141,17 @@ __device__ __forceinline__ int stencil(int nc, bool periodic, int c, int o[3]) {
 
 // COUNT = true: deg[m] = number of conflicting partners (self excluded).
 // COUNT = false: write the row (self included) at p_col[p_row_ptr[m] ...] unsorted.
+// Threads take orbitals in cell order (cell_list), so that the threads of a
+// wavefront mostly scan the same cells: uniform loop bounds, and each candidate's
+// coordinates are one load shared by the wavefront.
 template <bool COUNT>
 __global__ void k_neighbours(const double* __restrict__ xyz, int n, Grid g, double rc2,
                              const int* __restrict__ cell_of, const int* __restrict__ cell_start,
                              const int* __restrict__ cell_list, int* __restrict__ deg,
                              const int64_t* __restrict__ p_row_ptr, int32_t* __restrict__ p_col) {
-    int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int m = cell_list[i];
     int c = cell_of[m];
     int cz = c % g.nc[2];
     int cy = (c / g.nc[2]) % g.nc[1];
@@ -483,7 +491,7 @@ Grid make_grid(int n, const double box[3], double r_cut, const double bb[6]) {
 struct ColorWs {
     int *cell_of, *cell_count, *cell_start, *cell_fill, *cell_list, *deg, *scalars, *stamp;
     int64_t* block_sum;
-    double* bbox;
+    double *bbox, *bbox_part;
 };
 
 ColorWs carve_color(Arena& a, int n) {
@@ -499,6 +507,7 @@ ColorWs carve_color(Arena& a, int n) {
     w.scalars = a.take<int>(64);
     w.block_sum = a.take<int64_t>((n + kScanBlock - 1) / kScanBlock + 1);
     w.bbox = a.take<double>(8);
+    w.bbox_part = a.take<double>(6 * kBboxBlocks);
     return w;
 }
 
@@ -536,7 +545,12 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
     // finite coordinates and bounding box (open directions)
     CSS_HIP_TRY(hipMemsetAsync(w.scalars, 0, 64 * sizeof(int), s));
     k_finite_check<<<grid_for(3LL * n, 256), 256, 0, s>>>(xyz, 3LL * n, w.scalars);
-    k_bbox<<<1, 256, 0, s>>>(xyz, n, w.bbox);
+    {
+        // per-block boxes of the n centres (stride 3), then the box of those boxes (stride 6)
+        const unsigned nb = std::min<unsigned>(kBboxBlocks, grid_for(n, 256));
+        k_bbox<<<nb, 256, 0, s>>>(xyz, n, 3, w.bbox_part);
+        k_bbox<<<1, 256, 0, s>>>(w.bbox_part, nb, 6, w.bbox);
+    }
     double hb[8];
     int hbad = 0;
     CSS_HIP_TRY(hipMemcpyAsync(hb, w.bbox, 6 * sizeof(double), hipMemcpyDeviceToHost, s));

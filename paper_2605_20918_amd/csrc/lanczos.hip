@@ -28,25 +28,38 @@
 #include "css_common.h"
 #include "dense.h"
 #include "driver.h"
+#include "hist.h"
 #include "spmm.h"
 
 namespace css {
 namespace {
 
+// ||H||_inf in two levels: one wavefront per row (sum of |H_mn|), each
+// work-group's maximum to part[blockIdx.x]; k_max_reduce then takes the maximum
+// of the parts (order independent, hence deterministic).
+constexpr int kRowMaxBlocks = 1024;
+
 template <typename V>
-__global__ void k_row_abs_sum(int n, const int32_t* __restrict__ rp, const V* __restrict__ val,
-                              double* __restrict__ out_rows, int* __restrict__ state) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
+__global__ __launch_bounds__(256) void k_row_abs_max(int n, const int32_t* __restrict__ rp, const V* __restrict__ val,
+                                                     double* __restrict__ part, int* __restrict__ state) {
+    __shared__ double wm[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double mx = 0.0;
     bool finite = true;
-    for (int32_t t = rp[i]; t < rp[i + 1]; ++t) {
-        const double v = (double)val[t];
-        finite = finite && isfinite(v);
-        s += fabs(v);
+    for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < n; i += (int64_t)gridDim.x * 4) {
+        double s = 0.0;
+        for (int32_t t = rp[i] + lane; t < rp[i + 1]; t += 64) {
+            const double v = (double)val[t];
+            finite = finite && isfinite(v);
+            s += fabs(v);
+        }
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        mx = fmax(mx, s);
     }
     if (!finite) atomicOr(&state[1], 2);
-    out_rows[i] = s;
+    if (lane == 0) wm[w] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]));
 }
 
 // max over an array (deterministic: max is order independent)
@@ -67,17 +80,6 @@ template <typename S, typename D>
 __global__ void k_convert(const S* __restrict__ in, D* __restrict__ out, int64_t n) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) out[i] = D(in[i]);
-}
-
-__global__ void k_counts(const int32_t* __restrict__ color, int n, int b, int* __restrict__ counts,
-                         int* __restrict__ state) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int c = color[i];
-    if (c < 0 || c >= b)
-        atomicOr(&state[1], 4);
-    else
-        atomicAdd(&counts[c], 1);
 }
 
 __global__ void k_check_counts(const int* __restrict__ counts, int b, int* __restrict__ state) {
@@ -229,17 +231,18 @@ css_status prepare(const css_csr* H, const int32_t* color, const int8_t* sign, c
     CSS_HIP_TRY(hipStreamSynchronize(s));
     if (hst[1]) return CSS_E_CSR;
     if (p.grp_ok) spmm_grp_prepare(p.n, H->row_ptr, H->col, bf.grp, bf.state + 4, s);
-    double* rows = static_cast<double*>(bf.W);     // W is free scratch until the first SpMM
+    double* part = static_cast<double*>(bf.W);     // W (>= 256 x 16 elements) is free until the first SpMM
+    const unsigned rgrid = std::min<unsigned>(kRowMaxBlocks, grid_for(p.n, 4));
     if (H->val_dtype == CSS_F64)
-        k_row_abs_sum<double><<<grid_for(p.n, 256), 256, 0, s>>>(p.n, H->row_ptr,
-                                                                  static_cast<const double*>(H->val), rows, bf.state);
+        k_row_abs_max<double><<<rgrid, 256, 0, s>>>(p.n, H->row_ptr, static_cast<const double*>(H->val), part,
+                                                     bf.state);
     else
-        k_row_abs_sum<float><<<grid_for(p.n, 256), 256, 0, s>>>(p.n, H->row_ptr, static_cast<const float*>(H->val),
-                                                                rows, bf.state);
-    k_max_reduce<<<1, 256, 0, s>>>(rows, p.n, bf.scal);
+        k_row_abs_max<float><<<rgrid, 256, 0, s>>>(p.n, H->row_ptr, static_cast<const float*>(H->val), part,
+                                                    bf.state);
+    k_max_reduce<<<1, 256, 0, s>>>(part, rgrid, bf.scal);
     k_tau<<<1, 1, 0, s>>>(bf.scal);
     k_zero<int><<<grid_for(p.b, 256), 256, 0, s>>>(bf.counts, p.b);
-    k_counts<<<grid_for(p.n, 256), 256, 0, s>>>(color, p.n, p.b, bf.counts, bf.state);
+    colour_hist(color, p.n, p.b, bf.counts, bf.state + 1, 4, s);
     k_check_counts<<<grid_for(p.b, 256), 256, 0, s>>>(bf.counts, p.b, bf.state);
     CSS_HIP_TRY(hipMemcpyAsync(hst, bf.state, sizeof(hst), hipMemcpyDeviceToHost, s));
     CSS_HIP_TRY(hipStreamSynchronize(s));

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "css_common.h"
+#include "hist.h"
 
 namespace css {
 namespace {
@@ -21,13 +22,10 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t m) {
     return z ^ (z >> 31);
 }
 
-__global__ void k_probes(const int32_t* __restrict__ color, int n, int b, uint64_t seed, int ones,
-                         int8_t* __restrict__ sign, int32_t* __restrict__ count) {
+__global__ void k_probes(int n, uint64_t seed, int ones, int8_t* __restrict__ sign) {
     int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n) return;
-    int c = color[m];
     sign[m] = ones ? int8_t(1) : ((splitmix64_at(seed, (uint64_t)m) >> 63) ? int8_t(-1) : int8_t(1));
-    if (c >= 0 && c < b) atomicAdd(&count[c], 1);     // out-of-range colours show up in the sum
 }
 
 __global__ void k_zero_i32(int32_t* __restrict__ p, int cnt) {
@@ -45,8 +43,8 @@ extern "C" css_status css_build_probes(const int32_t* color, int32_t n, int32_t 
     if (n < 1 || n_colors < 1 || n_colors > n || !color || !sign || !color_count) return CSS_E_ARG;
     hipStream_t s = as_stream(stream);
     k_zero_i32<<<grid_for(n_colors, 256), 256, 0, s>>>(color_count, n_colors);
-    k_probes<<<grid_for(n, 256), 256, 0, s>>>(color, n, n_colors, seed, (flags & CSS_SIGNS_ONES) ? 1 : 0,
-                                              sign, color_count);
+    k_probes<<<grid_for(n, 256), 256, 0, s>>>(n, seed, (flags & CSS_SIGNS_ONES) ? 1 : 0, sign);
+    colour_hist(color, n, n_colors, color_count, nullptr, 0, s);     // out-of-range colours show in the sum
     std::vector<int32_t> h(n_colors);
     CSS_HIP_TRY(hipMemcpyAsync(h.data(), color_count, sizeof(int32_t) * n_colors, hipMemcpyDeviceToHost, s));
     CSS_HIP_TRY(hipStreamSynchronize(s));

@@ -47,15 +47,16 @@ int spmm_groups(int n);
 int64_t spmm_grp_block_cap(int n, int64_t nnz);
 // Takes the group arrays from an arena (elem = bytes per H value).
 void carve_groups(Arena& a, int n, int64_t nnz, size_t elem, SpmmGroups& g);
-// Builds the unions of a validated CSR (reads row_ptr and col only). Device ints:
-// stats[0] |= 1 if a group has more than kSpmmGroupCap nonzeros (its union is left
-// empty and the grouped kernel must not be used); stats[1] += sum of |U_g|.
+// Builds the unions and block offsets of a validated CSR (reads row_ptr and col
+// only). Device ints: stats[0] |= 1 if a group has more than kSpmmGroupCap nonzeros
+// (its union is left empty and the grouped kernel must not be used); stats[1] = sum
+// of |U_g| (capped at INT_MAX).
 void spmm_grp_prepare(int n, const int32_t* row_ptr, const int32_t* col, const SpmmGroups& gp, int* stats,
                       hipStream_t s);
 // Host decision from the two stats: no oversized group and blocks within kGroupFill nnz.
 bool spmm_grp_worthwhile(int64_t nnz, int too_long, int64_t sum_union);
-// Block offsets and the dense blocks from H's values (after spmm_grp_prepare, and
-// only when spmm_grp_worthwhile holds, so that the blocks fit in cap).
+// The dense blocks from H's values (after spmm_grp_prepare, and only when
+// spmm_grp_worthwhile holds, so that the blocks fit in cap).
 template <typename T>
 void spmm_grp_fill(int n, const int32_t* row_ptr, const T* val, const SpmmGroups& gp, hipStream_t s);
 // false if ld is not a multiple of 16 up to 128, or V / W are not 16-byte aligned.

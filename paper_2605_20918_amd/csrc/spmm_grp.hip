@@ -33,14 +33,38 @@ using GMF = Mfma<T>;
 
 // Per group: U_g (sorted unique columns) at U[rp[16g] ..], |U_g| in ucount[g], and for
 // every CSR entry t of the group pos[t] = (row - 16g) << 16 | (position of col[t] in U_g).
-// stats[0] |= 1 if a group holds more than kSpmmGroupCap entries; stats[1] += |U_g|.
-__global__ __launch_bounds__(256) void k_grp_union(int n, const int32_t* __restrict__ rp,
+// stats[0] |= 1 if a group holds more than kSpmmGroupCap entries.
+// The group's entries are sorted in LDS: with sorted rows by four levels of pairwise
+// merges of the 16 rows (an entry's place in the merged run is its place in its own
+// run plus the number of entries of the partner run before it, ties to the left
+// run), otherwise by a bitonic sort.
+__device__ __forceinline__ int lower_in(const int32_t* a, int lo, int hi, int x) {   // first a[i] >= x
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+__device__ __forceinline__ int upper_in(const int32_t* a, int lo, int hi, int x) {   // first a[i] > x
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+constexpr int kUnionThreads = 1024;
+
+__global__ __launch_bounds__(kUnionThreads) void k_grp_union(int n, const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ col, int32_t* __restrict__ U,
                                                    int32_t* __restrict__ ucount, int32_t* __restrict__ pos,
                                                    int* __restrict__ stats) {
-    __shared__ int32_t s[kSpmmGroupCap];
-    __shared__ int32_t uq[kSpmmGroupCap];
-    __shared__ int32_t scan[256];
+    __shared__ int32_t buf0[kSpmmGroupCap];
+    __shared__ int32_t buf1[kSpmmGroupCap];
+    __shared__ uint8_t rowof[kSpmmGroupCap];
+    __shared__ int32_t scan[kUnionThreads];
+    __shared__ int32_t grp[kSpmmGroup + 1];       // group-relative row starts
+    __shared__ int unsorted;
     const int g = blockIdx.x;
     const int r0 = g * kSpmmGroup;
     const int r1 = min(n, r0 + kSpmmGroup);
@@ -53,31 +77,64 @@ __global__ __launch_bounds__(256) void k_grp_union(int n, const int32_t* __restr
         }
         return;
     }
-    int len = 1;
-    while (len < cnt) len <<= 1;
-    for (int i = threadIdx.x; i < len; i += 256) s[i] = (i < cnt) ? col[t0 + i] : 0x7fffffff;
+    if (threadIdx.x <= kSpmmGroup) grp[threadIdx.x] = rp[min(r0 + (int)threadIdx.x, r1)] - t0;
+    if (threadIdx.x == 0) unsorted = 0;
+    for (int i = threadIdx.x; i < cnt; i += kUnionThreads) buf0[i] = col[t0 + i];
     __syncthreads();
-    // bitonic sort
-    for (int k = 2; k <= len; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < len; i += 256) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const int a = s[i], b = s[ixj];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) { s[i] = b; s[ixj] = a; }
-                }
+    for (int i = threadIdx.x; i < cnt; i += kUnionThreads) {
+        int r = 0;
+        while (grp[r + 1] <= i) ++r;
+        rowof[i] = static_cast<uint8_t>(r);
+        if (i > grp[r] && buf0[i - 1] > buf0[i]) unsorted = 1;
+    }
+    __syncthreads();
+    int32_t* srt = buf0;
+    int32_t* tmp = buf1;
+    if (!unsorted) {
+        for (int lev = 0; lev < 4; ++lev) {
+            for (int i = threadIdx.x; i < cnt; i += kUnionThreads) {
+                const int run = rowof[i] >> lev;
+                const int left = run & ~1;
+                const int ls = grp[min(kSpmmGroup, left << lev)];          // left run [ls, ms)
+                const int ms = grp[min(kSpmmGroup, (left + 1) << lev)];    // right run [ms, re)
+                const int re = grp[min(kSpmmGroup, (left + 2) << lev)];
+                const int x = srt[i];
+                const int at = (run & 1) ? (i - ms) + upper_in(srt, ls, ms, x) - ls
+                                         : (i - ls) + lower_in(srt, ms, re, x) - ms;
+                tmp[ls + at] = x;
             }
             __syncthreads();
+            int32_t* t = srt;
+            srt = tmp;
+            tmp = t;
         }
+    } else {
+        int len = 1;
+        while (len < cnt) len <<= 1;
+        for (int i = cnt + threadIdx.x; i < len; i += kUnionThreads) srt[i] = 0x7fffffff;
+        __syncthreads();
+        for (int k = 2; k <= len; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < len; i += kUnionThreads) {
+                    const int ixj = i ^ j;
+                    if (ixj > i) {
+                        const int a = srt[i], b = srt[ixj];
+                        const bool up = (i & k) == 0;
+                        if ((a > b) == up) { srt[i] = b; srt[ixj] = a; }
+                    }
+                }
+                __syncthreads();
+            }
+    }
     // unique: each thread handles a contiguous span, block scan of the span counts
-    const int per = (cnt + 255) / 256;
+    int32_t* uq = tmp;
+    const int per = (cnt + kUnionThreads - 1) / kUnionThreads;
     const int a0 = min(cnt, (int)threadIdx.x * per), a1 = min(cnt, a0 + per);
     int mine = 0;
-    for (int i = a0; i < a1; ++i) mine += (i == 0 || s[i] != s[i - 1]);
+    for (int i = a0; i < a1; ++i) mine += (i == 0 || srt[i] != srt[i - 1]);
     scan[threadIdx.x] = mine;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
+    for (int off = 1; off < kUnionThreads; off <<= 1) {
         const int v = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
         __syncthreads();
         scan[threadIdx.x] += v;
@@ -85,41 +142,37 @@ __global__ __launch_bounds__(256) void k_grp_union(int n, const int32_t* __restr
     }
     int w = scan[threadIdx.x] - mine;
     for (int i = a0; i < a1; ++i)
-        if (i == 0 || s[i] != s[i - 1]) {
-            U[t0 + w] = s[i];
-            uq[w] = s[i];
+        if (i == 0 || srt[i] != srt[i - 1]) {
+            U[t0 + w] = srt[i];
+            uq[w] = srt[i];
             ++w;
         }
-    const int nu = scan[255];
-    if (threadIdx.x == 0) {
-        ucount[g] = nu;
-        atomicAdd(&stats[1], nu);
-    }
+    const int nu = scan[kUnionThreads - 1];
+    if (threadIdx.x == 0) ucount[g] = nu;
     __syncthreads();
-    // positions by binary search in U_g; the row by a scan of the group's 17 row pointers
-    for (int t = t0 + threadIdx.x; t < t1; t += 256) {
-        const int c = col[t];
-        int lo = 0, hi = nu;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (uq[mid] < c) lo = mid + 1; else hi = mid;
-        }
-        int r = r0;
-        while (rp[r + 1] <= t) ++r;
-        pos[t] = ((r - r0) << 16) | lo;
-    }
+    // positions by binary search in U_g
+    for (int t = t0 + threadIdx.x; t < t1; t += kUnionThreads)
+        pos[t] = (static_cast<int>(rowof[t - t0]) << 16) | lower_in(uq, 0, nu, col[t]);
 }
 
 // Offsets of the groups' blocks (in elements): boff[g] = 16 * sum_{h<g} round4(|U_h|),
-// boff[ngroups] = total. One work-group; each thread sums a contiguous span.
+// boff[ngroups] = total; stats[1] = sum_g |U_g| (capped at INT_MAX). One work-group;
+// each thread sums a contiguous span.
 __global__ __launch_bounds__(1024) void k_grp_offsets(int ngroups, const int32_t* __restrict__ ucount,
-                                                      int64_t* __restrict__ boff) {
+                                                      int64_t* __restrict__ boff, int* __restrict__ stats) {
     __shared__ int64_t scan[1024];
+    __shared__ unsigned long long usum;
+    if (threadIdx.x == 0) usum = 0;
     const int per = (ngroups + 1023) / 1024;
     const int a0 = min(ngroups, (int)threadIdx.x * per), a1 = min(ngroups, a0 + per);
-    int64_t mine = 0;
-    for (int g = a0; g < a1; ++g) mine += 16 * (int64_t)((ucount[g] + 3) & ~3);
+    int64_t mine = 0, mine_u = 0;
+    for (int g = a0; g < a1; ++g) {
+        mine += 16 * (int64_t)((ucount[g] + 3) & ~3);
+        mine_u += ucount[g];
+    }
     scan[threadIdx.x] = mine;
+    __syncthreads();
+    atomicAdd(&usum, (unsigned long long)mine_u);       // LDS atomic: one work-group only
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
         const int64_t v = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
@@ -133,6 +186,7 @@ __global__ __launch_bounds__(1024) void k_grp_offsets(int ngroups, const int32_t
         run += 16 * (int64_t)((ucount[g] + 3) & ~3);
     }
     if (threadIdx.x == 1023) boff[ngroups] = scan[1023];
+    if (threadIdx.x == 0) stats[1] = (int)min<unsigned long long>(usum, 0x7fffffffull);
 }
 
 // Dense k-major block of group g: zero, then each CSR entry at [pos][row].
@@ -251,7 +305,8 @@ void carve_groups(Arena& a, int n, int64_t nnz, size_t elem, SpmmGroups& g) {
 
 void spmm_grp_prepare(int n, const int32_t* row_ptr, const int32_t* col, const SpmmGroups& gp, int* stats,
                       hipStream_t s) {
-    k_grp_union<<<spmm_groups(n), 256, 0, s>>>(n, row_ptr, col, gp.U, gp.ucount, gp.pos, stats);
+    k_grp_union<<<spmm_groups(n), kUnionThreads, 0, s>>>(n, row_ptr, col, gp.U, gp.ucount, gp.pos, stats);
+    k_grp_offsets<<<1, 1024, 0, s>>>(spmm_groups(n), gp.ucount, gp.boff, stats);
 }
 
 bool spmm_grp_worthwhile(int64_t nnz, int too_long, int64_t sum_union) {
@@ -261,7 +316,6 @@ bool spmm_grp_worthwhile(int64_t nnz, int too_long, int64_t sum_union) {
 template <typename T>
 void spmm_grp_fill(int n, const int32_t* row_ptr, const T* val, const SpmmGroups& gp, hipStream_t s) {
     const int ng = spmm_groups(n);
-    k_grp_offsets<<<1, 1024, 0, s>>>(ng, gp.ucount, gp.boff);
     k_grp_fill<T><<<ng, 256, 0, s>>>(n, row_ptr, val, gp.ucount, gp.pos, gp.boff, static_cast<T*>(gp.hblk));
 }
 

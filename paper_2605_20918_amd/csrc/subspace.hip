@@ -124,23 +124,26 @@ constexpr int kMaxDepth = 512;       // at most 256 poles (|y| up to about 1300)
 
 // ------------------------------------------------------------------ device
 
-// Gershgorin interval of T, one thread per row: lo[row], hi[row].
-__global__ void k_gersh(const double* __restrict__ A, const double* __restrict__ B, int v, int b, int ld,
-                        double* __restrict__ lo, double* __restrict__ hi) {
-    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+// Gershgorin interval of T, one wavefront per row: lo[row], hi[row].
+__global__ __launch_bounds__(256) void k_gersh(const double* __restrict__ A, const double* __restrict__ B, int v, int b,
+                                               int ld, double* __restrict__ lo, double* __restrict__ hi) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= v * b) return;
     const int j = row / b, r = row % b;
     const int64_t mat = (int64_t)ld * ld;
     double rad = 0.0;
-    for (int c = 0; c < b; ++c)
+    for (int c = lane; c < b; c += 64) {
         if (c != r) rad += fabs(A[j * mat + (int64_t)r * ld + c]);
-    if (j > 0)
-        for (int c = 0; c < b; ++c) rad += fabs(B[(j - 1) * mat + (int64_t)r * ld + c]);
-    if (j + 1 < v)
-        for (int c = 0; c < b; ++c) rad += fabs(B[j * mat + (int64_t)c * ld + r]);
-    const double dg = A[j * mat + (int64_t)r * ld + r];
-    lo[row] = dg - rad;
-    hi[row] = dg + rad;
+        if (j > 0) rad += fabs(B[(j - 1) * mat + (int64_t)r * ld + c]);
+        if (j + 1 < v) rad += fabs(B[j * mat + (int64_t)c * ld + r]);
+    }
+    for (int off = 32; off > 0; off >>= 1) rad += __shfl_xor(rad, off);
+    if (lane == 0) {
+        const double dg = A[j * mat + (int64_t)r * ld + r];
+        lo[row] = dg - rad;
+        hi[row] = dg + rad;
+    }
 }
 
 __global__ void k_minmax(const double* __restrict__ lo, const double* __restrict__ hi, int n, double* __restrict__ out) {
@@ -927,27 +930,38 @@ __global__ void k_pole_sum(const double* __restrict__ Wout, int npole, int64_t n
     F[idx] = g * (0.5 * e1b0 - s);
 }
 
-// trace_K = sum_c sqrt(n_c) F[c][c];  E_K = sum_c sqrt(n_c) (A_1 F_1 + B_1^T F_2)[c][c]
-__global__ void k_krylov_sums(const double* __restrict__ A, const double* __restrict__ B, const double* __restrict__ F,
-                              const int* __restrict__ counts, int v, int b, int ld, double* __restrict__ out) {
-    __shared__ double st[256], se[256];
-    double t = 0.0, e = 0.0;
-    for (int c = threadIdx.x; c < b; c += 256) {
-        const double sc = sqrt((double)counts[c]);
-        t += sc * F[(int64_t)c * b + c];
-        double tf = 0.0;
-        for (int k = 0; k < b; ++k) tf += A[(int64_t)c * ld + k] * F[(int64_t)k * b + c];
-        if (v > 1)
-            for (int k = 0; k < b; ++k) tf += B[(int64_t)k * ld + c] * F[(int64_t)(b + k) * b + c];
-        e += sc * tf;
-    }
-    st[threadIdx.x] = t;
-    se[threadIdx.x] = e;
+// trace_K = sum_c sqrt(n_c) F[c][c];  E_K = sum_c sqrt(n_c) (A_1 F_1 + B_1^T F_2)[c][c].
+// One work-group of kKsThreads: a wavefront per colour c (lanes over k), then a
+// fixed tree over the colours. b <= kKsMaxB.
+constexpr int kKsThreads = 1024;
+constexpr int kKsMaxB = 128;
+
+__global__ __launch_bounds__(kKsThreads) void k_krylov_sums(const double* __restrict__ A, const double* __restrict__ B,
+                                                            const double* __restrict__ F,
+                                                            const int* __restrict__ counts, int v, int b, int ld,
+                                                            double* __restrict__ out) {
+    __shared__ double st[kKsMaxB], se[kKsMaxB];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int c = threadIdx.x; c < kKsMaxB; c += kKsThreads) st[c] = se[c] = 0.0;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            st[threadIdx.x] += st[threadIdx.x + s];
-            se[threadIdx.x] += se[threadIdx.x + s];
+    for (int c = w; c < b; c += kKsThreads / 64) {
+        double tf = 0.0;
+        for (int k = lane; k < b; k += 64) {
+            tf += A[(int64_t)c * ld + k] * F[(int64_t)k * b + c];
+            if (v > 1) tf += B[(int64_t)k * ld + c] * F[(int64_t)(b + k) * b + c];
+        }
+        for (int off = 32; off > 0; off >>= 1) tf += __shfl_xor(tf, off);
+        if (lane == 0) {
+            const double sc = sqrt((double)counts[c]);
+            st[c] = sc * F[(int64_t)c * b + c];
+            se[c] = sc * tf;
+        }
+    }
+    __syncthreads();
+    for (int h = kKsMaxB / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            st[threadIdx.x] += st[threadIdx.x + h];
+            se[threadIdx.x] += se[threadIdx.x + h];
         }
         __syncthreads();
     }
@@ -990,7 +1004,7 @@ css_status subspace_fermi_poles(const double* A, const double* B, int v, int b, 
     double* glo = ar.take<double>(nT);
     double* ghi = ar.take<double>(nT);
     double* range = ar.take<double>(16);
-    k_gersh<<<grid_for(nT, 256), 256, 0, s>>>(A, B, v, b, ld, glo, ghi);
+    k_gersh<<<grid_for(nT, 4), 256, 0, s>>>(A, B, v, b, ld, glo, ghi);
     k_minmax<<<1, 256, 0, s>>>(glo, ghi, nT, range);
     double hr[2];
     CSS_HIP_TRY(hipMemcpyAsync(hr, range, sizeof(hr), hipMemcpyDeviceToHost, s));
@@ -1033,7 +1047,7 @@ css_status subspace_fermi_poles(const double* A, const double* B, int v, int b, 
                                                                                 kap, wgt, counts, Gbuf, Sg,
                                                                                 use_lds ? 1 : 0, Wout);
     k_pole_sum<<<grid_for((int64_t)nT * b, 256), 256, 0, s>>>(Wout, np, (int64_t)nT * b, b, counts, g, F);
-    k_krylov_sums<<<1, 256, 0, s>>>(A, B, F, counts, v, b, ld, sums);
+    k_krylov_sums<<<1, kKsThreads, 0, s>>>(A, B, F, counts, v, b, ld, sums);     // b <= 128 checked above
     if (npoles_out) *npoles_out = np;
     CSS_HIP_TRY(hipGetLastError());
     return CSS_OK;
