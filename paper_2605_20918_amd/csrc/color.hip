@@ -36,6 +36,7 @@ struct Grid {
     double w[3];        // cell width (>= r_cut)
     double lo[3];       // origin (open directions) / 0 (periodic)
     double L[3];        // box edge, 0 = open
+    double invL[3];     // 1 / L (0 for open directions)
 };
 
 __device__ __forceinline__ int cell_coord(double x, int k, const Grid& g) {
@@ -47,27 +48,6 @@ __device__ __forceinline__ int cell_coord(double x, int k, const Grid& g) {
     }
     int c = static_cast<int>(floor(t / g.w[k]));
     return c < 0 ? 0 : (c >= g.nc[k] ? g.nc[k] - 1 : c);
-}
-
-__device__ __forceinline__ bool conflict(const double* __restrict__ xyz, int64_t m, int64_t n,
-                                         const Grid& g, double rc2) {
-#pragma clang fp contract(off)
-    double d[3];
-    for (int k = 0; k < 3; ++k) {
-        double dk = xyz[3 * n + k] - xyz[3 * m + k];
-        if (g.L[k] > 0.0) {
-            double q = rint(dk / g.L[k]);
-            double s = g.L[k] * q;
-            dk = dk - s;
-        }
-        d[k] = dk;
-    }
-    double a = d[0] * d[0];
-    double b = d[1] * d[1];
-    double c = d[2] * d[2];
-    double ab = a + b;
-    double d2 = ab + c;
-    return d2 <= rc2;
 }
 
 // Bounding box in two levels: every work-group's min and max per coordinate to
@@ -139,43 +119,110 @@ __device__ __forceinline__ int stencil(int nc, bool periodic, int c, int o[3]) {
     return k;
 }
 
+// Minimum-image difference dk - L rint(dk / L). The integer rint(dk / L) is taken
+// from dk * (1/L) unless that product lies within a relative 1e-9 of a
+// half-integer (then from the IEEE quotient): away from ties both round to the
+// same integer, so the result is bitwise the plain formula's.
+__device__ __forceinline__ double min_image(double dk, double L, double invL) {
+#pragma clang fp contract(off)
+    const double t = dk * invL;
+    double q = rint(t);
+    if (fabs(fabs(t - q) - 0.5) <= 1e-9 * fmax(1.0, fabs(t))) q = rint(dk / L);
+    const double s = L * q;
+    return dk - s;
+}
+
+// Conflict pairs, one work-group per cell: the cell's orbitals are taken 64 at a
+// time (one per lane) and the orbitals of the (up to 27) neighbouring cells are
+// staged through LDS kCandChunk at a time, the four wavefronts taking every
+// fourth candidate (a broadcast read). Every conflict decision is the plain
+// ((dx*dx + dy*dy) + dz*dz) <= r_cut^2, products and sums rounded separately.
 // COUNT = true: deg[m] = number of conflicting partners (self excluded).
 // COUNT = false: write the row (self included) at p_col[p_row_ptr[m] ...] unsorted.
-// Threads take orbitals in cell order (cell_list), so that the threads of a
-// wavefront mostly scan the same cells: uniform loop bounds, and each candidate's
-// coordinates are one load shared by the wavefront.
+constexpr int kPairThreads = 256;
+constexpr int kCandChunk = 1024;
+
 template <bool COUNT>
-__global__ void k_neighbours(const double* __restrict__ xyz, int n, Grid g, double rc2,
-                             const int* __restrict__ cell_of, const int* __restrict__ cell_start,
-                             const int* __restrict__ cell_list, int* __restrict__ deg,
-                             const int64_t* __restrict__ p_row_ptr, int32_t* __restrict__ p_col) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int m = cell_list[i];
-    int c = cell_of[m];
-    int cz = c % g.nc[2];
-    int cy = (c / g.nc[2]) % g.nc[1];
-    int cx = c / (g.nc[2] * g.nc[1]);
-    int ox[3], oy[3], oz[3];
-    int nx = stencil(g.nc[0], g.L[0] > 0.0, cx, ox);
-    int ny = stencil(g.nc[1], g.L[1] > 0.0, cy, oy);
-    int nz = stencil(g.nc[2], g.L[2] > 0.0, cz, oz);
-    int64_t out = COUNT ? 0 : p_row_ptr[m];
-    int count = 0;
-    for (int a = 0; a < nx; ++a)
-        for (int b = 0; b < ny; ++b)
-            for (int d = 0; d < nz; ++d) {
-                int cc = (ox[a] * g.nc[1] + oy[b]) * g.nc[2] + oz[d];
-                int s = cell_start[cc], e = cell_start[cc + 1];
-                for (int t = s; t < e; ++t) {
-                    int nb = cell_list[t];
-                    if (nb == m || conflict(xyz, m, nb, g, rc2)) {
-                        if (!COUNT) p_col[out + count] = nb;
-                        ++count;
+__global__ __launch_bounds__(kPairThreads) void k_cell_pairs(const double* __restrict__ xyz, Grid g, double rc2,
+                                                             const int* __restrict__ cell_start,
+                                                             const int* __restrict__ cell_list, int* __restrict__ deg,
+                                                             const int64_t* __restrict__ p_row_ptr,
+                                                             int32_t* __restrict__ p_col) {
+#pragma clang fp contract(off)
+    __shared__ double sx[kCandChunk], sy[kCandChunk], sz[kCandChunk];
+    __shared__ int sid[kCandChunk];
+    __shared__ int ncells, ccell[27], cpre[28];
+    __shared__ int cnt[64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = blockIdx.x;
+    const int os = cell_start[c], oe = cell_start[c + 1];
+    if (os == oe) return;
+    if (threadIdx.x == 0) {
+        const int kz = c % g.nc[2], ky = (c / g.nc[2]) % g.nc[1], kx = c / (g.nc[2] * g.nc[1]);
+        int ox[3], oy[3], oz[3];
+        const int nx = stencil(g.nc[0], g.L[0] > 0.0, kx, ox);
+        const int ny = stencil(g.nc[1], g.L[1] > 0.0, ky, oy);
+        const int nz = stencil(g.nc[2], g.L[2] > 0.0, kz, oz);
+        int k = 0;
+        cpre[0] = 0;
+        for (int a = 0; a < nx; ++a)
+            for (int b = 0; b < ny; ++b)
+                for (int d = 0; d < nz; ++d) {
+                    const int cc = (ox[a] * g.nc[1] + oy[b]) * g.nc[2] + oz[d];
+                    ccell[k] = cc;
+                    cpre[k + 1] = cpre[k] + (cell_start[cc + 1] - cell_start[cc]);
+                    ++k;
+                }
+        ncells = k;
+    }
+    __syncthreads();
+    const int total = cpre[ncells];
+    for (int o0 = os; o0 < oe; o0 += 64) {
+        const int on = min(64, oe - o0);
+        const bool own = lane < on;
+        const int m = cell_list[o0 + (own ? lane : 0)];
+        const double mx = xyz[3 * (int64_t)m], my = xyz[3 * (int64_t)m + 1], mz = xyz[3 * (int64_t)m + 2];
+        const int64_t rbase = COUNT ? 0 : p_row_ptr[m];
+        if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
+        for (int j0 = 0; j0 < total; j0 += kCandChunk) {
+            const int jn = min(kCandChunk, total - j0);
+            __syncthreads();                       // counters zeroed / previous chunk consumed
+            for (int q = threadIdx.x; q < jn; q += kPairThreads) {
+                const int gj = j0 + q;
+                int k = 0;
+                while (cpre[k + 1] <= gj) ++k;
+                const int nb = cell_list[cell_start[ccell[k]] + (gj - cpre[k])];
+                sid[q] = nb;
+                sx[q] = xyz[3 * (int64_t)nb];
+                sy[q] = xyz[3 * (int64_t)nb + 1];
+                sz[q] = xyz[3 * (int64_t)nb + 2];
+            }
+            __syncthreads();
+            if (own)
+                for (int q = w; q < jn; q += kPairThreads / 64) {
+                    const int nb = sid[q];
+                    bool hit = nb == m;
+                    if (!hit) {
+                        double dx = sx[q] - mx, dy = sy[q] - my, dz = sz[q] - mz;
+                        if (g.L[0] > 0.0) dx = min_image(dx, g.L[0], g.invL[0]);
+                        if (g.L[1] > 0.0) dy = min_image(dy, g.L[1], g.invL[1]);
+                        if (g.L[2] > 0.0) dz = min_image(dz, g.L[2], g.invL[2]);
+                        const double a = dx * dx;
+                        const double b = dy * dy;
+                        const double e = dz * dz;
+                        const double ab = a + b;
+                        hit = ab + e <= rc2;
+                    }
+                    if (hit) {
+                        const int slot = atomicAdd(&cnt[lane], 1);
+                        if (!COUNT) p_col[rbase + slot] = nb;
                     }
                 }
-            }
-    if (COUNT) deg[m] = count - 1;      // self is always found once
+        }
+        __syncthreads();
+        if (COUNT && threadIdx.x < on) deg[cell_list[o0 + threadIdx.x]] = cnt[threadIdx.x] - 1;   // self once
+        __syncthreads();
+    }
 }
 
 // Sort each pattern row ascending by rank (entries are distinct).
@@ -484,6 +531,7 @@ Grid make_grid(int n, const double box[3], double r_cut, const double bb[6]) {
         double extent = g.L[k] > 0.0 ? g.L[k] : (bb[3 + k] - bb[k]);
         g.w[k] = extent > 0.0 ? extent / g.nc[k] : 1.0;
         if (g.w[k] < wmin) g.w[k] = wmin;   // open direction: cells may overhang the box
+        g.invL[k] = g.L[k] > 0.0 ? 1.0 / g.L[k] : 0.0;
     }
     return g;
 }
@@ -579,8 +627,8 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
     k_place<<<grid_for(n, 256), 256, 0, s>>>(n, w.cell_of, w.cell_start, w.cell_fill, w.cell_list);
 
     // degrees and row pointers
-    k_neighbours<true><<<grid_for(n, 128), 128, 0, s>>>(xyz, n, g, rc2, w.cell_of, w.cell_start,
-                                                        w.cell_list, w.deg, nullptr, nullptr);
+    k_cell_pairs<true><<<ncell, kPairThreads, 0, s>>>(xyz, g, rc2, w.cell_start, w.cell_list, w.deg, nullptr,
+                                                      nullptr);
     const int nblk = (n + kScanBlock - 1) / kScanBlock;
     k_scan_blocks<<<nblk, kScanBlock, 0, s>>>(w.deg, n, p_row_ptr, w.block_sum);
     k_scan_sums<<<1, kScanBlock, 0, s>>>(w.block_sum, nblk);
@@ -601,8 +649,8 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
     CSS_HIP_TRY(hipStreamSynchronize(s));
     if (hmax[1] > kMaxRowLds) return CSS_E_UNSUPPORTED;
 
-    k_neighbours<false><<<grid_for(n, 128), 128, 0, s>>>(xyz, n, g, rc2, w.cell_of, w.cell_start,
-                                                         w.cell_list, w.deg, p_row_ptr, p_col);
+    k_cell_pairs<false><<<ncell, kPairThreads, 0, s>>>(xyz, g, rc2, w.cell_start, w.cell_list, w.deg, p_row_ptr,
+                                                       p_col);
     k_sort_rows<<<n, 256, 0, s>>>(n, p_row_ptr, p_col);
 
     // fixed-point sweeps, kFpBatch per host check of the change counters

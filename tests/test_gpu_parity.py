@@ -65,6 +65,22 @@ def test_colour_special_graphs_bitexact():
     _colour_case(np.zeros((5, 3)), np.zeros(3), 1.0)                      # coincident centres
 
 
+def test_colour_minimum_image_ties_bitexact():
+    """Periodic separations of exactly half a box (the image integer at a rounding
+    tie) and centres many boxes away from [0, L) (image integers far from 0): the
+    conflict decisions, pattern and colours equal the oracle's plain formula."""
+    g = 6
+    idx = np.arange(g ** 3)
+    lat = np.stack([idx // 36, (idx // 6) % 6, idx % 6], 1).astype(float)
+    box = np.array([6.0, 6.0, 6.0])
+    _colour_case(lat, box, 3.0)                                           # one cell, d = L/2 ties
+    _colour_case(lat, box, 2.9)                                           # two cells per direction
+    rng = np.random.default_rng(7)
+    far = lat + 6.0 * rng.integers(-40, 41, size=lat.shape)
+    _colour_case(far, box, 2.9)
+    _colour_case(far + rng.uniform(-1e-3, 1e-3, size=lat.shape), box, 2.5)
+
+
 def test_colour_large_frontiers_bitexact():
     """6000 isolated orbitals (all in the first round, a frontier larger than one
     workgroup keeps) beside a dense 1-d chain (one orbital per round), colouring
