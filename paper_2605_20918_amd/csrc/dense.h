@@ -35,6 +35,16 @@ void update_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstrid
                    const double* S, int64_t sstride, bool trans, double scale, int64_t Np, int ld,
                    void* stage, const int* state, hipStream_t s);
 
+// update_launch for coefficient blocks S_p that are small corrections (full
+// reorthogonalisation after the three-term update). FP32 blocks with ld a multiple
+// of 16 up to 128: products on BF16 MFMA with both factors split in two BF16 parts
+// (relative error of each product term below 2^-15; stage holds the split
+// coefficients, at most nprod*ld*ld doubles). FP64, and other ld: update_launch.
+template <typename T>
+void update_correction_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, int nprod,
+                              const double* S, int64_t sstride, bool trans, double scale, int64_t Np, int ld,
+                              void* stage, const int* state, hipStream_t s);
+
 // Cholesky G = R^T R of the leading b x b block, R and R^-1 (ld x ld, zero
 // elsewhere). On failure (non-positive pivot, non-finite, min diag <= tau) sets
 // state[0] = 1, state[2] = step, writes R^-1 = 0. Tracks min diag in *min_diag.

@@ -331,6 +331,169 @@ __global__ __launch_bounds__(256) void k_update(T* OUT, const T* IN, double alph
         }
 }
 
+// ------------------------------------------------------------------ BF16 correction
+//
+// W -= sum_p Q_p C_p where the coefficients C_p are corrections of the size of the
+// basis' loss of orthogonality (full reorthogonalisation after the three-term
+// update): each FP32 factor is split into two BF16 parts, x = hi + lo with
+// hi = RNE(x), lo = RNE(x - hi), |x - hi - lo| <= 2^-17 |x|, and the product
+// is hi*hi + hi*lo + lo*hi on the 16x16x32 BF16 MFMA (FP32 accumulation). The
+// dropped and rounded parts are below 2^-15 |Q| |C| in each term, far under the
+// FP32 rounding of W when C is as small as such corrections are.
+//
+// MFMA 16x16x32 BF16 layout (gfx950): lane l supplies A[l%16][k] and B[k][l%16]
+// for the 8 K slots k of lane group l/16 (any assignment of K slots shared by A
+// and B gives the same product); D[4(l/16)+r][l%16] in result register r.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kSplitK = 32;
+
+// Work-group barrier that orders LDS accesses only: the LDS writes before it are
+// complete (release at work-group scope, LDS only) when the waves meet, and the
+// empty asm keeps the compiler from moving memory accesses across it. Global loads
+// in flight (the prefetched X chunks) stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ void split_bf16(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        hi[e] = static_cast<__bf16>(x[e]);
+        lo[e] = static_cast<__bf16>(x[e] - static_cast<float>(hi[e]));
+    }
+}
+
+// B fragments of S'_p = scale * (trans ? S_p^T : S_p), rounded to FP32 and split:
+// frag[((pk * 2 + plane) * NT + nt) * 64 + l][e] = plane of S'_p[32 kc + 8 (l/16) + e][16 nt + l%16]
+// (pk = p nkc + kc, zero for rows beyond ld), followed by one all-zero chunk
+// (pk = nprod nkc) that the update reads past the last chunk.
+__global__ void k_frag_s(const double* __restrict__ S, int64_t sstride, int nprod, int ld, int trans, double scale,
+                         bf16x8* __restrict__ frag) {
+    const int NT = ld / 16, nkc = (ld + kSplitK - 1) / kSplitK;
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= ((int64_t)nprod * nkc + 1) * NT * 64) return;
+    const int l = (int)(idx % 64), nt = (int)((idx / 64) % NT);
+    const int64_t pk = idx / (64 * NT);
+    const bool pad = pk == (int64_t)nprod * nkc;
+    const int kc = (int)(pk % nkc);
+    const double* Sp = S + (pad ? 0 : (pk / nkc) * sstride);
+    const int j = 16 * nt + (l & 15);
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = kSplitK * kc + 8 * (l >> 4) + e;
+        v[e] = (!pad && k < ld) ? static_cast<float>(scale * (trans ? Sp[(int64_t)j * ld + k] : Sp[(int64_t)k * ld + j]))
+                                : 0.f;
+    }
+    bf16x8 hi, lo;
+    split_bf16(v, hi, lo);
+    frag[((pk * 2 + 0) * NT + nt) * 64 + l] = hi;
+    frag[((pk * 2 + 1) * NT + nt) * 64 + l] = lo;
+}
+
+// OUT = alpha IN + sum_p X_p S'_p for FP32 blocks with ld = 16 NT. A wave owns 16 MT
+// rows and all ld columns; the X runs of a K chunk (8 consecutive elements per lane
+// and row tile) are fetched D chunks ahead, the chunk's B fragments go through LDS
+// (double buffered, shared by the four waves). The loop body has no branch: it runs
+// whole rounds of D chunks, chunks past the end take the zero fragments, and X
+// addresses are clamped into the block (a clamped value always meets a zero
+// coefficient), so that every wait for a load can leave the later loads in flight.
+template <int MT, int NT, int D>
+__global__ __launch_bounds__(256) void k_update_split(float* OUT, const float* IN, double alpha,
+                                                      const float* __restrict__ X, int64_t xstride, int nprod,
+                                                      const bf16x8* __restrict__ frag, int64_t Np, int ld,
+                                                      const int* __restrict__ state) {
+    if (state && state[0]) return;
+    constexpr int FR = 2 * NT * 64;                       // fragments of one K chunk
+    constexpr int PER = (FR + 255) / 256;
+    __shared__ bf16x8 sB[2][PER * 256];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, lr = l >> 4, lc = l & 15;
+    const int64_t m0 = ((int64_t)blockIdx.x * 4 + w) * (16 * MT);
+    const bool active = m0 < Np;
+    const int64_t mrow = active ? m0 : 0;                 // inactive waves read (and discard) rows 0..
+    const int nkc = (ld + kSplitK - 1) / kSplitK;
+    const int total = nprod * nkc;
+    mf_f4 c[MT][NT];
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) c[a][b] = mf_f4{0.f, 0.f, 0.f, 0.f};
+
+    auto fetch_x = [&](int it, float (&x)[MT][8]) {
+        const int p = it / nkc, k = min((it % nkc) * kSplitK + 8 * lr, ld - 8);
+        const float* Xp = X + (int64_t)p * xstride + (mrow + lc) * ld + k;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            float a4[4], b4[4];
+            load_q<float, 4>(Xp + (int64_t)16 * mt * ld, a4);
+            load_q<float, 4>(Xp + (int64_t)16 * mt * ld + 4, b4);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { x[mt][e] = a4[e]; x[mt][4 + e] = b4[e]; }
+        }
+    };
+    auto fetch_s = [&](int it, bf16x8 (&reg)[PER]) {
+        const bf16x8* src = frag + (int64_t)it * FR;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) reg[q] = src[min(threadIdx.x + 256 * q, (unsigned)FR - 1)];
+    };
+    auto store_s = [&](int buf, const bf16x8 (&reg)[PER]) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) sB[buf][threadIdx.x + 256 * q] = reg[q];
+    };
+    auto compute = [&](int buf, const float (&x)[MT][8]) {
+        bf16x8 ah[MT], al[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) split_bf16(x[mt], ah[mt], al[mt]);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const bf16x8 bh = sB[buf][nt * 64 + l], bl = sB[buf][(NT + nt) * 64 + l];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bh, c[mt][nt], 0, 0, 0);
+                c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bl, c[mt][nt], 0, 0, 0);
+                c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bh, c[mt][nt], 0, 0, 0);
+            }
+        }
+    };
+    float xr[D][MT][8];
+#pragma unroll
+    for (int d = 0; d < D; ++d) fetch_x(min(d, total - 1), xr[d]);
+    // loads are issued in the order they are needed (vmcnt counts in order): the
+    // coefficients of chunk it + 1 (stored after chunk it) one chunk ahead, then X
+    // D chunks ahead
+    bf16x8 sreg[PER];
+    fetch_s(0, sreg);
+    store_s(0, sreg);
+    fetch_s(min(1, total), sreg);
+    for (int it0 = 0; it0 < total; it0 += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int it = it0 + d;
+            lds_barrier();                                // sB[it & 1] holds chunk it; chunk it - 1 done
+            compute(it & 1, xr[d]);
+            store_s((it + 1) & 1, sreg);
+            fetch_s(min(it + 2, total), sreg);
+            fetch_x(min(it + D, total - 1), xr[d]);       // D chunks ahead (clamped at the end)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + 16 * mt + 4 * lr + r;
+                const int64_t idx = row * ld + nt * 16 + lc;
+                double v = (double)c[mt][nt][r];
+                if (IN != nullptr && alpha != 0.0) v += alpha * (double)IN[idx];
+                OUT[idx] = static_cast<float>(v);
+            }
+}
+
 // S'_p = scale * (trans ? S_p^T : S_p) in the block precision.
 template <typename T>
 __global__ void k_stage_s(const double* __restrict__ S, int64_t sstride, int nprod, int ld, int trans,
@@ -955,6 +1118,48 @@ void update_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstrid
         update_one<T, 6>(OUT, IN, alpha, X, xstride, nprod, st, Np, ld, state, s);
     else
         update_one<T, 8>(OUT, IN, alpha, X, xstride, nprod, st, Np, ld, state, s);
+}
+
+template <int NT>
+static void update_split_one(float* OUT, const float* IN, double alpha, const float* X, int64_t xstride, int nprod,
+                             const void* frag, int64_t Np, int ld, const int* state, hipStream_t s) {
+    constexpr int MT = 2, D = 4;
+    const int64_t rows_per_block = 4 * 16 * MT;
+    const unsigned grid = static_cast<unsigned>((Np + rows_per_block - 1) / rows_per_block);
+    k_update_split<MT, NT, D><<<grid, 256, 0, s>>>(OUT, IN, alpha, X, xstride, nprod,
+                                                    static_cast<const bf16x8*>(frag), Np, ld, state);
+}
+
+template <>
+void update_correction_launch<float>(float* OUT, const float* IN, double alpha, const float* X, int64_t xstride,
+                                     int nprod, const double* S, int64_t sstride, bool trans, double scale,
+                                     int64_t Np, int ld, void* stage, const int* state, hipStream_t s) {
+    const int nt = ld / 16;
+    if (ld % 16 != 0 || nt > 8) {
+        update_launch<float>(OUT, IN, alpha, X, xstride, nprod, S, sstride, trans, scale, Np, ld, stage, state, s);
+        return;
+    }
+    const int nkc = (ld + kSplitK - 1) / kSplitK;
+    const int64_t cnt = ((int64_t)nprod * nkc + 1) * nt * 64;
+    k_frag_s<<<grid_for(cnt, 256), 256, 0, s>>>(S, sstride, nprod, ld, trans ? 1 : 0, scale,
+                                                static_cast<bf16x8*>(stage));
+    switch (nt) {
+        case 1: update_split_one<1>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+        case 2: update_split_one<2>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+        case 3: update_split_one<3>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+        case 4: update_split_one<4>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+        case 5: update_split_one<5>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+        case 6: update_split_one<6>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+        case 7: update_split_one<7>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+        default: update_split_one<8>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+    }
+}
+
+template <>
+void update_correction_launch<double>(double* OUT, const double* IN, double alpha, const double* X, int64_t xstride,
+                                      int nprod, const double* S, int64_t sstride, bool trans, double scale,
+                                      int64_t Np, int ld, void* stage, const int* state, hipStream_t s) {
+    update_launch<double>(OUT, IN, alpha, X, xstride, nprod, S, sstride, trans, scale, Np, ld, stage, state, s);
 }
 
 size_t chol_scratch_bytes(int b) { return sizeof(double) * ((size_t)b * (b + 1) + b + 8); }

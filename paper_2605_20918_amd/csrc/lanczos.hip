@@ -191,7 +191,8 @@ struct Step {
                 const int cnt = std::min(cap, np - t0);
                 gram(q(t0), tall(), cnt, W, bf.C + t0 * mat(), mat(), false, 0);
             }
-            update(W, W, 1.0, q(0), tall(), np, bf.C, mat(), false, -1.0);
+            update_correction_launch<T>(W, W, 1.0, q(0), tall(), np, bf.C, mat(), false, -1.0, p.Np, p.ld,
+                                        bf.stage, bf.state, s);
             sym_add_launch(bf.C + j * mat(), Aj, ld, bf.state, s);
         }
         if (last) return true;
