@@ -35,6 +35,15 @@ void update_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstrid
                    const double* S, int64_t sstride, bool trans, double scale, int64_t Np, int ld,
                    void* stage, const int* state, hipStream_t s);
 
+// Gram X_p^T Y (p < nprod, X_p = X + p xstride) for the full reorthogonalisation
+// coefficients, mode as gram_launch, partial capacity cap_mats ld x ld matrices.
+// FP32 blocks with ld a multiple of 16 up to 96: BF16 MFMA with three-part operand
+// splits (per term no less accurate than the FP32 product); otherwise gram_launch.
+template <typename T>
+void gram_correction_launch(const T* X, int64_t xstride, int nprod, const T* Y, int64_t Np, int ld,
+                            int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
+                            const int* state, hipStream_t s);
+
 // update_launch for coefficient blocks S_p that are small corrections (full
 // reorthogonalisation after the three-term update). FP32 blocks with ld a multiple
 // of 16 up to 128: products on BF16 MFMA with both factors split in two BF16 parts

@@ -494,6 +494,131 @@ __global__ __launch_bounds__(256) void k_update_split(float* OUT, const float* I
             }
 }
 
+// ------------------------------------------------------------------ BF16 Gram
+//
+// X_p^T Y for FP32 blocks on the 16x16x32 BF16 MFMA, with every factor split
+// into NPL BF16 parts x = x0 + x1 (+ x2), x_i = RNE(x - x_0 - .. - x_{i-1}):
+// NPL = 3 keeps the six products of order >= 2^-16 (x0y0, x0y1, x1y0, x0y2, x1y1,
+// x2y0), each term then carries a relative error of a few 2^-24, no more than the
+// rounding of the FP32 product it replaces; NPL = 2 keeps x0y0 + x0y1 + x1y0
+// (a few 2^-17 per term). Accumulation is FP32 in the MFMA, at most kGramFp32Rows
+// rows per wave before the FP64 reduction, as in k_gram.
+// One workgroup of four waves per (chunk, p): NH column parts x 4/NH row groups.
+// Wave (grp, h) owns the ld x (ld/NH) tile of Y columns [h ld/NH, (h+1) ld/NH) and
+// takes the 32-row steps grp, grp + 4/NH, ... of the chunk; a lane holds the 8 rows
+// 8 (l/16) .. + 7 of a step (its K slots), for X the columns seg_col(a, l%16) of
+// each tile a, for Y the column 16 b + l%16 of each of its tiles b. Operands are
+// fetched one step ahead (the chunk's steps per wave are even, see
+// gram_plan_split). The row groups' tiles are added in LDS in group order and
+// written as one partial, as in k_gram.
+template <int NPL>
+__device__ __forceinline__ void split_planes(const float (&x)[8], bf16x8 (&pl)[NPL]) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        float r = x[e];
+#pragma unroll
+        for (int q = 0; q < NPL; ++q) {
+            pl[q][e] = static_cast<__bf16>(r);
+            if (q + 1 < NPL) r -= static_cast<float>(pl[q][e]);
+        }
+    }
+}
+
+template <int NT, int NH, int NPL>
+__global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ X, int64_t xstride,
+                                                    const float* __restrict__ Y, int64_t Np, int64_t rpc, int ld,
+                                                    float* __restrict__ partial, int nchunk,
+                                                    const int* __restrict__ state) {
+    if (state && state[0]) return;
+    constexpr int TILE = 16 * NT, NB = NT / NH, KG = 4 / NH;
+    static_assert(NT % NH == 0 && (NH == 1 || NH == 2), "column parts");
+    extern __shared__ char gram_lds[];
+    float* buf = reinterpret_cast<float*>(gram_lds);
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, lr = l >> 4, lc = l & 15;
+    const int grp = w / NH, h = w % NH;
+    const int chunk = blockIdx.x, p = blockIdx.z;
+    const int64_t r0 = (int64_t)chunk * rpc;
+    const int64_t r1 = r0 + rpc < Np ? r0 + rpc : Np;
+    const int nst = (int)((r1 - r0) / (32 * KG));         // steps of this wave (even)
+    mf_f4 c[NT][NB];
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) c[a][b] = mf_f4{0.f, 0.f, 0.f, 0.f};
+    const int64_t step = 32 * KG * (int64_t)ld;
+    const float* xa = X + (int64_t)p * xstride + (r0 + 32 * grp + 8 * lr) * ld;
+    const float* ya = Y + (r0 + 32 * grp + 8 * lr) * ld + 16 * NB * h + lc;
+    auto fetch = [&](int st, float (&x)[8][NT], float (&y)[8][NB]) {
+        const int64_t o = (int64_t)st * step;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            load_run<float, NT>(xa + o + (int64_t)e * ld, lc, x[e]);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) y[e][b] = ya[o + (int64_t)e * ld + 16 * b];
+        }
+    };
+    auto compute = [&](const float (&x)[8][NT], const float (&y)[8][NB]) {
+        bf16x8 yb[NB][NPL];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = y[e][b];
+            split_planes<NPL>(v, yb[b]);
+        }
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = x[e][a];
+            bf16x8 xb[NPL];
+            split_planes<NPL>(v, xb);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if constexpr (NPL == 3) {
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[2], yb[b][0], c[a][b], 0, 0, 0);
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[1], yb[b][1], c[a][b], 0, 0, 0);
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[0], yb[b][2], c[a][b], 0, 0, 0);
+                }
+                c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[1], yb[b][0], c[a][b], 0, 0, 0);
+                c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[0], yb[b][1], c[a][b], 0, 0, 0);
+                c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[0], yb[b][0], c[a][b], 0, 0, 0);
+            }
+        }
+    };
+    float x0[8][NT], x1[8][NT], y0[8][NB], y1[8][NB];
+    if (nst > 0) fetch(0, x0, y0);
+    for (int st = 0; st < nst; st += 2) {
+        fetch(st + 1, x1, y1);                            // nst is even
+        __builtin_amdgcn_sched_barrier(0);
+        compute(x0, y0);
+        fetch(min(st + 2, nst - 1), x0, y0);              // the last step again at the end (not used)
+        __builtin_amdgcn_sched_barrier(0);
+        compute(x1, y1);
+    }
+    // row groups' tiles added into LDS in group order (tile-local coordinates)
+#pragma unroll
+    for (int g = 0; g < KG; ++g) {
+        if (grp == g) {
+#pragma unroll
+            for (int a = 0; a < NT; ++a)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = seg_col<NT, 4>(a, 4 * lr + r);
+                        const int col = 16 * (NB * h + b) + lc;
+                        float& e = buf[row * TILE + col];
+                        e = (g == 0) ? c[a][b][r] : e + c[a][b][r];
+                        if (r == 3) __builtin_amdgcn_sched_barrier(0);
+                    }
+        }
+        __syncthreads();
+    }
+    float* out = partial + ((int64_t)p * nchunk + chunk) * ld * ld;
+    for (int e = threadIdx.x; e < TILE * TILE; e += 256) out[e] = buf[e];
+}
+
 // S'_p = scale * (trans ? S_p^T : S_p) in the block precision.
 template <typename T>
 __global__ void k_stage_s(const double* __restrict__ S, int64_t sstride, int nprod, int ld, int trans,
@@ -1160,6 +1285,74 @@ void update_correction_launch<double>(double* OUT, const double* IN, double alph
                                       int nprod, const double* S, int64_t sstride, bool trans, double scale,
                                       int64_t Np, int ld, void* stage, const int* state, hipStream_t s) {
     update_launch<double>(OUT, IN, alpha, X, xstride, nprod, S, sstride, trans, scale, Np, ld, stage, state, s);
+}
+
+// Column parts and row groups of k_gram_split for ld (two column parts, hence two
+// row groups, for the widest blocks).
+static int gram_split_parts(int ld) { return (ld / 16) % 2 == 0 && ld / 16 >= 4 ? 2 : 1; }
+static int gram_split_groups(int ld) { return 4 / gram_split_parts(ld); }
+
+// Plan for k_gram_split: chunks of a multiple of 256 rows (an even number of steps
+// per wave), at most kGramFp32Rows rows per wave.
+GramPlan gram_plan_split(int64_t Np, int ld, int nprod, int64_t cap_mats) {
+    GramPlan g;
+    g.ld = ld;
+    g.nprod = nprod;
+    g.Np = Np;
+    g.sym = false;
+    g.ntiles = 1;
+    int64_t nchunk = (256 + nprod - 1) / nprod;          // about a workgroup per compute unit
+    nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, Np / 256));
+    const int kg = gram_split_groups(ld);
+    nchunk = std::max<int64_t>(nchunk, (Np + kg * kGramFp32Rows - 1) / (kg * kGramFp32Rows));
+    nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, cap_mats / std::max(1, nprod)));
+    int64_t rpc = (Np + nchunk - 1) / nchunk;
+    rpc = (rpc + 255) / 256 * 256;                // Np is a multiple of 256
+    g.rows_per_chunk = rpc;
+    g.nchunk = static_cast<int>((Np + rpc - 1) / rpc);
+    return g;
+}
+
+template <int NT>
+static void gram_split_one(const GramPlan& g, const float* X, int64_t xstride, const float* Y, float* part,
+                           const int* state, hipStream_t s) {
+    constexpr int NH = (NT % 2 == 0 && NT >= 4) ? 2 : 1;
+    dim3 grid(g.nchunk, 1, g.nprod);
+    const size_t lds = sizeof(float) * 256 * NT * NT;
+    k_gram_split<NT, NH, 3><<<grid, 256, lds, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, part, g.nchunk,
+                                                    state);
+}
+
+template <>
+void gram_correction_launch<float>(const float* X, int64_t xstride, int nprod, const float* Y, int64_t Np, int ld,
+                                   int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
+                                   const int* state, hipStream_t s) {
+    if (ld % 16 != 0 || ld > 96 || Np % 256 != 0) {
+        const GramPlan g = gram_plan(Np, ld, nprod, false, cap_mats, 4);
+        gram_launch<float>(g, X, xstride, Y, partial, out, out_stride, mode, state, s);
+        return;
+    }
+    // the partials are FP32: the buffer (cap_mats FP64 matrices) holds twice as many
+    const GramPlan g = gram_plan_split(Np, ld, nprod, 2 * cap_mats);
+    float* part = reinterpret_cast<float*>(partial);
+    switch (ld / 16) {
+        case 1: gram_split_one<1>(g, X, xstride, Y, part, state, s); break;
+        case 2: gram_split_one<2>(g, X, xstride, Y, part, state, s); break;
+        case 3: gram_split_one<3>(g, X, xstride, Y, part, state, s); break;
+        case 4: gram_split_one<4>(g, X, xstride, Y, part, state, s); break;
+        case 5: gram_split_one<5>(g, X, xstride, Y, part, state, s); break;
+        default: gram_split_one<6>(g, X, xstride, Y, part, state, s); break;
+    }
+    dim3 rgrid(grid_for((int64_t)ld * ld, 64), nprod);
+    k_gram_reduce<float><<<rgrid, 64 * kRedGroups, 0, s>>>(part, g.nchunk, ld, 0, mode, out, out_stride, state);
+}
+
+template <>
+void gram_correction_launch<double>(const double* X, int64_t xstride, int nprod, const double* Y, int64_t Np, int ld,
+                                    int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
+                                    const int* state, hipStream_t s) {
+    const GramPlan g = gram_plan(Np, ld, nprod, false, cap_mats, 8);
+    gram_launch<double>(g, X, xstride, Y, partial, out, out_stride, mode, state, s);
 }
 
 size_t chol_scratch_bytes(int b) { return sizeof(double) * ((size_t)b * (b + 1) + b + 8); }

@@ -189,7 +189,8 @@ struct Step {
             const int cap = (int)std::max<int64_t>(1, p.partial_mats);
             for (int t0 = 0; t0 < np; t0 += cap) {
                 const int cnt = std::min(cap, np - t0);
-                gram(q(t0), tall(), cnt, W, bf.C + t0 * mat(), mat(), false, 0);
+                gram_correction_launch<T>(q(t0), tall(), cnt, W, p.Np, p.ld, p.partial_mats, bf.partial,
+                                          bf.C + t0 * mat(), mat(), 0, bf.state, s);
             }
             update_correction_launch<T>(W, W, 1.0, q(0), tall(), np, bf.C, mat(), false, -1.0, p.Np, p.ld,
                                         bf.stage, bf.state, s);
