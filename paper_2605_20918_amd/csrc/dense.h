@@ -35,6 +35,14 @@ void update_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstrid
                    const double* S, int64_t sstride, bool trans, double scale, int64_t Np, int ld,
                    void* stage, const int* state, hipStream_t s);
 
+// OUT = alpha*IN + X0 op0(S0) + X1 op1(S1) in one pass over OUT (two products with
+// their own transposition), op_i(S) = scale * (trans_i ? S^T : S). stage: 2*ld*ld
+// elements of T.
+template <typename T>
+void update2_launch(T* OUT, const T* IN, double alpha, const T* X0, const double* S0, bool trans0, const T* X1,
+                    const double* S1, bool trans1, double scale, int64_t Np, int ld, void* stage, const int* state,
+                    hipStream_t s);
+
 // Gram X_p^T Y (p < nprod, X_p = X + p xstride) for the full reorthogonalisation
 // coefficients, mode as gram_launch, partial capacity cap_mats ld x ld matrices.
 // FP32 blocks with ld a multiple of 16 up to 96: BF16 MFMA with three-part operand

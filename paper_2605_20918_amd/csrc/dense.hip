@@ -794,112 +794,127 @@ __global__ __launch_bounds__(256) void k_chol_inv_reg(const double* __restrict__
         }
 }
 
-// One wavefront, blocks of 16 (NB blocks, b <= 16 NB): Cholesky G = R^T R of the
-// leading b x b block and X = R^-1, with no workgroup barrier on the critical path.
+// Blocks of 16 (NB blocks, b <= 16 NB): Cholesky G = R^T R of the leading b x b
+// block and X = R^-1.
 // LDS holds the 16NB x 16NB matrix M (row stride W): G's upper triangle, then R;
 // rows/columns b..16NB-1 are padded with the identity. Diagonal blocks are factored
 // and inverted in registers (MFMA D layout: lane l holds rows (l>>4)+4r, column l&15)
 // with cross-lane broadcasts; panel solves R_kj = R_kk^-T A_kj, trailing updates
 // A_ij -= R_ki^T R_kj and the blocked inverse X_ij = -X_ii sum_{k=i+1..j} R_ik X_kj
 // run on FP64 MFMA. The X_jj are kept in XD (D layout); the X_ij (i < j) are stored
-// transposed in the strictly lower block triangle of M.
+// transposed in the strictly lower block triangle of M. Four waves: wave 0 factors
+// and inverts the diagonal blocks; panel and trailing tiles are dealt to all four,
+// with a work-group barrier between the phases of a block step; the block columns
+// of the inverse are independent and dealt to the waves.
 __device__ inline double lane_bcast(double v, int src) { return __shfl(v, src, 64); }
 
 template <int NB>
-__global__ __launch_bounds__(64) void k_chol_inv_blk(const double* __restrict__ G, int b, int ld,
-                                                     const double* __restrict__ tau_p, double* __restrict__ R,
-                                                     double* __restrict__ Rinv, int* state, int step,
-                                                     double* __restrict__ min_diag) {
+__global__ __launch_bounds__(256) void k_chol_inv_blk(const double* __restrict__ G, int b, int ld,
+                                                      const double* __restrict__ tau_p, double* __restrict__ R,
+                                                      double* __restrict__ Rinv, int* state, int step,
+                                                      double* __restrict__ min_diag) {
     constexpr int N = 16 * NB, W = N + 1;
     extern __shared__ double chol_lds[];
     double* M = chol_lds;                 // N x W
     double* XD = chol_lds + N * W;        // NB x 256 (D layout)
+    __shared__ int sfail;
     if (state[0]) return;
     typedef MF<double> Mf;
-    const int l = threadIdx.x, lr = l >> 4, lc = l & 15;
+    const int t = threadIdx.x, l = t & 63, wv = t >> 6, lr = l >> 4, lc = l & 15;
     const double tau = tau_p ? *tau_p : 0.0;
-    // rows in batches of 12 with every load issued before the LDS stores (N*N/64 = 4 N elements per lane)
-    for (int e0 = 0; e0 < N * N; e0 += 64 * 12) {
-        double v[12];
+    {
+        // every element of the upper triangle once, all loads issued before the LDS stores
+        constexpr int PER = (N * N + 255) / 256;
+        double v[PER];
 #pragma unroll
-        for (int q = 0; q < 12; ++q) {
-            const int e = e0 + 64 * q + l;
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q;
             const int i = e / N, j = e % N;
             v[q] = (e < N * N && i < b && j < b && j >= i) ? G[(int64_t)i * ld + j] : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < 12; ++q) {
-            const int e = e0 + 64 * q + l;
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q;
             const int i = e / N, j = e % N;
             if (e < N * N) M[i * W + j] = (i >= b && i == j) ? 1.0 : v[q];
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    bool fail = false;
+    if (t == 0) sfail = 0;
+    __syncthreads();
     double dmin = INFINITY;
-    for (int kb = 0; kb < NB && !fail; ++kb) {
+    for (int kb = 0; kb < NB; ++kb) {
         const int o = 16 * kb;
-        // (a)-(b) diagonal block: unblocked Cholesky in registers
-        double a[4];
+        if (wv == 0) {
+            // (a)-(b) diagonal block: unblocked Cholesky in registers (wave 0)
+            bool fail = false;
+            double a[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = M[(o + lr + 4 * r) * W + o + lc];
-        double dinv[16];
+            for (int r = 0; r < 4; ++r) a[r] = M[(o + lr + 4 * r) * W + o + lc];
+            double dinv[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int rk = k >> 2, sl = 16 * (k & 3);
-            const double piv = lane_bcast(a[rk], sl + k);
-            double d = 1.0;
-            if (o + k < b && !fail) {                   // uniform: piv is the same in every lane
-                if (!(piv > 0.0) || !isfinite(piv)) {
-                    fail = true;
-                } else {
-                    d = sqrt(piv);
-                    dmin = fmin(dmin, d);
-                    if (!(d > tau)) fail = true;
+            for (int k = 0; k < 16; ++k) {
+                const int rk = k >> 2, sl = 16 * (k & 3);
+                const double piv = lane_bcast(a[rk], sl + k);
+                double d = 1.0;
+                if (o + k < b && !fail) {                   // uniform: piv is the same in every lane
+                    if (!(piv > 0.0) || !isfinite(piv)) {
+                        fail = true;
+                    } else {
+                        d = sqrt(piv);
+                        dmin = fmin(dmin, d);
+                        if (!(d > tau)) fail = true;
+                    }
+                }
+                dinv[k] = 1.0 / d;                          // after a failure the block is discarded
+                if (lr == (k & 3)) a[rk] = lc > k ? a[rk] * dinv[k] : (lc == k ? d : 0.0);
+                const double vj = lane_bcast(a[rk], sl + lc);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double vi = lane_bcast(a[rk], sl + lr + 4 * r);
+                    if (lr + 4 * r > k && lc >= lr + 4 * r) a[r] -= vi * vj;
                 }
             }
-            dinv[k] = 1.0 / d;                          // after a failure the block is discarded
-            if (lr == (k & 3)) a[rk] = lc > k ? a[rk] * dinv[k] : (lc == k ? d : 0.0);
-            const double vj = lane_bcast(a[rk], sl + lc);
+            if (fail) {
+                if (l == 0) sfail = 1;
+            } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const double vi = lane_bcast(a[rk], sl + lr + 4 * r);
-                if (lr + 4 * r > k && lc >= lr + 4 * r) a[r] -= vi * vj;
+                for (int r = 0; r < 4; ++r) M[(o + lr + 4 * r) * W + o + lc] = a[r];
+                // (c) X_kk = R_kk^-1 by backward substitution: row i of X is final once scaled
+                double x[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) x[r] = (lr + 4 * r == lc) ? 1.0 : 0.0;
+#pragma unroll
+                for (int i = 15; i >= 0; --i) {
+                    const int ri = i >> 2, si = 16 * (i & 3);
+                    if (lr == (i & 3)) x[ri] *= dinv[i];
+                    const double xij = lane_bcast(x[ri], si + lc);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double rii = lane_bcast(a[r], 16 * lr + i);     // R_kk[lr + 4r][i]
+                        if (lr + 4 * r < i) x[r] -= rii * xij;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) XD[kb * 256 + r * 64 + l] = x[r];
             }
         }
-        if (fail) break;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) M[(o + lr + 4 * r) * W + o + lc] = a[r];
-        // (c) X_kk = R_kk^-1 by backward substitution: row i of X is final once scaled
-        double x[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) x[r] = (lr + 4 * r == lc) ? 1.0 : 0.0;
-#pragma unroll
-        for (int i = 15; i >= 0; --i) {
-            const int ri = i >> 2, si = 16 * (i & 3);
-            if (lr == (i & 3)) x[ri] *= dinv[i];
-            const double xij = lane_bcast(x[ri], si + lc);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const double rii = lane_bcast(a[r], 16 * lr + i);     // R_kk[lr + 4r][i]
-                if (lr + 4 * r < i) x[r] -= rii * xij;
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) XD[kb * 256 + r * 64 + l] = x[r];
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        // (d) panel R_kj = X_kk^T A_kj
-        for (int jb = kb + 1; jb < NB; ++jb) {
+        __syncthreads();
+        if (sfail) break;
+        // (d) panel R_kj = X_kk^T A_kj, tiles dealt to the waves
+        for (int jb = kb + 1 + wv; jb < NB; jb += 4) {
             Mf::acc c = Mf::zero();
 #pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) c = Mf::mma(x[s4], M[(o + 4 * s4 + lr) * W + 16 * jb + lc], c);
+            for (int s4 = 0; s4 < 4; ++s4)
+                c = Mf::mma(XD[kb * 256 + s4 * 64 + l], M[(o + 4 * s4 + lr) * W + 16 * jb + lc], c);
 #pragma unroll
             for (int r = 0; r < 4; ++r) M[(o + lr + 4 * r) * W + 16 * jb + lc] = c[r];
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        // (e) trailing update A_ij -= R_ki^T R_kj, kb < i <= j
+        __syncthreads();
+        // (e) trailing update A_ij -= R_ki^T R_kj, kb < i <= j, tiles dealt to the waves
+        int tile = 0;
         for (int ib = kb + 1; ib < NB; ++ib)
-            for (int jb = ib; jb < NB; ++jb) {
+            for (int jb = ib; jb < NB; ++jb, ++tile) {
+                if (tile % 4 != wv) continue;
                 Mf::acc c;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) c[r] = M[(16 * ib + lr + 4 * r) * W + 16 * jb + lc];
@@ -909,25 +924,26 @@ __global__ __launch_bounds__(64) void k_chol_inv_blk(const double* __restrict__ 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) M[(16 * ib + lr + 4 * r) * W + 16 * jb + lc] = c[r];
             }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __syncthreads();
     }
-    if (l == 0) min_diag[step] = dmin;
-    if (fail) {
-        for (int idx = l; idx < ld * ld; idx += 64) { Rinv[idx] = 0.0; R[idx] = 0.0; }
-        if (l == 0) { state[2] = step; state[0] = 1; }
+    if (t == 0) min_diag[step] = dmin;
+    if (sfail) {
+        for (int idx = t; idx < ld * ld; idx += 256) { Rinv[idx] = 0.0; R[idx] = 0.0; }
+        if (t == 0) { state[2] = step; state[0] = 1; }
         return;
     }
-    // blocked inverse, block column by block column
-    for (int jb = 1; jb < NB; ++jb)
+    // blocked inverse: block columns are independent (wave w takes NB-1-w, NB-5-w, ...);
+    // within a column the tiles go upwards
+    for (int jb = NB - 1 - wv; jb >= 1; jb -= 4)
         for (int ib = jb - 1; ib >= 0; --ib) {
-            Mf::acc t = Mf::zero();
+            Mf::acc tv = Mf::zero();
             for (int kb = ib + 1; kb <= jb; ++kb) {
 #pragma unroll
                 for (int s4 = 0; s4 < 4; ++s4) {
                     const double av = M[(16 * ib + lc) * W + 16 * kb + 4 * s4 + lr];          // R_ik[lc][4s+lr]
                     const double bv = kb == jb ? XD[jb * 256 + s4 * 64 + l]                    // X_jj[4s+lr][lc]
                                                : M[(16 * jb + lc) * W + 16 * kb + 4 * s4 + lr];  // X_kj^T
-                    t = Mf::mma(av, bv, t);
+                    tv = Mf::mma(av, bv, tv);
                 }
             }
             Mf::acc c = Mf::zero();
@@ -935,30 +951,29 @@ __global__ __launch_bounds__(64) void k_chol_inv_blk(const double* __restrict__ 
             for (int s4 = 0; s4 < 4; ++s4) {
                 const int li = lc, lj = 4 * s4 + lr;                   // X_ii[lc][4s+lr]
                 const double av = XD[ib * 256 + (li >> 2) * 64 + 16 * (li & 3) + lj];
-                c = Mf::mma(-av, t[s4], c);
+                c = Mf::mma(-av, tv[s4], c);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) M[(16 * jb + lc) * W + 16 * ib + lr + 4 * r] = c[r];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-#pragma unroll 4
-    for (int i = 0; i < ld; ++i)
-        for (int j = l; j < ld; j += 64) {
-            double rv = 0.0, xv = 0.0;
-            if (i < b && j < b && j >= i) {
-                rv = M[i * W + j];
-                const int bi = i >> 4, bj = j >> 4;
-                if (bi == bj) {
-                    const int li = i & 15, lj = j & 15;
-                    xv = XD[bi * 256 + (li >> 2) * 64 + 16 * (li & 3) + lj];
-                } else {
-                    xv = M[j * W + i];
-                }
+    __syncthreads();
+    for (int idx = t; idx < ld * ld; idx += 256) {
+        const int i = idx / ld, j = idx % ld;
+        double rv = 0.0, xv = 0.0;
+        if (i < b && j < b && j >= i) {
+            rv = M[i * W + j];
+            const int bi = i >> 4, bj = j >> 4;
+            if (bi == bj) {
+                const int li = i & 15, lj = j & 15;
+                xv = XD[bi * 256 + (li >> 2) * 64 + 16 * (li & 3) + lj];
+            } else {
+                xv = M[j * W + i];
             }
-            R[(int64_t)i * ld + j] = rv;
-            Rinv[(int64_t)i * ld + j] = xv;
         }
+        R[idx] = rv;
+        Rinv[idx] = xv;
+    }
 }
 
 // General-size fallback (global-memory working set).
@@ -1224,12 +1239,33 @@ void update_one(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, 
 }
 
 template <typename T>
+static void update_staged(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, int nprod, const T* st,
+                          int64_t Np, int ld, const int* state, hipStream_t s);
+
+template <typename T>
 void update_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, int nprod, const double* S,
                    int64_t sstride, bool trans, double scale, int64_t Np, int ld, void* stage, const int* state,
                    hipStream_t s) {
     T* st = static_cast<T*>(stage);
     const int64_t cnt = (int64_t)nprod * ld * ld;
     k_stage_s<T><<<grid_for(cnt, 256), 256, 0, s>>>(S, sstride, nprod, ld, trans ? 1 : 0, scale, st);
+    update_staged<T>(OUT, IN, alpha, X, xstride, nprod, st, Np, ld, state, s);
+}
+
+template <typename T>
+void update2_launch(T* OUT, const T* IN, double alpha, const T* X0, const double* S0, bool trans0, const T* X1,
+                    const double* S1, bool trans1, double scale, int64_t Np, int ld, void* stage, const int* state,
+                    hipStream_t s) {
+    T* st = static_cast<T*>(stage);
+    const int64_t mat = (int64_t)ld * ld;
+    k_stage_s<T><<<grid_for(mat, 256), 256, 0, s>>>(S0, 0, 1, ld, trans0 ? 1 : 0, scale, st);
+    k_stage_s<T><<<grid_for(mat, 256), 256, 0, s>>>(S1, 0, 1, ld, trans1 ? 1 : 0, scale, st + mat);
+    update_staged<T>(OUT, IN, alpha, X0, X1 - X0, 2, st, Np, ld, state, s);
+}
+
+template <typename T>
+static void update_staged(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, int nprod, const T* st,
+                          int64_t Np, int ld, const int* state, hipStream_t s) {
     const int nt = ld / 16;
     // fewer than ~4 row workgroups per CU: split the columns in two blocks for parallelism
     const bool few = Np / (sizeof(T) == 4 ? 128 : 64) < 1024;
@@ -1363,7 +1399,7 @@ void chol_inv_launch(const double* G, int b, int ld, const double* tau, double* 
         const int nb = (b + 15) / 16;
         const size_t lds = sizeof(double) * ((size_t)16 * nb * (16 * nb + 1) + 256 * (size_t)nb);
         switch (nb) {
-#define CSS_CHOL(NB) case NB: k_chol_inv_blk<NB><<<1, 64, lds, s>>>(G, b, ld, tau, R, Rinv, state, step, min_diag); return;
+#define CSS_CHOL(NB) case NB: k_chol_inv_blk<NB><<<1, 256, lds, s>>>(G, b, ld, tau, R, Rinv, state, step, min_diag); return;
             CSS_CHOL(1) CSS_CHOL(2) CSS_CHOL(3) CSS_CHOL(4) CSS_CHOL(5) CSS_CHOL(6) CSS_CHOL(7) CSS_CHOL(8)
 #undef CSS_CHOL
             default: break;
@@ -1400,5 +1436,10 @@ template void update_launch<double>(double*, const double*, double, const double
                                     int64_t, bool, double, int64_t, int, void*, const int*, hipStream_t);
 template void update_launch<float>(float*, const float*, double, const float*, int64_t, int, const double*,
                                    int64_t, bool, double, int64_t, int, void*, const int*, hipStream_t);
+template void update2_launch<double>(double*, const double*, double, const double*, const double*, bool,
+                                     const double*, const double*, bool, double, int64_t, int, void*, const int*,
+                                     hipStream_t);
+template void update2_launch<float>(float*, const float*, double, const float*, const double*, bool, const float*,
+                                    const double*, bool, double, int64_t, int, void*, const int*, hipStream_t);
 
 }  // namespace css

@@ -171,8 +171,11 @@ struct Step {
         double* Apre = bf.Apre + j * mat();
         if (!launch_spmm_t<T>(H, bf, Qj, W, ld, s)) return false;
         if (!replay) gram(Qj, 0, 1, W, Apre, 0, false, 1);                    // A_j = sym(Q_j^T W)
-        update(W, W, 1.0, Qj, 0, 1, Apre, 0, false, -1.0);                    // W -= Q_j A_j
-        if (j > 0) update(W, W, 1.0, q(j - 1), 0, 1, bf.B + (j - 1) * mat(), 0, true, -1.0);  // W -= Q_{j-1} B^T
+        if (j > 0)                                                           // W -= Q_j A_j + Q_{j-1} B^T
+            update2_launch<T>(W, W, 1.0, Qj, Apre, false, q(j - 1), bf.B + (j - 1) * mat(), true, -1.0, p.Np, p.ld,
+                              bf.stage, bf.state, s);
+        else
+            update(W, W, 1.0, Qj, 0, 1, Apre, 0, false, -1.0);                // W -= Q_j A_j
         if (!replay) k_copy_small_full<<<grid_for(mat(), 256), 256, 0, s>>>(Apre, Aj, mat(), bf.state);
         if (p.reorth == 1 || (p.reorth == 2 && p.twopass)) {
             // local: coefficients against Q_{j-1} and Q_j, one block at a time
