@@ -510,7 +510,8 @@ __global__ __launch_bounds__(256) void k_update_split(float* OUT, const float* I
 // each tile a, for Y the column 16 b + l%16 of each of its tiles b. Operands are
 // fetched one step ahead (the chunk's steps per wave are even, see
 // gram_plan_split). The row groups' tiles are added in LDS in group order and
-// written as one partial, as in k_gram.
+// written as one partial, as in k_gram. The product is the fastest grid index, so
+// the workgroups that read the same Y rows run at the same time (L2 / MALL hits).
 template <int NPL>
 __device__ __forceinline__ void split_planes(const float (&x)[8], bf16x8 (&pl)[NPL]) {
 #pragma unroll
@@ -536,7 +537,7 @@ __global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ X,
     float* buf = reinterpret_cast<float*>(gram_lds);
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, lr = l >> 4, lc = l & 15;
     const int grp = w / NH, h = w % NH;
-    const int chunk = blockIdx.x, p = blockIdx.z;
+    const int p = blockIdx.x, chunk = blockIdx.y;         // products of a chunk run together: Y rows reused
     const int64_t r0 = (int64_t)chunk * rpc;
     const int64_t r1 = r0 + rpc < Np ? r0 + rpc : Np;
     const int nst = (int)((r1 - r0) / (32 * KG));         // steps of this wave (even)
@@ -1353,7 +1354,7 @@ template <int NT>
 static void gram_split_one(const GramPlan& g, const float* X, int64_t xstride, const float* Y, float* part,
                            const int* state, hipStream_t s) {
     constexpr int NH = (NT % 2 == 0 && NT >= 4) ? 2 : 1;
-    dim3 grid(g.nchunk, 1, g.nprod);
+    dim3 grid(g.nprod, g.nchunk);
     const size_t lds = sizeof(float) * 256 * NT * NT;
     k_gram_split<NT, NH, 3><<<grid, 256, lds, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, part, g.nchunk,
                                                     state);
