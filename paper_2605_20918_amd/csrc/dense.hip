@@ -347,15 +347,6 @@ __global__ __launch_bounds__(256) void k_update(T* OUT, const T* IN, double alph
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kSplitK = 32;
 
-// Work-group barrier that orders LDS accesses only: the LDS writes before it are
-// complete (release at work-group scope, LDS only) when the waves meet, and the
-// empty asm keeps the compiler from moving memory accesses across it. Global loads
-// in flight (the prefetched X chunks) stay in flight.
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
 
 __device__ __forceinline__ void split_bf16(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
 #pragma unroll

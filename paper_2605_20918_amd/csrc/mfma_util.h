@@ -1,4 +1,5 @@
-// Internal: MFMA 16x16x4 operand helpers shared by the dense block and SpMM kernels.
+// Internal: MFMA 16x16x4 operand helpers shared by the dense block and SpMM kernels,
+// and an LDS-only work-group barrier.
 //
 // MFMA 16x16x4 layout (gfx950, FP32 and FP64): lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; result register r of lane l holds D[4(l/16)+r][l%16] (FP32) or
@@ -37,6 +38,16 @@ struct Mfma<float> {
     __device__ static acc mma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
     __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
 };
+
+// Work-group barrier that orders LDS accesses only: the LDS writes before it are
+// complete (release at work-group scope, LDS only) when the waves meet, and the
+// empty asm keeps the compiler from moving memory accesses across it. Global loads
+// in flight (the prefetched X chunks) stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
 
 template <typename T, int Q>
 __device__ inline void load_q(const T* p, T (&o)[Q]) {

@@ -35,6 +35,7 @@
 #include <vector>
 
 #include "css_common.h"
+#include "mfma_util.h"
 #include "subspace.h"
 
 namespace css {
@@ -846,72 +847,89 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
         }
         __syncthreads();
     }
-    // forward sweep: Z_0 = S_0^-1 diag(sqrt(n_c)), Z_j = -G_j Z_{j-1}; W_p block j = weight_p Im Z_j
+    // Z_0 = S_0^-1 diag(sqrt(n_c)) into slot 0 of G (no G_0 exists) and W_p block 0 =
+    // weight_p Im Z_0; the forward sweep Z_j = -G_j Z_{j-1} is k_pole_forward
+    double* Zr0 = Gp;
+    double* Zi0 = Gp + nn;
     for (int e = tid; e < N * N; e += kBlkThreads) {
         const int r = e / N, c = e % N;
         const double sc = c < b ? sqrt((double)counts[c]) : 0.0;
-        Sr[r * SW + c] *= sc;
-        Si[r * SW + c] *= sc;
-        if (r < b && c < b) Wp[r * b + c] = wgt * Si[r * SW + c];
+        const double zr = Sr[r * SW + c] * sc, zi = Si[r * SW + c] * sc;
+        Zr0[e] = zr;
+        Zi0[e] = zi;
+        if (r < b && c < b) Wp[r * b + c] = wgt * zi;
+    }
+}
+
+// Forward sweep of the block solve: Z_j = -G_j Z_{j-1}, W_p block j = weight_p Im Z_j,
+// for j = 1 .. v-1. The columns of Z are independent, so workgroup (p, slab) follows
+// the 16 CT columns 16 CT slab .. of pole p on its own: the slab of Z_{j-1} is in LDS
+// (double buffered, one barrier per step), wave w computes rows 16 w .. +15 of Z_j
+// (CT column tiles, so that each G_j row read serves CT tiles) with the rows of G_j
+// (complex, global) of the next step already in flight.
+template <int NB, int CT>
+__global__ __launch_bounds__(64 * NB) void k_pole_forward(int v, int b, const double* __restrict__ weight,
+                                                          const double* __restrict__ Gbuf,
+                                                          double* __restrict__ Wout) {
+    constexpr int N = 16 * NB, KS = N / 4, SC = 16 * CT;
+    __shared__ double zb[2][2][N * SC];                   // [buffer][re, im][k * SC + column]
+    const int p = blockIdx.x, c0 = SC * blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane >> 4, lc = lane & 15;
+    const int64_t nn = (int64_t)N * N;
+    const double wgt = weight[p];
+    const double* Gp = Gbuf + (int64_t)p * v * 2 * nn;
+    double* Wp = Wout + (int64_t)p * v * b * b;
+    for (int e = threadIdx.x; e < N * SC; e += 64 * NB) {
+        const int k = e / SC, c = e % SC;
+        zb[0][0][e] = Gp[(int64_t)k * N + c0 + c];
+        zb[0][1][e] = Gp[nn + (int64_t)k * N + c0 + c];
     }
     __syncthreads();
-    for (int j = 1; j < v; ++j) {
-        const double* Gr = Gp + (int64_t)j * 2 * nn;
-        const double* Gi = Gr + nn;
-        // an opaque zero keeps the per-tile LDS addresses from being hoisted out of this
-        // loop (they would exceed the register budget and be spilled)
-        int zoff = 0;
-        asm volatile("" : "+v"(zoff));
-        double* Sr = lds + zoff;
-        double* Si = lds + zoff + N * SW;
-        pd4 nr[MAXQ], ni[MAXQ];
+    const int m0 = 16 * wave;
+    auto load_g = [&](int j, double (&g)[2][KS]) {
+        const double* Gr = Gp + (int64_t)min(j, v - 1) * 2 * nn + (int64_t)(m0 + lc) * N + lr;
 #pragma unroll
-        for (int q = 0; q < MAXQ; ++q) {
-            const int t = wave + kBlkWaves * q;
-            nr[q] = pd4{0, 0, 0, 0};
-            ni[q] = pd4{0, 0, 0, 0};
-            if (t >= NTL) continue;
-            const int m0 = (t / NB) * 16, c0 = (t % NB) * 16;
-            constexpr int H = 8, NH = (N / 4 + H - 1) / H;      // K in chunks of 8 steps of global operands
+        for (int s4 = 0; s4 < KS; ++s4) {
+            g[0][s4] = Gr[4 * s4];
+            g[1][s4] = Gr[nn + 4 * s4];
+        }
+    };
+    auto step = [&](int j, const double (&g)[2][KS]) {
+        const int cur = (j - 1) & 1;
+        pd4 nr[CT], ni[CT];
 #pragma unroll
-            for (int h = 0; h < NH; ++h) {
-                double g_r[H], g_i[H];
+        for (int t = 0; t < CT; ++t) nr[t] = ni[t] = pd4{0, 0, 0, 0};
 #pragma unroll
-                for (int qq = 0; qq < H; ++qq) {
-                    const int s4 = h * H + qq;
-                    const bool in = s4 < N / 4;
-                    g_r[qq] = in ? Gr[(m0 + lc) * N + 4 * s4 + lr] : 0.0;
-                    g_i[qq] = in ? Gi[(m0 + lc) * N + 4 * s4 + lr] : 0.0;
-                }
+        for (int s4 = 0; s4 < KS; ++s4) {
+            const int k = 4 * s4 + lr;
 #pragma unroll
-                for (int qq = 0; qq < H; ++qq) {
-                    const int s4 = h * H + qq;
-                    if (s4 >= N / 4) break;
-                    const int k = 4 * s4 + lr;
-                    const double zr = Sr[k * SW + c0 + lc], zi = Si[k * SW + c0 + lc];
-                    nr[q] = mfma64(g_r[qq], zr, nr[q]);
-                    nr[q] = mfma64(-g_i[qq], zi, nr[q]);
-                    ni[q] = mfma64(g_r[qq], zi, ni[q]);
-                    ni[q] = mfma64(g_i[qq], zr, ni[q]);
-                }
-                __builtin_amdgcn_sched_barrier(0);
+            for (int t = 0; t < CT; ++t) {
+                const double zr = zb[cur][0][k * SC + 16 * t + lc], zi = zb[cur][1][k * SC + 16 * t + lc];
+                nr[t] = mfma64(g[0][s4], zr, nr[t]);
+                nr[t] = mfma64(-g[1][s4], zi, nr[t]);
+                ni[t] = mfma64(g[0][s4], zi, ni[t]);
+                ni[t] = mfma64(g[1][s4], zr, ni[t]);
             }
         }
-        __syncthreads();
 #pragma unroll
-        for (int q = 0; q < MAXQ; ++q) {
-            const int t = wave + kBlkWaves * q;
-            if (t >= NTL) continue;
-            const int m0 = (t / NB) * 16, c0 = (t % NB) * 16;
+        for (int t = 0; t < CT; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = m0 + lr + 4 * r, col = c0 + lc;
-                Sr[row * SW + col] = -nr[q][r];
-                Si[row * SW + col] = -ni[q][r];
-                if (row < b && col < b) Wp[(int64_t)j * b * b + row * b + col] = -wgt * ni[q][r];
+                const int row = m0 + lr + 4 * r, col = c0 + 16 * t + lc;
+                zb[cur ^ 1][0][row * SC + 16 * t + lc] = -nr[t][r];
+                zb[cur ^ 1][1][row * SC + 16 * t + lc] = -ni[t][r];
+                if (row < b && col < b) Wp[(int64_t)j * b * b + row * b + col] = -wgt * ni[t][r];
             }
-        }
-        __syncthreads();
+        lds_barrier();                                    // Z_j complete; Z_{j-1} no longer read
+    };
+    double ga[2][KS], gb[2][KS];
+    load_g(1, ga);
+    for (int j = 1; j < v; j += 2) {
+        load_g(j + 1, gb);                                // clamped: the last step again at the end
+        step(j, ga);
+        if (j + 1 >= v) break;
+        load_g(j + 2, ga);
+        step(j + 1, gb);
     }
 }
 
@@ -1028,7 +1046,8 @@ css_status subspace_fermi_poles(const double* A, const double* B, int v, int b, 
     CSS_HIP_TRY(hipMemcpyAsync(kap, pt.kappa.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
     CSS_HIP_TRY(hipMemcpyAsync(wgt, pt.weight.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
     const size_t blk_lds = pole_blk_lds_bytes(nb16);
-    if (b <= 96 && ld == 16 * nb16 && blk_lds <= (size_t)max_lds()) {
+    const bool used_blk = b <= 96 && ld == 16 * nb16 && blk_lds <= (size_t)max_lds();
+    if (used_blk) {
         switch (nb16) {
 #define CSS_POLE(NB)                                                                                              \
     case NB:                                                                                                      \
@@ -1046,6 +1065,15 @@ css_status subspace_fermi_poles(const double* A, const double* B, int v, int b, 
         k_pole_solve_generic<<<np, kPoleThreads, use_lds ? lds_bytes : 0, s>>>(A, B, v, b, ld, mu, 1.0 / (2.0 * kT),
                                                                                 kap, wgt, counts, Gbuf, Sg,
                                                                                 use_lds ? 1 : 0, Wout);
+    if (used_blk && v > 1) {
+        switch (nb16) {
+#define CSS_FWD(NB, CT) \
+    case NB: k_pole_forward<NB, CT><<<dim3(np, NB / CT), 64 * NB, 0, s>>>(v, b, wgt, Gbuf, Wout); break;
+            CSS_FWD(1, 1) CSS_FWD(2, 2) CSS_FWD(3, 1) CSS_FWD(4, 2) CSS_FWD(5, 1) CSS_FWD(6, 2)
+#undef CSS_FWD
+            default: break;
+        }
+    }
     k_pole_sum<<<grid_for((int64_t)nT * b, 256), 256, 0, s>>>(Wout, np, (int64_t)nT * b, b, counts, g, F);
     k_krylov_sums<<<1, kKsThreads, 0, s>>>(A, B, F, counts, v, b, ld, sums);     // b <= 128 checked above
     if (npoles_out) *npoles_out = np;
