@@ -43,14 +43,15 @@ void update2_launch(T* OUT, const T* IN, double alpha, const T* X0, const double
                     const double* S1, bool trans1, double scale, int64_t Np, int ld, void* stage, const int* state,
                     hipStream_t s);
 
-// Gram X_p^T Y (p < nprod, X_p = X + p xstride) for the full reorthogonalisation
-// coefficients, mode as gram_launch, partial capacity cap_mats ld x ld matrices.
-// FP32 blocks with ld a multiple of 16 up to 96: BF16 MFMA with three-part operand
-// splits (per term no less accurate than the FP32 product); otherwise gram_launch.
+// Gram X_p^T Y (p < nprod, X_p = X + p xstride), mode as gram_launch, partial
+// capacity cap_mats ld x ld FP64 matrices. FP32 blocks with ld a multiple of 16 up
+// to 96: BF16 MFMA with three-part operand splits (each term no less accurate than
+// the FP32 product; the whole tile is computed and sym is not used there);
+// otherwise gram_plan + gram_launch.
 template <typename T>
-void gram_correction_launch(const T* X, int64_t xstride, int nprod, const T* Y, int64_t Np, int ld,
-                            int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
-                            const int* state, hipStream_t s);
+void gram_blocks_launch(const T* X, int64_t xstride, int nprod, const T* Y, int64_t Np, int ld, bool sym,
+                        int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
+                        const int* state, hipStream_t s);
 
 // update_launch for coefficient blocks S_p that are small corrections (full
 // reorthogonalisation after the three-term update). FP32 blocks with ld a multiple

@@ -1352,11 +1352,11 @@ static void gram_split_one(const GramPlan& g, const float* X, int64_t xstride, c
 }
 
 template <>
-void gram_correction_launch<float>(const float* X, int64_t xstride, int nprod, const float* Y, int64_t Np, int ld,
-                                   int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
-                                   const int* state, hipStream_t s) {
+void gram_blocks_launch<float>(const float* X, int64_t xstride, int nprod, const float* Y, int64_t Np, int ld, bool sym,
+                               int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
+                               const int* state, hipStream_t s) {
     if (ld % 16 != 0 || ld > 96 || Np % 256 != 0) {
-        const GramPlan g = gram_plan(Np, ld, nprod, false, cap_mats, 4);
+        const GramPlan g = gram_plan(Np, ld, nprod, sym, cap_mats, 4);
         gram_launch<float>(g, X, xstride, Y, partial, out, out_stride, mode, state, s);
         return;
     }
@@ -1376,10 +1376,10 @@ void gram_correction_launch<float>(const float* X, int64_t xstride, int nprod, c
 }
 
 template <>
-void gram_correction_launch<double>(const double* X, int64_t xstride, int nprod, const double* Y, int64_t Np, int ld,
-                                    int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
-                                    const int* state, hipStream_t s) {
-    const GramPlan g = gram_plan(Np, ld, nprod, false, cap_mats, 8);
+void gram_blocks_launch<double>(const double* X, int64_t xstride, int nprod, const double* Y, int64_t Np, int ld,
+                                bool sym, int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
+                                const int* state, hipStream_t s) {
+    const GramPlan g = gram_plan(Np, ld, nprod, sym, cap_mats, 8);
     gram_launch<double>(g, X, xstride, Y, partial, out, out_stride, mode, state, s);
 }
 

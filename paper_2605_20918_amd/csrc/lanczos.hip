@@ -151,8 +151,8 @@ struct Step {
 
     void gram(const T* X, int64_t xstride, int nprod, const T* Y, double* out, int64_t out_stride, bool sym,
               int mode) const {
-        GramPlan g = gram_plan(p.Np, p.ld, nprod, sym, p.partial_mats, (int)sizeof(T));
-        gram_launch<T>(g, X, xstride, Y, bf.partial, out, out_stride, mode, bf.state, s);
+        gram_blocks_launch<T>(X, xstride, nprod, Y, p.Np, p.ld, sym, p.partial_mats, bf.partial, out, out_stride, mode,
+                              bf.state, s);
     }
     void update(T* out, const T* in, double alpha, const T* X, int64_t xstride, int nprod, const double* S,
                 int64_t sstride, bool trans, double scale) const {
@@ -192,8 +192,7 @@ struct Step {
             const int cap = (int)std::max<int64_t>(1, p.partial_mats);
             for (int t0 = 0; t0 < np; t0 += cap) {
                 const int cnt = std::min(cap, np - t0);
-                gram_correction_launch<T>(q(t0), tall(), cnt, W, p.Np, p.ld, p.partial_mats, bf.partial,
-                                          bf.C + t0 * mat(), mat(), 0, bf.state, s);
+                gram(q(t0), tall(), cnt, W, bf.C + t0 * mat(), mat(), false, 0);
             }
             update_correction_launch<T>(W, W, 1.0, q(0), tall(), np, bf.C, mat(), false, -1.0, p.Np, p.ld,
                                         bf.stage, bf.state, s);
