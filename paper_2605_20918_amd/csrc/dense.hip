@@ -348,12 +348,38 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kSplitK = 32;
 
 
-__device__ __forceinline__ void split_bf16(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
+// Splits of 8 floats into NPL BF16 parts, x = x_0 + .. + x_{NPL-1},
+// x_i = RNE(x - x_0 - .. - x_{i-1}), two elements at a time: one packed conversion,
+// the parts back to FP32 by shifts (exact), one subtraction each.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+template <int NPL>
+__device__ __forceinline__ void split_planes(const float (&x)[8], bf16x8 (&pl)[NPL]) {
+    unsigned w[NPL][4];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        hi[e] = static_cast<__bf16>(x[e]);
-        lo[e] = static_cast<__bf16>(x[e] - static_cast<float>(hi[e]));
+    for (int i = 0; i < 4; ++i) {
+        f32x2 r = {x[2 * i], x[2 * i + 1]};
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) {
+            const unsigned bits = __builtin_bit_cast(unsigned, __builtin_convertvector(r, bf16x2));
+            w[k][i] = bits;
+            if (k + 1 < NPL) {
+                const f32x2 back = {__uint_as_float(bits << 16), __uint_as_float(bits & 0xffff0000u)};
+                r = r - back;
+            }
+        }
     }
+#pragma unroll
+    for (int k = 0; k < NPL; ++k) pl[k] = __builtin_bit_cast(bf16x8, u32x4{w[k][0], w[k][1], w[k][2], w[k][3]});
+}
+
+__device__ __forceinline__ void split_bf16(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
+    bf16x8 pl[2];
+    split_planes<2>(x, pl);
+    hi = pl[0];
+    lo = pl[1];
 }
 
 // B fragments of S'_p = scale * (trans ? S_p^T : S_p), rounded to FP32 and split:
@@ -503,19 +529,6 @@ __global__ __launch_bounds__(256) void k_update_split(float* OUT, const float* I
 // gram_plan_split). The row groups' tiles are added in LDS in group order and
 // written as one partial, as in k_gram. The product is the fastest grid index, so
 // the workgroups that read the same Y rows run at the same time (L2 / MALL hits).
-template <int NPL>
-__device__ __forceinline__ void split_planes(const float (&x)[8], bf16x8 (&pl)[NPL]) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        float r = x[e];
-#pragma unroll
-        for (int q = 0; q < NPL; ++q) {
-            pl[q][e] = static_cast<__bf16>(r);
-            if (q + 1 < NPL) r -= static_cast<float>(pl[q][e]);
-        }
-    }
-}
-
 template <int NT, int NH, int NPL>
 __global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ X, int64_t xstride,
                                                     const float* __restrict__ Y, int64_t Np, int64_t rpc, int ld,
