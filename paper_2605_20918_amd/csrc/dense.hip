@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <atomic>
 #include <cmath>
 
@@ -511,6 +512,28 @@ __global__ __launch_bounds__(256) void k_update_split(float* OUT, const float* I
             }
 }
 
+// Y (Np x ld FP32, Np a multiple of 8) split into NPL BF16 planes in the operand
+// layout of the 16x16x32 MFMA: plane q, 8-row group r8, column c holds the 8 parts
+// of Y[8 r8 .. 8 r8 + 7][c] (16 bytes) at q (Np / 8) ld + r8 ld + c. One thread per
+// (r8, c); the parts are those of split_planes.
+template <int NPL>
+__global__ __launch_bounds__(256) void k_split_rows8(const float* __restrict__ Y, int64_t Np, int ld,
+                                                     bf16x8* __restrict__ P, const int* __restrict__ state) {
+    if (state && state[0]) return;
+    const int64_t cnt = (Np / 8) * ld;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= cnt) return;
+    const int64_t r8 = i / ld;
+    const int c = (int)(i % ld);
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = Y[(8 * r8 + e) * ld + c];
+    bf16x8 pl[NPL];
+    split_planes<NPL>(v, pl);
+#pragma unroll
+    for (int q = 0; q < NPL; ++q) P[q * cnt + i] = pl[q];
+}
+
 // ------------------------------------------------------------------ BF16 Gram
 //
 // X_p^T Y for FP32 blocks on the 16x16x32 BF16 MFMA, with every factor split
@@ -529,11 +552,12 @@ __global__ __launch_bounds__(256) void k_update_split(float* OUT, const float* I
 // gram_plan_split). The row groups' tiles are added in LDS in group order and
 // written as one partial, as in k_gram. The product is the fastest grid index, so
 // the workgroups that read the same Y rows run at the same time (L2 / MALL hits).
-template <int NT, int NH, int NPL>
+// YP: Y given as its NPL BF16 planes (k_split_rows8), loaded as ready operands.
+template <int NT, int NH, int NPL, bool YP>
 __global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ X, int64_t xstride,
-                                                    const float* __restrict__ Y, int64_t Np, int64_t rpc, int ld,
-                                                    float* __restrict__ partial, int nchunk,
-                                                    const int* __restrict__ state) {
+                                                    const float* __restrict__ Y, const bf16x8* __restrict__ Yp,
+                                                    int64_t Np, int64_t rpc, int ld, float* __restrict__ partial,
+                                                    int nchunk, const int* __restrict__ state) {
     if (state && state[0]) return;
     constexpr int TILE = 16 * NT, NB = NT / NH, KG = 4 / NH;
     static_assert(NT % NH == 0 && (NH == 1 || NH == 2), "column parts");
@@ -553,45 +577,82 @@ __global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ X,
     const int64_t step = 32 * KG * (int64_t)ld;
     const float* xa = X + (int64_t)p * xstride + (r0 + 32 * grp + 8 * lr) * ld;
     const float* ya = Y + (r0 + 32 * grp + 8 * lr) * ld + 16 * NB * h + lc;
-    auto fetch = [&](int st, float (&x)[8][NT], float (&y)[8][NB]) {
+    // plane layout: plane q, 8-row group r8, column c at q (Np / 8) ld + r8 ld + c
+    const int64_t pstride = (Np / 8) * ld;
+    const bf16x8* ypa = Yp + ((r0 + 32 * grp + 8 * lr) / 8) * ld + 16 * NB * h + lc;
+    typedef typename std::conditional<YP, bf16x8[NB][NPL], float[8][NB]>::type YBuf;
+    auto fetch = [&](int st, float (&x)[8][NT], YBuf& y) {
         const int64_t o = (int64_t)st * step;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            load_run<float, NT>(xa + o + (int64_t)e * ld, lc, x[e]);
+        for (int e = 0; e < 8; ++e) load_run<float, NT>(xa + o + (int64_t)e * ld, lc, x[e]);
+        if constexpr (YP) {
+            const int64_t o8 = (int64_t)st * (4 * KG) * ld;
 #pragma unroll
-            for (int b = 0; b < NB; ++b) y[e][b] = ya[o + (int64_t)e * ld + 16 * b];
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int q = 0; q < NPL; ++q) y[b][q] = ypa[q * pstride + o8 + 16 * b];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) y[e][b] = ya[o + (int64_t)e * ld + 16 * b];
         }
     };
-    auto compute = [&](const float (&x)[8][NT], const float (&y)[8][NB]) {
+    // The split of tile a + 1 is issued between the MFMAs of tile a: with one wave
+    // per SIMD the VALU work then runs while the matrix core is busy instead of
+    // after it (an MFMA blocks the wave's next MFMA, not its VALU instructions).
+    auto compute = [&](const float (&x)[8][NT], const YBuf& y) {
         bf16x8 yb[NB][NPL];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
+            if constexpr (YP) {
+#pragma unroll
+                for (int q = 0; q < NPL; ++q) yb[b][q] = y[b][q];
+            } else {
+                float v[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = y[e][b];
+                split_planes<NPL>(v, yb[b]);
+            }
+        }
+        bf16x8 xb[2][NPL];
+        {
             float v[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = y[e][b];
-            split_planes<NPL>(v, yb[b]);
+            for (int e = 0; e < 8; ++e) v[e] = x[e][0];
+            split_planes<NPL>(v, xb[0]);
         }
 #pragma unroll
         for (int a = 0; a < NT; ++a) {
-            float v[8];
+            const bf16x8 (&xc)[NPL] = xb[a & 1];
+            if (a + 1 < NT) {
+                float v[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = x[e][a];
-            bf16x8 xb[NPL];
-            split_planes<NPL>(v, xb);
+                for (int e = 0; e < 8; ++e) v[e] = x[e][a + 1];
+                split_planes<NPL>(v, xb[(a + 1) & 1]);
+            }
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 if constexpr (NPL == 3) {
-                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[2], yb[b][0], c[a][b], 0, 0, 0);
-                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[1], yb[b][1], c[a][b], 0, 0, 0);
-                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[0], yb[b][2], c[a][b], 0, 0, 0);
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[2], yb[b][0], c[a][b], 0, 0, 0);
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[1], yb[b][1], c[a][b], 0, 0, 0);
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[0], yb[b][2], c[a][b], 0, 0, 0);
                 }
-                c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[1], yb[b][0], c[a][b], 0, 0, 0);
-                c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[0], yb[b][1], c[a][b], 0, 0, 0);
-                c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xb[0], yb[b][0], c[a][b], 0, 0, 0);
+                c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[1], yb[b][0], c[a][b], 0, 0, 0);
+                c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[0], yb[b][1], c[a][b], 0, 0, 0);
+                c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[0], yb[b][0], c[a][b], 0, 0, 0);
+            }
+            if (a + 1 < NT) {
+#pragma unroll
+                for (int q = 0; q < NB * (2 * NPL); ++q) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // one MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);    // then up to three VALU
+                }
             }
         }
     };
-    float x0[8][NT], x1[8][NT], y0[8][NB], y1[8][NB];
+    float x0[8][NT], x1[8][NT];
+    YBuf y0, y1;
     if (nst > 0) fetch(0, x0, y0);
     for (int st = 0; st < nst; st += 2) {
         fetch(st + 1, x1, y1);                            // nst is even
@@ -1355,19 +1416,23 @@ GramPlan gram_plan_split(int64_t Np, int ld, int nprod, int64_t cap_mats) {
 }
 
 template <int NT>
-static void gram_split_one(const GramPlan& g, const float* X, int64_t xstride, const float* Y, float* part,
-                           const int* state, hipStream_t s) {
+static void gram_split_one(const GramPlan& g, const float* X, int64_t xstride, const float* Y, const bf16x8* Yp,
+                           float* part, const int* state, hipStream_t s) {
     constexpr int NH = (NT % 2 == 0 && NT >= 4) ? 2 : 1;
     dim3 grid(g.nprod, g.nchunk);
     const size_t lds = sizeof(float) * 256 * NT * NT;
-    k_gram_split<NT, NH, 3><<<grid, 256, lds, s>>>(X, xstride, Y, g.Np, g.rows_per_chunk, g.ld, part, g.nchunk,
-                                                    state);
+    if (Yp)
+        k_gram_split<NT, NH, 3, true><<<grid, 256, lds, s>>>(X, xstride, Y, Yp, g.Np, g.rows_per_chunk, g.ld, part,
+                                                             g.nchunk, state);
+    else
+        k_gram_split<NT, NH, 3, false><<<grid, 256, lds, s>>>(X, xstride, Y, Yp, g.Np, g.rows_per_chunk, g.ld, part,
+                                                              g.nchunk, state);
 }
 
 template <>
 void gram_blocks_launch<float>(const float* X, int64_t xstride, int nprod, const float* Y, int64_t Np, int ld, bool sym,
                                int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
-                               const int* state, hipStream_t s) {
+                               const int* state, hipStream_t s, void* yplanes) {
     if (ld % 16 != 0 || ld > 96 || Np % 256 != 0) {
         const GramPlan g = gram_plan(Np, ld, nprod, sym, cap_mats, 4);
         gram_launch<float>(g, X, xstride, Y, partial, out, out_stride, mode, state, s);
@@ -1376,13 +1441,19 @@ void gram_blocks_launch<float>(const float* X, int64_t xstride, int nprod, const
     // the partials are FP32: the buffer (cap_mats FP64 matrices) holds twice as many
     const GramPlan g = gram_plan_split(Np, ld, nprod, 2 * cap_mats);
     float* part = reinterpret_cast<float*>(partial);
+    // several products share Y: split it once into planes instead of once per product
+    bf16x8* Yp = nullptr;
+    if (yplanes && nprod > 1) {
+        Yp = static_cast<bf16x8*>(yplanes);
+        k_split_rows8<3><<<grid_for((Np / 8) * ld, 256), 256, 0, s>>>(Y, Np, ld, Yp, state);
+    }
     switch (ld / 16) {
-        case 1: gram_split_one<1>(g, X, xstride, Y, part, state, s); break;
-        case 2: gram_split_one<2>(g, X, xstride, Y, part, state, s); break;
-        case 3: gram_split_one<3>(g, X, xstride, Y, part, state, s); break;
-        case 4: gram_split_one<4>(g, X, xstride, Y, part, state, s); break;
-        case 5: gram_split_one<5>(g, X, xstride, Y, part, state, s); break;
-        default: gram_split_one<6>(g, X, xstride, Y, part, state, s); break;
+        case 1: gram_split_one<1>(g, X, xstride, Y, Yp, part, state, s); break;
+        case 2: gram_split_one<2>(g, X, xstride, Y, Yp, part, state, s); break;
+        case 3: gram_split_one<3>(g, X, xstride, Y, Yp, part, state, s); break;
+        case 4: gram_split_one<4>(g, X, xstride, Y, Yp, part, state, s); break;
+        case 5: gram_split_one<5>(g, X, xstride, Y, Yp, part, state, s); break;
+        default: gram_split_one<6>(g, X, xstride, Y, Yp, part, state, s); break;
     }
     dim3 rgrid(grid_for((int64_t)ld * ld, 64), nprod);
     k_gram_reduce<float><<<rgrid, 64 * kRedGroups, 0, s>>>(part, g.nchunk, ld, 0, mode, out, out_stride, state);
@@ -1391,7 +1462,7 @@ void gram_blocks_launch<float>(const float* X, int64_t xstride, int nprod, const
 template <>
 void gram_blocks_launch<double>(const double* X, int64_t xstride, int nprod, const double* Y, int64_t Np, int ld,
                                 bool sym, int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
-                                const int* state, hipStream_t s) {
+                                const int* state, hipStream_t s, void*) {
     const GramPlan g = gram_plan(Np, ld, nprod, sym, cap_mats, 8);
     gram_launch<double>(g, X, xstride, Y, partial, out, out_stride, mode, state, s);
 }

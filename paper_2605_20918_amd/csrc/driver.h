@@ -30,6 +30,7 @@ struct LzBufs {
     void* basis = nullptr;    // nslots x Np x ld
     void* W = nullptr;
     void* Wt = nullptr;
+    void* yplanes = nullptr;  // 3 x Np x ld bf16 (FP32, full reorth): W split once for the batched Gram
     void* hval = nullptr;     // converted H values (or nullptr)
     double* A = nullptr;      // v_max x ld x ld (final A_j)
     double* Apre = nullptr;   // v_max x ld x ld (A_j as used in the three-term update)
