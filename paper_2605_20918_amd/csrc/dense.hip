@@ -1119,6 +1119,36 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, 
     }
 }
 
+// R = R2 R1 for upper triangular ld x ld R1, R2 (zero below the diagonal), ld = 16 NB,
+// on FP64 MFMA: workgroup ib, wave jb forms tile (ib, jb) from k in [16 ib, 16 jb + 16),
+// the only k where R2[i][k] R1[k][j] can be nonzero; tiles below the diagonal are zero.
+// All operands of a wave are loaded before its first MFMA.
+template <int NB>
+__global__ __launch_bounds__(64 * NB) void k_trmm_upper_mfma(const double* __restrict__ R2,
+                                                             const double* __restrict__ R1, double* __restrict__ R,
+                                                             const int* __restrict__ state) {
+    if (state && state[0]) return;
+    constexpr int ld = 16 * NB, MAXS = 4 * NB;
+    typedef MF<double> M;
+    const int ib = blockIdx.x, jb = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l >> 4, lc = l & 15;
+    typename M::acc c = M::zero();
+    if (jb >= ib) {
+        const int nst = 4 * (jb - ib + 1);
+        double a[MAXS], bv[MAXS];
+#pragma unroll
+        for (int s4 = 0; s4 < MAXS; ++s4) {
+            const int k = 16 * ib + 4 * s4 + lr;
+            a[s4] = s4 < nst ? R2[(16 * ib + lc) * ld + k] : 0.0;
+            bv[s4] = s4 < nst ? R1[k * ld + 16 * jb + lc] : 0.0;
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < MAXS; ++s4)
+            if (s4 < nst) c = M::mma(a[s4], bv[s4], c);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) R[(16 * ib + M::row(l, r)) * ld + 16 * jb + lc] = c[r];
+}
+
 __global__ void k_trmm_upper(const double* __restrict__ R2, const double* __restrict__ R1, double* __restrict__ R,
                              int ld, const int* __restrict__ state) {
     if (state && state[0]) return;
@@ -1487,6 +1517,14 @@ void chol_inv_launch(const double* G, int b, int ld, const double* tau, double* 
 }
 
 void trmm_upper_launch(const double* R2, const double* R1, double* R, int ld, const int* state, hipStream_t s) {
+    if (ld % 16 == 0 && ld <= 128) {
+        switch (ld / 16) {
+#define CSS_TRMM(NB) case NB: k_trmm_upper_mfma<NB><<<NB, 64 * NB, 0, s>>>(R2, R1, R, state); return;
+            CSS_TRMM(1) CSS_TRMM(2) CSS_TRMM(3) CSS_TRMM(4) CSS_TRMM(5) CSS_TRMM(6) CSS_TRMM(7) CSS_TRMM(8)
+#undef CSS_TRMM
+            default: break;
+        }
+    }
     k_trmm_upper<<<grid_for((int64_t)ld * ld, 256), 256, 0, s>>>(R2, R1, R, ld, state);
 }
 

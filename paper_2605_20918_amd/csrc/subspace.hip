@@ -778,7 +778,9 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
         double* Si = lds + zoff + N * SW;
         gj_inverse_blk<NB>(Sr, Si, Pr, Pi);
         if (j == 0) break;
-        // G_j = -i a S_j^-1 B_{j-1} (B zero beyond b)
+        // G_j = -i a S_j^-1 B_{j-1} (B zero beyond b). B_{j-1} is upper triangular
+        // (a Cholesky factor, or the product of two): column c has no entries below row
+        // c, so tile column c0 needs the chunks of k < c0 + 16 only.
         const double* Bm = B + (int64_t)(j - 1) * mat;
         double* Gr = Gp + (int64_t)j * 2 * nn;
         double* Gi = Gr + nn;
@@ -786,8 +788,10 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
             const int m0 = (t / NB) * 16, c0 = (t % NB) * 16;
             pd4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
             constexpr int H = 8, NH = (N / 4 + H - 1) / H;      // K in chunks of 8 steps of global operands
+            const int hmax = (c0 + 16 + 4 * H - 1) / (4 * H);
 #pragma unroll
             for (int h = 0; h < NH; ++h) {
+                if (h >= hmax) break;
                 double bv[H];
 #pragma unroll
                 for (int q = 0; q < H; ++q) {
@@ -812,14 +816,17 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
             }
         }
         __syncthreads();
-        // S_{j-1} = I - i a (A_{j-1} - mu) + i a B_{j-1}^T G_j
+        // S_{j-1} = I - i a (A_{j-1} - mu) + i a B_{j-1}^T G_j; row m of B^T has no
+        // entries beyond column m, so tile row m0 needs the chunks of k < m0 + 16 only
         const double* Aj = A + (int64_t)(j - 1) * mat;
         for (int t = wave; t < NTL; t += kBlkWaves) {
             const int m0 = (t / NB) * 16, c0 = (t % NB) * 16;
             pd4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
             constexpr int H = 8, NH = (N / 4 + H - 1) / H;      // K in chunks of 8 steps of global operands
+            const int hmax = (m0 + 16 + 4 * H - 1) / (4 * H);
 #pragma unroll
             for (int h = 0; h < NH; ++h) {
+                if (h >= hmax) break;
                 double av[H], zr[H], zi[H];
 #pragma unroll
                 for (int q = 0; q < H; ++q) {
