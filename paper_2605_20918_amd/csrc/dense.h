@@ -29,15 +29,17 @@ void gram_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, dou
 
 // OUT = alpha*IN + sum_p X_p * op_p(S_p),  op_p(S) = scale * (trans ? S^T : S)
 // X_p = X + p*xstride (tall), S_p = S + p*sstride (small FP64). OUT may equal IN;
-// OUT must not alias any X_p. stage: nprod*ld*ld elements of T (scratch).
+// OUT must not alias any X_p. stage (scratch): (nprod + 1)*ld*ld doubles. FP32 with
+// ld = 16 NT, 3 <= NT <= 8: the products run on BF16 MFMA with both factors split
+// in three parts (six products, each term as accurate as the FP32 product).
 template <typename T>
 void update_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, int nprod,
                    const double* S, int64_t sstride, bool trans, double scale, int64_t Np, int ld,
                    void* stage, const int* state, hipStream_t s);
 
 // OUT = alpha*IN + X0 op0(S0) + X1 op1(S1) in one pass over OUT (two products with
-// their own transposition), op_i(S) = scale * (trans_i ? S^T : S). stage: 2*ld*ld
-// elements of T.
+// their own transposition), op_i(S) = scale * (trans_i ? S^T : S). stage: 3*ld*ld
+// doubles. FP32: as update_launch.
 template <typename T>
 void update2_launch(T* OUT, const T* IN, double alpha, const T* X0, const double* S0, bool trans0, const T* X1,
                     const double* S1, bool trans1, double scale, int64_t Np, int ld, void* stage, const int* state,

@@ -383,12 +383,14 @@ __device__ __forceinline__ void split_bf16(const float (&x)[8], bf16x8& hi, bf16
     lo = pl[1];
 }
 
-// B fragments of S'_p = scale * (trans ? S_p^T : S_p), rounded to FP32 and split:
-// frag[((pk * 2 + plane) * NT + nt) * 64 + l][e] = plane of S'_p[32 kc + 8 (l/16) + e][16 nt + l%16]
-// (pk = p nkc + kc, zero for rows beyond ld), followed by one all-zero chunk
-// (pk = nprod nkc) that the update reads past the last chunk.
+// B fragments of S'_p = scale * (trans ? S_p^T : S_p), rounded to FP32 and split in
+// NPL parts: frag[((pk * NPL + plane) * NT + nt) * 64 + l][e] = plane of
+// S'_p[32 kc + 8 (l/16) + e][16 nt + l%16] (pk = p nkc + kc, zero for rows beyond
+// ld), followed by one all-zero chunk (pk = nprod nkc) that the update reads past
+// the last chunk. With S1 set, products p >= 1 take S1 + (p - 1) sstride and trans1.
+template <int NPL>
 __global__ void k_frag_s(const double* __restrict__ S, int64_t sstride, int nprod, int ld, int trans, double scale,
-                         bf16x8* __restrict__ frag) {
+                         const double* __restrict__ S1, int trans1, bf16x8* __restrict__ frag) {
     const int NT = ld / 16, nkc = (ld + kSplitK - 1) / kSplitK;
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (idx >= ((int64_t)nprod * nkc + 1) * NT * 64) return;
@@ -396,7 +398,9 @@ __global__ void k_frag_s(const double* __restrict__ S, int64_t sstride, int npro
     const int64_t pk = idx / (64 * NT);
     const bool pad = pk == (int64_t)nprod * nkc;
     const int kc = (int)(pk % nkc);
-    const double* Sp = S + (pad ? 0 : (pk / nkc) * sstride);
+    const int64_t p = pad ? 0 : pk / nkc;
+    const double* Sp = (S1 && p >= 1) ? S1 + (p - 1) * sstride : S + p * sstride;
+    if (S1 && p >= 1) trans = trans1;
     const int j = 16 * nt + (l & 15);
     float v[8];
 #pragma unroll
@@ -405,10 +409,10 @@ __global__ void k_frag_s(const double* __restrict__ S, int64_t sstride, int npro
         v[e] = (!pad && k < ld) ? static_cast<float>(scale * (trans ? Sp[(int64_t)j * ld + k] : Sp[(int64_t)k * ld + j]))
                                 : 0.f;
     }
-    bf16x8 hi, lo;
-    split_bf16(v, hi, lo);
-    frag[((pk * 2 + 0) * NT + nt) * 64 + l] = hi;
-    frag[((pk * 2 + 1) * NT + nt) * 64 + l] = lo;
+    bf16x8 pl[NPL];
+    split_planes<NPL>(v, pl);
+#pragma unroll
+    for (int q = 0; q < NPL; ++q) frag[((pk * NPL + q) * NT + nt) * 64 + l] = pl[q];
 }
 
 // OUT = alpha IN + sum_p X_p S'_p for FP32 blocks with ld = 16 NT. A wave owns 16 MT
@@ -418,13 +422,13 @@ __global__ void k_frag_s(const double* __restrict__ S, int64_t sstride, int npro
 // whole rounds of D chunks, chunks past the end take the zero fragments, and X
 // addresses are clamped into the block (a clamped value always meets a zero
 // coefficient), so that every wait for a load can leave the later loads in flight.
-template <int MT, int NT, int D>
+template <int MT, int NT, int D, int NPL>
 __global__ __launch_bounds__(256) void k_update_split(float* OUT, const float* IN, double alpha,
                                                       const float* __restrict__ X, int64_t xstride, int nprod,
                                                       const bf16x8* __restrict__ frag, int64_t Np, int ld,
                                                       const int* __restrict__ state) {
     if (state && state[0]) return;
-    constexpr int FR = 2 * NT * 64;                       // fragments of one K chunk
+    constexpr int FR = NPL * NT * 64;                     // fragments of one K chunk
     constexpr int PER = (FR + 255) / 256;
     __shared__ bf16x8 sB[2][PER * 256];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, lr = l >> 4, lc = l & 15;
@@ -461,17 +465,25 @@ __global__ __launch_bounds__(256) void k_update_split(float* OUT, const float* I
         for (int q = 0; q < PER; ++q) sB[buf][threadIdx.x + 256 * q] = reg[q];
     };
     auto compute = [&](int buf, const float (&x)[MT][8]) {
-        bf16x8 ah[MT], al[MT];
+        bf16x8 ap[MT][NPL];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) split_bf16(x[mt], ah[mt], al[mt]);
+        for (int mt = 0; mt < MT; ++mt) split_planes<NPL>(x[mt], ap[mt]);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            const bf16x8 bh = sB[buf][nt * 64 + l], bl = sB[buf][(NT + nt) * 64 + l];
+            bf16x8 bp[NPL];
+#pragma unroll
+            for (int q = 0; q < NPL; ++q) bp[q] = sB[buf][(q * NT + nt) * 64 + l];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-                c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bh, c[mt][nt], 0, 0, 0);
-                c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bl, c[mt][nt], 0, 0, 0);
-                c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bh, c[mt][nt], 0, 0, 0);
+                // the terms of order >= 2^-16 (NPL = 3) or >= 2^-8 (NPL = 2), smallest first
+                if constexpr (NPL == 3) {
+                    c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[mt][2], bp[0], c[mt][nt], 0, 0, 0);
+                    c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[mt][1], bp[1], c[mt][nt], 0, 0, 0);
+                    c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[mt][0], bp[2], c[mt][nt], 0, 0, 0);
+                }
+                c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[mt][1], bp[0], c[mt][nt], 0, 0, 0);
+                c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[mt][0], bp[1], c[mt][nt], 0, 0, 0);
+                c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[mt][0], bp[0], c[mt][nt], 0, 0, 0);
             }
         }
     };
@@ -1338,10 +1350,25 @@ template <typename T>
 static void update_staged(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, int nprod, const T* st,
                           int64_t Np, int ld, const int* state, hipStream_t s);
 
+static bool split_full_ok(int ld);
+template <int NPL>
+static void frag_launch(const double* S, int64_t sstride, int nprod, int ld, bool trans, double scale, void* stage,
+                        hipStream_t s, const double* S1 = nullptr, bool trans1 = false);
+template <int NPL>
+static void update_split_any(float* OUT, const float* IN, double alpha, const float* X, int64_t xstride, int nprod,
+                             const void* frag, int64_t Np, int ld, const int* state, hipStream_t s);
+
 template <typename T>
 void update_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, int nprod, const double* S,
                    int64_t sstride, bool trans, double scale, int64_t Np, int ld, void* stage, const int* state,
                    hipStream_t s) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (split_full_ok(ld)) {
+            frag_launch<3>(S, sstride, nprod, ld, trans, scale, stage, s);
+            update_split_any<3>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s);
+            return;
+        }
+    }
     T* st = static_cast<T*>(stage);
     const int64_t cnt = (int64_t)nprod * ld * ld;
     k_stage_s<T><<<grid_for(cnt, 256), 256, 0, s>>>(S, sstride, nprod, ld, trans ? 1 : 0, scale, st);
@@ -1352,6 +1379,13 @@ template <typename T>
 void update2_launch(T* OUT, const T* IN, double alpha, const T* X0, const double* S0, bool trans0, const T* X1,
                     const double* S1, bool trans1, double scale, int64_t Np, int ld, void* stage, const int* state,
                     hipStream_t s) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (split_full_ok(ld)) {
+            frag_launch<3>(S0, 0, 2, ld, trans0, scale, stage, s, S1, trans1);
+            update_split_any<3>(OUT, IN, alpha, X0, X1 - X0, 2, stage, Np, ld, state, s);
+            return;
+        }
+    }
     T* st = static_cast<T*>(stage);
     const int64_t mat = (int64_t)ld * ld;
     k_stage_s<T><<<grid_for(mat, 256), 256, 0, s>>>(S0, 0, 1, ld, trans0 ? 1 : 0, scale, st);
@@ -1377,15 +1411,45 @@ static void update_staged(T* OUT, const T* IN, double alpha, const T* X, int64_t
         update_one<T, 8>(OUT, IN, alpha, X, xstride, nprod, st, Np, ld, state, s);
 }
 
-template <int NT>
+template <int NT, int NPL>
 static void update_split_one(float* OUT, const float* IN, double alpha, const float* X, int64_t xstride, int nprod,
                              const void* frag, int64_t Np, int ld, const int* state, hipStream_t s) {
     constexpr int MT = 2, D = 4;
     const int64_t rows_per_block = 4 * 16 * MT;
     const unsigned grid = static_cast<unsigned>((Np + rows_per_block - 1) / rows_per_block);
-    k_update_split<MT, NT, D><<<grid, 256, 0, s>>>(OUT, IN, alpha, X, xstride, nprod,
-                                                    static_cast<const bf16x8*>(frag), Np, ld, state);
+    k_update_split<MT, NT, D, NPL><<<grid, 256, 0, s>>>(OUT, IN, alpha, X, xstride, nprod,
+                                                         static_cast<const bf16x8*>(frag), Np, ld, state);
 }
+
+template <int NPL>
+static void update_split_any(float* OUT, const float* IN, double alpha, const float* X, int64_t xstride, int nprod,
+                             const void* frag, int64_t Np, int ld, const int* state, hipStream_t s) {
+    switch (ld / 16) {
+        case 1: update_split_one<1, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
+        case 2: update_split_one<2, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
+        case 3: update_split_one<3, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
+        case 4: update_split_one<4, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
+        case 5: update_split_one<5, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
+        case 6: update_split_one<6, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
+        case 7: update_split_one<7, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
+        default: update_split_one<8, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
+    }
+}
+
+// Fragments of scale * op(S_p), p < nprod (S_p = S1 and op1 for p = 1 when S1 is set).
+template <int NPL>
+static void frag_launch(const double* S, int64_t sstride, int nprod, int ld, bool trans, double scale, void* stage,
+                        hipStream_t s, const double* S1, bool trans1) {
+    const int nt = ld / 16, nkc = (ld + kSplitK - 1) / kSplitK;
+    const int64_t cnt = ((int64_t)nprod * nkc + 1) * nt * 64;
+    k_frag_s<NPL><<<grid_for(cnt, 256), 256, 0, s>>>(S, sstride, nprod, ld, trans ? 1 : 0, scale, S1, trans1 ? 1 : 0,
+                                                     static_cast<bf16x8*>(stage));
+}
+
+// Full-accuracy FP32 block updates on split BF16 (three parts, six products) when
+// ld = 16 NT with 3 <= NT <= 8: the fragments of nprod coefficient blocks, plus the
+// zero chunk, then fit the staging area of nprod + 1 ld x ld FP64 matrices.
+static bool split_full_ok(int ld) { return ld % 16 == 0 && ld / 16 >= 3 && ld / 16 <= 8; }
 
 template <>
 void update_correction_launch<float>(float* OUT, const float* IN, double alpha, const float* X, int64_t xstride,
@@ -1396,20 +1460,8 @@ void update_correction_launch<float>(float* OUT, const float* IN, double alpha, 
         update_launch<float>(OUT, IN, alpha, X, xstride, nprod, S, sstride, trans, scale, Np, ld, stage, state, s);
         return;
     }
-    const int nkc = (ld + kSplitK - 1) / kSplitK;
-    const int64_t cnt = ((int64_t)nprod * nkc + 1) * nt * 64;
-    k_frag_s<<<grid_for(cnt, 256), 256, 0, s>>>(S, sstride, nprod, ld, trans ? 1 : 0, scale,
-                                                static_cast<bf16x8*>(stage));
-    switch (nt) {
-        case 1: update_split_one<1>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
-        case 2: update_split_one<2>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
-        case 3: update_split_one<3>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
-        case 4: update_split_one<4>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
-        case 5: update_split_one<5>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
-        case 6: update_split_one<6>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
-        case 7: update_split_one<7>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
-        default: update_split_one<8>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
-    }
+    frag_launch<2>(S, sstride, nprod, ld, trans, scale, stage, s);
+    update_split_any<2>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s);
 }
 
 template <>

@@ -42,7 +42,7 @@ struct LzBufs {
     double* R1 = nullptr;
     double* R2 = nullptr;
     double* partial = nullptr;
-    double* stage = nullptr;      // staged small matrices for the block update (max_prod x ld x ld)
+    double* stage = nullptr;      // staged small matrices for the block update ((max_prod + 1) x ld x ld)
     double* chol_scratch = nullptr;
     double* min_diag = nullptr;   // 2 * v_max
     double* scal = nullptr;       // 16 doubles: [0] ||H||_inf

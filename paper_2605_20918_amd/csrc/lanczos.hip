@@ -373,7 +373,7 @@ void carve_lanczos(Arena& a, const LzPlan& p, LzBufs& bf) {
     bf.R1 = a.take<double>(mat);
     bf.R2 = a.take<double>(mat);
     bf.partial = a.take<double>(p.partial_mats * mat);
-    bf.stage = a.take<double>((int64_t)std::max({2, p.v_max, p.max_coef}) * mat);
+    bf.stage = a.take<double>((int64_t)(std::max({2, p.v_max, p.max_coef}) + 1) * mat);
     bf.chol_scratch = a.take<double>(chol_scratch_bytes(p.b) / sizeof(double) + 1);
     bf.min_diag = a.take<double>(2 * v);
     bf.scal = a.take<double>(16);
