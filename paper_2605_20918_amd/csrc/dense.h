@@ -51,11 +51,14 @@ void update2_launch(T* OUT, const T* IN, double alpha, const T* X0, const double
 // the FP32 product; the whole tile is computed and sym is not used there);
 // otherwise gram_plan + gram_launch. yplanes (FP32 split path, nprod > 1): room for
 // Y's three BF16 planes (3 Np ld bf16), so that Y is split once for all products;
-// nullptr splits Y inside every product.
+// nullptr splits Y inside every product. hinf (device, ||H||_inf; with yplanes):
+// the products take two FP16 parts of scaled operands and three FP16 MFMA products
+// instead (each term within 3 2^-22 of the exact one), for X blocks of unit-norm
+// columns and Y bounded entrywise by ||H||_inf (the re-orthogonalisation Gram).
 template <typename T>
 void gram_blocks_launch(const T* X, int64_t xstride, int nprod, const T* Y, int64_t Np, int ld, bool sym,
                         int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
-                        const int* state, hipStream_t s, void* yplanes = nullptr);
+                        const int* state, hipStream_t s, void* yplanes = nullptr, const double* hinf = nullptr);
 
 // update_launch for coefficient blocks S_p that are small corrections (full
 // reorthogonalisation after the three-term update). FP32 blocks with ld a multiple

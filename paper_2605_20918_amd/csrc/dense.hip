@@ -383,6 +383,40 @@ __device__ __forceinline__ void split_bf16(const float (&x)[8], bf16x8& hi, bf16
     lo = pl[1];
 }
 
+// FP16 two-part split of s x (s a power of two, so s x is exact): s x = hi + lo + r with
+// hi = RNE(s x), lo = RNE(s x - hi), |r| <= 2^-22 |s x| while lo is a normal FP16 number
+// and <= 2^-25 below that (FP16 subnormals, which the MFMA honours). The residual
+// s x - hi is exact in FP32; the compiler forms it with one mixed-precision FMA.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split_f16(const float (&x)[8], float sc, f16x8 (&pl)[2]) {
+    unsigned w[2][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const f32x2 y = f32x2{x[2 * i], x[2 * i + 1]} * sc;
+        const f16x2 h = __builtin_convertvector(y, f16x2);
+        const f16x2 lo = __builtin_convertvector(y - __builtin_convertvector(h, f32x2), f16x2);
+        w[0][i] = __builtin_bit_cast(unsigned, h);
+        w[1][i] = __builtin_bit_cast(unsigned, lo);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) pl[k] = __builtin_bit_cast(f16x8, u32x4{w[k][0], w[k][1], w[k][2], w[k][3]});
+}
+
+// Power-of-two scales for the FP16 split of Krylov blocks (unit-norm columns, entries
+// of about Np^-1/2) and of W (entries bounded by ||H||_2 <= ||H||_inf): the typical
+// entry lands near 1, the largest at most 2^12 (Np < 2^24), far from FP16 overflow.
+__device__ __forceinline__ float q_split_scale(int64_t Np) {
+    const int e = (63 - __builtin_clzll((unsigned long long)(Np > 1 ? Np : 1))) / 2;
+    return __builtin_ldexpf(1.f, e);
+}
+__device__ __forceinline__ float w_split_scale(int64_t Np, const double* hinf) {
+    int e = 0;
+    const double h = hinf ? *hinf : 1.0;
+    if (h > 0.0 && isfinite(h)) frexp(h, &e);               // 2^(e-1) <= h < 2^e
+    return __builtin_ldexpf(q_split_scale(Np), -e);
+}
+
 // B fragments of S'_p = scale * (trans ? S_p^T : S_p), rounded to FP32 and split in
 // NPL parts: frag[((pk * NPL + plane) * NT + nt) * 64 + l][e] = plane of
 // S'_p[32 kc + 8 (l/16) + e][16 nt + l%16] (pk = p nkc + kc, zero for rows beyond
@@ -528,9 +562,11 @@ __global__ __launch_bounds__(256) void k_update_split(float* OUT, const float* I
 // layout of the 16x16x32 MFMA: plane q, 8-row group r8, column c holds the 8 parts
 // of Y[8 r8 .. 8 r8 + 7][c] (16 bytes) at q (Np / 8) ld + r8 ld + c. One thread per
 // (r8, c); the parts are those of split_planes.
-template <int NPL>
+// F16: the two FP16 parts of w_split_scale(Np, hinf) Y instead (same layout).
+template <int NPL, bool F16>
 __global__ __launch_bounds__(256) void k_split_rows8(const float* __restrict__ Y, int64_t Np, int ld,
-                                                     bf16x8* __restrict__ P, const int* __restrict__ state) {
+                                                     bf16x8* __restrict__ P, const int* __restrict__ state,
+                                                     const double* __restrict__ hinf) {
     if (state && state[0]) return;
     const int64_t cnt = (Np / 8) * ld;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -540,10 +576,18 @@ __global__ __launch_bounds__(256) void k_split_rows8(const float* __restrict__ Y
     float v[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) v[e] = Y[(8 * r8 + e) * ld + c];
-    bf16x8 pl[NPL];
-    split_planes<NPL>(v, pl);
+    if constexpr (F16) {
+        static_assert(NPL == 2, "two FP16 parts");
+        f16x8 pl[2];
+        split_f16(v, w_split_scale(Np, hinf), pl);
 #pragma unroll
-    for (int q = 0; q < NPL; ++q) P[q * cnt + i] = pl[q];
+        for (int q = 0; q < 2; ++q) P[q * cnt + i] = __builtin_bit_cast(bf16x8, pl[q]);
+    } else {
+        bf16x8 pl[NPL];
+        split_planes<NPL>(v, pl);
+#pragma unroll
+        for (int q = 0; q < NPL; ++q) P[q * cnt + i] = pl[q];
+    }
 }
 
 // ------------------------------------------------------------------ BF16 Gram
@@ -565,11 +609,16 @@ __global__ __launch_bounds__(256) void k_split_rows8(const float* __restrict__ Y
 // written as one partial, as in k_gram. The product is the fastest grid index, so
 // the workgroups that read the same Y rows run at the same time (L2 / MALL hits).
 // YP: Y given as its NPL BF16 planes (k_split_rows8), loaded as ready operands.
-template <int NT, int NH, int NPL, bool YP>
+// F16 (with YP, NPL = 2): two FP16 parts of q_split_scale X and w_split_scale Y, the
+// three products lo*hi + hi*lo + hi*hi on the FP16 MFMA (dropped and rounded parts
+// below 3 2^-22 of each term), the partial scaled back exactly.
+template <int NT, int NH, int NPL, bool YP, bool F16>
 __global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ X, int64_t xstride,
                                                     const float* __restrict__ Y, const bf16x8* __restrict__ Yp,
                                                     int64_t Np, int64_t rpc, int ld, float* __restrict__ partial,
-                                                    int nchunk, const int* __restrict__ state) {
+                                                    int nchunk, const int* __restrict__ state,
+                                                    const double* __restrict__ hinf) {
+    static_assert(!F16 || (YP && NPL == 2), "FP16 parts come with the pre-split Y");
     if (state && state[0]) return;
     constexpr int TILE = 16 * NT, NB = NT / NH, KG = 4 / NH;
     static_assert(NT % NH == 0 && (NH == 1 || NH == 2), "column parts");
@@ -613,6 +662,7 @@ __global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ X,
     // The split of tile a + 1 is issued between the MFMAs of tile a: with one wave
     // per SIMD the VALU work then runs while the matrix core is busy instead of
     // after it (an MFMA blocks the wave's next MFMA, not its VALU instructions).
+    const float xsc = F16 ? q_split_scale(Np) : 1.f;
     auto compute = [&](const float (&x)[8][NT], const YBuf& y) {
         bf16x8 yb[NB][NPL];
 #pragma unroll
@@ -628,11 +678,21 @@ __global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ X,
             }
         }
         bf16x8 xb[2][NPL];
+        auto split_x = [&](const float (&v)[8], bf16x8 (&o)[NPL]) {
+            if constexpr (F16) {
+                f16x8 t[2];
+                split_f16(v, xsc, t);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) o[q] = __builtin_bit_cast(bf16x8, t[q]);
+            } else {
+                split_planes<NPL>(v, o);
+            }
+        };
         {
             float v[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) v[e] = x[e][0];
-            split_planes<NPL>(v, xb[0]);
+            split_x(v, xb[0]);
         }
 #pragma unroll
         for (int a = 0; a < NT; ++a) {
@@ -641,10 +701,18 @@ __global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ X,
                 float v[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) v[e] = x[e][a + 1];
-                split_planes<NPL>(v, xb[(a + 1) & 1]);
+                split_x(v, xb[(a + 1) & 1]);
             }
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
+                if constexpr (F16) {
+                    const f16x8 x0 = __builtin_bit_cast(f16x8, xc[0]), x1 = __builtin_bit_cast(f16x8, xc[1]);
+                    const f16x8 y0 = __builtin_bit_cast(f16x8, yb[b][0]), y1 = __builtin_bit_cast(f16x8, yb[b][1]);
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x1, y0, c[a][b], 0, 0, 0);
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x0, y1, c[a][b], 0, 0, 0);
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x0, y0, c[a][b], 0, 0, 0);
+                    continue;
+                }
                 if constexpr (NPL == 3) {
                     c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[2], yb[b][0], c[a][b], 0, 0, 0);
                     c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[1], yb[b][1], c[a][b], 0, 0, 0);
@@ -656,7 +724,7 @@ __global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ X,
             }
             if (a + 1 < NT) {
 #pragma unroll
-                for (int q = 0; q < NB * (2 * NPL); ++q) {
+                for (int q = 0; q < NB * (F16 ? 3 : 2 * NPL); ++q) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // one MFMA
                     __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);    // then up to three VALU
                 }
@@ -694,7 +762,12 @@ __global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ X,
         __syncthreads();
     }
     float* out = partial + ((int64_t)p * nchunk + chunk) * ld * ld;
-    for (int e = threadIdx.x; e < TILE * TILE; e += 256) out[e] = buf[e];
+    if constexpr (F16) {
+        const float unscale = 1.f / (xsc * w_split_scale(Np, hinf));   // a power of two
+        for (int e = threadIdx.x; e < TILE * TILE; e += 256) out[e] = buf[e] * unscale;
+    } else {
+        for (int e = threadIdx.x; e < TILE * TILE; e += 256) out[e] = buf[e];
+    }
 }
 
 // S'_p = scale * (trans ? S_p^T : S_p) in the block precision.
@@ -1499,22 +1572,25 @@ GramPlan gram_plan_split(int64_t Np, int ld, int nprod, int64_t cap_mats) {
 
 template <int NT>
 static void gram_split_one(const GramPlan& g, const float* X, int64_t xstride, const float* Y, const bf16x8* Yp,
-                           float* part, const int* state, hipStream_t s) {
+                           const double* hinf, float* part, const int* state, hipStream_t s) {
     constexpr int NH = (NT % 2 == 0 && NT >= 4) ? 2 : 1;
     dim3 grid(g.nprod, g.nchunk);
     const size_t lds = sizeof(float) * 256 * NT * NT;
-    if (Yp)
-        k_gram_split<NT, NH, 3, true><<<grid, 256, lds, s>>>(X, xstride, Y, Yp, g.Np, g.rows_per_chunk, g.ld, part,
-                                                             g.nchunk, state);
+    if (Yp && hinf)
+        k_gram_split<NT, NH, 2, true, true><<<grid, 256, lds, s>>>(X, xstride, Y, Yp, g.Np, g.rows_per_chunk, g.ld,
+                                                                   part, g.nchunk, state, hinf);
+    else if (Yp)
+        k_gram_split<NT, NH, 3, true, false><<<grid, 256, lds, s>>>(X, xstride, Y, Yp, g.Np, g.rows_per_chunk, g.ld,
+                                                                    part, g.nchunk, state, hinf);
     else
-        k_gram_split<NT, NH, 3, false><<<grid, 256, lds, s>>>(X, xstride, Y, Yp, g.Np, g.rows_per_chunk, g.ld, part,
-                                                              g.nchunk, state);
+        k_gram_split<NT, NH, 3, false, false><<<grid, 256, lds, s>>>(X, xstride, Y, Yp, g.Np, g.rows_per_chunk, g.ld,
+                                                                     part, g.nchunk, state, hinf);
 }
 
 template <>
 void gram_blocks_launch<float>(const float* X, int64_t xstride, int nprod, const float* Y, int64_t Np, int ld, bool sym,
                                int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
-                               const int* state, hipStream_t s, void* yplanes) {
+                               const int* state, hipStream_t s, void* yplanes, const double* hinf) {
     if (ld % 16 != 0 || ld > 96 || Np % 256 != 0) {
         const GramPlan g = gram_plan(Np, ld, nprod, sym, cap_mats, 4);
         gram_launch<float>(g, X, xstride, Y, partial, out, out_stride, mode, state, s);
@@ -1527,15 +1603,20 @@ void gram_blocks_launch<float>(const float* X, int64_t xstride, int nprod, const
     bf16x8* Yp = nullptr;
     if (yplanes && nprod > 1) {
         Yp = static_cast<bf16x8*>(yplanes);
-        k_split_rows8<3><<<grid_for((Np / 8) * ld, 256), 256, 0, s>>>(Y, Np, ld, Yp, state);
+        if (hinf)
+            k_split_rows8<2, true><<<grid_for((Np / 8) * ld, 256), 256, 0, s>>>(Y, Np, ld, Yp, state, hinf);
+        else
+            k_split_rows8<3, false><<<grid_for((Np / 8) * ld, 256), 256, 0, s>>>(Y, Np, ld, Yp, state, hinf);
+    } else {
+        hinf = nullptr;
     }
     switch (ld / 16) {
-        case 1: gram_split_one<1>(g, X, xstride, Y, Yp, part, state, s); break;
-        case 2: gram_split_one<2>(g, X, xstride, Y, Yp, part, state, s); break;
-        case 3: gram_split_one<3>(g, X, xstride, Y, Yp, part, state, s); break;
-        case 4: gram_split_one<4>(g, X, xstride, Y, Yp, part, state, s); break;
-        case 5: gram_split_one<5>(g, X, xstride, Y, Yp, part, state, s); break;
-        default: gram_split_one<6>(g, X, xstride, Y, Yp, part, state, s); break;
+        case 1: gram_split_one<1>(g, X, xstride, Y, Yp, hinf, part, state, s); break;
+        case 2: gram_split_one<2>(g, X, xstride, Y, Yp, hinf, part, state, s); break;
+        case 3: gram_split_one<3>(g, X, xstride, Y, Yp, hinf, part, state, s); break;
+        case 4: gram_split_one<4>(g, X, xstride, Y, Yp, hinf, part, state, s); break;
+        case 5: gram_split_one<5>(g, X, xstride, Y, Yp, hinf, part, state, s); break;
+        default: gram_split_one<6>(g, X, xstride, Y, Yp, hinf, part, state, s); break;
     }
     dim3 rgrid(grid_for((int64_t)ld * ld, 64), nprod);
     k_gram_reduce<float><<<rgrid, 64 * kRedGroups, 0, s>>>(part, g.nchunk, ld, 0, mode, out, out_stride, state);
@@ -1544,7 +1625,7 @@ void gram_blocks_launch<float>(const float* X, int64_t xstride, int nprod, const
 template <>
 void gram_blocks_launch<double>(const double* X, int64_t xstride, int nprod, const double* Y, int64_t Np, int ld,
                                 bool sym, int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
-                                const int* state, hipStream_t s, void*) {
+                                const int* state, hipStream_t s, void*, const double*) {
     const GramPlan g = gram_plan(Np, ld, nprod, sym, cap_mats, 8);
     gram_launch<double>(g, X, xstride, Y, partial, out, out_stride, mode, state, s);
 }

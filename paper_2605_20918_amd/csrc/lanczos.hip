@@ -150,9 +150,9 @@ struct Step {
     T* q(int j) const { return static_cast<T*>(slot_ptr(p, bf, p.twopass ? j % 3 : j)); }
 
     void gram(const T* X, int64_t xstride, int nprod, const T* Y, double* out, int64_t out_stride, bool sym,
-              int mode, void* yplanes = nullptr) const {
+              int mode, void* yplanes = nullptr, const double* hinf = nullptr) const {
         gram_blocks_launch<T>(X, xstride, nprod, Y, p.Np, p.ld, sym, p.partial_mats, bf.partial, out, out_stride, mode,
-                              bf.state, s, yplanes);
+                              bf.state, s, yplanes, hinf);
     }
     void update(T* out, const T* in, double alpha, const T* X, int64_t xstride, int nprod, const double* S,
                 int64_t sstride, bool trans, double scale) const {
@@ -192,7 +192,7 @@ struct Step {
             const int cap = (int)std::max<int64_t>(1, p.partial_mats);
             for (int t0 = 0; t0 < np; t0 += cap) {
                 const int cnt = std::min(cap, np - t0);
-                gram(q(t0), tall(), cnt, W, bf.C + t0 * mat(), mat(), false, 0, bf.yplanes);
+                gram(q(t0), tall(), cnt, W, bf.C + t0 * mat(), mat(), false, 0, bf.yplanes, bf.scal);
             }
             update_correction_launch<T>(W, W, 1.0, q(0), tall(), np, bf.C, mat(), false, -1.0, p.Np, p.ld,
                                         bf.stage, bf.state, s);
