@@ -288,7 +288,9 @@ css_status css_color_batched_workspace_size(const css_color_job* jobs, int32_t c
  * css_workspace_size -- bytes of workspace an entry point needs.
  *   entry  CSS_ENTRY_*; the other arguments as they will be passed
  *   (nnz = H's nnz, or for CSS_ENTRY_COLOR unused; CSS_ENTRY_SPMM uses n and
- *   nnz only).
+ *   nnz only). For CSS_ENTRY_LANCZOS / CSS_ENTRY_DENSITY the size holds for H's
+ *   values in either FP32 or FP64 (values not in the precision the flags select
+ *   are converted into the workspace).
  */
 css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, int32_t n_colors,
                               int32_t depth, uint32_t flags, size_t* bytes);

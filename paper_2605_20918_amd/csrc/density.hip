@@ -477,22 +477,25 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
         *bytes = spmm_workspace_bytes(n, nnz);
         return CSS_OK;
     }
-    // a shape-only CSR for planning
-    css_csr H{n, nnz, reinterpret_cast<const int32_t*>(1), reinterpret_cast<const int32_t*>(1),
-              reinterpret_cast<const void*>(1), (flags & CSS_PREC_MASK) == CSS_PREC_FP32 ? CSS_F32 : CSS_F64};
-    if (entry == CSS_ENTRY_LANCZOS) {
-        LzPlan p;
-        CSS_TRY(plan_lanczos(&H, n_colors, depth, flags, p));
-        *bytes = lanczos_workspace_bytes(p);
-        return CSS_OK;
+    if (entry != CSS_ENTRY_LANCZOS && entry != CSS_ENTRY_DENSITY) return CSS_E_ARG;
+    // shape-only CSRs for planning; H's value type is not an argument, so the size
+    // covers both (values in the other precision need a converted copy)
+    size_t most = 0;
+    for (const int vt : {CSS_F32, CSS_F64}) {
+        css_csr H{n, nnz, reinterpret_cast<const int32_t*>(1), reinterpret_cast<const int32_t*>(1),
+                  reinterpret_cast<const void*>(1), vt};
+        if (entry == CSS_ENTRY_LANCZOS) {
+            LzPlan p;
+            CSS_TRY(plan_lanczos(&H, n_colors, depth, flags, p));
+            most = std::max(most, lanczos_workspace_bytes(p));
+        } else {
+            DmPlan p;
+            CSS_TRY(plan_dm(&H, n_colors, depth, flags, p));
+            most = std::max(most, dm_workspace_bytes(p));
+        }
     }
-    if (entry == CSS_ENTRY_DENSITY) {
-        DmPlan p;
-        CSS_TRY(plan_dm(&H, n_colors, depth, flags, p));
-        *bytes = dm_workspace_bytes(p);
-        return CSS_OK;
-    }
-    return CSS_E_ARG;
+    *bytes = most;
+    return CSS_OK;
 }
 
 extern "C" int32_t css_block_ld(int32_t n_colors) { return n_colors > 0 ? block_ld(n_colors) : 0; }

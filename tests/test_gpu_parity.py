@@ -274,6 +274,30 @@ def test_density_fp32_parity(M, seed, depth):
     assert rel_e <= 1e-7
 
 
+@pytest.mark.parametrize("scale", [2.0 ** -12, 2.0 ** 12, 1000.0])
+def test_mixed_path_follows_energy_scale(scale):
+    """P(s H, s mu, s kT) = P(H, mu, kT) for the mixed path, whose FP16 and BF16 operand
+    splits are scaled from ||H||_inf: exactly (to FP64 rounding) for a power of two,
+    to the mixed tolerance otherwise (H's FP32 rounding changes with s)."""
+    print(f"energy scale {scale}", flush=True)
+    ws, H, rp, col, color, b, sign, mu = water_case(216, 3)
+    def run(s):
+        Hs = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val * s, device="cuda", dtype=torch.float64)
+        return css.css_density_matrix(Hs, dev_i32(color), dev_i8(sign), b, mu * s, KT * s, 40, dev_i64(rp),
+                                      dev_i32(col), FP32_FLAGS)
+    p0, e0, t0, i0 = run(1.0)
+    p0 = p0.clone()
+    p1, e1, t1, i1 = run(scale)
+    err = torch.max(torch.abs(p1 - p0)).item()
+    rel_e = abs(e1 / scale - e0) / abs(e0)
+    print(f"  max|dP|={err:.3e} rel dE={rel_e:.3e} depth {i0['depth_eff']} {i1['depth_eff']}", flush=True)
+    assert i1["depth_eff"] == i0["depth_eff"]
+    tol = 1e-12 if np.log2(scale) == round(np.log2(scale)) else 1e-5
+    assert err <= tol
+    assert rel_e <= (1e-12 if tol < 1e-6 else 1e-7)
+    assert abs(t1 - t0) <= 1e-6 * abs(t0)
+
+
 def test_twopass_matches_stored_basis():
     ws, H, rp, col, color, b, sign, mu = water_case(216, 3)
     args = (to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, 12, dev_i64(rp), dev_i32(col))
