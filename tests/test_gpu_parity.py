@@ -281,6 +281,9 @@ def test_mixed_path_follows_energy_scale(scale):
     to the mixed tolerance otherwise (H's FP32 rounding changes with s)."""
     print(f"energy scale {scale}", flush=True)
     ws, H, rp, col, color, b, sign, mu = water_case(216, 3)
+    # exactly the queried workspace (no larger buffer left from earlier tests): FP64
+    # values with FP32 blocks need room for the converted copy of H
+    css._ws_cache.clear()
     def run(s):
         Hs = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val * s, device="cuda", dtype=torch.float64)
         return css.css_density_matrix(Hs, dev_i32(color), dev_i8(sign), b, mu * s, KT * s, 40, dev_i64(rp),
