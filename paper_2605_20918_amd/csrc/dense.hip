@@ -606,8 +606,8 @@ __global__ __launch_bounds__(256) void k_split_rows8(const float* __restrict__ Y
 // each tile a, for Y the column 16 b + l%16 of each of its tiles b. Operands are
 // fetched one step ahead (the chunk's steps per wave are even, see
 // gram_plan_split). The row groups' tiles are added in LDS in group order and
-// written as one partial, as in k_gram. The product is the fastest grid index, so
-// the workgroups that read the same Y rows run at the same time (L2 / MALL hits).
+// written as one partial, as in k_gram. The products of a chunk run together on one
+// XCD, so the workgroups that read the same Y rows share that XCD's L2.
 // YP: Y given as its NPL BF16 planes (k_split_rows8), loaded as ready operands.
 // F16 (with YP, NPL = 2): two FP16 parts of q_split_scale X and w_split_scale Y, the
 // three products lo*hi + hi*lo + hi*hi on the FP16 MFMA (dropped and rounded parts
@@ -626,7 +626,12 @@ __global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ X,
     float* buf = reinterpret_cast<float*>(gram_lds);
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, lr = l >> 4, lc = l & 15;
     const int grp = w / NH, h = w % NH;
-    const int p = blockIdx.x, chunk = blockIdx.y;         // products of a chunk run together: Y rows reused
+    // Workgroups are dealt round-robin to the 8 XCDs: XCD x takes chunks x, x + 8, ...
+    // with all their products, so the products of a chunk share its Y rows in one L2.
+    const int nprod = (int)(gridDim.x / (8 * ((nchunk + 7) / 8)));
+    const int xcd = (int)(blockIdx.x % 8), k = (int)(blockIdx.x / 8);
+    const int p = k % nprod, chunk = (k / nprod) * 8 + xcd;
+    if (chunk >= nchunk) return;
     const int64_t r0 = (int64_t)chunk * rpc;
     const int64_t r1 = r0 + rpc < Np ? r0 + rpc : Np;
     const int nst = (int)((r1 - r0) / (32 * KG));         // steps of this wave (even)
@@ -1574,7 +1579,7 @@ template <int NT>
 static void gram_split_one(const GramPlan& g, const float* X, int64_t xstride, const float* Y, const bf16x8* Yp,
                            const double* hinf, float* part, const int* state, hipStream_t s) {
     constexpr int NH = (NT % 2 == 0 && NT >= 4) ? 2 : 1;
-    dim3 grid(g.nprod, g.nchunk);
+    const unsigned grid = static_cast<unsigned>(8 * ((g.nchunk + 7) / 8) * g.nprod);   // see k_gram_split
     const size_t lds = sizeof(float) * 256 * NT * NT;
     if (Yp && hinf)
         k_gram_split<NT, NH, 2, true, true><<<grid, 256, lds, s>>>(X, xstride, Y, Yp, g.Np, g.rows_per_chunk, g.ld,
