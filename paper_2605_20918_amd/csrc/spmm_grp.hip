@@ -220,18 +220,20 @@ __device__ inline void load_step(const T* __restrict__ Hb, const T* __restrict__
 // chunks of UC columns whose indices are staged in LDS; the A values and V values
 // of each k-step (4 union columns) are fetched D steps ahead of their use. Loads
 // past the chunk's last step repeat that step (in bounds) and are multiplied by
-// zero. Work-groups are dealt round-robin to the 8 XCDs; block b takes group
-// (b % 8) * per_xcd + b / 8 so that each XCD (and its L2) sweeps a contiguous
-// range of rows, whose neighbourhoods overlap.
+// zero. Work-groups are dealt round-robin to the 8 XCDs; XCD x takes the runs of
+// `run` consecutive groups x, x + 8, x + 16, ... (block b: run (b / 8) / run * 8 + b % 8,
+// group (b / 8) % run within it): an XCD's L2 sees neighbouring rows, and the eight
+// XCDs sweep the rows together, so the V rows in use at any time stay in the MALL.
 template <typename T, int NT, int UC, int D>
-__global__ __launch_bounds__(64) void k_spmm_grp(int n, int ngroups, int per_xcd, const int32_t* __restrict__ rp,
+__global__ __launch_bounds__(64) void k_spmm_grp(int n, int ngroups, int run, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ U, const int32_t* __restrict__ ucount,
                                                  const int64_t* __restrict__ boff, const T* __restrict__ hblk,
                                                  const T* __restrict__ V, T* __restrict__ W, int ld) {
     typedef GMF<T> M;
     __shared__ int32_t uidx[UC];
     const int lane = threadIdx.x, lr = lane >> 4, lc = lane & 15;
-    const int g = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    const int xi = (int)(blockIdx.x / 8);
+    const int g = ((xi / run) * 8 + (int)(blockIdx.x % 8)) * run + xi % run;
     if (g >= ngroups) return;
     const int r0 = g * kSpmmGroup;
     const int r1 = min(n, r0 + kSpmmGroup);
@@ -281,10 +283,14 @@ template <typename T, int NT>
 void launch_grp(const SpmmArgs<T>& a, const SpmmGroups& gp, hipStream_t s) {
     constexpr int UC = 256;                           // union columns per index chunk
     constexpr int D = 8;                              // k-steps in flight per wave
+    // groups per XCD run: at most 512 (on 10^6 water 512 beat one contiguous range per
+    // XCD by 7%; at 10k, 469 groups per XCD, one range per XCD moved the fewest bytes)
     const int ngroups = spmm_groups(a.n);
-    const int per_xcd = (ngroups + 7) / 8;
-    k_spmm_grp<T, NT, UC, D><<<8 * per_xcd, 64, 0, s>>>(a.n, ngroups, per_xcd, a.row_ptr, gp.U, gp.ucount, gp.boff,
-                                                        static_cast<const T*>(gp.hblk), a.V, a.W, a.ld);
+    const int run = std::min(512, (ngroups + 7) / 8);
+    const int nruns = (ngroups + run - 1) / run;
+    const int blocks = 8 * ((nruns + 7) / 8) * run;
+    k_spmm_grp<T, NT, UC, D><<<blocks, 64, 0, s>>>(a.n, ngroups, run, a.row_ptr, gp.U, gp.ucount, gp.boff,
+                                                   static_cast<const T*>(gp.hblk), a.V, a.W, a.ld);
 }
 
 }  // namespace
