@@ -329,6 +329,26 @@ def main():
                      "kernel_sha256_16": kernel_hash()},
     }
 
+    if args.workload == "10k":
+        # the energy-weighted estimate P_E = (H X) r^T on the pattern: its cost over a
+        # density call alone (one more sparse x block product and gather)
+        color, bb, p_rp, p_col, _ = css.css_color(xyz, box, R_CUT)
+        sign, _ = css.css_build_probes(color, bb, wl["seed"])
+        dm_args = (H, color, sign, bb, mu, KT, depth, p_rp, p_col, flags)
+        times = {}
+        for name, fn in (("density", css.css_density_matrix), ("energy", css.css_energy_density_matrix)):
+            fn(*dm_args)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = fn(*dm_args)
+            torch.cuda.synchronize()
+            times[name] = time.perf_counter() - t
+        _, _, _, _, pe_trace, einfo = r
+        out["energy_weighted"] = {"extra_ms": (times["energy"] - times["density"]) * 1e3,
+                                  "density_ms": times["density"] * 1e3, "energy_ms": times["energy"] * 1e3,
+                                  "pe_trace": pe_trace, "e_band_krylov": einfo["e_band_krylov"]}
+        del r
+
     if wl["prec"] == "fp32" and not args.no_fp64:
         p_mixed = state["p_val"].double().cpu()
         e_mixed = state["e_band"]

@@ -77,7 +77,8 @@ enum { CSS_F64 = 0, CSS_F32 = 1 };
                                      are dense enough (see css_spmm_prepare) */
 
 /* workspace query selectors */
-enum { CSS_ENTRY_COLOR = 0, CSS_ENTRY_LANCZOS = 1, CSS_ENTRY_DENSITY = 2, CSS_ENTRY_SPMM = 3 };
+enum { CSS_ENTRY_COLOR = 0, CSS_ENTRY_LANCZOS = 1, CSS_ENTRY_DENSITY = 2, CSS_ENTRY_SPMM = 3,
+       CSS_ENTRY_ENERGY_DENSITY = 4 };
 
 /* Sparse symmetric H in CSR form; all pointers device. Column indices must be
  * sorted within each row; row_ptr[0] = 0, row_ptr[n] = nnz < 2^31. */
@@ -216,6 +217,27 @@ css_status css_density_matrix(const css_csr* H, const int32_t* color, const int8
                               int64_t p_nnz, uint32_t flags, double* p_val,
                               double* e_band, double* trace, css_info* info,
                               void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * css_energy_density_matrix -- css_density_matrix together with the CSS estimate
+ *   of the energy-weighted density matrix P_E = g f(H) H (the force expression
+ *   of the paper's SCF section, rho_E = sum_i f(e_i) e_i |psi_i><psi_i|, taken as
+ *   S^-1 H rho~ with S = I): X_E = H X, then P_E,mn = sign[n] X_E[m, colour(n)] on
+ *   the same pattern, symmetrised with CSS_SYMMETRIZE. One more sparse x block
+ *   product and one more gather than css_density_matrix.
+ *   Arguments as css_density_matrix, and:
+ *   pe_val      device double[p_nnz] out: P_E on the pattern
+ *   pe_trace    host out (may be NULL): sum_m P_E,mm (the Krylov band energy up to
+ *               rounding, Tr(r^T H X) = Tr(H rho~))
+ *   ws          css_workspace_size(CSS_ENTRY_ENERGY_DENSITY, ...) bytes.
+ *   p_val, e_band, trace and info are those css_density_matrix returns.
+ */
+css_status css_energy_density_matrix(const css_csr* H, const int32_t* color, const int8_t* sign,
+                                     int32_t n_colors, double mu, double kT, int32_t depth,
+                                     double spin_deg, const int64_t* p_row_ptr, const int32_t* p_col,
+                                     int64_t p_nnz, uint32_t flags, double* p_val, double* pe_val,
+                                     double* e_band, double* trace, double* pe_trace, css_info* info,
+                                     void* ws, size_t ws_bytes, void* stream);
 
 /* One system of a batch (all arrays device, as for css_density_matrix). */
 typedef struct {

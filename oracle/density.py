@@ -93,6 +93,16 @@ def density_matrix(H, color, sign, n_colors, mu, kT, depth, p_row_ptr, p_col,
     }
 
 
+def energy_density_matrix(H, res: dict, color, sign, p_row_ptr, p_col, symmetrize_p=True) -> dict:
+    """The CSS estimate of the energy-weighted density matrix, rho~_E = S^-1 H rho~
+    (the force expression of the paper's SCF section) with S = I: X_E = H X from the
+    X of `density_matrix` (its result dict `res`), read off the pattern as P is."""
+    XE = H @ res["X"]
+    pe_raw = gather_raw(XE, np.asarray(color), np.asarray(sign), p_row_ptr, p_col)
+    pe_val = symmetrize(pe_raw, p_row_ptr, p_col) if symmetrize_p else pe_raw
+    return {"pe_val": pe_val, "pe_raw": pe_raw, "XE": XE, "pe_trace": trace_of(pe_val, p_row_ptr, p_col)}
+
+
 # ---- references used to separate the method error from the parity error ----
 
 def dense_fermi_dm(H, mu, kT, spin_deg=2.0) -> np.ndarray:
@@ -100,6 +110,13 @@ def dense_fermi_dm(H, mu, kT, spin_deg=2.0) -> np.ndarray:
     Hd = H.toarray() if hasattr(H, "toarray") else np.asarray(H)
     lam, U = np.linalg.eigh(Hd)
     return (U * (spin_deg * fermi(lam, mu, kT))[None, :]) @ U.T
+
+
+def dense_energy_fermi_dm(H, mu, kT, spin_deg=2.0) -> np.ndarray:
+    """sum_i g f(e_i) e_i psi_i psi_i^T from dense diagonalisation (S = I)."""
+    Hd = H.toarray() if hasattr(H, "toarray") else np.asarray(H)
+    lam, U = np.linalg.eigh(Hd)
+    return (U * (spin_deg * fermi(lam, mu, kT) * lam)[None, :]) @ U.T
 
 
 def css_exact_X(P_dense: np.ndarray, color, sign, n_colors) -> np.ndarray:

@@ -265,6 +265,7 @@ struct DmPlan {
     size_t eig_ws = 0;
     size_t pole_ws = 0;
     bool sep_X = false;
+    bool energy = false;      // also the energy-weighted estimate (X_E = H X)
 };
 
 struct DmBufs {
@@ -274,6 +275,7 @@ struct DmBufs {
     double *t0 = nullptr, *t1 = nullptr, *rows = nullptr, *tmp = nullptr, *res = nullptr;
     int* flags = nullptr;
     void* X = nullptr;
+    void* XE = nullptr;       // H X (energy-weighted estimate)
     void* eig_ws = nullptr;
 };
 
@@ -294,6 +296,7 @@ void carve_dm(Arena& a, const DmPlan& p, DmBufs& bf) {
     bf.res = a.take<double>(16);
     bf.flags = a.take<int>(16);
     bf.X = p.sep_X ? a.take<char>((size_t)p.lz.Np * p.lz.ld * p.lz.elem) : bf.lz.W;
+    bf.XE = p.energy ? a.take<char>((size_t)p.lz.Np * p.lz.ld * p.lz.elem) : nullptr;
     bf.eig_ws = p.eig_ws ? a.take<char>(p.eig_ws) : nullptr;
     bf.pole_ws = p.pole_ws ? a.take<char>(p.pole_ws) : nullptr;
 }
@@ -332,15 +335,19 @@ void launch_gather(int n, const int64_t* prp, const int32_t* pcol, const int32_t
 
 using namespace css;
 
-extern "C" css_status css_density_matrix(const css_csr* H, const int32_t* color, const int8_t* sign,
-                                         int32_t n_colors, double mu, double kT, int32_t depth, double spin_deg,
-                                         const int64_t* p_row_ptr, const int32_t* p_col, int64_t p_nnz,
-                                         uint32_t flags, double* p_val, double* e_band, double* trace,
-                                         css_info* info, void* ws, size_t ws_bytes, void* stream) {
+namespace css {
+namespace {
+
+// The density-matrix path; with pe_val also the energy-weighted estimate.
+css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, int32_t n_colors, double mu, double kT,
+                  int32_t depth, double spin_deg, const int64_t* p_row_ptr, const int32_t* p_col, int64_t p_nnz,
+                  uint32_t flags, double* p_val, double* pe_val, double* e_band, double* trace, double* pe_trace,
+                  css_info* info, void* ws, size_t ws_bytes, void* stream) {
     if (!color || !sign || !p_row_ptr || !p_col || !p_val || !e_band || !trace || !ws || p_nnz < 1) return CSS_E_ARG;
     if (!(kT > 0.0) || !std::isfinite(kT) || !std::isfinite(mu) || !(spin_deg > 0.0)) return CSS_E_ARG;
     DmPlan p;
     CSS_TRY(plan_dm(H, n_colors, depth, flags, p));
+    p.energy = pe_val != nullptr;
     if (ws_bytes < dm_workspace_bytes(p)) return CSS_E_WORKSPACE;
     Arena a;
     a.base = static_cast<char*>(ws);
@@ -434,16 +441,27 @@ extern "C" css_status css_density_matrix(const css_csr* H, const int32_t* color,
     det_sum(rt, lz.n, bf.tmp + 2 * kSumBlocks, bf.res + 0, s);
     det_sum(re, lz.n, bf.tmp + 3 * kSumBlocks, bf.res + 1, s);
     det_max(ra, lz.n, bf.tmp, bf.res + 4, s);
+    if (pe_val) {
+        // energy-weighted estimate: X_E = H X, gathered as P (the rows' scratch is reused
+        // after the reductions above, in stream order)
+        CSS_TRY(lanczos_spmm(H, lz, bf.lz, bf.X, bf.XE, s));
+        if (lz.fp32)
+            launch_gather<float>(lz.n, p_row_ptr, p_col, color, sign, bf.XE, lz.ld, sym, pe_val, rt, ra, s);
+        else
+            launch_gather<double>(lz.n, p_row_ptr, p_col, color, sign, bf.XE, lz.ld, sym, pe_val, rt, ra, s);
+        det_sum(rt, lz.n, bf.tmp + 2 * kSumBlocks, bf.res + 5, s);
+    }
     CSS_HIP_TRY(hipEventRecord(ev[5], s));
     double hres[8];
     int hinfo = 0;
-    CSS_HIP_TRY(hipMemcpyAsync(hres, bf.res, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipMemcpyAsync(hres, bf.res, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
     CSS_HIP_TRY(hipMemcpyAsync(&hinfo, bf.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
     CSS_HIP_TRY(hipStreamSynchronize(s));
     CSS_HIP_TRY(hipGetLastError());
     if (hinfo != 0) return CSS_E_EIG;
     *trace = hres[0];
     *e_band = hres[1];
+    if (pe_val && pe_trace) *pe_trace = hres[5];
     if (info) {
         *info = css_info{};
         info->depth_eff = v_eff;
@@ -465,6 +483,29 @@ extern "C" css_status css_density_matrix(const css_csr* H, const int32_t* color,
     return CSS_OK;
 }
 
+}  // namespace
+}  // namespace css
+
+extern "C" css_status css_density_matrix(const css_csr* H, const int32_t* color, const int8_t* sign,
+                                         int32_t n_colors, double mu, double kT, int32_t depth, double spin_deg,
+                                         const int64_t* p_row_ptr, const int32_t* p_col, int64_t p_nnz,
+                                         uint32_t flags, double* p_val, double* e_band, double* trace,
+                                         css_info* info, void* ws, size_t ws_bytes, void* stream) {
+    return css::dm_run(H, color, sign, n_colors, mu, kT, depth, spin_deg, p_row_ptr, p_col, p_nnz, flags, p_val,
+                       nullptr, e_band, trace, nullptr, info, ws, ws_bytes, stream);
+}
+
+extern "C" css_status css_energy_density_matrix(const css_csr* H, const int32_t* color, const int8_t* sign,
+                                                int32_t n_colors, double mu, double kT, int32_t depth,
+                                                double spin_deg, const int64_t* p_row_ptr, const int32_t* p_col,
+                                                int64_t p_nnz, uint32_t flags, double* p_val, double* pe_val,
+                                                double* e_band, double* trace, double* pe_trace, css_info* info,
+                                                void* ws, size_t ws_bytes, void* stream) {
+    if (!pe_val) return CSS_E_ARG;
+    return css::dm_run(H, color, sign, n_colors, mu, kT, depth, spin_deg, p_row_ptr, p_col, p_nnz, flags, p_val,
+                       pe_val, e_band, trace, pe_trace, info, ws, ws_bytes, stream);
+}
+
 extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, int32_t n_colors, int32_t depth,
                                          uint32_t flags, size_t* bytes) {
     if (!bytes || n < 1) return CSS_E_ARG;
@@ -477,7 +518,8 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
         *bytes = spmm_workspace_bytes(n, nnz);
         return CSS_OK;
     }
-    if (entry != CSS_ENTRY_LANCZOS && entry != CSS_ENTRY_DENSITY) return CSS_E_ARG;
+    if (entry != CSS_ENTRY_LANCZOS && entry != CSS_ENTRY_DENSITY && entry != CSS_ENTRY_ENERGY_DENSITY)
+        return CSS_E_ARG;
     // shape-only CSRs for planning; H's value type is not an argument, so the size
     // covers both (values in the other precision need a converted copy)
     size_t most = 0;
@@ -491,6 +533,7 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
         } else {
             DmPlan p;
             CSS_TRY(plan_dm(&H, n_colors, depth, flags, p));
+            p.energy = entry == CSS_ENTRY_ENERGY_DENSITY;
             most = std::max(most, dm_workspace_bytes(p));
         }
     }

@@ -58,6 +58,10 @@ void carve_lanczos(Arena& a, const LzPlan& p, LzBufs& bf);
 // Validates H (and colours), converts H if needed, builds Q_1 in slot 0 and
 // runs pass 1. On return (stream synchronised) *v_eff and *breakdown are set.
 // Also decides bf.use_grp.
+// W = H V for an Np x ld block in the Lanczos precision, on the kernel the Lanczos
+// steps use (the grouped kernel when it was prepared). Rows n..Np-1 of W are not written.
+css_status lanczos_spmm(const css_csr* H, const LzPlan& p, const LzBufs& bf, const void* V, void* W, hipStream_t s);
+
 css_status run_lanczos_pass1(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p,
                              LzBufs& bf, hipStream_t s, int* v_eff, int* breakdown, double* min_diag);
 

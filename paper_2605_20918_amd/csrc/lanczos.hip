@@ -317,6 +317,15 @@ css_status pass2_t(const css_csr* H, const int32_t* color, const int8_t* sign, c
 
 }  // namespace
 
+css_status lanczos_spmm(const css_csr* H, const LzPlan& p, const LzBufs& bf, const void* V, void* W, hipStream_t s) {
+    const bool ok = p.fp32 ? launch_spmm_t<float>(H, bf, static_cast<const float*>(V), static_cast<float*>(W), p.ld, s)
+                           : launch_spmm_t<double>(H, bf, static_cast<const double*>(V), static_cast<double*>(W),
+                                                   p.ld, s);
+    if (!ok) return CSS_E_UNSUPPORTED;
+    CSS_HIP_TRY(hipGetLastError());
+    return CSS_OK;
+}
+
 // ------------------------------------------------------------------ plan / carve
 
 css_status plan_lanczos(const css_csr* H, int32_t b, int32_t depth, uint32_t flags, LzPlan& p) {

@@ -38,7 +38,7 @@ SIGNS_ONES = 0x80
 SUBSPACE_EIG = 0x100
 SPMM_CSR = 0x200
 
-ENTRY_COLOR, ENTRY_LANCZOS, ENTRY_DENSITY, ENTRY_SPMM = 0, 1, 2, 3
+ENTRY_COLOR, ENTRY_LANCZOS, ENTRY_DENSITY, ENTRY_SPMM, ENTRY_ENERGY_DENSITY = 0, 1, 2, 3, 4
 
 
 class CssError(RuntimeError):
@@ -117,6 +117,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.css_block_lanczos.argtypes = [pcsr, vp, vp, i32, i32, u32, vp, vp, pinfo, vp, sz, vp]
     lib.css_density_matrix.argtypes = [pcsr, vp, vp, i32, dbl, dbl, i32, dbl, vp, vp, i64, u32, vp,
                                        ctypes.POINTER(dbl), ctypes.POINTER(dbl), pinfo, vp, sz, vp]
+    lib.css_energy_density_matrix.argtypes = [pcsr, vp, vp, i32, dbl, dbl, i32, dbl, vp, vp, i64, u32, vp, vp,
+                                              ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl), pinfo,
+                                              vp, sz, vp]
     lib.css_workspace_size.argtypes = [i32, i32, i64, i32, i32, u32, ctypes.POINTER(sz)]
     lib.css_fermi_poles.argtypes = [i32, vp, vp, ctypes.POINTER(i32)]
     lib.css_fermi_poles.restype = i32
@@ -334,6 +337,30 @@ def css_density_matrix(H: DeviceCSR, color, sign, n_colors: int, mu: float, kT: 
                                      ctypes.byref(e_band), ctypes.byref(trace), ctypes.byref(info), _ptr(ws),
                                      ws.numel(), _stream(dev)))
     return p_val, float(e_band.value), float(trace.value), info.as_dict()
+
+
+def css_energy_density_matrix(H: DeviceCSR, color, sign, n_colors: int, mu: float, kT: float, depth: int,
+                              p_row_ptr, p_col, flags: int, spin_deg: float = 2.0):
+    """P and the energy-weighted P_E on the pattern. Returns (p_val, pe_val float64
+    [nnz_P], e_band, trace, pe_trace, info dict)."""
+    torch = _torch()
+    dev = color.device
+    nnz = int(p_col.numel())
+    p_val = torch.empty(nnz, dtype=torch.float64, device=dev)
+    pe_val = torch.empty(nnz, dtype=torch.float64, device=dev)
+    ws = workspace(workspace_size(ENTRY_ENERGY_DENSITY, H.n, H.nnz, n_colors, depth, flags), dev)
+    e_band = ctypes.c_double(0.0)
+    trace = ctypes.c_double(0.0)
+    pe_trace = ctypes.c_double(0.0)
+    info = InfoStruct()
+    csr = H.struct()
+    _check("css_energy_density_matrix",
+           load().css_energy_density_matrix(ctypes.byref(csr), _ptr(color), _ptr(sign), n_colors, float(mu),
+                                            float(kT), depth, float(spin_deg), _ptr(p_row_ptr), _ptr(p_col), nnz,
+                                            flags, _ptr(p_val), _ptr(pe_val), ctypes.byref(e_band),
+                                            ctypes.byref(trace), ctypes.byref(pe_trace), ctypes.byref(info),
+                                            _ptr(ws), ws.numel(), _stream(dev)))
+    return p_val, pe_val, float(e_band.value), float(trace.value), float(pe_trace.value), info.as_dict()
 
 
 def css_density_matrix_batched(systems, kT: float, depth: int, flags: int, concurrency: int = 4,

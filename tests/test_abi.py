@@ -14,7 +14,7 @@ def test_every_declared_symbol_is_exported():
     assert {"css_color", "css_build_probes", "css_block_lanczos", "css_density_matrix", "css_spmm",
             "css_spmm_prepare", "css_workspace_size", "css_status_string", "css_block_ld",
             "css_density_matrix_batched", "css_batched_workspace_size", "css_color_batched",
-            "css_color_batched_workspace_size"} <= set(names)
+            "css_color_batched_workspace_size", "css_energy_density_matrix"} <= set(names)
     lib = ctypes.CDLL(css.LIB_PATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
@@ -38,6 +38,15 @@ def test_argument_errors_before_any_device_work():
     assert lib.css_batched_workspace_size(None, 0, 4, 0, 4, ctypes.byref(out_b)) == 1
     out = ctypes.c_size_t(0)
     assert lib.css_workspace_size(0, 0, 0, 1, 1, 0, ctypes.byref(out)) == 1
+    # the energy-weighted call needs the density workspace and one more N x ld block;
+    # without its output array it is an argument error
+    d = ctypes.c_size_t(0)
+    e = ctypes.c_size_t(0)
+    assert lib.css_workspace_size(css.ENTRY_DENSITY, 1000, 50000, 40, 10, css.PREC_FP32, ctypes.byref(d)) == 0
+    assert lib.css_workspace_size(css.ENTRY_ENERGY_DENSITY, 1000, 50000, 40, 10, css.PREC_FP32, ctypes.byref(e)) == 0
+    assert e.value >= d.value + 4 * 1000 * css.block_ld(40)
+    assert lib.css_energy_density_matrix(None, None, None, 40, 0.0, 0.01, 10, 2.0, None, None, 0, 0, None, None,
+                                         None, None, None, None, None, 0, None) == 1
     # shape-only CSR with placeholder pointers: the size checks come before any device work
     csr = css.CsrStruct(1000, 5000, 8, 8, 8, css.CSS_F64)
     assert lib.css_workspace_size(css.ENTRY_SPMM, 1000, 5000, 1, 1, 0, ctypes.byref(out)) == 0

@@ -70,6 +70,18 @@ def test_10k_against_the_oracle():
     assert errs["mixed (bench)"][0] <= 1e-5 and errs["mixed (bench)"][1] <= 1e-7
     assert errs["fp64 full"][0] <= 1e-10 and errs["fp64 full"][1] <= 1e-10
     assert errs["fp64 local (bench comparator)"][0] <= 1e-8 and errs["fp64 local (bench comparator)"][1] <= 1e-10
+    # the energy-weighted estimate, mixed precision, element by element against the oracle
+    eref = D.energy_density_matrix(ws.H.to_scipy(), ref, color, sign, rp, col)
+    xyz = torch.as_tensor(ws.orb_xyz, dtype=torch.float64, device="cuda")
+    g_color, g_b, g_rp, g_col, _ = css.css_color(xyz, [float(x) for x in ws.box], R_CUT)
+    g_sign, _ = css.css_build_probes(g_color, g_b, wl["seed"])
+    _, pe, _, _, pe_trace, _ = css.css_energy_density_matrix(H32, g_color, g_sign, g_b, MU, KT, wl["depth"], g_rp,
+                                                             g_col, bench.flags_for("fp32"))
+    hinf = float(np.max(np.abs(ws.H.to_scipy()).sum(axis=1)))
+    dpe = float(np.max(np.abs(pe.cpu().numpy() - eref["pe_val"])))
+    dtr = abs(pe_trace - eref["pe_trace"]) / abs(eref["pe_trace"])
+    print(f"10k energy-weighted mixed: max|dP_E| {dpe:.3e} (||H||_inf {hinf:.2f})  rel dTr {dtr:.3e}", flush=True)
+    assert dpe <= 1e-5 * hinf and dtr <= 1e-7
 
 
 def test_1m_identities_and_mixed_against_fp64():

@@ -274,6 +274,31 @@ def test_density_fp32_parity(M, seed, depth):
     assert rel_e <= 1e-7
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("M,seed", [(64, 20919), (216, 3)])
+def test_energy_dm_parity(M, seed, prec):
+    """Energy-weighted estimate P_E = (H X) r^T on the pattern against the oracle; P from
+    the same call equals css_density_matrix's bitwise; Tr P_E is the Krylov band energy."""
+    print(f"energy dm {prec} M={M}", flush=True)
+    flags = FP64_FLAGS if prec == "fp64" else FP32_FLAGS
+    ws, H, rp, col, color, b, sign, mu = water_case(M, seed)
+    ref = D.density_matrix(H, color, sign, b, mu, KT, 40, rp, col, reorth="full", cholqr2=True)
+    eref = D.energy_density_matrix(H, ref, color, sign, rp, col)
+    args = (to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, 40, dev_i64(rp), dev_i32(col), flags)
+    p, pe, e_band, trace, pe_trace, info = css.css_energy_density_matrix(*args)
+    p, pe = p.clone(), pe.cpu().numpy()
+    p0, e0, t0, _ = css.css_density_matrix(*args)
+    assert torch.equal(p, p0) and e_band == e0 and trace == t0
+    hinf = float(np.max(np.abs(H).sum(axis=1)))
+    err = np.max(np.abs(pe - eref["pe_val"]))
+    rel_t = abs(pe_trace - eref["pe_trace"]) / abs(eref["pe_trace"])
+    print(f"  max|dP_E|={err:.3e} (||H||_inf {hinf:.2f}) rel dTr={rel_t:.3e}", flush=True)
+    tol = (1e-10 if prec == "fp64" else 1e-5) * hinf
+    assert err <= tol
+    assert rel_t <= (1e-10 if prec == "fp64" else 1e-7)
+    assert abs(pe_trace - info["e_band_krylov"]) <= (1e-9 if prec == "fp64" else 1e-6) * abs(pe_trace)
+
+
 @pytest.mark.parametrize("scale", [2.0 ** -12, 2.0 ** 12, 1000.0])
 def test_mixed_path_follows_energy_scale(scale):
     """P(s H, s mu, s kT) = P(H, mu, kT) for the mixed path, whose FP16 and BF16 operand

@@ -224,6 +224,51 @@ def test_mu_bisection_on_krylov_trace():
     assert ev[K - 1] - 0.05 < mu_k < ev[K] + 0.05 and abs(mu_k - mu_d) < 0.05
 
 
+# ---------------------------------------------------------------- energy-weighted DM
+
+def test_energy_dm_reduces_to_dense_when_b_equals_n():
+    """Every orbital its own colour: rho~_E = H f(H) = sum_i g f(e_i) e_i psi_i psi_i^T."""
+    n = 24
+    rng = np.random.default_rng(8)
+    xyz = rng.uniform(0, 1, size=(n, 3))
+    H = synth.random_symmetric_csr(xyz, np.zeros(3), 10.0, seed=9).to_scipy()
+    rp, col, deg = conflict_pattern(xyz, np.zeros(3), 10.0)
+    color, b = greedy_color(rp, col, deg)
+    sign = probe_signs(n, 3)
+    mu, kT = 0.05, 0.2
+    r = D.density_matrix(H, color, sign, b, mu, kT, 3, rp, col)
+    e = D.energy_density_matrix(H, r, color, sign, rp, col)
+    PE = D.dense_energy_fermi_dm(H, mu, kT)
+    assert np.max(np.abs(e["pe_val"] - PE[D.pattern_rows(rp), col])) < 1e-12
+    assert np.max(np.abs(e["pe_raw"] - e["pe_val"])) < 1e-12
+
+
+def test_energy_dm_closed_form_for_scaled_identity():
+    """H = c I: P_E = c P, diagonal g c f(c)."""
+    n, c = 36, -0.37
+    xyz, box = synth.chain_1d(n, 1.0)
+    rp, col, deg = conflict_pattern(xyz, box, 2.0)
+    color, b = greedy_color(rp, col, deg)
+    H = sp.identity(n, format="csr") * c
+    mu, kT = -0.4, 0.01
+    sign = probe_signs(n, 2)
+    r = D.density_matrix(H, color, sign, b, mu, kT, 5, rp, col)
+    e = D.energy_density_matrix(H, r, color, sign, rp, col)
+    expect = np.where(D.pattern_rows(rp) == col, 2.0 * c * fermi(np.array([c]), mu, kT)[0], 0.0)
+    assert np.max(np.abs(e["pe_val"] - expect)) < 1e-14
+
+
+def test_energy_dm_trace_is_krylov_band_energy():
+    """Tr(P_E raw) = sum_c r_c^T H X_c = Tr(H rho~), the Krylov quadrature sum
+    sum_k lambda_k g f(lambda_k) w_k (exact Lanczos relation); symmetrising keeps the diagonal."""
+    ws, H, rp, col, color, b, sign = small_water(M=64, seed=20919)
+    mu = D.mu_midgap_dense(H, ws.n_electrons)
+    r = D.density_matrix(H, color, sign, b, mu, 0.01, 40, rp, col)
+    e = D.energy_density_matrix(H, r, color, sign, rp, col)
+    assert abs(e["pe_trace"] - r["e_band_krylov"]) < 1e-10 * ws.n
+    assert abs(D.trace_of(e["pe_raw"], rp, col) - e["pe_trace"]) < 1e-12 * ws.n
+
+
 # ---------------------------------------------------------------- planted mistakes
 
 def test_planted_mistakes_are_caught(monkeypatch):
@@ -243,6 +288,26 @@ def test_planted_mistakes_are_caught(monkeypatch):
     # (2) transposed B in T: Phi^T H Phi no longer matches
     Tt = assemble_T(lz.A, [B.T for B in lz.B])
     assert np.max(np.abs(Phi.T @ (H @ Phi) - Tt)) > 1e-3
+
+    # (2b) energy-weighted estimate without the probe signs: the dense pin for b = N
+    #      fails; with H applied on the probe side (X r^T H r instead of H X, which
+    #      coincide when b = N): the Krylov band-energy trace pin fails
+    n = 24
+    rng = np.random.default_rng(8)
+    xyz = rng.uniform(0, 1, size=(n, 3))
+    Hs = synth.random_symmetric_csr(xyz, np.zeros(3), 10.0, seed=9).to_scipy()
+    rps, cols, degs = conflict_pattern(xyz, np.zeros(3), 10.0)
+    cs, bs = greedy_color(rps, cols, degs)
+    ss = probe_signs(n, 3)
+    res = D.density_matrix(Hs, cs, ss, bs, 0.05, 0.2, 3, rps, cols)
+    PE = D.dense_energy_fermi_dm(Hs, 0.05, 0.2)[D.pattern_rows(rps), cols]
+    no_sign = D.gather_raw(Hs @ res["X"], cs, np.ones_like(ss), rps, cols)
+    assert np.max(np.abs(no_sign - PE)) > 1e-3
+    mu_w = D.mu_midgap_dense(H, ws.n_electrons)
+    rw = D.density_matrix(H, color, sign, b, mu_w, 0.01, 40, rp, col)
+    r_probe = probe_block(np.asarray(color), np.asarray(sign), b)
+    wrong_side = D.gather_raw(rw["X"] @ (r_probe.T @ (H @ r_probe)), color, sign, rp, col)
+    assert abs(D.trace_of(wrong_side, rp, col) - rw["e_band_krylov"]) > 1e-3
 
     # (3) wrong sign in the Fermi function: closed form f(mu+t)=1/(e^{t/kT}+1) fails
     monkeypatch.setattr(S, "fermi", lambda x, mu, kT: 1.0 / (1.0 + np.exp(-(np.asarray(x) - mu) / kT)))
