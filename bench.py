@@ -348,6 +348,16 @@ def main():
                                   "density_ms": times["density"] * 1e3, "energy_ms": times["energy"] * 1e3,
                                   "pe_trace": pe_trace, "e_band_krylov": einfo["e_band_krylov"]}
         del r
+        # mu for the workload's electron count from the Krylov quadrature (one Lanczos
+        # pass, dense diagonalisation of T, bisection on the device)
+        css.css_find_mu(H, color, sign, bb, float(ws.n_electrons), KT, depth, flags)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        mu_k, count_k, minfo = css.css_find_mu(H, color, sign, bb, float(ws.n_electrons), KT, depth, flags)
+        torch.cuda.synchronize()
+        out["mu_search"] = {"ms": (time.perf_counter() - t) * 1e3, "mu": mu_k, "count": count_k,
+                            "n_electrons": ws.n_electrons, "mu_used": mu,
+                            "phase_ms": minfo["t_phase_ms"]}
 
     if wl["prec"] == "fp32" and not args.no_fp64:
         p_mixed = state["p_val"].double().cpu()

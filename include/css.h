@@ -78,7 +78,7 @@ enum { CSS_F64 = 0, CSS_F32 = 1 };
 
 /* workspace query selectors */
 enum { CSS_ENTRY_COLOR = 0, CSS_ENTRY_LANCZOS = 1, CSS_ENTRY_DENSITY = 2, CSS_ENTRY_SPMM = 3,
-       CSS_ENTRY_ENERGY_DENSITY = 4 };
+       CSS_ENTRY_ENERGY_DENSITY = 4, CSS_ENTRY_FIND_MU = 5 };
 
 /* Sparse symmetric H in CSR form; all pointers device. Column indices must be
  * sorted within each row; row_ptr[0] = 0, row_ptr[n] = nnz < 2^31. */
@@ -238,6 +238,30 @@ css_status css_energy_density_matrix(const css_csr* H, const int32_t* color, con
                                      int64_t p_nnz, uint32_t flags, double* p_val, double* pe_val,
                                      double* e_band, double* trace, double* pe_trace, css_info* info,
                                      void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * css_find_mu -- the chemical potential for a given electron count (the mu of
+ *   Eq.(1) that an SCF cycle must supply): block Lanczos as in css_density_matrix,
+ *   T = U diag(lambda) U^T by dense diagonalisation (Eq.(7); rocSOLVER dsyevd),
+ *   Krylov quadrature weights w_k = sum_c n_c U[c,k]^2, then bisection for the mu
+ *   at which the quadrature count sum_k g f_mu(lambda_k) w_k (the Krylov estimate
+ *   of Tr P, Eq.(6)-(7)) equals n_electrons. The count is monotone in mu; the
+ *   bracket is [min lambda - 50 kT, max lambda + 50 kT] and the search stops when
+ *   it is narrower than 1e-13 max(1, |ends|).
+ *   H, color, sign, n_colors, kT, depth, spin_deg, flags as css_density_matrix
+ *   (CSS_SUBSPACE_EIG is implied; CSS_SYMMETRIZE has no effect).
+ *   n_electrons  in (0, spin_deg * n), else CSS_E_ARG before any device work
+ *   mu           host out: the chemical potential
+ *   count        host out (may be NULL): the quadrature count at mu
+ *   info         host out (may be NULL): depth_eff, n_colors, breakdown,
+ *                min_diag_r, trace_krylov (= count), t_phase_ms[0..2] (lanczos,
+ *                diagonalisation, bisection) and [5] (total)
+ *   ws           css_workspace_size(CSS_ENTRY_FIND_MU, ...) bytes, device.
+ *   Synchronises the stream before returning.
+ */
+css_status css_find_mu(const css_csr* H, const int32_t* color, const int8_t* sign, int32_t n_colors,
+                       double n_electrons, double kT, int32_t depth, double spin_deg, uint32_t flags,
+                       double* mu, double* count, css_info* info, void* ws, size_t ws_bytes, void* stream);
 
 /* One system of a batch (all arrays device, as for css_density_matrix). */
 typedef struct {

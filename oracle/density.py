@@ -153,3 +153,28 @@ def mu_krylov_bisection(lam: np.ndarray, w: np.ndarray, n_electrons: float, kT: 
         else:
             hi = mid
     return 0.5 * (lo + hi)
+
+
+def find_mu(H, color, sign, n_colors, n_electrons, kT, depth, spin_deg=2.0, reorth=REORTH_FULL,
+            cholqr2=True) -> dict:
+    """The mu of Eq.(1) for a given electron count, from the Krylov quadrature of
+    Tr P (Eqs.(6)-(7)): block Lanczos, the eigenpairs of T, the weights
+    w_k = sum_c n_c U[c,k]^2, then bisection on sum_k g f_mu(lambda_k) w_k."""
+    lz = block_lanczos(H, np.asarray(color), np.asarray(sign), n_colors, depth, reorth=reorth, cholqr2=cholqr2)
+    lam, U = eig_subspace(assemble_T(lz.A, lz.B))
+    w = krylov_weights(U, lz.b0)
+    mu = mu_krylov_bisection(lam, w, n_electrons, kT, spin_deg)
+    return {"mu": mu, "lam": lam, "w": w, "v_eff": lz.v_eff,
+            "count": float(np.sum(spin_deg * fermi(lam, mu, kT) * w))}
+
+
+def krylov_count(lam, w, mu, kT, spin_deg=2.0) -> float:
+    """sum_k g f_mu(lambda_k) w_k."""
+    return float(np.sum(spin_deg * fermi(lam, mu, kT) * w))
+
+
+def krylov_count_slope(lam, w, mu, kT, spin_deg=2.0) -> float:
+    """d/dmu of the quadrature count: (g/kT) sum_k f (1 - f) w_k."""
+    f = fermi(lam, mu, kT)
+    return float(np.sum(spin_deg * f * (1.0 - f) * w) / kT)
+

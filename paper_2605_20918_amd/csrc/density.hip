@@ -130,6 +130,88 @@ __global__ void k_quad_terms(const double* __restrict__ U, const double* __restr
     t1[k] = lam[k] * occ * w;
 }
 
+// Krylov quadrature weights alone: w_k = sum_c n_c U[c,k]^2.
+__global__ void k_quad_weights(const double* __restrict__ U, const int* __restrict__ counts, int nT, int b,
+                               double* __restrict__ w) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nT) return;
+    double acc = 0.0;
+    for (int c = 0; c < b; ++c) {
+        const double u = U[(int64_t)k * nT + c];
+        acc += (double)counts[c] * u * u;
+    }
+    w[k] = acc;
+}
+
+constexpr int kMuThreads = 256;
+constexpr int kMuMaxIter = 400;
+
+// Block-uniform sum over k of g f_mu(lambda_k) w_k in a fixed order (strided
+// per-thread sums, then a fixed tree).
+__device__ double krylov_count(const double* __restrict__ lam, const double* __restrict__ w, int nT, double mu,
+                               double kT, double g, double* sm) {
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nT; k += kMuThreads) acc += g * fermi(lam[k], mu, kT) * w[k];
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kMuThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
+        __syncthreads();
+    }
+    const double r = sm[0];
+    __syncthreads();
+    return r;
+}
+
+// Bisection for the mu at which the Krylov quadrature count equals n_e, on
+// [min lambda - 50 kT, max lambda + 50 kT] (the count is monotone in mu).
+// One workgroup; out = {mu, count at mu, iterations, count at the lower end,
+// count at the upper end}.
+__global__ __launch_bounds__(kMuThreads) void k_mu_bisect(const double* __restrict__ lam, const double* __restrict__ w,
+                                                          int nT, double n_e, double kT, double g, double tol,
+                                                          double* __restrict__ out) {
+    __shared__ double sm[kMuThreads];
+    __shared__ double smx[kMuThreads];
+    double lo = INFINITY, hi = -INFINITY;
+    for (int k = threadIdx.x; k < nT; k += kMuThreads) {
+        lo = fmin(lo, lam[k]);
+        hi = fmax(hi, lam[k]);
+    }
+    sm[threadIdx.x] = lo;
+    smx[threadIdx.x] = hi;
+    __syncthreads();
+    for (int h = kMuThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + h]);
+            smx[threadIdx.x] = fmax(smx[threadIdx.x], smx[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    lo = sm[0] - 50.0 * kT;
+    hi = smx[0] + 50.0 * kT;
+    __syncthreads();
+    const double n_lo = krylov_count(lam, w, nT, lo, kT, g, sm);
+    const double n_hi = krylov_count(lam, w, nT, hi, kT, g, sm);
+    int it = 0;
+    while (hi - lo > tol * fmax(1.0, fmax(fabs(lo), fabs(hi))) && it < kMuMaxIter) {
+        const double mid = 0.5 * (lo + hi);
+        if (krylov_count(lam, w, nT, mid, kT, g, sm) < n_e)
+            lo = mid;
+        else
+            hi = mid;
+        ++it;
+    }
+    const double mu = 0.5 * (lo + hi);
+    const double n_mu = krylov_count(lam, w, nT, mu, kT, g, sm);
+    if (threadIdx.x == 0) {
+        out[0] = mu;
+        out[1] = n_mu;
+        out[2] = (double)it;
+        out[3] = n_lo;
+        out[4] = n_hi;
+    }
+}
+
 // Pattern sanity: row pointers monotone from 0 to nnz, columns in range.
 __global__ void k_validate_pattern(int n, int64_t nnz, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                    int* __restrict__ bad) {
@@ -506,6 +588,77 @@ extern "C" css_status css_energy_density_matrix(const css_csr* H, const int32_t*
                        pe_val, e_band, trace, pe_trace, info, ws, ws_bytes, stream);
 }
 
+extern "C" css_status css_find_mu(const css_csr* H, const int32_t* color, const int8_t* sign, int32_t n_colors,
+                                  double n_electrons, double kT, int32_t depth, double spin_deg, uint32_t flags,
+                                  double* mu, double* count, css_info* info, void* ws, size_t ws_bytes,
+                                  void* stream) {
+    if (!H || !color || !sign || !mu || !ws) return CSS_E_ARG;
+    if (!(kT > 0.0) || !std::isfinite(kT) || !(spin_deg > 0.0) || !std::isfinite(spin_deg)) return CSS_E_ARG;
+    if (!(n_electrons > 0.0) || !(n_electrons < spin_deg * (double)H->n)) return CSS_E_ARG;
+    DmPlan p;
+    CSS_TRY(plan_dm(H, n_colors, depth, flags | CSS_SUBSPACE_EIG, p));
+    if (ws_bytes < dm_workspace_bytes(p)) return CSS_E_WORKSPACE;
+    Arena a;
+    a.base = static_cast<char*>(ws);
+    a.cap = ws_bytes;
+    DmBufs bf;
+    carve_dm(a, p, bf);
+    if (a.overflow) return CSS_E_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    const LzPlan& lz = p.lz;
+
+    hipEvent_t ev[4] = {};
+    for (auto& e : ev) CSS_HIP_TRY(hipEventCreate(&e));
+    struct Guard {
+        hipEvent_t* e;
+        ~Guard() { for (int i = 0; i < 4; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
+    } guard{ev};
+    CSS_HIP_TRY(hipEventRecord(ev[0], s));
+    int v_eff = 0, brk = 0;
+    double md = 0.0;
+    CSS_TRY(run_lanczos_pass1(H, color, sign, lz, bf.lz, s, &v_eff, &brk, &md));
+    CSS_HIP_TRY(hipEventRecord(ev[1], s));
+
+    const int nT = v_eff * lz.b;
+    CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+    k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T, bf.flags);
+    int hbad = 0;
+    CSS_HIP_TRY(hipMemcpyAsync(&hbad, bf.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    if (hbad) return CSS_E_NONFINITE;
+    CSS_TRY(eig(bf.T, nT, bf.lam, bf.E, bf.flags + 1, bf.eig_ws, p.eig_ws, s));
+    CSS_HIP_TRY(hipEventRecord(ev[2], s));
+    k_quad_weights<<<grid_for(nT, 256), 256, 0, s>>>(bf.T, bf.lz.counts, nT, lz.b, bf.t0);
+    k_mu_bisect<<<1, kMuThreads, 0, s>>>(bf.lam, bf.t0, nT, n_electrons, kT, spin_deg, 1e-13, bf.res);
+    CSS_HIP_TRY(hipGetLastError());
+    CSS_HIP_TRY(hipEventRecord(ev[3], s));
+    double hres[5];
+    int hinfo = 0;
+    CSS_HIP_TRY(hipMemcpyAsync(hres, bf.res, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipMemcpyAsync(&hinfo, bf.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    if (hinfo != 0) return CSS_E_EIG;
+    if (!std::isfinite(hres[0]) || !std::isfinite(hres[1])) return CSS_E_NONFINITE;
+    *mu = hres[0];
+    if (count) *count = hres[1];
+    if (info) {
+        *info = css_info{};
+        info->depth_eff = v_eff;
+        info->n_colors = lz.b;
+        info->breakdown = brk;
+        info->spmm_kernel = bf.lz.use_grp ? 1 : 0;
+        info->min_diag_r = md;
+        info->trace_krylov = hres[1];
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess) info->t_phase_ms[k] = ms;
+        }
+        float tot = 0.f;
+        if (hipEventElapsedTime(&tot, ev[0], ev[3]) == hipSuccess) info->t_phase_ms[5] = tot;
+    }
+    return CSS_OK;
+}
+
 extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, int32_t n_colors, int32_t depth,
                                          uint32_t flags, size_t* bytes) {
     if (!bytes || n < 1) return CSS_E_ARG;
@@ -518,7 +671,8 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
         *bytes = spmm_workspace_bytes(n, nnz);
         return CSS_OK;
     }
-    if (entry != CSS_ENTRY_LANCZOS && entry != CSS_ENTRY_DENSITY && entry != CSS_ENTRY_ENERGY_DENSITY)
+    if (entry != CSS_ENTRY_LANCZOS && entry != CSS_ENTRY_DENSITY && entry != CSS_ENTRY_ENERGY_DENSITY &&
+        entry != CSS_ENTRY_FIND_MU)
         return CSS_E_ARG;
     // shape-only CSRs for planning; H's value type is not an argument, so the size
     // covers both (values in the other precision need a converted copy)
@@ -532,7 +686,7 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
             most = std::max(most, lanczos_workspace_bytes(p));
         } else {
             DmPlan p;
-            CSS_TRY(plan_dm(&H, n_colors, depth, flags, p));
+            CSS_TRY(plan_dm(&H, n_colors, depth, entry == CSS_ENTRY_FIND_MU ? (flags | CSS_SUBSPACE_EIG) : flags, p));
             p.energy = entry == CSS_ENTRY_ENERGY_DENSITY;
             most = std::max(most, dm_workspace_bytes(p));
         }

@@ -38,7 +38,7 @@ SIGNS_ONES = 0x80
 SUBSPACE_EIG = 0x100
 SPMM_CSR = 0x200
 
-ENTRY_COLOR, ENTRY_LANCZOS, ENTRY_DENSITY, ENTRY_SPMM, ENTRY_ENERGY_DENSITY = 0, 1, 2, 3, 4
+ENTRY_COLOR, ENTRY_LANCZOS, ENTRY_DENSITY, ENTRY_SPMM, ENTRY_ENERGY_DENSITY, ENTRY_FIND_MU = 0, 1, 2, 3, 4, 5
 
 
 class CssError(RuntimeError):
@@ -120,6 +120,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.css_energy_density_matrix.argtypes = [pcsr, vp, vp, i32, dbl, dbl, i32, dbl, vp, vp, i64, u32, vp, vp,
                                               ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl), pinfo,
                                               vp, sz, vp]
+    lib.css_find_mu.argtypes = [pcsr, vp, vp, i32, dbl, dbl, i32, dbl, u32, ctypes.POINTER(dbl),
+                                ctypes.POINTER(dbl), pinfo, vp, sz, vp]
     lib.css_workspace_size.argtypes = [i32, i32, i64, i32, i32, u32, ctypes.POINTER(sz)]
     lib.css_fermi_poles.argtypes = [i32, vp, vp, ctypes.POINTER(i32)]
     lib.css_fermi_poles.restype = i32
@@ -130,7 +132,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in ("css_color", "css_build_probes", "css_spmm_prepare", "css_spmm", "css_block_lanczos",
                  "css_density_matrix", "css_density_matrix_batched", "css_batched_workspace_size",
                  "css_color_batched", "css_color_batched_workspace_size",
-                 "css_workspace_size"):
+                 "css_energy_density_matrix", "css_find_mu", "css_workspace_size"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -361,6 +363,26 @@ def css_energy_density_matrix(H: DeviceCSR, color, sign, n_colors: int, mu: floa
                                             ctypes.byref(trace), ctypes.byref(pe_trace), ctypes.byref(info),
                                             _ptr(ws), ws.numel(), _stream(dev)))
     return p_val, pe_val, float(e_band.value), float(trace.value), float(pe_trace.value), info.as_dict()
+
+
+def css_find_mu(H: DeviceCSR, color, sign, n_colors: int, n_electrons: float, kT: float, depth: int, flags: int,
+                spin_deg: float = 2.0):
+    """The mu at which the Krylov quadrature count equals n_electrons. Returns
+    (mu, count at mu, info dict)."""
+    dev = color.device
+    ws = workspace(workspace_size(ENTRY_FIND_MU, H.n, H.nnz, n_colors, depth, flags), dev)
+    mu = ctypes.c_double(0.0)
+    count = ctypes.c_double(0.0)
+    info = InfoStruct()
+    csr = H.struct()
+    _check("css_find_mu",
+           load().css_find_mu(ctypes.byref(csr), _ptr(color), _ptr(sign), n_colors, float(n_electrons), float(kT),
+                              depth, float(spin_deg), flags, ctypes.byref(mu), ctypes.byref(count),
+                              ctypes.byref(info), _ptr(ws), ws.numel(), _stream(dev)))
+    d = info.as_dict()
+    d["t_phase_ms"] = {"lanczos": info.t_phase_ms[0], "eig": info.t_phase_ms[1], "bisection": info.t_phase_ms[2],
+                       "total": info.t_phase_ms[5]}
+    return float(mu.value), float(count.value), d
 
 
 def css_density_matrix_batched(systems, kT: float, depth: int, flags: int, concurrency: int = 4,

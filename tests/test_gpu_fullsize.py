@@ -82,6 +82,19 @@ def test_10k_against_the_oracle():
     dtr = abs(pe_trace - eref["pe_trace"]) / abs(eref["pe_trace"])
     print(f"10k energy-weighted mixed: max|dP_E| {dpe:.3e} (||H||_inf {hinf:.2f})  rel dTr {dtr:.3e}", flush=True)
     assert dpe <= 1e-5 * hinf and dtr <= 1e-7
+    # mu for N_e electrons, mixed precision, against the oracle's bisection on its own T
+    from oracle.subspace import eig_subspace
+    lam, U = eig_subspace(ref["T"])
+    w = D.krylov_weights(U, ref["lanczos"].b0)
+    ne = float(ws.n_electrons)
+    mu_ref = D.mu_krylov_bisection(lam, w, ne, KT)
+    mu, count, minfo = css.css_find_mu(H32, g_color, g_sign, g_b, ne, KT, wl["depth"], bench.flags_for("fp32"))
+    resid = abs(D.krylov_count(lam, w, mu, KT) - ne)
+    slope = D.krylov_count_slope(lam, w, mu_ref, KT)
+    print(f"10k mu mixed: {mu:.10f} oracle {mu_ref:.10f} |dmu| {abs(mu - mu_ref):.3e} resid {resid:.3e} "
+          f"slope {slope:.1f} ({minfo['t_phase_ms']['total']:.1f} ms)", flush=True)
+    assert minfo["depth_eff"] == ref["v_eff"]
+    assert resid <= 1e-7 * ne and abs(mu - mu_ref) <= 1e-7 * ne / slope
 
 
 def test_1m_identities_and_mixed_against_fp64():

@@ -299,6 +299,34 @@ def test_energy_dm_parity(M, seed, prec):
     assert abs(pe_trace - info["e_band_krylov"]) <= (1e-9 if prec == "fp64" else 1e-6) * abs(pe_trace)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("M,seed", [(64, 20919), (216, 3)])
+def test_find_mu_parity(M, seed, prec):
+    """mu for N_e = 8 M from the Krylov quadrature count against the oracle's bisection
+    on its own Lanczos: the oracle's count at the GPU's mu is N_e to the trace
+    tolerance (1e-10 N_e in FP64, 1e-7 N_e mixed), and the two mu agree to that
+    tolerance over the count's slope; the density at that mu has trace N_e."""
+    print(f"find mu {prec} M={M}", flush=True)
+    flags = FP64_FLAGS if prec == "fp64" else FP32_FLAGS
+    ws, H, rp, col, color, b, sign, _ = water_case(M, seed)
+    ne = float(ws.n_electrons)
+    ref = D.find_mu(H, color, sign, b, ne, KT, 40, reorth="full", cholqr2=True)
+    Hd, cd, sd = to_dev(ws), dev_i32(color), dev_i8(sign)
+    mu, count, info = css.css_find_mu(Hd, cd, sd, b, ne, KT, 40, flags)
+    assert info["depth_eff"] == ref["v_eff"]
+    tol_n = (1e-10 if prec == "fp64" else 1e-7) * ne
+    resid = abs(D.krylov_count(ref["lam"], ref["w"], mu, KT) - ne)
+    slope = D.krylov_count_slope(ref["lam"], ref["w"], ref["mu"], KT)
+    print(f"  mu={mu:.12f} oracle {ref['mu']:.12f} |dmu|={abs(mu - ref['mu']):.3e} "
+          f"resid={resid:.3e} slope={slope:.2f} count-Ne={count - ne:.3e}", flush=True)
+    assert resid <= tol_n
+    assert abs(mu - ref["mu"]) <= tol_n / slope + 1e-12
+    assert abs(count - ne) <= 1e-12 * ne + 1e-9
+    # the density matrix at that mu holds N_e electrons (Krylov quadrature trace)
+    _, _, _, dinfo = css.css_density_matrix(Hd, cd, sd, b, mu, KT, 40, dev_i64(rp), dev_i32(col), flags)
+    assert abs(dinfo["trace_krylov"] - ne) <= tol_n
+
+
 @pytest.mark.parametrize("scale", [2.0 ** -12, 2.0 ** 12, 1000.0])
 def test_mixed_path_follows_energy_scale(scale):
     """P(s H, s mu, s kT) = P(H, mu, kT) for the mixed path, whose FP16 and BF16 operand

@@ -224,6 +224,39 @@ def test_mu_bisection_on_krylov_trace():
     assert ev[K - 1] - 0.05 < mu_k < ev[K] + 0.05 and abs(mu_k - mu_d) < 0.05
 
 
+def test_find_mu_equals_dense_root_when_b_equals_n():
+    """Every orbital its own colour: the quadrature is exact (nodes = eigenvalues of
+    H, weights 1), so mu is the root of sum_i g f_mu(e_i) = N_e, found here by
+    scipy's brentq on a dense eigendecomposition."""
+    from scipy.optimize import brentq
+    n = 30
+    rng = np.random.default_rng(21)
+    A = rng.normal(size=(n, n)) * 0.1
+    Hd = 0.5 * (A + A.T)
+    H = sp.csr_matrix(Hd)
+    color = np.arange(n, dtype=np.int32)
+    sign = probe_signs(n, 5)
+    ev = np.linalg.eigvalsh(Hd)
+    for kT, ne in ((0.02, 23.0), (0.05, 31.7), (0.2, 1.5)):
+        r = D.find_mu(H, color, sign, n, ne, kT, 2)
+        assert r["v_eff"] == 1
+        root = brentq(lambda m: np.sum(2.0 / (np.exp((ev - m) / kT) + 1.0)) - ne, ev[0] - 3, ev[-1] + 3,
+                      xtol=1e-15, rtol=1e-15)
+        assert abs(r["mu"] - root) < 1e-11, (kT, ne, r["mu"], root)
+
+
+def test_find_mu_closed_form_for_scaled_identity():
+    """H = c I: the count is g N f(c; mu), so mu = c - kT ln(g N / N_e - 1)."""
+    ws, H0, rp, col, color, b, sign = small_water(M=64, seed=20919)
+    n = H0.shape[0]
+    c = -0.37
+    H = sp.identity(n, format="csr") * c
+    for ne in (0.2 * n, 1.0 * n, 1.7 * n):
+        r = D.find_mu(H, color, sign, b, ne, 0.01, 10)
+        assert r["v_eff"] == 1
+        assert abs(r["mu"] - (c - 0.01 * np.log(2.0 * n / ne - 1.0))) < 1e-12
+
+
 # ---------------------------------------------------------------- energy-weighted DM
 
 def test_energy_dm_reduces_to_dense_when_b_equals_n():
@@ -308,6 +341,19 @@ def test_planted_mistakes_are_caught(monkeypatch):
     r_probe = probe_block(np.asarray(color), np.asarray(sign), b)
     wrong_side = D.gather_raw(rw["X"] @ (r_probe.T @ (H @ r_probe)), color, sign, rp, col)
     assert abs(D.trace_of(wrong_side, rp, col) - rw["e_band_krylov"]) > 1e-3
+
+    # (2c) quadrature weights from |U| instead of U^2: the dense-root pin for b = N fails
+    from scipy.optimize import brentq
+    n = 30
+    rng = np.random.default_rng(21)
+    A = rng.normal(size=(n, n)) * 0.1
+    Hd = 0.5 * (A + A.T)
+    lam, U = np.linalg.eigh(Hd)
+    w_bad = np.abs(U[:n, :]).sum(axis=0)
+    mu_bad = D.mu_krylov_bisection(lam, w_bad, 23.0, 0.02)
+    root = brentq(lambda m: np.sum(2.0 / (np.exp((lam - m) / 0.02) + 1.0)) - 23.0, lam[0] - 3, lam[-1] + 3,
+                  xtol=1e-15, rtol=1e-15)
+    assert abs(mu_bad - root) > 1e-3
 
     # (3) wrong sign in the Fermi function: closed form f(mu+t)=1/(e^{t/kT}+1) fails
     monkeypatch.setattr(S, "fermi", lambda x, mu, kT: 1.0 / (1.0 + np.exp(-(np.asarray(x) - mu) / kT)))
