@@ -21,7 +21,7 @@ from __future__ import annotations
 import numpy as np
 
 from .lanczos import REORTH_FULL, assemble_T, block_lanczos
-from .subspace import contraction, eig_subspace, fermi
+from .subspace import contraction, eig_subspace, fermi, inv_sqrt_contraction
 
 
 def reconstruct_X(Q: list, F: np.ndarray) -> np.ndarray:
@@ -177,4 +177,25 @@ def krylov_count_slope(lam, w, mu, kT, spin_deg=2.0) -> float:
     """d/dmu of the quadrature count: (g/kT) sum_k f (1 - f) w_k."""
     f = fermi(lam, mu, kT)
     return float(np.sum(spin_deg * f * (1.0 - f) * w) / kT)
+
+
+def inv_sqrt_matrix(S, color, sign, n_colors, depth, p_row_ptr, p_col, reorth=REORTH_FULL, cholqr2=True,
+                    symmetrize_p=True) -> dict:
+    """The CSS estimate of S^(-1/2) on the pattern (the overlap step of the
+    non-orthogonal case): block Lanczos on S from the probes o, the projected
+    overlap T = U diag(lambda) U^T, Y = Psi U diag(lambda^(-1/2)) U^T Psi^T o,
+    read off as P is: S^(-1/2)_mn = o_n-component of Y[m]."""
+    color = np.asarray(color)
+    sign = np.asarray(sign)
+    lz = block_lanczos(S, color, sign, n_colors, depth, reorth=reorth, cholqr2=cholqr2)
+    T = assemble_T(lz.A, lz.B)
+    lam, U = eig_subspace(T)
+    F, trace_k, half_k = inv_sqrt_contraction(lam, U, lz.b0)
+    Y = reconstruct_X(lz.Q, F)
+    y_raw = gather_raw(Y, color, sign, p_row_ptr, p_col)
+    y_sym = symmetrize(y_raw, p_row_ptr, p_col)
+    y_val = y_sym if symmetrize_p else y_raw
+    return {"y_val": y_val, "y_raw": y_raw, "Y": Y, "lam": lam, "v_eff": lz.v_eff, "lanczos": lz,
+            "trace": trace_of(y_val, p_row_ptr, p_col), "trace_krylov": trace_k,
+            "s_dot": band_energy(S, y_val, p_row_ptr, p_col), "half_krylov": half_k}
 

@@ -53,3 +53,20 @@ def contraction(lam: np.ndarray, U: np.ndarray, b0: np.ndarray, mu: float, kT: f
     trace_k = float(np.sum(occ * w))
     e_k = float(np.sum(lam * occ * w))
     return F, trace_k, e_k
+
+
+def inv_sqrt_contraction(lam: np.ndarray, U: np.ndarray, b0: np.ndarray):
+    """The same contraction for f(x) = x^(-1/2) (the Krylov estimate of S^(-1/2) applied
+    to the probes, from the eigenpairs of the projected overlap): F (n_T x b),
+    the quadrature trace sum_k lambda_k^(-1/2) w_k and sum_k lambda_k^(1/2) w_k.
+    The projected matrix must be positive definite."""
+    if np.any(lam <= 0.0):
+        raise ValueError("projected overlap is not positive definite")
+    b = b0.shape[0]
+    occ = 1.0 / np.sqrt(lam)
+    Utop = U[:b, :]
+    F = (U * occ[None, :]) @ Utop.T
+    F = F * b0[None, :]
+    w = (b0[:, None] ** 2 * Utop ** 2).sum(axis=0)
+    return F, float(np.sum(occ * w)), float(np.sum(np.sqrt(lam) * w))
+

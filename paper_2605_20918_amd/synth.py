@@ -26,6 +26,10 @@ stand-in with the same shapes is generated:
   pattern is purely geometric.
 
 H is returned as CSR with int32 column indices sorted within each row.
+
+For the non-orthogonal case an overlap matrix S of the same pattern is
+generated too (`overlap_s`, `water_overlap`): 1 on the diagonal and a
+positive two-centre term with the same angular factors as the hopping.
 """
 from __future__ import annotations
 
@@ -45,6 +49,8 @@ ONSITE_NOISE = 0.01       # Ha, standard deviation
 HOP_T0 = -0.4             # Ha
 HOP_DECAY = 1.0           # Angstrom
 HOP_CUT = 5.0             # Angstrom
+OVL_S0 = 0.4              # overlap amplitude (dimensionless)
+OVL_DECAY = 1.0           # Angstrom
 ORB_PER_MOL = 6
 ELECTRONS_PER_MOL = 8
 KT_DEFAULT = 0.01         # Ha
@@ -152,16 +158,9 @@ def _atom_pairs(atoms: np.ndarray, L: float, cut: float):
 
 
 def tight_binding_h(atoms: np.ndarray, L: float, rng, n_mol: int, progress=None) -> CSR:
-    n_atoms = atoms.shape[0]
-    is_o = (np.arange(n_atoms) % 3) == 0
-    n_orb_atom = np.where(is_o, 4, 1)
-    first_orb = np.zeros(n_atoms, dtype=np.int64)
-    first_orb[1:] = np.cumsum(n_orb_atom)[:-1]
-    N = int(n_orb_atom.sum())
-
-    rows, cols, vals = [], [], []
-
-    # same-atom blocks: onsite on the diagonal, explicit zeros off it
+    is_o = (np.arange(atoms.shape[0]) % 3) == 0
+    first_orb, N = _orbital_offsets(is_o)
+    # onsite energies with their noise (the only random draw of H)
     onsite = np.empty(N)
     o_first = first_orb[is_o]
     h_first = first_orb[~is_o]
@@ -170,25 +169,58 @@ def tight_binding_h(atoms: np.ndarray, L: float, rng, n_mol: int, progress=None)
         onsite[o_first + k] = ONSITE_O_P
     onsite[h_first] = ONSITE_H_S
     onsite = onsite + rng.normal(0.0, ONSITE_NOISE, size=N)
+    return _two_centre_matrix(atoms, L, onsite, HOP_T0, HOP_DECAY, HOP_CUT, "H", progress)
+
+
+def overlap_s(atoms: np.ndarray, L: float, progress=None) -> CSR:
+    """A non-orthogonal basis' overlap matrix on the same atoms: 1 on the diagonal
+    and s(r) g_a(u) g_b(-u), s(r) = 0.4 exp(-r / 1 Angstrom), between orbitals
+    of different atoms closer than 5 Angstrom (the same angular factors and
+    pattern as H). On water boxes its spectrum lies in about [0.76, 1.84]."""
+    is_o = (np.arange(atoms.shape[0]) % 3) == 0
+    _, N = _orbital_offsets(is_o)
+    return _two_centre_matrix(atoms, L, np.ones(N), OVL_S0, OVL_DECAY, HOP_CUT, "S", progress)
+
+
+def _orbital_offsets(is_o: np.ndarray):
+    n_orb_atom = np.where(is_o, 4, 1)
+    first_orb = np.zeros(is_o.size, dtype=np.int64)
+    first_orb[1:] = np.cumsum(n_orb_atom)[:-1]
+    return first_orb, int(n_orb_atom.sum())
+
+
+def _two_centre_matrix(atoms: np.ndarray, L: float, diag: np.ndarray, t0: float, decay: float, cut: float,
+                       name: str, progress=None) -> CSR:
+    """diag on the diagonal, explicit zeros between different orbitals of one atom,
+    t0 exp(-r / decay) g_a(u) g_b(-u) between orbitals of atoms closer than cut."""
+    n_atoms = atoms.shape[0]
+    is_o = (np.arange(n_atoms) % 3) == 0
+    first_orb, N = _orbital_offsets(is_o)
+
+    rows, cols, vals = [], [], []
+
+    # same-atom blocks: diag on the diagonal, explicit zeros off it
+    o_first = first_orb[is_o]
+    h_first = first_orb[~is_o]
     for a in range(4):
         for b in range(4):
             rows.append(o_first + a)
             cols.append(o_first + b)
-            vals.append(onsite[o_first + a] if a == b else np.zeros(o_first.size))
+            vals.append(diag[o_first + a] if a == b else np.zeros(o_first.size))
     rows.append(h_first)
     cols.append(h_first)
-    vals.append(onsite[h_first])
+    vals.append(diag[h_first])
 
-    # inter-atomic hopping, each pair computed once and mirrored
-    pairs = _atom_pairs(atoms, L, HOP_CUT)
+    # inter-atomic terms, each pair computed once and mirrored
+    pairs = _atom_pairs(atoms, L, cut)
     if progress:
-        progress(f"{pairs.shape[0]} atom pairs within {HOP_CUT} A")
+        progress(f"{pairs.shape[0]} atom pairs within {cut} A")
     A, B = pairs[:, 0], pairs[:, 1]
     d = atoms[B] - atoms[A]
     d -= L * np.rint(d / L)
     r = np.sqrt((d * d).sum(axis=1))
     u = d / r[:, None]
-    t = HOP_T0 * np.exp(-r / HOP_DECAY)
+    t = t0 * np.exp(-r / decay)
 
     def gvec(is_oxygen, uvec):
         # angular factors per orbital of an atom: [s, px, py, pz] (O) or [s] (H)
@@ -196,7 +228,7 @@ def tight_binding_h(atoms: np.ndarray, L: float, rng, n_mol: int, progress=None)
 
     for oa in (True, False):
         if progress:
-            progress(f"hopping blocks from {'O' if oa else 'H'} atoms")
+            progress(f"{name} blocks from {'O' if oa else 'H'} atoms")
         for ob in (True, False):
             sel = (is_o[A] == oa) & (is_o[B] == ob)
             if not np.any(sel):
@@ -216,7 +248,7 @@ def tight_binding_h(atoms: np.ndarray, L: float, rng, n_mol: int, progress=None)
     col = np.concatenate(cols).astype(np.int32)
     val = np.concatenate(vals).astype(np.float64)
     if row.size >= 2 ** 31:
-        raise ValueError("H has too many nonzeros for int32 row pointers")
+        raise ValueError(f"{name} has too many nonzeros for int32 row pointers")
     # CSR with sorted columns; every (row, col) occurs once, so nothing is summed
     import scipy.sparse as sp
     if progress:
@@ -224,7 +256,7 @@ def tight_binding_h(atoms: np.ndarray, L: float, rng, n_mol: int, progress=None)
     m = sp.csr_matrix((val, (row, col)), shape=(N, N))
     m.sort_indices()
     if m.nnz != row.size:
-        raise AssertionError("duplicate orbital pair in H")
+        raise AssertionError(f"duplicate orbital pair in {name}")
     return CSR(N, m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.astype(np.float64))
 
 
@@ -241,6 +273,11 @@ def water_system(n_mol: int, seed: int, edge: float | None = None, progress=None
     orb_xyz = atoms[orb_atom]
     return WaterSystem(n_mol, box, atoms, np.ascontiguousarray(orb_xyz), orb_atom, H, seed,
                        meta={"edge": float(box[0]), "grid": _grid_size(n_mol)})
+
+
+def water_overlap(ws: WaterSystem, progress=None) -> CSR:
+    """The overlap matrix S of a water box (see `overlap_s`); it draws no random numbers."""
+    return overlap_s(ws.atom_xyz, float(ws.box[0]), progress)
 
 
 def chain_1d(n_sites: int, spacing: float = 1.0):

@@ -257,6 +257,47 @@ def test_find_mu_closed_form_for_scaled_identity():
         assert abs(r["mu"] - (c - 0.01 * np.log(2.0 * n / ne - 1.0))) < 1e-12
 
 
+# ---------------------------------------------------------------- overlap S^(-1/2)
+
+def test_inv_sqrt_reduces_to_dense_when_b_equals_n():
+    """Every orbital its own colour: the Krylov space is exhausted after one block and
+    the estimate is S^(-1/2) itself, here from scipy's fractional_matrix_power."""
+    import scipy.linalg as sla
+    n = 24
+    rng = np.random.default_rng(8)
+    xyz = rng.uniform(0, 1, size=(n, 3))
+    A = synth.random_symmetric_csr(xyz, np.zeros(3), 10.0, seed=9).to_scipy().toarray()
+    S = np.eye(n) + 0.3 * A / np.max(np.abs(np.linalg.eigvalsh(A)))
+    rp, col, _ = conflict_pattern(xyz, np.zeros(3), 10.0)
+    color = np.arange(n, dtype=np.int32)
+    r = D.inv_sqrt_matrix(sp.csr_matrix(S), color, probe_signs(n, 4), n, 3, rp, col)
+    ref = sla.fractional_matrix_power(S, -0.5).real
+    assert r["v_eff"] == 1
+    assert np.max(np.abs(r["y_val"] - ref[D.pattern_rows(rp), col])) < 1e-12
+
+
+def test_inv_sqrt_closed_form_for_scaled_identity():
+    """S = c I: c^(-1/2) on the diagonal, zero elsewhere."""
+    ws, H, rp, col, color, b, sign = small_water(M=64, seed=20919)
+    c = 1.7
+    r = D.inv_sqrt_matrix(sp.identity(ws.n, format="csr") * c, color, sign, b, 10, rp, col)
+    rows = D.pattern_rows(rp)
+    want = np.where(rows == col, c ** -0.5, 0.0)
+    assert np.max(np.abs(r["y_val"] - want)) < 1e-14
+
+
+def test_inv_sqrt_krylov_identities_on_water_overlap():
+    """Tr(o^T Y) = sum_k lambda_k^(-1/2) w_k and Tr(o^T S Y) = sum_k lambda_k^(1/2) w_k
+    (the Lanczos relation, S's pattern inside the cutoff pattern); S is positive
+    definite, so every Ritz value is too."""
+    ws, H, rp, col, color, b, sign = small_water(M=216, seed=3)
+    S = synth.water_overlap(ws).to_scipy()
+    r = D.inv_sqrt_matrix(S, color, sign, b, 10, rp, col)
+    assert r["v_eff"] == 10 and np.all(r["lam"] > 0.5)
+    assert abs(D.trace_of(r["y_raw"], rp, col) - r["trace_krylov"]) < 1e-11 * ws.n
+    assert abs(D.band_energy(S, r["y_raw"], rp, col) - r["half_krylov"]) < 1e-11 * ws.n
+
+
 # ---------------------------------------------------------------- energy-weighted DM
 
 def test_energy_dm_reduces_to_dense_when_b_equals_n():
@@ -354,6 +395,17 @@ def test_planted_mistakes_are_caught(monkeypatch):
     root = brentq(lambda m: np.sum(2.0 / (np.exp((lam - m) / 0.02) + 1.0)) - 23.0, lam[0] - 3, lam[-1] + 3,
                   xtol=1e-15, rtol=1e-15)
     assert abs(mu_bad - root) > 1e-3
+
+    # (2d) S^(-1/2) with lambda^(-1) in place of lambda^(-1/2): the dense pin fails
+    import scipy.linalg as sla
+    ns = Hs.shape[0]
+    Sd = np.eye(ns) + 0.3 * Hs.toarray() / np.max(np.abs(np.linalg.eigvalsh(Hs.toarray())))
+    lz1 = L.block_lanczos(sp.csr_matrix(Sd), np.arange(ns), ss, ns, 3)
+    lam1, U1 = eig_subspace(assemble_T(lz1.A, lz1.B))
+    F_bad = (U1 / lam1[None, :]) @ U1[:ns, :].T * lz1.b0[None, :]
+    Y_bad = D.reconstruct_X(lz1.Q, F_bad)
+    S_half = sla.fractional_matrix_power(Sd, -0.5).real
+    assert np.max(np.abs(Y_bad @ probe_block(np.arange(ns), ss, ns).T - S_half)) > 1e-2
 
     # (3) wrong sign in the Fermi function: closed form f(mu+t)=1/(e^{t/kT}+1) fails
     monkeypatch.setattr(S, "fermi", lambda x, mu, kT: 1.0 / (1.0 + np.exp(-(np.asarray(x) - mu) / kT)))
