@@ -358,6 +358,18 @@ def main():
         out["mu_search"] = {"ms": (time.perf_counter() - t) * 1e3, "mu": mu_k, "count": count_k,
                             "n_electrons": ws.n_electrons, "mu_used": mu,
                             "phase_ms": minfo["t_phase_ms"]}
+        # S^(-1/2) of the overlap matrix on the same pattern (non-orthogonal basis), v^s = 10
+        So = synth.water_overlap(ws)
+        Sdev = css.DeviceCSR.from_host(So.row_ptr, So.col, So.val, dev, torch.float32)
+        inv_args = (Sdev, color, sign, bb, 10, p_rp, p_col, flags)
+        css.css_inv_sqrt_overlap(*inv_args)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, ytr, _, yinfo = css.css_inv_sqrt_overlap(*inv_args)
+        torch.cuda.synchronize()
+        out["inv_sqrt_overlap"] = {"ms": (time.perf_counter() - t) * 1e3, "depth": 10,
+                                   "depth_eff": yinfo["depth_eff"], "trace": ytr, "phase_ms": yinfo["t_phase_ms"]}
+        del Sdev
 
     if wl["prec"] == "fp32" and not args.no_fp64:
         p_mixed = state["p_val"].double().cpu()

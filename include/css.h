@@ -78,7 +78,7 @@ enum { CSS_F64 = 0, CSS_F32 = 1 };
 
 /* workspace query selectors */
 enum { CSS_ENTRY_COLOR = 0, CSS_ENTRY_LANCZOS = 1, CSS_ENTRY_DENSITY = 2, CSS_ENTRY_SPMM = 3,
-       CSS_ENTRY_ENERGY_DENSITY = 4, CSS_ENTRY_FIND_MU = 5 };
+       CSS_ENTRY_ENERGY_DENSITY = 4, CSS_ENTRY_FIND_MU = 5, CSS_ENTRY_INV_SQRT = 6 };
 
 /* Sparse symmetric H in CSR form; all pointers device. Column indices must be
  * sorted within each row; row_ptr[0] = 0, row_ptr[n] = nnz < 2^31. */
@@ -238,6 +238,40 @@ css_status css_energy_density_matrix(const css_csr* H, const int32_t* color, con
                                      int64_t p_nnz, uint32_t flags, double* p_val, double* pe_val,
                                      double* e_band, double* trace, double* pe_trace, css_info* info,
                                      void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * css_inv_sqrt_overlap -- the CSS estimate of S^(-1/2) on a cutoff pattern, for a
+ *   non-orthogonal basis (the overlap step that precedes H' = S^(-1/2) H S^(-1/2):
+ *   S^(-1/2) taken as -1/pi Im of the integral of z^(-1/2) G_S(z), projected onto
+ *   coloured probes o). The same path as css_density_matrix with S in place of H
+ *   and x^(-1/2) in place of g f(x): block Lanczos on S from the probes, the
+ *   projected overlap T = U diag(lambda) U^T by dense diagonalisation (rocSOLVER
+ *   dsyevd), Y = sum_j Q_j F_j with F = U diag(lambda^(-1/2)) U[0:b,:]^T B_0, then
+ *   y_mn = sign[n] Y[m, colour(n)] on the pattern (symmetrised with
+ *   CSS_SYMMETRIZE).
+ *   S            device CSR, symmetric positive definite (the overlap matrix)
+ *   color, sign, n_colors   the probes o (css_color / css_build_probes on the
+ *                overlap's cutoff)
+ *   depth        Krylov blocks v^s
+ *   p_row_ptr, p_col, p_nnz  the pattern S^(-1/2) is read on (device, as for
+ *                css_density_matrix)
+ *   flags        as css_density_matrix (CSS_SUBSPACE_EIG is implied)
+ *   y_val        device double[p_nnz] out: S^(-1/2) on the pattern
+ *   trace        host out: sum_m y_mm
+ *   s_dot        host out (may be NULL): sum over entries of S in the pattern of
+ *                S_mn y_mn (an estimate of Tr S^(1/2))
+ *   info         host out (may be NULL): as css_density_matrix, with
+ *                trace_krylov = sum_k lambda_k^(-1/2) w_k and
+ *                e_band_krylov = sum_k lambda_k^(1/2) w_k
+ *   ws           css_workspace_size(CSS_ENTRY_INV_SQRT, ...) bytes, device.
+ *   Errors as css_density_matrix; CSS_E_NONFINITE also when a Ritz value of S is
+ *   <= 0 (S not positive definite). Synchronises the stream before returning.
+ */
+css_status css_inv_sqrt_overlap(const css_csr* S, const int32_t* color, const int8_t* sign,
+                                int32_t n_colors, int32_t depth, const int64_t* p_row_ptr,
+                                const int32_t* p_col, int64_t p_nnz, uint32_t flags, double* y_val,
+                                double* trace, double* s_dot, css_info* info, void* ws,
+                                size_t ws_bytes, void* stream);
 
 /*
  * css_find_mu -- the chemical potential for a given electron count (the mu of

@@ -104,20 +104,29 @@ __device__ __forceinline__ double fermi(double x, double mu, double kT) {
     return 1.0 / (1.0 + exp(t));
 }
 
-// Y[k][c] = g f(lambda_k) U[c][k] sqrt(n_c)   (nT x b, row-major)
+// The function of the projected matrix: g f(x) (Fermi, Eq.(1)) or x^(-1/2) (the
+// overlap's inverse square root, 1/sqrt(x) with IEEE sqrt and division).
+enum SubFn { kFnFermi = 0, kFnInvSqrt = 1 };
+
+__device__ __forceinline__ double sub_fn(int fn, double x, double mu, double kT, double g) {
+    return fn == kFnInvSqrt ? 1.0 / sqrt(x) : g * fermi(x, mu, kT);
+}
+
+// Y[k][c] = fn(lambda_k) U[c][k] sqrt(n_c)   (nT x b, row-major)
 __global__ void k_occ_y(const double* __restrict__ U, const double* __restrict__ lam, const int* __restrict__ counts,
-                        int nT, int b, double mu, double kT, double g, double* __restrict__ Y) {
+                        int nT, int b, int fn, double mu, double kT, double g, double* __restrict__ Y) {
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (idx >= (int64_t)nT * b) return;
     const int k = (int)(idx / b), c = (int)(idx % b);
-    const double occ = g * fermi(lam[k], mu, kT);
+    const double occ = sub_fn(fn, lam[k], mu, kT, g);
     Y[idx] = occ * U[(int64_t)k * nT + c] * sqrt((double)counts[c]);
 }
 
-// Per-eigenpair quadrature terms: t0 = g f w, t1 = lambda g f w
+// Per-eigenpair quadrature terms: t0 = fn(lambda) w, t1 = lambda fn(lambda) w; with
+// x^(-1/2) a Ritz value <= 0 (overlap not positive definite) sets *bad.
 __global__ void k_quad_terms(const double* __restrict__ U, const double* __restrict__ lam,
-                             const int* __restrict__ counts, int nT, int b, double mu, double kT, double g,
-                             double* __restrict__ t0, double* __restrict__ t1) {
+                             const int* __restrict__ counts, int nT, int b, int fn, double mu, double kT, double g,
+                             double* __restrict__ t0, double* __restrict__ t1, int* __restrict__ bad) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nT) return;
     double w = 0.0;
@@ -125,7 +134,8 @@ __global__ void k_quad_terms(const double* __restrict__ U, const double* __restr
         const double u = U[(int64_t)k * nT + c];
         w += (double)counts[c] * u * u;
     }
-    const double occ = g * fermi(lam[k], mu, kT);
+    if (fn == kFnInvSqrt && !(lam[k] > 0.0)) atomicOr(bad, 1);
+    const double occ = sub_fn(fn, lam[k], mu, kT, g);
     t0[k] = occ * w;
     t1[k] = lam[k] * occ * w;
 }
@@ -424,9 +434,11 @@ namespace {
 css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, int32_t n_colors, double mu, double kT,
                   int32_t depth, double spin_deg, const int64_t* p_row_ptr, const int32_t* p_col, int64_t p_nnz,
                   uint32_t flags, double* p_val, double* pe_val, double* e_band, double* trace, double* pe_trace,
-                  css_info* info, void* ws, size_t ws_bytes, void* stream) {
+                  css_info* info, void* ws, size_t ws_bytes, void* stream, int fn = kFnFermi) {
     if (!color || !sign || !p_row_ptr || !p_col || !p_val || !e_band || !trace || !ws || p_nnz < 1) return CSS_E_ARG;
-    if (!(kT > 0.0) || !std::isfinite(kT) || !std::isfinite(mu) || !(spin_deg > 0.0)) return CSS_E_ARG;
+    if (fn == kFnFermi && (!(kT > 0.0) || !std::isfinite(kT) || !std::isfinite(mu) || !(spin_deg > 0.0)))
+        return CSS_E_ARG;
+    if (fn == kFnInvSqrt) flags |= CSS_SUBSPACE_EIG;
     DmPlan p;
     CSS_TRY(plan_dm(H, n_colors, depth, flags, p));
     p.energy = pe_val != nullptr;
@@ -476,11 +488,11 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
         if (hbad) return CSS_E_NONFINITE;
         CSS_TRY(eig(bf.T, nT, bf.lam, bf.E, bf.flags + 1, bf.eig_ws, p.eig_ws, s));
         CSS_HIP_TRY(hipEventRecord(ev[2], s));
-        k_occ_y<<<grid_for((int64_t)nT * lz.b, 256), 256, 0, s>>>(bf.T, bf.lam, bf.lz.counts, nT, lz.b, mu, kT,
+        k_occ_y<<<grid_for((int64_t)nT * lz.b, 256), 256, 0, s>>>(bf.T, bf.lam, bf.lz.counts, nT, lz.b, fn, mu, kT,
                                                                     spin_deg, bf.Y);
         gemm_f64_launch(nT, lz.b, nT, bf.T, 1, nT, bf.Y, lz.b, 1, bf.F, lz.b, 1, s);
-        k_quad_terms<<<grid_for(nT, 256), 256, 0, s>>>(bf.T, bf.lam, bf.lz.counts, nT, lz.b, mu, kT, spin_deg, bf.t0,
-                                                       bf.t1);
+        k_quad_terms<<<grid_for(nT, 256), 256, 0, s>>>(bf.T, bf.lam, bf.lz.counts, nT, lz.b, fn, mu, kT, spin_deg,
+                                                       bf.t0, bf.t1, bf.flags + 2);
         det_sum(bf.t0, nT, bf.tmp, bf.res + 2, s);
         det_sum(bf.t1, nT, bf.tmp + kSumBlocks, bf.res + 3, s);
     } else {
@@ -535,12 +547,13 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     }
     CSS_HIP_TRY(hipEventRecord(ev[5], s));
     double hres[8];
-    int hinfo = 0;
+    int hinfo[2] = {0, 0};
     CSS_HIP_TRY(hipMemcpyAsync(hres, bf.res, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
-    CSS_HIP_TRY(hipMemcpyAsync(&hinfo, bf.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipMemcpyAsync(hinfo, bf.flags + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     CSS_HIP_TRY(hipStreamSynchronize(s));
     CSS_HIP_TRY(hipGetLastError());
-    if (hinfo != 0) return CSS_E_EIG;
+    if (hinfo[0] != 0) return CSS_E_EIG;
+    if (hinfo[1] != 0) return CSS_E_NONFINITE;
     *trace = hres[0];
     *e_band = hres[1];
     if (pe_val && pe_trace) *pe_trace = hres[5];
@@ -586,6 +599,19 @@ extern "C" css_status css_energy_density_matrix(const css_csr* H, const int32_t*
     if (!pe_val) return CSS_E_ARG;
     return css::dm_run(H, color, sign, n_colors, mu, kT, depth, spin_deg, p_row_ptr, p_col, p_nnz, flags, p_val,
                        pe_val, e_band, trace, pe_trace, info, ws, ws_bytes, stream);
+}
+
+extern "C" css_status css_inv_sqrt_overlap(const css_csr* S, const int32_t* color, const int8_t* sign,
+                                           int32_t n_colors, int32_t depth, const int64_t* p_row_ptr,
+                                           const int32_t* p_col, int64_t p_nnz, uint32_t flags, double* y_val,
+                                           double* trace, double* s_dot, css_info* info, void* ws, size_t ws_bytes,
+                                           void* stream) {
+    if (!trace) return CSS_E_ARG;
+    double sd = 0.0;
+    CSS_TRY(css::dm_run(S, color, sign, n_colors, 0.0, 1.0, depth, 1.0, p_row_ptr, p_col, p_nnz, flags, y_val,
+                        nullptr, &sd, trace, nullptr, info, ws, ws_bytes, stream, css::kFnInvSqrt));
+    if (s_dot) *s_dot = sd;
+    return CSS_OK;
 }
 
 extern "C" css_status css_find_mu(const css_csr* H, const int32_t* color, const int8_t* sign, int32_t n_colors,
@@ -672,7 +698,7 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
         return CSS_OK;
     }
     if (entry != CSS_ENTRY_LANCZOS && entry != CSS_ENTRY_DENSITY && entry != CSS_ENTRY_ENERGY_DENSITY &&
-        entry != CSS_ENTRY_FIND_MU)
+        entry != CSS_ENTRY_FIND_MU && entry != CSS_ENTRY_INV_SQRT)
         return CSS_E_ARG;
     // shape-only CSRs for planning; H's value type is not an argument, so the size
     // covers both (values in the other precision need a converted copy)
@@ -686,7 +712,8 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
             most = std::max(most, lanczos_workspace_bytes(p));
         } else {
             DmPlan p;
-            CSS_TRY(plan_dm(&H, n_colors, depth, entry == CSS_ENTRY_FIND_MU ? (flags | CSS_SUBSPACE_EIG) : flags, p));
+            const bool eig = entry == CSS_ENTRY_FIND_MU || entry == CSS_ENTRY_INV_SQRT;
+            CSS_TRY(plan_dm(&H, n_colors, depth, eig ? (flags | CSS_SUBSPACE_EIG) : flags, p));
             p.energy = entry == CSS_ENTRY_ENERGY_DENSITY;
             most = std::max(most, dm_workspace_bytes(p));
         }

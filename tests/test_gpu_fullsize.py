@@ -95,6 +95,16 @@ def test_10k_against_the_oracle():
           f"slope {slope:.1f} ({minfo['t_phase_ms']['total']:.1f} ms)", flush=True)
     assert minfo["depth_eff"] == ref["v_eff"]
     assert resid <= 1e-7 * ne and abs(mu - mu_ref) <= 1e-7 * ne / slope
+    # S^(-1/2) of the overlap, mixed precision, v^s = 10, against the oracle
+    So = synth.water_overlap(ws)
+    yref = D.inv_sqrt_matrix(So.to_scipy(), color, sign, b, 10, rp, col)
+    S32 = css.DeviceCSR.from_host(So.row_ptr, So.col, So.val, "cuda", torch.float32)
+    y, ytr, _, yinfo = css.css_inv_sqrt_overlap(S32, g_color, g_sign, g_b, 10, g_rp, g_col, bench.flags_for("fp32"))
+    dy = float(np.max(np.abs(y.cpu().numpy() - yref["y_val"])))
+    dytr = abs(ytr - yref["trace"]) / abs(yref["trace"])
+    print(f"10k S^-1/2 mixed: max|dY| {dy:.3e}  rel dTr {dytr:.3e} ({yinfo['t_phase_ms']['total']:.1f} ms)",
+          flush=True)
+    assert yinfo["depth_eff"] == yref["v_eff"] and dy <= 1e-5 and dytr <= 1e-7
 
 
 def test_1m_identities_and_mixed_against_fp64():

@@ -327,6 +327,51 @@ def test_find_mu_parity(M, seed, prec):
     assert abs(dinfo["trace_krylov"] - ne) <= tol_n
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("M,seed", [(64, 20919), (216, 3)])
+def test_inv_sqrt_overlap_parity(M, seed, prec):
+    """S^(-1/2) of the water overlap on the 6 Angstrom pattern (probes o = the density's
+    colouring and signs, v^s = 10) against the oracle element by element; the trace,
+    the S-weighted sum and the two Krylov quadratures too."""
+    print(f"inv sqrt {prec} M={M}", flush=True)
+    flags = FP64_FLAGS if prec == "fp64" else FP32_FLAGS
+    ws, H, rp, col, color, b, sign, _ = water_case(M, seed)
+    So = synth.water_overlap(ws)
+    ref = D.inv_sqrt_matrix(So.to_scipy(), color, sign, b, 10, rp, col)
+    Sd = css.DeviceCSR.from_host(So.row_ptr, So.col, So.val, "cuda", torch.float64)
+    y, tr, sdot, info = css.css_inv_sqrt_overlap(Sd, dev_i32(color), dev_i8(sign), b, 10, dev_i64(rp), dev_i32(col),
+                                                 flags)
+    err = float(np.max(np.abs(y.cpu().numpy() - ref["y_val"])))
+    print(f"  max|dY|={err:.3e} dtr={abs(tr - ref['trace']):.3e} dsdot={abs(sdot - ref['s_dot']):.3e} "
+          f"v_eff={info['depth_eff']}", flush=True)
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert info["depth_eff"] == ref["v_eff"]
+    assert err <= tol
+    rel = 1e-10 if prec == "fp64" else 1e-7
+    for got, want in ((tr, ref["trace"]), (sdot, ref["s_dot"]), (info["trace_krylov"], ref["trace_krylov"]),
+                      (info["e_band_krylov"], ref["half_krylov"])):
+        assert abs(got - want) <= rel * abs(want)
+
+
+def test_inv_sqrt_rejects_an_indefinite_overlap():
+    """S = -I has Ritz value -1: CSS_E_NONFINITE, every kernel still runs to its end."""
+    n = 48
+    xyz, box = synth.chain_1d(n, 1.0)
+    rp, col, deg = conflict_pattern(xyz, box, 2.0)
+    color, b = greedy_color(rp, col, deg)
+    Sd = css.DeviceCSR.from_host(np.arange(n + 1), np.arange(n), np.full(n, -1.0), "cuda", torch.float64)
+    with pytest.raises(css.CssError) as e:
+        css.css_inv_sqrt_overlap(Sd, dev_i32(color), dev_i8(probe_signs(n, 2)), b, 4, dev_i64(rp), dev_i32(col),
+                                 FP64_FLAGS)
+    assert e.value.code == 6
+    # and S = c I gives c^(-1/2) on the diagonal
+    Sd = css.DeviceCSR.from_host(np.arange(n + 1), np.arange(n), np.full(n, 2.25), "cuda", torch.float64)
+    y, tr, _, info = css.css_inv_sqrt_overlap(Sd, dev_i32(color), dev_i8(probe_signs(n, 2)), b, 4, dev_i64(rp),
+                                              dev_i32(col), FP64_FLAGS)
+    expect = np.where(D.pattern_rows(rp) == col, 1.0 / 1.5, 0.0)
+    assert info["depth_eff"] == 1 and np.max(np.abs(y.cpu().numpy() - expect)) < 1e-15
+
+
 @pytest.mark.parametrize("scale", [2.0 ** -12, 2.0 ** 12, 1000.0])
 def test_mixed_path_follows_energy_scale(scale):
     """P(s H, s mu, s kT) = P(H, mu, kT) for the mixed path, whose FP16 and BF16 operand
