@@ -199,3 +199,22 @@ def inv_sqrt_matrix(S, color, sign, n_colors, depth, p_row_ptr, p_col, reorth=RE
             "trace": trace_of(y_val, p_row_ptr, p_col), "trace_krylov": trace_k,
             "s_dot": band_energy(S, y_val, p_row_ptr, p_col), "half_krylov": half_k}
 
+
+def transform_hamiltonian(H, S, color, sign, n_colors, depth, p_row_ptr, p_col, reorth=REORTH_FULL,
+                          cholqr2=True, symmetrize_p=True) -> dict:
+    """H' = S^(-1/2) H S^(-1/2) on the pattern, read off S^(-1/2) H Y o^T with
+    Y = S^(-1/2) o from `inv_sqrt_matrix` and the left S^(-1/2) the sparse estimate
+    on the pattern (the non-orthogonal step after Eqs.(8)-(10))."""
+    import scipy.sparse as sp
+    r = inv_sqrt_matrix(S, color, sign, n_colors, depth, p_row_ptr, p_col, reorth=reorth, cholqr2=cholqr2,
+                        symmetrize_p=symmetrize_p)
+    n = len(p_row_ptr) - 1
+    S_half = sp.csr_matrix((r["y_val"], np.asarray(p_col, dtype=np.int64), np.asarray(p_row_ptr, dtype=np.int64)),
+                           shape=(n, n))
+    Z = S_half @ (H @ r["Y"])
+    h_raw = gather_raw(Z, color, sign, p_row_ptr, p_col)
+    h_sym = symmetrize(h_raw, p_row_ptr, p_col)
+    h_val = h_sym if symmetrize_p else h_raw
+    return {"y_val": r["y_val"], "hp_val": h_val, "hp_raw": h_raw, "Z": Z, "v_eff": r["v_eff"],
+            "y_trace": r["trace"], "hp_trace": trace_of(h_val, p_row_ptr, p_col)}
+

@@ -298,6 +298,43 @@ def test_inv_sqrt_krylov_identities_on_water_overlap():
     assert abs(D.band_energy(S, r["y_raw"], rp, col) - r["half_krylov"]) < 1e-11 * ws.n
 
 
+def test_transform_hamiltonian_reduces_to_dense_when_b_equals_n():
+    """Every orbital its own colour: H' = S^(-1/2) H S^(-1/2) exactly (scipy's
+    fractional_matrix_power for S^(-1/2))."""
+    import scipy.linalg as sla
+    n = 24
+    rng = np.random.default_rng(8)
+    xyz = rng.uniform(0, 1, size=(n, 3))
+    Hs = synth.random_symmetric_csr(xyz, np.zeros(3), 10.0, seed=9).to_scipy()
+    A = synth.random_symmetric_csr(xyz, np.zeros(3), 10.0, seed=12).to_scipy().toarray()
+    S = np.eye(n) + 0.3 * A / np.max(np.abs(np.linalg.eigvalsh(A)))
+    rp, col, _ = conflict_pattern(xyz, np.zeros(3), 10.0)
+    r = D.transform_hamiltonian(Hs, sp.csr_matrix(S), np.arange(n, dtype=np.int32), probe_signs(n, 4), n, 3, rp, col)
+    Sh = sla.fractional_matrix_power(S, -0.5).real
+    ref = Sh @ Hs.toarray() @ Sh
+    assert np.max(np.abs(r["hp_val"] - ref[D.pattern_rows(rp), col])) < 1e-12
+
+
+def test_transform_hamiltonian_is_exact_with_a_distance_two_colouring():
+    """S = c I on a nearest-neighbour chain, colours separating every pair within three
+    bonds, values read on the pairs within two: no probe mixes a neighbour of m with
+    the column read, so H' = H / c on the pattern."""
+    n, c = 40, 1.44
+    xyz, box = synth.chain_1d(n, 1.0)
+    crp, ccol, cdeg = conflict_pattern(xyz, box, 3.0)
+    color, b = greedy_color(crp, ccol, cdeg)
+    rp, col, _ = conflict_pattern(xyz, box, 2.0)
+    rng = np.random.default_rng(5)
+    off = rng.normal(size=n)
+    rows = np.arange(n)
+    Hs = sp.csr_matrix((np.concatenate([rng.normal(size=n), off, off]),
+                        (np.concatenate([rows, rows, (rows + 1) % n]), np.concatenate([rows, (rows + 1) % n, rows]))),
+                       shape=(n, n))
+    r = D.transform_hamiltonian(Hs, sp.identity(n, format="csr") * c, color, probe_signs(n, 6), b, 4, rp, col)
+    want = np.asarray(Hs[D.pattern_rows(rp), col]).ravel() / c
+    assert np.max(np.abs(r["hp_val"] - want)) < 1e-14
+
+
 # ---------------------------------------------------------------- energy-weighted DM
 
 def test_energy_dm_reduces_to_dense_when_b_equals_n():
@@ -406,6 +443,12 @@ def test_planted_mistakes_are_caught(monkeypatch):
     Y_bad = D.reconstruct_X(lz1.Q, F_bad)
     S_half = sla.fractional_matrix_power(Sd, -0.5).real
     assert np.max(np.abs(Y_bad @ probe_block(np.arange(ns), ss, ns).T - S_half)) > 1e-2
+
+    # (2e) H' without the left S^(-1/2) (H Y o^T read off): the dense pin for b = N fails
+    ry = D.inv_sqrt_matrix(sp.csr_matrix(Sd), np.arange(ns), ss, ns, 3, rps, cols)
+    h_bad = D.gather_raw(Hs @ ry["Y"], np.arange(ns), ss, rps, cols)
+    h_ref = (S_half @ Hs.toarray() @ S_half)[D.pattern_rows(rps), cols]
+    assert np.max(np.abs(h_bad - h_ref)) > 1e-3
 
     # (3) wrong sign in the Fermi function: closed form f(mu+t)=1/(e^{t/kT}+1) fails
     monkeypatch.setattr(S, "fermi", lambda x, mu, kT: 1.0 / (1.0 + np.exp(-(np.asarray(x) - mu) / kT)))
