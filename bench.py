@@ -369,6 +369,12 @@ def main():
         torch.cuda.synchronize()
         out["inv_sqrt_overlap"] = {"ms": (time.perf_counter() - t) * 1e3, "depth": 10,
                                    "depth_eff": yinfo["depth_eff"], "trace": ytr, "phase_ms": yinfo["t_phase_ms"]}
+        css.css_transform_hamiltonian(H, *inv_args)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        css.css_transform_hamiltonian(H, *inv_args)
+        torch.cuda.synchronize()
+        out["transform_hamiltonian"] = {"ms": (time.perf_counter() - t) * 1e3, "depth": 10}
         del Sdev
 
     if wl["prec"] == "fp32" and not args.no_fp64:

@@ -78,7 +78,8 @@ enum { CSS_F64 = 0, CSS_F32 = 1 };
 
 /* workspace query selectors */
 enum { CSS_ENTRY_COLOR = 0, CSS_ENTRY_LANCZOS = 1, CSS_ENTRY_DENSITY = 2, CSS_ENTRY_SPMM = 3,
-       CSS_ENTRY_ENERGY_DENSITY = 4, CSS_ENTRY_FIND_MU = 5, CSS_ENTRY_INV_SQRT = 6 };
+       CSS_ENTRY_ENERGY_DENSITY = 4, CSS_ENTRY_FIND_MU = 5, CSS_ENTRY_INV_SQRT = 6,
+       CSS_ENTRY_TRANSFORM_H = 7 };
 
 /* Sparse symmetric H in CSR form; all pointers device. Column indices must be
  * sorted within each row; row_ptr[0] = 0, row_ptr[n] = nnz < 2^31. */
@@ -272,6 +273,34 @@ css_status css_inv_sqrt_overlap(const css_csr* S, const int32_t* color, const in
                                 const int32_t* p_col, int64_t p_nnz, uint32_t flags, double* y_val,
                                 double* trace, double* s_dot, css_info* info, void* ws,
                                 size_t ws_bytes, void* stream);
+
+/*
+ * css_transform_hamiltonian -- S^(-1/2) and the orthogonalised Hamiltonian
+ *   H' = S^(-1/2) H S^(-1/2) on a cutoff pattern, for a non-orthogonal basis (the
+ *   step after Eqs.(8)-(10): H' read off S^(-1/2) H Y o^T with Y = S^(-1/2) o).
+ *   First css_inv_sqrt_overlap (Y and the sparse S^(-1/2) on the pattern), then
+ *   Z = S^(-1/2) (H Y) with both sparse x block products in FP64 (the sparse
+ *   S^(-1/2) is the one just gathered), then h'_mn = sign[n] Z[m, colour(n)] on
+ *   the pattern (symmetrised with CSS_SYMMETRIZE). Only sparse x block products.
+ *   H            device CSR of S's size, FP64 or FP32 values (widened to FP64),
+ *                nnz at most S's
+ *   S, color, sign, n_colors, depth, p_row_ptr, p_col, flags  as
+ *                css_inv_sqrt_overlap (p_nnz < 2^31)
+ *   y_val        device double[p_nnz] out: S^(-1/2) on the pattern
+ *   hp_val       device double[p_nnz] out: H' on the pattern
+ *   y_trace      host out: sum_m y_mm
+ *   hp_trace     host out (may be NULL): sum_m h'_mm
+ *   info         host out (may be NULL): as css_inv_sqrt_overlap
+ *   ws           css_workspace_size(CSS_ENTRY_TRANSFORM_H, n, nnz of S, ...) bytes.
+ *   Errors as css_inv_sqrt_overlap; CSS_E_CSR for a malformed H. Synchronises
+ *   the stream before returning.
+ */
+css_status css_transform_hamiltonian(const css_csr* H, const css_csr* S, const int32_t* color,
+                                     const int8_t* sign, int32_t n_colors, int32_t depth,
+                                     const int64_t* p_row_ptr, const int32_t* p_col, int64_t p_nnz,
+                                     uint32_t flags, double* y_val, double* hp_val, double* y_trace,
+                                     double* hp_trace, css_info* info, void* ws, size_t ws_bytes,
+                                     void* stream);
 
 /*
  * css_find_mu -- the chemical potential for a given electron count (the mu of

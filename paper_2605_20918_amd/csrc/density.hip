@@ -222,6 +222,19 @@ __global__ __launch_bounds__(kMuThreads) void k_mu_bisect(const double* __restri
     }
 }
 
+// out[i] = (double)in[i]
+template <typename T>
+__global__ void k_widen(const T* __restrict__ in, double* __restrict__ out, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (double)in[i];
+}
+
+// int32 row pointers of a pattern whose nnz is below 2^31 (checked on the host).
+__global__ void k_narrow_rp(const int64_t* __restrict__ rp, int32_t* __restrict__ out, int64_t n1) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n1) out[i] = (int32_t)rp[i];
+}
+
 // Pattern sanity: row pointers monotone from 0 to nnz, columns in range.
 __global__ void k_validate_pattern(int n, int64_t nnz, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                    int* __restrict__ bad) {
@@ -358,6 +371,7 @@ struct DmPlan {
     size_t pole_ws = 0;
     bool sep_X = false;
     bool energy = false;      // also the energy-weighted estimate (X_E = H X)
+    bool hprime = false;      // also H' = S^-1/2 H S^-1/2 extracted after S^-1/2 (FP64 products)
 };
 
 struct DmBufs {
@@ -368,6 +382,8 @@ struct DmBufs {
     int* flags = nullptr;
     void* X = nullptr;
     void* XE = nullptr;       // H X (energy-weighted estimate)
+    double *Y64 = nullptr, *Z1 = nullptr, *Z = nullptr, *h64 = nullptr;   // H' extraction (FP64)
+    int32_t* rp32 = nullptr;
     void* eig_ws = nullptr;
 };
 
@@ -389,6 +405,14 @@ void carve_dm(Arena& a, const DmPlan& p, DmBufs& bf) {
     bf.flags = a.take<int>(16);
     bf.X = p.sep_X ? a.take<char>((size_t)p.lz.Np * p.lz.ld * p.lz.elem) : bf.lz.W;
     bf.XE = p.energy ? a.take<char>((size_t)p.lz.Np * p.lz.ld * p.lz.elem) : nullptr;
+    if (p.hprime) {
+        const int64_t tall = p.lz.Np * p.lz.ld;
+        bf.Y64 = a.take<double>(tall);
+        bf.Z1 = a.take<double>(tall);
+        bf.Z = a.take<double>(tall);
+        bf.h64 = a.take<double>(std::max<int64_t>(1, p.lz.nnz));
+        bf.rp32 = a.take<int32_t>(p.lz.n + 1);
+    }
     bf.eig_ws = p.eig_ws ? a.take<char>(p.eig_ws) : nullptr;
     bf.pole_ws = p.pole_ws ? a.take<char>(p.pole_ws) : nullptr;
 }
@@ -434,7 +458,8 @@ namespace {
 css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, int32_t n_colors, double mu, double kT,
                   int32_t depth, double spin_deg, const int64_t* p_row_ptr, const int32_t* p_col, int64_t p_nnz,
                   uint32_t flags, double* p_val, double* pe_val, double* e_band, double* trace, double* pe_trace,
-                  css_info* info, void* ws, size_t ws_bytes, void* stream, int fn = kFnFermi) {
+                  css_info* info, void* ws, size_t ws_bytes, void* stream, int fn = kFnFermi,
+                  const css_csr* H2 = nullptr, double* h2_val = nullptr) {
     if (!color || !sign || !p_row_ptr || !p_col || !p_val || !e_band || !trace || !ws || p_nnz < 1) return CSS_E_ARG;
     if (fn == kFnFermi && (!(kT > 0.0) || !std::isfinite(kT) || !std::isfinite(mu) || !(spin_deg > 0.0)))
         return CSS_E_ARG;
@@ -442,6 +467,13 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     DmPlan p;
     CSS_TRY(plan_dm(H, n_colors, depth, flags, p));
     p.energy = pe_val != nullptr;
+    p.hprime = h2_val != nullptr;
+    if (p.hprime) {
+        // H' extraction: H2 shares S's size, and its nnz fits the reserved FP64 copy
+        if (fn != kFnInvSqrt || !H2 || !H2->row_ptr || !H2->col || !H2->val || H2->n != H->n || H2->nnz < 1 ||
+            H2->nnz > H->nnz || p_nnz >= (int64_t(1) << 31))
+            return CSS_E_ARG;
+    }
     if (ws_bytes < dm_workspace_bytes(p)) return CSS_E_WORKSPACE;
     Arena a;
     a.base = static_cast<char*>(ws);
@@ -545,6 +577,35 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
             launch_gather<double>(lz.n, p_row_ptr, p_col, color, sign, bf.XE, lz.ld, sym, pe_val, rt, ra, s);
         det_sum(rt, lz.n, bf.tmp + 2 * kSumBlocks, bf.res + 5, s);
     }
+    if (h2_val) {
+        // H' = S^-1/2 H S^-1/2 read off S^-1/2 (H Y) o^T: Y is S^-1/2 applied to the
+        // probes (X above), S^-1/2 the sparse estimate just gathered; FP64 products
+        CSS_HIP_TRY(hipMemsetAsync(bf.flags + 3, 0, 4 * sizeof(int), s));
+        csr_validate_launch(lz.n, H2->nnz, H2->row_ptr, H2->col, bf.flags + 3, s);
+        int vbad[2] = {0, 0};
+        CSS_HIP_TRY(hipMemcpyAsync(vbad, bf.flags + 3, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        CSS_HIP_TRY(hipStreamSynchronize(s));
+        if (vbad[1]) return CSS_E_CSR;
+        const int64_t tall = lz.Np * lz.ld;
+        if (lz.fp32)
+            k_widen<float><<<grid_for(tall, 256), 256, 0, s>>>(static_cast<const float*>(bf.X), bf.Y64, tall);
+        else
+            CSS_HIP_TRY(hipMemcpyAsync(bf.Y64, bf.X, tall * sizeof(double), hipMemcpyDeviceToDevice, s));
+        const double* h2v = static_cast<const double*>(H2->val);
+        if (H2->val_dtype == CSS_F32) {
+            k_widen<float><<<grid_for(H2->nnz, 256), 256, 0, s>>>(static_cast<const float*>(H2->val), bf.h64,
+                                                                   H2->nnz);
+            h2v = bf.h64;
+        } else if (H2->val_dtype != CSS_F64) {
+            return CSS_E_ARG;
+        }
+        k_narrow_rp<<<grid_for(lz.n + 1, 256), 256, 0, s>>>(p_row_ptr, bf.rp32, lz.n + 1);
+        if (!spmm_launch<double>(SpmmArgs<double>{lz.n, H2->row_ptr, H2->col, h2v, bf.Y64, bf.Z1, lz.ld}, s) ||
+            !spmm_launch<double>(SpmmArgs<double>{lz.n, bf.rp32, p_col, p_val, bf.Z1, bf.Z, lz.ld}, s))
+            return CSS_E_UNSUPPORTED;
+        launch_gather<double>(lz.n, p_row_ptr, p_col, color, sign, bf.Z, lz.ld, sym, h2_val, rt, ra, s);
+        det_sum(rt, lz.n, bf.tmp + 2 * kSumBlocks, bf.res + 5, s);
+    }
     CSS_HIP_TRY(hipEventRecord(ev[5], s));
     double hres[8];
     int hinfo[2] = {0, 0};
@@ -556,7 +617,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     if (hinfo[1] != 0) return CSS_E_NONFINITE;
     *trace = hres[0];
     *e_band = hres[1];
-    if (pe_val && pe_trace) *pe_trace = hres[5];
+    if ((pe_val || h2_val) && pe_trace) *pe_trace = hres[5];
     if (info) {
         *info = css_info{};
         info->depth_eff = v_eff;
@@ -611,6 +672,20 @@ extern "C" css_status css_inv_sqrt_overlap(const css_csr* S, const int32_t* colo
     CSS_TRY(css::dm_run(S, color, sign, n_colors, 0.0, 1.0, depth, 1.0, p_row_ptr, p_col, p_nnz, flags, y_val,
                         nullptr, &sd, trace, nullptr, info, ws, ws_bytes, stream, css::kFnInvSqrt));
     if (s_dot) *s_dot = sd;
+    return CSS_OK;
+}
+
+extern "C" css_status css_transform_hamiltonian(const css_csr* H, const css_csr* S, const int32_t* color,
+                                                const int8_t* sign, int32_t n_colors, int32_t depth,
+                                                const int64_t* p_row_ptr, const int32_t* p_col, int64_t p_nnz,
+                                                uint32_t flags, double* y_val, double* hp_val, double* y_trace,
+                                                double* hp_trace, css_info* info, void* ws, size_t ws_bytes,
+                                                void* stream) {
+    if (!H || !hp_val || !y_trace) return CSS_E_ARG;
+    double sd = 0.0, ht = 0.0;
+    CSS_TRY(css::dm_run(S, color, sign, n_colors, 0.0, 1.0, depth, 1.0, p_row_ptr, p_col, p_nnz, flags, y_val,
+                        nullptr, &sd, y_trace, &ht, info, ws, ws_bytes, stream, css::kFnInvSqrt, H, hp_val));
+    if (hp_trace) *hp_trace = ht;
     return CSS_OK;
 }
 
@@ -698,7 +773,7 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
         return CSS_OK;
     }
     if (entry != CSS_ENTRY_LANCZOS && entry != CSS_ENTRY_DENSITY && entry != CSS_ENTRY_ENERGY_DENSITY &&
-        entry != CSS_ENTRY_FIND_MU && entry != CSS_ENTRY_INV_SQRT)
+        entry != CSS_ENTRY_FIND_MU && entry != CSS_ENTRY_INV_SQRT && entry != CSS_ENTRY_TRANSFORM_H)
         return CSS_E_ARG;
     // shape-only CSRs for planning; H's value type is not an argument, so the size
     // covers both (values in the other precision need a converted copy)
@@ -712,9 +787,11 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
             most = std::max(most, lanczos_workspace_bytes(p));
         } else {
             DmPlan p;
-            const bool eig = entry == CSS_ENTRY_FIND_MU || entry == CSS_ENTRY_INV_SQRT;
+            const bool eig = entry == CSS_ENTRY_FIND_MU || entry == CSS_ENTRY_INV_SQRT ||
+                             entry == CSS_ENTRY_TRANSFORM_H;
             CSS_TRY(plan_dm(&H, n_colors, depth, eig ? (flags | CSS_SUBSPACE_EIG) : flags, p));
             p.energy = entry == CSS_ENTRY_ENERGY_DENSITY;
+            p.hprime = entry == CSS_ENTRY_TRANSFORM_H;
             most = std::max(most, dm_workspace_bytes(p));
         }
     }

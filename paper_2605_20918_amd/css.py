@@ -38,8 +38,8 @@ SIGNS_ONES = 0x80
 SUBSPACE_EIG = 0x100
 SPMM_CSR = 0x200
 
-ENTRY_COLOR, ENTRY_LANCZOS, ENTRY_DENSITY, ENTRY_SPMM, ENTRY_ENERGY_DENSITY, ENTRY_FIND_MU, ENTRY_INV_SQRT = \
-    0, 1, 2, 3, 4, 5, 6
+(ENTRY_COLOR, ENTRY_LANCZOS, ENTRY_DENSITY, ENTRY_SPMM, ENTRY_ENERGY_DENSITY, ENTRY_FIND_MU, ENTRY_INV_SQRT,
+ ENTRY_TRANSFORM_H) = 0, 1, 2, 3, 4, 5, 6, 7
 
 
 class CssError(RuntimeError):
@@ -125,6 +125,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                 ctypes.POINTER(dbl), pinfo, vp, sz, vp]
     lib.css_inv_sqrt_overlap.argtypes = [pcsr, vp, vp, i32, i32, vp, vp, i64, u32, vp, ctypes.POINTER(dbl),
                                          ctypes.POINTER(dbl), pinfo, vp, sz, vp]
+    lib.css_transform_hamiltonian.argtypes = [pcsr, pcsr, vp, vp, i32, i32, vp, vp, i64, u32, vp, vp,
+                                              ctypes.POINTER(dbl), ctypes.POINTER(dbl), pinfo, vp, sz, vp]
     lib.css_workspace_size.argtypes = [i32, i32, i64, i32, i32, u32, ctypes.POINTER(sz)]
     lib.css_fermi_poles.argtypes = [i32, vp, vp, ctypes.POINTER(i32)]
     lib.css_fermi_poles.restype = i32
@@ -135,7 +137,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in ("css_color", "css_build_probes", "css_spmm_prepare", "css_spmm", "css_block_lanczos",
                  "css_density_matrix", "css_density_matrix_batched", "css_batched_workspace_size",
                  "css_color_batched", "css_color_batched_workspace_size",
-                 "css_energy_density_matrix", "css_find_mu", "css_inv_sqrt_overlap", "css_workspace_size"):
+                 "css_energy_density_matrix", "css_find_mu", "css_inv_sqrt_overlap", "css_transform_hamiltonian",
+                 "css_workspace_size"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -404,6 +407,28 @@ def css_inv_sqrt_overlap(S: DeviceCSR, color, sign, n_colors: int, depth: int, p
                                        _ptr(p_col), nnz, flags, _ptr(y_val), ctypes.byref(trace), ctypes.byref(s_dot),
                                        ctypes.byref(info), _ptr(ws), ws.numel(), _stream(dev)))
     return y_val, float(trace.value), float(s_dot.value), info.as_dict()
+
+
+def css_transform_hamiltonian(H: DeviceCSR, S: DeviceCSR, color, sign, n_colors: int, depth: int, p_row_ptr, p_col,
+                              flags: int):
+    """S^(-1/2) and H' = S^(-1/2) H S^(-1/2) on the pattern. Returns (y_val, hp_val
+    float64 [nnz_P], y_trace, hp_trace, info dict)."""
+    torch = _torch()
+    dev = color.device
+    nnz = int(p_col.numel())
+    y_val = torch.empty(nnz, dtype=torch.float64, device=dev)
+    hp_val = torch.empty(nnz, dtype=torch.float64, device=dev)
+    ws = workspace(workspace_size(ENTRY_TRANSFORM_H, S.n, S.nnz, n_colors, depth, flags), dev)
+    y_trace = ctypes.c_double(0.0)
+    hp_trace = ctypes.c_double(0.0)
+    info = InfoStruct()
+    h_csr, s_csr = H.struct(), S.struct()
+    _check("css_transform_hamiltonian",
+           load().css_transform_hamiltonian(ctypes.byref(h_csr), ctypes.byref(s_csr), _ptr(color), _ptr(sign),
+                                            n_colors, depth, _ptr(p_row_ptr), _ptr(p_col), nnz, flags, _ptr(y_val),
+                                            _ptr(hp_val), ctypes.byref(y_trace), ctypes.byref(hp_trace),
+                                            ctypes.byref(info), _ptr(ws), ws.numel(), _stream(dev)))
+    return y_val, hp_val, float(y_trace.value), float(hp_trace.value), info.as_dict()
 
 
 def css_density_matrix_batched(systems, kT: float, depth: int, flags: int, concurrency: int = 4,

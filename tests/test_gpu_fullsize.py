@@ -105,6 +105,14 @@ def test_10k_against_the_oracle():
     print(f"10k S^-1/2 mixed: max|dY| {dy:.3e}  rel dTr {dytr:.3e} ({yinfo['t_phase_ms']['total']:.1f} ms)",
           flush=True)
     assert yinfo["depth_eff"] == yref["v_eff"] and dy <= 1e-5 and dytr <= 1e-7
+    # H' = S^(-1/2) H S^(-1/2), mixed precision, against the oracle
+    href = D.transform_hamiltonian(ws.H.to_scipy(), So.to_scipy(), color, sign, b, 10, rp, col)
+    _, hp, _, hptr, _ = css.css_transform_hamiltonian(H32, S32, g_color, g_sign, g_b, 10, g_rp, g_col,
+                                                      bench.flags_for("fp32"))
+    dh = float(np.max(np.abs(hp.cpu().numpy() - href["hp_val"])))
+    dhtr = abs(hptr - href["hp_trace"]) / abs(href["hp_trace"])
+    print(f"10k H' mixed: max|dH'| {dh:.3e}  rel dTr {dhtr:.3e}", flush=True)
+    assert dh <= 1e-5 * hinf and dhtr <= 1e-7
 
 
 def test_1m_identities_and_mixed_against_fp64():

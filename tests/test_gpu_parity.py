@@ -353,6 +353,29 @@ def test_inv_sqrt_overlap_parity(M, seed, prec):
         assert abs(got - want) <= rel * abs(want)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("M,seed", [(64, 20919), (216, 3)])
+def test_transform_hamiltonian_parity(M, seed, prec):
+    """H' = S^(-1/2) H S^(-1/2) on the pattern against the oracle element by element;
+    S^(-1/2) from the same call equals css_inv_sqrt_overlap's bitwise."""
+    print(f"transform H {prec} M={M}", flush=True)
+    flags = FP64_FLAGS if prec == "fp64" else FP32_FLAGS
+    ws, H, rp, col, color, b, sign, _ = water_case(M, seed)
+    So = synth.water_overlap(ws)
+    ref = D.transform_hamiltonian(H, So.to_scipy(), color, sign, b, 10, rp, col)
+    Sd = css.DeviceCSR.from_host(So.row_ptr, So.col, So.val, "cuda", torch.float64)
+    args = (dev_i32(color), dev_i8(sign), b, 10, dev_i64(rp), dev_i32(col), flags)
+    y, hp, ytr, hptr, info = css.css_transform_hamiltonian(to_dev(ws), Sd, *args)
+    y0, ytr0, _, _ = css.css_inv_sqrt_overlap(Sd, *args)
+    assert torch.equal(y, y0) and ytr == ytr0
+    hinf = float(np.max(np.abs(H).sum(axis=1)))
+    err = float(np.max(np.abs(hp.cpu().numpy() - ref["hp_val"])))
+    print(f"  max|dH'|={err:.3e} (||H||_inf {hinf:.2f}) dtr={abs(hptr - ref['hp_trace']):.3e}", flush=True)
+    tol = (1e-10 if prec == "fp64" else 1e-5) * hinf
+    assert err <= tol
+    assert abs(hptr - ref["hp_trace"]) <= (1e-10 if prec == "fp64" else 1e-7) * abs(ref["hp_trace"])
+
+
 def test_inv_sqrt_rejects_an_indefinite_overlap():
     """S = -I has Ritz value -1: CSS_E_NONFINITE, every kernel still runs to its end."""
     n = 48
