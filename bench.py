@@ -372,9 +372,20 @@ def main():
         css.css_transform_hamiltonian(H, *inv_args)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        css.css_transform_hamiltonian(H, *inv_args)
+        y_s, hp_s, _, _, _ = css.css_transform_hamiltonian(H, *inv_args)
         torch.cuda.synchronize()
         out["transform_hamiltonian"] = {"ms": (time.perf_counter() - t) * 1e3, "depth": 10}
+        # density matrix of the non-orthogonal basis from that S^(-1/2) and H'
+        no_args = (css.pattern_csr(p_rp, p_col, hp_s), css.pattern_csr(p_rp, p_col, y_s), color, sign, bb, mu, KT,
+                   depth, p_rp, p_col, flags)
+        css.css_density_matrix_nonorth(*no_args, H=H, S=Sdev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, e_no, n_no, _, ninfo = css.css_density_matrix_nonorth(*no_args, H=H, S=Sdev)
+        torch.cuda.synchronize()
+        out["density_nonorth"] = {"ms": (time.perf_counter() - t) * 1e3, "depth_eff": ninfo["depth_eff"],
+                                  "n_elec": n_no, "e_band": e_no, "phase_ms": ninfo["t_phase_ms"]}
+        del y_s, hp_s, no_args
         del Sdev
 
     if wl["prec"] == "fp32" and not args.no_fp64:

@@ -79,7 +79,7 @@ enum { CSS_F64 = 0, CSS_F32 = 1 };
 /* workspace query selectors */
 enum { CSS_ENTRY_COLOR = 0, CSS_ENTRY_LANCZOS = 1, CSS_ENTRY_DENSITY = 2, CSS_ENTRY_SPMM = 3,
        CSS_ENTRY_ENERGY_DENSITY = 4, CSS_ENTRY_FIND_MU = 5, CSS_ENTRY_INV_SQRT = 6,
-       CSS_ENTRY_TRANSFORM_H = 7 };
+       CSS_ENTRY_TRANSFORM_H = 7, CSS_ENTRY_DENSITY_NONORTH = 8 };
 
 /* Sparse symmetric H in CSR form; all pointers device. Column indices must be
  * sorted within each row; row_ptr[0] = 0, row_ptr[n] = nnz < 2^31. */
@@ -301,6 +301,45 @@ css_status css_transform_hamiltonian(const css_csr* H, const css_csr* S, const i
                                      uint32_t flags, double* y_val, double* hp_val, double* y_trace,
                                      double* hp_trace, css_info* info, void* ws, size_t ws_bytes,
                                      void* stream);
+
+/*
+ * css_density_matrix_nonorth -- the CSS density matrix of a non-orthogonal basis
+ *   (Eq.(9)): rho~ = S^(-1/2) Phi rho^K Phi^T r~ r^T, with r the probes, r~ =
+ *   S^(-1/2) r, Phi the block Krylov basis of H' = S^(-1/2) H S^(-1/2) from r~
+ *   (the first block Q_1 R_0 = r~ by Cholesky QR, so B_0 = R_0 is triangular) and
+ *   rho^K = g f(T) by dense diagonalisation (Eq.(10), rocSOLVER dsyevd). Only
+ *   sparse x block products: r~ = S^(-1/2) r and X = S^(-1/2) X' in FP64, the
+ *   Lanczos steps on H' in the precision the flags select. Then P_mn =
+ *   sign[n] X[m, colour(n)] on the pattern (symmetrised with CSS_SYMMETRIZE).
+ *   Hp           device CSR of H' (css_transform_hamiltonian's values on an int32
+ *                copy of the pattern's row pointers), FP64 or FP32
+ *   S_isqrt      device CSR of the sparse S^(-1/2), FP64 values (nnz < 2^31)
+ *   H, S         device CSRs of the original H and S (either may be NULL): for
+ *                e_band = sum H_mn P_mn and n_elec = sum S_mn P_mn (= Tr(P S),
+ *                the Mulliken electron count) over entries in the pattern
+ *   color, sign, n_colors, mu, kT, depth, spin_deg, p_row_ptr, p_col, p_nnz  as
+ *                css_density_matrix (the probes r on the density's cutoff)
+ *   flags        precision and re-orthogonalisation as css_density_matrix; stored
+ *                basis only (CSS_E_UNSUPPORTED with CSS_BASIS_TWOPASS);
+ *                CSS_SUBSPACE_EIG is implied
+ *   p_val        device double[p_nnz] out
+ *   e_band       host out (NULL allowed when H is NULL)
+ *   n_elec       host out (NULL allowed when S is NULL)
+ *   trace        host out: sum_m P_mm
+ *   info         host out (may be NULL): as css_density_matrix; trace_krylov =
+ *                sum_k g f(lambda_k) w_k with w_k = |R_0^T U[0:b,k]|^2 (the Krylov
+ *                estimate of Tr(r~^T f(H') r~), which is Tr(P_raw) up to rounding)
+ *   ws           css_workspace_size(CSS_ENTRY_DENSITY_NONORTH, n, nnz of H', ...)
+ *   Errors as css_density_matrix; CSS_E_BREAKDOWN_AT_1 when r~ is rank deficient.
+ *   Synchronises the stream before returning.
+ */
+css_status css_density_matrix_nonorth(const css_csr* Hp, const css_csr* S_isqrt, const css_csr* H,
+                                      const css_csr* S, const int32_t* color, const int8_t* sign,
+                                      int32_t n_colors, double mu, double kT, int32_t depth,
+                                      double spin_deg, const int64_t* p_row_ptr, const int32_t* p_col,
+                                      int64_t p_nnz, uint32_t flags, double* p_val, double* e_band,
+                                      double* n_elec, double* trace, css_info* info, void* ws,
+                                      size_t ws_bytes, void* stream);
 
 /*
  * css_find_mu -- the chemical potential for a given electron count (the mu of

@@ -218,3 +218,47 @@ def transform_hamiltonian(H, S, color, sign, n_colors, depth, p_row_ptr, p_col, 
     return {"y_val": r["y_val"], "hp_val": h_val, "hp_raw": h_raw, "Z": Z, "v_eff": r["v_eff"],
             "y_trace": r["trace"], "hp_trace": trace_of(h_val, p_row_ptr, p_col)}
 
+
+def density_matrix_nonorth(Hp, S_isqrt, color, sign, n_colors, mu, kT, depth, p_row_ptr, p_col, spin_deg=2.0,
+                           H=None, S=None, reorth=REORTH_FULL, cholqr2=True, symmetrize_p=True) -> dict:
+    """The CSS density matrix of a non-orthogonal basis (Eq.(9)):
+    rho~ = S^(-1/2) Phi rho^K Phi^T r~ r^T, r~ = S^(-1/2) r, Phi the block Krylov
+    basis of H' from r~ (Q_1 R_0 = r~), rho^K = g f(T) from the eigenpairs of T
+    (Eq.(10)). Hp and S_isqrt are the sparse H' and S^(-1/2)."""
+    from .probes import probe_block
+    color = np.asarray(color)
+    sign = np.asarray(sign)
+    r = probe_block(color, sign, n_colors)
+    r_t = S_isqrt @ r
+    lz = block_lanczos(Hp, color, sign, n_colors, depth, reorth=reorth, cholqr2=cholqr2, start=r_t)
+    T = assemble_T(lz.A, lz.B)
+    lam, U = eig_subspace(T)
+    b = n_colors
+    occ = spin_deg * fermi(lam, mu, kT)
+    UR = U[:b, :].T @ lz.r0                      # U[0:b,:]^T R_0  (n_T x b)
+    F = (U * occ[None, :]) @ UR                  # U g f(Lambda) U[0:b,:]^T R_0
+    w = (UR ** 2).sum(axis=1)
+    Xp = reconstruct_X(lz.Q, F)
+    X = S_isqrt @ Xp
+    p_raw = gather_raw(X, color, sign, p_row_ptr, p_col)
+    p_sym = symmetrize(p_raw, p_row_ptr, p_col)
+    p_val = p_sym if symmetrize_p else p_raw
+    out = {"p_val": p_val, "p_raw": p_raw, "X": X, "lam": lam, "v_eff": lz.v_eff, "lanczos": lz,
+           "trace": trace_of(p_val, p_row_ptr, p_col), "trace_krylov": float(np.sum(occ * w)),
+           "e_band_krylov": float(np.sum(lam * occ * w))}
+    if H is not None:
+        out["e_band"] = band_energy(H, p_val, p_row_ptr, p_col)
+    if S is not None:
+        out["n_elec"] = band_energy(S, p_val, p_row_ptr, p_col)
+    return out
+
+
+def dense_fermi_dm_generalized(H, S, mu, kT, spin_deg=2.0) -> np.ndarray:
+    """g f of the generalised problem H c = e S c with S-orthonormal c:
+    rho = sum_i g f(e_i) c_i c_i^T (scipy's generalised symmetric eigensolver)."""
+    import scipy.linalg as sla
+    Hd = H.toarray() if hasattr(H, "toarray") else np.asarray(H)
+    Sd = S.toarray() if hasattr(S, "toarray") else np.asarray(S)
+    e, C = sla.eigh(Hd, Sd)
+    return (C * (spin_deg * fermi(e, mu, kT))[None, :]) @ C.T
+

@@ -45,10 +45,11 @@ class LanczosResult:
     A: list            # v_eff blocks, b x b
     B: list            # v_eff - 1 blocks, b x b, upper triangular
     Q: list            # v_eff blocks, N x b
-    b0: np.ndarray     # diag of B_0
+    b0: np.ndarray     # diag of B_0 (probes as the first block), else None
     v_eff: int
     breakdown: bool
     min_diag_r: float  # smallest diag of the first Cholesky factor over all steps
+    r0: np.ndarray = None   # B_0 = R_0, upper triangular, when a start block is given
 
 
 def inf_norm(H) -> float:
@@ -64,13 +65,23 @@ def _cholesky_upper(G: np.ndarray):
 
 
 def block_lanczos(H, color, sign, n_colors: int, depth: int,
-                  reorth: str = REORTH_FULL, cholqr2: bool = True) -> LanczosResult:
+                  reorth: str = REORTH_FULL, cholqr2: bool = True, start=None) -> LanczosResult:
+    """start: an N x b first block (the non-orthogonal case's r~ = S^(-1/2) r); its
+    QR with a positive-diagonal R_0 (numpy's Householder QR, signs fixed) gives Q_1
+    and B_0 = R_0. Otherwise the first block is the normalised probes."""
     N = H.shape[0]
     b = n_colors
     v_max = min(depth, N // b)
     if v_max < 1:
         raise ValueError("depth must be >= 1 and n_colors <= N")
-    Q1, b0 = first_block(np.asarray(color), np.asarray(sign), b)
+    r0 = None
+    if start is None:
+        Q1, b0 = first_block(np.asarray(color), np.asarray(sign), b)
+    else:
+        Q1, r0 = np.linalg.qr(np.asarray(start, dtype=np.float64))
+        d = np.sign(np.diag(r0))
+        d[d == 0] = 1.0
+        Q1, r0, b0 = Q1 * d[None, :], r0 * d[:, None], None
     tau = BREAKDOWN_REL * inf_norm(H)
 
     Qs, As, Bs = [Q1], [], []
@@ -112,7 +123,7 @@ def block_lanczos(H, color, sign, n_colors: int, depth: int,
         Qs.append(Qn)
     v_eff = len(As)
     return LanczosResult(As, Bs, Qs[:v_eff], b0, v_eff, breakdown,
-                         float(min_diag) if np.isfinite(min_diag) else float("nan"))
+                         float(min_diag) if np.isfinite(min_diag) else float("nan"), r0)
 
 
 def assemble_T(A: list, B: list) -> np.ndarray:

@@ -235,6 +235,50 @@ __global__ void k_narrow_rp(const int64_t* __restrict__ rp, int32_t* __restrict_
     if (i < n1) out[i] = (int32_t)rp[i];
 }
 
+// The probe block r (Eq.(2)): out[m][c] = sign[m] if c = colour(m), else 0; zero padding.
+__global__ void k_probe_block(const int32_t* __restrict__ color, const int8_t* __restrict__ sign, int n, int64_t Np,
+                              int ld, double* __restrict__ out) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= Np * ld) return;
+    const int64_t m = idx / ld;
+    const int c = (int)(idx % ld);
+    out[idx] = (m < n && color[m] == c) ? (double)sign[m] : 0.0;
+}
+
+__global__ void k_fill0(double* __restrict__ p, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// General first block B_0 = R0 (ld x ld row-major, upper): UB[k][c] = sum_{c' <= c}
+// U[c'][k] R0[c'][c]; Y[k][c] = fn(lambda_k) UB[k][c].
+__global__ void k_occ_y_r0(const double* __restrict__ U, const double* __restrict__ lam, const double* __restrict__ R0,
+                           int nT, int b, int ld, double mu, double kT, double g, double* __restrict__ Y) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nT * b) return;
+    const int k = (int)(idx / b), c = (int)(idx % b);
+    double ub = 0.0;
+    for (int cp = 0; cp <= c; ++cp) ub += U[(int64_t)k * nT + cp] * R0[(int64_t)cp * ld + c];
+    Y[idx] = g * fermi(lam[k], mu, kT) * ub;
+}
+
+// Quadrature terms with B_0 = R0: w_k = |R0^T U[0:b,k]|^2, t0 = g f w, t1 = lambda g f w.
+__global__ void k_quad_terms_r0(const double* __restrict__ U, const double* __restrict__ lam,
+                                const double* __restrict__ R0, int nT, int b, int ld, double mu, double kT, double g,
+                                double* __restrict__ t0, double* __restrict__ t1) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nT) return;
+    double w = 0.0;
+    for (int c = 0; c < b; ++c) {
+        double ub = 0.0;
+        for (int cp = 0; cp <= c; ++cp) ub += U[(int64_t)k * nT + cp] * R0[(int64_t)cp * ld + c];
+        w += ub * ub;
+    }
+    const double occ = g * fermi(lam[k], mu, kT);
+    t0[k] = occ * w;
+    t1[k] = lam[k] * occ * w;
+}
+
 // Pattern sanity: row pointers monotone from 0 to nnz, columns in range.
 __global__ void k_validate_pattern(int n, int64_t nnz, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                    int* __restrict__ bad) {
@@ -372,6 +416,7 @@ struct DmPlan {
     bool sep_X = false;
     bool energy = false;      // also the energy-weighted estimate (X_E = H X)
     bool hprime = false;      // also H' = S^-1/2 H S^-1/2 extracted after S^-1/2 (FP64 products)
+    bool nonorth = false;     // density of a non-orthogonal basis: Lanczos on H' from S^-1/2 r
 };
 
 struct DmBufs {
@@ -383,6 +428,7 @@ struct DmBufs {
     void* X = nullptr;
     void* XE = nullptr;       // H X (energy-weighted estimate)
     double *Y64 = nullptr, *Z1 = nullptr, *Z = nullptr, *h64 = nullptr;   // H' extraction (FP64)
+    double* R0 = nullptr;     // non-orthogonal: the first block's triangular factor
     int32_t* rp32 = nullptr;
     void* eig_ws = nullptr;
 };
@@ -405,14 +451,17 @@ void carve_dm(Arena& a, const DmPlan& p, DmBufs& bf) {
     bf.flags = a.take<int>(16);
     bf.X = p.sep_X ? a.take<char>((size_t)p.lz.Np * p.lz.ld * p.lz.elem) : bf.lz.W;
     bf.XE = p.energy ? a.take<char>((size_t)p.lz.Np * p.lz.ld * p.lz.elem) : nullptr;
-    if (p.hprime) {
+    if (p.hprime || p.nonorth) {
         const int64_t tall = p.lz.Np * p.lz.ld;
         bf.Y64 = a.take<double>(tall);
         bf.Z1 = a.take<double>(tall);
         bf.Z = a.take<double>(tall);
+    }
+    if (p.hprime) {
         bf.h64 = a.take<double>(std::max<int64_t>(1, p.lz.nnz));
         bf.rp32 = a.take<int32_t>(p.lz.n + 1);
     }
+    if (p.nonorth) bf.R0 = a.take<double>(mat);
     bf.eig_ws = p.eig_ws ? a.take<char>(p.eig_ws) : nullptr;
     bf.pole_ws = p.pole_ws ? a.take<char>(p.pole_ws) : nullptr;
 }
@@ -639,8 +688,171 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     return CSS_OK;
 }
 
+// Density matrix of a non-orthogonal basis (Eq.(9)): rho~ = S^-1/2 Phi rho^K Phi^T r~ r^T
+// with r~ = S^-1/2 r and the block Krylov space of H' from r~; S^-1/2 sparse.
+css_status nonorth_run(const css_csr* Hp, const css_csr* Sih, const css_csr* He, const css_csr* Se,
+                       const int32_t* color, const int8_t* sign, int32_t n_colors, double mu, double kT,
+                       int32_t depth, double spin_deg, const int64_t* p_row_ptr, const int32_t* p_col, int64_t p_nnz,
+                       uint32_t flags, double* p_val, double* e_band, double* n_elec, double* trace, css_info* info,
+                       void* ws, size_t ws_bytes, void* stream) {
+    if (!Hp || !Sih || !color || !sign || !p_row_ptr || !p_col || !p_val || !trace || !ws || p_nnz < 1)
+        return CSS_E_ARG;
+    if (!(kT > 0.0) || !std::isfinite(kT) || !std::isfinite(mu) || !(spin_deg > 0.0)) return CSS_E_ARG;
+    if (!Sih->row_ptr || !Sih->col || !Sih->val || Sih->n != Hp->n || Sih->val_dtype != CSS_F64 || Sih->nnz < 1 ||
+        Sih->nnz >= (int64_t(1) << 31))
+        return CSS_E_ARG;
+    if ((e_band && !He) || (n_elec && !Se)) return CSS_E_ARG;
+    for (const css_csr* M : {He, Se})
+        if (M && (M->n != Hp->n || !M->row_ptr || !M->col || !M->val || M->nnz < 1 ||
+                  (M->val_dtype != CSS_F64 && M->val_dtype != CSS_F32)))
+            return CSS_E_ARG;
+    DmPlan p;
+    CSS_TRY(plan_dm(Hp, n_colors, depth, flags | CSS_SUBSPACE_EIG, p));
+    if (p.lz.twopass) return CSS_E_UNSUPPORTED;
+    p.nonorth = true;
+    if (ws_bytes < dm_workspace_bytes(p)) return CSS_E_WORKSPACE;
+    Arena a;
+    a.base = static_cast<char*>(ws);
+    a.cap = ws_bytes;
+    DmBufs bf;
+    carve_dm(a, p, bf);
+    if (a.overflow) return CSS_E_WORKSPACE;
+    hipStream_t s = as_stream(stream);
+    const LzPlan& lz = p.lz;
+    const int64_t tall = lz.Np * lz.ld;
+
+    hipEvent_t ev[6] = {};
+    for (auto& e : ev) CSS_HIP_TRY(hipEventCreate(&e));
+    struct Guard {
+        hipEvent_t* e;
+        ~Guard() { for (int i = 0; i < 6; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
+    } guard{ev};
+    CSS_HIP_TRY(hipEventRecord(ev[0], s));
+
+    // inputs: the pattern and the sparse S^-1/2 (and H, S for the sums)
+    CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+    k_validate_pattern<<<grid_for(std::max<int64_t>(lz.n, p_nnz), 256), 256, 0, s>>>(lz.n, p_nnz, p_row_ptr, p_col,
+                                                                                     bf.flags);
+    csr_validate_launch(lz.n, Sih->nnz, Sih->row_ptr, Sih->col, bf.flags + 3, s);
+    if (He) csr_validate_launch(lz.n, He->nnz, He->row_ptr, He->col, bf.flags + 5, s);
+    if (Se) csr_validate_launch(lz.n, Se->nnz, Se->row_ptr, Se->col, bf.flags + 7, s);
+    int vbad[9] = {};
+    CSS_HIP_TRY(hipMemcpyAsync(vbad, bf.flags, 9 * sizeof(int), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    if (vbad[0] || vbad[4] || vbad[6] || vbad[8]) return CSS_E_CSR;
+    const double* sv = static_cast<const double*>(Sih->val);
+
+    // r~ = S^-1/2 r (FP64), then the Lanczos pass from it
+    k_probe_block<<<grid_for(tall, 256), 256, 0, s>>>(color, sign, lz.n, lz.Np, lz.ld, bf.Y64);
+    k_fill0<<<grid_for(tall, 256), 256, 0, s>>>(bf.Z1, tall);
+    if (!spmm_launch<double>(SpmmArgs<double>{lz.n, Sih->row_ptr, Sih->col, sv, bf.Y64, bf.Z1, lz.ld}, s))
+        return CSS_E_UNSUPPORTED;
+    int v_eff = 0, brk = 0;
+    double md = 0.0;
+    CSS_TRY(run_lanczos_pass1(Hp, color, sign, lz, bf.lz, s, &v_eff, &brk, &md, bf.Z1, bf.R0));
+    CSS_HIP_TRY(hipEventRecord(ev[1], s));
+
+    // rho^K = g f(T) by diagonalisation; F = U g f(Lambda) U[0:b,:]^T R0
+    const int nT = v_eff * lz.b;
+    const int64_t mat = (int64_t)lz.ld * lz.ld;
+    CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+    k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T, bf.flags);
+    int hbad = 0;
+    CSS_HIP_TRY(hipMemcpyAsync(&hbad, bf.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    if (hbad) return CSS_E_NONFINITE;
+    CSS_TRY(eig(bf.T, nT, bf.lam, bf.E, bf.flags + 1, bf.eig_ws, p.eig_ws, s));
+    CSS_HIP_TRY(hipEventRecord(ev[2], s));
+    k_occ_y_r0<<<grid_for((int64_t)nT * lz.b, 256), 256, 0, s>>>(bf.T, bf.lam, bf.R0, nT, lz.b, lz.ld, mu, kT,
+                                                                  spin_deg, bf.Y);
+    gemm_f64_launch(nT, lz.b, nT, bf.T, 1, nT, bf.Y, lz.b, 1, bf.F, lz.b, 1, s);
+    k_quad_terms_r0<<<grid_for(nT, 256), 256, 0, s>>>(bf.T, bf.lam, bf.R0, nT, lz.b, lz.ld, mu, kT, spin_deg, bf.t0,
+                                                      bf.t1);
+    det_sum(bf.t0, nT, bf.tmp, bf.res + 2, s);
+    det_sum(bf.t1, nT, bf.tmp + kSumBlocks, bf.res + 3, s);
+    k_pad_F<<<grid_for(v_eff * mat, 256), 256, 0, s>>>(bf.F, v_eff, lz.b, lz.ld, bf.Fpad);
+    CSS_HIP_TRY(hipEventRecord(ev[3], s));
+
+    // X' = sum_j Q_j F_j, then X = S^-1/2 X' (FP64)
+    if (lz.fp32) {
+        update_launch<float>(static_cast<float*>(bf.X), nullptr, 0.0, static_cast<const float*>(slot_ptr(lz, bf.lz, 0)),
+                             tall, v_eff, bf.Fpad, mat, false, 1.0, lz.Np, lz.ld, bf.lz.stage, nullptr, s);
+        k_widen<float><<<grid_for(tall, 256), 256, 0, s>>>(static_cast<const float*>(bf.X), bf.Y64, tall);
+    } else {
+        update_launch<double>(static_cast<double*>(bf.X), nullptr, 0.0,
+                              static_cast<const double*>(slot_ptr(lz, bf.lz, 0)), tall, v_eff, bf.Fpad, mat, false,
+                              1.0, lz.Np, lz.ld, bf.lz.stage, nullptr, s);
+        CSS_HIP_TRY(hipMemcpyAsync(bf.Y64, bf.X, tall * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    if (!spmm_launch<double>(SpmmArgs<double>{lz.n, Sih->row_ptr, Sih->col, sv, bf.Y64, bf.Z, lz.ld}, s))
+        return CSS_E_UNSUPPORTED;
+    CSS_HIP_TRY(hipEventRecord(ev[4], s));
+
+    // extraction with the probes r, the diagonal sum, H.P and S.P
+    const int sym = (flags & CSS_SYMMETRIZE) ? 1 : 0;
+    double* rt = bf.rows;
+    double* ra = bf.rows + lz.n;
+    double* re = bf.rows + 2 * (int64_t)lz.n;
+    launch_gather<double>(lz.n, p_row_ptr, p_col, color, sign, bf.Z, lz.ld, sym, p_val, rt, ra, s);
+    det_sum(rt, lz.n, bf.tmp + 2 * kSumBlocks, bf.res + 0, s);
+    det_max(ra, lz.n, bf.tmp, bf.res + 4, s);
+    for (int t = 0; t < 2; ++t) {
+        const css_csr* M = t == 0 ? He : Se;
+        if (!M) continue;
+        if (M->val_dtype == CSS_F64)
+            k_energy<double><<<grid_for(lz.n, 4), 256, 0, s>>>(lz.n, M->row_ptr, M->col,
+                                                               static_cast<const double*>(M->val), p_row_ptr, p_col,
+                                                               p_val, re);
+        else
+            k_energy<float><<<grid_for(lz.n, 4), 256, 0, s>>>(lz.n, M->row_ptr, M->col,
+                                                              static_cast<const float*>(M->val), p_row_ptr, p_col,
+                                                              p_val, re);
+        det_sum(re, lz.n, bf.tmp + 3 * kSumBlocks, bf.res + (t == 0 ? 1 : 5), s);
+    }
+    CSS_HIP_TRY(hipEventRecord(ev[5], s));
+    double hres[8] = {};
+    int hinfo = 0;
+    CSS_HIP_TRY(hipMemcpyAsync(hres, bf.res, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipMemcpyAsync(&hinfo, bf.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    CSS_HIP_TRY(hipGetLastError());
+    if (hinfo != 0) return CSS_E_EIG;
+    *trace = hres[0];
+    if (e_band) *e_band = hres[1];
+    if (n_elec) *n_elec = hres[5];
+    if (info) {
+        *info = css_info{};
+        info->depth_eff = v_eff;
+        info->n_colors = lz.b;
+        info->breakdown = brk;
+        info->spmm_kernel = bf.lz.use_grp ? 1 : 0;
+        info->min_diag_r = md;
+        info->asym_max = hres[4];
+        info->trace_krylov = hres[2];
+        info->e_band_krylov = hres[3];
+        for (int k = 0; k < 5; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess) info->t_phase_ms[k] = ms;
+        }
+        float tot = 0.f;
+        if (hipEventElapsedTime(&tot, ev[0], ev[5]) == hipSuccess) info->t_phase_ms[5] = tot;
+    }
+    return CSS_OK;
+}
+
 }  // namespace
 }  // namespace css
+
+extern "C" css_status css_density_matrix_nonorth(const css_csr* Hp, const css_csr* S_isqrt, const css_csr* H,
+                                                 const css_csr* S, const int32_t* color, const int8_t* sign,
+                                                 int32_t n_colors, double mu, double kT, int32_t depth,
+                                                 double spin_deg, const int64_t* p_row_ptr, const int32_t* p_col,
+                                                 int64_t p_nnz, uint32_t flags, double* p_val, double* e_band,
+                                                 double* n_elec, double* trace, css_info* info, void* ws,
+                                                 size_t ws_bytes, void* stream) {
+    return css::nonorth_run(Hp, S_isqrt, H, S, color, sign, n_colors, mu, kT, depth, spin_deg, p_row_ptr, p_col,
+                            p_nnz, flags, p_val, e_band, n_elec, trace, info, ws, ws_bytes, stream);
+}
 
 extern "C" css_status css_density_matrix(const css_csr* H, const int32_t* color, const int8_t* sign,
                                          int32_t n_colors, double mu, double kT, int32_t depth, double spin_deg,
@@ -773,7 +985,8 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
         return CSS_OK;
     }
     if (entry != CSS_ENTRY_LANCZOS && entry != CSS_ENTRY_DENSITY && entry != CSS_ENTRY_ENERGY_DENSITY &&
-        entry != CSS_ENTRY_FIND_MU && entry != CSS_ENTRY_INV_SQRT && entry != CSS_ENTRY_TRANSFORM_H)
+        entry != CSS_ENTRY_FIND_MU && entry != CSS_ENTRY_INV_SQRT && entry != CSS_ENTRY_TRANSFORM_H &&
+        entry != CSS_ENTRY_DENSITY_NONORTH)
         return CSS_E_ARG;
     // shape-only CSRs for planning; H's value type is not an argument, so the size
     // covers both (values in the other precision need a converted copy)
@@ -788,10 +1001,11 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
         } else {
             DmPlan p;
             const bool eig = entry == CSS_ENTRY_FIND_MU || entry == CSS_ENTRY_INV_SQRT ||
-                             entry == CSS_ENTRY_TRANSFORM_H;
+                             entry == CSS_ENTRY_TRANSFORM_H || entry == CSS_ENTRY_DENSITY_NONORTH;
             CSS_TRY(plan_dm(&H, n_colors, depth, eig ? (flags | CSS_SUBSPACE_EIG) : flags, p));
             p.energy = entry == CSS_ENTRY_ENERGY_DENSITY;
             p.hprime = entry == CSS_ENTRY_TRANSFORM_H;
+            p.nonorth = entry == CSS_ENTRY_DENSITY_NONORTH;
             most = std::max(most, dm_workspace_bytes(p));
         }
     }

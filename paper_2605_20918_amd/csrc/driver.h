@@ -62,8 +62,12 @@ void carve_lanczos(Arena& a, const LzPlan& p, LzBufs& bf);
 // steps use (the grouped kernel when it was prepared). Rows n..Np-1 of W are not written.
 css_status lanczos_spmm(const css_csr* H, const LzPlan& p, const LzBufs& bf, const void* V, void* W, hipStream_t s);
 
+// start (optional, device FP64 Np x ld, zero in the padding): the first block is
+// then Q_1 with Q_1 R0 = start (Cholesky QR of the steps, R0 ld x ld upper) instead
+// of the normalised probes; stored basis only.
 css_status run_lanczos_pass1(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p,
-                             LzBufs& bf, hipStream_t s, int* v_eff, int* breakdown, double* min_diag);
+                             LzBufs& bf, hipStream_t s, int* v_eff, int* breakdown, double* min_diag,
+                             const double* start = nullptr, double* R0 = nullptr);
 
 // Pointer to the tall block holding Q_{j} (0-based j) after pass 1 with a stored basis.
 inline void* slot_ptr(const LzPlan& p, const LzBufs& bf, int j) {

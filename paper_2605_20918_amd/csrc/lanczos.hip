@@ -199,30 +199,44 @@ struct Step {
             sym_add_launch(bf.C + j * mat(), Aj, ld, bf.state, s);
         }
         if (last) return true;
-        T* Qn = q(j + 1);
         double* R1inv = p.twopass ? bf.R1inv + j * mat() : bf.R1inv;
         double* R2inv = p.twopass ? bf.R2inv + j * mat() : bf.R2inv;
-        double* Bj = bf.B + j * mat();
+        qr(j, q(j + 1), bf.B + j * mat(), R1inv, R2inv, replay);            // W = Q_{j+1} B_j
+        return true;
+    }
+
+    // W = Qn R by Cholesky QR (twice with CholQR2); R into Rout. Factorisation idx
+    // records its smallest pivots at min_diag[2 idx ..] and fails as step idx.
+    void qr(int idx, T* Qn, double* Rout, double* R1inv, double* R2inv, bool replay) const {
+        const int ld = p.ld;
+        T* W = static_cast<T*>(bf.W);
+        T* Wt = static_cast<T*>(bf.Wt);
         if (!replay) {
             gram(W, 0, 1, W, bf.G, 0, true, 0);                               // G = W^T W
-            chol_inv_launch(bf.G, p.b, ld, bf.scal + 1, p.cholqr2 ? bf.R1 : Bj, R1inv, bf.chol_scratch,
-                            bf.state, 2 * j, bf.min_diag, s);
+            chol_inv_launch(bf.G, p.b, ld, bf.scal + 1, p.cholqr2 ? bf.R1 : Rout, R1inv, bf.chol_scratch,
+                            bf.state, 2 * idx, bf.min_diag, s);
         }
         if (p.cholqr2) {
             update(Wt, nullptr, 0.0, W, 0, 1, R1inv, 0, false, 1.0);           // Wt = W R1^-1
             if (!replay) {
                 gram(Wt, 0, 1, Wt, bf.G, 0, true, 0);
-                chol_inv_launch(bf.G, p.b, ld, nullptr, bf.R2, R2inv, bf.chol_scratch, bf.state, 2 * j + 1,
+                chol_inv_launch(bf.G, p.b, ld, nullptr, bf.R2, R2inv, bf.chol_scratch, bf.state, 2 * idx + 1,
                                 bf.min_diag, s);
-                trmm_upper_launch(bf.R2, bf.R1, Bj, ld, bf.state, s);        // B_j = R2 R1
+                trmm_upper_launch(bf.R2, bf.R1, Rout, ld, bf.state, s);      // R = R2 R1
             }
-            update(Qn, nullptr, 0.0, Wt, 0, 1, R2inv, 0, false, 1.0);          // Q_{j+1} = Wt R2^-1
+            update(Qn, nullptr, 0.0, Wt, 0, 1, R2inv, 0, false, 1.0);          // Qn = Wt R2^-1
         } else {
-            update(Qn, nullptr, 0.0, W, 0, 1, R1inv, 0, false, 1.0);           // Q_{j+1} = W R1^-1
+            update(Qn, nullptr, 0.0, W, 0, 1, R1inv, 0, false, 1.0);           // Qn = W R1^-1
         }
-        return true;
     }
 };
+
+// Start block (FP64, Np x ld, zero padding) into W in the Lanczos precision.
+template <typename T>
+__global__ void k_start_block(const double* __restrict__ in, T* __restrict__ W, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) W[i] = T(in[i]);
+}
 
 template <typename T>
 css_status prepare(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p, LzBufs& bf,
@@ -278,10 +292,24 @@ css_status prepare(const css_csr* H, const int32_t* color, const int8_t* sign, c
 
 template <typename T>
 css_status pass1_t(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p, LzBufs& bf,
-                   hipStream_t s, int* v_eff, int* breakdown, double* min_diag) {
+                   hipStream_t s, int* v_eff, int* breakdown, double* min_diag, const double* start, double* R0) {
     CSS_TRY(prepare<T>(H, color, sign, p, bf, s));
     Step<T> st{H, p, bf, s};
-    k_init_q1<T><<<grid_for(p.Np * p.ld, 256), 256, 0, s>>>(color, sign, bf.counts, p.n, p.Np, p.ld, st.q(0));
+    if (start) {
+        // general first block: Q_1 R_0 = start by the step's Cholesky QR
+        k_start_block<T><<<grid_for(p.Np * p.ld, 256), 256, 0, s>>>(start, static_cast<T*>(bf.W), p.Np * p.ld);
+        k_zero_small<<<grid_for((int64_t)p.ld * p.ld, 256), 256, 0, s>>>(R0, (int64_t)p.ld * p.ld);
+        st.qr(0, st.q(0), R0, bf.R1inv, bf.R2inv, false);
+        int hst[16];
+        CSS_HIP_TRY(hipGetLastError());
+        CSS_HIP_TRY(hipMemcpyAsync(hst, bf.state, sizeof(hst), hipMemcpyDeviceToHost, s));
+        CSS_HIP_TRY(hipStreamSynchronize(s));
+        if (hst[0]) return CSS_E_BREAKDOWN_AT_1;
+        zero_tall<T>(static_cast<T*>(bf.W), p.Np * p.ld, s);
+        if (bf.Wt) zero_tall<T>(static_cast<T*>(bf.Wt), p.Np * p.ld, s);
+    } else {
+        k_init_q1<T><<<grid_for(p.Np * p.ld, 256), 256, 0, s>>>(color, sign, bf.counts, p.n, p.Np, p.ld, st.q(0));
+    }
     for (int j = 0; j < p.v_max; ++j)
         if (!st.run(j, false, j == p.v_max - 1)) return CSS_E_UNSUPPORTED;
     CSS_HIP_TRY(hipGetLastError());
@@ -392,9 +420,11 @@ void carve_lanczos(Arena& a, const LzPlan& p, LzBufs& bf) {
 }
 
 css_status run_lanczos_pass1(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p,
-                             LzBufs& bf, hipStream_t s, int* v_eff, int* breakdown, double* min_diag) {
-    if (p.fp32) return pass1_t<float>(H, color, sign, p, bf, s, v_eff, breakdown, min_diag);
-    return pass1_t<double>(H, color, sign, p, bf, s, v_eff, breakdown, min_diag);
+                             LzBufs& bf, hipStream_t s, int* v_eff, int* breakdown, double* min_diag,
+                             const double* start, double* R0) {
+    if (start && (p.twopass || !R0)) return CSS_E_UNSUPPORTED;
+    if (p.fp32) return pass1_t<float>(H, color, sign, p, bf, s, v_eff, breakdown, min_diag, start, R0);
+    return pass1_t<double>(H, color, sign, p, bf, s, v_eff, breakdown, min_diag, start, R0);
 }
 
 css_status run_lanczos_pass2(const css_csr* H, const int32_t* color, const int8_t* sign, const LzPlan& p,

@@ -39,7 +39,7 @@ SUBSPACE_EIG = 0x100
 SPMM_CSR = 0x200
 
 (ENTRY_COLOR, ENTRY_LANCZOS, ENTRY_DENSITY, ENTRY_SPMM, ENTRY_ENERGY_DENSITY, ENTRY_FIND_MU, ENTRY_INV_SQRT,
- ENTRY_TRANSFORM_H) = 0, 1, 2, 3, 4, 5, 6, 7
+ ENTRY_TRANSFORM_H, ENTRY_DENSITY_NONORTH) = 0, 1, 2, 3, 4, 5, 6, 7, 8
 
 
 class CssError(RuntimeError):
@@ -127,6 +127,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                          ctypes.POINTER(dbl), pinfo, vp, sz, vp]
     lib.css_transform_hamiltonian.argtypes = [pcsr, pcsr, vp, vp, i32, i32, vp, vp, i64, u32, vp, vp,
                                               ctypes.POINTER(dbl), ctypes.POINTER(dbl), pinfo, vp, sz, vp]
+    lib.css_density_matrix_nonorth.argtypes = [pcsr, pcsr, pcsr, pcsr, vp, vp, i32, dbl, dbl, i32, dbl, vp, vp, i64,
+                                               u32, vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                               ctypes.POINTER(dbl), pinfo, vp, sz, vp]
     lib.css_workspace_size.argtypes = [i32, i32, i64, i32, i32, u32, ctypes.POINTER(sz)]
     lib.css_fermi_poles.argtypes = [i32, vp, vp, ctypes.POINTER(i32)]
     lib.css_fermi_poles.restype = i32
@@ -138,7 +141,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                  "css_density_matrix", "css_density_matrix_batched", "css_batched_workspace_size",
                  "css_color_batched", "css_color_batched_workspace_size",
                  "css_energy_density_matrix", "css_find_mu", "css_inv_sqrt_overlap", "css_transform_hamiltonian",
-                 "css_workspace_size"):
+                 "css_density_matrix_nonorth", "css_workspace_size"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -429,6 +432,44 @@ def css_transform_hamiltonian(H: DeviceCSR, S: DeviceCSR, color, sign, n_colors:
                                             _ptr(hp_val), ctypes.byref(y_trace), ctypes.byref(hp_trace),
                                             ctypes.byref(info), _ptr(ws), ws.numel(), _stream(dev)))
     return y_val, hp_val, float(y_trace.value), float(hp_trace.value), info.as_dict()
+
+
+def pattern_csr(p_row_ptr, p_col, values) -> DeviceCSR:
+    """A device CSR on a cutoff pattern (int64 row pointers narrowed to int32) with the
+    given values, e.g. S^(-1/2) or H' from css_transform_hamiltonian."""
+    torch = _torch()
+    if int(p_col.numel()) >= 2 ** 31:
+        raise ValueError("pattern too large for int32 row pointers")
+    return DeviceCSR(int(p_row_ptr.numel()) - 1, p_row_ptr.to(torch.int32).contiguous(), p_col.contiguous(),
+                     values.contiguous())
+
+
+def css_density_matrix_nonorth(Hp: DeviceCSR, S_isqrt: DeviceCSR, color, sign, n_colors: int, mu: float, kT: float,
+                               depth: int, p_row_ptr, p_col, flags: int, H: DeviceCSR = None, S: DeviceCSR = None,
+                               spin_deg: float = 2.0):
+    """Density matrix of a non-orthogonal basis on the pattern. Returns (p_val,
+    e_band or None, n_elec or None, trace, info dict)."""
+    torch = _torch()
+    dev = color.device
+    nnz = int(p_col.numel())
+    p_val = torch.empty(nnz, dtype=torch.float64, device=dev)
+    ws = workspace(workspace_size(ENTRY_DENSITY_NONORTH, Hp.n, Hp.nnz, n_colors, depth, flags), dev)
+    e_band = ctypes.c_double(0.0)
+    n_elec = ctypes.c_double(0.0)
+    trace = ctypes.c_double(0.0)
+    info = InfoStruct()
+    structs = [Hp.struct(), S_isqrt.struct(), H.struct() if H is not None else None,
+               S.struct() if S is not None else None]
+    refs = [ctypes.byref(x) if x is not None else None for x in structs]
+    _check("css_density_matrix_nonorth",
+           load().css_density_matrix_nonorth(refs[0], refs[1], refs[2], refs[3], _ptr(color), _ptr(sign), n_colors,
+                                             float(mu), float(kT), depth, float(spin_deg), _ptr(p_row_ptr),
+                                             _ptr(p_col), nnz, flags, _ptr(p_val),
+                                             ctypes.byref(e_band) if H is not None else None,
+                                             ctypes.byref(n_elec) if S is not None else None, ctypes.byref(trace),
+                                             ctypes.byref(info), _ptr(ws), ws.numel(), _stream(dev)))
+    return (p_val, float(e_band.value) if H is not None else None, float(n_elec.value) if S is not None else None,
+            float(trace.value), info.as_dict())
 
 
 def css_density_matrix_batched(systems, kT: float, depth: int, flags: int, concurrency: int = 4,

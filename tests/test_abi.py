@@ -15,7 +15,7 @@ def test_every_declared_symbol_is_exported():
             "css_spmm_prepare", "css_workspace_size", "css_status_string", "css_block_ld",
             "css_density_matrix_batched", "css_batched_workspace_size", "css_color_batched",
             "css_color_batched_workspace_size", "css_energy_density_matrix", "css_find_mu",
-            "css_inv_sqrt_overlap", "css_transform_hamiltonian"} <= set(names)
+            "css_inv_sqrt_overlap", "css_transform_hamiltonian", "css_density_matrix_nonorth"} <= set(names)
     lib = ctypes.CDLL(css.LIB_PATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
@@ -64,6 +64,8 @@ def test_argument_errors_before_any_device_work():
                                     None) == 1
     assert lib.css_transform_hamiltonian(None, None, None, None, 40, 10, None, None, 0, 0, None, None, None, None,
                                          None, None, 0, None) == 1
+    assert lib.css_density_matrix_nonorth(None, None, None, None, None, None, 40, 0.0, 0.01, 10, 2.0, None, None, 0,
+                                          0, None, None, None, None, None, None, 0, None) == 1
     p = ctypes.c_void_p(256)
     for ne, kT in ((0.0, 0.01), (-1.0, 0.01), (2000.0, 0.01), (float("nan"), 0.01), (100.0, 0.0)):
         assert lib.css_find_mu(ctypes.byref(csr), p, p, 40, ne, kT, 10, 2.0, 0, ctypes.byref(mu), None, None, p,

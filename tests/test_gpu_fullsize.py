@@ -113,6 +113,27 @@ def test_10k_against_the_oracle():
     dhtr = abs(hptr - href["hp_trace"]) / abs(href["hp_trace"])
     print(f"10k H' mixed: max|dH'| {dh:.3e}  rel dTr {dhtr:.3e}", flush=True)
     assert dh <= 1e-5 * hinf and dhtr <= 1e-7
+    # density matrix of the non-orthogonal basis, mixed precision, from the oracle's sparse
+    # S^(-1/2) and H' (the same inputs on both sides), against the oracle
+    import scipy.sparse as sp
+    Sh = sp.csr_matrix((href["y_val"], col, rp), shape=(ws.n, ws.n))
+    Hp = sp.csr_matrix((href["hp_val"], col, rp), shape=(ws.n, ws.n))
+    nref = D.density_matrix_nonorth(Hp, Sh, color, sign, b, MU, KT, wl["depth"], rp, col, H=ws.H.to_scipy(),
+                                    S=So.to_scipy())
+    S64 = css.DeviceCSR.from_host(So.row_ptr, So.col, So.val, "cuda", torch.float64)
+    pn, en, nn, _, ninfo = css.css_density_matrix_nonorth(
+        css.pattern_csr(g_rp, g_col, torch.as_tensor(href["hp_val"]).cuda()),
+        css.pattern_csr(g_rp, g_col, torch.as_tensor(href["y_val"]).cuda()), g_color, g_sign, g_b, MU, KT,
+        wl["depth"], g_rp, g_col, bench.flags_for("fp32"), H=H32, S=S64)
+    # P = S^(-1/2) X' (Eq.(9)): an error in X' reaches P through S^(-1/2), so the
+    # tolerance is the X-level one times max(1, ||S^(-1/2)||_inf)
+    sinf = max(1.0, float(np.max(np.abs(Sh).sum(axis=1))))
+    dpn = float(np.max(np.abs(pn.cpu().numpy() - nref["p_val"])))
+    dn = abs(nn - nref["n_elec"]) / abs(nref["n_elec"])
+    den = abs(en - nref["e_band"]) / abs(nref["e_band"])
+    print(f"10k non-orthogonal mixed: max|dP| {dpn:.3e} (||S^-1/2||_inf {sinf:.2f})  rel dN {dn:.3e}  "
+          f"rel dE {den:.3e} ({ninfo['t_phase_ms']['total']:.1f} ms)", flush=True)
+    assert ninfo["depth_eff"] == nref["v_eff"] and dpn <= 1e-5 * sinf and dn <= 1e-7 and den <= 1e-7
 
 
 def test_1m_identities_and_mixed_against_fp64():

@@ -5,6 +5,7 @@ max|dP| <= 1e-10 (the stated target); FP32 path max|dP| <= 1e-5 and relative
 band energy <= 1e-7 against the FP64 oracle.
 """
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -374,6 +375,52 @@ def test_transform_hamiltonian_parity(M, seed, prec):
     tol = (1e-10 if prec == "fp64" else 1e-5) * hinf
     assert err <= tol
     assert abs(hptr - ref["hp_trace"]) <= (1e-10 if prec == "fp64" else 1e-7) * abs(ref["hp_trace"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("M,seed", [(64, 20919), (216, 3)])
+def test_nonorth_density_parity(M, seed, prec):
+    """Density matrix of the non-orthogonal basis from the oracle's own sparse S^(-1/2) and
+    H' (both sides take the same inputs), element by element; Tr(P S), sum H.P, the
+    trace and the Krylov count too. Then the chained GPU path (S^(-1/2) and H' from
+    css_transform_hamiltonian) against the chained oracle."""
+    print(f"nonorth {prec} M={M}", flush=True)
+    flags = FP64_FLAGS if prec == "fp64" else FP32_FLAGS
+    ws, H, rp, col, color, b, sign, mu = water_case(M, seed)
+    So = synth.water_overlap(ws)
+    S = So.to_scipy()
+    n = ws.n
+    tr = D.transform_hamiltonian(H, S, color, sign, b, 10, rp, col)
+    Sh = sp.csr_matrix((tr["y_val"], col, rp), shape=(n, n))
+    Hp = sp.csr_matrix((tr["hp_val"], col, rp), shape=(n, n))
+    ref = D.density_matrix_nonorth(Hp, Sh, color, sign, b, mu, KT, 40, rp, col, H=H, S=S)
+    rp_d, col_d = dev_i64(rp), dev_i32(col)
+    Sd = css.DeviceCSR.from_host(So.row_ptr, So.col, So.val, "cuda", torch.float64)
+    Hd = to_dev(ws)
+    Sh_d = css.pattern_csr(rp_d, col_d, torch.as_tensor(tr["y_val"]).cuda())
+    Hp_d = css.pattern_csr(rp_d, col_d, torch.as_tensor(tr["hp_val"]).cuda())
+    args = (dev_i32(color), dev_i8(sign), b, mu, KT, 40, rp_d, col_d, flags)
+    p, e_band, n_elec, trace, info = css.css_density_matrix_nonorth(Hp_d, Sh_d, *args, H=Hd, S=Sd)
+    err = float(np.max(np.abs(p.cpu().numpy() - ref["p_val"])))
+    # P = S^(-1/2) X': the X-level tolerance times max(1, ||S^(-1/2)||_inf)
+    sinf = max(1.0, float(np.max(np.abs(Sh).sum(axis=1))))
+    tol = (1e-10 if prec == "fp64" else 1e-5) * sinf
+    print(f"  max|dP|={err:.3e} (||S^-1/2||_inf {sinf:.2f}) dN={abs(n_elec - ref['n_elec']):.3e} "
+          f"dE={abs(e_band - ref['e_band']):.3e} v_eff={info['depth_eff']}", flush=True)
+    assert info["depth_eff"] == ref["v_eff"]
+    assert err <= tol
+    rel = 1e-10 if prec == "fp64" else 1e-7
+    for got, want in ((n_elec, ref["n_elec"]), (e_band, ref["e_band"]), (trace, ref["trace"]),
+                      (info["trace_krylov"], ref["trace_krylov"])):
+        assert abs(got - want) <= rel * abs(want)
+    # chained: S^(-1/2) and H' from the GPU
+    y, hp, _, _, _ = css.css_transform_hamiltonian(Hd, Sd, dev_i32(color), dev_i8(sign), b, 10, rp_d, col_d, flags)
+    p2, e2, n2, _, _ = css.css_density_matrix_nonorth(css.pattern_csr(rp_d, col_d, hp), css.pattern_csr(rp_d, col_d, y),
+                                                      *args, H=Hd, S=Sd)
+    err2 = float(np.max(np.abs(p2.cpu().numpy() - ref["p_val"])))
+    print(f"  chained max|dP|={err2:.3e} dN={abs(n2 - ref['n_elec']):.3e}", flush=True)
+    assert err2 <= tol
+    assert abs(n2 - ref["n_elec"]) <= rel * abs(ref["n_elec"]) and abs(e2 - ref["e_band"]) <= rel * abs(ref["e_band"])
 
 
 def test_inv_sqrt_rejects_an_indefinite_overlap():

@@ -335,6 +335,45 @@ def test_transform_hamiltonian_is_exact_with_a_distance_two_colouring():
     assert np.max(np.abs(r["hp_val"] - want)) < 1e-14
 
 
+def test_nonorth_density_reduces_to_generalized_eigenproblem_when_b_equals_n():
+    """Every orbital its own colour, exact S^(-1/2) and H' = S^(-1/2) H S^(-1/2): the
+    Krylov space is exhausted by the first block and the estimate is the density
+    matrix of H c = e S c (scipy.linalg.eigh(H, S)); Tr(P S) is the electron count
+    sum_i g f(e_i), and sum H.P the band energy sum_i g f(e_i) e_i."""
+    import scipy.linalg as sla
+    n = 24
+    rng = np.random.default_rng(8)
+    xyz = rng.uniform(0, 1, size=(n, 3))
+    Hs = synth.random_symmetric_csr(xyz, np.zeros(3), 10.0, seed=9).to_scipy()
+    A = synth.random_symmetric_csr(xyz, np.zeros(3), 10.0, seed=12).to_scipy().toarray()
+    Sd = np.eye(n) + 0.3 * A / np.max(np.abs(np.linalg.eigvalsh(A)))
+    Sh = sla.fractional_matrix_power(Sd, -0.5).real
+    rp, col, _ = conflict_pattern(xyz, np.zeros(3), 10.0)
+    color = np.arange(n, dtype=np.int32)
+    mu, kT = 0.05, 0.2
+    r = D.density_matrix_nonorth(sp.csr_matrix(Sh @ Hs.toarray() @ Sh), sp.csr_matrix(Sh), color,
+                                 probe_signs(n, 4), n, mu, kT, 3, rp, col, H=Hs, S=sp.csr_matrix(Sd))
+    ref = D.dense_fermi_dm_generalized(Hs, Sd, mu, kT)
+    assert r["v_eff"] == 1
+    assert np.max(np.abs(r["p_val"] - ref[D.pattern_rows(rp), col])) < 1e-12
+    e = sla.eigh(Hs.toarray(), Sd, eigvals_only=True)
+    occ = 2.0 / (np.exp((e - mu) / kT) + 1.0)
+    assert abs(r["n_elec"] - occ.sum()) < 1e-11 and abs(r["e_band"] - (occ * e).sum()) < 1e-11
+
+
+def test_nonorth_density_with_unit_overlap_is_the_orthogonal_one():
+    """S = I (S^(-1/2) = I, H' = H): the general first block r has the QR r = Q_1 diag(sqrt n_c),
+    so the estimate is the orthogonal one."""
+    ws, H, rp, col, color, b, sign = small_water(M=64, seed=20919)
+    mu = D.mu_midgap_dense(H, ws.n_electrons)
+    I = sp.identity(ws.n, format="csr")
+    r = D.density_matrix_nonorth(H, I, color, sign, b, mu, 0.01, 40, rp, col)
+    o = D.density_matrix(H, color, sign, b, mu, 0.01, 40, rp, col)
+    assert r["v_eff"] == o["v_eff"]
+    assert np.max(np.abs(r["p_val"] - o["p_val"])) < 1e-10
+    assert np.allclose(np.diag(r["lanczos"].r0), o["lanczos"].b0, rtol=1e-14)
+
+
 # ---------------------------------------------------------------- energy-weighted DM
 
 def test_energy_dm_reduces_to_dense_when_b_equals_n():
