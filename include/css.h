@@ -307,7 +307,9 @@ css_status css_transform_hamiltonian(const css_csr* H, const css_csr* S, const i
  *   (Eq.(9)): rho~ = S^(-1/2) Phi rho^K Phi^T r~ r^T, with r the probes, r~ =
  *   S^(-1/2) r, Phi the block Krylov basis of H' = S^(-1/2) H S^(-1/2) from r~
  *   (the first block Q_1 R_0 = r~ by Cholesky QR, so B_0 = R_0 is triangular) and
- *   rho^K = g f(T) by dense diagonalisation (Eq.(10), rocSOLVER dsyevd). Only
+ *   rho^K = g f(T) (Eq.(10)) by the pole expansion of css_density_matrix with
+ *   B_0 = I, then F = F_I R_0 (F is linear in B_0), or with CSS_SUBSPACE_EIG by
+ *   dense diagonalisation (rocSOLVER dsyevd). Only
  *   sparse x block products: r~ = S^(-1/2) r and X = S^(-1/2) X' in FP64, the
  *   Lanczos steps on H' in the precision the flags select. Then P_mn =
  *   sign[n] X[m, colour(n)] on the pattern (symmetrised with CSS_SYMMETRIZE).
@@ -321,14 +323,15 @@ css_status css_transform_hamiltonian(const css_csr* H, const css_csr* S, const i
  *                css_density_matrix (the probes r on the density's cutoff)
  *   flags        precision and re-orthogonalisation as css_density_matrix; stored
  *                basis only (CSS_E_UNSUPPORTED with CSS_BASIS_TWOPASS);
- *                CSS_SUBSPACE_EIG is implied
+ *                CSS_SUBSPACE_EIG selects the dense diagonalisation
  *   p_val        device double[p_nnz] out
  *   e_band       host out (NULL allowed when H is NULL)
  *   n_elec       host out (NULL allowed when S is NULL)
  *   trace        host out: sum_m P_mm
  *   info         host out (may be NULL): as css_density_matrix; trace_krylov =
- *                sum_k g f(lambda_k) w_k with w_k = |R_0^T U[0:b,k]|^2 (the Krylov
- *                estimate of Tr(r~^T f(H') r~), which is Tr(P_raw) up to rounding)
+ *                Tr(R_0^T [g f(T)]_11 R_0) = sum_k g f(lambda_k) |R_0^T U[0:b,k]|^2
+ *                (the Krylov estimate of Tr(r~^T g f(H') r~), which is Tr(P_raw)
+ *                up to rounding) and e_band_krylov the same with T g f(T)
  *   ws           css_workspace_size(CSS_ENTRY_DENSITY_NONORTH, n, nnz of H', ...)
  *   Errors as css_density_matrix; CSS_E_BREAKDOWN_AT_1 when r~ is rank deficient.
  *   Synchronises the stream before returning.

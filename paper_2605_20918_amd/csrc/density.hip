@@ -279,6 +279,48 @@ __global__ void k_quad_terms_r0(const double* __restrict__ U, const double* __re
     t1[k] = lam[k] * occ * w;
 }
 
+__global__ void k_fill_ones(int* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 1;
+}
+
+// Krylov sums with a triangular B_0 = R0 from F = g f(T) E_1 R0 (nT x b):
+// trace_K = sum R0 .* F_1, E_K = sum R0 .* (A_1 F_1 + B_1^T F_2) over the b x b
+// leading blocks (elementwise products, entries with c' <= c). One workgroup,
+// strided per-thread sums, then a fixed tree.
+constexpr int kR0SumThreads = 1024;
+__global__ __launch_bounds__(kR0SumThreads) void k_krylov_sums_r0(const double* __restrict__ A,
+                                                                   const double* __restrict__ B,
+                                                                   const double* __restrict__ F,
+                                                                   const double* __restrict__ R0, int v, int b,
+                                                                   int ld, double* __restrict__ out) {
+    __shared__ double st[kR0SumThreads], se[kR0SumThreads];
+    double tr = 0.0, en = 0.0;
+    for (int e = threadIdx.x; e < b * b; e += kR0SumThreads) {
+        const int cp = e / b, c = e % b;
+        if (cp > c) continue;
+        const double r = R0[(int64_t)cp * ld + c];
+        double g = 0.0;
+        for (int k = 0; k < b; ++k) {
+            g += A[(int64_t)cp * ld + k] * F[(int64_t)k * b + c];
+            if (v > 1) g += B[(int64_t)k * ld + cp] * F[(int64_t)(b + k) * b + c];
+        }
+        tr += r * F[(int64_t)cp * b + c];
+        en += r * g;
+    }
+    st[threadIdx.x] = tr;
+    se[threadIdx.x] = en;
+    __syncthreads();
+    for (int h = kR0SumThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            st[threadIdx.x] += st[threadIdx.x + h];
+            se[threadIdx.x] += se[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = st[0]; out[1] = se[0]; }
+}
+
 // Pattern sanity: row pointers monotone from 0 to nnz, columns in range.
 __global__ void k_validate_pattern(int n, int64_t nnz, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                    int* __restrict__ bad) {
@@ -429,6 +471,7 @@ struct DmBufs {
     void* XE = nullptr;       // H X (energy-weighted estimate)
     double *Y64 = nullptr, *Z1 = nullptr, *Z = nullptr, *h64 = nullptr;   // H' extraction (FP64)
     double* R0 = nullptr;     // non-orthogonal: the first block's triangular factor
+    int* ones = nullptr;      // non-orthogonal pole path: B_0 = I for the pole solve
     int32_t* rp32 = nullptr;
     void* eig_ws = nullptr;
 };
@@ -440,7 +483,7 @@ void carve_dm(Arena& a, const DmPlan& p, DmBufs& bf) {
     bf.T = p.use_eig ? a.take<double>(nT * nT) : nullptr;
     bf.lam = a.take<double>(nT);
     bf.E = a.take<double>(nT);
-    bf.Y = p.use_eig ? a.take<double>(nT * p.lz.b) : nullptr;
+    bf.Y = (p.use_eig || p.nonorth) ? a.take<double>(nT * p.lz.b) : nullptr;
     bf.F = a.take<double>(nT * p.lz.b);
     bf.Fpad = a.take<double>(std::max(1, p.lz.v_max) * mat);
     bf.t0 = a.take<double>(nT);
@@ -461,7 +504,10 @@ void carve_dm(Arena& a, const DmPlan& p, DmBufs& bf) {
         bf.h64 = a.take<double>(std::max<int64_t>(1, p.lz.nnz));
         bf.rp32 = a.take<int32_t>(p.lz.n + 1);
     }
-    if (p.nonorth) bf.R0 = a.take<double>(mat);
+    if (p.nonorth) {
+        bf.R0 = a.take<double>(mat);
+        bf.ones = a.take<int>(p.lz.b);
+    }
     bf.eig_ws = p.eig_ws ? a.take<char>(p.eig_ws) : nullptr;
     bf.pole_ws = p.pole_ws ? a.take<char>(p.pole_ws) : nullptr;
 }
@@ -707,7 +753,7 @@ css_status nonorth_run(const css_csr* Hp, const css_csr* Sih, const css_csr* He,
                   (M->val_dtype != CSS_F64 && M->val_dtype != CSS_F32)))
             return CSS_E_ARG;
     DmPlan p;
-    CSS_TRY(plan_dm(Hp, n_colors, depth, flags | CSS_SUBSPACE_EIG, p));
+    CSS_TRY(plan_dm(Hp, n_colors, depth, flags, p));
     if (p.lz.twopass) return CSS_E_UNSUPPORTED;
     p.nonorth = true;
     if (ws_bytes < dm_workspace_bytes(p)) return CSS_E_WORKSPACE;
@@ -752,24 +798,37 @@ css_status nonorth_run(const css_csr* Hp, const css_csr* Sih, const css_csr* He,
     CSS_TRY(run_lanczos_pass1(Hp, color, sign, lz, bf.lz, s, &v_eff, &brk, &md, bf.Z1, bf.R0));
     CSS_HIP_TRY(hipEventRecord(ev[1], s));
 
-    // rho^K = g f(T) by diagonalisation; F = U g f(Lambda) U[0:b,:]^T R0
+    // rho^K = g f(T); F = g f(T) E_1 R0
     const int nT = v_eff * lz.b;
     const int64_t mat = (int64_t)lz.ld * lz.ld;
+    int npoles = 0;
     CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
-    k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T, bf.flags);
-    int hbad = 0;
-    CSS_HIP_TRY(hipMemcpyAsync(&hbad, bf.flags, sizeof(int), hipMemcpyDeviceToHost, s));
-    CSS_HIP_TRY(hipStreamSynchronize(s));
-    if (hbad) return CSS_E_NONFINITE;
-    CSS_TRY(eig(bf.T, nT, bf.lam, bf.E, bf.flags + 1, bf.eig_ws, p.eig_ws, s));
-    CSS_HIP_TRY(hipEventRecord(ev[2], s));
-    k_occ_y_r0<<<grid_for((int64_t)nT * lz.b, 256), 256, 0, s>>>(bf.T, bf.lam, bf.R0, nT, lz.b, lz.ld, mu, kT,
-                                                                  spin_deg, bf.Y);
-    gemm_f64_launch(nT, lz.b, nT, bf.T, 1, nT, bf.Y, lz.b, 1, bf.F, lz.b, 1, s);
-    k_quad_terms_r0<<<grid_for(nT, 256), 256, 0, s>>>(bf.T, bf.lam, bf.R0, nT, lz.b, lz.ld, mu, kT, spin_deg, bf.t0,
-                                                      bf.t1);
-    det_sum(bf.t0, nT, bf.tmp, bf.res + 2, s);
-    det_sum(bf.t1, nT, bf.tmp + kSumBlocks, bf.res + 3, s);
+    if (p.use_eig) {
+        // by diagonalisation: F = U g f(Lambda) U[0:b,:]^T R0
+        k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T,
+                                                                     bf.flags);
+        int hbad = 0;
+        CSS_HIP_TRY(hipMemcpyAsync(&hbad, bf.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+        CSS_HIP_TRY(hipStreamSynchronize(s));
+        if (hbad) return CSS_E_NONFINITE;
+        CSS_TRY(eig(bf.T, nT, bf.lam, bf.E, bf.flags + 1, bf.eig_ws, p.eig_ws, s));
+        CSS_HIP_TRY(hipEventRecord(ev[2], s));
+        k_occ_y_r0<<<grid_for((int64_t)nT * lz.b, 256), 256, 0, s>>>(bf.T, bf.lam, bf.R0, nT, lz.b, lz.ld, mu, kT,
+                                                                      spin_deg, bf.Y);
+        gemm_f64_launch(nT, lz.b, nT, bf.T, 1, nT, bf.Y, lz.b, 1, bf.F, lz.b, 1, s);
+        k_quad_terms_r0<<<grid_for(nT, 256), 256, 0, s>>>(bf.T, bf.lam, bf.R0, nT, lz.b, lz.ld, mu, kT, spin_deg,
+                                                          bf.t0, bf.t1);
+        det_sum(bf.t0, nT, bf.tmp, bf.res + 2, s);
+        det_sum(bf.t1, nT, bf.tmp + kSumBlocks, bf.res + 3, s);
+    } else {
+        // by the pole expansion with B_0 = I (F is linear in B_0), then F = F_I R0
+        k_fill_ones<<<grid_for(lz.b, 256), 256, 0, s>>>(bf.ones, lz.b);
+        CSS_TRY(subspace_fermi_poles(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.ones, mu, kT, spin_deg, bf.Y,
+                                     bf.res + 6, bf.pole_ws, p.pole_ws, &npoles, s));
+        CSS_HIP_TRY(hipEventRecord(ev[2], s));
+        gemm_f64_launch(nT, lz.b, lz.b, bf.Y, lz.b, 1, bf.R0, lz.ld, 1, bf.F, lz.b, 1, s);
+        k_krylov_sums_r0<<<1, kR0SumThreads, 0, s>>>(bf.lz.A, bf.lz.B, bf.F, bf.R0, v_eff, lz.b, lz.ld, bf.res + 2);
+    }
     k_pad_F<<<grid_for(v_eff * mat, 256), 256, 0, s>>>(bf.F, v_eff, lz.b, lz.ld, bf.Fpad);
     CSS_HIP_TRY(hipEventRecord(ev[3], s));
 
@@ -828,6 +887,7 @@ css_status nonorth_run(const css_csr* Hp, const css_csr* Sih, const css_csr* He,
         info->spmm_kernel = bf.lz.use_grp ? 1 : 0;
         info->min_diag_r = md;
         info->asym_max = hres[4];
+        info->n_poles = npoles;
         info->trace_krylov = hres[2];
         info->e_band_krylov = hres[3];
         for (int k = 0; k < 5; ++k) {
@@ -1001,7 +1061,7 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
         } else {
             DmPlan p;
             const bool eig = entry == CSS_ENTRY_FIND_MU || entry == CSS_ENTRY_INV_SQRT ||
-                             entry == CSS_ENTRY_TRANSFORM_H || entry == CSS_ENTRY_DENSITY_NONORTH;
+                             entry == CSS_ENTRY_TRANSFORM_H;
             CSS_TRY(plan_dm(&H, n_colors, depth, eig ? (flags | CSS_SUBSPACE_EIG) : flags, p));
             p.energy = entry == CSS_ENTRY_ENERGY_DENSITY;
             p.hprime = entry == CSS_ENTRY_TRANSFORM_H;

@@ -377,7 +377,7 @@ def test_transform_hamiltonian_parity(M, seed, prec):
     assert abs(hptr - ref["hp_trace"]) <= (1e-10 if prec == "fp64" else 1e-7) * abs(ref["hp_trace"])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64-eig"])
 @pytest.mark.parametrize("M,seed", [(64, 20919), (216, 3)])
 def test_nonorth_density_parity(M, seed, prec):
     """Density matrix of the non-orthogonal basis from the oracle's own sparse S^(-1/2) and
@@ -385,7 +385,8 @@ def test_nonorth_density_parity(M, seed, prec):
     trace and the Krylov count too. Then the chained GPU path (S^(-1/2) and H' from
     css_transform_hamiltonian) against the chained oracle."""
     print(f"nonorth {prec} M={M}", flush=True)
-    flags = FP64_FLAGS if prec == "fp64" else FP32_FLAGS
+    flags = {"fp64": FP64_FLAGS, "fp32": FP32_FLAGS, "fp64-eig": FP64_FLAGS | css.SUBSPACE_EIG}[prec]
+    prec = prec[:4]
     ws, H, rp, col, color, b, sign, mu = water_case(M, seed)
     So = synth.water_overlap(ws)
     S = So.to_scipy()
@@ -411,7 +412,7 @@ def test_nonorth_density_parity(M, seed, prec):
     assert err <= tol
     rel = 1e-10 if prec == "fp64" else 1e-7
     for got, want in ((n_elec, ref["n_elec"]), (e_band, ref["e_band"]), (trace, ref["trace"]),
-                      (info["trace_krylov"], ref["trace_krylov"])):
+                      (info["trace_krylov"], ref["trace_krylov"]), (info["e_band_krylov"], ref["e_band_krylov"])):
         assert abs(got - want) <= rel * abs(want)
     # chained: S^(-1/2) and H' from the GPU
     y, hp, _, _, _ = css.css_transform_hamiltonian(Hd, Sd, dev_i32(color), dev_i8(sign), b, 10, rp_d, col_d, flags)
