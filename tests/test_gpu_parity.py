@@ -588,6 +588,69 @@ def test_every_orbital_its_own_colour_gives_dense_fermi():
     assert np.max(np.abs(p.cpu().numpy() - P[D.pattern_rows(rp), col])) < 1e-12
 
 
+def test_find_mu_closed_form_for_scaled_identity():
+    """H = c I: one Krylov block, count g N f(c; mu), so mu = c - kT ln(g N / N_e - 1)."""
+    n, c = 48, -0.37
+    xyz, box = synth.chain_1d(n, 1.0)
+    rp, col, deg = conflict_pattern(xyz, box, 2.0)
+    color, b = greedy_color(rp, col, deg)
+    Hd = css.DeviceCSR.from_host(np.arange(n + 1), np.arange(n), np.full(n, c), "cuda", torch.float64)
+    for ne in (10.0, 48.0, 90.0):
+        mu, count, info = css.css_find_mu(Hd, dev_i32(color), dev_i8(probe_signs(n, 2)), b, ne, KT, 6, FP64_FLAGS)
+        assert info["depth_eff"] == 1
+        assert abs(mu - (c - KT * np.log(2.0 * n / ne - 1.0))) < 1e-12 and abs(count - ne) < 1e-9
+
+
+def test_energy_dm_two_pass_equals_stored_basis():
+    """The two-pass reconstruction replays the stored coefficients, so P_E (and P) match
+    the stored basis to rounding."""
+    ws, H, rp, col, color, b, sign, mu = water_case(216, 3)
+    args = (to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, 40, dev_i64(rp), dev_i32(col))
+    p1, pe1, *_ = css.css_energy_density_matrix(*args, FP64_FLAGS)
+    p1, pe1 = p1.clone(), pe1.clone()
+    p2, pe2, *_ = css.css_energy_density_matrix(*args, css.PREC_FP64 | css.REORTH_LOCAL | css.CHOLQR2 |
+                                               css.SYMMETRIZE | css.BASIS_TWOPASS)
+    p3, pe3, *_ = css.css_energy_density_matrix(*args, css.PREC_FP64 | css.REORTH_LOCAL | css.CHOLQR2 |
+                                               css.SYMMETRIZE)
+    assert torch.max(torch.abs(p2 - p3)).item() < 1e-12 and torch.max(torch.abs(pe2 - pe3)).item() < 1e-12
+    assert torch.max(torch.abs(pe1 - pe2)).item() < 1e-9
+
+
+def test_nonorthogonal_entry_errors():
+    """Errors of the non-orthogonal entry points, each caught before the data is used."""
+    ws, H, rp, col, color, b, sign, mu = water_case(64, 20919)
+    So = synth.water_overlap(ws)
+    Sd = css.DeviceCSR.from_host(So.row_ptr, So.col, So.val, "cuda", torch.float64)
+    rp_d, col_d = dev_i64(rp), dev_i32(col)
+    y, hp, *_ = css.css_transform_hamiltonian(to_dev(ws), Sd, dev_i32(color), dev_i8(sign), b, 10, rp_d, col_d,
+                                              FP64_FLAGS)
+    Hp, Sh = css.pattern_csr(rp_d, col_d, hp), css.pattern_csr(rp_d, col_d, y)
+    args = (dev_i32(color), dev_i8(sign), b, mu, KT, 10, rp_d, col_d)
+    with pytest.raises(css.CssError) as e:                       # two-pass: stored basis only
+        css.css_density_matrix_nonorth(Hp, Sh, *args, FP64_FLAGS | css.BASIS_TWOPASS)
+    assert e.value.code == 8
+    with pytest.raises(css.CssError) as e:                       # S^(-1/2) values must be FP64
+        css.css_density_matrix_nonorth(Hp, css.pattern_csr(rp_d, col_d, y.float()), *args, FP64_FLAGS)
+    assert e.value.code == 1
+    bad = css.pattern_csr(rp_d, col_d, y)
+    bad.row_ptr = bad.row_ptr.clone()
+    bad.row_ptr[5] = bad.row_ptr[6] + 3                          # malformed S^(-1/2) rows
+    with pytest.raises(css.CssError) as e:
+        css.css_density_matrix_nonorth(Hp, bad, *args, FP64_FLAGS)
+    assert e.value.code == 2
+    # H with more entries than S (its FP64 copy is sized by S): argument error
+    Sdiag = css.DeviceCSR.from_host(np.arange(ws.n + 1), np.arange(ws.n), np.full(ws.n, 1.0), "cuda", torch.float64)
+    with pytest.raises(css.CssError) as e:
+        css.css_transform_hamiltonian(to_dev(ws), Sdiag, dev_i32(color), dev_i8(sign), b, 10, rp_d, col_d, FP64_FLAGS)
+    assert e.value.code == 1
+    bad_rp = ws.H.row_ptr.copy()
+    bad_rp[5] = bad_rp[6] + 3                                    # malformed H rows
+    Hb = css.DeviceCSR.from_host(bad_rp, ws.H.col, ws.H.val, "cuda", torch.float64)
+    with pytest.raises(css.CssError) as e:
+        css.css_transform_hamiltonian(Hb, Sd, dev_i32(color), dev_i8(sign), b, 10, rp_d, col_d, FP64_FLAGS)
+    assert e.value.code == 2
+
+
 def test_errors_are_reported():
     ws, H, rp, col, color, b, sign, mu = water_case(64, 20919)
     good = (to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, 4, dev_i64(rp), dev_i32(col), FP64_FLAGS)
