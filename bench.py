@@ -221,6 +221,9 @@ def main():
     ap.add_argument("--workload", default="10k", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 10k-only extra entry points (energy-weighted, mu, S^-1/2, H', "
+                         "non-orthogonal) after the timed region")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -329,7 +332,7 @@ def main():
                      "kernel_sha256_16": kernel_hash()},
     }
 
-    if args.workload == "10k":
+    if args.workload == "10k" and not args.no_extras:
         # the energy-weighted estimate P_E = (H X) r^T on the pattern: its cost over a
         # density call alone (one more sparse x block product and gather)
         color, bb, p_rp, p_col, _ = css.css_color(xyz, box, R_CUT)
