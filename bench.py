@@ -360,7 +360,7 @@ def main():
         torch.cuda.synchronize()
         out["mu_search"] = {"ms": (time.perf_counter() - t) * 1e3, "mu": mu_k, "count": count_k,
                             "n_electrons": ws.n_electrons, "mu_used": mu,
-                            "phase_ms": minfo["t_phase_ms"]}
+                            "phase_ms": minfo["t_phase_ms"], "count_evaluations": minfo["n_evals"]}
         # S^(-1/2) of the overlap matrix on the same pattern (non-orthogonal basis), v^s = 10
         So = synth.water_overlap(ws)
         Sdev = css.DeviceCSR.from_host(So.row_ptr, So.col, So.val, dev, torch.float32)

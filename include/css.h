@@ -99,7 +99,7 @@ typedef struct {
     int32_t breakdown;        /* 1 if the recurrence stopped early on a degenerate block */
     int32_t n_poles;          /* poles of the Fermi expansion (0 with CSS_SUBSPACE_EIG) */
     int32_t spmm_kernel;      /* 1: the 16-row grouped MFMA SpMM ran, 0: the CSR kernel */
-    int32_t reserved;
+    int32_t n_evals;          /* css_find_mu: evaluations of the electron count (0 elsewhere) */
     double min_diag_r;        /* smallest diagonal of the Cholesky factors of W^T W */
     double asym_max;          /* max |P_raw - (P_raw + P_raw^T)/2| on the pattern */
     double trace_krylov;      /* sum_k g f(lambda_k) w_k (Krylov quadrature of Tr P) */
@@ -346,21 +346,25 @@ css_status css_density_matrix_nonorth(const css_csr* Hp, const css_csr* S_isqrt,
 
 /*
  * css_find_mu -- the chemical potential for a given electron count (the mu of
- *   Eq.(1) that an SCF cycle must supply): block Lanczos as in css_density_matrix,
- *   T = U diag(lambda) U^T by dense diagonalisation (Eq.(7); rocSOLVER dsyevd),
- *   Krylov quadrature weights w_k = sum_c n_c U[c,k]^2, then bisection for the mu
- *   at which the quadrature count sum_k g f_mu(lambda_k) w_k (the Krylov estimate
- *   of Tr P, Eq.(6)-(7)) equals n_electrons. The count is monotone in mu; the
- *   bracket is [min lambda - 50 kT, max lambda + 50 kT] and the search stops when
- *   it is narrower than 1e-13 max(1, |ends|).
+ *   Eq.(1) that an SCF cycle must supply): the mu at which the Krylov quadrature
+ *   count N(mu) = Tr(B_0^T [g f_mu(T)]_11 B_0) = sum_k g f_mu(lambda_k) w_k (the
+ *   Krylov estimate of Tr P, Eqs.(6)-(7), monotone in mu) equals n_electrons,
+ *   after one block Lanczos pass as in css_density_matrix.
+ *   Default: N(mu) from the pole expansion of css_density_matrix's subspace step
+ *   at each trial mu, root by Brent's method on the Gershgorin bracket of T widened
+ *   by 50 kT, to an interval of 1e-13 max(1, |ends|).
+ *   CSS_SUBSPACE_EIG (and n_colors > 128): T = U diag(lambda) U^T by rocSOLVER
+ *   dsyevd, w_k = sum_c n_c U[c,k]^2, bisection on the device on
+ *   [min lambda - 50 kT, max lambda + 50 kT] to the same width.
  *   H, color, sign, n_colors, kT, depth, spin_deg, flags as css_density_matrix
- *   (CSS_SUBSPACE_EIG is implied; CSS_SYMMETRIZE has no effect).
+ *   (CSS_SYMMETRIZE has no effect).
  *   n_electrons  in (0, spin_deg * n), else CSS_E_ARG before any device work
  *   mu           host out: the chemical potential
  *   count        host out (may be NULL): the quadrature count at mu
  *   info         host out (may be NULL): depth_eff, n_colors, breakdown,
- *                min_diag_r, trace_krylov (= count), t_phase_ms[0..2] (lanczos,
- *                diagonalisation, bisection) and [5] (total)
+ *                min_diag_r, trace_krylov (= count), n_evals, t_phase_ms[0..2]
+ *                (lanczos, spectral bounds or diagonalisation, root search) and
+ *                [5] (total)
  *   ws           css_workspace_size(CSS_ENTRY_FIND_MU, ...) bytes, device.
  *   Synchronises the stream before returning.
  */

@@ -961,6 +961,72 @@ extern "C" css_status css_transform_hamiltonian(const css_csr* H, const css_csr*
     return CSS_OK;
 }
 
+namespace css {
+namespace {
+
+// Root of c(mu) - n_e on [lo, hi] with c(lo) = c_lo < n_e < c_hi = c(hi) by Brent's
+// method (inverse quadratic interpolation, secant steps and bisection, as in Brent,
+// "Algorithms for Minimization without Derivatives", 1973, ch. 4), to an interval of
+// xtol or a residual |c - n_e| <= ftol. eval(mu, &c) computes c(mu); *evals counts
+// the calls.
+template <typename Eval>
+css_status brent_root(Eval&& eval, double lo, double hi, double c_lo, double c_hi, double n_e, double xtol,
+                      double ftol, double* root, double* c_root, int* evals) {
+    double a = lo, b = hi, fa = c_lo - n_e, fb = c_hi - n_e;
+    double c = a, fc = fa, d = b - a, e = d;
+    *evals = 0;
+    for (int it = 0; it < 200; ++it) {
+        if ((fb > 0.0) == (fc > 0.0)) {
+            c = a;
+            fc = fa;
+            d = e = b - a;
+        }
+        if (std::fabs(fc) < std::fabs(fb)) {
+            a = b; b = c; c = a;
+            fa = fb; fb = fc; fc = fa;
+        }
+        const double tol1 = 2.0 * 2.220446049250313e-16 * std::fabs(b) + 0.5 * xtol;
+        const double xm = 0.5 * (c - b);
+        if (std::fabs(xm) <= tol1 || std::fabs(fb) <= ftol) break;
+        if (std::fabs(e) >= tol1 && std::fabs(fa) > std::fabs(fb)) {
+            const double sr = fb / fa;
+            double pp, qq;
+            if (a == c) {
+                pp = 2.0 * xm * sr;
+                qq = 1.0 - sr;
+            } else {
+                const double q0 = fa / fc, r0 = fb / fc;
+                pp = sr * (2.0 * xm * q0 * (q0 - r0) - (b - a) * (r0 - 1.0));
+                qq = (q0 - 1.0) * (r0 - 1.0) * (sr - 1.0);
+            }
+            if (pp > 0.0) qq = -qq; else pp = -pp;
+            if (2.0 * pp < std::min(3.0 * xm * qq - std::fabs(tol1 * qq), std::fabs(e * qq))) {
+                e = d;
+                d = pp / qq;
+            } else {
+                d = xm;
+                e = d;
+            }
+        } else {
+            d = xm;
+            e = d;
+        }
+        a = b;
+        fa = fb;
+        b += std::fabs(d) > tol1 ? d : std::copysign(tol1, xm);
+        double cb = 0.0;
+        CSS_TRY(eval(b, &cb));
+        ++*evals;
+        fb = cb - n_e;
+    }
+    *root = b;
+    *c_root = fb + n_e;
+    return CSS_OK;
+}
+
+}  // namespace
+}  // namespace css
+
 extern "C" css_status css_find_mu(const css_csr* H, const int32_t* color, const int8_t* sign, int32_t n_colors,
                                   double n_electrons, double kT, int32_t depth, double spin_deg, uint32_t flags,
                                   double* mu, double* count, css_info* info, void* ws, size_t ws_bytes,
@@ -968,8 +1034,9 @@ extern "C" css_status css_find_mu(const css_csr* H, const int32_t* color, const 
     if (!H || !color || !sign || !mu || !ws) return CSS_E_ARG;
     if (!(kT > 0.0) || !std::isfinite(kT) || !(spin_deg > 0.0) || !std::isfinite(spin_deg)) return CSS_E_ARG;
     if (!(n_electrons > 0.0) || !(n_electrons < spin_deg * (double)H->n)) return CSS_E_ARG;
+    if (n_colors > 128) flags |= CSS_SUBSPACE_EIG;       // the pole solves take b <= 128
     DmPlan p;
-    CSS_TRY(plan_dm(H, n_colors, depth, flags | CSS_SUBSPACE_EIG, p));
+    CSS_TRY(plan_dm(H, n_colors, depth, flags, p));
     if (ws_bytes < dm_workspace_bytes(p)) return CSS_E_WORKSPACE;
     Arena a;
     a.base = static_cast<char*>(ws);
@@ -993,24 +1060,54 @@ extern "C" css_status css_find_mu(const css_csr* H, const int32_t* color, const 
     CSS_HIP_TRY(hipEventRecord(ev[1], s));
 
     const int nT = v_eff * lz.b;
-    CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
-    k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T, bf.flags);
-    int hbad = 0;
-    CSS_HIP_TRY(hipMemcpyAsync(&hbad, bf.flags, sizeof(int), hipMemcpyDeviceToHost, s));
-    CSS_HIP_TRY(hipStreamSynchronize(s));
-    if (hbad) return CSS_E_NONFINITE;
-    CSS_TRY(eig(bf.T, nT, bf.lam, bf.E, bf.flags + 1, bf.eig_ws, p.eig_ws, s));
-    CSS_HIP_TRY(hipEventRecord(ev[2], s));
-    k_quad_weights<<<grid_for(nT, 256), 256, 0, s>>>(bf.T, bf.lz.counts, nT, lz.b, bf.t0);
-    k_mu_bisect<<<1, kMuThreads, 0, s>>>(bf.lam, bf.t0, nT, n_electrons, kT, spin_deg, 1e-13, bf.res);
-    CSS_HIP_TRY(hipGetLastError());
-    CSS_HIP_TRY(hipEventRecord(ev[3], s));
-    double hres[5];
-    int hinfo = 0;
-    CSS_HIP_TRY(hipMemcpyAsync(hres, bf.res, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
-    CSS_HIP_TRY(hipMemcpyAsync(&hinfo, bf.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    CSS_HIP_TRY(hipStreamSynchronize(s));
-    if (hinfo != 0) return CSS_E_EIG;
+    double hres[5] = {};
+    int evals = 0;
+    if (p.use_eig) {
+        // eigenpairs of T, weights, bisection on the device
+        CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+        k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T,
+                                                                     bf.flags);
+        int hbad = 0;
+        CSS_HIP_TRY(hipMemcpyAsync(&hbad, bf.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+        CSS_HIP_TRY(hipStreamSynchronize(s));
+        if (hbad) return CSS_E_NONFINITE;
+        CSS_TRY(eig(bf.T, nT, bf.lam, bf.E, bf.flags + 1, bf.eig_ws, p.eig_ws, s));
+        CSS_HIP_TRY(hipEventRecord(ev[2], s));
+        k_quad_weights<<<grid_for(nT, 256), 256, 0, s>>>(bf.T, bf.lz.counts, nT, lz.b, bf.t0);
+        k_mu_bisect<<<1, kMuThreads, 0, s>>>(bf.lam, bf.t0, nT, n_electrons, kT, spin_deg, 1e-13, bf.res);
+        CSS_HIP_TRY(hipGetLastError());
+        CSS_HIP_TRY(hipEventRecord(ev[3], s));
+        int hinfo = 0;
+        CSS_HIP_TRY(hipMemcpyAsync(hres, bf.res, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+        CSS_HIP_TRY(hipMemcpyAsync(&hinfo, bf.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+        CSS_HIP_TRY(hipStreamSynchronize(s));
+        if (hinfo != 0) return CSS_E_EIG;
+        evals = (int)hres[2];
+    } else {
+        // the count at each trial mu from the pole expansion (the Krylov trace of
+        // css_density_matrix), root by Brent's method on the Gershgorin bracket
+        // widened by 50 kT, where the count is 0 and g N to within g N e^-50
+        double glo = 0.0, ghi = 0.0;
+        CSS_TRY(subspace_spectral_bounds(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.pole_ws, p.pole_ws, &glo, &ghi, s));
+        CSS_HIP_TRY(hipEventRecord(ev[2], s));
+        auto eval = [&](double m, double* out) -> css_status {
+            int np = 0;
+            CSS_TRY(subspace_fermi_poles(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.lz.counts, m, kT, spin_deg, bf.F,
+                                         bf.res + 6, bf.pole_ws, p.pole_ws, &np, s));
+            double h = 0.0;
+            CSS_HIP_TRY(hipMemcpyAsync(&h, bf.res + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+            CSS_HIP_TRY(hipStreamSynchronize(s));
+            if (!std::isfinite(h)) return CSS_E_NONFINITE;
+            *out = h;
+            return CSS_OK;
+        };
+        const double lo = glo - 50.0 * kT, hi = ghi + 50.0 * kT;
+        const double xtol = 1e-13 * std::max(1.0, std::max(std::fabs(lo), std::fabs(hi)));
+        CSS_TRY(brent_root(eval, lo, hi, 0.0, spin_deg * (double)lz.n, n_electrons, xtol, 1e-12 * n_electrons,
+                           &hres[0], &hres[1], &evals));
+        CSS_HIP_TRY(hipEventRecord(ev[3], s));
+        CSS_HIP_TRY(hipStreamSynchronize(s));
+    }
     if (!std::isfinite(hres[0]) || !std::isfinite(hres[1])) return CSS_E_NONFINITE;
     *mu = hres[0];
     if (count) *count = hres[1];
@@ -1020,6 +1117,7 @@ extern "C" css_status css_find_mu(const css_csr* H, const int32_t* color, const 
         info->n_colors = lz.b;
         info->breakdown = brk;
         info->spmm_kernel = bf.lz.use_grp ? 1 : 0;
+        info->n_evals = evals;
         info->min_diag_r = md;
         info->trace_krylov = hres[1];
         for (int k = 0; k < 3; ++k) {
@@ -1060,8 +1158,8 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
             most = std::max(most, lanczos_workspace_bytes(p));
         } else {
             DmPlan p;
-            const bool eig = entry == CSS_ENTRY_FIND_MU || entry == CSS_ENTRY_INV_SQRT ||
-                             entry == CSS_ENTRY_TRANSFORM_H;
+            const bool eig = entry == CSS_ENTRY_INV_SQRT || entry == CSS_ENTRY_TRANSFORM_H ||
+                             (entry == CSS_ENTRY_FIND_MU && n_colors > 128);
             CSS_TRY(plan_dm(&H, n_colors, depth, eig ? (flags | CSS_SUBSPACE_EIG) : flags, p));
             p.energy = entry == CSS_ENTRY_ENERGY_DENSITY;
             p.hprime = entry == CSS_ENTRY_TRANSFORM_H;

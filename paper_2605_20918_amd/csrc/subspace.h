@@ -16,5 +16,9 @@ css_status subspace_fermi_poles(const double* A, const double* B, int v, int b, 
                                 double mu, double kT, double g, double* F, double* sums, void* ws, size_t ws_bytes,
                                 int* npoles_out, hipStream_t s);
 size_t pole_workspace_bytes(int v, int b);
+// Gershgorin bounds of T (every Ritz value lies in [lo, hi]); host outputs,
+// synchronises the stream. ws: at least 2 v b + 16 doubles (the pole workspace is).
+css_status subspace_spectral_bounds(const double* A, const double* B, int v, int b, int ld, void* ws, size_t ws_bytes,
+                                    double* lo, double* hi, hipStream_t s);
 
 }  // namespace css

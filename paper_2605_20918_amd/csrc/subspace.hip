@@ -1088,6 +1088,27 @@ css_status subspace_fermi_poles(const double* A, const double* B, int v, int b, 
     return CSS_OK;
 }
 
+css_status subspace_spectral_bounds(const double* A, const double* B, int v, int b, int ld, void* ws, size_t ws_bytes,
+                                    double* lo, double* hi, hipStream_t s) {
+    const int nT = v * b;
+    Arena ar;
+    ar.base = static_cast<char*>(ws);
+    ar.cap = ws_bytes;
+    double* glo = ar.take<double>(nT);
+    double* ghi = ar.take<double>(nT);
+    double* range = ar.take<double>(16);
+    if (ar.overflow) return CSS_E_WORKSPACE;
+    k_gersh<<<grid_for(nT, 4), 256, 0, s>>>(A, B, v, b, ld, glo, ghi);
+    k_minmax<<<1, 256, 0, s>>>(glo, ghi, nT, range);
+    double hr[2];
+    CSS_HIP_TRY(hipMemcpyAsync(hr, range, sizeof(hr), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    if (!std::isfinite(hr[0]) || !std::isfinite(hr[1])) return CSS_E_NONFINITE;
+    *lo = hr[0];
+    *hi = hr[1];
+    return CSS_OK;
+}
+
 }  // namespace css
 
 extern "C" css_status css_fermi_poles(int32_t depth, double* kappa, double* weight, int32_t* npoles) {

@@ -55,7 +55,7 @@ class CsrStruct(ctypes.Structure):
 
 class InfoStruct(ctypes.Structure):
     _fields_ = [("depth_eff", ctypes.c_int32), ("n_colors", ctypes.c_int32), ("breakdown", ctypes.c_int32),
-                ("n_poles", ctypes.c_int32), ("spmm_kernel", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_poles", ctypes.c_int32), ("spmm_kernel", ctypes.c_int32), ("n_evals", ctypes.c_int32),
                 ("min_diag_r", ctypes.c_double), ("asym_max", ctypes.c_double),
                 ("trace_krylov", ctypes.c_double), ("e_band_krylov", ctypes.c_double),
                 ("t_phase_ms", ctypes.c_double * 6)]
@@ -389,8 +389,9 @@ def css_find_mu(H: DeviceCSR, color, sign, n_colors: int, n_electrons: float, kT
                               depth, float(spin_deg), flags, ctypes.byref(mu), ctypes.byref(count),
                               ctypes.byref(info), _ptr(ws), ws.numel(), _stream(dev)))
     d = info.as_dict()
-    d["t_phase_ms"] = {"lanczos": info.t_phase_ms[0], "eig": info.t_phase_ms[1], "bisection": info.t_phase_ms[2],
+    d["t_phase_ms"] = {"lanczos": info.t_phase_ms[0], "subspace": info.t_phase_ms[1], "search": info.t_phase_ms[2],
                        "total": info.t_phase_ms[5]}
+    d["n_evals"] = info.n_evals
     return float(mu.value), float(count.value), d
 
 

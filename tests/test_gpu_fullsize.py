@@ -92,7 +92,8 @@ def test_10k_against_the_oracle():
     resid = abs(D.krylov_count(lam, w, mu, KT) - ne)
     slope = D.krylov_count_slope(lam, w, mu_ref, KT)
     print(f"10k mu mixed: {mu:.10f} oracle {mu_ref:.10f} |dmu| {abs(mu - mu_ref):.3e} resid {resid:.3e} "
-          f"slope {slope:.1f} ({minfo['t_phase_ms']['total']:.1f} ms)", flush=True)
+          f"slope {slope:.1f} ({minfo['t_phase_ms']['total']:.1f} ms, {minfo['n_evals']} count evaluations)",
+          flush=True)
     assert minfo["depth_eff"] == ref["v_eff"]
     assert resid <= 1e-7 * ne and abs(mu - mu_ref) <= 1e-7 * ne / slope
     # S^(-1/2) of the overlap, mixed precision, v^s = 10, against the oracle

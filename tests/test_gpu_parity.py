@@ -300,7 +300,7 @@ def test_energy_dm_parity(M, seed, prec):
     assert abs(pe_trace - info["e_band_krylov"]) <= (1e-9 if prec == "fp64" else 1e-6) * abs(pe_trace)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64-eig", "fp32-eig"])
 @pytest.mark.parametrize("M,seed", [(64, 20919), (216, 3)])
 def test_find_mu_parity(M, seed, prec):
     """mu for N_e = 8 M from the Krylov quadrature count against the oracle's bisection
@@ -308,7 +308,8 @@ def test_find_mu_parity(M, seed, prec):
     tolerance (1e-10 N_e in FP64, 1e-7 N_e mixed), and the two mu agree to that
     tolerance over the count's slope; the density at that mu has trace N_e."""
     print(f"find mu {prec} M={M}", flush=True)
-    flags = FP64_FLAGS if prec == "fp64" else FP32_FLAGS
+    flags = (FP64_FLAGS if prec.startswith("fp64") else FP32_FLAGS) | (css.SUBSPACE_EIG if "eig" in prec else 0)
+    prec = prec[:4]
     ws, H, rp, col, color, b, sign, _ = water_case(M, seed)
     ne = float(ws.n_electrons)
     ref = D.find_mu(H, color, sign, b, ne, KT, 40, reorth="full", cholqr2=True)
@@ -319,7 +320,7 @@ def test_find_mu_parity(M, seed, prec):
     resid = abs(D.krylov_count(ref["lam"], ref["w"], mu, KT) - ne)
     slope = D.krylov_count_slope(ref["lam"], ref["w"], ref["mu"], KT)
     print(f"  mu={mu:.12f} oracle {ref['mu']:.12f} |dmu|={abs(mu - ref['mu']):.3e} "
-          f"resid={resid:.3e} slope={slope:.2f} count-Ne={count - ne:.3e}", flush=True)
+          f"resid={resid:.3e} slope={slope:.2f} count-Ne={count - ne:.3e} evals={info['n_evals']}", flush=True)
     assert resid <= tol_n
     assert abs(mu - ref["mu"]) <= tol_n / slope + 1e-12
     assert abs(count - ne) <= 1e-12 * ne + 1e-9
