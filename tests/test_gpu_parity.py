@@ -422,7 +422,9 @@ def test_nonorth_density_parity(M, seed, prec):
     err2 = float(np.max(np.abs(p2.cpu().numpy() - ref["p_val"])))
     print(f"  chained max|dP|={err2:.3e} dN={abs(n2 - ref['n_elec']):.3e}", flush=True)
     assert err2 <= tol
-    assert abs(n2 - ref["n_elec"]) <= rel * abs(ref["n_elec"]) and abs(e2 - ref["e_band"]) <= rel * abs(ref["e_band"])
+    # three stages (S^(-1/2), H', the density), each held to rel above: their sums compose
+    assert abs(n2 - ref["n_elec"]) <= 3 * rel * abs(ref["n_elec"])
+    assert abs(e2 - ref["e_band"]) <= 3 * rel * abs(ref["e_band"])
 
 
 def test_inv_sqrt_rejects_an_indefinite_overlap():
