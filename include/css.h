@@ -245,18 +245,20 @@ css_status css_energy_density_matrix(const css_csr* H, const int32_t* color, con
  *   non-orthogonal basis (the overlap step that precedes H' = S^(-1/2) H S^(-1/2):
  *   S^(-1/2) taken as -1/pi Im of the integral of z^(-1/2) G_S(z), projected onto
  *   coloured probes o). The same path as css_density_matrix with S in place of H
- *   and x^(-1/2) in place of g f(x): block Lanczos on S from the probes, the
- *   projected overlap T = U diag(lambda) U^T by dense diagonalisation (rocSOLVER
- *   dsyevd), Y = sum_j Q_j F_j with F = U diag(lambda^(-1/2)) U[0:b,:]^T B_0, then
- *   y_mn = sign[n] Y[m, colour(n)] on the pattern (symmetrised with
- *   CSS_SYMMETRIZE).
+ *   and x^(-1/2) in place of g f(x): block Lanczos on S from the probes, then
+ *   F = T^(-1/2) E_1 B_0 for the projected overlap T, by the coupled Newton-Schulz
+ *   iteration on T / c (c its Gershgorin upper bound; FP64 MFMA products, run until
+ *   |Z Y - I| <= 1e-9 and one more step), or with CSS_SUBSPACE_EIG by dense
+ *   diagonalisation T = U diag(lambda) U^T (rocSOLVER dsyevd), F = U
+ *   diag(lambda^(-1/2)) U[0:b,:]^T B_0; Y = sum_j Q_j F_j, then y_mn = sign[n]
+ *   Y[m, colour(n)] on the pattern (symmetrised with CSS_SYMMETRIZE).
  *   S            device CSR, symmetric positive definite (the overlap matrix)
  *   color, sign, n_colors   the probes o (css_color / css_build_probes on the
  *                overlap's cutoff)
  *   depth        Krylov blocks v^s
  *   p_row_ptr, p_col, p_nnz  the pattern S^(-1/2) is read on (device, as for
  *                css_density_matrix)
- *   flags        as css_density_matrix (CSS_SUBSPACE_EIG is implied)
+ *   flags        as css_density_matrix; CSS_SUBSPACE_EIG selects dsyevd
  *   y_val        device double[p_nnz] out: S^(-1/2) on the pattern
  *   trace        host out: sum_m y_mm
  *   s_dot        host out (may be NULL): sum over entries of S in the pattern of
@@ -265,8 +267,10 @@ css_status css_energy_density_matrix(const css_csr* H, const int32_t* color, con
  *                trace_krylov = sum_k lambda_k^(-1/2) w_k and
  *                e_band_krylov = sum_k lambda_k^(1/2) w_k
  *   ws           css_workspace_size(CSS_ENTRY_INV_SQRT, ...) bytes, device.
- *   Errors as css_density_matrix; CSS_E_NONFINITE also when a Ritz value of S is
- *   <= 0 (S not positive definite). Synchronises the stream before returning.
+ *   Errors as css_density_matrix; CSS_E_NONFINITE also when S is not positive
+ *   definite (a Ritz value <= 0 with dsyevd; a non-positive Gershgorin bound or no
+ *   convergence in 60 steps with Newton-Schulz). Synchronises the stream before
+ *   returning.
  */
 css_status css_inv_sqrt_overlap(const css_csr* S, const int32_t* color, const int8_t* sign,
                                 int32_t n_colors, int32_t depth, const int64_t* p_row_ptr,

@@ -61,6 +61,21 @@ size_t eig_workspace_bytes(int nT) {
     return sz;
 }
 
+// Row-major n x n products C = A B on rocBLAS (a plain dense GEMM): column-major
+// dgemm of the transposes, C^T = B^T A^T. Workspace from the caller.
+css_status gemm_rowmajor(int n, const double* A, const double* B, double* C, void* ws, size_t wsb, hipStream_t s) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    rocblas_handle h = handle_for_current_device();
+    if (!h) return CSS_E_DEVICE;
+    if (rocblas_set_stream(h, s) != rocblas_status_success) return CSS_E_DEVICE;
+    if (rocblas_set_workspace(h, ws, wsb) != rocblas_status_success) return CSS_E_DEVICE;
+    const double one = 1.0, zero = 0.0;
+    rocblas_status st = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, B, n, A, n,
+                                      &zero, C, n);
+    rocblas_set_workspace(h, nullptr, 0);
+    return st == rocblas_status_success ? CSS_OK : CSS_E_DEVICE;
+}
+
 css_status eig(double* T, int nT, double* lam, double* E, int* dinfo, void* ws, size_t wsb, hipStream_t s) {
     std::lock_guard<std::mutex> lock(g_mu);
     rocblas_handle h = handle_for_current_device();
@@ -321,6 +336,48 @@ __global__ __launch_bounds__(kR0SumThreads) void k_krylov_sums_r0(const double* 
     if (threadIdx.x == 0) { out[0] = st[0]; out[1] = se[0]; }
 }
 
+// Coupled Newton-Schulz iteration for the inverse square root of the projected
+// overlap (Higham, "Functions of Matrices", 2008, sec. 6.7): with Y_0 = T / c
+// (c >= the largest eigenvalue, so the spectrum is in (0, 1]) and Z_0 = I,
+//   M = (3 I - Z_k Y_k) / 2,  Y_{k+1} = Y_k M,  Z_{k+1} = M Z_k
+// converge quadratically to (T/c)^(1/2) and (T/c)^(-1/2). Matrices n x n row-major.
+__global__ void k_ns_init(const double* __restrict__ T, int n, double inv_c, double* __restrict__ Y,
+                          double* __restrict__ Z) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * n) return;
+    const int64_t i = idx / n, j = idx % n;
+    Y[idx] = T[idx] * inv_c;
+    Z[idx] = (i == j) ? 1.0 : 0.0;
+}
+
+// M = (3 I - P) / 2 with P = Z Y; dev[idx] = |P - I| entry (the residual of Z Y = I).
+__global__ void k_ns_m(const double* __restrict__ P, int n, double* __restrict__ M, double* __restrict__ dev) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * n) return;
+    const bool d = (idx / n) == (idx % n);
+    const double pv = P[idx];
+    M[idx] = 0.5 * ((d ? 3.0 : 0.0) - pv);
+    dev[idx] = fabs(pv - (d ? 1.0 : 0.0));
+}
+
+// F[k][col] = T^-1/2[k][col] sqrt(n_col) for the first b columns, T^-1/2 = Z / sqrt(c);
+// t0[col] = n_col (T^-1/2)[col][col], t1[col] = n_col (T^1/2)[col][col] (T^1/2 = Y sqrt(c)).
+__global__ void k_ns_finish(const double* __restrict__ Z, const double* __restrict__ Y, const int* __restrict__ counts,
+                            int nT, int b, double c, double* __restrict__ F, double* __restrict__ t0,
+                            double* __restrict__ t1) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nT * b) return;
+    const int64_t k = idx / b;
+    const int col = (int)(idx % b);
+    const double rs = 1.0 / sqrt(c);
+    const double nc = (double)counts[col];
+    F[idx] = Z[k * nT + col] * rs * sqrt(nc);
+    if (k == 0) {
+        t0[col] = nc * Z[(int64_t)col * nT + col] * rs;
+        t1[col] = nc * Y[(int64_t)col * nT + col] * sqrt(c);
+    }
+}
+
 // Pattern sanity: row pointers monotone from 0 to nnz, columns in range.
 __global__ void k_validate_pattern(int n, int64_t nnz, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                    int* __restrict__ bad) {
@@ -449,6 +506,10 @@ void det_max(const double* v, int64_t n, double* tmp, double* out, hipStream_t s
 
 // ------------------------------------------------------------------ plan
 
+// Newton-Schulz scratch (one nT x nT product buffer, also the Gershgorin scratch of
+// 2 nT + 16 doubles taken in three 256-byte-aligned pieces).
+int64_t ns_scratch_doubles(int64_t nT) { return std::max<int64_t>(nT * nT, 2 * nT + 16) + 128; }
+
 struct DmPlan {
     LzPlan lz;
     int nTmax = 0;
@@ -459,6 +520,7 @@ struct DmPlan {
     bool energy = false;      // also the energy-weighted estimate (X_E = H X)
     bool hprime = false;      // also H' = S^-1/2 H S^-1/2 extracted after S^-1/2 (FP64 products)
     bool nonorth = false;     // density of a non-orthogonal basis: Lanczos on H' from S^-1/2 r
+    bool ns = false;          // T^-1/2 by the coupled Newton-Schulz iteration (overlap path)
 };
 
 struct DmBufs {
@@ -472,6 +534,7 @@ struct DmBufs {
     double *Y64 = nullptr, *Z1 = nullptr, *Z = nullptr, *h64 = nullptr;   // H' extraction (FP64)
     double* R0 = nullptr;     // non-orthogonal: the first block's triangular factor
     int* ones = nullptr;      // non-orthogonal pole path: B_0 = I for the pole solve
+    double *nsY = nullptr, *nsZ = nullptr, *nsM = nullptr, *nsP = nullptr;   // Newton-Schulz (nT x nT)
     int32_t* rp32 = nullptr;
     void* eig_ws = nullptr;
 };
@@ -507,6 +570,12 @@ void carve_dm(Arena& a, const DmPlan& p, DmBufs& bf) {
     if (p.nonorth) {
         bf.R0 = a.take<double>(mat);
         bf.ones = a.take<int>(p.lz.b);
+    }
+    if (p.ns) {
+        bf.nsY = a.take<double>(nT * nT);
+        bf.nsZ = a.take<double>(nT * nT);
+        bf.nsM = a.take<double>(nT * nT);
+        bf.nsP = a.take<double>(ns_scratch_doubles(nT));
     }
     bf.eig_ws = p.eig_ws ? a.take<char>(p.eig_ws) : nullptr;
     bf.pole_ws = p.pole_ws ? a.take<char>(p.pole_ws) : nullptr;
@@ -558,9 +627,11 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     if (!color || !sign || !p_row_ptr || !p_col || !p_val || !e_band || !trace || !ws || p_nnz < 1) return CSS_E_ARG;
     if (fn == kFnFermi && (!(kT > 0.0) || !std::isfinite(kT) || !std::isfinite(mu) || !(spin_deg > 0.0)))
         return CSS_E_ARG;
+    const bool ns = fn == kFnInvSqrt && !(flags & CSS_SUBSPACE_EIG);
     if (fn == kFnInvSqrt) flags |= CSS_SUBSPACE_EIG;
     DmPlan p;
     CSS_TRY(plan_dm(H, n_colors, depth, flags, p));
+    p.ns = ns;
     p.energy = pe_val != nullptr;
     p.hprime = h2_val != nullptr;
     if (p.hprime) {
@@ -605,7 +676,45 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     const int nT = v_eff * lz.b;
     const int64_t mat = (int64_t)lz.ld * lz.ld;
     int npoles = 0;
-    if (p.use_eig) {
+    if (p.ns) {
+        // T^-1/2 E_1 B_0 by the coupled Newton-Schulz iteration on T / c, c the
+        // Gershgorin upper bound; a non-positive bound or no convergence in 60
+        // iterations means T (so S) is not positive definite
+        CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+        k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T,
+                                                                     bf.flags);
+        int hbad = 0;
+        CSS_HIP_TRY(hipMemcpyAsync(&hbad, bf.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+        CSS_HIP_TRY(hipStreamSynchronize(s));
+        if (hbad) return CSS_E_NONFINITE;
+        double glo = 0.0, ghi = 0.0;
+        CSS_TRY(subspace_spectral_bounds(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.nsP,
+                                         sizeof(double) * ns_scratch_doubles(p.nTmax), &glo, &ghi, s));
+        if (!(ghi > 0.0)) return CSS_E_NONFINITE;
+        const int64_t nn = (int64_t)nT * nT;
+        k_ns_init<<<grid_for(nn, 256), 256, 0, s>>>(bf.T, nT, 1.0 / ghi, bf.nsY, bf.nsZ);
+        bool conv = false;
+        for (int it = 0; it < 60 && !conv; ++it) {
+            CSS_TRY(gemm_rowmajor(nT, bf.nsZ, bf.nsY, bf.nsP, bf.eig_ws, p.eig_ws, s));         // P = Z Y
+            k_ns_m<<<grid_for(nn, 256), 256, 0, s>>>(bf.nsP, nT, bf.nsM, bf.T);               // M, |ZY - I|
+            det_max(bf.T, nn, bf.tmp, bf.res + 8, s);
+            double r = 0.0;
+            CSS_HIP_TRY(hipMemcpyAsync(&r, bf.res + 8, sizeof(double), hipMemcpyDeviceToHost, s));
+            CSS_TRY(gemm_rowmajor(nT, bf.nsY, bf.nsM, bf.nsP, bf.eig_ws, p.eig_ws, s));         // P = Y M
+            std::swap(bf.nsY, bf.nsP);
+            CSS_TRY(gemm_rowmajor(nT, bf.nsM, bf.nsZ, bf.nsP, bf.eig_ws, p.eig_ws, s));         // P = M Z
+            std::swap(bf.nsZ, bf.nsP);
+            CSS_HIP_TRY(hipStreamSynchronize(s));
+            if (!std::isfinite(r)) return CSS_E_NONFINITE;
+            conv = r <= 1e-9;          // the update above then leaves an error of order r^2
+        }
+        if (!conv) return CSS_E_NONFINITE;
+        CSS_HIP_TRY(hipEventRecord(ev[2], s));
+        k_ns_finish<<<grid_for((int64_t)nT * lz.b, 256), 256, 0, s>>>(bf.nsZ, bf.nsY, bf.lz.counts, nT, lz.b, ghi,
+                                                                       bf.F, bf.t0, bf.t1);
+        det_sum(bf.t0, lz.b, bf.tmp, bf.res + 2, s);
+        det_sum(bf.t1, lz.b, bf.tmp + kSumBlocks, bf.res + 3, s);
+    } else if (p.use_eig) {
         CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
         k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T,
                                                                      bf.flags);
@@ -1164,6 +1273,7 @@ extern "C" css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, 
             p.energy = entry == CSS_ENTRY_ENERGY_DENSITY;
             p.hprime = entry == CSS_ENTRY_TRANSFORM_H;
             p.nonorth = entry == CSS_ENTRY_DENSITY_NONORTH;
+            p.ns = (entry == CSS_ENTRY_INV_SQRT || entry == CSS_ENTRY_TRANSFORM_H) && !(flags & CSS_SUBSPACE_EIG);
             most = std::max(most, dm_workspace_bytes(p));
         }
     }

@@ -329,14 +329,15 @@ def test_find_mu_parity(M, seed, prec):
     assert abs(dinfo["trace_krylov"] - ne) <= tol_n
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64-eig"])
 @pytest.mark.parametrize("M,seed", [(64, 20919), (216, 3)])
 def test_inv_sqrt_overlap_parity(M, seed, prec):
     """S^(-1/2) of the water overlap on the 6 Angstrom pattern (probes o = the density's
     colouring and signs, v^s = 10) against the oracle element by element; the trace,
     the S-weighted sum and the two Krylov quadratures too."""
     print(f"inv sqrt {prec} M={M}", flush=True)
-    flags = FP64_FLAGS if prec == "fp64" else FP32_FLAGS
+    flags = {"fp64": FP64_FLAGS, "fp32": FP32_FLAGS, "fp64-eig": FP64_FLAGS | css.SUBSPACE_EIG}[prec]
+    prec = prec[:4]
     ws, H, rp, col, color, b, sign, _ = water_case(M, seed)
     So = synth.water_overlap(ws)
     ref = D.inv_sqrt_matrix(So.to_scipy(), color, sign, b, 10, rp, col)
