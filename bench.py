@@ -193,7 +193,8 @@ def cpu_model() -> str:
 
 
 def cpu_baseline(ws, depth_sample: int, mu: float):
-    """The oracle, as it stands, on a bounded sample of the same workload (reduced depth)."""
+    """The oracle, as it stands, on the same workload at depth depth_sample (the whole
+    step at the workload's depth for the 10k and 1k inputs)."""
     from threadpoolctl import threadpool_info
     from oracle import density as D
     from oracle.coloring import greedy_color
@@ -423,7 +424,7 @@ def main():
         args.no_cpu_baseline = True        # the oracle at this size takes hours; the default run reports it
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the CPU sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(ws, 6, mu)
+        out["cpu_baseline"] = cpu_baseline(ws, depth, mu)       # the whole step (about 15 s on 16 cores)
     print(json.dumps(out), flush=True)
 
 
