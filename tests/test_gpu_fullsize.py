@@ -7,6 +7,7 @@ path against the FP64 path.
 """
 import os
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -48,9 +49,10 @@ def test_10k_against_the_oracle():
     rp, col, deg = conflict_pattern(ws.orb_xyz, ws.box, R_CUT)
     color, b = greedy_color(rp, col, deg)
     sign = probe_signs(ws.n, wl["seed"])
+    t0 = time.perf_counter()
     ref = D.density_matrix(ws.H.to_scipy(), color, sign, b, MU, KT, wl["depth"], rp, col, reorth="full",
                            cholqr2=True)
-    print(f"10k: oracle done (b={b}, v_eff={ref['v_eff']})", flush=True)
+    print(f"10k: oracle done (b={b}, v_eff={ref['v_eff']}, density {time.perf_counter() - t0:.1f} s)", flush=True)
     H32 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, "cuda", torch.float32)
     H64 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, "cuda", torch.float64)
     runs = {"mixed (bench)": (H32, bench.flags_for("fp32")),
@@ -71,7 +73,9 @@ def test_10k_against_the_oracle():
     assert errs["fp64 full"][0] <= 1e-10 and errs["fp64 full"][1] <= 1e-10
     assert errs["fp64 local (bench comparator)"][0] <= 1e-8 and errs["fp64 local (bench comparator)"][1] <= 1e-10
     # the energy-weighted estimate, mixed precision, element by element against the oracle
+    t0 = time.perf_counter()
     eref = D.energy_density_matrix(ws.H.to_scipy(), ref, color, sign, rp, col)
+    print(f"10k oracle energy-weighted (after the density): {time.perf_counter() - t0:.2f} s", flush=True)
     xyz = torch.as_tensor(ws.orb_xyz, dtype=torch.float64, device="cuda")
     g_color, g_b, g_rp, g_col, _ = css.css_color(xyz, [float(x) for x in ws.box], R_CUT)
     g_sign, _ = css.css_build_probes(g_color, g_b, wl["seed"])
@@ -84,10 +88,12 @@ def test_10k_against_the_oracle():
     assert dpe <= 1e-5 * hinf and dtr <= 1e-7
     # mu for N_e electrons, mixed precision, against the oracle's bisection on its own T
     from oracle.subspace import eig_subspace
+    t0 = time.perf_counter()
     lam, U = eig_subspace(ref["T"])
     w = D.krylov_weights(U, ref["lanczos"].b0)
     ne = float(ws.n_electrons)
     mu_ref = D.mu_krylov_bisection(lam, w, ne, KT)
+    print(f"10k oracle mu (after the Lanczos pass): {time.perf_counter() - t0:.2f} s", flush=True)
     mu, count, minfo = css.css_find_mu(H32, g_color, g_sign, g_b, ne, KT, wl["depth"], bench.flags_for("fp32"))
     resid = abs(D.krylov_count(lam, w, mu, KT) - ne)
     slope = D.krylov_count_slope(lam, w, mu_ref, KT)
@@ -98,7 +104,9 @@ def test_10k_against_the_oracle():
     assert resid <= 1e-7 * ne and abs(mu - mu_ref) <= 1e-7 * ne / slope
     # S^(-1/2) of the overlap, mixed precision, v^s = 10, against the oracle
     So = synth.water_overlap(ws)
+    t0 = time.perf_counter()
     yref = D.inv_sqrt_matrix(So.to_scipy(), color, sign, b, 10, rp, col)
+    print(f"10k oracle S^-1/2: {time.perf_counter() - t0:.2f} s", flush=True)
     S32 = css.DeviceCSR.from_host(So.row_ptr, So.col, So.val, "cuda", torch.float32)
     y, ytr, _, yinfo = css.css_inv_sqrt_overlap(S32, g_color, g_sign, g_b, 10, g_rp, g_col, bench.flags_for("fp32"))
     dy = float(np.max(np.abs(y.cpu().numpy() - yref["y_val"])))
@@ -107,7 +115,9 @@ def test_10k_against_the_oracle():
           flush=True)
     assert yinfo["depth_eff"] == yref["v_eff"] and dy <= 1e-5 and dytr <= 1e-7
     # H' = S^(-1/2) H S^(-1/2), mixed precision, against the oracle
+    t0 = time.perf_counter()
     href = D.transform_hamiltonian(ws.H.to_scipy(), So.to_scipy(), color, sign, b, 10, rp, col)
+    print(f"10k oracle H': {time.perf_counter() - t0:.2f} s", flush=True)
     _, hp, _, hptr, _ = css.css_transform_hamiltonian(H32, S32, g_color, g_sign, g_b, 10, g_rp, g_col,
                                                       bench.flags_for("fp32"))
     dh = float(np.max(np.abs(hp.cpu().numpy() - href["hp_val"])))
@@ -119,8 +129,10 @@ def test_10k_against_the_oracle():
     import scipy.sparse as sp
     Sh = sp.csr_matrix((href["y_val"], col, rp), shape=(ws.n, ws.n))
     Hp = sp.csr_matrix((href["hp_val"], col, rp), shape=(ws.n, ws.n))
+    t0 = time.perf_counter()
     nref = D.density_matrix_nonorth(Hp, Sh, color, sign, b, MU, KT, wl["depth"], rp, col, H=ws.H.to_scipy(),
                                     S=So.to_scipy())
+    print(f"10k oracle non-orthogonal density: {time.perf_counter() - t0:.2f} s", flush=True)
     S64 = css.DeviceCSR.from_host(So.row_ptr, So.col, So.val, "cuda", torch.float64)
     pn, en, nn, _, ninfo = css.css_density_matrix_nonorth(
         css.pattern_csr(g_rp, g_col, torch.as_tensor(href["hp_val"]).cuda()),
