@@ -264,7 +264,7 @@ def test_density_fp64_cfg2_parity(subspace):
     assert abs(e_band - ref["e_band"]) <= 1e-10 * abs(ref["e_band"])
 
 
-@pytest.mark.parametrize("M,seed,depth", [(64, 20919, 40), (216, 3, 40), (1000, 20920, 40)])
+@pytest.mark.parametrize("M,seed,depth", [(64, 20919, 40), (125, 11, 40), (216, 3, 40), (1000, 20920, 40)])
 def test_density_fp32_parity(M, seed, depth):
     print(f"density fp32 M={M}", flush=True)
     ws, ref, p, e_band, trace, info = _dm_case(M, seed, depth, FP32_FLAGS, "full")
@@ -380,7 +380,7 @@ def test_transform_hamiltonian_parity(M, seed, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64-eig"])
-@pytest.mark.parametrize("M,seed", [(64, 20919), (216, 3)])
+@pytest.mark.parametrize("M,seed", [(64, 20919), (125, 11), (216, 3)])
 def test_nonorth_density_parity(M, seed, prec):
     """Density matrix of the non-orthogonal basis from the oracle's own sparse S^(-1/2) and
     H' (both sides take the same inputs), element by element; Tr(P S), sum H.P, the
