@@ -276,7 +276,7 @@ def test_density_fp32_parity(M, seed, depth):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("M,seed", [(64, 20919), (216, 3)])
+@pytest.mark.parametrize("M,seed", [(64, 20919), (125, 11), (216, 3)])
 def test_energy_dm_parity(M, seed, prec):
     """Energy-weighted estimate P_E = (H X) r^T on the pattern against the oracle; P from
     the same call equals css_density_matrix's bitwise; Tr P_E is the Krylov band energy."""
@@ -301,7 +301,7 @@ def test_energy_dm_parity(M, seed, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64-eig", "fp32-eig"])
-@pytest.mark.parametrize("M,seed", [(64, 20919), (216, 3)])
+@pytest.mark.parametrize("M,seed", [(64, 20919), (125, 11), (216, 3)])
 def test_find_mu_parity(M, seed, prec):
     """mu for N_e = 8 M from the Krylov quadrature count against the oracle's bisection
     on its own Lanczos: the oracle's count at the GPU's mu is N_e to the trace
@@ -330,7 +330,7 @@ def test_find_mu_parity(M, seed, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64-eig"])
-@pytest.mark.parametrize("M,seed", [(64, 20919), (216, 3)])
+@pytest.mark.parametrize("M,seed", [(64, 20919), (125, 11), (216, 3)])
 def test_inv_sqrt_overlap_parity(M, seed, prec):
     """S^(-1/2) of the water overlap on the 6 Angstrom pattern (probes o = the density's
     colouring and signs, v^s = 10) against the oracle element by element; the trace,
@@ -357,7 +357,7 @@ def test_inv_sqrt_overlap_parity(M, seed, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("M,seed", [(64, 20919), (216, 3)])
+@pytest.mark.parametrize("M,seed", [(64, 20919), (125, 11), (216, 3)])
 def test_transform_hamiltonian_parity(M, seed, prec):
     """H' = S^(-1/2) H S^(-1/2) on the pattern against the oracle element by element;
     S^(-1/2) from the same call equals css_inv_sqrt_overlap's bitwise."""
