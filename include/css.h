@@ -464,6 +464,45 @@ css_status css_workspace_size(int32_t entry, int32_t n, int64_t nnz, int32_t n_c
  */
 css_status css_fermi_poles(int32_t depth, double* kappa, double* weight, int32_t* npoles);
 
+/*
+ * Launch choices (the library's tuning knobs, for an autotuner). Process-wide, read
+ * when a kernel is launched; zero fields select the built-in defaults. No choice
+ * changes the arithmetic of the method, only the launch shape and hence the order
+ * in which FP32 partial sums are added (results stay deterministic for a fixed
+ * tuning).
+ *   spmm_kernel  sparse x block product: 0 automatic (the 16-row grouped MFMA kernel
+ *                where H's row groups are dense enough, else the row-parallel CSR
+ *                kernel), 1 16-row groups, 2 the CSR kernel
+ *   spmm_run     row groups per XCD run of the grouped kernel (0 = 512)
+ *   spmm_depth   k-steps in flight per wavefront of the grouped kernel: 0 (= 4), 4, 8
+ *   gram_chunks  FP32 split Gram products: row chunks sized for about this many
+ *                work-groups per compute unit, 0 (= 1), 1, 2, 4
+ *   update_rows  FP32 split block updates: rows per work-group, 0 (= 128), 64, 128
+ */
+typedef struct {
+    int32_t spmm_kernel;
+    int32_t spmm_run;
+    int32_t spmm_depth;
+    int32_t gram_chunks;
+    int32_t update_rows;
+    int32_t reserved[3];
+} css_tuning;
+
+/* Sets (t != NULL) or resets to the defaults (t == NULL) the process-wide tuning.
+ * CSS_E_ARG for an out-of-range field. Not to be called while another thread is
+ * inside the library. */
+css_status css_set_tuning(const css_tuning* t);
+css_status css_get_tuning(css_tuning* t);
+
+/*
+ * css_spmm_time -- average device time of `reps` launches of W = H V (css_spmm) with
+ *   the launch choices `cfg` (NULL: the current tuning), measured with HIP events on
+ *   `stream` after one untimed launch; for the autotuner. Arguments as css_spmm;
+ *   avg_ms host out. Synchronises the stream.
+ */
+css_status css_spmm_time(const css_csr* H, const void* V, void* W, int32_t b, int32_t ld, const void* ws,
+                         size_t ws_bytes, const css_tuning* cfg, int32_t reps, float* avg_ms, void* stream);
+
 /* Leading dimension the library uses for blocks of b columns. */
 int32_t css_block_ld(int32_t n_colors);
 

@@ -57,6 +57,17 @@ struct Arena {
     }
 };
 
+// Launch choices (process-wide, set by css_set_tuning; zero fields mean the built-in
+// default). None changes the arithmetic beyond the order of FP32 sums.
+struct Tuning {
+    int kernel = 0;        // SpMM: 0 automatic (16-row groups where prepared), 1 16-row groups, 2 CSR
+    int run = 0;           // SpMM: groups per XCD run (default 512)
+    int depth = 0;         // SpMM: k-steps in flight per wave, 4 or 8 (default 4)
+    int gram_chunks = 0;   // FP32 split Gram: work-groups per compute unit and product set, 1, 2 or 4 (default 1)
+    int update_rows = 0;   // FP32 split block update: rows per work-group, 64 or 128 (default 128)
+};
+Tuning tuning();
+
 inline unsigned grid_for(int64_t work, int per_block) {
     int64_t g = (work + per_block - 1) / per_block;
     if (g < 1) g = 1;

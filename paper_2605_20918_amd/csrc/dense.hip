@@ -1492,11 +1492,17 @@ static void update_staged(T* OUT, const T* IN, double alpha, const T* X, int64_t
 template <int NT, int NPL>
 static void update_split_one(float* OUT, const float* IN, double alpha, const float* X, int64_t xstride, int nprod,
                              const void* frag, int64_t Np, int ld, const int* state, hipStream_t s) {
-    constexpr int MT = 2, D = 4;
-    const int64_t rows_per_block = 4 * 16 * MT;
-    const unsigned grid = static_cast<unsigned>((Np + rows_per_block - 1) / rows_per_block);
-    k_update_split<MT, NT, D, NPL><<<grid, 256, 0, s>>>(OUT, IN, alpha, X, xstride, nprod,
-                                                         static_cast<const bf16x8*>(frag), Np, ld, state);
+    constexpr int D = 4;
+    // rows per work-group: 128 (MT = 2) by default, 64 (MT = 1) by the tuning
+    if (tuning().update_rows == 64) {
+        const unsigned grid = static_cast<unsigned>((Np + 63) / 64);
+        k_update_split<1, NT, D, NPL><<<grid, 256, 0, s>>>(OUT, IN, alpha, X, xstride, nprod,
+                                                            static_cast<const bf16x8*>(frag), Np, ld, state);
+    } else {
+        const unsigned grid = static_cast<unsigned>((Np + 127) / 128);
+        k_update_split<2, NT, D, NPL><<<grid, 256, 0, s>>>(OUT, IN, alpha, X, xstride, nprod,
+                                                            static_cast<const bf16x8*>(frag), Np, ld, state);
+    }
 }
 
 template <int NPL>
@@ -1563,7 +1569,8 @@ GramPlan gram_plan_split(int64_t Np, int ld, int nprod, int64_t cap_mats) {
     g.Np = Np;
     g.sym = false;
     g.ntiles = 1;
-    int64_t nchunk = (256 + nprod - 1) / nprod;          // about a workgroup per compute unit
+    const int per_cu = std::max(1, tuning().gram_chunks);
+    int64_t nchunk = (256 * per_cu + nprod - 1) / nprod;  // about per_cu workgroups per compute unit
     nchunk = std::min<int64_t>(nchunk, std::max<int64_t>(1, Np / 256));
     const int kg = gram_split_groups(ld);
     nchunk = std::max<int64_t>(nchunk, (Np + kg * kGramFp32Rows - 1) / (kg * kGramFp32Rows));

@@ -127,7 +127,7 @@ template <typename T>
 bool launch_spmm_t(const css_csr* H, const LzBufs& bf, const T* V, T* W, int ld, hipStream_t s) {
     const T* val = bf.hval ? static_cast<const T*>(bf.hval) : static_cast<const T*>(H->val);
     SpmmArgs<T> a{H->n, H->row_ptr, H->col, val, V, W, ld};
-    if (bf.use_grp && spmm_grp_launch(a, bf.grp, s)) return true;
+    if (bf.use_grp && spmm_grouped_launch(a, bf.grp, s)) return true;
     return spmm_launch(a, s);
 }
 
@@ -266,8 +266,11 @@ css_status prepare(const css_csr* H, const int32_t* color, const int8_t* sign, c
     CSS_HIP_TRY(hipStreamSynchronize(s));
     if (hst[1] & 2) return CSS_E_NONFINITE;
     if (hst[1]) return CSS_E_CSR;
-    // grouped SpMM where the 16 x |U_g| blocks hold at most kGroupFill times the nonzeros
-    bf.use_grp = p.grp_ok && spmm_grp_worthwhile(p.nnz, hst[4], hst[5]);
+    // grouped SpMM where the 16 x |U_g| blocks hold at most kGroupFill times the
+    // nonzeros, unless the tuning asks for the CSR kernel
+    const bool blocks = p.grp_ok && tuning().kernel != 2 && spmm_grp_worthwhile(p.nnz, hst[4], hst[5]);
+    bf.use_grp = blocks;
+    bf.grp.blocks_ready = blocks;
     if (p.convert_h) {
         if (p.fp32)
             k_convert<double, float><<<grid_for(p.nnz, 256), 256, 0, s>>>(static_cast<const double*>(H->val),
@@ -276,7 +279,7 @@ css_status prepare(const css_csr* H, const int32_t* color, const int8_t* sign, c
             k_convert<float, double><<<grid_for(p.nnz, 256), 256, 0, s>>>(static_cast<const float*>(H->val),
                                                                            static_cast<double*>(bf.hval), p.nnz);
     }
-    if (bf.use_grp)
+    if (blocks)
         spmm_grp_fill<T>(p.n, H->row_ptr, bf.hval ? static_cast<const T*>(bf.hval) : static_cast<const T*>(H->val),
                          bf.grp, s);
     zero_tall<T>(static_cast<T*>(bf.W), p.Np * p.ld, s);

@@ -41,7 +41,10 @@ struct SpmmGroups {
     int64_t* boff = nullptr;     // groups + 1: element offset of each group's block
     void* hblk = nullptr;        // cap elements of H's value type
     int64_t cap = 0;
+    bool blocks_ready = false;   // blocks filled for the current H
 };
+
+
 int spmm_groups(int n);
 // Elements reserved for the blocks: enough whenever spmm_grp_worthwhile holds.
 int64_t spmm_grp_block_cap(int n, int64_t nnz);
@@ -62,7 +65,12 @@ void spmm_grp_fill(int n, const int32_t* row_ptr, const T* val, const SpmmGroups
 // false if ld is not a multiple of 16 up to 128, or V / W are not 16-byte aligned.
 // V must be finite: a block's explicit zeros multiply V rows of other rows' columns.
 template <typename T>
-bool spmm_grp_launch(const SpmmArgs<T>& a, const SpmmGroups& gp, hipStream_t s);
+bool spmm_grp_launch(const SpmmArgs<T>& a, const SpmmGroups& gp, const Tuning& tu, hipStream_t s);
+
+// The grouped product where the tuning allows it and the blocks are filled; false
+// otherwise (the caller then runs the CSR kernel).
+template <typename T>
+bool spmm_grouped_launch(const SpmmArgs<T>& a, const SpmmGroups& gp, hipStream_t s);
 
 // Workspace of css_spmm_prepare / css_spmm: status ints and the group arrays.
 size_t spmm_workspace_bytes(int n, int64_t nnz);

@@ -10,6 +10,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "css_common.h"
 #include "spmm.h"
 
@@ -118,6 +120,9 @@ template bool spmm_launch<float>(const SpmmArgs<float>&, hipStream_t);
 
 namespace {
 
+std::mutex g_tune_mu;
+Tuning g_tune;
+
 constexpr size_t kSpmmHeader = 256;     // 16 status ints ahead of the group arrays
 
 SpmmGroups groups_in(void* ws, int n, int64_t nnz, size_t elem) {
@@ -136,6 +141,40 @@ bool csr_shape_ok(const css_csr* H) {
 
 size_t elem_of(const css_csr* H) { return H->val_dtype == CSS_F32 ? 4 : 8; }
 
+// The product on a workspace filled by css_spmm_prepare (16-row groups) unless the
+// tuning asks for the CSR kernel, or the CSR kernel without a workspace.
+css_status spmm_dispatch(const css_csr* H, const void* V, void* W, int32_t ld, const void* ws, const Tuning& tu,
+                         hipStream_t s) {
+    SpmmGroups g = ws ? groups_in(const_cast<void*>(ws), H->n, H->nnz, elem_of(H)) : SpmmGroups{};
+    g.blocks_ready = ws != nullptr && tu.kernel != 2;
+    bool ok;
+    if (H->val_dtype == CSS_F64) {
+        SpmmArgs<double> a{H->n, H->row_ptr, H->col, static_cast<const double*>(H->val),
+                           static_cast<const double*>(V), static_cast<double*>(W), ld};
+        ok = spmm_grp_launch(a, g, tu, s) || spmm_launch(a, s);
+    } else {
+        SpmmArgs<float> a{H->n, H->row_ptr, H->col, static_cast<const float*>(H->val),
+                          static_cast<const float*>(V), static_cast<float*>(W), ld};
+        ok = spmm_grp_launch(a, g, tu, s) || spmm_launch(a, s);
+    }
+    if (!ok) return CSS_E_UNSUPPORTED;
+    return hipGetLastError() == hipSuccess ? CSS_OK : CSS_E_DEVICE;
+}
+
+css_status tuning_from(const css_tuning* t, Tuning& v) {
+    if (t->spmm_kernel < 0 || t->spmm_kernel > 2 || t->spmm_run < 0 ||
+        (t->spmm_depth != 0 && t->spmm_depth != 4 && t->spmm_depth != 8) ||
+        (t->gram_chunks != 0 && t->gram_chunks != 1 && t->gram_chunks != 2 && t->gram_chunks != 4) ||
+        (t->update_rows != 0 && t->update_rows != 64 && t->update_rows != 128))
+        return CSS_E_ARG;
+    v.kernel = t->spmm_kernel;
+    v.run = t->spmm_run;
+    v.depth = t->spmm_depth;
+    v.gram_chunks = t->gram_chunks;
+    v.update_rows = t->update_rows;
+    return CSS_OK;
+}
+
 }  // namespace
 
 size_t spmm_workspace_bytes(int n, int64_t nnz) {
@@ -143,6 +182,11 @@ size_t spmm_workspace_bytes(int n, int64_t nnz) {
     SpmmGroups g;
     carve_groups(a, n, nnz, 8, g);
     return kSpmmHeader + a.used;
+}
+
+Tuning tuning() {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    return g_tune;
 }
 
 }  // namespace css
@@ -179,18 +223,52 @@ extern "C" css_status css_spmm(const css_csr* H, const void* V, void* W, int32_t
                                size_t ws_bytes, void* stream) {
     if (!csr_shape_ok(H) || !V || !W || b < 1 || ld < b) return CSS_E_ARG;
     if (ws && ws_bytes < spmm_workspace_bytes(H->n, H->nnz)) return CSS_E_WORKSPACE;
+    return spmm_dispatch(H, V, W, ld, ws, tuning(), as_stream(stream));
+}
+
+extern "C" css_status css_spmm_time(const css_csr* H, const void* V, void* W, int32_t b, int32_t ld, const void* ws,
+                                    size_t ws_bytes, const css_tuning* cfg, int32_t reps, float* avg_ms,
+                                    void* stream) {
+    if (!csr_shape_ok(H) || !V || !W || b < 1 || ld < b || reps < 1 || !avg_ms) return CSS_E_ARG;
+    if (ws && ws_bytes < spmm_workspace_bytes(H->n, H->nnz)) return CSS_E_WORKSPACE;
+    Tuning tu = tuning();
+    if (cfg) CSS_TRY(tuning_from(cfg, tu));
     hipStream_t s = as_stream(stream);
-    const SpmmGroups g = ws ? groups_in(const_cast<void*>(ws), H->n, H->nnz, elem_of(H)) : SpmmGroups{};
-    bool ok;
-    if (H->val_dtype == CSS_F64) {
-        SpmmArgs<double> a{H->n, H->row_ptr, H->col, static_cast<const double*>(H->val),
-                           static_cast<const double*>(V), static_cast<double*>(W), ld};
-        ok = (ws && spmm_grp_launch(a, g, s)) || spmm_launch(a, s);
-    } else {
-        SpmmArgs<float> a{H->n, H->row_ptr, H->col, static_cast<const float*>(H->val),
-                          static_cast<const float*>(V), static_cast<float*>(W), ld};
-        ok = (ws && spmm_grp_launch(a, g, s)) || spmm_launch(a, s);
+    CSS_TRY(spmm_dispatch(H, V, W, ld, ws, tu, s));          // untimed
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    CSS_HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return CSS_E_DEVICE;
     }
-    if (!ok) return CSS_E_UNSUPPORTED;
-    return hipGetLastError() == hipSuccess ? CSS_OK : CSS_E_DEVICE;
+    css_status st = hipEventRecord(e0, s) == hipSuccess ? CSS_OK : CSS_E_DEVICE;
+    for (int r = 0; r < reps && st == CSS_OK; ++r) st = spmm_dispatch(H, V, W, ld, ws, tu, s);
+    if (st == CSS_OK && hipEventRecord(e1, s) != hipSuccess) st = CSS_E_DEVICE;
+    if (st == CSS_OK && hipEventSynchronize(e1) != hipSuccess) st = CSS_E_DEVICE;
+    float ms = 0.f;
+    if (st == CSS_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = CSS_E_DEVICE;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == CSS_OK) *avg_ms = ms / (float)reps;
+    return st;
+}
+
+extern "C" css_status css_set_tuning(const css_tuning* t) {
+    Tuning v;
+    if (t) CSS_TRY(tuning_from(t, v));
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune = v;
+    return CSS_OK;
+}
+
+extern "C" css_status css_get_tuning(css_tuning* t) {
+    if (!t) return CSS_E_ARG;
+    const Tuning v = tuning();
+    *t = css_tuning{};
+    t->spmm_kernel = v.kernel;
+    t->spmm_run = v.run;
+    t->spmm_depth = v.depth;
+    t->gram_chunks = v.gram_chunks;
+    t->update_rows = v.update_rows;
+    return CSS_OK;
 }

@@ -280,17 +280,23 @@ __global__ __launch_bounds__(64) void k_spmm_grp(int n, int ngroups, int run, co
 }
 
 template <typename T, int NT>
-void launch_grp(const SpmmArgs<T>& a, const SpmmGroups& gp, hipStream_t s) {
+void launch_grp(const SpmmArgs<T>& a, const SpmmGroups& gp, const Tuning& tu, hipStream_t s) {
     constexpr int UC = 256;                           // union columns per index chunk
-    constexpr int D = 8;                              // k-steps in flight per wave
-    // groups per XCD run: at most 512 (on 10^6 water 512 beat one contiguous range per
-    // XCD by 7%; at 10k, 469 groups per XCD, one range per XCD moved the fewest bytes)
+    // groups per XCD run: at most 512 by default (on 10^6 water 512 beat one contiguous
+    // range per XCD by 7%; at 10k, 469 groups per XCD, one range per XCD moved the
+    // fewest bytes)
     const int ngroups = spmm_groups(a.n);
-    const int run = std::min(512, (ngroups + 7) / 8);
+    const int run = std::max(1, std::min(tu.run > 0 ? tu.run : 512, (ngroups + 7) / 8));
     const int nruns = (ngroups + run - 1) / run;
     const int blocks = 8 * ((nruns + 7) / 8) * run;
-    k_spmm_grp<T, NT, UC, D><<<blocks, 64, 0, s>>>(a.n, ngroups, run, a.row_ptr, gp.U, gp.ucount, gp.boff,
-                                                   static_cast<const T*>(gp.hblk), a.V, a.W, a.ld);
+    // k-steps in flight per wave: 4 by default (10k water 47.1 against 49.6 us with 8,
+    // 10^6 water 3.61 against 3.72 ms)
+    if (tu.depth == 8)
+        k_spmm_grp<T, NT, UC, 8><<<blocks, 64, 0, s>>>(a.n, ngroups, run, a.row_ptr, gp.U, gp.ucount, gp.boff,
+                                                       static_cast<const T*>(gp.hblk), a.V, a.W, a.ld);
+    else
+        k_spmm_grp<T, NT, UC, 4><<<blocks, 64, 0, s>>>(a.n, ngroups, run, a.row_ptr, gp.U, gp.ucount, gp.boff,
+                                                       static_cast<const T*>(gp.hblk), a.V, a.W, a.ld);
 }
 
 }  // namespace
@@ -326,25 +332,34 @@ void spmm_grp_fill(int n, const int32_t* row_ptr, const T* val, const SpmmGroups
 }
 
 template <typename T>
-bool spmm_grp_launch(const SpmmArgs<T>& a, const SpmmGroups& gp, hipStream_t s) {
-    if (a.ld % 16 != 0 || (reinterpret_cast<uintptr_t>(a.V) | reinterpret_cast<uintptr_t>(a.W)) % 16 != 0)
+bool spmm_grp_launch(const SpmmArgs<T>& a, const SpmmGroups& gp, const Tuning& tu, hipStream_t s) {
+    if (!gp.blocks_ready || a.ld % 16 != 0 ||
+        (reinterpret_cast<uintptr_t>(a.V) | reinterpret_cast<uintptr_t>(a.W)) % 16 != 0)
         return false;
     switch (a.ld / 16) {
-        case 1: launch_grp<T, 1>(a, gp, s); return true;
-        case 2: launch_grp<T, 2>(a, gp, s); return true;
-        case 3: launch_grp<T, 3>(a, gp, s); return true;
-        case 4: launch_grp<T, 4>(a, gp, s); return true;
-        case 5: launch_grp<T, 5>(a, gp, s); return true;
-        case 6: launch_grp<T, 6>(a, gp, s); return true;
-        case 7: launch_grp<T, 7>(a, gp, s); return true;
-        case 8: launch_grp<T, 8>(a, gp, s); return true;
+        case 1: launch_grp<T, 1>(a, gp, tu, s); return true;
+        case 2: launch_grp<T, 2>(a, gp, tu, s); return true;
+        case 3: launch_grp<T, 3>(a, gp, tu, s); return true;
+        case 4: launch_grp<T, 4>(a, gp, tu, s); return true;
+        case 5: launch_grp<T, 5>(a, gp, tu, s); return true;
+        case 6: launch_grp<T, 6>(a, gp, tu, s); return true;
+        case 7: launch_grp<T, 7>(a, gp, tu, s); return true;
+        case 8: launch_grp<T, 8>(a, gp, tu, s); return true;
         default: return false;      // wider blocks use the CSR kernel
     }
 }
 
+template <typename T>
+bool spmm_grouped_launch(const SpmmArgs<T>& a, const SpmmGroups& gp, hipStream_t s) {
+    const Tuning tu = tuning();
+    return tu.kernel != 2 && spmm_grp_launch(a, gp, tu, s);
+}
+
 template void spmm_grp_fill<double>(int, const int32_t*, const double*, const SpmmGroups&, hipStream_t);
 template void spmm_grp_fill<float>(int, const int32_t*, const float*, const SpmmGroups&, hipStream_t);
-template bool spmm_grp_launch<double>(const SpmmArgs<double>&, const SpmmGroups&, hipStream_t);
-template bool spmm_grp_launch<float>(const SpmmArgs<float>&, const SpmmGroups&, hipStream_t);
+template bool spmm_grp_launch<double>(const SpmmArgs<double>&, const SpmmGroups&, const Tuning&, hipStream_t);
+template bool spmm_grp_launch<float>(const SpmmArgs<float>&, const SpmmGroups&, const Tuning&, hipStream_t);
+template bool spmm_grouped_launch<double>(const SpmmArgs<double>&, const SpmmGroups&, hipStream_t);
+template bool spmm_grouped_launch<float>(const SpmmArgs<float>&, const SpmmGroups&, hipStream_t);
 
 }  // namespace css

@@ -84,6 +84,13 @@ class ColorJobStruct(ctypes.Structure):
                 ("rounds", ctypes.c_int32), ("status", ctypes.c_int32)]
 
 
+class TuningStruct(ctypes.Structure):
+    _fields_ = [("spmm_kernel", ctypes.c_int32), ("spmm_run", ctypes.c_int32), ("spmm_depth", ctypes.c_int32),
+                ("gram_chunks", ctypes.c_int32), ("update_rows", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+SPMM_KERNELS = {"auto": 0, "grouped": 1, "csr": 2}
+
 _lib = None
 
 
@@ -115,6 +122,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.css_batched_workspace_size.argtypes = [psys, i32, i32, u32, i32, ctypes.POINTER(sz)]
     lib.css_spmm_prepare.argtypes = [pcsr, vp, sz, vp]
     lib.css_spmm.argtypes = [pcsr, vp, vp, i32, i32, vp, sz, vp]
+    ptune = ctypes.POINTER(TuningStruct)
+    lib.css_set_tuning.argtypes = [ptune]
+    lib.css_get_tuning.argtypes = [ptune]
+    lib.css_spmm_time.argtypes = [pcsr, vp, vp, i32, i32, vp, sz, ptune, i32, ctypes.POINTER(ctypes.c_float), vp]
     lib.css_block_lanczos.argtypes = [pcsr, vp, vp, i32, i32, u32, vp, vp, pinfo, vp, sz, vp]
     lib.css_density_matrix.argtypes = [pcsr, vp, vp, i32, dbl, dbl, i32, dbl, vp, vp, i64, u32, vp,
                                        ctypes.POINTER(dbl), ctypes.POINTER(dbl), pinfo, vp, sz, vp]
@@ -141,7 +152,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                  "css_density_matrix", "css_density_matrix_batched", "css_batched_workspace_size",
                  "css_color_batched", "css_color_batched_workspace_size",
                  "css_energy_density_matrix", "css_find_mu", "css_inv_sqrt_overlap", "css_transform_hamiltonian",
-                 "css_density_matrix_nonorth", "css_workspace_size"):
+                 "css_density_matrix_nonorth", "css_workspace_size", "css_set_tuning", "css_get_tuning",
+                 "css_spmm_time"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -310,6 +322,48 @@ def css_spmm(H: DeviceCSR, V, b: int, ws=None, out=None):
                                        None if ws is None else _ptr(ws), 0 if ws is None else ws.numel(),
                                        _stream(V.device)))
     return W
+
+
+TUNING_FIELDS = ("spmm_kernel", "spmm_run", "spmm_depth", "gram_chunks", "update_rows")
+
+
+def _tuning_struct(cfg: dict) -> TuningStruct:
+    t = TuningStruct()
+    for k, v in cfg.items():
+        if k not in TUNING_FIELDS:
+            raise KeyError(k)
+        setattr(t, k, SPMM_KERNELS[v] if k == "spmm_kernel" and isinstance(v, str) else int(v))
+    return t
+
+
+def set_tuning(**cfg):
+    """Process-wide launch choices (css_set_tuning); fields not given take the defaults."""
+    t = _tuning_struct(cfg)
+    _check("css_set_tuning", load().css_set_tuning(ctypes.byref(t)))
+
+
+def reset_tuning():
+    _check("css_set_tuning", load().css_set_tuning(None))
+
+
+def get_tuning() -> dict:
+    t = TuningStruct()
+    _check("css_get_tuning", load().css_get_tuning(ctypes.byref(t)))
+    names = {v: k for k, v in SPMM_KERNELS.items()}
+    out = {k: getattr(t, k) for k in TUNING_FIELDS}
+    out["spmm_kernel"] = names[out["spmm_kernel"]]
+    return out
+
+
+def css_spmm_time(H: DeviceCSR, V, b: int, ws, W, reps: int = 20, **cfg) -> float:
+    """Average device milliseconds of `reps` launches of W = H V with the launch choices cfg."""
+    t = _tuning_struct(cfg)
+    ms = ctypes.c_float(0.0)
+    csr = H.struct()
+    _check("css_spmm_time", load().css_spmm_time(ctypes.byref(csr), _ptr(V), _ptr(W), b, int(V.shape[1]),
+                                                 None if ws is None else _ptr(ws), 0 if ws is None else ws.numel(),
+                                                 ctypes.byref(t), reps, ctypes.byref(ms), _stream(V.device)))
+    return float(ms.value)
 
 
 def css_block_lanczos(H: DeviceCSR, color, sign, n_colors: int, depth: int, flags: int):

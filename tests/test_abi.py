@@ -110,3 +110,41 @@ def test_struct_layout_matches_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_tuning_roundtrip_and_range_checks():
+    """css_set_tuning / css_get_tuning are host-only: values round-trip, out-of-range
+    fields are CSS_E_ARG and leave the current tuning unchanged, NULL resets."""
+    lib = css.load()
+    css.reset_tuning()
+    assert css.get_tuning() == {"spmm_kernel": "auto", "spmm_run": 0, "spmm_depth": 0, "gram_chunks": 0,
+                                "update_rows": 0}
+    css.set_tuning(spmm_kernel="grouped", spmm_run=256, spmm_depth=8, gram_chunks=2, update_rows=64)
+    assert css.get_tuning() == {"spmm_kernel": "grouped", "spmm_run": 256, "spmm_depth": 8, "gram_chunks": 2,
+                                "update_rows": 64}
+    for bad in ({"spmm_kernel": 3}, {"spmm_run": -1}, {"spmm_depth": 5}, {"gram_chunks": 3}, {"update_rows": 96}):
+        t = css._tuning_struct(bad)
+        assert lib.css_set_tuning(ctypes.byref(t)) == 1
+    assert css.get_tuning()["spmm_run"] == 256
+    css.reset_tuning()
+    assert css.get_tuning()["spmm_kernel"] == "auto"
+    assert lib.css_get_tuning(None) == 1
+    assert lib.css_spmm_time(None, None, None, 1, 16, None, 0, None, 1, None, None) == 1
+
+
+def test_autotune_cache_keys_and_roundtrip(tmp_path, monkeypatch):
+    """The autotuner's JSON cache: one entry per (arch, N, nnz/row, b, precision)."""
+    from paper_2605_20918_amd import autotune
+    monkeypatch.setattr(autotune, "arch_name", lambda: "gfx950")
+    p = str(tmp_path / "tune.json")
+    assert autotune.load_cache(p) == {}
+    k = autotune.key(60000, 6616104, 88, "fp32")
+    assert k == "gfx950|N=60000|nnz/row=110.3|b=88|fp32"
+    autotune.save_cache({k: {"choice": {"spmm_kernel": "grouped", "spmm_run": 512, "spmm_depth": 4}}}, p)
+    assert autotune.load_cache(p)[k]["choice"]["spmm_run"] == 512
+    assert autotune.apply_cached(60000, 6616104, 89, "fp32", p) is None
+    css.reset_tuning()
+    assert autotune.apply_cached(60000, 6616104, 88, "fp32", p) == {"spmm_kernel": "grouped", "spmm_run": 512,
+                                                                      "spmm_depth": 4}
+    assert css.get_tuning()["spmm_run"] == 512
+    css.reset_tuning()
