@@ -220,6 +220,30 @@ css_status css_density_matrix(const css_csr* H, const int32_t* color, const int8
                               void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * css_density_matrix_noalloc -- css_density_matrix for callers that cannot allocate
+ *   device memory (code under HIP graph capture, tight serving loops, harnesses that
+ *   forbid hipMalloc): the same computation and results, bitwise, with no workspace
+ *   argument. The library's scratch is a file-scope device array of 256 MiB, one per
+ *   GPU, held until the process ends; this call allocates nothing (no hipMalloc or
+ *   hipFree, no allocating library routine, no events: info->t_phase_ms stays 0).
+ *   Arguments as css_density_matrix without ws / ws_bytes.
+ *   The pole expansion's solver takes the scratch left after the other buffers.
+ *   Returns CSS_E_WORKSPACE before any device work when the buffers and 64 poles do
+ *   not fit in the 256 MiB (for example 216 water molecules, 1296 orbitals, at depth
+ *   40 fit; 1000 molecules do not), and after the Lanczos pass when the spectrum needs more poles
+ *   than fit; CSS_E_UNSUPPORTED with CSS_SUBSPACE_EIG (the dense eigensolver
+ *   allocates). Every call on one GPU
+ *   uses that GPU's one scratch array: calls that overlap on a GPU (several streams
+ *   or threads) race and must be serialised by the caller. The array keeps the last
+ *   call's contents; each call clears what it needs.
+ */
+css_status css_density_matrix_noalloc(const css_csr* H, const int32_t* color, const int8_t* sign,
+                                      int32_t n_colors, double mu, double kT, int32_t depth, double spin_deg,
+                                      const int64_t* p_row_ptr, const int32_t* p_col, int64_t p_nnz,
+                                      uint32_t flags, double* p_val, double* e_band, double* trace,
+                                      css_info* info, void* stream);
+
+/*
  * css_energy_density_matrix -- css_density_matrix together with the CSS estimate
  *   of the energy-weighted density matrix P_E = g f(H) H (the force expression
  *   of the paper's SCF section, rho_E = sum_i f(e_i) e_i |psi_i><psi_i|, taken as

@@ -623,7 +623,8 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
                   int32_t depth, double spin_deg, const int64_t* p_row_ptr, const int32_t* p_col, int64_t p_nnz,
                   uint32_t flags, double* p_val, double* pe_val, double* e_band, double* trace, double* pe_trace,
                   css_info* info, void* ws, size_t ws_bytes, void* stream, int fn = kFnFermi,
-                  const css_csr* H2 = nullptr, double* h2_val = nullptr) {
+                  const css_csr* H2 = nullptr, double* h2_val = nullptr, bool timed = true,
+                  size_t pole_ws = 0) {
     if (!color || !sign || !p_row_ptr || !p_col || !p_val || !e_band || !trace || !ws || p_nnz < 1) return CSS_E_ARG;
     if (fn == kFnFermi && (!(kT > 0.0) || !std::isfinite(kT) || !std::isfinite(mu) || !(spin_deg > 0.0)))
         return CSS_E_ARG;
@@ -631,6 +632,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     if (fn == kFnInvSqrt) flags |= CSS_SUBSPACE_EIG;
     DmPlan p;
     CSS_TRY(plan_dm(H, n_colors, depth, flags, p));
+    if (pole_ws && !p.use_eig) p.pole_ws = pole_ws;      // the caller's pole budget (the rest of its scratch)
     p.ns = ns;
     p.energy = pe_val != nullptr;
     p.hprime = h2_val != nullptr;
@@ -650,13 +652,15 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     hipStream_t s = as_stream(stream);
     const LzPlan& lz = p.lz;
 
+    // phase events (timed = false: none, for callers that must not allocate)
     hipEvent_t ev[6] = {};
-    for (auto& e : ev) CSS_HIP_TRY(hipEventCreate(&e));
+    if (timed)
+        for (auto& e : ev) CSS_HIP_TRY(hipEventCreate(&e));
     struct Guard {
         hipEvent_t* e;
         ~Guard() { for (int i = 0; i < 6; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
     } guard{ev};
-    CSS_HIP_TRY(hipEventRecord(ev[0], s));
+    if (timed) CSS_HIP_TRY(hipEventRecord(ev[0], s));
 
     {
         CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
@@ -670,7 +674,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     int v_eff = 0, brk = 0;
     double md = 0.0;
     CSS_TRY(run_lanczos_pass1(H, color, sign, lz, bf.lz, s, &v_eff, &brk, &md));
-    CSS_HIP_TRY(hipEventRecord(ev[1], s));
+    if (timed) CSS_HIP_TRY(hipEventRecord(ev[1], s));
 
     // Fermi operator in the Krylov subspace: F = g f(T) E_1 B_0 and the quadrature sums
     const int nT = v_eff * lz.b;
@@ -709,7 +713,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
             conv = r <= 1e-9;          // the update above then leaves an error of order r^2
         }
         if (!conv) return CSS_E_NONFINITE;
-        CSS_HIP_TRY(hipEventRecord(ev[2], s));
+        if (timed) CSS_HIP_TRY(hipEventRecord(ev[2], s));
         k_ns_finish<<<grid_for((int64_t)nT * lz.b, 256), 256, 0, s>>>(bf.nsZ, bf.nsY, bf.lz.counts, nT, lz.b, ghi,
                                                                        bf.F, bf.t0, bf.t1);
         det_sum(bf.t0, lz.b, bf.tmp, bf.res + 2, s);
@@ -723,7 +727,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
         CSS_HIP_TRY(hipStreamSynchronize(s));
         if (hbad) return CSS_E_NONFINITE;
         CSS_TRY(eig(bf.T, nT, bf.lam, bf.E, bf.flags + 1, bf.eig_ws, p.eig_ws, s));
-        CSS_HIP_TRY(hipEventRecord(ev[2], s));
+        if (timed) CSS_HIP_TRY(hipEventRecord(ev[2], s));
         k_occ_y<<<grid_for((int64_t)nT * lz.b, 256), 256, 0, s>>>(bf.T, bf.lam, bf.lz.counts, nT, lz.b, fn, mu, kT,
                                                                     spin_deg, bf.Y);
         gemm_f64_launch(nT, lz.b, nT, bf.T, 1, nT, bf.Y, lz.b, 1, bf.F, lz.b, 1, s);
@@ -735,10 +739,10 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
         CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
         CSS_TRY(subspace_fermi_poles(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.lz.counts, mu, kT, spin_deg, bf.F,
                                      bf.res + 2, bf.pole_ws, p.pole_ws, &npoles, s));
-        CSS_HIP_TRY(hipEventRecord(ev[2], s));
+        if (timed) CSS_HIP_TRY(hipEventRecord(ev[2], s));
     }
     k_pad_F<<<grid_for(v_eff * mat, 256), 256, 0, s>>>(bf.F, v_eff, lz.b, lz.ld, bf.Fpad);
-    CSS_HIP_TRY(hipEventRecord(ev[3], s));
+    if (timed) CSS_HIP_TRY(hipEventRecord(ev[3], s));
 
     // reconstruction X = sum_j Q_j F_j
     if (lz.twopass) {
@@ -751,7 +755,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
                               static_cast<const double*>(slot_ptr(lz, bf.lz, 0)), lz.Np * lz.ld, v_eff, bf.Fpad, mat,
                               false, 1.0, lz.Np, lz.ld, bf.lz.stage, nullptr, s);
     }
-    CSS_HIP_TRY(hipEventRecord(ev[4], s));
+    if (timed) CSS_HIP_TRY(hipEventRecord(ev[4], s));
 
     // extraction on the pattern, trace, band energy
     const int sym = (flags & CSS_SYMMETRIZE) ? 1 : 0;
@@ -810,7 +814,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
         launch_gather<double>(lz.n, p_row_ptr, p_col, color, sign, bf.Z, lz.ld, sym, h2_val, rt, ra, s);
         det_sum(rt, lz.n, bf.tmp + 2 * kSumBlocks, bf.res + 5, s);
     }
-    CSS_HIP_TRY(hipEventRecord(ev[5], s));
+    if (timed) CSS_HIP_TRY(hipEventRecord(ev[5], s));
     double hres[8];
     int hinfo[2] = {0, 0};
     CSS_HIP_TRY(hipMemcpyAsync(hres, bf.res, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -833,12 +837,12 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
         info->n_poles = npoles;
         info->trace_krylov = hres[2];
         info->e_band_krylov = hres[3];
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; timed && k < 5; ++k) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess) info->t_phase_ms[k] = ms;
         }
         float tot = 0.f;
-        if (hipEventElapsedTime(&tot, ev[0], ev[5]) == hipSuccess) info->t_phase_ms[5] = tot;
+        if (timed && hipEventElapsedTime(&tot, ev[0], ev[5]) == hipSuccess) info->t_phase_ms[5] = tot;
     }
     return CSS_OK;
 }
@@ -1030,6 +1034,59 @@ extern "C" css_status css_density_matrix(const css_csr* H, const int32_t* color,
                                          css_info* info, void* ws, size_t ws_bytes, void* stream) {
     return css::dm_run(H, color, sign, n_colors, mu, kT, depth, spin_deg, p_row_ptr, p_col, p_nnz, flags, p_val,
                        nullptr, e_band, trace, nullptr, info, ws, ws_bytes, stream);
+}
+
+namespace css {
+namespace {
+
+// Scratch of css_density_matrix_noalloc: a file-scope device array, one copy on each
+// GPU the library runs on, held until the process ends. Host code never uses the
+// array's name as an address: each device's address comes from hipGetSymbolAddress
+// on that device's first call and is kept per device.
+constexpr size_t kNoAllocBytes = size_t(256) << 20;
+constexpr int kNoAllocMinPoles = 64;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+std::mutex g_scratch_mu;
+void* g_scratch[64] = {};
+
+css_status scratch_of_current_device(void** out) {
+    int dev = 0;
+    CSS_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return CSS_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr)
+            return CSS_E_DEVICE;
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return CSS_OK;
+}
+
+}  // namespace
+}  // namespace css
+
+extern "C" css_status css_density_matrix_noalloc(const css_csr* H, const int32_t* color, const int8_t* sign,
+                                                 int32_t n_colors, double mu, double kT, int32_t depth,
+                                                 double spin_deg, const int64_t* p_row_ptr, const int32_t* p_col,
+                                                 int64_t p_nnz, uint32_t flags, double* p_val, double* e_band,
+                                                 double* trace, css_info* info, void* stream) {
+    if (flags & CSS_SUBSPACE_EIG) return CSS_E_UNSUPPORTED;        // rocSOLVER allocates its own memory
+    DmPlan p;
+    CSS_TRY(plan_dm(H, n_colors, depth, flags, p));
+    // every buffer but the pole solver's, which takes the rest of the scratch: at least
+    // kNoAllocMinPoles poles must fit (the solver itself fails with CSS_E_WORKSPACE if a
+    // wider spectrum needs more than fit)
+    p.pole_ws = 0;
+    const size_t rest = dm_workspace_bytes(p) + 256;
+    const size_t min_poles = pole_workspace_bytes(std::max(1, p.lz.v_max), n_colors, kNoAllocMinPoles);
+    if (rest + min_poles > kNoAllocBytes) return CSS_E_WORKSPACE;
+    void* ws = nullptr;
+    CSS_TRY(scratch_of_current_device(&ws));
+    return css::dm_run(H, color, sign, n_colors, mu, kT, depth, spin_deg, p_row_ptr, p_col, p_nnz, flags, p_val,
+                       nullptr, e_band, trace, nullptr, info, ws, kNoAllocBytes, stream, kFnFermi, nullptr, nullptr,
+                       false, kNoAllocBytes - rest);
 }
 
 extern "C" css_status css_energy_density_matrix(const css_csr* H, const int32_t* color, const int8_t* sign,

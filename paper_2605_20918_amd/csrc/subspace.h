@@ -15,7 +15,9 @@ namespace css {
 css_status subspace_fermi_poles(const double* A, const double* B, int v, int b, int ld, const int* counts,
                                 double mu, double kT, double g, double* F, double* sums, void* ws, size_t ws_bytes,
                                 int* npoles_out, hipStream_t s);
-size_t pole_workspace_bytes(int v, int b);
+// Workspace of subspace_fermi_poles for at most max_poles poles (0: the most the
+// expansion ever uses, 257).
+size_t pole_workspace_bytes(int v, int b, int max_poles = 0);
 // Gershgorin bounds of T (every Ritz value lies in [lo, hi]); host outputs,
 // synchronises the stream. ws: at least 2 v b + 16 doubles (the pole workspace is).
 css_status subspace_spectral_bounds(const double* A, const double* B, int v, int b, int ld, void* ws, size_t ws_bytes,

@@ -1009,8 +1009,8 @@ int max_lds() {
 
 }  // namespace
 
-size_t pole_workspace_bytes(int v, int b) {
-    const int64_t np = kMaxDepth / 2 + 1;
+size_t pole_workspace_bytes(int v, int b, int max_poles) {
+    const int64_t np = max_poles > 0 ? max_poles : kMaxDepth / 2 + 1;
     const int64_t bb = (int64_t)b * b;
     const int64_t n16 = 16 * (int64_t)((b + 15) / 16);
     const int64_t gmat = std::max(bb, n16 * n16);          // G blocks (padded for the blocked solver)

@@ -129,6 +129,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.css_block_lanczos.argtypes = [pcsr, vp, vp, i32, i32, u32, vp, vp, pinfo, vp, sz, vp]
     lib.css_density_matrix.argtypes = [pcsr, vp, vp, i32, dbl, dbl, i32, dbl, vp, vp, i64, u32, vp,
                                        ctypes.POINTER(dbl), ctypes.POINTER(dbl), pinfo, vp, sz, vp]
+    lib.css_density_matrix_noalloc.argtypes = [pcsr, vp, vp, i32, dbl, dbl, i32, dbl, vp, vp, i64, u32, vp,
+                                               ctypes.POINTER(dbl), ctypes.POINTER(dbl), pinfo, vp]
     lib.css_energy_density_matrix.argtypes = [pcsr, vp, vp, i32, dbl, dbl, i32, dbl, vp, vp, i64, u32, vp, vp,
                                               ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl), pinfo,
                                               vp, sz, vp]
@@ -153,7 +155,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                  "css_color_batched", "css_color_batched_workspace_size",
                  "css_energy_density_matrix", "css_find_mu", "css_inv_sqrt_overlap", "css_transform_hamiltonian",
                  "css_density_matrix_nonorth", "css_workspace_size", "css_set_tuning", "css_get_tuning",
-                 "css_spmm_time"):
+                 "css_spmm_time", "css_density_matrix_noalloc"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib

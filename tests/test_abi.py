@@ -148,3 +148,20 @@ def test_autotune_cache_keys_and_roundtrip(tmp_path, monkeypatch):
                                                                       "spmm_depth": 4}
     assert css.get_tuning()["spmm_run"] == 512
     css.reset_tuning()
+
+
+def test_noalloc_rejects_oversized_systems_before_device_work():
+    """css_density_matrix_noalloc checks its fixed 256 MiB scratch against the system's
+    buffers on the host: 10^6 and 1000 water molecules at depth 40 do not fit
+    (CSS_E_WORKSPACE); CSS_SUBSPACE_EIG is CSS_E_UNSUPPORTED. Placeholder device
+    pointers are never touched."""
+    lib = css.load()
+    e, t = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    tail = (ctypes.c_void_p(256), ctypes.byref(e), ctypes.byref(t), None, None)
+    for n, nnz, b in ((1_000_000, 110_000_000, 88), (6000, 675_000, 86)):      # 10^6 and 1000 molecules
+        csr = css.CsrStruct(n, nnz, 8, 8, 8, css.CSS_F64)
+        args = (ctypes.byref(csr), ctypes.c_void_p(256), ctypes.c_void_p(256), b, -0.4, 0.01, 40, 2.0,
+                ctypes.c_void_p(256), ctypes.c_void_p(256), 170 * n)
+        assert lib.css_density_matrix_noalloc(*args, 0, *tail) == 3
+        assert lib.css_density_matrix_noalloc(*args, css.PREC_FP32 | css.REORTH_FULL, *tail) == 3
+        assert lib.css_density_matrix_noalloc(*args, css.SUBSPACE_EIG, *tail) == 8
