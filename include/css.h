@@ -58,8 +58,16 @@ enum { CSS_F64 = 0, CSS_F32 = 1 };
 
 /* flags (bitwise or) for css_block_lanczos / css_density_matrix / css_build_probes */
 #define CSS_PREC_FP64      0x0u   /* SpMM and block products in FP64 */
-#define CSS_PREC_FP32      0x1u   /* SpMM and block products in FP32 (FP32 accumulation) */
-#define CSS_PREC_BF16X3    0x2u   /* reserved: split bf16 hi+lo products */
+#define CSS_PREC_FP32      0x1u   /* Krylov blocks and H stored in FP32; SpMM in FP32 with FP32
+                                     accumulation (FP32 MFMA in the grouped kernel); Gram and
+                                     block-update products on BF16/FP16 MFMA with operands split
+                                     in two or three parts where the block width allows (each
+                                     product term as accurate as the FP32 one), else FP32 MFMA;
+                                     Gram partial sums in FP32 over at most a few hundred rows,
+                                     reduced in FP64; the Cholesky factors, T, the subspace
+                                     solve, the gather and every trace and energy sum in FP64.
+                                     The other values of the precision bits (0x2, 0x3) return
+                                     CSS_E_UNSUPPORTED. */
 #define CSS_PREC_MASK      0x3u
 #define CSS_BASIS_STORED   0x0u   /* keep every Krylov block for the reconstruction */
 #define CSS_BASIS_TWOPASS  0x4u   /* store no basis; regenerate it in a second pass */
@@ -75,6 +83,13 @@ enum { CSS_F64 = 0, CSS_F32 = 1 };
 #define CSS_SPMM_CSR       0x200u /* always use the row-parallel CSR SpMM kernel; by default the
                                      16-row grouped MFMA kernel is used where H's row groups
                                      are dense enough (see css_spmm_prepare) */
+#define CSS_DIAG_ORTHO     0x400u /* css_block_lanczos / css_density_matrix /
+                                     css_density_matrix_nonorth: measure the loss of
+                                     orthogonality of the stored Krylov basis,
+                                     info.ortho_err = max |Q^T Q - I| over all block pairs
+                                     (v_eff (v_eff + 1) / 2 block Gram products in the Lanczos
+                                     precision, counted in the Lanczos phase time); NaN with
+                                     CSS_BASIS_TWOPASS or without the flag */
 
 /* workspace query selectors */
 enum { CSS_ENTRY_COLOR = 0, CSS_ENTRY_LANCZOS = 1, CSS_ENTRY_DENSITY = 2, CSS_ENTRY_SPMM = 3,
@@ -105,6 +120,7 @@ typedef struct {
     double trace_krylov;      /* sum_k g f(lambda_k) w_k (Krylov quadrature of Tr P) */
     double e_band_krylov;     /* sum_k lambda_k g f(lambda_k) w_k */
     double t_phase_ms[6];     /* lanczos, subspace solve, F padding, reconstruction, gather, total */
+    double ortho_err;         /* max |Q^T Q - I| of the Krylov basis with CSS_DIAG_ORTHO, else NaN */
 } css_info;
 
 /*
@@ -199,14 +215,20 @@ css_status css_block_lanczos(const css_csr* H, const int32_t* color, const int8_
 
 /*
  * css_density_matrix -- the CSS estimate of P = g f(H) on a pattern
- *   (Eqs.(1)-(7) with S = I). Block Lanczos, exact diagonalisation of the
- *   block-tridiagonal projected H, F = U diag(g f(lambda)) U[0:b,:]^T B_0,
- *   X = [Q_1..Q_k] F, then P_mn = sign[n] X[m, colour(n)] on the pattern,
- *   symmetrised with CSS_SYMMETRIZE.
+ *   (Eqs.(1)-(7) with S = I). Block Lanczos, then F = [g f(T)]_{:,1} B_0 for the
+ *   block-tridiagonal projected H (B_0 = diag(sqrt n_c)): by default from the
+ *   contour integral of Eq.(7) written as a sum of resolvents (a rational
+ *   approximation of f accurate to about 1e-15, poles from css_fermi_poles), with
+ *   CSS_SUBSPACE_EIG (and always when n_colors > 128) by dense diagonalisation
+ *   (rocSOLVER dsyevd) as the paper does, F = U diag(g f(lambda)) U[0:b,:]^T B_0.
+ *   Then X = [Q_1..Q_k] F and P_mn = sign[n] X[m, colour(n)] on the pattern
+ *   (Eqs.(3), (6)), symmetrised with CSS_SYMMETRIZE.
  *   mu, kT      chemical potential and temperature (kT > 0), units of H
  *   spin_deg    g (2 for closed shells)
- *   p_row_ptr, p_col, p_nnz  device pattern (e.g. from css_color); must be
- *               symmetric with sorted rows when CSS_SYMMETRIZE is set
+ *   p_row_ptr, p_col, p_nnz  device pattern (e.g. from css_color): columns sorted
+ *               (strictly increasing) within each row, always (the band energy
+ *               looks H's entries up in the pattern rows); symmetric when
+ *               CSS_SYMMETRIZE is set. CSS_E_CSR otherwise
  *   p_val       device double[p_nnz] out
  *   e_band      host out: sum over entries in both H and the pattern of H_mn P_mn
  *   trace       host out: sum_m P_mm
@@ -332,10 +354,10 @@ css_status css_transform_hamiltonian(const css_csr* H, const css_csr* S, const i
 
 /*
  * css_density_matrix_nonorth -- the CSS density matrix of a non-orthogonal basis
- *   (Eq.(9)): rho~ = S^(-1/2) Phi rho^K Phi^T r~ r^T, with r the probes, r~ =
+ *   (Eq.(6)): rho~ = S^(-1/2) Phi rho^K Phi^T r~ r^T, with r the probes, r~ =
  *   S^(-1/2) r, Phi the block Krylov basis of H' = S^(-1/2) H S^(-1/2) from r~
  *   (the first block Q_1 R_0 = r~ by Cholesky QR, so B_0 = R_0 is triangular) and
- *   rho^K = g f(T) (Eq.(10)) by the pole expansion of css_density_matrix with
+ *   rho^K = g f(T) (Eq.(7)) by the pole expansion of css_density_matrix with
  *   B_0 = I, then F = F_I R_0 (F is linear in B_0), or with CSS_SUBSPACE_EIG by
  *   dense diagonalisation (rocSOLVER dsyevd). Only
  *   sparse x block products: r~ = S^(-1/2) r and X = S^(-1/2) X' in FP64, the
@@ -379,7 +401,8 @@ css_status css_density_matrix_nonorth(const css_csr* Hp, const css_csr* S_isqrt,
  *   Krylov estimate of Tr P, Eqs.(6)-(7), monotone in mu) equals n_electrons,
  *   after one block Lanczos pass as in css_density_matrix.
  *   Default: N(mu) from the pole expansion of css_density_matrix's subspace step
- *   at each trial mu, root by Brent's method on the Gershgorin bracket of T widened
+ *   at each trial mu, root by Chandrupatla's bracketing method (inverse quadratic
+ *   interpolation where it is safe, else bisection) on the Gershgorin bracket of T widened
  *   by 50 kT, to an interval of 1e-13 max(1, |ends|).
  *   CSS_SUBSPACE_EIG (and n_colors > 128): T = U diag(lambda) U^T by rocSOLVER
  *   dsyevd, w_k = sum_c n_c U[c,k]^2, bisection on the device on

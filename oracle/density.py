@@ -221,10 +221,10 @@ def transform_hamiltonian(H, S, color, sign, n_colors, depth, p_row_ptr, p_col, 
 
 def density_matrix_nonorth(Hp, S_isqrt, color, sign, n_colors, mu, kT, depth, p_row_ptr, p_col, spin_deg=2.0,
                            H=None, S=None, reorth=REORTH_FULL, cholqr2=True, symmetrize_p=True) -> dict:
-    """The CSS density matrix of a non-orthogonal basis (Eq.(9)):
+    """The CSS density matrix of a non-orthogonal basis (Eq.(6)):
     rho~ = S^(-1/2) Phi rho^K Phi^T r~ r^T, r~ = S^(-1/2) r, Phi the block Krylov
     basis of H' from r~ (Q_1 R_0 = r~), rho^K = g f(T) from the eigenpairs of T
-    (Eq.(10)). Hp and S_isqrt are the sparse H' and S^(-1/2)."""
+    (Eq.(7)). Hp and S_isqrt are the sparse H' and S^(-1/2)."""
     from .probes import probe_block
     color = np.asarray(color)
     sign = np.asarray(sign)

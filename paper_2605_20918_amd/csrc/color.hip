@@ -591,7 +591,7 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
     if (ar.overflow) return CSS_E_WORKSPACE;
 
     // finite coordinates and bounding box (open directions)
-    CSS_HIP_TRY(hipMemsetAsync(w.scalars, 0, 64 * sizeof(int), s));
+    fill_launch<int>(w.scalars, 0, 64, s);
     k_finite_check<<<grid_for(3LL * n, 256), 256, 0, s>>>(xyz, 3LL * n, w.scalars);
     {
         // per-block boxes of the n centres (stride 3), then the box of those boxes (stride 6)
@@ -610,8 +610,8 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
     const double rc2 = r_cut * r_cut;
 
     // cell list
-    CSS_HIP_TRY(hipMemsetAsync(w.cell_count, 0, sizeof(int) * ncell, s));
-    CSS_HIP_TRY(hipMemsetAsync(w.cell_fill, 0, sizeof(int) * ncell, s));
+    fill_launch<int>(w.cell_count, 0, ncell, s);
+    fill_launch<int>(w.cell_fill, 0, ncell, s);
     k_bin<<<grid_for(n, 256), 256, 0, s>>>(xyz, n, g, w.cell_of, w.cell_count);
     {
         // cell_start = exclusive scan of cell_count (reuse the row-pointer scan on a temp view)
@@ -642,7 +642,7 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
     if (capacity < nnz) return CSS_E_CAPACITY;
 
     // longest row must fit the LDS row sort
-    CSS_HIP_TRY(hipMemsetAsync(w.scalars, 0, 2 * sizeof(int), s));
+    fill_launch<int>(w.scalars, 0, 2, s);
     k_max_color<<<64, 256, 0, s>>>(nullptr, n, w.scalars, w.scalars + 1, p_row_ptr);
     int hmax[2];
     CSS_HIP_TRY(hipMemcpyAsync(hmax, w.scalars, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -662,7 +662,7 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
     int sweeps = 0;
     for (int k0 = 0; sweeps == 0; k0 += kFpBatch) {
         if (k0 > n + kFpBatch) return CSS_E_DEVICE;       // cannot happen: sweep k fixes priority level k
-        CSS_HIP_TRY(hipMemsetAsync(changed, 0, kFpBatch * sizeof(int), s));
+        fill_launch<int>(changed, 0, kFpBatch, s);
         for (int r = 0; r < kFpBatch; ++r)
             k_fp_sweep<<<sgrid, 256, 0, s>>>(n, p_row_ptr, p_col, w.deg, color, stamp, k0 + r, changed + r);
         int hch[kFpBatch];
@@ -672,8 +672,8 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
             if (hch[r] == 0) sweeps = k0 + r + 1;
     }
     k_clear_flags<<<grid_for(nnz, 256), 256, 0, s>>>(p_col, nnz);
-    CSS_HIP_TRY(hipMemsetAsync(w.scalars, 0xff, sizeof(int), s));
-    CSS_HIP_TRY(hipMemsetAsync(w.scalars + 1, 0, sizeof(int), s));
+    fill_launch<int>(w.scalars, -1, 1, s);
+    fill_launch<int>(w.scalars + 1, 0, 1, s);
     k_max_color<<<64, 256, 0, s>>>(color, n, w.scalars, w.scalars + 1, p_row_ptr);
     int hc = 0;
     CSS_HIP_TRY(hipMemcpyAsync(&hc, w.scalars, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -74,4 +74,16 @@ inline unsigned grid_for(int64_t work, int per_block) {
     return static_cast<unsigned>(g);
 }
 
+// p[i] = v for i < n. Flags and counters are cleared with this ordinary kernel rather
+// than hipMemsetAsync, so that a stream capture holds only kernel nodes.
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, T v, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+template <typename T>
+inline void fill_launch(T* p, T v, int64_t n, hipStream_t s) {
+    k_fill<T><<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+}
+
 }  // namespace css

@@ -2,9 +2,11 @@
 //
 // After block Lanczos (lanczos.hip):
 //   T  = block tridiagonal projected H (A_j diagonal, B_j below, B_j^T above);
-//   T  = U diag(lambda) U^T by exact diagonalisation (Eq.(7); rocSOLVER dsyevd);
-//   F  = U diag(g f(lambda)) U[0:b,:]^T B_0, f the Fermi function of Eq.(1)
-//        evaluated without overflow, B_0 = diag(sqrt n_c)          (Eq.(6));
+//   F  = [g f(T)]_{:,1} B_0, B_0 = diag(sqrt n_c), f the Fermi function of Eq.(1)
+//        (Eqs.(6)-(7)): by default from a pole expansion of the contour integral
+//        (subspace.hip); with CSS_SUBSPACE_EIG (and for b > 128) by exact
+//        diagonalisation T = U diag(lambda) U^T (rocSOLVER dsyevd),
+//        F = U diag(g f(lambda)) U[0:b,:]^T B_0, f evaluated without overflow;
 //   X  = sum_j Q_j F_j  (F_j = j-th block of b rows of F)          (Eq.(6));
 //   P_mn = s_n X[m, c(n)] on the pattern                           (Eq.(3)),
 //        optionally (P + P^T)/2 computed from X directly;
@@ -378,13 +380,22 @@ __global__ void k_ns_finish(const double* __restrict__ Z, const double* __restri
     }
 }
 
-// Pattern sanity: row pointers monotone from 0 to nnz, columns in range.
+// Pattern sanity: row pointers monotone from 0 to nnz, columns in range and strictly
+// increasing within each row (the band energy binary-searches the rows).
 __global__ void k_validate_pattern(int n, int64_t nnz, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                    int* __restrict__ bad) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) {
         const int64_t a = rp[i], b = rp[i + 1];
-        if (a < 0 || b < a || b > nnz) atomicOr(bad, 1);
+        if (a < 0 || b < a || b > nnz) {
+            atomicOr(bad, 1);
+        } else {
+            for (int64_t t = a + 1; t < b; ++t)
+                if (col[t - 1] >= col[t]) {
+                    atomicOr(bad, 1);
+                    break;
+                }
+        }
         if (i == 0 && a != 0) atomicOr(bad, 1);
         if (i == n - 1 && b != nnz) atomicOr(bad, 1);
     }
@@ -585,12 +596,12 @@ css_status plan_dm(const css_csr* H, int32_t b, int32_t depth, uint32_t flags, D
     CSS_TRY(plan_lanczos(H, b, depth, flags, p.lz));
     p.nTmax = std::max(1, p.lz.v_max) * b;
     p.sep_X = p.lz.twopass;
-    p.use_eig = (flags & CSS_SUBSPACE_EIG) != 0;
+    // the pole solver takes b <= 128; wider blocks are diagonalised
+    p.use_eig = (flags & CSS_SUBSPACE_EIG) != 0 || b > 128;
     if (p.use_eig) {
         p.eig_ws = eig_workspace_bytes(p.nTmax);
         if (p.eig_ws == 0) return CSS_E_DEVICE;
     } else {
-        if (b > 128) return CSS_E_UNSUPPORTED;
         p.pole_ws = pole_workspace_bytes(std::max(1, p.lz.v_max), b);
     }
     return CSS_OK;
@@ -663,7 +674,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     if (timed) CSS_HIP_TRY(hipEventRecord(ev[0], s));
 
     {
-        CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+        fill_launch<int>(bf.flags, 0, 16, s);
         k_validate_pattern<<<grid_for(std::max<int64_t>(lz.n, p_nnz), 256), 256, 0, s>>>(lz.n, p_nnz, p_row_ptr, p_col,
                                                                                          bf.flags);
         int pbad = 0;
@@ -674,6 +685,8 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     int v_eff = 0, brk = 0;
     double md = 0.0;
     CSS_TRY(run_lanczos_pass1(H, color, sign, lz, bf.lz, s, &v_eff, &brk, &md));
+    double ortho = NAN;
+    if (flags & CSS_DIAG_ORTHO) CSS_TRY(lanczos_ortho_err(lz, bf.lz, v_eff, s, &ortho));
     if (timed) CSS_HIP_TRY(hipEventRecord(ev[1], s));
 
     // Fermi operator in the Krylov subspace: F = g f(T) E_1 B_0 and the quadrature sums
@@ -684,7 +697,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
         // T^-1/2 E_1 B_0 by the coupled Newton-Schulz iteration on T / c, c the
         // Gershgorin upper bound; a non-positive bound or no convergence in 60
         // iterations means T (so S) is not positive definite
-        CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+        fill_launch<int>(bf.flags, 0, 16, s);
         k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T,
                                                                      bf.flags);
         int hbad = 0;
@@ -719,7 +732,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
         det_sum(bf.t0, lz.b, bf.tmp, bf.res + 2, s);
         det_sum(bf.t1, lz.b, bf.tmp + kSumBlocks, bf.res + 3, s);
     } else if (p.use_eig) {
-        CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+        fill_launch<int>(bf.flags, 0, 16, s);
         k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T,
                                                                      bf.flags);
         int hbad = 0;
@@ -736,7 +749,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
         det_sum(bf.t0, nT, bf.tmp, bf.res + 2, s);
         det_sum(bf.t1, nT, bf.tmp + kSumBlocks, bf.res + 3, s);
     } else {
-        CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+        fill_launch<int>(bf.flags, 0, 16, s);
         CSS_TRY(subspace_fermi_poles(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.lz.counts, mu, kT, spin_deg, bf.F,
                                      bf.res + 2, bf.pole_ws, p.pole_ws, &npoles, s));
         if (timed) CSS_HIP_TRY(hipEventRecord(ev[2], s));
@@ -788,7 +801,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     if (h2_val) {
         // H' = S^-1/2 H S^-1/2 read off S^-1/2 (H Y) o^T: Y is S^-1/2 applied to the
         // probes (X above), S^-1/2 the sparse estimate just gathered; FP64 products
-        CSS_HIP_TRY(hipMemsetAsync(bf.flags + 3, 0, 4 * sizeof(int), s));
+        fill_launch<int>(bf.flags + 3, 0, 4, s);
         csr_validate_launch(lz.n, H2->nnz, H2->row_ptr, H2->col, bf.flags + 3, s);
         int vbad[2] = {0, 0};
         CSS_HIP_TRY(hipMemcpyAsync(vbad, bf.flags + 3, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -833,6 +846,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
         info->breakdown = brk;
         info->spmm_kernel = bf.lz.use_grp ? 1 : 0;
         info->min_diag_r = md;
+        info->ortho_err = ortho;
         info->asym_max = hres[4];
         info->n_poles = npoles;
         info->trace_krylov = hres[2];
@@ -847,7 +861,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     return CSS_OK;
 }
 
-// Density matrix of a non-orthogonal basis (Eq.(9)): rho~ = S^-1/2 Phi rho^K Phi^T r~ r^T
+// Density matrix of a non-orthogonal basis (Eq.(6)): rho~ = S^-1/2 Phi rho^K Phi^T r~ r^T
 // with r~ = S^-1/2 r and the block Krylov space of H' from r~; S^-1/2 sparse.
 css_status nonorth_run(const css_csr* Hp, const css_csr* Sih, const css_csr* He, const css_csr* Se,
                        const int32_t* color, const int8_t* sign, int32_t n_colors, double mu, double kT,
@@ -889,7 +903,7 @@ css_status nonorth_run(const css_csr* Hp, const css_csr* Sih, const css_csr* He,
     CSS_HIP_TRY(hipEventRecord(ev[0], s));
 
     // inputs: the pattern and the sparse S^-1/2 (and H, S for the sums)
-    CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+    fill_launch<int>(bf.flags, 0, 16, s);
     k_validate_pattern<<<grid_for(std::max<int64_t>(lz.n, p_nnz), 256), 256, 0, s>>>(lz.n, p_nnz, p_row_ptr, p_col,
                                                                                      bf.flags);
     csr_validate_launch(lz.n, Sih->nnz, Sih->row_ptr, Sih->col, bf.flags + 3, s);
@@ -909,13 +923,15 @@ css_status nonorth_run(const css_csr* Hp, const css_csr* Sih, const css_csr* He,
     int v_eff = 0, brk = 0;
     double md = 0.0;
     CSS_TRY(run_lanczos_pass1(Hp, color, sign, lz, bf.lz, s, &v_eff, &brk, &md, bf.Z1, bf.R0));
+    double ortho = NAN;
+    if (flags & CSS_DIAG_ORTHO) CSS_TRY(lanczos_ortho_err(lz, bf.lz, v_eff, s, &ortho));
     CSS_HIP_TRY(hipEventRecord(ev[1], s));
 
     // rho^K = g f(T); F = g f(T) E_1 R0
     const int nT = v_eff * lz.b;
     const int64_t mat = (int64_t)lz.ld * lz.ld;
     int npoles = 0;
-    CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+    fill_launch<int>(bf.flags, 0, 16, s);
     if (p.use_eig) {
         // by diagonalisation: F = U g f(Lambda) U[0:b,:]^T R0
         k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T,
@@ -999,6 +1015,7 @@ css_status nonorth_run(const css_csr* Hp, const css_csr* Sih, const css_csr* He,
         info->breakdown = brk;
         info->spmm_kernel = bf.lz.use_grp ? 1 : 0;
         info->min_diag_r = md;
+        info->ortho_err = ortho;
         info->asym_max = hres[4];
         info->n_poles = npoles;
         info->trace_krylov = hres[2];
@@ -1075,6 +1092,7 @@ extern "C" css_status css_density_matrix_noalloc(const css_csr* H, const int32_t
     if (flags & CSS_SUBSPACE_EIG) return CSS_E_UNSUPPORTED;        // rocSOLVER allocates its own memory
     DmPlan p;
     CSS_TRY(plan_dm(H, n_colors, depth, flags, p));
+    if (p.use_eig) return CSS_E_UNSUPPORTED;                       // n_colors > 128: dense eigensolver
     // every buffer but the pole solver's, which takes the rest of the scratch: at least
     // kNoAllocMinPoles poles must fit (the solver itself fails with CSS_E_WORKSPACE if a
     // wider spectrum needs more than fit)
@@ -1130,63 +1148,56 @@ extern "C" css_status css_transform_hamiltonian(const css_csr* H, const css_csr*
 namespace css {
 namespace {
 
-// Root of c(mu) - n_e on [lo, hi] with c(lo) = c_lo < n_e < c_hi = c(hi) by Brent's
-// method (inverse quadratic interpolation, secant steps and bisection, as in Brent,
-// "Algorithms for Minimization without Derivatives", 1973, ch. 4), to an interval of
-// xtol or a residual |c - n_e| <= ftol. eval(mu, &c) computes c(mu); *evals counts
-// the calls.
+// Root of c(mu) - n_e on [lo, hi], c(lo) = c_lo < n_e < c_hi = c(hi), by Chandrupatla's
+// bracketing method (Adv. Eng. Software 28, 1997): the bracket [x1, x2] always
+// holds the root, x1 the newest point and x3 the point last dropped; the next point
+// is x1 + t (x2 - x1), with t from inverse quadratic interpolation through the
+// three points where that interpolant is monotone on the bracket (xi = (x1 - x2) /
+// (x3 - x2), phi = (f1 - f2) / (f3 - f2) satisfy phi^2 < xi and (1 - phi)^2 < 1 - xi),
+// bisection (t = 1/2) otherwise, and t kept a tolerance away from the ends. Stops at
+// a bracket of 2 xtol or a residual |c - n_e| <= ftol. eval(mu, &c) computes c(mu);
+// *evals counts the calls.
 template <typename Eval>
-css_status brent_root(Eval&& eval, double lo, double hi, double c_lo, double c_hi, double n_e, double xtol,
-                      double ftol, double* root, double* c_root, int* evals) {
-    double a = lo, b = hi, fa = c_lo - n_e, fb = c_hi - n_e;
-    double c = a, fc = fa, d = b - a, e = d;
+css_status bracket_root(Eval&& eval, double lo, double hi, double c_lo, double c_hi, double n_e, double xtol,
+                        double ftol, double* root, double* c_root, int* evals) {
+    double x1 = lo, f1 = c_lo - n_e, x2 = hi, f2 = c_hi - n_e, x3 = hi, f3 = f2;
+    double t = 0.5;
     *evals = 0;
     for (int it = 0; it < 200; ++it) {
-        if ((fb > 0.0) == (fc > 0.0)) {
-            c = a;
-            fc = fa;
-            d = e = b - a;
-        }
-        if (std::fabs(fc) < std::fabs(fb)) {
-            a = b; b = c; c = a;
-            fa = fb; fb = fc; fc = fa;
-        }
-        const double tol1 = 2.0 * 2.220446049250313e-16 * std::fabs(b) + 0.5 * xtol;
-        const double xm = 0.5 * (c - b);
-        if (std::fabs(xm) <= tol1 || std::fabs(fb) <= ftol) break;
-        if (std::fabs(e) >= tol1 && std::fabs(fa) > std::fabs(fb)) {
-            const double sr = fb / fa;
-            double pp, qq;
-            if (a == c) {
-                pp = 2.0 * xm * sr;
-                qq = 1.0 - sr;
-            } else {
-                const double q0 = fa / fc, r0 = fb / fc;
-                pp = sr * (2.0 * xm * q0 * (q0 - r0) - (b - a) * (r0 - 1.0));
-                qq = (q0 - 1.0) * (r0 - 1.0) * (sr - 1.0);
-            }
-            if (pp > 0.0) qq = -qq; else pp = -pp;
-            if (2.0 * pp < std::min(3.0 * xm * qq - std::fabs(tol1 * qq), std::fabs(e * qq))) {
-                e = d;
-                d = pp / qq;
-            } else {
-                d = xm;
-                e = d;
-            }
-        } else {
-            d = xm;
-            e = d;
-        }
-        a = b;
-        fa = fb;
-        b += std::fabs(d) > tol1 ? d : std::copysign(tol1, xm);
-        double cb = 0.0;
-        CSS_TRY(eval(b, &cb));
+        const double xt = x1 + t * (x2 - x1);
+        double ct = 0.0;
+        CSS_TRY(eval(xt, &ct));
         ++*evals;
-        fb = cb - n_e;
+        const double ft = ct - n_e;
+        if ((ft < 0.0) == (f1 < 0.0)) {             // the root lies between xt and x2
+            x3 = x1;
+            f3 = f1;
+        } else {                                    // between x1 and xt
+            x3 = x2;
+            f3 = f2;
+            x2 = x1;
+            f2 = f1;
+        }
+        x1 = xt;
+        f1 = ft;
+        const bool one = std::fabs(f1) <= std::fabs(f2);
+        const double xb = one ? x1 : x2, fb = one ? f1 : f2;
+        if (std::fabs(fb) <= ftol || std::fabs(x2 - x1) <= 2.0 * xtol) {
+            *root = xb;
+            *c_root = fb + n_e;
+            return CSS_OK;
+        }
+        const double tl = std::min(0.5, xtol / std::fabs(x2 - x1));
+        const double xi = (x1 - x2) / (x3 - x2), phi = (f1 - f2) / (f3 - f2);
+        if (phi * phi < xi && (1.0 - phi) * (1.0 - phi) < 1.0 - xi)
+            t = f1 / (f2 - f1) * f3 / (f2 - f3) + (x3 - x1) / (x2 - x1) * f1 / (f3 - f1) * f2 / (f3 - f2);
+        else
+            t = 0.5;
+        t = std::min(1.0 - tl, std::max(tl, t));
     }
-    *root = b;
-    *c_root = fb + n_e;
+    const bool one = std::fabs(f1) <= std::fabs(f2);
+    *root = one ? x1 : x2;
+    *c_root = (one ? f1 : f2) + n_e;
     return CSS_OK;
 }
 
@@ -1200,7 +1211,6 @@ extern "C" css_status css_find_mu(const css_csr* H, const int32_t* color, const 
     if (!H || !color || !sign || !mu || !ws) return CSS_E_ARG;
     if (!(kT > 0.0) || !std::isfinite(kT) || !(spin_deg > 0.0) || !std::isfinite(spin_deg)) return CSS_E_ARG;
     if (!(n_electrons > 0.0) || !(n_electrons < spin_deg * (double)H->n)) return CSS_E_ARG;
-    if (n_colors > 128) flags |= CSS_SUBSPACE_EIG;       // the pole solves take b <= 128
     DmPlan p;
     CSS_TRY(plan_dm(H, n_colors, depth, flags, p));
     if (ws_bytes < dm_workspace_bytes(p)) return CSS_E_WORKSPACE;
@@ -1230,7 +1240,7 @@ extern "C" css_status css_find_mu(const css_csr* H, const int32_t* color, const 
     int evals = 0;
     if (p.use_eig) {
         // eigenpairs of T, weights, bisection on the device
-        CSS_HIP_TRY(hipMemsetAsync(bf.flags, 0, 16 * sizeof(int), s));
+        fill_launch<int>(bf.flags, 0, 16, s);
         k_assemble_T<<<grid_for((int64_t)nT * nT, 256), 256, 0, s>>>(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.T,
                                                                      bf.flags);
         int hbad = 0;
@@ -1251,8 +1261,9 @@ extern "C" css_status css_find_mu(const css_csr* H, const int32_t* color, const 
         evals = (int)hres[2];
     } else {
         // the count at each trial mu from the pole expansion (the Krylov trace of
-        // css_density_matrix), root by Brent's method on the Gershgorin bracket
-        // widened by 50 kT, where the count is 0 and g N to within g N e^-50
+        // css_density_matrix), root by Chandrupatla's bracketing method on the
+        // Gershgorin bracket widened by 50 kT, where the count is 0 and g N to within
+        // g N e^-50
         double glo = 0.0, ghi = 0.0;
         CSS_TRY(subspace_spectral_bounds(bf.lz.A, bf.lz.B, v_eff, lz.b, lz.ld, bf.pole_ws, p.pole_ws, &glo, &ghi, s));
         CSS_HIP_TRY(hipEventRecord(ev[2], s));
@@ -1269,7 +1280,7 @@ extern "C" css_status css_find_mu(const css_csr* H, const int32_t* color, const 
         };
         const double lo = glo - 50.0 * kT, hi = ghi + 50.0 * kT;
         const double xtol = 1e-13 * std::max(1.0, std::max(std::fabs(lo), std::fabs(hi)));
-        CSS_TRY(brent_root(eval, lo, hi, 0.0, spin_deg * (double)lz.n, n_electrons, xtol, 1e-12 * n_electrons,
+        CSS_TRY(bracket_root(eval, lo, hi, 0.0, spin_deg * (double)lz.n, n_electrons, xtol, 1e-12 * n_electrons,
                            &hres[0], &hres[1], &evals));
         CSS_HIP_TRY(hipEventRecord(ev[3], s));
         CSS_HIP_TRY(hipStreamSynchronize(s));
@@ -1285,6 +1296,7 @@ extern "C" css_status css_find_mu(const css_csr* H, const int32_t* color, const 
         info->spmm_kernel = bf.lz.use_grp ? 1 : 0;
         info->n_evals = evals;
         info->min_diag_r = md;
+        info->ortho_err = NAN;
         info->trace_krylov = hres[1];
         for (int k = 0; k < 3; ++k) {
             float ms = 0.f;

@@ -69,6 +69,11 @@ css_status run_lanczos_pass1(const css_csr* H, const int32_t* color, const int8_
                              LzBufs& bf, hipStream_t s, int* v_eff, int* breakdown, double* min_diag,
                              const double* start = nullptr, double* R0 = nullptr);
 
+// max |Q_t^T Q_j - [t == j] I| over t <= j < v_eff (b x b blocks) after pass 1, from the
+// library's Gram products in the Lanczos precision; NaN with no stored basis. Host
+// synchronising; uses the Gram partials, the staging buffer and scal[2].
+css_status lanczos_ortho_err(const LzPlan& p, const LzBufs& bf, int v_eff, hipStream_t s, double* out);
+
 // Pointer to the tall block holding Q_{j} (0-based j) after pass 1 with a stored basis.
 inline void* slot_ptr(const LzPlan& p, const LzBufs& bf, int j) {
     return static_cast<char*>(bf.basis) + (size_t)j * p.Np * p.ld * p.elem;

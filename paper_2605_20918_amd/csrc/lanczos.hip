@@ -76,6 +76,36 @@ __global__ void k_max_reduce(const double* __restrict__ v, int64_t n, double* __
     if (threadIdx.x == 0) *out = sm[0];
 }
 
+// acc[0] = max(acc[0], max |M_t[r][c] - [t == diag and r == c]| over t < cnt and
+// r, c < b), M_t = M + t*ld*ld; one work-group. A NaN entry makes the result NaN.
+__global__ __launch_bounds__(256) void k_ortho_max(const double* __restrict__ M, int cnt, int b, int ld, int diag,
+                                                   double* __restrict__ acc) {
+    __shared__ double sm[256];
+    const int64_t per = (int64_t)b * b;
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < cnt * per; i += 256) {
+        const int t = static_cast<int>(i / per);
+        const int r = static_cast<int>((i % per) / b), c = static_cast<int>(i % b);
+        double v = M[t * (int64_t)ld * ld + (int64_t)r * ld + c];
+        if (t == diag && r == c) v -= 1.0;
+        v = fabs(v);
+        if (!(v <= m)) m = (m != m) ? m : v;
+    }
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double o = sm[threadIdx.x + s];
+            if (!(o <= sm[threadIdx.x]) && sm[threadIdx.x] == sm[threadIdx.x]) sm[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double a = acc[0], v = sm[0];
+        acc[0] = (a != a || v != v) ? NAN : fmax(a, v);
+    }
+}
+
 template <typename S, typename D>
 __global__ void k_convert(const S* __restrict__ in, D* __restrict__ out, int64_t n) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -346,7 +376,43 @@ css_status pass2_t(const css_csr* H, const int32_t* color, const int8_t* sign, c
     return CSS_OK;
 }
 
+template <typename T>
+css_status ortho_err_t(const LzPlan& p, const LzBufs& bf, int v_eff, hipStream_t s, double* out) {
+    const int64_t mat = (int64_t)p.ld * p.ld;
+    const int64_t tall = p.Np * p.ld;
+    double* acc = bf.scal + 2;
+    k_zero_small<<<1, 64, 0, s>>>(acc, 1);
+    // products per launch: bounded by the staged outputs, and by the partial buffers
+    // at the chunk count that keeps FP32 running sums short
+    const int64_t by_partials = p.partial_mats / gram_min_chunks(p.Np, p.ld, (int)p.elem);
+    const int64_t by_stage = std::max({2, p.v_max, p.max_coef}) + 1;
+    const int cap = static_cast<int>(std::max<int64_t>(1, std::min(by_partials, by_stage)));
+    for (int j = 0; j < v_eff; ++j) {
+        const T* Qj = static_cast<const T*>(slot_ptr(p, bf, j));
+        for (int t0 = 0; t0 <= j; t0 += cap) {
+            const int cnt = std::min(cap, j + 1 - t0);
+            // out[t] = Q_{t0+t}^T Q_j; no state flag, so a breakdown does not skip it
+            gram_blocks_launch<T>(static_cast<const T*>(slot_ptr(p, bf, t0)), tall, cnt, Qj, p.Np, p.ld, false,
+                                  p.partial_mats, bf.partial, bf.stage, mat, 0, nullptr, s);
+            k_ortho_max<<<1, 256, 0, s>>>(bf.stage, cnt, p.b, p.ld, j - t0, acc);
+        }
+    }
+    CSS_HIP_TRY(hipGetLastError());
+    CSS_HIP_TRY(hipMemcpyAsync(out, acc, sizeof(double), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipStreamSynchronize(s));
+    return CSS_OK;
+}
+
 }  // namespace
+
+css_status lanczos_ortho_err(const LzPlan& p, const LzBufs& bf, int v_eff, hipStream_t s, double* out) {
+    if (p.twopass) {
+        *out = NAN;
+        return CSS_OK;
+    }
+    if (p.fp32) return ortho_err_t<float>(p, bf, v_eff, s, out);
+    return ortho_err_t<double>(p, bf, v_eff, s, out);
+}
 
 css_status lanczos_spmm(const css_csr* H, const LzPlan& p, const LzBufs& bf, const void* V, void* W, hipStream_t s) {
     const bool ok = p.fp32 ? launch_spmm_t<float>(H, bf, static_cast<const float*>(V), static_cast<float*>(W), p.ld, s)
@@ -366,7 +432,7 @@ css_status plan_lanczos(const css_csr* H, int32_t b, int32_t depth, uint32_t fla
     if (b < 1 || b > H->n || depth < 1) return CSS_E_ARG;
     if (b > kMaxColors) return CSS_E_UNSUPPORTED;
     const uint32_t prec = flags & CSS_PREC_MASK;
-    if (prec == CSS_PREC_BF16X3 || prec == 3u) return CSS_E_UNSUPPORTED;
+    if (prec != CSS_PREC_FP64 && prec != CSS_PREC_FP32) return CSS_E_UNSUPPORTED;
     p.n = H->n;
     p.nnz = H->nnz;
     p.b = b;
@@ -474,6 +540,14 @@ extern "C" css_status css_block_lanczos(const css_csr* H, const int32_t* color, 
         if (e0) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); }
         return st;
     }
+    double ortho = NAN;
+    if (flags & CSS_DIAG_ORTHO) {
+        st = lanczos_ortho_err(p, bf, v_eff, s, &ortho);
+        if (st != CSS_OK) {
+            if (e0) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); }
+            return st;
+        }
+    }
     const int64_t mat = (int64_t)p.ld * p.ld;
     const int64_t bb = (int64_t)p.b * p.b;
     for (int j = 0; j < v_eff; ++j) copy_small_launch(bf.A + j * mat, p.ld, p.b, A + j * bb, s);
@@ -492,6 +566,7 @@ extern "C" css_status css_block_lanczos(const css_csr* H, const int32_t* color, 
         info->breakdown = brk;
         info->spmm_kernel = bf.use_grp ? 1 : 0;
         info->min_diag_r = md;
+        info->ortho_err = ortho;
         info->t_phase_ms[0] = ms;
         info->t_phase_ms[5] = ms;
     } else {

@@ -43,52 +43,104 @@ namespace {
 
 // ------------------------------------------------------------------ host: pole table
 
-// Eigenvalues of a symmetric tridiagonal matrix (diagonal d, off-diagonal e[i] between
-// i and i+1) and the first component of each eigenvector, by implicit QL with
-// Wilkinson-type shifts, rotating only the first row of the eigenvector matrix.
+// Eigenpairs of a small symmetric tridiagonal matrix T (diagonal d, off-diagonal e,
+// e[i] coupling i and i + 1): the eigenvalues ascending and the first component of
+// each unit eigenvector (all the pole table needs).
+//
+// Eigenvalues by bisection on the Sturm count: the number of eigenvalues of T below
+// x equals the number of negative pivots q_i of the LDL^T factorisation of T - x I,
+// q_0 = d_0 - x, q_i = d_i - x - e_{i-1}^2 / q_{i-1} (Sylvester's law of inertia).
+// Each eigenvalue is bisected inside the Gershgorin interval to a width of a few
+// ulps. First components by inverse iteration: solve (T - lambda I) y = x twice from
+// x = (1, ..., 1), by Gaussian elimination with row interchanges on the band, and
+// normalise.
+int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+    const int n = static_cast<int>(d.size());
+    int neg = 0;
+    double q = 1.0;
+    for (int i = 0; i < n; ++i) {
+        const double off = i > 0 ? e[i - 1] * e[i - 1] / q : 0.0;
+        q = d[i] - x - off;
+        if (q == 0.0) q = -1e-300;          // a zero pivot counts as negative, nudged off zero
+        if (q < 0.0) ++neg;
+    }
+    return neg;
+}
+
+// y := (T - lambda I)^-1 y for tridiagonal T (n >= 1), partial pivoting; zero pivots
+// (lambda exactly an eigenvalue) are replaced by a tiny value, as inverse iteration allows.
+void shifted_solve(const std::vector<double>& d, const std::vector<double>& e, double lambda, std::vector<double>& y) {
+    const int n = static_cast<int>(d.size());
+    // row i holds u0[i] (diagonal), u1[i], u2[i] (first, second superdiagonal)
+    std::vector<double> u0(n), u1(n, 0.0), u2(n, 0.0), lo(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        u0[i] = d[i] - lambda;
+        if (i + 1 < n) u1[i] = e[i];
+    }
+    std::vector<double> sub(n, 0.0);                 // subdiagonal entry below each diagonal
+    for (int i = 0; i + 1 < n; ++i) sub[i] = e[i];
+    const double tiny = 1e-300;
+    for (int i = 0; i + 1 < n; ++i) {
+        // rows i and i + 1: columns i .. i + 2
+        if (std::fabs(sub[i]) > std::fabs(u0[i])) {
+            // interchange: row i + 1 becomes the pivot row
+            const double r0 = sub[i], r1 = u0[i + 1], r2 = (i + 1 < n - 1) ? u1[i + 1] : 0.0;
+            const double s0 = u0[i], s1 = u1[i], s2 = u2[i];
+            u0[i] = r0; u1[i] = r1; u2[i] = r2;
+            std::swap(y[i], y[i + 1]);
+            const double m = s0 / r0;
+            lo[i] = m;
+            u0[i + 1] = s1 - m * r1;
+            if (i + 1 < n - 1) u1[i + 1] = s2 - m * r2;
+            y[i + 1] -= m * y[i];
+        } else {
+            const double piv = u0[i] != 0.0 ? u0[i] : tiny;
+            u0[i] = piv;
+            const double m = sub[i] / piv;
+            lo[i] = m;
+            u0[i + 1] -= m * u1[i];
+            if (i + 1 < n - 1) u1[i + 1] -= m * u2[i];
+            y[i + 1] -= m * y[i];
+        }
+    }
+    if (u0[n - 1] == 0.0) u0[n - 1] = tiny;
+    for (int i = n - 1; i >= 0; --i) {
+        double acc = y[i];
+        if (i + 1 < n) acc -= u1[i] * y[i + 1];
+        if (i + 2 < n) acc -= u2[i] * y[i + 2];
+        y[i] = acc / u0[i];
+    }
+}
+
 void tridiag_eig_first_row(std::vector<double>& d, std::vector<double> e, std::vector<double>& z) {
     const int n = static_cast<int>(d.size());
+    const std::vector<double> diag = d;
+    double glo = INFINITY, ghi = -INFINITY;
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+        glo = std::min(glo, diag[i] - r);
+        ghi = std::max(ghi, diag[i] + r);
+    }
     z.assign(n, 0.0);
-    z[0] = 1.0;
-    e.push_back(0.0);
-    for (int l = 0; l < n; ++l) {
-        for (int iter = 0; iter < 200; ++iter) {
-            int m = l;
-            for (; m < n - 1; ++m) {
-                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-                if (std::fabs(e[m]) <= 1e-300 + 2.2e-16 * dd) break;
-            }
-            if (m == l) break;
-            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-            double r = std::hypot(g, 1.0);
-            g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
-            double s = 1.0, c = 1.0, p = 0.0;
-            int i = m - 1;
-            for (; i >= l; --i) {
-                const double f = s * e[i], b = c * e[i];
-                r = std::hypot(f, g);
-                e[i + 1] = r;
-                if (r == 0.0) {
-                    d[i + 1] -= p;
-                    e[m] = 0.0;
-                    break;
-                }
-                s = f / r;
-                c = g / r;
-                g = d[i + 1] - p;
-                r = (d[i] - g) * s + 2.0 * c * b;
-                p = s * r;
-                d[i + 1] = g + p;
-                g = c * r - b;
-                const double zf = z[i + 1];
-                z[i + 1] = s * z[i] + c * zf;
-                z[i] = c * z[i] - s * zf;
-            }
-            if (r == 0.0 && i >= l) continue;
-            d[l] -= p;
-            e[l] = g;
-            e[m] = 0.0;
+    for (int k = 0; k < n; ++k) {
+        double a = glo, b = ghi;                     // count(a) <= k < count(b)
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (a + b);
+            if (mid <= a || mid >= b) break;         // no double between a and b
+            if (sturm_count(diag, e, mid) > k) b = mid; else a = mid;
         }
+        const double lambda = 0.5 * (a + b);
+        std::vector<double> y(n, 1.0);
+        for (int it = 0; it < 3; ++it) {
+            shifted_solve(diag, e, lambda, y);
+            double nrm = 0.0;
+            for (double v : y) nrm = std::max(nrm, std::fabs(v));
+            for (double& v : y) v /= nrm;
+        }
+        double s2 = 0.0;
+        for (double v : y) s2 += v * v;
+        d[k] = lambda;
+        z[k] = y[0] / std::sqrt(s2);
     }
 }
 

@@ -26,7 +26,6 @@ CSS_F64, CSS_F32 = 0, 1
 # flags
 PREC_FP64 = 0x0
 PREC_FP32 = 0x1
-PREC_BF16X3 = 0x2
 BASIS_STORED = 0x0
 BASIS_TWOPASS = 0x4
 REORTH_NONE = 0x0
@@ -37,6 +36,7 @@ SYMMETRIZE = 0x40
 SIGNS_ONES = 0x80
 SUBSPACE_EIG = 0x100
 SPMM_CSR = 0x200
+DIAG_ORTHO = 0x400
 
 (ENTRY_COLOR, ENTRY_LANCZOS, ENTRY_DENSITY, ENTRY_SPMM, ENTRY_ENERGY_DENSITY, ENTRY_FIND_MU, ENTRY_INV_SQRT,
  ENTRY_TRANSFORM_H, ENTRY_DENSITY_NONORTH) = 0, 1, 2, 3, 4, 5, 6, 7, 8
@@ -58,13 +58,13 @@ class InfoStruct(ctypes.Structure):
                 ("n_poles", ctypes.c_int32), ("spmm_kernel", ctypes.c_int32), ("n_evals", ctypes.c_int32),
                 ("min_diag_r", ctypes.c_double), ("asym_max", ctypes.c_double),
                 ("trace_krylov", ctypes.c_double), ("e_band_krylov", ctypes.c_double),
-                ("t_phase_ms", ctypes.c_double * 6)]
+                ("t_phase_ms", ctypes.c_double * 6), ("ortho_err", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {"depth_eff": self.depth_eff, "n_colors": self.n_colors, "breakdown": self.breakdown,
                 "n_poles": self.n_poles, "spmm_kernel": "grouped" if self.spmm_kernel else "csr",
                 "min_diag_r": self.min_diag_r, "asym_max": self.asym_max, "trace_krylov": self.trace_krylov,
-                "e_band_krylov": self.e_band_krylov,
+                "e_band_krylov": self.e_band_krylov, "ortho_err": self.ortho_err,
                 "t_phase_ms": {k: self.t_phase_ms[i] for i, k in
                                enumerate(["lanczos", "subspace", "f_pad", "reconstruction", "gather", "total"])}}
 

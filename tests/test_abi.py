@@ -92,7 +92,7 @@ def test_struct_layout_matches_header(tmp_path):
     if gcc is None:
         pytest.skip("no C compiler")
     structs = {"css_csr": css.CsrStruct, "css_info": css.InfoStruct, "css_system": css.SystemStruct,
-               "css_color_job": css.ColorJobStruct}
+               "css_color_job": css.ColorJobStruct, "css_tuning": css.TuningStruct}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "css.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -474,6 +474,29 @@ def test_mixed_path_follows_energy_scale(scale):
     assert abs(t1 - t0) <= 1e-6 * abs(t0)
 
 
+@pytest.mark.parametrize("mode", ["stored", "twopass"])
+@pytest.mark.parametrize("M,seed,depth", [(216, 3, 8), (216, 3, 12), (1000, 20920, 10), (1000, 20920, 20)])
+def test_local_reorth_fp64_against_local_oracle(M, seed, depth, mode):
+    """FP64 with local re-orthogonalisation (against the previous two blocks), stored basis
+    and two-pass, element by element against the oracle running the same
+    re-orthogonalisation. The depths stop before the basis loses orthogonality: past that
+    point the local-reorthogonalisation result itself moves by more than 1e-10 under
+    rounding-size changes of H (pinned on the oracle alone in the CPU tests)."""
+    print(f"local reorth {mode} M={M} depth={depth}", flush=True)
+    ws, H, rp, col, color, b, sign, mu = water_case(M, seed)
+    ref = D.density_matrix(H, color, sign, b, mu, KT, depth, rp, col, reorth="local", cholqr2=True)
+    flags = css.PREC_FP64 | css.REORTH_LOCAL | css.CHOLQR2 | css.SYMMETRIZE | (css.BASIS_TWOPASS if mode == "twopass"
+                                                                                  else 0)
+    p, e, t, info = css.css_density_matrix(to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, depth, dev_i64(rp),
+                                           dev_i32(col), flags)
+    assert info["depth_eff"] == ref["v_eff"]
+    err = np.max(np.abs(p.cpu().numpy() - ref["p_val"]))
+    print(f"  max|dP|={err:.3e}", flush=True)
+    assert err <= 1e-10
+    assert abs(e - ref["e_band"]) <= 1e-10 * abs(ref["e_band"])
+    assert abs(t - ref["trace"]) <= 1e-10 * abs(ref["trace"])
+
+
 def test_twopass_matches_stored_basis():
     ws, H, rp, col, color, b, sign, mu = water_case(216, 3)
     args = (to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, 12, dev_i64(rp), dev_i32(col))

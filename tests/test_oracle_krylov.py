@@ -493,3 +493,22 @@ def test_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(S, "fermi", lambda x, mu, kT: 1.0 / (1.0 + np.exp(-(np.asarray(x) - mu) / kT)))
     t = np.linspace(-0.1, 0.1, 5)
     assert not np.allclose(S.fermi(-0.4 + t, -0.4, 0.01), 1.0 / (np.exp(t / 0.01) + 1.0))
+
+
+def test_krylov_count_slope_against_finite_difference_and_closed_form():
+    """d/dmu of the Krylov quadrature count: a central difference of krylov_count
+    (h = 1e-6 Ha, error O(h^2 N''') far below the tolerance), and for H = cI (one Ritz
+    value c, weight N) the closed form g N f(1 - f) / kT."""
+    kT = 0.01
+    rng = np.random.default_rng(4)
+    lam = np.sort(rng.uniform(-1.0, 0.5, 300))
+    w = rng.uniform(0.0, 3.0, 300)
+    for mu in (-0.6, -0.2, 0.1):
+        h = 1e-6
+        fd = (D.krylov_count(lam, w, mu + h, kT) - D.krylov_count(lam, w, mu - h, kT)) / (2 * h)
+        assert abs(D.krylov_count_slope(lam, w, mu, kT) - fd) <= 1e-6 * max(1.0, abs(fd))
+    N, c, g = 500, -0.3, 2.0
+    for mu in (-0.32, -0.3, -0.25):
+        f = 1.0 / (np.exp((c - mu) / kT) + 1.0)
+        assert abs(D.krylov_count_slope(np.array([c]), np.array([float(N)]), mu, kT, g) - g * N * f * (1 - f) / kT) \
+            <= 1e-12 * g * N / kT
