@@ -14,12 +14,16 @@ kT = 0.01 Ha, depth 40):
         the FP64 path (local re-orthogonalisation) is timed beside it
   1m    1 000 000 molecules (6 000 000 orbitals), mixed precision with a stored
         basis; FP64 beside it with the two-pass (no stored basis) variant
-  1k    1 000 molecules, FP64
+  1k    1 000 molecules, FP64 (full re-orthogonalisation)
   batch48  48 independent boxes of 200..8000 molecules (log-uniform sizes, seed
         20922), mixed precision: all boxes coloured in one css_color_batched call,
         then all densities in one css_density_matrix_batched call; compared with
         one density call per box
-Prints one JSON line.
+Before the timed steps the launch choices are autotuned for the workload
+(--no-tune keeps the built-in ones). The default run (10k) also carries, after its
+timed region, sub-records for depth 60, for 10^6 molecules (one mixed step, one
+FP64 two-pass step, the SpMM roofline at that size) and for the 48-box batch
+(--no-sub skips them). Prints one JSON line.
 
 --copy-calibration copies 1 GiB device to device three times and prints its
 size: the reference for scaling the HBM byte counters of a profiler run.
@@ -62,7 +66,8 @@ def batch_sizes():
 
 
 def run_batch(args):
-    """48 uneven water boxes: colouring per box, then one batched density call."""
+    """48 uneven water boxes: colouring per box, then one batched density call.
+    Returns the record (a dict)."""
     import torch
     from paper_2605_20918_amd import css, synth
     wl = WORKLOADS["batch48"]
@@ -139,7 +144,7 @@ def run_batch(args):
         "density_rate_sequential": work / ts,
         "batched_equals_sequential_bitwise": same,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 # HBM bytes per launch of the grouped SpMM from FETCH_SIZE + WRITE_SIZE counter runs
 # (scaled by a 1 GiB copy), valid while the kernel source hashes to the recorded value
@@ -220,38 +225,55 @@ def cpu_baseline(ws, depth_sample: int, mu: float):
                       f"BLAS threads {threads}, SciPy SpMM single-threaded; host {cpu_model()}, nproc {os.cpu_count()}"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="10k", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="skip the 10k-only extra entry points (energy-weighted, mu, S^-1/2, H', "
-                         "non-orthogonal) after the timed region")
-    ap.add_argument("--copy-calibration", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
-        sys.exit(2)
-
+def spmm_roofline(css, H, ws_n: int, nnz: int, b: int, tdt, label: str, grouped: bool):
+    """The SpMM of the Lanczos steps (same kernel and launch shape), timed with events
+    on the stream it is launched on; algorithmic bytes nnz (val + col) + row pointers
+    + one read of V and one write of W (N x b)."""
     import torch
-    from paper_2605_20918_amd import css, synth
-    if not torch.cuda.is_available():
-        print("no ROCm device visible", file=sys.stderr)
-        sys.exit(1)
-    css.load()
-    if args.copy_calibration:
-        copy_calibration()
-        return
-    if args.workload == "batch48":
-        run_batch(args)
-        return
-    wl = WORKLOADS[args.workload]
-    print(f"[bench] generating {wl['n_mol']} molecules", file=sys.stderr, flush=True)
+    dev = H.row_ptr.device
+    ld = css.block_ld(b)
+    V = torch.zeros((ws_n, ld), dtype=tdt, device=dev)
+    V[:, :b] = torch.randn((ws_n, b), dtype=tdt, device=dev)
+    W = torch.empty_like(V)
+    spmm_ws = css.css_spmm_prepare(H) if grouped else None      # the kernel the Lanczos steps ran
+    for _ in range(3):
+        css.css_spmm(H, V, b, ws=spmm_ws, out=W)
+    reps = 50 if ws_n < 10 ** 6 else 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        css.css_spmm(H, V, b, ws=spmm_ws, out=W)
+    e1.record()
+    torch.cuda.synchronize()
+    t_spmm = e0.elapsed_time(e1) / reps * 1e-3
+    s_val = 4 if tdt == torch.float32 else 8
+    bytes_alg = nnz * (s_val + 4) + 4 * (ws_n + 1) + 2 * ws_n * b * s_val
+    achieved = bytes_alg / t_spmm / 1e9
+    del V, W, spmm_ws
+    return {"bound": "hbm", "label": label, "kernel": "k_spmm_grp" if grouped else "k_spmm_csr",
+            "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+            "bytes_per_launch": bytes_alg, "avg_launch_us": t_spmm * 1e6, "grouped": grouped}
+
+
+def timed_call(torch, fn, reps: int = 1):
+    """fn() once untimed, then the mean wall time of `reps` calls (device synchronised)."""
+    r = fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        r = fn()
+    torch.cuda.synchronize()
+    return r, (time.perf_counter() - t) / reps
+
+
+def measure_single(name: str, steps: int, warmup: int, extras: bool, fp64: bool, tune: bool,
+                   cpu: bool, depth60: bool = False):
+    """One workload: `steps` timed steps of colouring + probes + density matrix on
+    device-resident inputs, then the sub-measurements. Returns the record (a dict)."""
+    import torch
+    from paper_2605_20918_amd import autotune, css, synth
+    wl = WORKLOADS[name]
+    print(f"[bench] {name}: generating {wl['n_mol']} molecules", file=sys.stderr, flush=True)
     t_gen = time.perf_counter()
     ws = synth.water_system(wl["n_mol"], wl["seed"], progress=lambda m: print(
         f"[bench] generator: {m} ({time.perf_counter() - t_gen:.0f} s)", file=sys.stderr, flush=True))
@@ -265,172 +287,233 @@ def main():
     mu = MU_WATER
     state = {}
 
-    def step(fl=flags):
+    def colour():
         color, b, p_rp, p_col, rounds = css.css_color(xyz, box, R_CUT)
         sign, _ = css.css_build_probes(color, b, wl["seed"])
-        p_val, e_band, trace, info = css.css_density_matrix(H, color, sign, b, mu, KT, depth, p_rp, p_col, fl)
+        return color, b, p_rp, p_col, rounds, sign
+
+    css.reset_tuning()
+    tuning = None
+    if tune:
+        # launch choices for this workload shape, swept on the library's own kernels
+        color, b, _, _, _, sign = colour()
+        res = autotune.autotune(H, color, sign, b, depth, flags, write=False,
+                                lanczos_depth=depth if ws.n < 10 ** 6 else 4)
+        tuning = {"choice": res["choice"], "seconds": res["seconds"],
+                  "spmm_ms_best": min(t["ms"] for t in res["spmm_trials"]),
+                  "spmm_ms_default": next((t["ms"] for t in res["spmm_trials"]
+                                           if t["config"].get("spmm_run") == 512 and t["config"].get("spmm_depth") == 4),
+                                          None),
+                  "spmm_trials": len(res["spmm_trials"]), "lanczos_trials": len(res["lanczos_trials"])}
+        print(f"[bench] tuned in {res['seconds']:.1f} s: {res['choice']}", file=sys.stderr, flush=True)
+        del color, sign
+
+    def step(fl=flags, d=depth):
+        color, b, p_rp, p_col, rounds, sign = colour()
+        p_val, e_band, trace, info = css.css_density_matrix(H, color, sign, b, mu, KT, d, p_rp, p_col, fl)
         state.update(b=b, nnz_p=int(p_col.numel()), rounds=rounds, e_band=e_band, trace=trace, info=info,
                      p_val=p_val)
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         step()
-        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        print(f"[bench] warmup {i + 1}/{warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         step()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = (time.perf_counter() - t0) / steps
     info = state["info"]
     v_eff = info["depth_eff"]
     b = state["b"]
-    print(f"[bench] timed {args.steps} steps: {dt * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    print(f"[bench] {name}: timed {steps} steps: {dt * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
 
     # colouring alone (css_color) for the phase table
-    torch.cuda.synchronize()
-    tc = time.perf_counter()
-    css.css_color(xyz, box, R_CUT)
-    torch.cuda.synchronize()
-    t_color = time.perf_counter() - tc
-
-    # SpMM roofline: the same kernel and launch shape as inside the Lanczos loop,
-    # timed with events on the stream it runs on
-    ld = css.block_ld(b)
-    V = torch.zeros((ws.n, ld), dtype=tdt, device=dev)
-    V[:, :b] = torch.randn((ws.n, b), dtype=tdt, device=dev)
-    W = torch.empty_like(V)
-    grouped = info["spmm_kernel"] == "grouped"
-    spmm_ws = css.css_spmm_prepare(H) if grouped else None
-    for _ in range(3):
-        css.css_spmm(H, V, b, ws=spmm_ws, out=W)
-    reps = 50
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        css.css_spmm(H, V, b, ws=spmm_ws, out=W)
-    e1.record()
-    torch.cuda.synchronize()
-    t_spmm = e0.elapsed_time(e1) / reps * 1e-3
-    s_val = 4 if tdt == torch.float32 else 8
+    _, t_color = timed_call(torch, lambda: css.css_color(xyz, box, R_CUT))
     nnz = ws.H.nnz
-    bytes_alg = nnz * (s_val + 4) + 4 * (ws.n + 1) + 2 * ws.n * b * s_val
-    achieved = bytes_alg / t_spmm / 1e9
+    big = ws.n >= 10 ** 6
+    roof = spmm_roofline(css, H, ws.n, nnz, b, tdt,
+                         "HBM-streaming (working set far above the 256 MB last-level cache)" if big else
+                         "effective (MALL-resident): the 10k working set fits the 256 MB last-level cache",
+                         info["spmm_kernel"] == "grouped")
+    roof["traffic"] = measured_traffic(name) if roof["grouped"] else None
+    roof["kernel_sha256_16"] = kernel_hash()
 
     out = {
         "metric": "orbital*Krylov-steps/s (P-build incl. colouring)",
         "value": ws.n * v_eff / dt,
         "unit": "orbital*steps/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": dt * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if wl["prec"] == "fp32" else "f64",
+        "dtype_detail": ("H and Krylov blocks FP32; SpMM FP32 (FP32 MFMA, FP32 accumulation); Gram and block "
+                         "updates on BF16/FP16 MFMA with operands split in 2-3 parts (FP32-accurate terms), "
+                         "FP32 partial sums reduced in FP64; Cholesky, T, subspace solve, gather, sums FP64")
+        if wl["prec"] == "fp32" else "FP64 throughout (FP64 MFMA for the block products)",
         "data": "synthetic",
         "config": {"workload": f"water {wl['n_mol']} H2O ({ws.n} orbitals), {wl['prec']} blocks, depth {depth}",
                    "n_orbitals": ws.n, "nnz_H": nnz, "nnz_P": state["nnz_p"], "n_colors": b,
                    "depth": depth, "depth_eff": v_eff, "kT": KT, "mu": mu, "r_cut": R_CUT,
-                   "flags": flags},
+                   "flags": flags, "reorth": "full" if flags & css.REORTH_FULL else "local"},
         "phases_ms": {**info["t_phase_ms"], "colour_probe_total": t_color * 1e3,
                       "colour_rounds": state["rounds"]},
         "trace": state["trace"], "e_band": state["e_band"], "trace_krylov": info["trace_krylov"],
-        "roofline": {"bound": "hbm", "kernel": "k_spmm_grp" if grouped else "k_spmm_csr", "achieved": achieved,
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": measured_traffic(args.workload) if grouped else None,
-                     "bytes_per_launch": bytes_alg, "avg_launch_us": t_spmm * 1e6,
-                     "kernel_sha256_16": kernel_hash()},
+        "idem_defect_per_electron": info["idem_defect"] / state["trace"],
+        "roofline": roof,
     }
+    if tuning is not None:
+        out["tuning"] = tuning
+    # loss of orthogonality of the basis the timed step builds (an extra, untimed call)
+    color, bb, p_rp, p_col, _, sign = colour()
+    _, _, _, dinfo = css.css_density_matrix(H, color, sign, bb, mu, KT, depth, p_rp, p_col, flags | css.DIAG_ORTHO)
+    out["ortho_err"] = dinfo["ortho_err"]
+    del dinfo
 
-    if args.workload == "10k" and not args.no_extras:
-        # the energy-weighted estimate P_E = (H X) r^T on the pattern: its cost over a
-        # density call alone (one more sparse x block product and gather)
-        color, bb, p_rp, p_col, _ = css.css_color(xyz, box, R_CUT)
-        sign, _ = css.css_build_probes(color, bb, wl["seed"])
+    if extras:
         dm_args = (H, color, sign, bb, mu, KT, depth, p_rp, p_col, flags)
-        times = {}
-        for name, fn in (("density", css.css_density_matrix), ("energy", css.css_energy_density_matrix)):
-            fn(*dm_args)
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            r = fn(*dm_args)
-            torch.cuda.synchronize()
-            times[name] = time.perf_counter() - t
+        _, t_d = timed_call(torch, lambda: css.css_density_matrix(*dm_args))
+        r, t_e = timed_call(torch, lambda: css.css_energy_density_matrix(*dm_args))
         _, _, _, _, pe_trace, einfo = r
-        out["energy_weighted"] = {"extra_ms": (times["energy"] - times["density"]) * 1e3,
-                                  "density_ms": times["density"] * 1e3, "energy_ms": times["energy"] * 1e3,
+        out["energy_weighted"] = {"extra_ms": (t_e - t_d) * 1e3, "density_ms": t_d * 1e3, "energy_ms": t_e * 1e3,
                                   "pe_trace": pe_trace, "e_band_krylov": einfo["e_band_krylov"]}
         del r
-        # mu for the workload's electron count from the Krylov quadrature (one Lanczos
-        # pass, dense diagonalisation of T, bisection on the device)
-        css.css_find_mu(H, color, sign, bb, float(ws.n_electrons), KT, depth, flags)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        mu_k, count_k, minfo = css.css_find_mu(H, color, sign, bb, float(ws.n_electrons), KT, depth, flags)
-        torch.cuda.synchronize()
-        out["mu_search"] = {"ms": (time.perf_counter() - t) * 1e3, "mu": mu_k, "count": count_k,
-                            "n_electrons": ws.n_electrons, "mu_used": mu,
-                            "phase_ms": minfo["t_phase_ms"], "count_evaluations": minfo["n_evals"]}
+        # mu for the workload's electron count from the Krylov quadrature
+        (mu_k, count_k, minfo), t_mu = timed_call(
+            torch, lambda: css.css_find_mu(H, color, sign, bb, float(ws.n_electrons), KT, depth, flags))
+        out["mu_search"] = {"ms": t_mu * 1e3, "mu": mu_k, "count": count_k, "n_electrons": ws.n_electrons,
+                            "mu_used": mu, "phase_ms": minfo["t_phase_ms"], "count_evaluations": minfo["n_evals"]}
         # S^(-1/2) of the overlap matrix on the same pattern (non-orthogonal basis), v^s = 10
         So = synth.water_overlap(ws)
         Sdev = css.DeviceCSR.from_host(So.row_ptr, So.col, So.val, dev, torch.float32)
         inv_args = (Sdev, color, sign, bb, 10, p_rp, p_col, flags)
-        css.css_inv_sqrt_overlap(*inv_args)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        _, ytr, _, yinfo = css.css_inv_sqrt_overlap(*inv_args)
-        torch.cuda.synchronize()
-        out["inv_sqrt_overlap"] = {"ms": (time.perf_counter() - t) * 1e3, "depth": 10,
-                                   "depth_eff": yinfo["depth_eff"], "trace": ytr, "phase_ms": yinfo["t_phase_ms"]}
-        css.css_transform_hamiltonian(H, *inv_args)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        y_s, hp_s, _, _, _ = css.css_transform_hamiltonian(H, *inv_args)
-        torch.cuda.synchronize()
-        out["transform_hamiltonian"] = {"ms": (time.perf_counter() - t) * 1e3, "depth": 10}
+        (_, ytr, _, yinfo), t_y = timed_call(torch, lambda: css.css_inv_sqrt_overlap(*inv_args))
+        out["inv_sqrt_overlap"] = {"ms": t_y * 1e3, "depth": 10, "depth_eff": yinfo["depth_eff"], "trace": ytr,
+                                   "phase_ms": yinfo["t_phase_ms"]}
+        (y_s, hp_s, _, _, _), t_h = timed_call(torch, lambda: css.css_transform_hamiltonian(H, *inv_args))
+        out["transform_hamiltonian"] = {"ms": t_h * 1e3, "depth": 10}
         # density matrix of the non-orthogonal basis from that S^(-1/2) and H'
         no_args = (css.pattern_csr(p_rp, p_col, hp_s), css.pattern_csr(p_rp, p_col, y_s), color, sign, bb, mu, KT,
                    depth, p_rp, p_col, flags)
-        css.css_density_matrix_nonorth(*no_args, H=H, S=Sdev)
+        (_, e_no, n_no, _, ninfo), t_n = timed_call(
+            torch, lambda: css.css_density_matrix_nonorth(*no_args, H=H, S=Sdev))
+        out["density_nonorth"] = {"ms": t_n * 1e3, "depth_eff": ninfo["depth_eff"], "n_elec": n_no, "e_band": e_no,
+                                  "phase_ms": ninfo["t_phase_ms"]}
+        del y_s, hp_s, no_args, Sdev
+
+    if depth60:
+        # the same input at Krylov depth 60 (mixed, timed) against FP64 at depth 60
+        state.clear()
+        step(flags, 60)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        _, e_no, n_no, _, ninfo = css.css_density_matrix_nonorth(*no_args, H=H, S=Sdev)
+        step(flags, 60)
         torch.cuda.synchronize()
-        out["density_nonorth"] = {"ms": (time.perf_counter() - t) * 1e3, "depth_eff": ninfo["depth_eff"],
-                                  "n_elec": n_no, "e_band": e_no, "phase_ms": ninfo["t_phase_ms"]}
-        del y_s, hp_s, no_args
-        del Sdev
+        t60 = time.perf_counter() - t
+        p60, e60, i60 = state["p_val"].double().cpu(), state["e_band"], state["info"]
+        # at depth 60 local re-orthogonalisation in FP64 loses orthogonality (max|Q^T Q - I|
+        # about 1e-2 at 10^4 molecules), so the comparator re-orthogonalises fully
+        f64 = flags_for("fp64", reorth="full")
+        H64 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, dev, torch.float64)
+        (q64, e64, _, i64), t64 = timed_call(
+            torch, lambda: css.css_density_matrix(H64, color, sign, bb, mu, KT, 60, p_rp, p_col, f64 | css.DIAG_ORTHO))
+        out["depth60"] = {"ms_per_step": t60 * 1e3, "value": ws.n * i60["depth_eff"] / t60,
+                          "depth_eff": i60["depth_eff"], "phases_ms": i60["t_phase_ms"],
+                          "fp64_density_ms": t64 * 1e3, "fp64_mode": "FP64, full re-orthogonalisation, stored basis",
+                          "fp64_ortho_err": i64["ortho_err"],
+                          "mixed_vs_fp64_max_abs_dP": float(torch.max(torch.abs(q64.cpu() - p60))),
+                          "mixed_vs_fp64_rel_dE": abs(e60 - e64) / abs(e64),
+                          "idem_defect_per_electron": i60["idem_defect"] / state["trace"]}
+        del H64, q64, p60
+        print(f"[bench] depth 60: {t60 * 1e3:.1f} ms mixed, {t64 * 1e3:.1f} ms FP64", file=sys.stderr, flush=True)
 
-    if wl["prec"] == "fp32" and not args.no_fp64:
+    if wl["prec"] == "fp32" and fp64:
+        step()
         p_mixed = state["p_val"].double().cpu()
         e_mixed = state["e_band"]
         del state["p_val"]
-        H = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, dev, torch.float64)
+        H64 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, dev, torch.float64)
         f64 = flags_for("fp64", wl["fp64_twopass"])
         res = {}
 
         def step64():
-            color, bb, p_rp, p_col, _ = css.css_color(xyz, box, R_CUT)
-            sign, _ = css.css_build_probes(color, bb, wl["seed"])
-            res["p"], res["e"], _, res["info"] = css.css_density_matrix(H, color, sign, bb, mu, KT, depth, p_rp,
-                                                                         p_col, f64)
-        step64()
-        torch.cuda.synchronize()
-        t64 = time.perf_counter()
-        step64()
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t64
+            c, b64, rp64, col64, _, sg = colour()
+            res["p"], res["e"], _, res["info"] = css.css_density_matrix(H64, c, sg, b64, mu, KT, depth, rp64, col64,
+                                                                         f64)
+        _, t64 = timed_call(torch, step64)
         dp = float(torch.max(torch.abs(res["p"].cpu() - p_mixed)))
         out["fp64_ms_per_step"] = t64 * 1e3
         out["fp64_flags"] = f64
+        out["fp64_mode"] = ("FP64, local re-orthogonalisation (previous two blocks), "
+                            + ("two-pass (no stored basis)" if wl["fp64_twopass"] else "stored basis"))
         out["fp64_phases_ms"] = res["info"]["t_phase_ms"]
         out["mixed_vs_fp64_speedup"] = t64 / dt
         out["mixed_vs_fp64_max_abs_dP"] = dp
         out["mixed_vs_fp64_rel_dE"] = abs(e_mixed - res["e"]) / abs(res["e"])
-        del H, res
+        del H64, res
 
-    if args.workload == "1m":
-        args.no_cpu_baseline = True        # the oracle at this size takes hours; the default run reports it
-    if not args.no_cpu_baseline:
+    if cpu:
         print("[bench] timing the oracle on the CPU sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(ws, depth, mu)       # the whole step (about 15 s on 16 cores)
+    css.reset_tuning()
+    del H, xyz, state
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="10k", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 10k-only extra entry points (energy-weighted, mu, S^-1/2, H', "
+                         "non-orthogonal) after the timed region")
+    ap.add_argument("--no-sub", action="store_true",
+                    help="10k: skip the sub-records (depth 60, 10^6 molecules, 48-box batch)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch choices")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_20918_amd import css
+    if not torch.cuda.is_available():
+        print("no ROCm device visible", file=sys.stderr)
+        sys.exit(1)
+    css.load()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.workload == "batch48":
+        print(json.dumps(run_batch(args)), flush=True)
+        return
+    name = args.workload
+    sub = name == "10k" and not args.no_sub
+    out = measure_single(name, args.steps, args.warmup, extras=name == "10k" and not args.no_extras,
+                         fp64=not args.no_fp64, tune=not args.no_tune,
+                         cpu=not args.no_cpu_baseline and name != "1m", depth60=sub)
+    if sub:
+        # the 10^6-molecule P-build (mixed, then FP64 two-pass) and its SpMM roofline
+        one_m = measure_single("1m", 1, 1, extras=False, fp64=True, tune=not args.no_tune, cpu=False)
+        out["roofline_1m"] = one_m.pop("roofline")
+        keep = ("value", "ms_per_step", "config", "phases_ms", "trace", "e_band", "idem_defect_per_electron",
+                "ortho_err", "tuning", "fp64_ms_per_step", "fp64_mode", "fp64_phases_ms", "mixed_vs_fp64_speedup",
+                "mixed_vs_fp64_max_abs_dP", "mixed_vs_fp64_rel_dE")
+        out["1m"] = {k: one_m[k] for k in keep if k in one_m}
+        # 48 uneven boxes in one batched call against one call per box
+        bargs = argparse.Namespace(steps=2, warmup=1)
+        b48 = run_batch(bargs)
+        out["batch48"] = {k: b48[k] for k in ("value", "ms_per_step", "colour_ms_per_step", "batched_density_ms",
+                                             "sequential_density_ms", "batched_vs_sequential_density",
+                                             "batched_equals_sequential_bitwise") if k in b48}
+        out["batch48"]["workload"] = b48["config"]["workload"]
     print(json.dumps(out), flush=True)
 
 

@@ -121,6 +121,11 @@ typedef struct {
     double e_band_krylov;     /* sum_k lambda_k g f(lambda_k) w_k */
     double t_phase_ms[6];     /* lanczos, subspace solve, F padding, reconstruction, gather, total */
     double ortho_err;         /* max |Q^T Q - I| of the Krylov basis with CSS_DIAG_ORTHO, else NaN */
+    double idem_defect;       /* css_density_matrix / css_energy_density_matrix: Tr P - ||P||_F^2 / g
+                                 over the returned pattern values (g = spin_deg); for the Fermi-Dirac
+                                 operator of Eq.(1), P = g f(H), it is g sum_k f_k (1 - f_k) >= 0,
+                                 zero for a projector and small at small kT in a gapped system.
+                                 NaN elsewhere */
 } css_info;
 
 /*

@@ -69,6 +69,14 @@ def band_energy(H, p_val, p_row_ptr, p_col) -> float:
     return float(np.sum(h * p_val))
 
 
+def idempotency_defect(p_val, p_row_ptr, p_col, spin_deg=2.0) -> float:
+    """Tr P - ||P||_F^2 / g over the pattern. For symmetric P this is Tr P - Tr(P^2)/g;
+    for the Fermi-Dirac operator P = g f(H) of Eq.(1) it equals g sum_k f_k (1 - f_k),
+    zero when P/g is a projector (an insulator at zero temperature) and small at
+    small kT in a gapped system."""
+    return trace_of(p_val, p_row_ptr, p_col) - float(np.sum(np.asarray(p_val) ** 2)) / spin_deg
+
+
 def density_matrix(H, color, sign, n_colors, mu, kT, depth, p_row_ptr, p_col,
                    spin_deg=2.0, reorth=REORTH_FULL, cholqr2=True, symmetrize_p=True,
                    eig_driver="evd"):
@@ -88,6 +96,7 @@ def density_matrix(H, color, sign, n_colors, mu, kT, depth, p_row_ptr, p_col,
         "lanczos": lz, "v_eff": lz.v_eff, "breakdown": lz.breakdown,
         "trace": trace_of(p_val, p_row_ptr, p_col),
         "e_band": band_energy(H, p_val, p_row_ptr, p_col),
+        "idem": idempotency_defect(p_val, p_row_ptr, p_col, spin_deg),
         "trace_krylov": trace_k, "e_band_krylov": e_k,
         "asym_max": float(np.max(np.abs(p_raw - p_sym))) if p_raw.size else 0.0,
     }

@@ -472,6 +472,18 @@ __global__ __launch_bounds__(256) void k_energy(int n, const int32_t* __restrict
     if (lane == 0) row_e[m] = e;
 }
 
+// One wavefront per pattern row: sum of P_mn^2 over the row (fixed order per row).
+__global__ __launch_bounds__(256) void k_row_sq(int n, const int64_t* __restrict__ prp,
+                                                const double* __restrict__ pval, double* __restrict__ row_sq) {
+    const int lane = threadIdx.x & 63;
+    const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (m >= n) return;
+    double q = 0.0;
+    for (int64_t t = prp[m] + lane; t < prp[m + 1]; t += 64) q += pval[t] * pval[t];
+    for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
+    if (lane == 0) row_sq[m] = q;
+}
+
 // Deterministic two-level sum: block b sums v[b*chunk ...) in a fixed tree.
 __global__ void k_block_sum(const double* __restrict__ v, int64_t n, int64_t chunk, double* __restrict__ out) {
     __shared__ double sm[256];
@@ -788,6 +800,9 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     det_sum(rt, lz.n, bf.tmp + 2 * kSumBlocks, bf.res + 0, s);
     det_sum(re, lz.n, bf.tmp + 3 * kSumBlocks, bf.res + 1, s);
     det_max(ra, lz.n, bf.tmp, bf.res + 4, s);
+    // ||P||_F^2 on the pattern for the idempotency defect (rows of ra reused in stream order)
+    k_row_sq<<<grid_for(lz.n, 4), 256, 0, s>>>(lz.n, p_row_ptr, p_val, ra);
+    det_sum(ra, lz.n, bf.tmp + kSumBlocks, bf.res + 6, s);
     if (pe_val) {
         // energy-weighted estimate: X_E = H X, gathered as P (the rows' scratch is reused
         // after the reductions above, in stream order)
@@ -830,7 +845,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
     if (timed) CSS_HIP_TRY(hipEventRecord(ev[5], s));
     double hres[8];
     int hinfo[2] = {0, 0};
-    CSS_HIP_TRY(hipMemcpyAsync(hres, bf.res, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipMemcpyAsync(hres, bf.res, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
     CSS_HIP_TRY(hipMemcpyAsync(hinfo, bf.flags + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     CSS_HIP_TRY(hipStreamSynchronize(s));
     CSS_HIP_TRY(hipGetLastError());
@@ -847,6 +862,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
         info->spmm_kernel = bf.lz.use_grp ? 1 : 0;
         info->min_diag_r = md;
         info->ortho_err = ortho;
+        info->idem_defect = fn == kFnFermi ? hres[0] - hres[6] / spin_deg : NAN;
         info->asym_max = hres[4];
         info->n_poles = npoles;
         info->trace_krylov = hres[2];
@@ -1016,6 +1032,7 @@ css_status nonorth_run(const css_csr* Hp, const css_csr* Sih, const css_csr* He,
         info->spmm_kernel = bf.lz.use_grp ? 1 : 0;
         info->min_diag_r = md;
         info->ortho_err = ortho;
+        info->idem_defect = NAN;      // P S P = P is the non-orthogonal relation; not measured
         info->asym_max = hres[4];
         info->n_poles = npoles;
         info->trace_krylov = hres[2];
@@ -1297,6 +1314,7 @@ extern "C" css_status css_find_mu(const css_csr* H, const int32_t* color, const 
         info->n_evals = evals;
         info->min_diag_r = md;
         info->ortho_err = NAN;
+        info->idem_defect = NAN;
         info->trace_krylov = hres[1];
         for (int k = 0; k < 3; ++k) {
             float ms = 0.f;

@@ -567,6 +567,7 @@ extern "C" css_status css_block_lanczos(const css_csr* H, const int32_t* color, 
         info->spmm_kernel = bf.use_grp ? 1 : 0;
         info->min_diag_r = md;
         info->ortho_err = ortho;
+        info->idem_defect = NAN;
         info->t_phase_ms[0] = ms;
         info->t_phase_ms[5] = ms;
     } else {

@@ -58,13 +58,15 @@ class InfoStruct(ctypes.Structure):
                 ("n_poles", ctypes.c_int32), ("spmm_kernel", ctypes.c_int32), ("n_evals", ctypes.c_int32),
                 ("min_diag_r", ctypes.c_double), ("asym_max", ctypes.c_double),
                 ("trace_krylov", ctypes.c_double), ("e_band_krylov", ctypes.c_double),
-                ("t_phase_ms", ctypes.c_double * 6), ("ortho_err", ctypes.c_double)]
+                ("t_phase_ms", ctypes.c_double * 6), ("ortho_err", ctypes.c_double),
+                ("idem_defect", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {"depth_eff": self.depth_eff, "n_colors": self.n_colors, "breakdown": self.breakdown,
                 "n_poles": self.n_poles, "spmm_kernel": "grouped" if self.spmm_kernel else "csr",
                 "min_diag_r": self.min_diag_r, "asym_max": self.asym_max, "trace_krylov": self.trace_krylov,
                 "e_band_krylov": self.e_band_krylov, "ortho_err": self.ortho_err,
+                "idem_defect": self.idem_defect,
                 "t_phase_ms": {k: self.t_phase_ms[i] for i, k in
                                enumerate(["lanczos", "subspace", "f_pad", "reconstruction", "gather", "total"])}}
 

@@ -251,6 +251,8 @@ def test_density_fp64_parity(M, seed, depth, subspace):
     assert abs(info["trace_krylov"] - ref["trace_krylov"]) <= 1e-9
     assert abs(info["e_band_krylov"] - ref["e_band_krylov"]) <= 1e-9
     assert abs(info["asym_max"] - ref["asym_max"]) <= 1e-10
+    # idempotency defect Tr P - ||P||_F^2 / g of the returned P
+    assert abs(info["idem_defect"] - ref["idem"]) <= 1e-10 * abs(ref["trace"])
 
 
 @pytest.mark.parametrize("subspace", ["poles", "eig"])
@@ -270,9 +272,12 @@ def test_density_fp32_parity(M, seed, depth):
     ws, ref, p, e_band, trace, info = _dm_case(M, seed, depth, FP32_FLAGS, "full")
     err = np.max(np.abs(p - ref["p_val"]))
     rel_e = abs(e_band - ref["e_band"]) / abs(ref["e_band"])
-    print(f"  fp32 max|dP|={err:.3e} rel dE={rel_e:.3e}", flush=True)
+    d_idem = abs(info["idem_defect"] - ref["idem"]) / abs(ref["trace"])
+    print(f"  fp32 max|dP|={err:.3e} rel dE={rel_e:.3e} idem {info['idem_defect']:.6e} "
+          f"(oracle {ref['idem']:.6e}, diff/Tr {d_idem:.2e})", flush=True)
     assert err <= 1e-5
     assert rel_e <= 1e-7
+    assert d_idem <= 1e-7
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])

@@ -161,6 +161,10 @@ def test_pipeline_reduces_to_dense_when_b_equals_n():
     P = D.dense_fermi_dm(H, mu, kT)
     assert np.max(np.abs(r["p_val"] - P[D.pattern_rows(rp), col])) < 1e-12
     assert np.max(np.abs(r["p_raw"] - r["p_val"])) < 1e-12
+    # full pattern: Tr P - Tr(P^2)/g of g f(H) is g sum_k f(eps_k)(1 - f(eps_k))
+    f = fermi(np.linalg.eigvalsh(H.toarray()), mu, kT)
+    assert abs(r["idem"] - 2.0 * np.sum(f * (1.0 - f))) < 1e-12
+    assert r["idem"] > 0.1
 
 
 def test_pipeline_equals_css_exact_when_krylov_space_is_exhausted():
@@ -189,9 +193,11 @@ def test_pipeline_closed_form_for_scaled_identity():
     H = sp.identity(n, format="csr") * c
     mu, kT = -0.4, 0.01
     r = D.density_matrix(H, color, probe_signs(n, 2), b, mu, kT, 5, rp, col)
-    expect = np.where(D.pattern_rows(rp) == col, 2.0 * fermi(np.array([c]), mu, kT)[0], 0.0)
+    f = fermi(np.array([c]), mu, kT)[0]
+    expect = np.where(D.pattern_rows(rp) == col, 2.0 * f, 0.0)
     assert r["v_eff"] == 1
     assert np.max(np.abs(r["p_val"] - expect)) < 1e-14
+    assert abs(r["idem"] - 2.0 * n * f * (1.0 - f)) < 1e-12
 
 
 def test_pipeline_invariants_on_water():
