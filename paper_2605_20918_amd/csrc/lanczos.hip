@@ -76,17 +76,20 @@ __global__ void k_max_reduce(const double* __restrict__ v, int64_t n, double* __
     if (threadIdx.x == 0) *out = sm[0];
 }
 
-// acc[0] = max(acc[0], max |M_t[r][c] - [t == diag and r == c]| over t < cnt and
-// r, c < b), M_t = M + t*ld*ld; one work-group. A NaN entry makes the result NaN.
-__global__ __launch_bounds__(256) void k_ortho_max(const double* __restrict__ M, int cnt, int b, int ld, int diag,
-                                                   double* __restrict__ acc) {
+// *acc = max(*acc, max |M_t[r][c] - [t == diag and r == c]| over r, c < b) for
+// t = blockIdx.y, M_t = M + t*ld*ld. The maximum of non-negative doubles is taken on
+// their bit patterns (an order-independent atomic maximum, so the result does not
+// depend on the order of the work-groups); a NaN entry makes the result NaN.
+__global__ __launch_bounds__(256) void k_ortho_max(const double* __restrict__ M, int b, int ld, int diag,
+                                                   unsigned long long* __restrict__ acc) {
     __shared__ double sm[256];
+    const int t = blockIdx.y;
     const int64_t per = (int64_t)b * b;
+    const double* Mt = M + t * (int64_t)ld * ld;
     double m = 0.0;
-    for (int64_t i = threadIdx.x; i < cnt * per; i += 256) {
-        const int t = static_cast<int>(i / per);
-        const int r = static_cast<int>((i % per) / b), c = static_cast<int>(i % b);
-        double v = M[t * (int64_t)ld * ld + (int64_t)r * ld + c];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < per; i += (int64_t)gridDim.x * 256) {
+        const int r = static_cast<int>(i / b), c = static_cast<int>(i % b);
+        double v = Mt[(int64_t)r * ld + c];
         if (t == diag && r == c) v -= 1.0;
         v = fabs(v);
         if (!(v <= m)) m = (m != m) ? m : v;
@@ -100,10 +103,7 @@ __global__ __launch_bounds__(256) void k_ortho_max(const double* __restrict__ M,
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double a = acc[0], v = sm[0];
-        acc[0] = (a != a || v != v) ? NAN : fmax(a, v);
-    }
+    if (threadIdx.x == 0) atomicMax(acc, static_cast<unsigned long long>(__double_as_longlong(fabs(sm[0]))));
 }
 
 template <typename S, typename D>
@@ -394,7 +394,8 @@ css_status ortho_err_t(const LzPlan& p, const LzBufs& bf, int v_eff, hipStream_t
             // out[t] = Q_{t0+t}^T Q_j; no state flag, so a breakdown does not skip it
             gram_blocks_launch<T>(static_cast<const T*>(slot_ptr(p, bf, t0)), tall, cnt, Qj, p.Np, p.ld, false,
                                   p.partial_mats, bf.partial, bf.stage, mat, 0, nullptr, s);
-            k_ortho_max<<<1, 256, 0, s>>>(bf.stage, cnt, p.b, p.ld, j - t0, acc);
+            k_ortho_max<<<dim3(grid_for((int64_t)p.b * p.b, 256 * 8), cnt), 256, 0, s>>>(
+                bf.stage, p.b, p.ld, j - t0, reinterpret_cast<unsigned long long*>(acc));
         }
     }
     CSS_HIP_TRY(hipGetLastError());
