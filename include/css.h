@@ -521,7 +521,8 @@ css_status css_fermi_poles(int32_t depth, double* kappa, double* weight, int32_t
  * when a kernel is launched; zero fields select the built-in defaults. No choice
  * changes the arithmetic of the method, only the launch shape and hence the order
  * in which FP32 partial sums are added (results stay deterministic for a fixed
- * tuning).
+ * tuning); cholqr2_series selects between two evaluations of the second CholQR
+ * factor that agree to below the working precision's rounding.
  *   spmm_kernel  sparse x block product: 0 automatic (the 16-row grouped MFMA kernel
  *                where H's row groups are dense enough, else the row-parallel CSR
  *                kernel), 1 16-row groups, 2 the CSR kernel
@@ -530,6 +531,11 @@ css_status css_fermi_poles(int32_t depth, double* kappa, double* weight, int32_t
  *   gram_chunks  FP32 split Gram products: row chunks sized for about this many
  *                work-groups per compute unit, 0 (= 1), 1, 2, 4
  *   update_rows  FP32 split block updates: rows per work-group, 0 (= 128), 64, 128
+ *   cholqr2_series  second Cholesky QR pass (CSS_CHOLQR2), whose Gram is I + E with E
+ *                of the first pass's loss of orthogonality: 0 (= 1), 1 a second-order
+ *                series in E when max|E| <= 2e-6 (FP64) or 1e-4 (FP32), so that the
+ *                neglected |E|^3 is below rounding, else the factorisation; 2 always the
+ *                factorisation
  */
 typedef struct {
     int32_t spmm_kernel;
@@ -537,7 +543,8 @@ typedef struct {
     int32_t spmm_depth;
     int32_t gram_chunks;
     int32_t update_rows;
-    int32_t reserved[3];
+    int32_t cholqr2_series;
+    int32_t reserved[2];
 } css_tuning;
 
 /* Sets (t != NULL) or resets to the defaults (t == NULL) the process-wide tuning.

@@ -65,6 +65,7 @@ struct Tuning {
     int depth = 0;         // SpMM: k-steps in flight per wave, 4 or 8 (default 4)
     int gram_chunks = 0;   // FP32 split Gram: work-groups per compute unit and product set, 1, 2 or 4 (default 1)
     int update_rows = 0;   // FP32 split block update: rows per work-group, 64 or 128 (default 128)
+    int chol_series = 0;   // second CholQR factor: 0 or 1 series near the identity, 2 always factorise
 };
 Tuning tuning();
 

@@ -77,6 +77,12 @@ void update_correction_launch(T* OUT, const T* IN, double alpha, const T* X, int
 void chol_inv_launch(const double* G, int b, int ld, const double* tau, double* R, double* Rinv,
                      double* scratch, int* state, int step, double* min_diag, hipStream_t s);
 
+// chol_inv_launch without a threshold for G near the identity: a second-order series
+// (R^T R = G + O(|E|^3), R^-1 to the same order, E = G - I) when max |E_ij| <= thresh,
+// the blocked factorisation otherwise (b <= 128; larger b always factorise).
+void chol_inv_near_identity_launch(const double* G, int b, int ld, double thresh, double* R, double* Rinv,
+                                   double* scratch, int* state, int step, double* min_diag, hipStream_t s);
+
 // A += (C + C^T)/2 (ld x ld)
 void sym_add_launch(const double* C, double* A, int ld, const int* state, hipStream_t s);
 

@@ -965,16 +965,13 @@ __global__ __launch_bounds__(256) void k_chol_inv_reg(const double* __restrict__
 __device__ inline double lane_bcast(double v, int src) { return __shfl(v, src, 64); }
 
 template <int NB>
-__global__ __launch_bounds__(256) void k_chol_inv_blk(const double* __restrict__ G, int b, int ld,
-                                                      const double* __restrict__ tau_p, double* __restrict__ R,
-                                                      double* __restrict__ Rinv, int* state, int step,
-                                                      double* __restrict__ min_diag) {
+__device__ __forceinline__ void chol_inv_blk(const double* __restrict__ G, int b, int ld, const double* __restrict__ tau_p,
+                             double* __restrict__ R, double* __restrict__ Rinv, int* state, int step,
+                             double* __restrict__ min_diag, double* chol_lds) {
     constexpr int N = 16 * NB, W = N + 1;
-    extern __shared__ double chol_lds[];
     double* M = chol_lds;                 // N x W
     double* XD = chol_lds + N * W;        // NB x 256 (D layout)
     __shared__ int sfail;
-    if (state[0]) return;
     typedef MF<double> Mf;
     const int t = threadIdx.x, l = t & 63, wv = t >> 6, lr = l >> 4, lc = l & 15;
     const double tau = tau_p ? *tau_p : 0.0;
@@ -1114,8 +1111,10 @@ __global__ __launch_bounds__(256) void k_chol_inv_blk(const double* __restrict__
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
     __syncthreads();
-    for (int idx = t; idx < ld * ld; idx += 256) {
-        const int i = idx / ld, j = idx % ld;
+    // ld == N (checked by the launcher): constant index arithmetic
+#pragma unroll 4
+    for (int idx = t; idx < N * N; idx += 256) {
+        const int i = idx / N, j = idx % N;
         double rv = 0.0, xv = 0.0;
         if (i < b && j < b && j >= i) {
             rv = M[i * W + j];
@@ -1129,6 +1128,153 @@ __global__ __launch_bounds__(256) void k_chol_inv_blk(const double* __restrict__
         }
         R[idx] = rv;
         Rinv[idx] = xv;
+    }
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_chol_inv_blk(const double* __restrict__ G, int b, int ld,
+                                                      const double* __restrict__ tau_p, double* __restrict__ R,
+                                                      double* __restrict__ Rinv, int* state, int step,
+                                                      double* __restrict__ min_diag) {
+    extern __shared__ double chol_lds[];
+    if (state[0]) return;
+    chol_inv_blk<NB>(G, b, ld, tau_p, R, Rinv, state, step, min_diag, chol_lds);
+}
+
+// Cholesky G = R^T R and X = R^-1 for G = I + E near the identity (the second pass of
+// CholQR2, where E is of the order of the first pass's loss of orthogonality). With
+// U1 = up(E) and U = U1 + up(-U1^T U1), up(S) = strict upper part of S plus half its
+// diagonal, R = I + U is upper triangular and R^T R = G + O(|E|^3); X = I - U + U^2
+// has X R = I + O(|E|^3). Used when max |E_ij| <= thresh (a bound that keeps |E|^3
+// below the rounding of the working precision); otherwise, and for a non-finite E, the
+// blocked factorisation above runs. The two products are on FP64 MFMA, U in LDS.
+template <int NB>
+__global__ __launch_bounds__(256) void k_chol_inv_near_id(const double* __restrict__ G, int b, int ld,
+                                                          double thresh, double* __restrict__ R,
+                                                          double* __restrict__ Rinv, int* state, int step,
+                                                          double* __restrict__ min_diag) {
+    constexpr int N = 16 * NB, W = N + 1, NT = NB * (NB + 1) / 2, TPW = (NT + 3) / 4;
+    extern __shared__ double chol_lds[];
+    double* M = chol_lds;                 // N x W: U1, then U
+    __shared__ double red[256];
+    if (state[0]) return;
+    typedef MF<double> Mf;
+    const int t = threadIdx.x, l = t & 63, wv = t >> 6, lr = l >> 4, lc = l & 15;
+    // U1 = up(E) over the upper triangle (zero beyond b) and max |E|; every load is
+    // issued before the first use
+    constexpr int PER = (N * N + 255) / 256;
+    double g[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = t + 256 * q;
+        const int i = e / N, j = e % N;
+        g[q] = (e < N * N && i < b && j < b && j >= i) ? G[(int64_t)i * ld + j] : 0.0;
+    }
+    double emax = 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = t + 256 * q;
+        const int i = e / N, j = e % N;
+        if (e >= N * N) continue;
+        double u = 0.0;
+        if (i < b && j < b && j >= i) {
+            const double ev = g[q] - (i == j ? 1.0 : 0.0);
+            const double a = fabs(ev);
+            if (!(a <= emax)) emax = (emax != emax) ? emax : a;
+            u = i == j ? 0.5 * ev : ev;
+        }
+        M[i * W + j] = u;
+    }
+    // max over the work-group: within each wave by shuffles, then the four wave maxima
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(emax, off);
+        if (!(o <= emax) && emax == emax) emax = o;
+    }
+    if (l == 0) red[wv] = emax;
+    __syncthreads();
+    double gmax = red[0];
+    for (int w2 = 1; w2 < 4; ++w2) {
+        const double o = red[w2];
+        if (!(o <= gmax) && gmax == gmax) gmax = o;
+    }
+    if (!(gmax <= thresh)) {              // uniform: every thread reads the same values
+        __syncthreads();
+        chol_inv_blk<NB>(G, b, ld, nullptr, R, Rinv, state, step, min_diag, chol_lds);
+        return;
+    }
+    // upper tiles (ib <= jb) dealt to the waves: tile q of wave wv is number wv + 4 q
+    int tib[TPW], tjb[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        int n = wv + 4 * q < NT ? wv + 4 * q : NT - 1;          // past the end: not used
+        int ib = 0;
+        while (n >= NB - ib) { n -= NB - ib; ++ib; }
+        tib[q] = ib;
+        tjb[q] = ib + n;
+    }
+    // P = U1^T U1 on the upper tiles, kept in registers across the barrier. A wave's
+    // tiles are independent chains, interleaved over the whole K range so that the LDS
+    // reads of a step are in flight together (terms outside a tile's nonzero range are
+    // zeros of the triangular factor).
+    Mf::acc pt[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) pt[q] = Mf::zero();
+    for (int k4 = 0; k4 < N; k4 += 4)
+#pragma unroll
+        for (int q = 0; q < TPW; ++q)
+            pt[q] = Mf::mma(M[(k4 + lr) * W + 16 * tib[q] + lc], M[(k4 + lr) * W + 16 * tjb[q] + lc], pt[q]);
+    __syncthreads();
+    // U = U1 + up(-P) in place
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        if (wv + 4 * q >= NT) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * tib[q] + lr + 4 * r, j = 16 * tjb[q] + lc;
+            if (j > i) M[i * W + j] -= pt[q][r];
+            else if (j == i) M[i * W + j] -= 0.5 * pt[q][r];
+        }
+    }
+    __syncthreads();
+    // U U on the same tiles, interleaved as above (U[i][k] = 0 for k < i, U[k][j] = 0 for k > j)
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) pt[q] = Mf::zero();
+    for (int k4 = 0; k4 < N; k4 += 4)
+#pragma unroll
+        for (int q = 0; q < TPW; ++q)
+            pt[q] = Mf::mma(M[(16 * tib[q] + lc) * W + k4 + lr], M[(k4 + lr) * W + 16 * tjb[q] + lc], pt[q]);
+    // R = I + U and X = I - U + U U: the upper tiles from the registers, everything else
+    // zero (ld == N); two adjacent entries per store
+#pragma unroll 2
+    for (int e = 2 * t; e < N * N; e += 512) {
+        const int i = e / N, j = e % N;                   // j even, j + 1 in the same row
+        double2 rv, xv;
+        rv.x = (i < b && j < b && j >= i) ? (i == j ? 1.0 : 0.0) + M[i * W + j] : 0.0;
+        rv.y = (i < b && j + 1 < b && j + 1 >= i) ? (i == j + 1 ? 1.0 : 0.0) + M[i * W + j + 1] : 0.0;
+        *reinterpret_cast<double2*>(R + e) = rv;
+        // X entries outside the upper tiles (the strict lower block triangle and
+        // rows/columns beyond b inside the tiles are written by the tile owners)
+        if ((i >> 4) > (j >> 4)) {
+            xv.x = 0.0;
+            xv.y = 0.0;
+            *reinterpret_cast<double2*>(Rinv + e) = xv;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        if (wv + 4 * q >= NT) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * tib[q] + lr + 4 * r, j = 16 * tjb[q] + lc;
+            const bool in = i < b && j < b && j >= i;
+            Rinv[i * N + j] = in ? (i == j ? 1.0 : 0.0) - M[i * W + j] + pt[q][r] : 0.0;
+        }
+    }
+    if (wv == 0) {
+        double d = INFINITY;
+        for (int i = l; i < b; i += 64) d = fmin(d, 1.0 + M[i * W + i]);
+        for (int off = 32; off > 0; off >>= 1) d = fmin(d, __shfl_xor(d, off));
+        if (l == 0) min_diag[step] = d;
     }
 }
 
@@ -1644,9 +1790,25 @@ void gram_blocks_launch<double>(const double* X, int64_t xstride, int nprod, con
 
 size_t chol_scratch_bytes(int b) { return sizeof(double) * ((size_t)b * (b + 1) + b + 8); }
 
+void chol_inv_near_identity_launch(const double* G, int b, int ld, double thresh, double* R, double* Rinv,
+                                   double* scratch, int* state, int step, double* min_diag, hipStream_t s) {
+    if (b <= 128 && ld == 16 * ((b + 15) / 16)) {
+        const int nb = (b + 15) / 16;
+        const size_t lds = sizeof(double) * ((size_t)16 * nb * (16 * nb + 1) + 256 * (size_t)nb);
+        switch (nb) {
+#define CSS_CHOL(NB) case NB: k_chol_inv_near_id<NB><<<1, 256, lds, s>>>(G, b, ld, thresh, R, Rinv, state, step, \
+                                                                         min_diag); return;
+            CSS_CHOL(1) CSS_CHOL(2) CSS_CHOL(3) CSS_CHOL(4) CSS_CHOL(5) CSS_CHOL(6) CSS_CHOL(7) CSS_CHOL(8)
+#undef CSS_CHOL
+            default: break;
+        }
+    }
+    chol_inv_launch(G, b, ld, nullptr, R, Rinv, scratch, state, step, min_diag, s);
+}
+
 void chol_inv_launch(const double* G, int b, int ld, const double* tau, double* R, double* Rinv, double* scratch,
                      int* state, int step, double* min_diag, hipStream_t s) {
-    if (b <= 128) {
+    if (b <= 128 && ld == 16 * ((b + 15) / 16)) {
         const int nb = (b + 15) / 16;
         const size_t lds = sizeof(double) * ((size_t)16 * nb * (16 * nb + 1) + 256 * (size_t)nb);
         switch (nb) {

@@ -250,8 +250,11 @@ struct Step {
             update(Wt, nullptr, 0.0, W, 0, 1, R1inv, 0, false, 1.0);           // Wt = W R1^-1
             if (!replay) {
                 gram(Wt, 0, 1, Wt, bf.G, 0, true, 0);
-                chol_inv_launch(bf.G, p.b, ld, nullptr, bf.R2, R2inv, bf.chol_scratch, bf.state, 2 * idx + 1,
-                                bf.min_diag, s);
+                // Wt^T Wt = I + E, E of the first pass's loss of orthogonality: the series
+                // factorisation when |E|^3 is below the working precision's rounding
+                const double bound = tuning().chol_series == 2 ? -1.0 : (p.fp32 ? 1e-4 : 2e-6);
+                chol_inv_near_identity_launch(bf.G, p.b, ld, bound, bf.R2, R2inv, bf.chol_scratch, bf.state,
+                                              2 * idx + 1, bf.min_diag, s);
                 trmm_upper_launch(bf.R2, bf.R1, Rout, ld, bf.state, s);      // R = R2 R1
             }
             update(Qn, nullptr, 0.0, Wt, 0, 1, R2inv, 0, false, 1.0);          // Qn = Wt R2^-1

@@ -165,13 +165,15 @@ css_status tuning_from(const css_tuning* t, Tuning& v) {
     if (t->spmm_kernel < 0 || t->spmm_kernel > 2 || t->spmm_run < 0 ||
         (t->spmm_depth != 0 && t->spmm_depth != 4 && t->spmm_depth != 8) ||
         (t->gram_chunks != 0 && t->gram_chunks != 1 && t->gram_chunks != 2 && t->gram_chunks != 4) ||
-        (t->update_rows != 0 && t->update_rows != 64 && t->update_rows != 128))
+        (t->update_rows != 0 && t->update_rows != 64 && t->update_rows != 128) || t->cholqr2_series < 0 ||
+        t->cholqr2_series > 2)
         return CSS_E_ARG;
     v.kernel = t->spmm_kernel;
     v.run = t->spmm_run;
     v.depth = t->spmm_depth;
     v.gram_chunks = t->gram_chunks;
     v.update_rows = t->update_rows;
+    v.chol_series = t->cholqr2_series;
     return CSS_OK;
 }
 
@@ -270,5 +272,6 @@ extern "C" css_status css_get_tuning(css_tuning* t) {
     t->spmm_depth = v.depth;
     t->gram_chunks = v.gram_chunks;
     t->update_rows = v.update_rows;
+    t->cholqr2_series = v.chol_series;
     return CSS_OK;
 }

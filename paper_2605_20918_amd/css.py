@@ -88,7 +88,8 @@ class ColorJobStruct(ctypes.Structure):
 
 class TuningStruct(ctypes.Structure):
     _fields_ = [("spmm_kernel", ctypes.c_int32), ("spmm_run", ctypes.c_int32), ("spmm_depth", ctypes.c_int32),
-                ("gram_chunks", ctypes.c_int32), ("update_rows", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("gram_chunks", ctypes.c_int32), ("update_rows", ctypes.c_int32), ("cholqr2_series", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 SPMM_KERNELS = {"auto": 0, "grouped": 1, "csr": 2}
@@ -328,7 +329,7 @@ def css_spmm(H: DeviceCSR, V, b: int, ws=None, out=None):
     return W
 
 
-TUNING_FIELDS = ("spmm_kernel", "spmm_run", "spmm_depth", "gram_chunks", "update_rows")
+TUNING_FIELDS = ("spmm_kernel", "spmm_run", "spmm_depth", "gram_chunks", "update_rows", "cholqr2_series")
 
 
 def _tuning_struct(cfg: dict) -> TuningStruct:

@@ -118,11 +118,13 @@ def test_tuning_roundtrip_and_range_checks():
     lib = css.load()
     css.reset_tuning()
     assert css.get_tuning() == {"spmm_kernel": "auto", "spmm_run": 0, "spmm_depth": 0, "gram_chunks": 0,
-                                "update_rows": 0}
-    css.set_tuning(spmm_kernel="grouped", spmm_run=256, spmm_depth=8, gram_chunks=2, update_rows=64)
+                                "update_rows": 0, "cholqr2_series": 0}
+    css.set_tuning(spmm_kernel="grouped", spmm_run=256, spmm_depth=8, gram_chunks=2, update_rows=64,
+                   cholqr2_series=2)
     assert css.get_tuning() == {"spmm_kernel": "grouped", "spmm_run": 256, "spmm_depth": 8, "gram_chunks": 2,
-                                "update_rows": 64}
-    for bad in ({"spmm_kernel": 3}, {"spmm_run": -1}, {"spmm_depth": 5}, {"gram_chunks": 3}, {"update_rows": 96}):
+                                "update_rows": 64, "cholqr2_series": 2}
+    for bad in ({"spmm_kernel": 3}, {"spmm_run": -1}, {"spmm_depth": 5}, {"gram_chunks": 3}, {"update_rows": 96},
+                {"cholqr2_series": 3}):
         t = css._tuning_struct(bad)
         assert lib.css_set_tuning(ctypes.byref(t)) == 1
     assert css.get_tuning()["spmm_run"] == 256

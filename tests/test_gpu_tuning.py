@@ -17,7 +17,7 @@ FP32_FLAGS = css.PREC_FP32 | css.REORTH_FULL | css.CHOLQR2 | css.SYMMETRIZE
 
 CHOICES = [dict(), dict(spmm_kernel="grouped", spmm_run=64, spmm_depth=8),
            dict(spmm_kernel="grouped", spmm_run=4096, spmm_depth=4), dict(spmm_kernel="csr"),
-           dict(gram_chunks=2, update_rows=64), dict(gram_chunks=4, update_rows=128)]
+           dict(gram_chunks=2, update_rows=64), dict(gram_chunks=4, update_rows=128), dict(cholqr2_series=2)]
 
 
 def setup_module(module):
@@ -70,6 +70,30 @@ def test_density_every_choice_within_mixed_tolerance(cfg):
     assert torch.equal(p1, p2) and e1 == e2
     assert np.max(np.abs(p1.cpu().numpy() - ref["p_val"])) <= 1e-5
     assert abs(e1 - ref["e_band"]) <= 1e-7 * abs(ref["e_band"])
+
+
+@pytest.mark.parametrize("M,seed,depth", [(216, 3, 40), (1000, 20920, 40)])
+def test_series_second_cholqr_factor_equals_factorisation_fp64(M, seed, depth):
+    """FP64: the second CholQR factor by the near-identity series (default) and by the
+    blocked factorisation give the same P to rounding, both at the oracle's 1e-10."""
+    print(f"cholqr2 series M={M}", flush=True)
+    ws, H, rp, col, color, b, sign, mu = water_case(M, seed)
+    ref = D.density_matrix(H, color, sign, b, mu, KT, depth, rp, col, reorth="full")
+    args = (to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, depth, dev_i64(rp), dev_i32(col),
+            css.PREC_FP64 | css.REORTH_FULL | css.CHOLQR2 | css.SYMMETRIZE)
+    css.reset_tuning()
+    p1, e1, _, i1 = css.css_density_matrix(*args)
+    p1 = p1.clone()
+    css.set_tuning(cholqr2_series=2)
+    try:
+        p2, e2, _, i2 = css.css_density_matrix(*args)
+    finally:
+        css.reset_tuning()
+    d = torch.max(torch.abs(p1 - p2)).item()
+    print(f"  series vs factorisation max|dP| {d:.3e}", flush=True)
+    assert d <= 1e-13 and abs(e1 - e2) <= 1e-13 * abs(e1)
+    for p in (p1, p2):
+        assert np.max(np.abs(p.cpu().numpy() - ref["p_val"])) <= 1e-10
 
 
 def test_twopass_replay_bitwise_under_a_tuning():
