@@ -32,10 +32,24 @@ void gram_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, dou
 // OUT must not alias any X_p. stage (scratch): (nprod + 1)*ld*ld doubles. FP32 with
 // ld = 16 NT, 3 <= NT <= 8: the products run on BF16 MFMA with both factors split
 // in three parts (six products, each term as accurate as the FP32 product).
+// out16 (FP32 only, may be nullptr): also a BF16 (nearest-even) copy of OUT, Np x ld.
 template <typename T>
 void update_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, int nprod,
                    const double* S, int64_t sstride, bool trans, double scale, int64_t Np, int ld,
-                   void* stage, const int* state, hipStream_t s);
+                   void* stage, const int* state, hipStream_t s, void* out16 = nullptr);
+
+// out[i] = BF16 (nearest even) of in[i], i < n.
+void bf16_copy_launch(const float* in, void* out, int64_t n, hipStream_t s);
+
+// The re-orthogonalisation correction OUT = alpha IN + sum_p X16_p op(S_p) with the
+// blocks X_p given by their BF16 copies (X16_p = X16 + p xstride, BF16 elements) and
+// the coefficients rounded to one BF16 part: one BF16 MFMA product per term, each
+// within 2^-8 |X||S| of the exact one (for coefficients of the size of a loss of
+// orthogonality, far under FP32 rounding of OUT). stage: as update_launch. Returns
+// false (nothing launched) when ld is not 16, 32, ..., 128.
+bool update_correction_bf16_launch(float* OUT, const float* IN, double alpha, const void* X16, int64_t xstride,
+                                   int nprod, const double* S, int64_t sstride, bool trans, double scale, int64_t Np,
+                                   int ld, void* stage, const int* state, hipStream_t s);
 
 // OUT = alpha*IN + X0 op0(S0) + X1 op1(S1) in one pass over OUT (two products with
 // their own transposition), op_i(S) = scale * (trans_i ? S^T : S). stage: 3*ld*ld

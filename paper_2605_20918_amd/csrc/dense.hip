@@ -354,6 +354,11 @@ constexpr int kSplitK = 32;
 // the parts back to FP32 by shifts (exact), one subtraction each.
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Bits of the BF16 value nearest to x (ties to even).
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+    return __builtin_bit_cast(unsigned short, static_cast<__bf16>(x));
+}
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 template <int NPL>
@@ -460,7 +465,8 @@ template <int MT, int NT, int D, int NPL>
 __global__ __launch_bounds__(256) void k_update_split(float* OUT, const float* IN, double alpha,
                                                       const float* __restrict__ X, int64_t xstride, int nprod,
                                                       const bf16x8* __restrict__ frag, int64_t Np, int ld,
-                                                      const int* __restrict__ state) {
+                                                      const int* __restrict__ state,
+                                                      unsigned short* __restrict__ OUT16) {
     if (state && state[0]) return;
     constexpr int FR = NPL * NT * 64;                     // fragments of one K chunk
     constexpr int PER = (FR + 255) / 256;
@@ -554,8 +560,100 @@ __global__ __launch_bounds__(256) void k_update_split(float* OUT, const float* I
                 const int64_t idx = row * ld + nt * 16 + lc;
                 double v = (double)c[mt][nt][r];
                 if (IN != nullptr && alpha != 0.0) v += alpha * (double)IN[idx];
+                const float o = static_cast<float>(v);
+                OUT[idx] = o;
+                if (OUT16) OUT16[idx] = bf16_bits(o);
+            }
+}
+
+// OUT = alpha IN + sum_p X_p S'_p with X_p given as BF16 values (a rounded copy of an
+// FP32 block) and S'_p as one BF16 part: one 16x16x32 BF16 MFMA per tile and K chunk.
+// For coefficient blocks of the size of a loss of orthogonality (the correction of
+// the re-orthogonalisation), each term is within 2^-8 |X||S| of the exact one, far
+// under FP32 rounding of OUT. Structure as k_update_split (X runs of a K chunk fetched
+// D chunks ahead, fragments double buffered in LDS, branch-free loop).
+template <int MT, int NT, int D>
+__global__ __launch_bounds__(256) void k_update_bf16x(float* OUT, const float* IN, double alpha,
+                                                      const unsigned short* __restrict__ X, int64_t xstride, int nprod,
+                                                      const bf16x8* __restrict__ frag, int64_t Np, int ld,
+                                                      const int* __restrict__ state) {
+    if (state && state[0]) return;
+    constexpr int FR = NT * 64;                           // fragments of one K chunk
+    constexpr int PER = (FR + 255) / 256;
+    __shared__ bf16x8 sB[2][PER * 256];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, lr = l >> 4, lc = l & 15;
+    const int64_t m0 = ((int64_t)blockIdx.x * 4 + w) * (16 * MT);
+    const bool active = m0 < Np;
+    const int64_t mrow = active ? m0 : 0;
+    const int nkc = (ld + kSplitK - 1) / kSplitK;
+    const int total = nprod * nkc;
+    mf_f4 c[MT][NT];
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) c[a][b] = mf_f4{0.f, 0.f, 0.f, 0.f};
+    auto fetch_x = [&](int it, bf16x8 (&x)[MT]) {
+        const int p = it / nkc, k = min((it % nkc) * kSplitK + 8 * lr, ld - 8);
+        const unsigned short* Xp = X + (int64_t)p * xstride + (mrow + lc) * ld + k;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) x[mt] = *reinterpret_cast<const bf16x8*>(Xp + (int64_t)16 * mt * ld);
+    };
+    auto fetch_s = [&](int it, bf16x8 (&reg)[PER]) {
+        const bf16x8* src = frag + (int64_t)it * FR;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) reg[q] = src[min(threadIdx.x + 256 * q, (unsigned)FR - 1)];
+    };
+    auto store_s = [&](int buf, const bf16x8 (&reg)[PER]) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) sB[buf][threadIdx.x + 256 * q] = reg[q];
+    };
+    auto compute = [&](int buf, const bf16x8 (&x)[MT]) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const bf16x8 bp = sB[buf][nt * 64 + l];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[mt], bp, c[mt][nt], 0, 0, 0);
+        }
+    };
+    bf16x8 xr[D][MT];
+#pragma unroll
+    for (int d = 0; d < D; ++d) fetch_x(min(d, total - 1), xr[d]);
+    bf16x8 sreg[PER];
+    fetch_s(0, sreg);
+    store_s(0, sreg);
+    fetch_s(min(1, total), sreg);
+    for (int it0 = 0; it0 < total; it0 += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int it = it0 + d;
+            lds_barrier();                                // sB[it & 1] holds chunk it; chunk it - 1 done
+            compute(it & 1, xr[d]);
+            store_s((it + 1) & 1, sreg);
+            fetch_s(min(it + 2, total), sreg);
+            fetch_x(min(it + D, total - 1), xr[d]);       // D chunks ahead (clamped at the end)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m0 + 16 * mt + 4 * lr + r;
+                const int64_t idx = row * ld + nt * 16 + lc;
+                double v = (double)c[mt][nt][r];
+                if (IN != nullptr && alpha != 0.0) v += alpha * (double)IN[idx];
                 OUT[idx] = static_cast<float>(v);
             }
+}
+
+// BF16 (round to nearest even) copy of an FP32 array.
+__global__ void k_to_bf16(const float* __restrict__ in, unsigned short* __restrict__ out, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = bf16_bits(in[i]);
 }
 
 // Y (Np x ld FP32, Np a multiple of 8) split into NPL BF16 planes in the operand
@@ -1580,16 +1678,18 @@ static void frag_launch(const double* S, int64_t sstride, int nprod, int ld, boo
                         hipStream_t s, const double* S1 = nullptr, bool trans1 = false);
 template <int NPL>
 static void update_split_any(float* OUT, const float* IN, double alpha, const float* X, int64_t xstride, int nprod,
-                             const void* frag, int64_t Np, int ld, const int* state, hipStream_t s);
+                             const void* frag, int64_t Np, int ld, const int* state, hipStream_t s,
+                             unsigned short* OUT16 = nullptr);
 
 template <typename T>
 void update_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstride, int nprod, const double* S,
                    int64_t sstride, bool trans, double scale, int64_t Np, int ld, void* stage, const int* state,
-                   hipStream_t s) {
+                   hipStream_t s, void* out16) {
     if constexpr (std::is_same<T, float>::value) {
         if (split_full_ok(ld)) {
             frag_launch<3>(S, sstride, nprod, ld, trans, scale, stage, s);
-            update_split_any<3>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s);
+            update_split_any<3>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s,
+                                static_cast<unsigned short*>(out16));
             return;
         }
     }
@@ -1597,6 +1697,9 @@ void update_launch(T* OUT, const T* IN, double alpha, const T* X, int64_t xstrid
     const int64_t cnt = (int64_t)nprod * ld * ld;
     k_stage_s<T><<<grid_for(cnt, 256), 256, 0, s>>>(S, sstride, nprod, ld, trans ? 1 : 0, scale, st);
     update_staged<T>(OUT, IN, alpha, X, xstride, nprod, st, Np, ld, state, s);
+    if constexpr (std::is_same<T, float>::value) {
+        if (out16) bf16_copy_launch(OUT, out16, Np * ld, s);
+    }
 }
 
 template <typename T>
@@ -1637,32 +1740,49 @@ static void update_staged(T* OUT, const T* IN, double alpha, const T* X, int64_t
 
 template <int NT, int NPL>
 static void update_split_one(float* OUT, const float* IN, double alpha, const float* X, int64_t xstride, int nprod,
-                             const void* frag, int64_t Np, int ld, const int* state, hipStream_t s) {
+                             const void* frag, int64_t Np, int ld, const int* state, hipStream_t s,
+                             unsigned short* OUT16) {
     constexpr int D = 4;
     // rows per work-group: 128 (MT = 2) by default, 64 (MT = 1) by the tuning
     if (tuning().update_rows == 64) {
         const unsigned grid = static_cast<unsigned>((Np + 63) / 64);
         k_update_split<1, NT, D, NPL><<<grid, 256, 0, s>>>(OUT, IN, alpha, X, xstride, nprod,
-                                                            static_cast<const bf16x8*>(frag), Np, ld, state);
+                                                            static_cast<const bf16x8*>(frag), Np, ld, state, OUT16);
     } else {
         const unsigned grid = static_cast<unsigned>((Np + 127) / 128);
         k_update_split<2, NT, D, NPL><<<grid, 256, 0, s>>>(OUT, IN, alpha, X, xstride, nprod,
-                                                            static_cast<const bf16x8*>(frag), Np, ld, state);
+                                                            static_cast<const bf16x8*>(frag), Np, ld, state, OUT16);
     }
 }
 
 template <int NPL>
 static void update_split_any(float* OUT, const float* IN, double alpha, const float* X, int64_t xstride, int nprod,
-                             const void* frag, int64_t Np, int ld, const int* state, hipStream_t s) {
+                             const void* frag, int64_t Np, int ld, const int* state, hipStream_t s,
+                             unsigned short* OUT16) {
     switch (ld / 16) {
-        case 1: update_split_one<1, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
-        case 2: update_split_one<2, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
-        case 3: update_split_one<3, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
-        case 4: update_split_one<4, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
-        case 5: update_split_one<5, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
-        case 6: update_split_one<6, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
-        case 7: update_split_one<7, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
-        default: update_split_one<8, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s); break;
+        case 1: update_split_one<1, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s, OUT16); break;
+        case 2: update_split_one<2, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s, OUT16); break;
+        case 3: update_split_one<3, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s, OUT16); break;
+        case 4: update_split_one<4, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s, OUT16); break;
+        case 5: update_split_one<5, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s, OUT16); break;
+        case 6: update_split_one<6, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s, OUT16); break;
+        case 7: update_split_one<7, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s, OUT16); break;
+        default: update_split_one<8, NPL>(OUT, IN, alpha, X, xstride, nprod, frag, Np, ld, state, s, OUT16); break;
+    }
+}
+
+template <int NT>
+static void update_bf16x_one(float* OUT, const float* IN, double alpha, const unsigned short* X, int64_t xstride,
+                             int nprod, const void* frag, int64_t Np, int ld, const int* state, hipStream_t s) {
+    constexpr int D = 4;
+    if (tuning().update_rows == 64) {
+        const unsigned grid = static_cast<unsigned>((Np + 63) / 64);
+        k_update_bf16x<1, NT, D><<<grid, 256, 0, s>>>(OUT, IN, alpha, X, xstride, nprod,
+                                                       static_cast<const bf16x8*>(frag), Np, ld, state);
+    } else {
+        const unsigned grid = static_cast<unsigned>((Np + 127) / 128);
+        k_update_bf16x<2, NT, D><<<grid, 256, 0, s>>>(OUT, IN, alpha, X, xstride, nprod,
+                                                       static_cast<const bf16x8*>(frag), Np, ld, state);
     }
 }
 
@@ -1680,6 +1800,29 @@ static void frag_launch(const double* S, int64_t sstride, int nprod, int ld, boo
 // ld = 16 NT with 3 <= NT <= 8: the fragments of nprod coefficient blocks, plus the
 // zero chunk, then fit the staging area of nprod + 1 ld x ld FP64 matrices.
 static bool split_full_ok(int ld) { return ld % 16 == 0 && ld / 16 >= 3 && ld / 16 <= 8; }
+
+void bf16_copy_launch(const float* in, void* out, int64_t n, hipStream_t s) {
+    k_to_bf16<<<grid_for(n, 256), 256, 0, s>>>(in, static_cast<unsigned short*>(out), n);
+}
+
+bool update_correction_bf16_launch(float* OUT, const float* IN, double alpha, const void* X16, int64_t xstride,
+                                   int nprod, const double* S, int64_t sstride, bool trans, double scale, int64_t Np,
+                                   int ld, void* stage, const int* state, hipStream_t s) {
+    if (ld % 16 != 0 || ld / 16 < 1 || ld / 16 > 8) return false;
+    frag_launch<1>(S, sstride, nprod, ld, trans, scale, stage, s);
+    const unsigned short* X = static_cast<const unsigned short*>(X16);
+    switch (ld / 16) {
+        case 1: update_bf16x_one<1>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+        case 2: update_bf16x_one<2>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+        case 3: update_bf16x_one<3>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+        case 4: update_bf16x_one<4>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+        case 5: update_bf16x_one<5>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+        case 6: update_bf16x_one<6>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+        case 7: update_bf16x_one<7>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+        default: update_bf16x_one<8>(OUT, IN, alpha, X, xstride, nprod, stage, Np, ld, state, s); break;
+    }
+    return true;
+}
 
 template <>
 void update_correction_launch<float>(float* OUT, const float* IN, double alpha, const float* X, int64_t xstride,
@@ -1854,9 +1997,9 @@ template void gram_launch<double>(const GramPlan&, const double*, int64_t, const
 template void gram_launch<float>(const GramPlan&, const float*, int64_t, const float*, double*, double*, int64_t,
                                  int, const int*, hipStream_t);
 template void update_launch<double>(double*, const double*, double, const double*, int64_t, int, const double*,
-                                    int64_t, bool, double, int64_t, int, void*, const int*, hipStream_t);
+                                    int64_t, bool, double, int64_t, int, void*, const int*, hipStream_t, void*);
 template void update_launch<float>(float*, const float*, double, const float*, int64_t, int, const double*,
-                                   int64_t, bool, double, int64_t, int, void*, const int*, hipStream_t);
+                                   int64_t, bool, double, int64_t, int, void*, const int*, hipStream_t, void*);
 template void update2_launch<double>(double*, const double*, double, const double*, const double*, bool,
                                      const double*, const double*, bool, double, int64_t, int, void*, const int*,
                                      hipStream_t);

@@ -28,6 +28,8 @@ struct LzPlan {
 
 struct LzBufs {
     void* basis = nullptr;    // nslots x Np x ld
+    void* basis16 = nullptr;  // FP32 with full re-orthogonalisation: BF16 copies of the basis blocks,
+                              // read by the re-orthogonalisation correction (nslots x Np x ld)
     void* W = nullptr;
     void* Wt = nullptr;
     void* yplanes = nullptr;  // 3 x Np x ld bf16 (FP32, full reorth): W split once for the batched Gram

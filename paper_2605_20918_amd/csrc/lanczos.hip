@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <vector>
 
@@ -178,6 +179,11 @@ struct Step {
     int64_t tall() const { return p.Np * p.ld; }
     // Block holding Q_j (0-based): stored basis slot j, two-pass slot j % 3.
     T* q(int j) const { return static_cast<T*>(slot_ptr(p, bf, p.twopass ? j % 3 : j)); }
+    // BF16 copy of Q_j (nullptr unless FP32 with full re-orthogonalisation)
+    void* q16(int j) const {
+        return bf.basis16 ? static_cast<void*>(static_cast<char*>(bf.basis16) + (size_t)j * p.Np * p.ld * 2)
+                          : nullptr;
+    }
 
     void gram(const T* X, int64_t xstride, int nprod, const T* Y, double* out, int64_t out_stride, bool sym,
               int mode, void* yplanes = nullptr, const double* hinf = nullptr) const {
@@ -185,9 +191,9 @@ struct Step {
                               bf.state, s, yplanes, hinf);
     }
     void update(T* out, const T* in, double alpha, const T* X, int64_t xstride, int nprod, const double* S,
-                int64_t sstride, bool trans, double scale) const {
+                int64_t sstride, bool trans, double scale, void* out16 = nullptr) const {
         update_launch<T>(out, in, alpha, X, xstride, nprod, S, sstride, trans, scale, p.Np, p.ld, bf.stage, bf.state,
-                         s);
+                         s, out16);
     }
 
     // Step j (0-based). replay: regenerate Q_{j+1} from stored coefficients
@@ -224,20 +230,29 @@ struct Step {
                 const int cnt = std::min(cap, np - t0);
                 gram(q(t0), tall(), cnt, W, bf.C + t0 * mat(), mat(), false, 0, bf.yplanes, bf.scal);
             }
-            update_correction_launch<T>(W, W, 1.0, q(0), tall(), np, bf.C, mat(), false, -1.0, p.Np, p.ld,
-                                        bf.stage, bf.state, s);
+            // the corrections are of the size of the loss of orthogonality: with FP32 blocks
+            // they read the BF16 copies of the basis (half the bytes of the stored blocks)
+            bool done = false;
+            if constexpr (std::is_same<T, float>::value) {
+                if (bf.basis16)
+                    done = update_correction_bf16_launch(W, W, 1.0, q16(0), tall(), np, bf.C, mat(), false, -1.0,
+                                                         p.Np, p.ld, bf.stage, bf.state, s);
+            }
+            if (!done)
+                update_correction_launch<T>(W, W, 1.0, q(0), tall(), np, bf.C, mat(), false, -1.0, p.Np, p.ld,
+                                            bf.stage, bf.state, s);
             sym_add_launch(bf.C + j * mat(), Aj, ld, bf.state, s);
         }
         if (last) return true;
         double* R1inv = p.twopass ? bf.R1inv + j * mat() : bf.R1inv;
         double* R2inv = p.twopass ? bf.R2inv + j * mat() : bf.R2inv;
-        qr(j, q(j + 1), bf.B + j * mat(), R1inv, R2inv, replay);            // W = Q_{j+1} B_j
+        qr(j, q(j + 1), q16(j + 1), bf.B + j * mat(), R1inv, R2inv, replay);  // W = Q_{j+1} B_j
         return true;
     }
 
     // W = Qn R by Cholesky QR (twice with CholQR2); R into Rout. Factorisation idx
     // records its smallest pivots at min_diag[2 idx ..] and fails as step idx.
-    void qr(int idx, T* Qn, double* Rout, double* R1inv, double* R2inv, bool replay) const {
+    void qr(int idx, T* Qn, void* Qn16, double* Rout, double* R1inv, double* R2inv, bool replay) const {
         const int ld = p.ld;
         T* W = static_cast<T*>(bf.W);
         T* Wt = static_cast<T*>(bf.Wt);
@@ -257,9 +272,9 @@ struct Step {
                                               2 * idx + 1, bf.min_diag, s);
                 trmm_upper_launch(bf.R2, bf.R1, Rout, ld, bf.state, s);      // R = R2 R1
             }
-            update(Qn, nullptr, 0.0, Wt, 0, 1, R2inv, 0, false, 1.0);          // Qn = Wt R2^-1
+            update(Qn, nullptr, 0.0, Wt, 0, 1, R2inv, 0, false, 1.0, Qn16);    // Qn = Wt R2^-1
         } else {
-            update(Qn, nullptr, 0.0, W, 0, 1, R1inv, 0, false, 1.0);           // Qn = W R1^-1
+            update(Qn, nullptr, 0.0, W, 0, 1, R1inv, 0, false, 1.0, Qn16);     // Qn = W R1^-1
         }
     }
 };
@@ -335,7 +350,7 @@ css_status pass1_t(const css_csr* H, const int32_t* color, const int8_t* sign, c
         // general first block: Q_1 R_0 = start by the step's Cholesky QR
         k_start_block<T><<<grid_for(p.Np * p.ld, 256), 256, 0, s>>>(start, static_cast<T*>(bf.W), p.Np * p.ld);
         k_zero_small<<<grid_for((int64_t)p.ld * p.ld, 256), 256, 0, s>>>(R0, (int64_t)p.ld * p.ld);
-        st.qr(0, st.q(0), R0, bf.R1inv, bf.R2inv, false);
+        st.qr(0, st.q(0), st.q16(0), R0, bf.R1inv, bf.R2inv, false);
         int hst[16];
         CSS_HIP_TRY(hipGetLastError());
         CSS_HIP_TRY(hipMemcpyAsync(hst, bf.state, sizeof(hst), hipMemcpyDeviceToHost, s));
@@ -345,6 +360,9 @@ css_status pass1_t(const css_csr* H, const int32_t* color, const int8_t* sign, c
         if (bf.Wt) zero_tall<T>(static_cast<T*>(bf.Wt), p.Np * p.ld, s);
     } else {
         k_init_q1<T><<<grid_for(p.Np * p.ld, 256), 256, 0, s>>>(color, sign, bf.counts, p.n, p.Np, p.ld, st.q(0));
+        if constexpr (std::is_same<T, float>::value) {
+            if (bf.basis16) bf16_copy_launch(st.q(0), st.q16(0), p.Np * p.ld, s);
+        }
     }
     for (int j = 0; j < p.v_max; ++j)
         if (!st.run(j, false, j == p.v_max - 1)) return CSS_E_UNSUPPORTED;
@@ -468,6 +486,7 @@ void carve_lanczos(Arena& a, const LzPlan& p, LzBufs& bf) {
     const int64_t mat = (int64_t)p.ld * p.ld;
     const int64_t tall_bytes = p.Np * p.ld * (int64_t)p.elem;
     bf.basis = a.take<char>((size_t)p.nslots * tall_bytes);
+    bf.basis16 = (p.fp32 && p.reorth == 2 && !p.twopass) ? a.take<char>((size_t)p.nslots * p.Np * p.ld * 2) : nullptr;
     bf.W = a.take<char>(tall_bytes);
     bf.Wt = p.cholqr2 ? a.take<char>(tall_bytes) : nullptr;
     bf.yplanes = (p.fp32 && p.reorth == 2) ? a.take<char>((size_t)3 * p.Np * p.ld * 2) : nullptr;
