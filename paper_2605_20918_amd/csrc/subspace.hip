@@ -657,67 +657,120 @@ __global__ __launch_bounds__(kPoleThreads) void k_pole_solve(const double* __res
 // one workgroup per pole, the complex Schur complement S (N x N, row stride
 // N + 1) in LDS. Each S_j is inverted in place by block Gauss-Jordan without
 // pivoting: wave 0 inverts the 16 x 16 diagonal block P = S_kk^-1 in registers,
-// then the row block (S_kj <- P S_kj), the trailing blocks (S_ij -= S_ik S_kj)
-// and the column block (S_ik <- -S_ik P) are updated on FP64 MFMA, four
-// barriers per block step instead of one per pivot. G_j (N x N, global) and the
-// forward sweep are as in k_pole_solve_generic.
+// the row block (S_kj <- P S_kj), the trailing blocks (S_ij -= S_ik S_kj) and the
+// column block (S_ik <- -S_ik P) are updated on FP64 MFMA, three barriers per block
+// step, with the next pivot inverted during the trailing update (gj_inverse_blk).
+// G_j (N x N, global) and the forward sweep are as in k_pole_solve_generic.
 constexpr int kBlkThreads = 512;     // 8 waves: 256 registers per lane, no spills
 constexpr int kBlkWaves = kBlkThreads / 64;
 
 __device__ inline double pole_bcast(double v, int src) { return __shfl(v, src, 64); }
+// v of lane src (src the same in every lane): two readlanes, no lane permute
+__device__ inline double lane_read(double v, int src) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), src);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
 
+// Wave 0: the 16 x 16 diagonal block at (o, o) of S inverted in registers (Gauss-Jordan
+// without pivoting, MFMA D layout: lane l holds rows (l>>4)+4r, column l&15) into Pr/Pi
+// (row stride 17). The pivot itself comes by readlane (its lane is known), the pivot
+// row and column by lane permutes.
 template <int NB>
-__device__ void gj_inverse_blk(double* Sr, double* Si, double* Pr, double* Pi) {
+__device__ __forceinline__ void pivot_inverse(const double* Sr, const double* Si, int o, double* Pr, double* Pi) {
     constexpr int SW = 16 * NB + 1;
+    const int lane = threadIdx.x & 63, lr = lane >> 4, lc = lane & 15;
+    double xr[4], xi[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        xr[r] = Sr[(o + lr + 4 * r) * SW + o + lc];
+        xi[r] = Si[(o + lr + 4 * r) * SW + o + lc];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int rk = k >> 2, sk = 16 * (k & 3);
+        const double pr = lane_read(xr[rk], sk + k), pi = lane_read(xi[rk], sk + k);
+        const double den = 1.0 / (pr * pr + pi * pi);
+        const double qr = pr * den, qi = -pi * den;                       // 1 / pivot
+        const double mr = pole_bcast(xr[rk], sk + lc), mi = pole_bcast(xi[rk], sk + lc);
+        const double rr = mr * qr - mi * qi, ri = mr * qi + mi * qr;      // pivot row / pivot
+        double cr[4], ci[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {                                     // column k, my rows
+            cr[r] = pole_bcast(xr[r], 16 * lr + k);
+            ci[r] = pole_bcast(xi[r], 16 * lr + k);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = lr + 4 * r;
+            double nr, ni;
+            if (i == k) {
+                nr = (lc == k) ? qr : rr;
+                ni = (lc == k) ? qi : ri;
+            } else if (lc == k) {
+                nr = -(cr[r] * qr - ci[r] * qi);
+                ni = -(cr[r] * qi + ci[r] * qr);
+            } else {
+                nr = xr[r] - (cr[r] * rr - ci[r] * ri);
+                ni = xi[r] - (cr[r] * ri + ci[r] * rr);
+            }
+            xr[r] = nr;
+            xi[r] = ni;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        Pr[(lr + 4 * r) * 17 + lc] = xr[r];
+        Pi[(lr + 4 * r) * 17 + lc] = xi[r];
+    }
+}
+
+// Trailing update of one tile: S_ij -= S_ik S_kj (k = kb, complex, FP64 MFMA).
+template <int NB>
+__device__ __forceinline__ void trailing_tile(double* Sr, double* Si, int ib, int jb, int kb) {
+    constexpr int SW = 16 * NB + 1;
+    const int lane = threadIdx.x & 63, lr = lane >> 4, lc = lane & 15;
+    const int o = 16 * kb;
+    pd4 cr, ci;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        cr[r] = Sr[(16 * ib + lr + 4 * r) * SW + 16 * jb + lc];
+        ci[r] = Si[(16 * ib + lr + 4 * r) * SW + 16 * jb + lc];
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+        const int k = o + 4 * s4 + lr;
+        const double ar = Sr[(16 * ib + lc) * SW + k], ai = Si[(16 * ib + lc) * SW + k];
+        const double br = Sr[k * SW + 16 * jb + lc], bi = Si[k * SW + 16 * jb + lc];
+        cr = mfma64(-ar, br, cr);
+        cr = mfma64(ai, bi, cr);
+        ci = mfma64(-ar, bi, ci);
+        ci = mfma64(-ai, br, ci);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        Sr[(16 * ib + lr + 4 * r) * SW + 16 * jb + lc] = cr[r];
+        Si[(16 * ib + lr + 4 * r) * SW + 16 * jb + lc] = ci[r];
+    }
+}
+
+// S (16 NB x 16 NB complex, in LDS) replaced by its inverse, block Gauss-Jordan without
+// pivoting. P holds two pivot inverses (re/im, 16 x 17 each; P + 2*272 q for buffer q).
+// Look-ahead: in block step kb, once the row block is updated, wave 0 updates the next
+// diagonal tile (kb+1, kb+1) and inverts it into the other buffer while the other waves
+// update the rest of the trailing tiles, so the sequential 16 x 16 inversions overlap
+// the MFMA updates; then the column block and S_kk <- P. Three barriers per block step.
+template <int NB>
+__device__ void gj_inverse_blk(double* Sr, double* Si, double* P) {
+    constexpr int SW = 16 * NB + 1, PB = 2 * 16 * 17;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane >> 4, lc = lane & 15;
+    if (wave == 0) pivot_inverse<NB>(Sr, Si, 0, P, P + 16 * 17);
+    __syncthreads();
     for (int kb = 0; kb < NB; ++kb) {
         const int o = 16 * kb;
-        if (wave == 0) {
-            double xr[4], xi[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                xr[r] = Sr[(o + lr + 4 * r) * SW + o + lc];
-                xi[r] = Si[(o + lr + 4 * r) * SW + o + lc];
-            }
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int rk = k >> 2, sk = 16 * (k & 3);
-                const double pr = pole_bcast(xr[rk], sk + k), pi = pole_bcast(xi[rk], sk + k);
-                const double den = 1.0 / (pr * pr + pi * pi);
-                const double qr = pr * den, qi = -pi * den;                       // 1 / pivot
-                const double mr = pole_bcast(xr[rk], sk + lc), mi = pole_bcast(xi[rk], sk + lc);
-                const double rr = mr * qr - mi * qi, ri = mr * qi + mi * qr;      // pivot row / pivot
-                double cr[4], ci[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {                                     // column k, my rows
-                    cr[r] = pole_bcast(xr[r], 16 * lr + k);
-                    ci[r] = pole_bcast(xi[r], 16 * lr + k);
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = lr + 4 * r;
-                    double nr, ni;
-                    if (i == k) {
-                        nr = (lc == k) ? qr : rr;
-                        ni = (lc == k) ? qi : ri;
-                    } else if (lc == k) {
-                        nr = -(cr[r] * qr - ci[r] * qi);
-                        ni = -(cr[r] * qi + ci[r] * qr);
-                    } else {
-                        nr = xr[r] - (cr[r] * rr - ci[r] * ri);
-                        ni = xi[r] - (cr[r] * ri + ci[r] * rr);
-                    }
-                    xr[r] = nr;
-                    xi[r] = ni;
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                Pr[(lr + 4 * r) * 17 + lc] = xr[r];
-                Pi[(lr + 4 * r) * 17 + lc] = xi[r];
-            }
-        }
-        __syncthreads();
+        const double* Pr = P + (kb & 1) * PB;
+        const double* Pi = Pr + 16 * 17;
         if (wave < NB - 1) {                                  // row block: S_kj <- P S_kj
             const int jb = wave < kb ? wave : wave + 1;
             pd4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
@@ -738,30 +791,25 @@ __device__ void gj_inverse_blk(double* Sr, double* Si, double* Pr, double* Pi) {
             }
         }
         __syncthreads();
-        for (int t = wave; t < (NB - 1) * (NB - 1); t += kBlkWaves) {   // trailing: S_ij -= S_ik S_kj
-            int ib = t / (NB - 1), jb = t % (NB - 1);
-            ib += ib >= kb;
-            jb += jb >= kb;
-            pd4 cr, ci;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                cr[r] = Sr[(16 * ib + lr + 4 * r) * SW + 16 * jb + lc];
-                ci[r] = Si[(16 * ib + lr + 4 * r) * SW + 16 * jb + lc];
-            }
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-                const int k = o + 4 * s4 + lr;
-                const double ar = Sr[(16 * ib + lc) * SW + k], ai = Si[(16 * ib + lc) * SW + k];
-                const double br = Sr[k * SW + 16 * jb + lc], bi = Si[k * SW + 16 * jb + lc];
-                cr = mfma64(-ar, br, cr);
-                cr = mfma64(ai, bi, cr);
-                ci = mfma64(-ar, bi, ci);
-                ci = mfma64(-ai, br, ci);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                Sr[(16 * ib + lr + 4 * r) * SW + 16 * jb + lc] = cr[r];
-                Si[(16 * ib + lr + 4 * r) * SW + 16 * jb + lc] = ci[r];
+        if constexpr (NB > 1) {
+            const int k1 = kb + 1;
+            const bool ahead = k1 < NB;                        // a next pivot exists
+            if (ahead && wave == 0) {
+                trailing_tile<NB>(Sr, Si, k1, k1, kb);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // the tile's LDS writes before its reads
+                double* Qr = P + (k1 & 1) * PB;
+                pivot_inverse<NB>(Sr, Si, 16 * k1, Qr, Qr + 16 * 17);
+            } else {
+                // the trailing tiles (i, j != kb): all of them to every wave in the last
+                // block step, all but (k1, k1) to waves 1.. before it
+                const int w0 = ahead ? wave - 1 : wave, nw = ahead ? kBlkWaves - 1 : kBlkWaves;
+                for (int t = w0; t < (NB - 1) * (NB - 1); t += nw) {
+                    int ib = t / (NB - 1), jb = t % (NB - 1);
+                    ib += ib >= kb;
+                    jb += jb >= kb;
+                    if (ahead && ib == k1 && jb == k1) continue;
+                    trailing_tile<NB>(Sr, Si, ib, jb, kb);
+                }
             }
         }
         __syncthreads();
@@ -807,8 +855,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
     extern __shared__ double lds[];
     double* Sr = lds;
     double* Si = lds + N * SW;
-    double* Pr = lds + 2 * N * SW;
-    double* Pi = Pr + 16 * 17;
+    double* P = lds + 2 * N * SW;          // two 16 x 17 complex pivot inverses
     const int p = blockIdx.x, tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, lr = lane >> 4, lc = lane & 15;
     const int64_t mat = (int64_t)ld * ld, nn = (int64_t)N * N;
@@ -831,7 +878,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
         asm volatile("" : "+v"(zoff));
         double* Sr = lds + zoff;
         double* Si = lds + zoff + N * SW;
-        gj_inverse_blk<NB>(Sr, Si, Pr, Pi);
+        gj_inverse_blk<NB>(Sr, Si, P);
         if (j == 0) break;
         // G_j = -i a S_j^-1 B_{j-1} (B zero beyond b). B_{j-1} is upper triangular
         // (a Cholesky factor, or the product of two): column c has no entries below row
@@ -995,7 +1042,7 @@ __global__ __launch_bounds__(64 * NB) void k_pole_forward(int v, int b, const do
     }
 }
 
-size_t pole_blk_lds_bytes(int nb) { return sizeof(double) * (2 * (size_t)16 * nb * (16 * nb + 1) + 2 * 16 * 17); }
+size_t pole_blk_lds_bytes(int nb) { return sizeof(double) * (2 * (size_t)16 * nb * (16 * nb + 1) + 4 * 16 * 17); }
 
 // F = g (E_1 B_0 / 2 - sum_p W_p), poles summed in order.
 __global__ void k_pole_sum(const double* __restrict__ Wout, int npole, int64_t nTb, int b,
