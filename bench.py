@@ -50,9 +50,10 @@ PEAK_HBM_GBS = 8000.0
 WORKLOADS = {
     "10k": dict(n_mol=10000, seed=20921, depth=40, prec="fp32", fp64_twopass=False),
     "1m": dict(n_mol=1000000, seed=20923, depth=40, prec="fp32", fp64_twopass=True),
-    # FP64 at 1 000 molecules re-orthogonalises fully: at depth 40 the Krylov space spans
-    # more than half of the 6 000 orbitals, and a local re-orthogonalisation loses
-    # orthogonality there (P then moves by ~3e-5 under a 2e-16 perturbation of H)
+    # FP64 at 1 000 molecules re-orthogonalises against every block (on alternate steps):
+    # at depth 40 the Krylov space spans more than half of the 6 000 orbitals, and a
+    # local re-orthogonalisation loses orthogonality there (P then moves by ~3e-5 under a
+    # 2e-16 perturbation of H)
     "1k": dict(n_mol=1000, seed=20920, depth=40, prec="fp64", fp64_twopass=False, reorth="full"),
     "batch48": dict(n_mol=0, seed=20922, depth=40, prec="fp32", fp64_twopass=False),
 }
@@ -148,17 +149,20 @@ def run_batch(args):
 
 # HBM bytes per launch of the grouped SpMM from FETCH_SIZE + WRITE_SIZE counter runs
 # (scaled by a 1 GiB copy), valid while the kernel source hashes to the recorded value
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmm_grp_traffic_10k.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmm_grp_traffic_{}.json")
 
 
 def flags_for(prec: str, twopass: bool = False, reorth: str = "local"):
-    """Mixed path: full re-orthogonalisation. FP64 path: local (against the previous two
-    blocks) unless `reorth` is "full"; local suffices while the Krylov space is a small
-    part of the orbital space (10^4 and 10^6 molecules at depth 40)."""
+    """Mixed path: re-orthogonalisation against every block on alternate steps (against
+    the previous two on the others). FP64 path: local (the previous two blocks) unless
+    `reorth` is "full" (then the same alternating schedule); local suffices while the
+    Krylov space is a small part of the orbital space (10^4 and 10^6 molecules at depth
+    40)."""
     from paper_2605_20918_amd import css
+    alternate = css.REORTH_FULL | css.REORTH_ALTERNATE
     if prec == "fp32":
-        return css.PREC_FP32 | css.REORTH_FULL | css.CHOLQR2 | css.SYMMETRIZE
-    ro = css.REORTH_FULL if reorth == "full" else css.REORTH_LOCAL
+        return css.PREC_FP32 | alternate | css.CHOLQR2 | css.SYMMETRIZE
+    ro = alternate if reorth == "full" else css.REORTH_LOCAL
     return css.PREC_FP64 | ro | css.CHOLQR2 | css.SYMMETRIZE | (css.BASIS_TWOPASS if twopass else 0)
 
 
@@ -171,7 +175,7 @@ def kernel_hash() -> str:
 def measured_traffic(workload: str):
     """HBM bytes per launch from the committed counter summary, or None."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILE.format(workload)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -355,7 +359,9 @@ def measure_single(name: str, steps: int, warmup: int, extras: bool, fp64: bool,
         "config": {"workload": f"water {wl['n_mol']} H2O ({ws.n} orbitals), {wl['prec']} blocks, depth {depth}",
                    "n_orbitals": ws.n, "nnz_H": nnz, "nnz_P": state["nnz_p"], "n_colors": b,
                    "depth": depth, "depth_eff": v_eff, "kT": KT, "mu": mu, "r_cut": R_CUT,
-                   "flags": flags, "reorth": "full" if flags & css.REORTH_FULL else "local"},
+                   "flags": flags,
+                   "reorth": ("full on alternate steps, local between" if flags & css.REORTH_ALTERNATE else "full")
+                   if flags & css.REORTH_FULL else "local"},
         "phases_ms": {**info["t_phase_ms"], "colour_probe_total": t_color * 1e3,
                       "colour_rounds": state["rounds"]},
         "trace": state["trace"], "e_band": state["e_band"], "trace_krylov": info["trace_krylov"],
@@ -412,14 +418,15 @@ def measure_single(name: str, steps: int, warmup: int, extras: bool, fp64: bool,
         t60 = time.perf_counter() - t
         p60, e60, i60 = state["p_val"].double().cpu(), state["e_band"], state["info"]
         # at depth 60 local re-orthogonalisation in FP64 loses orthogonality (max|Q^T Q - I|
-        # about 1e-2 at 10^4 molecules), so the comparator re-orthogonalises fully
+        # about 1e-2 at 10^4 molecules), so the comparator re-orthogonalises against every
+        # block (on alternate steps)
         f64 = flags_for("fp64", reorth="full")
         H64 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, dev, torch.float64)
         (q64, e64, _, i64), t64 = timed_call(
             torch, lambda: css.css_density_matrix(H64, color, sign, bb, mu, KT, 60, p_rp, p_col, f64 | css.DIAG_ORTHO))
         out["depth60"] = {"ms_per_step": t60 * 1e3, "value": ws.n * i60["depth_eff"] / t60,
                           "depth_eff": i60["depth_eff"], "phases_ms": i60["t_phase_ms"],
-                          "fp64_density_ms": t64 * 1e3, "fp64_mode": "FP64, full re-orthogonalisation, stored basis",
+                          "fp64_density_ms": t64 * 1e3, "fp64_mode": "FP64, full re-orthogonalisation on alternate steps, stored basis",
                           "fp64_ortho_err": i64["ortho_err"],
                           "mixed_vs_fp64_max_abs_dP": float(torch.max(torch.abs(q64.cpu() - p60))),
                           "mixed_vs_fp64_rel_dE": abs(e60 - e64) / abs(e64),

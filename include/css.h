@@ -83,6 +83,8 @@ enum { CSS_F64 = 0, CSS_F32 = 1 };
 #define CSS_SPMM_CSR       0x200u /* always use the row-parallel CSR SpMM kernel; by default the
                                      16-row grouped MFMA kernel is used where H's row groups
                                      are dense enough (see css_spmm_prepare) */
+#define CSS_REORTH_ALTERNATE 0x800u /* with CSS_REORTH_FULL: the full pass on even steps
+                                       only, the local pass on odd steps */
 #define CSS_DIAG_ORTHO     0x400u /* css_block_lanczos / css_density_matrix /
                                      css_density_matrix_nonorth: measure the loss of
                                      orthogonality of the stored Krylov basis,

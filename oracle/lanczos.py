@@ -19,8 +19,10 @@ Readings (the paper gives no detail of its block Lanczos):
 * one step: W = H Q_j - Q_{j-1} B_{j-1}^T; A_j = Q_j^T W symmetrised as
   (A + A^T)/2; W <- W - Q_j A_j;
 * re-orthogonalisation: "full" repeats classical Gram-Schmidt once against
-  Q_1..Q_j, "local" against Q_{j-1}, Q_j only, "none" skips it; the
-  symmetrised coefficient against Q_j is added to A_j, the others are dropped;
+  Q_1..Q_j, "local" against Q_{j-1}, Q_j only, "alternate" does the full pass
+  on the steps j = 0, 2, 4, ... (counting from 0) and the local pass on the
+  others, "none" skips it; the symmetrised coefficient against Q_j is added to
+  A_j, the others are dropped;
 * W = Q_{j+1} B_j by Cholesky QR: G = W^T W = R^T R (R upper, positive
   diagonal), Q_{j+1} = W R^-1, B_j = R; with CholQR2 the factorisation is
   repeated once on Q_{j+1} and B_j = R_2 R;
@@ -36,7 +38,7 @@ import scipy.linalg as sla
 
 from .probes import first_block
 
-REORTH_NONE, REORTH_LOCAL, REORTH_FULL = "none", "local", "full"
+REORTH_NONE, REORTH_LOCAL, REORTH_FULL, REORTH_ALTERNATE = "none", "local", "full", "alternate"
 BREAKDOWN_REL = 1e-10
 
 
@@ -95,8 +97,11 @@ def block_lanczos(H, color, sign, n_colors: int, depth: int,
         A = Qj.T @ W
         A = 0.5 * (A + A.T)
         W = W - Qj @ A
+        if reorth not in (REORTH_NONE, REORTH_FULL, REORTH_LOCAL, REORTH_ALTERNATE):
+            raise ValueError(f"unknown re-orthogonalisation {reorth!r}")
         if reorth != REORTH_NONE:
-            basis = Qs if reorth == REORTH_FULL else Qs[max(0, j - 1):]
+            full = reorth == REORTH_FULL or (reorth == REORTH_ALTERNATE and j % 2 == 0)
+            basis = Qs if full else Qs[max(0, j - 1):]
             coeff = [Qi.T @ W for Qi in basis]
             for Qi, C in zip(basis, coeff):
                 W = W - Qi @ C

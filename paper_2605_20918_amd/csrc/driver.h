@@ -17,6 +17,7 @@ struct LzPlan {
     bool fp32 = false;        // blocks and SpMM in FP32
     bool twopass = false;     // no stored basis
     int reorth = 0;           // 0 none, 1 local, 2 full
+    bool reorth_alt = false;  // full on even steps, local on odd steps
     bool cholqr2 = false;
     bool convert_h = false;   // H values converted into the workspace
     int nslots = 0;           // tall blocks kept for the basis

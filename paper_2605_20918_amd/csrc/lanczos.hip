@@ -223,25 +223,27 @@ struct Step {
             for (int t = 0; t < np; ++t) update(W, W, 1.0, q(first + t), 0, 1, C + t * mat(), 0, false, -1.0);
             if (!replay) sym_add_launch(C + (np - 1) * mat(), Aj, ld, bf.state, s);
         } else if (p.reorth == 2) {
-            // full: coefficients against Q_0..Q_j (contiguous stored slots), batched
-            const int np = j + 1;
+            // full: coefficients against Q_0..Q_j (contiguous stored slots), batched; with
+            // the alternating schedule, odd steps only against Q_{j-1}, Q_j
+            const int first = (p.reorth_alt && (j & 1)) ? std::max(0, j - 1) : 0;
+            const int np = j + 1 - first;
             const int cap = (int)std::max<int64_t>(1, p.partial_mats);
             for (int t0 = 0; t0 < np; t0 += cap) {
                 const int cnt = std::min(cap, np - t0);
-                gram(q(t0), tall(), cnt, W, bf.C + t0 * mat(), mat(), false, 0, bf.yplanes, bf.scal);
+                gram(q(first + t0), tall(), cnt, W, bf.C + t0 * mat(), mat(), false, 0, bf.yplanes, bf.scal);
             }
             // the corrections are of the size of the loss of orthogonality: with FP32 blocks
             // they read the BF16 copies of the basis (half the bytes of the stored blocks)
             bool done = false;
             if constexpr (std::is_same<T, float>::value) {
                 if (bf.basis16)
-                    done = update_correction_bf16_launch(W, W, 1.0, q16(0), tall(), np, bf.C, mat(), false, -1.0,
+                    done = update_correction_bf16_launch(W, W, 1.0, q16(first), tall(), np, bf.C, mat(), false, -1.0,
                                                          p.Np, p.ld, bf.stage, bf.state, s);
             }
             if (!done)
-                update_correction_launch<T>(W, W, 1.0, q(0), tall(), np, bf.C, mat(), false, -1.0, p.Np, p.ld,
+                update_correction_launch<T>(W, W, 1.0, q(first), tall(), np, bf.C, mat(), false, -1.0, p.Np, p.ld,
                                             bf.stage, bf.state, s);
-            sym_add_launch(bf.C + j * mat(), Aj, ld, bf.state, s);
+            sym_add_launch(bf.C + (j - first) * mat(), Aj, ld, bf.state, s);
         }
         if (last) return true;
         double* R1inv = p.twopass ? bf.R1inv + j * mat() : bf.R1inv;
@@ -466,6 +468,7 @@ css_status plan_lanczos(const css_csr* H, int32_t b, int32_t depth, uint32_t fla
     p.elem = p.fp32 ? 4 : 8;
     p.twopass = (flags & CSS_BASIS_TWOPASS) != 0;
     p.reorth = (flags & CSS_REORTH_FULL) ? 2 : ((flags & CSS_REORTH_LOCAL) ? 1 : 0);
+    p.reorth_alt = p.reorth == 2 && (flags & CSS_REORTH_ALTERNATE) != 0;
     if (p.twopass && p.reorth == 2) return CSS_E_UNSUPPORTED;
     p.cholqr2 = (flags & CSS_CHOLQR2) != 0;
     p.convert_h = (p.fp32 && H->val_dtype == CSS_F64) || (!p.fp32 && H->val_dtype == CSS_F32);

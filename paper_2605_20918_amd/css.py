@@ -37,6 +37,7 @@ SIGNS_ONES = 0x80
 SUBSPACE_EIG = 0x100
 SPMM_CSR = 0x200
 DIAG_ORTHO = 0x400
+REORTH_ALTERNATE = 0x800
 
 (ENTRY_COLOR, ENTRY_LANCZOS, ENTRY_DENSITY, ENTRY_SPMM, ENTRY_ENERGY_DENSITY, ENTRY_FIND_MU, ENTRY_INV_SQRT,
  ENTRY_TRANSFORM_H, ENTRY_DENSITY_NONORTH) = 0, 1, 2, 3, 4, 5, 6, 7, 8

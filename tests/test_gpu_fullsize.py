@@ -60,7 +60,13 @@ def test_10k_against_the_oracle():
     print(f"10k: oracle with local re-orthogonalisation {time.perf_counter() - t0:.1f} s", flush=True)
     H32 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, "cuda", torch.float32)
     H64 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, "cuda", torch.float64)
-    runs = {"mixed (bench)": (H32, bench.flags_for("fp32"), ref),
+    # the mixed path of the bench re-orthogonalises against every block on alternate steps
+    t0 = time.perf_counter()
+    ref_alt = D.density_matrix(ws.H.to_scipy(), color, sign, b, MU, KT, wl["depth"], rp, col, reorth="alternate",
+                               cholqr2=True)
+    print(f"10k: oracle with the alternating schedule {time.perf_counter() - t0:.1f} s", flush=True)
+    runs = {"mixed (bench)": (H32, bench.flags_for("fp32"), ref_alt),
+            "fp64 alternate": (H64, bench.flags_for("fp64", reorth="full"), ref_alt),
             "fp64 full": (H64, css.PREC_FP64 | css.REORTH_FULL | css.CHOLQR2 | css.SYMMETRIZE, ref),
             "fp64 local (bench comparator)": (H64, bench.flags_for("fp64"), ref_local),
             "fp64 local two-pass": (H64, bench.flags_for("fp64", twopass=True), ref_local)}
@@ -77,7 +83,7 @@ def test_10k_against_the_oracle():
         print(f"10k {name}: max|dP| {dp:.3e}  rel dE {de:.3e}", flush=True)
     assert errs["mixed (bench)"][0] <= 1e-5 and errs["mixed (bench)"][1] <= 1e-7
     assert errs["fp64 full"][0] <= 1e-10 and errs["fp64 full"][1] <= 1e-10
-    for name in ("fp64 local (bench comparator)", "fp64 local two-pass"):
+    for name in ("fp64 local (bench comparator)", "fp64 local two-pass", "fp64 alternate"):
         assert errs[name][0] <= 1e-10 and errs[name][1] <= 1e-10
     # the energy-weighted estimate, mixed precision, element by element against the oracle
     t0 = time.perf_counter()

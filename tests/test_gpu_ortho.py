@@ -72,10 +72,12 @@ def test_local_reorth_loss_tracks_the_oracle(M, seed, depth):
     assert e_ref / 30 <= e <= 30 * e_ref
 
 
-def test_mixed_path_basis_is_orthonormal_to_fp32_rounding():
+@pytest.mark.parametrize("schedule", ["full", "alternate"])
+def test_mixed_path_basis_is_orthonormal_to_fp32_rounding(schedule):
     ws, H, rp, col, color, b, sign, mu = water_case(1000, 20920)
-    v, e = _gpu_loss(ws, color, sign, b, 40, css.PREC_FP32 | BASE | css.REORTH_FULL, torch.float32)
-    print(f"ortho fp32 full: {e:.3e}", flush=True)
+    flags = css.PREC_FP32 | BASE | css.REORTH_FULL | (css.REORTH_ALTERNATE if schedule == "alternate" else 0)
+    v, e = _gpu_loss(ws, color, sign, b, 40, flags, torch.float32)
+    print(f"ortho fp32 {schedule}: {e:.3e}", flush=True)
     assert v == 40
     assert 0.0 < e <= 1e-5
 

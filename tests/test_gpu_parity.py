@@ -502,6 +502,37 @@ def test_local_reorth_fp64_against_local_oracle(M, seed, depth, mode):
     assert abs(t - ref["trace"]) <= 1e-10 * abs(ref["trace"])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("M,seed,depth", [(216, 3, 40), (1000, 20920, 40), (125, 11, 7)])
+def test_alternate_reorth_against_oracle(M, seed, depth, prec):
+    """Re-orthogonalisation against every block on the steps j = 0, 2, ... and against
+    the previous two on the others, against the oracle running the same schedule."""
+    print(f"alternate reorth {prec} M={M} depth={depth}", flush=True)
+    flags = (css.PREC_FP64 if prec == "fp64" else css.PREC_FP32) | css.REORTH_FULL | css.REORTH_ALTERNATE | \
+        css.CHOLQR2 | css.SYMMETRIZE
+    ws, H, rp, col, color, b, sign, mu = water_case(M, seed)
+    ref = D.density_matrix(H, color, sign, b, mu, KT, depth, rp, col, reorth="alternate", cholqr2=True)
+    p, e, t, info = css.css_density_matrix(to_dev(ws, None if prec == "fp64" else torch.float32), dev_i32(color),
+                                           dev_i8(sign), b, mu, KT, depth, dev_i64(rp), dev_i32(col), flags)
+    assert info["depth_eff"] == ref["v_eff"]
+    err = np.max(np.abs(p.cpu().numpy() - ref["p_val"]))
+    rel_e = abs(e - ref["e_band"]) / abs(ref["e_band"])
+    print(f"  max|dP|={err:.3e} rel dE={rel_e:.3e}", flush=True)
+    if prec == "fp64":
+        assert err <= 1e-10 and rel_e <= 1e-10
+    else:
+        assert err <= 1e-5 and rel_e <= 1e-7
+
+
+def test_alternate_reorth_needs_the_stored_basis():
+    ws, H, rp, col, color, b, sign, mu = water_case(64, 20919)
+    flags = css.PREC_FP64 | css.REORTH_FULL | css.REORTH_ALTERNATE | css.BASIS_TWOPASS
+    with pytest.raises(css.CssError) as e:
+        css.css_density_matrix(to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, 10, dev_i64(rp), dev_i32(col),
+                               flags)
+    assert e.value.code == 8
+
+
 def test_twopass_matches_stored_basis():
     ws, H, rp, col, color, b, sign, mu = water_case(216, 3)
     args = (to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, 12, dev_i64(rp), dev_i32(col))

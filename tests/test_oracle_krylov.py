@@ -59,7 +59,7 @@ def small_water(M=27, seed=11, r_cut=6.0):
 
 # ---------------------------------------------------------------- Lanczos
 
-@pytest.mark.parametrize("reorth", ["full", "local", "none"])
+@pytest.mark.parametrize("reorth", ["full", "local", "alternate", "none"])
 def test_krylov_polynomial_exactness(reorth):
     # Phi T^p E_1 B_0 = H^p r for every p <= v_eff - 1 (exact arithmetic)
     ws, H, rp, col, color, b, sign = small_water(M=64, seed=20919)
@@ -77,6 +77,49 @@ def test_krylov_polynomial_exactness(reorth):
         assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref)), p
         Hp_r = H @ Hp_r
         Tp = T @ Tp
+
+
+def test_alternate_schedule_is_full_then_local():
+    """The alternating schedule takes the full pass at j = 0, 2, ... and the local one
+    at odd j: it equals full for up to 3 blocks (local and full differ from j = 2 on)
+    and differs from both at 4; its coefficients are those of the other schedules'
+    pass at each step."""
+    ws, H, rp, col, color, b, sign = small_water(M=64, seed=20919)
+    run = {r: block_lanczos(H, color, sign, b, depth=5, reorth=r) for r in ("full", "local", "alternate")}
+    short = {r: block_lanczos(H, color, sign, b, depth=3, reorth=r) for r in ("full", "alternate")}
+    for a, f in zip(short["alternate"].A, short["full"].A):
+        assert np.array_equal(a, f)
+    for a, f in zip(short["alternate"].B, short["full"].B):
+        assert np.array_equal(a, f)
+    # B_j comes from W after step j's pass: step 2 (even) is the full pass, so B_2 is
+    # the full schedule's and not the local one's; step 3 (odd) is local, so B_3
+    # differs from the full schedule's
+    assert np.array_equal(run["alternate"].B[2], run["full"].B[2])
+    assert not np.array_equal(run["alternate"].B[2], run["local"].B[2])
+    assert not np.array_equal(run["alternate"].B[3], run["full"].B[3])
+    with pytest.raises(ValueError):
+        block_lanczos(H, color, sign, b, depth=2, reorth="sometimes")
+
+
+def test_alternate_schedule_keeps_fp64_orthonormality_where_local_loses_it():
+    """216 water molecules, depth 40 (Krylov exhaustion at 15 blocks): local
+    re-orthogonalisation loses orthogonality (measured 3e-6), the alternating schedule
+    keeps it at rounding level and gives the full schedule's P to 1e-13."""
+    ws = synth.water_system(216, 3)
+    H = ws.H.to_scipy()
+    rp, col, deg = conflict_pattern(ws.orb_xyz, ws.box, 6.0)
+    color, b = greedy_color(rp, col, deg)
+    sign = probe_signs(ws.n, 3)
+    loss = {}
+    for r in ("local", "alternate"):
+        lz = block_lanczos(H, color, sign, b, depth=40, reorth=r)
+        Phi = np.hstack(lz.Q)
+        loss[r] = np.max(np.abs(Phi.T @ Phi - np.eye(Phi.shape[1])))
+    assert loss["local"] > 1e-7 and loss["alternate"] < 1e-13
+    mu = D.mu_midgap_dense(H, ws.n_electrons)
+    pa = D.density_matrix(H, color, sign, b, mu, 0.01, 40, rp, col, reorth="alternate")["p_val"]
+    pf = D.density_matrix(H, color, sign, b, mu, 0.01, 40, rp, col, reorth="full")["p_val"]
+    assert np.max(np.abs(pa - pf)) < 1e-13
 
 
 def test_three_term_relation_and_orthonormality():
