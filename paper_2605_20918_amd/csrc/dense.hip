@@ -1057,10 +1057,18 @@ __global__ __launch_bounds__(256) void k_chol_inv_reg(const double* __restrict__
 // A_ij -= R_ki^T R_kj and the blocked inverse X_ij = -X_ii sum_{k=i+1..j} R_ik X_kj
 // run on FP64 MFMA. The X_jj are kept in XD (D layout); the X_ij (i < j) are stored
 // transposed in the strictly lower block triangle of M. Four waves: wave 0 factors
-// and inverts the diagonal blocks; panel and trailing tiles are dealt to all four,
-// with a work-group barrier between the phases of a block step; the block columns
-// of the inverse are independent and dealt to the waves.
+// and inverts the diagonal blocks, the next one during the trailing update of the
+// current step (look-ahead), which waves 1..3 do for the other tiles; the panel
+// tiles are dealt to all four; two work-group barriers per block step; the block
+// columns of the inverse are independent and dealt to the waves.
 __device__ inline double lane_bcast(double v, int src) { return __shfl(v, src, 64); }
+// v of lane src (src the same in every lane): two readlanes, no lane permute
+__device__ inline double lane_read(double v, int src) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), src);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
 
 template <int NB>
 __device__ __forceinline__ void chol_inv_blk(const double* __restrict__ G, int b, int ld, const double* __restrict__ tau_p,
@@ -1093,64 +1101,79 @@ __device__ __forceinline__ void chol_inv_blk(const double* __restrict__ G, int b
     if (t == 0) sfail = 0;
     __syncthreads();
     double dmin = INFINITY;
-    for (int kb = 0; kb < NB; ++kb) {
+    // (a)-(c) of block kb by wave 0: unblocked Cholesky of the 16 x 16 diagonal block in
+    // registers (the pivot by readlane, rows and columns by lane permutes), R_kk into M,
+    // X_kk = R_kk^-1 by backward substitution into XD; a failure sets sfail
+    auto diag_block = [&](int kb) {
         const int o = 16 * kb;
-        if (wv == 0) {
-            // (a)-(b) diagonal block: unblocked Cholesky in registers (wave 0)
-            bool fail = false;
-            double a[4];
+        bool fail = false;
+        double a[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = M[(o + lr + 4 * r) * W + o + lc];
-            double dinv[16];
+        for (int r = 0; r < 4; ++r) a[r] = M[(o + lr + 4 * r) * W + o + lc];
+        double dinv[16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int rk = k >> 2, sl = 16 * (k & 3);
-                const double piv = lane_bcast(a[rk], sl + k);
-                double d = 1.0;
-                if (o + k < b && !fail) {                   // uniform: piv is the same in every lane
-                    if (!(piv > 0.0) || !isfinite(piv)) {
-                        fail = true;
-                    } else {
-                        d = sqrt(piv);
-                        dmin = fmin(dmin, d);
-                        if (!(d > tau)) fail = true;
-                    }
-                }
-                dinv[k] = 1.0 / d;                          // after a failure the block is discarded
-                if (lr == (k & 3)) a[rk] = lc > k ? a[rk] * dinv[k] : (lc == k ? d : 0.0);
-                const double vj = lane_bcast(a[rk], sl + lc);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const double vi = lane_bcast(a[rk], sl + lr + 4 * r);
-                    if (lr + 4 * r > k && lc >= lr + 4 * r) a[r] -= vi * vj;
+        for (int k = 0; k < 16; ++k) {
+            const int rk = k >> 2, sl = 16 * (k & 3);
+            const double piv = lane_read(a[rk], sl + k);
+            double d = 1.0;
+            if (o + k < b && !fail) {                   // uniform: piv is the same in every lane
+                if (!(piv > 0.0) || !isfinite(piv)) {
+                    fail = true;
+                } else {
+                    d = sqrt(piv);
+                    dmin = fmin(dmin, d);
+                    if (!(d > tau)) fail = true;
                 }
             }
-            if (fail) {
-                if (l == 0) sfail = 1;
-            } else {
+            dinv[k] = 1.0 / d;                          // after a failure the block is discarded
+            if (lr == (k & 3)) a[rk] = lc > k ? a[rk] * dinv[k] : (lc == k ? d : 0.0);
+            const double vj = lane_bcast(a[rk], sl + lc);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) M[(o + lr + 4 * r) * W + o + lc] = a[r];
-                // (c) X_kk = R_kk^-1 by backward substitution: row i of X is final once scaled
-                double x[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) x[r] = (lr + 4 * r == lc) ? 1.0 : 0.0;
-#pragma unroll
-                for (int i = 15; i >= 0; --i) {
-                    const int ri = i >> 2, si = 16 * (i & 3);
-                    if (lr == (i & 3)) x[ri] *= dinv[i];
-                    const double xij = lane_bcast(x[ri], si + lc);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const double rii = lane_bcast(a[r], 16 * lr + i);     // R_kk[lr + 4r][i]
-                        if (lr + 4 * r < i) x[r] -= rii * xij;
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) XD[kb * 256 + r * 64 + l] = x[r];
+            for (int r = 0; r < 4; ++r) {
+                const double vi = lane_bcast(a[rk], sl + lr + 4 * r);
+                if (lr + 4 * r > k && lc >= lr + 4 * r) a[r] -= vi * vj;
             }
         }
-        __syncthreads();
-        if (sfail) break;
+        if (fail) {
+            if (l == 0) sfail = 1;
+            return;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) M[(o + lr + 4 * r) * W + o + lc] = a[r];
+        double x[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = (lr + 4 * r == lc) ? 1.0 : 0.0;
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+            const int ri = i >> 2, si = 16 * (i & 3);
+            if (lr == (i & 3)) x[ri] *= dinv[i];
+            const double xij = lane_bcast(x[ri], si + lc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double rii = lane_bcast(a[r], 16 * lr + i);     // R_kk[lr + 4r][i]
+                if (lr + 4 * r < i) x[r] -= rii * xij;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) XD[kb * 256 + r * 64 + l] = x[r];
+    };
+    // A_ij -= R_ki^T R_kj for one tile
+    auto trailing = [&](int ib, int jb, int o) {
+        Mf::acc c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c[r] = M[(16 * ib + lr + 4 * r) * W + 16 * jb + lc];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+            c = Mf::mma(-M[(o + 4 * s4 + lr) * W + 16 * ib + lc], M[(o + 4 * s4 + lr) * W + 16 * jb + lc], c);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) M[(16 * ib + lr + 4 * r) * W + 16 * jb + lc] = c[r];
+    };
+    if (wv == 0) diag_block(0);
+    __syncthreads();
+    // Look-ahead: in block step kb, after the panel, wave 0 updates the next diagonal
+    // tile and factors it while waves 1..3 update the other trailing tiles.
+    for (int kb = 0; kb < NB && !sfail; ++kb) {
+        const int o = 16 * kb;
         // (d) panel R_kj = X_kk^T A_kj, tiles dealt to the waves
         for (int jb = kb + 1 + wv; jb < NB; jb += 4) {
             Mf::acc c = Mf::zero();
@@ -1161,21 +1184,24 @@ __device__ __forceinline__ void chol_inv_blk(const double* __restrict__ G, int b
             for (int r = 0; r < 4; ++r) M[(o + lr + 4 * r) * W + 16 * jb + lc] = c[r];
         }
         __syncthreads();
-        // (e) trailing update A_ij -= R_ki^T R_kj, kb < i <= j, tiles dealt to the waves
-        int tile = 0;
-        for (int ib = kb + 1; ib < NB; ++ib)
-            for (int jb = ib; jb < NB; ++jb, ++tile) {
-                if (tile % 4 != wv) continue;
-                Mf::acc c;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) c[r] = M[(16 * ib + lr + 4 * r) * W + 16 * jb + lc];
-#pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4)
-                    c = Mf::mma(-M[(o + 4 * s4 + lr) * W + 16 * ib + lc], M[(o + 4 * s4 + lr) * W + 16 * jb + lc], c);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) M[(16 * ib + lr + 4 * r) * W + 16 * jb + lc] = c[r];
+        if (kb + 1 < NB) {
+            const int k1 = kb + 1;
+            if (wv == 0) {
+                trailing(k1, k1, o);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // the tile's LDS writes before its reads
+                diag_block(k1);
+            } else {
+                // (e) the other trailing tiles kb < i <= j, dealt to waves 1..3
+                int tile = 0;
+                for (int ib = k1; ib < NB; ++ib)
+                    for (int jb = ib; jb < NB; ++jb) {
+                        if (ib == k1 && jb == k1) continue;
+                        if (tile++ % 3 != wv - 1) continue;
+                        trailing(ib, jb, o);
+                    }
             }
-        __syncthreads();
+            __syncthreads();
+        }
     }
     if (t == 0) min_diag[step] = dmin;
     if (sfail) {
