@@ -56,14 +56,14 @@ def test_10k_against_the_oracle():
     # the FP64 comparator of the bench re-orthogonalises locally: its oracle does the same
     t0 = time.perf_counter()
     ref_local = D.density_matrix(ws.H.to_scipy(), color, sign, b, MU, KT, wl["depth"], rp, col, reorth="local",
-                                 cholqr2=True)
+                                 cholqr2=bench.BENCH_CHOLQR2)
     print(f"10k: oracle with local re-orthogonalisation {time.perf_counter() - t0:.1f} s", flush=True)
     H32 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, "cuda", torch.float32)
     H64 = css.DeviceCSR.from_host(ws.H.row_ptr, ws.H.col, ws.H.val, "cuda", torch.float64)
     # the mixed path of the bench re-orthogonalises against every block on alternate steps
     t0 = time.perf_counter()
     ref_alt = D.density_matrix(ws.H.to_scipy(), color, sign, b, MU, KT, wl["depth"], rp, col, reorth="alternate",
-                               cholqr2=True)
+                               cholqr2=bench.BENCH_CHOLQR2)
     print(f"10k: oracle with the alternating schedule {time.perf_counter() - t0:.1f} s", flush=True)
     runs = {"mixed (bench)": (H32, bench.flags_for("fp32"), ref_alt),
             "fp64 alternate": (H64, bench.flags_for("fp64", reorth="full"), ref_alt),
