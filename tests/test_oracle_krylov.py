@@ -122,6 +122,26 @@ def test_alternate_schedule_keeps_fp64_orthonormality_where_local_loses_it():
     assert np.max(np.abs(pa - pf)) < 1e-13
 
 
+def test_one_cholesky_qr_suffices_after_reorthogonalisation():
+    """A re-orthogonalised W_j is close to orthogonal to the basis and well conditioned,
+    so one Cholesky QR leaves the basis orthonormal at rounding level (216 molecules,
+    depth 40: 2e-14 on the alternating schedule, 4e-15 with full) and P equal to the
+    CholQR2 result to rounding (measured 6e-15)."""
+    ws = synth.water_system(216, 3)
+    H = ws.H.to_scipy()
+    rp, col, deg = conflict_pattern(ws.orb_xyz, ws.box, 6.0)
+    color, b = greedy_color(rp, col, deg)
+    sign = probe_signs(ws.n, 3)
+    for r in ("alternate", "full"):
+        lz = block_lanczos(H, color, sign, b, depth=40, reorth=r, cholqr2=False)
+        Phi = np.hstack(lz.Q)
+        assert np.max(np.abs(Phi.T @ Phi - np.eye(Phi.shape[1]))) < 1e-13
+    mu = D.mu_midgap_dense(H, ws.n_electrons)
+    p1 = D.density_matrix(H, color, sign, b, mu, 0.01, 40, rp, col, reorth="alternate", cholqr2=False)["p_val"]
+    p2 = D.density_matrix(H, color, sign, b, mu, 0.01, 40, rp, col, reorth="full", cholqr2=True)["p_val"]
+    assert np.max(np.abs(p1 - p2)) < 1e-13
+
+
 def test_three_term_relation_and_orthonormality():
     ws, H, rp, col, color, b, sign = small_water(M=64, seed=20919)
     lz = block_lanczos(H, color, sign, b, depth=5)
