@@ -1050,7 +1050,8 @@ __global__ __launch_bounds__(256) void k_chol_inv_reg(const double* __restrict__
 
 // Blocks of 16 (NB blocks, b <= 16 NB): Cholesky G = R^T R of the leading b x b
 // block and X = R^-1.
-// LDS holds the 16NB x 16NB matrix M (row stride W): G's upper triangle, then R;
+// LDS holds the 16NB x 16NB matrix M (row stride W): G (mirrored from its upper
+// triangle), then R in the upper triangle;
 // rows/columns b..16NB-1 are padded with the identity. Diagonal blocks are factored
 // and inverted in registers (MFMA D layout: lane l holds rows (l>>4)+4r, column l&15)
 // with cross-lane broadcasts; panel solves R_kj = R_kk^-T A_kj, trailing updates
@@ -1061,15 +1062,6 @@ __global__ __launch_bounds__(256) void k_chol_inv_reg(const double* __restrict__
 // current step (look-ahead), which waves 1..3 do for the other tiles; the panel
 // tiles are dealt to all four; two work-group barriers per block step; the block
 // columns of the inverse are independent and dealt to the waves.
-__device__ inline double lane_bcast(double v, int src) { return __shfl(v, src, 64); }
-// v of lane src (src the same in every lane): two readlanes, no lane permute
-__device__ inline double lane_read(double v, int src) {
-    const long long u = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffLL), src);
-    const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), src);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-
 template <int NB>
 __device__ __forceinline__ void chol_inv_blk(const double* __restrict__ G, int b, int ld, const double* __restrict__ tau_p,
                              double* __restrict__ R, double* __restrict__ Rinv, int* state, int step,
@@ -1082,14 +1074,16 @@ __device__ __forceinline__ void chol_inv_blk(const double* __restrict__ G, int b
     const int t = threadIdx.x, l = t & 63, wv = t >> 6, lr = l >> 4, lc = l & 15;
     const double tau = tau_p ? *tau_p : 0.0;
     {
-        // every element of the upper triangle once, all loads issued before the LDS stores
+        // G from its upper triangle, mirrored (the diagonal tiles stay symmetric through
+        // the trailing updates, so their factorisation reads a pivot column in-row); all
+        // loads issued before the LDS stores
         constexpr int PER = (N * N + 255) / 256;
         double v[PER];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = t + 256 * q;
             const int i = e / N, j = e % N;
-            v[q] = (e < N * N && i < b && j < b && j >= i) ? G[(int64_t)i * ld + j] : 0.0;
+            v[q] = (e < N * N && i < b && j < b) ? G[(int64_t)min(i, j) * ld + max(i, j)] : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -1101,9 +1095,10 @@ __device__ __forceinline__ void chol_inv_blk(const double* __restrict__ G, int b
     if (t == 0) sfail = 0;
     __syncthreads();
     double dmin = INFINITY;
-    // (a)-(c) of block kb by wave 0: unblocked Cholesky of the 16 x 16 diagonal block in
-    // registers (the pivot by readlane, rows and columns by lane permutes), R_kk into M,
-    // X_kk = R_kk^-1 by backward substitution into XD; a failure sets sfail
+    // (a)-(c) of block kb by wave 0: unblocked Cholesky of the symmetric 16 x 16 diagonal
+    // block in registers (pivot by readlane, the pivot row to every row group by lane
+    // swaps, the pivot column within each row group by DPP broadcast: VALU moves only),
+    // R_kk into M, X_kk = R_kk^-1 by backward substitution into XD; a failure sets sfail
     auto diag_block = [&](int kb) {
         const int o = 16 * kb;
         bool fail = false;
@@ -1111,29 +1106,33 @@ __device__ __forceinline__ void chol_inv_blk(const double* __restrict__ G, int b
 #pragma unroll
         for (int r = 0; r < 4; ++r) a[r] = M[(o + lr + 4 * r) * W + o + lc];
         double dinv[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int rk = k >> 2, sl = 16 * (k & 3);
-            const double piv = lane_read(a[rk], sl + k);
-            double d = 1.0;
+        static_steps([&](auto kc) {
+            constexpr int k = decltype(kc)::value, rk = k >> 2, g = k & 3;
+            const double piv = lane_read(a[rk], 16 * g + k);
+            double d = 1.0, di = 1.0;
             if (o + k < b && !fail) {                   // uniform: piv is the same in every lane
                 if (!(piv > 0.0) || !isfinite(piv)) {
                     fail = true;
                 } else {
-                    d = sqrt(piv);
+                    di = rsqrt_newton(piv);
+                    d = piv * di;
                     dmin = fmin(dmin, d);
                     if (!(d > tau)) fail = true;
                 }
             }
-            dinv[k] = 1.0 / d;                          // after a failure the block is discarded
-            if (lr == (k & 3)) a[rk] = lc > k ? a[rk] * dinv[k] : (lc == k ? d : 0.0);
-            const double vj = lane_bcast(a[rk], sl + lc);
+            dinv[k] = di;                               // after a failure the block is discarded
+            double c[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const double vi = lane_bcast(a[rk], sl + lr + 4 * r);
-                if (lr + 4 * r > k && lc >= lr + 4 * r) a[r] -= vi * vj;
+            for (int r = 0; r < 4; ++r) c[r] = col_bcast<k>(a[r]);      // column k of my rows
+            const double rk_row = lc > k ? a[rk] * di : (lc == k ? d : 0.0);   // R_k,lc
+            a[rk] = lr == g ? rk_row : a[rk];
+            const double vj = grp_bcast<g>(rk_row);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {                               // both triangles, branch-free
+                const double upd = __builtin_fma(-(c[r] * di), vj, a[r]);
+                a[r] = (lr + 4 * r > k && lc > k) ? upd : a[r];
             }
-        }
+        }, std::make_integer_sequence<int, 16>{});
         if (fail) {
             if (l == 0) sfail = 1;
             return;
@@ -1143,17 +1142,18 @@ __device__ __forceinline__ void chol_inv_blk(const double* __restrict__ G, int b
         double x[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) x[r] = (lr + 4 * r == lc) ? 1.0 : 0.0;
-#pragma unroll
-        for (int i = 15; i >= 0; --i) {
-            const int ri = i >> 2, si = 16 * (i & 3);
-            if (lr == (i & 3)) x[ri] *= dinv[i];
-            const double xij = lane_bcast(x[ri], si + lc);
+        static_steps([&](auto ic) {
+            constexpr int i = 15 - decltype(ic)::value, ri = i >> 2, g = i & 3;
+            const double xrow = x[ri] * dinv[i];                        // X row i, column lc
+            x[ri] = lr == g ? xrow : x[ri];
+            const double xij = grp_bcast<g>(xrow);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const double rii = lane_bcast(a[r], 16 * lr + i);     // R_kk[lr + 4r][i]
-                if (lr + 4 * r < i) x[r] -= rii * xij;
+                const double rii = col_bcast<i>(a[r]);                 // R_kk[lr + 4r][i]
+                const double upd = __builtin_fma(-rii, xij, x[r]);
+                x[r] = lr + 4 * r < i ? upd : x[r];
             }
-        }
+        }, std::make_integer_sequence<int, 16>{});
 #pragma unroll
         for (int r = 0; r < 4; ++r) XD[kb * 256 + r * 64 + l] = x[r];
     };

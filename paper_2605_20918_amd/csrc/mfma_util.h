@@ -15,6 +15,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 namespace css {
 
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
@@ -38,6 +41,63 @@ struct Mfma<float> {
     __device__ static acc mma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
     __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
 };
+
+// Cross-lane moves for a 16 x 16 FP64 tile held in the D layout (row group g = lanes
+// 16g .. 16g+15 holds rows g + 4r, lane 16g + c column c), all on the VALU:
+//   lane_read(v, s): v of lane s in every lane (two readlanes; s uniform);
+//   col_bcast<K>(v): v of lane K of the lane's own row group (DPP row_newbcast), i.e.
+//     the element of column K in each of the lane's rows;
+//   grp_bcast<G>(v): v of the lane in row group G with the lane's own column, i.e. a
+//     row held by group G sent to every group (permlane32_swap gives groups 0,1,0,1 and
+//     2,3,2,3; permlane16_swap of either gives a,a,a,a and b,b,b,b).
+__device__ __forceinline__ double lane_read(double v, int src) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), src);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+template <int K>
+__device__ __forceinline__ double col_bcast(double v) {     // one 64-bit DPP move
+    static_assert(K >= 0 && K < 16, "lane within a row group");
+    return __longlong_as_double(__builtin_amdgcn_mov_dpp(__double_as_longlong(v), 0x150 + K, 0xf, 0xf, true));
+}
+template <int G>
+__device__ __forceinline__ int grp_bcast32(int x) {
+    static_assert(G >= 0 && G < 4, "row group");
+    const auto h = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    const int y = static_cast<int>(h[G >> 1]);
+    const auto q = __builtin_amdgcn_permlane16_swap(y, y, false, false);
+    return static_cast<int>(q[G & 1]);
+}
+template <int G>
+__device__ __forceinline__ double grp_bcast(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = grp_bcast32<G>(static_cast<int>(u & 0xffffffffLL));
+    const int hi = grp_bcast32<G>(static_cast<int>(u >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+// f(std::integral_constant<int, K>) for K = 0 .. N-1 in order (compile-time step index)
+template <typename F, int... K>
+__device__ __forceinline__ void static_steps(F&& f, std::integer_sequence<int, K...>) {
+    (f(std::integral_constant<int, K>{}), ...);
+}
+// 1/x and 1/sqrt(x) for positive normal x: the hardware estimate refined by two Newton
+// steps, r <- r + r (1 - x r) and r <- r + (r/2)(1 - x r^2); each step squares the
+// relative error, so the result is within a few units in the last place.
+__device__ __forceinline__ double recip_newton(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ double rsqrt_newton(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    double e = __builtin_fma(-x * r, r, 1.0);
+    r = __builtin_fma(0.5 * r, e, r);
+    e = __builtin_fma(-x * r, r, 1.0);
+    return __builtin_fma(0.5 * r, e, r);
+}
 
 // Work-group barrier that orders LDS accesses only: the LDS writes before it are
 // complete (release at work-group scope, LDS only) when the waves meet, and the

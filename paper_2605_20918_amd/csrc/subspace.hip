@@ -664,19 +664,14 @@ __global__ __launch_bounds__(kPoleThreads) void k_pole_solve(const double* __res
 constexpr int kBlkThreads = 512;     // 8 waves: 256 registers per lane, no spills
 constexpr int kBlkWaves = kBlkThreads / 64;
 
-__device__ inline double pole_bcast(double v, int src) { return __shfl(v, src, 64); }
-// v of lane src (src the same in every lane): two readlanes, no lane permute
-__device__ inline double lane_read(double v, int src) {
-    const long long u = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffLL), src);
-    const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), src);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-
 // Wave 0: the 16 x 16 diagonal block at (o, o) of S inverted in registers (Gauss-Jordan
 // without pivoting, MFMA D layout: lane l holds rows (l>>4)+4r, column l&15) into Pr/Pi
-// (row stride 17). The pivot itself comes by readlane (its lane is known), the pivot
-// row and column by lane permutes.
+// (row stride 17). Step k needs the pivot (readlane), the pivot row in every row group
+// (grp_bcast) and the pivot column in every lane of each row (col_bcast): VALU moves
+// only. The step is one formula for every element, branch-free: with m = 0 in the pivot
+// column and 1 elsewhere, and t_j = x_kj / p (j != k), t_k = 1 / p,
+//   x_ij <- m_j x_ij - x_ik t_j   (rows i != k; gives -x_ik / p in the pivot column),
+// and the pivot row is then replaced by t.
 template <int NB>
 __device__ __forceinline__ void pivot_inverse(const double* Sr, const double* Si, int o, double* Pr, double* Pi) {
     constexpr int SW = 16 * NB + 1;
@@ -687,38 +682,33 @@ __device__ __forceinline__ void pivot_inverse(const double* Sr, const double* Si
         xr[r] = Sr[(o + lr + 4 * r) * SW + o + lc];
         xi[r] = Si[(o + lr + 4 * r) * SW + o + lc];
     }
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int rk = k >> 2, sk = 16 * (k & 3);
-        const double pr = lane_read(xr[rk], sk + k), pi = lane_read(xi[rk], sk + k);
-        const double den = 1.0 / (pr * pr + pi * pi);
+    static_steps([&](auto kc) {
+        constexpr int k = decltype(kc)::value, rk = k >> 2, g = k & 3;
+        const bool pc = lc == k;                                          // pivot column
+        const double pr = lane_read(xr[rk], 16 * g + k), pi = lane_read(xi[rk], 16 * g + k);
+        const double den = recip_newton(pr * pr + pi * pi);
         const double qr = pr * den, qi = -pi * den;                       // 1 / pivot
-        const double mr = pole_bcast(xr[rk], sk + lc), mi = pole_bcast(xi[rk], sk + lc);
-        const double rr = mr * qr - mi * qi, ri = mr * qi + mi * qr;      // pivot row / pivot
+        const double mr = grp_bcast<g>(xr[rk]), mi = grp_bcast<g>(xi[rk]);
+        const double tr = pc ? qr : mr * qr - mi * qi;                    // t = pivot row / pivot
+        const double ti = pc ? qi : mr * qi + mi * qr;
+        const double m = pc ? 0.0 : 1.0;
         double cr[4], ci[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {                                     // column k, my rows
-            cr[r] = pole_bcast(xr[r], 16 * lr + k);
-            ci[r] = pole_bcast(xi[r], 16 * lr + k);
+            cr[r] = col_bcast<k>(xr[r]);
+            ci[r] = col_bcast<k>(xi[r]);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int i = lr + 4 * r;
-            double nr, ni;
-            if (i == k) {
-                nr = (lc == k) ? qr : rr;
-                ni = (lc == k) ? qi : ri;
-            } else if (lc == k) {
-                nr = -(cr[r] * qr - ci[r] * qi);
-                ni = -(cr[r] * qi + ci[r] * qr);
-            } else {
-                nr = xr[r] - (cr[r] * rr - ci[r] * ri);
-                ni = xi[r] - (cr[r] * ri + ci[r] * rr);
-            }
+            const double nr = __builtin_fma(xr[r], m, __builtin_fma(ci[r], ti, -cr[r] * tr));
+            const double ni = __builtin_fma(xi[r], m, -__builtin_fma(cr[r], ti, ci[r] * tr));
             xr[r] = nr;
             xi[r] = ni;
         }
-    }
+        const bool prow = lr == g;                                        // row k
+        xr[rk] = prow ? tr : xr[rk];
+        xi[rk] = prow ? ti : xi[rk];
+    }, std::make_integer_sequence<int, 16>{});
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         Pr[(lr + 4 * r) * 17 + lc] = xr[r];
