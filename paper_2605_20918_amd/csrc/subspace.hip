@@ -716,9 +716,11 @@ __device__ __forceinline__ void pivot_inverse(const double* Sr, const double* Si
     }
 }
 
-// Trailing update of one tile: S_ij -= S_ik S_kj (k = kb, complex, FP64 MFMA).
+// Trailing update of one tile with the new column block C (column kb) and the old
+// row block (row kb): S_ij += C_ik S_kj (complex, FP64 MFMA). With mirror, the tile's
+// transpose times sgn also goes to (jb, ib).
 template <int NB>
-__device__ __forceinline__ void trailing_tile(double* Sr, double* Si, int ib, int jb, int kb) {
+__device__ __forceinline__ void trailing_tile(double* Sr, double* Si, int ib, int jb, int kb, bool mirror, double sgn) {
     constexpr int SW = 16 * NB + 1;
     const int lane = threadIdx.x & 63, lr = lane >> 4, lc = lane & 15;
     const int o = 16 * kb;
@@ -733,35 +735,72 @@ __device__ __forceinline__ void trailing_tile(double* Sr, double* Si, int ib, in
         const int k = o + 4 * s4 + lr;
         const double ar = Sr[(16 * ib + lc) * SW + k], ai = Si[(16 * ib + lc) * SW + k];
         const double br = Sr[k * SW + 16 * jb + lc], bi = Si[k * SW + 16 * jb + lc];
-        cr = mfma64(-ar, br, cr);
-        cr = mfma64(ai, bi, cr);
-        ci = mfma64(-ar, bi, ci);
-        ci = mfma64(-ai, br, ci);
+        cr = mfma64(ar, br, cr);
+        cr = mfma64(-ai, bi, cr);
+        ci = mfma64(ar, bi, ci);
+        ci = mfma64(ai, br, ci);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         Sr[(16 * ib + lr + 4 * r) * SW + 16 * jb + lc] = cr[r];
         Si[(16 * ib + lr + 4 * r) * SW + 16 * jb + lc] = ci[r];
     }
+    if (mirror) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Sr[(16 * jb + lc) * SW + 16 * ib + lr + 4 * r] = sgn * cr[r];
+            Si[(16 * jb + lc) * SW + 16 * ib + lr + 4 * r] = sgn * ci[r];
+        }
+    }
 }
 
-// S (16 NB x 16 NB complex, in LDS) replaced by its inverse, block Gauss-Jordan without
-// pivoting. P holds two pivot inverses (re/im, 16 x 17 each; P + 2*272 q for buffer q).
-// Look-ahead: in block step kb, once the row block is updated, wave 0 updates the next
-// diagonal tile (kb+1, kb+1) and inverts it into the other buffer while the other waves
-// update the rest of the trailing tiles, so the sequential 16 x 16 inversions overlap
-// the MFMA updates; then the column block and S_kk <- P. Three barriers per block step.
+// S (16 NB x 16 NB complex symmetric, in LDS) replaced by its inverse, block
+// Gauss-Jordan without pivoting. After the pivots K = {0 .. k-1} the matrix is
+// [[A_KK^-1, A_KK^-1 A_KU], [-A_UK A_KK^-1, Schur complement]]: symmetric within K x K
+// and U x U and antisymmetric between them (M_UK = -M_KU^T). Block step k therefore
+// needs only the row block R_kj = P S_kj (P = S_kk^-1, symmetric): the column block
+// -S_ik P equals -R_ki^T for i > k and R_ki^T for i < k. The trailing update
+// S_ij += C_ik S_kj (old row block) is computed for i <= j and mirrored with that sign
+// rule. P holds two pivot inverses (re/im, 16 x 17 each; P + 2*272 q for buffer q).
+// Per block step: waves 0 .. NB-2 compute the row tiles into registers and write the
+// column block; barrier; wave 0 updates the next diagonal tile and inverts it into the
+// other buffer (look-ahead) while waves 1 .. 7 update the other upper trailing tiles;
+// barrier; the row tiles go to row k at the start of the next step (the tile in
+// column k+1 is superseded there by the next column block) with S_kk <- P.
 template <int NB>
 __device__ void gj_inverse_blk(double* Sr, double* Si, double* P) {
     constexpr int SW = 16 * NB + 1, PB = 2 * 16 * 17;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane >> 4, lc = lane & 15;
     if (wave == 0) pivot_inverse<NB>(Sr, Si, 0, P, P + 16 * 17);
     __syncthreads();
+    pd4 hr = {0, 0, 0, 0}, hi = {0, 0, 0, 0};             // this wave's row tile of the previous step
+    int hj = -1;                                          // its block column (-1: none)
+    auto put_row = [&](int kprev, int skip) {             // row tiles and P of block step kprev
+        const int op = 16 * kprev;
+        if (hj >= 0 && hj != skip) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Sr[(op + lr + 4 * r) * SW + 16 * hj + lc] = hr[r];
+                Si[(op + lr + 4 * r) * SW + 16 * hj + lc] = hi[r];
+            }
+        }
+        if (wave == kBlkWaves - 1) {
+            const double* Qr = P + (kprev & 1) * PB;
+            const double* Qi = Qr + 16 * 17;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Sr[(op + lr + 4 * r) * SW + op + lc] = Qr[(lr + 4 * r) * 17 + lc];
+                Si[(op + lr + 4 * r) * SW + op + lc] = Qi[(lr + 4 * r) * 17 + lc];
+            }
+        }
+    };
     for (int kb = 0; kb < NB; ++kb) {
         const int o = 16 * kb;
         const double* Pr = P + (kb & 1) * PB;
         const double* Pi = Pr + 16 * 17;
-        if (wave < NB - 1) {                                  // row block: S_kj <- P S_kj
+        if (kb > 0) put_row(kb - 1, kb);
+        hj = -1;
+        if (wave < NB - 1) {                                  // row block R_kj = P S_kj
             const int jb = wave < kb ? wave : wave + 1;
             pd4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
 #pragma unroll
@@ -774,62 +813,45 @@ __device__ void gj_inverse_blk(double* Sr, double* Si, double* P) {
                 ci = mfma64(ar, bi, ci);
                 ci = mfma64(ai, br, ci);
             }
+            const double sg = jb < kb ? 1.0 : -1.0;           // column block C_jk = sg R_kj^T
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                Sr[(o + lr + 4 * r) * SW + 16 * jb + lc] = cr[r];
-                Si[(o + lr + 4 * r) * SW + 16 * jb + lc] = ci[r];
+                Sr[(16 * jb + lc) * SW + o + lr + 4 * r] = sg * cr[r];
+                Si[(16 * jb + lc) * SW + o + lr + 4 * r] = sg * ci[r];
             }
+            hr = cr;
+            hi = ci;
+            hj = jb;
         }
         __syncthreads();
         if constexpr (NB > 1) {
             const int k1 = kb + 1;
             const bool ahead = k1 < NB;                        // a next pivot exists
             if (ahead && wave == 0) {
-                trailing_tile<NB>(Sr, Si, k1, k1, kb);
+                trailing_tile<NB>(Sr, Si, k1, k1, kb, false, 1.0);
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // the tile's LDS writes before its reads
                 double* Qr = P + (k1 & 1) * PB;
                 pivot_inverse<NB>(Sr, Si, 16 * k1, Qr, Qr + 16 * 17);
             } else {
-                // the trailing tiles (i, j != kb): all of them to every wave in the last
-                // block step, all but (k1, k1) to waves 1.. before it
+                // the upper trailing tiles i <= j (i, j != kb), mirrored: all of them to every
+                // wave in the last block step, all but (k1, k1) to waves 1.. before it
                 const int w0 = ahead ? wave - 1 : wave, nw = ahead ? kBlkWaves - 1 : kBlkWaves;
-                for (int t = w0; t < (NB - 1) * (NB - 1); t += nw) {
-                    int ib = t / (NB - 1), jb = t % (NB - 1);
+                constexpr int NU = (NB - 1) * NB / 2;
+                for (int t = w0; t < NU; t += nw) {
+                    int ib = 0, rem = t;                        // t-th pair i <= j of 0 .. NB-2
+                    while (rem >= NB - 1 - ib) { rem -= NB - 1 - ib; ++ib; }
+                    int jb = ib + rem;
                     ib += ib >= kb;
                     jb += jb >= kb;
                     if (ahead && ib == k1 && jb == k1) continue;
-                    trailing_tile<NB>(Sr, Si, ib, jb, kb);
+                    trailing_tile<NB>(Sr, Si, ib, jb, kb, ib != jb, (ib < kb) == (jb < kb) ? 1.0 : -1.0);
                 }
             }
         }
         __syncthreads();
-        if (wave < NB - 1) {                                  // column block: S_ik <- -S_ik P
-            const int ib = wave < kb ? wave : wave + 1;
-            pd4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-                const int k = 4 * s4 + lr;
-                const double ar = Sr[(16 * ib + lc) * SW + o + k], ai = Si[(16 * ib + lc) * SW + o + k];
-                const double br = Pr[k * 17 + lc], bi = Pi[k * 17 + lc];
-                cr = mfma64(-ar, br, cr);
-                cr = mfma64(ai, bi, cr);
-                ci = mfma64(-ar, bi, ci);
-                ci = mfma64(-ai, br, ci);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                Sr[(16 * ib + lr + 4 * r) * SW + o + lc] = cr[r];
-                Si[(16 * ib + lr + 4 * r) * SW + o + lc] = ci[r];
-            }
-        } else if (wave == NB - 1) {                          // S_kk <- P
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                Sr[(o + lr + 4 * r) * SW + o + lc] = Pr[(lr + 4 * r) * 17 + lc];
-                Si[(o + lr + 4 * r) * SW + o + lc] = Pi[(lr + 4 * r) * 17 + lc];
-            }
-        }
-        __syncthreads();
     }
+    put_row(NB - 1, -1);
+    __syncthreads();
 }
 
 template <int NB>
@@ -908,11 +930,16 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
             }
         }
         __syncthreads();
-        // S_{j-1} = I - i a (A_{j-1} - mu) + i a B_{j-1}^T G_j; row m of B^T has no
-        // entries beyond column m, so tile row m0 needs the chunks of k < m0 + 16 only
+        // S_{j-1} = I - i a (A_{j-1} - mu) + i a B_{j-1}^T G_j, complex symmetric
+        // (B^T G_j = -i a B^T S_j^-1 B): the upper tiles m0 <= c0 only, each mirrored. Row
+        // m of B^T has no entries beyond column m, so tile row m0 needs the chunks of
+        // k < m0 + 16 only; the tiles are dealt from the last tile row up (costliest first).
         const double* Aj = A + (int64_t)(j - 1) * mat;
-        for (int t = wave; t < NTL; t += kBlkWaves) {
-            const int m0 = (t / NB) * 16, c0 = (t % NB) * 16;
+        constexpr int NU = NB * (NB + 1) / 2;
+        for (int t = wave; t < NU; t += kBlkWaves) {
+            int mb = NB - 1, rem = t;                          // tile rows NB-1, NB-2, ..: NB - mb tiles each
+            while (rem >= NB - mb) { rem -= NB - mb; --mb; }
+            const int m0 = 16 * mb, c0 = 16 * (mb + rem);
             pd4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
             constexpr int H = 8, NH = (N / 4 + H - 1) / H;      // K in chunks of 8 steps of global operands
             const int hmax = (m0 + 16 + 4 * H - 1) / (4 * H);
@@ -940,8 +967,13 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + lr + 4 * r, col = c0 + lc;
                 const double am = (row < b && col < b) ? Aj[(int64_t)row * ld + col] - (row == col ? mu : 0.0) : 0.0;
-                Sr[row * SW + col] = (row == col ? 1.0 : 0.0) - a * ti[r];
-                Si[row * SW + col] = -a * am + a * tr[r];
+                const double vr = (row == col ? 1.0 : 0.0) - a * ti[r], vi = -a * am + a * tr[r];
+                Sr[row * SW + col] = vr;
+                Si[row * SW + col] = vi;
+                if (m0 != c0) {
+                    Sr[col * SW + row] = vr;
+                    Si[col * SW + row] = vi;
+                }
             }
         }
         __syncthreads();
