@@ -149,9 +149,16 @@ __global__ __launch_bounds__(64 * WPG * KS) void k_gram(const T* __restrict__ X,
 }
 
 // Sum of the chunk partials in a fixed order: thread group g (of 16) adds chunks
-// g, g+16, ... for 64 consecutive entries, then the group sums are added in
-// order. mode 0: plain; 1: (S + S^T)/2; 2: out += (S + S^T)/2.
+// g, g+16, ... for 64 entries, then the group sums are added in order. mode 0: plain,
+// 64 consecutive entries per work-group; 1: (S + S^T)/2; 2: out += (S + S^T)/2. The
+// symmetrised modes take an 8 x 8 tile (bi, bj) per work-group: lane e = 8r + c adds
+// entry (r, c) of tile (bi, bj) and entry (r, c) of tile (bj, bi), both read as rows
+// of 8, and S^T's entry comes from the lane 8c + r through LDS.
 constexpr int kRedGroups = 16;
+static unsigned reduce_blocks(int ld, int mode) {
+    return mode == 0 ? static_cast<unsigned>(grid_for((int64_t)ld * ld, 64))
+                     : static_cast<unsigned>(((ld + 7) / 8) * ((ld + 7) / 8));
+}
 
 template <typename PT>
 __global__ __launch_bounds__(64 * kRedGroups) void k_gram_reduce(const PT* __restrict__ partial, int nchunk, int ld,
@@ -161,26 +168,38 @@ __global__ __launch_bounds__(64 * kRedGroups) void k_gram_reduce(const PT* __res
     __shared__ double s1s[kRedGroups][64], s2s[kRedGroups][64];
     const int p = blockIdx.y;
     const int g = threadIdx.x >> 6, e = threadIdx.x & 63;
-    const int idx = blockIdx.x * 64 + e;
     const int64_t mat = (int64_t)ld * ld;
-    const bool valid = idx < ld * ld;
-    const int i = valid ? idx / ld : 0, j = valid ? idx % ld : 0;
+    int i, j, i2 = 0, j2 = 0;
+    bool valid, valid2 = false;
+    if (mode == 0) {
+        const int idx = blockIdx.x * 64 + e;
+        valid = idx < ld * ld;
+        i = valid ? idx / ld : 0;
+        j = valid ? idx % ld : 0;
+    } else {
+        const int nt = (ld + 7) / 8;
+        const int bi = (int)blockIdx.x / nt, bj = (int)blockIdx.x % nt, r = e >> 3, c = e & 7;
+        i = 8 * bi + r;
+        j = 8 * bj + c;
+        i2 = 8 * bj + r;                                       // entry (r, c) of tile (bj, bi)
+        j2 = 8 * bi + c;
+        valid = i < ld && j < ld;
+        valid2 = i2 < ld && j2 < ld;
+    }
     const int64_t sij = (sym && i > j) ? (int64_t)j * ld + i : (int64_t)i * ld + j;
-    const int64_t sji = (sym && j > i) ? (int64_t)i * ld + j : (int64_t)j * ld + i;
+    const int64_t s2ij = (sym && i2 > j2) ? (int64_t)j2 * ld + i2 : (int64_t)i2 * ld + j2;
     const PT* base = partial + (int64_t)p * nchunk * mat;
     double s1 = 0.0, s2 = 0.0;
-    if (valid) {
-        // chunks g, g+16, ... added in that order; unrolled so the loads are issued together
-        if (mode != 0) {
+    // chunks g, g+16, ... added in that order; unrolled so the loads are issued together
+    if (mode != 0) {
 #pragma unroll 8
-            for (int c = g; c < nchunk; c += kRedGroups) {
-                s1 += (double)base[c * mat + sij];
-                s2 += (double)base[c * mat + sji];
-            }
-        } else {
-#pragma unroll 8
-            for (int c = g; c < nchunk; c += kRedGroups) s1 += (double)base[c * mat + sij];
+        for (int c = g; c < nchunk; c += kRedGroups) {
+            if (valid) s1 += (double)base[c * mat + sij];
+            if (valid2) s2 += (double)base[c * mat + s2ij];
         }
+    } else if (valid) {
+#pragma unroll 8
+        for (int c = g; c < nchunk; c += kRedGroups) s1 += (double)base[c * mat + sij];
     }
     s1s[g][e] = s1;
     s2s[g][e] = s2;
@@ -190,10 +209,11 @@ __global__ __launch_bounds__(64 * kRedGroups) void k_gram_reduce(const PT* __res
         for (int q = 0; q < kRedGroups; ++q) t1 += s1s[q][e];
         double v = t1;
         if (mode != 0) {
-            for (int q = 0; q < kRedGroups; ++q) t2 += s2s[q][e];
+            const int et = 8 * (e & 7) + (e >> 3);             // S_ji: lane (c, r) of the mirror tile
+            for (int q = 0; q < kRedGroups; ++q) t2 += s2s[q][et];
             v = 0.5 * (t1 + t2);
         }
-        double* o = out + p * out_stride + idx;
+        double* o = out + p * out_stride + (int64_t)i * ld + j;
         if (mode == 2)
             *o += v;
         else
@@ -1680,7 +1700,7 @@ void gram_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, dou
     } else {
         gram_tw_launch<T, 4, 4, false>(g, X, xstride, Y, part, ntw, state, s);
     }
-    dim3 rgrid(grid_for((int64_t)g.ld * g.ld, 64), g.nprod);
+    dim3 rgrid(reduce_blocks(g.ld, mode), g.nprod);
     k_gram_reduce<T><<<rgrid, 64 * kRedGroups, 0, s>>>(part, g.nchunk, g.ld, g.sym ? 1 : 0, mode, out, out_stride,
                                                         state);
 }
@@ -1945,7 +1965,7 @@ void gram_blocks_launch<float>(const float* X, int64_t xstride, int nprod, const
         case 5: gram_split_one<5>(g, X, xstride, Y, Yp, hinf, part, state, s); break;
         default: gram_split_one<6>(g, X, xstride, Y, Yp, hinf, part, state, s); break;
     }
-    dim3 rgrid(grid_for((int64_t)ld * ld, 64), nprod);
+    dim3 rgrid(reduce_blocks(ld, mode), nprod);
     k_gram_reduce<float><<<rgrid, 64 * kRedGroups, 0, s>>>(part, g.nchunk, ld, 0, mode, out, out_stride, state);
 }
 
