@@ -22,10 +22,20 @@ int64_t gram_partial_mats(int ld);                 // capacity (in ld x ld matri
 // is longer than a fixed row count (1 for FP64); reserve nprod times this.
 int64_t gram_min_chunks(int64_t Np, int ld, int elem);
 
+// Further outputs of a Gram's reduction, in place of separate small kernels:
+// copy (mode 1): the symmetrised result also written here; sym_to, sym_p: for product
+// sym_p of the launch, sym_to += (S + S^T)/2 as well (any mode).
+struct GramExtra {
+    double* copy = nullptr;
+    double* sym_to = nullptr;
+    int sym_p = -1;
+};
+
 // mode: 0 = plain, 1 = (S + S^T)/2, 2 = add (S + S^T)/2 into out (out += sym)
 template <typename T>
 void gram_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, double* partial,
-                 double* out, int64_t out_stride, int mode, const int* state, hipStream_t s);
+                 double* out, int64_t out_stride, int mode, const int* state, hipStream_t s,
+                 const GramExtra& ex = GramExtra());
 
 // OUT = alpha*IN + sum_p X_p * op_p(S_p),  op_p(S) = scale * (trans ? S^T : S)
 // X_p = X + p*xstride (tall), S_p = S + p*sstride (small FP64). OUT may equal IN;
@@ -72,7 +82,8 @@ void update2_launch(T* OUT, const T* IN, double alpha, const T* X0, const double
 template <typename T>
 void gram_blocks_launch(const T* X, int64_t xstride, int nprod, const T* Y, int64_t Np, int ld, bool sym,
                         int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
-                        const int* state, hipStream_t s, void* yplanes = nullptr, const double* hinf = nullptr);
+                        const int* state, hipStream_t s, void* yplanes = nullptr, const double* hinf = nullptr,
+                        const GramExtra& ex = GramExtra());
 
 // update_launch for coefficient blocks S_p that are small corrections (full
 // reorthogonalisation after the three-term update). FP32 blocks with ld a multiple
@@ -97,8 +108,6 @@ void chol_inv_launch(const double* G, int b, int ld, const double* tau, double* 
 void chol_inv_near_identity_launch(const double* G, int b, int ld, double thresh, double* R, double* Rinv,
                                    double* scratch, int* state, int step, double* min_diag, hipStream_t s);
 
-// A += (C + C^T)/2 (ld x ld)
-void sym_add_launch(const double* C, double* A, int ld, const int* state, hipStream_t s);
 
 // R = R2 * R1 (upper triangular, ld x ld)
 void trmm_upper_launch(const double* R2, const double* R1, double* R, int ld, const int* state,

@@ -151,27 +151,31 @@ __global__ __launch_bounds__(64 * WPG * KS) void k_gram(const T* __restrict__ X,
 // Sum of the chunk partials in a fixed order: thread group g (of 16) adds chunks
 // g, g+16, ... for 64 entries, then the group sums are added in order. mode 0: plain,
 // 64 consecutive entries per work-group; 1: (S + S^T)/2; 2: out += (S + S^T)/2. The
-// symmetrised modes take an 8 x 8 tile (bi, bj) per work-group: lane e = 8r + c adds
+// symmetrised outputs take an 8 x 8 tile (bi, bj) per work-group: lane e = 8r + c adds
 // entry (r, c) of tile (bi, bj) and entry (r, c) of tile (bj, bi), both read as rows
-// of 8, and S^T's entry comes from the lane 8c + r through LDS.
+// of 8, and S^T's entry comes from the lane 8c + r through LDS. copy: mode 1's result
+// also written there; product sym_p (tiled in any mode): sym_to += (S + S^T)/2.
 constexpr int kRedGroups = 16;
-static unsigned reduce_blocks(int ld, int mode) {
-    return mode == 0 ? static_cast<unsigned>(grid_for((int64_t)ld * ld, 64))
-                     : static_cast<unsigned>(((ld + 7) / 8) * ((ld + 7) / 8));
+static unsigned reduce_blocks(int ld, bool tiled) {
+    const int64_t lin = grid_for((int64_t)ld * ld, 64), til = (int64_t)((ld + 7) / 8) * ((ld + 7) / 8);
+    return static_cast<unsigned>(tiled ? std::max(lin, til) : lin);
 }
 
 template <typename PT>
 __global__ __launch_bounds__(64 * kRedGroups) void k_gram_reduce(const PT* __restrict__ partial, int nchunk, int ld,
                                                                 int sym, int mode, double* __restrict__ out,
-                                                                int64_t out_stride, const int* __restrict__ state) {
+                                                                int64_t out_stride, const int* __restrict__ state,
+                                                                double* __restrict__ copy, double* __restrict__ sym_to,
+                                                                int sym_p) {
     if (state && state[0]) return;
     __shared__ double s1s[kRedGroups][64], s2s[kRedGroups][64];
     const int p = blockIdx.y;
     const int g = threadIdx.x >> 6, e = threadIdx.x & 63;
     const int64_t mat = (int64_t)ld * ld;
+    const bool tiled = mode != 0 || p == sym_p;           // uniform in the work-group
     int i, j, i2 = 0, j2 = 0;
     bool valid, valid2 = false;
-    if (mode == 0) {
+    if (!tiled) {
         const int idx = blockIdx.x * 64 + e;
         valid = idx < ld * ld;
         i = valid ? idx / ld : 0;
@@ -191,7 +195,7 @@ __global__ __launch_bounds__(64 * kRedGroups) void k_gram_reduce(const PT* __res
     const PT* base = partial + (int64_t)p * nchunk * mat;
     double s1 = 0.0, s2 = 0.0;
     // chunks g, g+16, ... added in that order; unrolled so the loads are issued together
-    if (mode != 0) {
+    if (tiled) {
 #pragma unroll 8
         for (int c = g; c < nchunk; c += kRedGroups) {
             if (valid) s1 += (double)base[c * mat + sij];
@@ -207,17 +211,21 @@ __global__ __launch_bounds__(64 * kRedGroups) void k_gram_reduce(const PT* __res
     if (g == 0 && valid) {
         double t1 = 0.0, t2 = 0.0;
         for (int q = 0; q < kRedGroups; ++q) t1 += s1s[q][e];
-        double v = t1;
-        if (mode != 0) {
+        if (tiled) {
             const int et = 8 * (e & 7) + (e >> 3);             // S_ji: lane (c, r) of the mirror tile
             for (int q = 0; q < kRedGroups; ++q) t2 += s2s[q][et];
-            v = 0.5 * (t1 + t2);
         }
-        double* o = out + p * out_stride + (int64_t)i * ld + j;
+        const double sv = 0.5 * (t1 + t2);
+        const int64_t at = (int64_t)i * ld + j;
+        double* o = out + p * out_stride + at;
         if (mode == 2)
-            *o += v;
+            *o += sv;
+        else if (mode == 1)
+            *o = sv;
         else
-            *o = v;
+            *o = t1;
+        if (mode == 1 && copy) copy[at] = sv;
+        if (p == sym_p) sym_to[at] += sv;
     }
 }
 
@@ -1540,14 +1548,6 @@ __global__ void k_trmm_upper(const double* __restrict__ R2, const double* __rest
     R[idx] = (j >= i) ? s : 0.0;
 }
 
-__global__ void k_sym_add(const double* __restrict__ C, double* __restrict__ A, int ld,
-                          const int* __restrict__ state) {
-    if (state && state[0]) return;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ld * ld) return;
-    const int i = idx / ld, j = idx % ld;
-    A[idx] += 0.5 * (C[idx] + C[j * ld + i]);
-}
 
 __global__ void k_copy_small(const double* __restrict__ M, int ld, int b, double* __restrict__ out) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1670,7 +1670,7 @@ void gram_tw_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, 
 
 template <typename T>
 void gram_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, double* partial, double* out,
-                 int64_t out_stride, int mode, const int* state, hipStream_t s) {
+                 int64_t out_stride, int mode, const int* state, hipStream_t s, const GramExtra& ex) {
     const int elem = (int)sizeof(T);
     const int tile = gram_tile(g.ld, elem);
     const int ntw = (g.ld + tile - 1) / tile;
@@ -1700,9 +1700,9 @@ void gram_launch(const GramPlan& g, const T* X, int64_t xstride, const T* Y, dou
     } else {
         gram_tw_launch<T, 4, 4, false>(g, X, xstride, Y, part, ntw, state, s);
     }
-    dim3 rgrid(reduce_blocks(g.ld, mode), g.nprod);
+    dim3 rgrid(reduce_blocks(g.ld, mode != 0 || ex.sym_p >= 0), g.nprod);
     k_gram_reduce<T><<<rgrid, 64 * kRedGroups, 0, s>>>(part, g.nchunk, g.ld, g.sym ? 1 : 0, mode, out, out_stride,
-                                                        state);
+                                                        state, ex.copy, ex.sym_to, ex.sym_p);
 }
 
 template <typename T, int NTW>
@@ -1937,10 +1937,11 @@ static void gram_split_one(const GramPlan& g, const float* X, int64_t xstride, c
 template <>
 void gram_blocks_launch<float>(const float* X, int64_t xstride, int nprod, const float* Y, int64_t Np, int ld, bool sym,
                                int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
-                               const int* state, hipStream_t s, void* yplanes, const double* hinf) {
+                               const int* state, hipStream_t s, void* yplanes, const double* hinf,
+                               const GramExtra& ex) {
     if (ld % 16 != 0 || ld > 96 || Np % 256 != 0) {
         const GramPlan g = gram_plan(Np, ld, nprod, sym, cap_mats, 4);
-        gram_launch<float>(g, X, xstride, Y, partial, out, out_stride, mode, state, s);
+        gram_launch<float>(g, X, xstride, Y, partial, out, out_stride, mode, state, s, ex);
         return;
     }
     // the partials are FP32: the buffer (cap_mats FP64 matrices) holds twice as many
@@ -1965,16 +1966,17 @@ void gram_blocks_launch<float>(const float* X, int64_t xstride, int nprod, const
         case 5: gram_split_one<5>(g, X, xstride, Y, Yp, hinf, part, state, s); break;
         default: gram_split_one<6>(g, X, xstride, Y, Yp, hinf, part, state, s); break;
     }
-    dim3 rgrid(reduce_blocks(ld, mode), nprod);
-    k_gram_reduce<float><<<rgrid, 64 * kRedGroups, 0, s>>>(part, g.nchunk, ld, 0, mode, out, out_stride, state);
+    dim3 rgrid(reduce_blocks(ld, mode != 0 || ex.sym_p >= 0), nprod);
+    k_gram_reduce<float><<<rgrid, 64 * kRedGroups, 0, s>>>(part, g.nchunk, ld, 0, mode, out, out_stride, state,
+                                                           ex.copy, ex.sym_to, ex.sym_p);
 }
 
 template <>
 void gram_blocks_launch<double>(const double* X, int64_t xstride, int nprod, const double* Y, int64_t Np, int ld,
                                 bool sym, int64_t cap_mats, double* partial, double* out, int64_t out_stride, int mode,
-                                const int* state, hipStream_t s, void*, const double*) {
+                                const int* state, hipStream_t s, void*, const double*, const GramExtra& ex) {
     const GramPlan g = gram_plan(Np, ld, nprod, sym, cap_mats, 8);
-    gram_launch<double>(g, X, xstride, Y, partial, out, out_stride, mode, state, s);
+    gram_launch<double>(g, X, xstride, Y, partial, out, out_stride, mode, state, s, ex);
 }
 
 size_t chol_scratch_bytes(int b) { return sizeof(double) * ((size_t)b * (b + 1) + b + 8); }
@@ -2024,10 +2026,6 @@ void trmm_upper_launch(const double* R2, const double* R1, double* R, int ld, co
     k_trmm_upper<<<grid_for((int64_t)ld * ld, 256), 256, 0, s>>>(R2, R1, R, ld, state);
 }
 
-void sym_add_launch(const double* C, double* A, int ld, const int* state, hipStream_t s) {
-    k_sym_add<<<grid_for((int64_t)ld * ld, 256), 256, 0, s>>>(C, A, ld, state);
-}
-
 void copy_small_launch(const double* M, int ld, int b, double* out, hipStream_t s) {
     k_copy_small<<<grid_for((int64_t)b * b, 256), 256, 0, s>>>(M, ld, b, out);
 }
@@ -2039,9 +2037,9 @@ void gemm_f64_launch(int M, int N, int K, const double* A, int64_t a_rs, int64_t
 }
 
 template void gram_launch<double>(const GramPlan&, const double*, int64_t, const double*, double*, double*,
-                                  int64_t, int, const int*, hipStream_t);
+                                  int64_t, int, const int*, hipStream_t, const GramExtra&);
 template void gram_launch<float>(const GramPlan&, const float*, int64_t, const float*, double*, double*, int64_t,
-                                 int, const int*, hipStream_t);
+                                 int, const int*, hipStream_t, const GramExtra&);
 template void update_launch<double>(double*, const double*, double, const double*, int64_t, int, const double*,
                                     int64_t, bool, double, int64_t, int, void*, const int*, hipStream_t, void*);
 template void update_launch<float>(float*, const float*, double, const float*, int64_t, int, const double*,

@@ -142,13 +142,6 @@ __global__ void k_zero_small(double* __restrict__ p, int64_t n) {
     if (i < n) p[i] = 0.0;
 }
 
-__global__ void k_copy_small_full(const double* __restrict__ a, double* __restrict__ b, int64_t n,
-                                  const int* __restrict__ state) {
-    if (state && state[0]) return;
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) b[i] = a[i];
-}
-
 template <typename T>
 void zero_tall(T* p, int64_t count, hipStream_t s) {
     k_zero<T><<<grid_for(count, 256), 256, 0, s>>>(p, count);
@@ -186,9 +179,10 @@ struct Step {
     }
 
     void gram(const T* X, int64_t xstride, int nprod, const T* Y, double* out, int64_t out_stride, bool sym,
-              int mode, void* yplanes = nullptr, const double* hinf = nullptr) const {
+              int mode, void* yplanes = nullptr, const double* hinf = nullptr,
+              const GramExtra& ex = GramExtra()) const {
         gram_blocks_launch<T>(X, xstride, nprod, Y, p.Np, p.ld, sym, p.partial_mats, bf.partial, out, out_stride, mode,
-                              bf.state, s, yplanes, hinf);
+                              bf.state, s, yplanes, hinf, ex);
     }
     void update(T* out, const T* in, double alpha, const T* X, int64_t xstride, int nprod, const double* S,
                 int64_t sstride, bool trans, double scale, void* out16 = nullptr) const {
@@ -206,22 +200,31 @@ struct Step {
         double* Aj = bf.A + j * mat();
         double* Apre = bf.Apre + j * mat();
         if (!launch_spmm_t<T>(H, bf, Qj, W, ld, s)) return false;
-        if (!replay) gram(Qj, 0, 1, W, Apre, 0, false, 1);                    // A_j = sym(Q_j^T W)
+        if (!replay) {                                                       // A_j = sym(Q_j^T W), also into Aj
+            GramExtra ex;
+            ex.copy = Aj;
+            gram(Qj, 0, 1, W, Apre, 0, false, 1, nullptr, nullptr, ex);
+        }
         if (j > 0)                                                           // W -= Q_j A_j + Q_{j-1} B^T
             update2_launch<T>(W, W, 1.0, Qj, Apre, false, q(j - 1), bf.B + (j - 1) * mat(), true, -1.0, p.Np, p.ld,
                               bf.stage, bf.state, s);
         else
             update(W, W, 1.0, Qj, 0, 1, Apre, 0, false, -1.0);                // W -= Q_j A_j
-        if (!replay) k_copy_small_full<<<grid_for(mat(), 256), 256, 0, s>>>(Apre, Aj, mat(), bf.state);
         if (p.reorth == 1 || (p.reorth == 2 && p.twopass)) {
             // local: coefficients against Q_{j-1} and Q_j, one block at a time
             const int first = std::max(0, j - 1);
             const int np = j - first + 1;
             double* C = p.twopass ? bf.C + (int64_t)j * p.max_coef * mat() : bf.C;
             if (!replay)
-                for (int t = 0; t < np; ++t) gram(q(first + t), 0, 1, W, C + t * mat(), 0, false, 0);
+                for (int t = 0; t < np; ++t) {
+                    GramExtra ex;                                   // A_j += sym(C) of Q_j
+                    if (t == np - 1) {
+                        ex.sym_to = Aj;
+                        ex.sym_p = 0;
+                    }
+                    gram(q(first + t), 0, 1, W, C + t * mat(), 0, false, 0, nullptr, nullptr, ex);
+                }
             for (int t = 0; t < np; ++t) update(W, W, 1.0, q(first + t), 0, 1, C + t * mat(), 0, false, -1.0);
-            if (!replay) sym_add_launch(C + (np - 1) * mat(), Aj, ld, bf.state, s);
         } else if (p.reorth == 2) {
             // full: coefficients against Q_0..Q_j (contiguous stored slots), batched; with
             // the alternating schedule, odd steps only against Q_{j-1}, Q_j
@@ -230,7 +233,12 @@ struct Step {
             const int cap = (int)std::max<int64_t>(1, p.partial_mats);
             for (int t0 = 0; t0 < np; t0 += cap) {
                 const int cnt = std::min(cap, np - t0);
-                gram(q(first + t0), tall(), cnt, W, bf.C + t0 * mat(), mat(), false, 0, bf.yplanes, bf.scal);
+                GramExtra ex;                                       // A_j += sym(C) of Q_j (the last product)
+                if (np - 1 < t0 + cnt) {
+                    ex.sym_to = Aj;
+                    ex.sym_p = np - 1 - t0;
+                }
+                gram(q(first + t0), tall(), cnt, W, bf.C + t0 * mat(), mat(), false, 0, bf.yplanes, bf.scal, ex);
             }
             // the corrections are of the size of the loss of orthogonality: with FP32 blocks
             // they read the BF16 copies of the basis (half the bytes of the stored blocks)
@@ -243,7 +251,6 @@ struct Step {
             if (!done)
                 update_correction_launch<T>(W, W, 1.0, q(first), tall(), np, bf.C, mat(), false, -1.0, p.Np, p.ld,
                                             bf.stage, bf.state, s);
-            sym_add_launch(bf.C + (j - first) * mat(), Aj, ld, bf.state, s);
         }
         if (last) return true;
         double* R1inv = p.twopass ? bf.R1inv + j * mat() : bf.R1inv;
