@@ -292,6 +292,7 @@ __global__ void k_clear_flags(int32_t* __restrict__ p_col, int64_t nnz) {
 // mostly on one molecule). A row is read kFpLoads entries per lane at a time; the
 // first batch of every due orbital's row is requested before the first is used.
 constexpr int kFpChunk = 8;
+constexpr int kFpBatch = 64;                 // colouring sweeps per host check
 constexpr int kFpLoads = 4;
 constexpr int kFpSpan = 64 * kFpLoads;               // row entries per batch
 
@@ -339,8 +340,12 @@ __device__ __forceinline__ void mark_lower(const int (&u)[kFpLoads], int v, int6
 
 __global__ __launch_bounds__(256) void k_fp_sweep(int n, const int64_t* __restrict__ p_row_ptr,
                                                   const int32_t* __restrict__ p_col, const int* __restrict__ deg,
-                                                  int* color, int* stamp, int k, int* __restrict__ changed) {
-    // changed: set to 1 if this sweep changed a colour (cleared by the host before)
+                                                  int* color, int* stamp, int k, int* __restrict__ changed,
+                                                  const int* __restrict__ prev_changed) {
+    // changed: set to 1 if this sweep changed a colour (cleared by the host before).
+    // prev_changed (may be nullptr): the previous sweep's flag; if it changed nothing,
+    // no orbital carries stamp k and this sweep is a no-op, so it returns at once
+    if (prev_changed && *prev_changed == 0) return;
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     int nchanged = 0;
@@ -552,7 +557,7 @@ ColorWs carve_color(Arena& a, int n) {
     w.cell_list = a.take<int>(n);
     w.deg = a.take<int>(n);
     w.stamp = a.take<int>(n);
-    w.scalars = a.take<int>(64);
+    w.scalars = a.take<int>(16 + kFpBatch);
     w.block_sum = a.take<int64_t>((n + kScanBlock - 1) / kScanBlock + 1);
     w.bbox = a.take<double>(8);
     w.bbox_part = a.take<double>(6 * kBboxBlocks);
@@ -591,7 +596,7 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
     if (ar.overflow) return CSS_E_WORKSPACE;
 
     // finite coordinates and bounding box (open directions)
-    fill_launch<int>(w.scalars, 0, 64, s);
+    fill_launch<int>(w.scalars, 0, 16 + kFpBatch, s);
     k_finite_check<<<grid_for(3LL * n, 256), 256, 0, s>>>(xyz, 3LL * n, w.scalars);
     {
         // per-block boxes of the n centres (stride 3), then the box of those boxes (stride 6)
@@ -653,8 +658,8 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
                                                        p_col);
     k_sort_rows<<<n, 256, 0, s>>>(n, p_row_ptr, p_col);
 
-    // fixed-point sweeps, kFpBatch per host check of the change counters
-    constexpr int kFpBatch = 16;
+    // fixed-point sweeps, kFpBatch per host check of the change counters; a sweep after
+    // one that changed nothing returns at once, so a batch costs one host round trip
     int* stamp = w.stamp;
     int* changed = w.scalars + 16;                // kFpBatch change counters
     k_fp_init<<<grid_for(n, 4), 256, 0, s>>>(n, p_row_ptr, p_col, w.deg, color, stamp);
@@ -664,7 +669,8 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
         if (k0 > n + kFpBatch) return CSS_E_DEVICE;       // cannot happen: sweep k fixes priority level k
         fill_launch<int>(changed, 0, kFpBatch, s);
         for (int r = 0; r < kFpBatch; ++r)
-            k_fp_sweep<<<sgrid, 256, 0, s>>>(n, p_row_ptr, p_col, w.deg, color, stamp, k0 + r, changed + r);
+            k_fp_sweep<<<sgrid, 256, 0, s>>>(n, p_row_ptr, p_col, w.deg, color, stamp, k0 + r, changed + r,
+                                             r > 0 ? changed + r - 1 : nullptr);
         int hch[kFpBatch];
         CSS_HIP_TRY(hipMemcpyAsync(hch, changed, sizeof(hch), hipMemcpyDeviceToHost, s));
         CSS_HIP_TRY(hipStreamSynchronize(s));
