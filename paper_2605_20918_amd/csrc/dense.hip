@@ -492,9 +492,11 @@ __global__ void k_frag_s(const double* __restrict__ S, int64_t sstride, int npro
 template <int MT, int NT, int D, int NPL>
 __global__ __launch_bounds__(256) void k_update_split(float* OUT, const float* IN, double alpha,
                                                       const float* __restrict__ X, int64_t xstride, int nprod,
-                                                      const bf16x8* __restrict__ frag, int64_t Np, int ld,
+                                                      const bf16x8* __restrict__ frag, int64_t Np, int ld_arg,
                                                       const int* __restrict__ state,
                                                       unsigned short* __restrict__ OUT16) {
+    constexpr int ld = 16 * NT;                           // the launcher passes ld = 16 NT
+    (void)ld_arg;
     if (state && state[0]) return;
     constexpr int FR = NPL * NT * 64;                     // fragments of one K chunk
     constexpr int PER = (FR + 255) / 256;
@@ -603,8 +605,10 @@ __global__ __launch_bounds__(256) void k_update_split(float* OUT, const float* I
 template <int MT, int NT, int D>
 __global__ __launch_bounds__(256) void k_update_bf16x(float* OUT, const float* IN, double alpha,
                                                       const unsigned short* __restrict__ X, int64_t xstride, int nprod,
-                                                      const bf16x8* __restrict__ frag, int64_t Np, int ld,
+                                                      const bf16x8* __restrict__ frag, int64_t Np, int ld_arg,
                                                       const int* __restrict__ state) {
+    constexpr int ld = 16 * NT;                           // the launcher passes ld = 16 NT
+    (void)ld_arg;
     if (state && state[0]) return;
     constexpr int FR = NT * 64;                           // fragments of one K chunk
     constexpr int PER = (FR + 255) / 256;
@@ -739,11 +743,13 @@ __global__ __launch_bounds__(256) void k_split_rows8(const float* __restrict__ Y
 // three products lo*hi + hi*lo + hi*hi on the FP16 MFMA (dropped and rounded parts
 // below 3 2^-22 of each term), the partial scaled back exactly.
 template <int NT, int NH, int NPL, bool YP, bool F16>
-__global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ X, int64_t xstride,
+__global__ __launch_bounds__(256, F16 ? 2 : 1) void k_gram_split(const float* __restrict__ X, int64_t xstride,
                                                     const float* __restrict__ Y, const bf16x8* __restrict__ Yp,
-                                                    int64_t Np, int64_t rpc, int ld, float* __restrict__ partial,
+                                                    int64_t Np, int64_t rpc, int ld_arg, float* __restrict__ partial,
                                                     int nchunk, const int* __restrict__ state,
                                                     const double* __restrict__ hinf) {
+    constexpr int ld = 16 * NT;                           // the launcher passes ld = 16 NT: row offsets fold into immediates
+    (void)ld_arg;
     static_assert(!F16 || (YP && NPL == 2), "FP16 parts come with the pre-split Y");
     if (state && state[0]) return;
     constexpr int TILE = 16 * NT, NB = NT / NH, KG = 4 / NH;
@@ -834,24 +840,43 @@ __global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ X,
                 for (int e = 0; e < 8; ++e) v[e] = x[e][a + 1];
                 split_x(v, xb[(a + 1) & 1]);
             }
+            // the product terms in the outer loop: an accumulator's next MFMA comes NB
+            // instructions later, not right after its previous one (same order of terms)
+            if constexpr (F16) {
+                const f16x8 x0 = __builtin_bit_cast(f16x8, xc[0]), x1 = __builtin_bit_cast(f16x8, xc[1]);
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                if constexpr (F16) {
-                    const f16x8 x0 = __builtin_bit_cast(f16x8, xc[0]), x1 = __builtin_bit_cast(f16x8, xc[1]);
-                    const f16x8 y0 = __builtin_bit_cast(f16x8, yb[b][0]), y1 = __builtin_bit_cast(f16x8, yb[b][1]);
-                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x1, y0, c[a][b], 0, 0, 0);
-                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x0, y1, c[a][b], 0, 0, 0);
-                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x0, y0, c[a][b], 0, 0, 0);
-                    continue;
-                }
+                for (int b = 0; b < NB; ++b)
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x1, __builtin_bit_cast(f16x8, yb[b][0]), c[a][b],
+                                                                     0, 0, 0);
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x0, __builtin_bit_cast(f16x8, yb[b][1]), c[a][b],
+                                                                     0, 0, 0);
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x0, __builtin_bit_cast(f16x8, yb[b][0]), c[a][b],
+                                                                     0, 0, 0);
+            } else {
                 if constexpr (NPL == 3) {
-                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[2], yb[b][0], c[a][b], 0, 0, 0);
-                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[1], yb[b][1], c[a][b], 0, 0, 0);
-                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[0], yb[b][2], c[a][b], 0, 0, 0);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[2], yb[b][0], c[a][b], 0, 0, 0);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[1], yb[b][1], c[a][b], 0, 0, 0);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[0], yb[b][2], c[a][b], 0, 0, 0);
                 }
-                c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[1], yb[b][0], c[a][b], 0, 0, 0);
-                c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[0], yb[b][1], c[a][b], 0, 0, 0);
-                c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[0], yb[b][0], c[a][b], 0, 0, 0);
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[1], yb[b][0], c[a][b], 0, 0, 0);
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[0], yb[b][1], c[a][b], 0, 0, 0);
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    c[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xc[0], yb[b][0], c[a][b], 0, 0, 0);
             }
             if (a + 1 < NT) {
 #pragma unroll
