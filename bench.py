@@ -58,6 +58,9 @@ WORKLOADS = {
     "batch48": dict(n_mol=0, seed=20922, depth=40, prec="fp32", fp64_twopass=False),
 }
 BATCH_SIZE_SEED = 20922
+# library streams of the batched calls: 8 measured fastest for the 48 boxes (densities 201 ms, against
+# 229 ms on 4, 208 ms on 16 and 299 ms on 2): the extra host workers cover each system's host checks
+BATCH_STREAMS = 8
 BATCH_COUNT = 48
 
 
@@ -89,7 +92,7 @@ def run_batch(args):
 
     def colour_all():
         systems = []
-        cols = css.css_color_batched([(xyz, box) for (w, H, xyz, box) in boxes], R_CUT, concurrency=4)
+        cols = css.css_color_batched([(xyz, box) for (w, H, xyz, box) in boxes], R_CUT, concurrency=BATCH_STREAMS)
         for k, ((w, H, xyz, box), (color, b, p_rp, p_col, _)) in enumerate(zip(boxes, cols)):
             sign, _ = css.css_build_probes(color, b, BATCH_SIZE_SEED * 100 + k)
             systems.append(dict(H=H, color=color, sign=sign, n_colors=b, mu=MU_WATER, p_row_ptr=p_rp, p_col=p_col))
@@ -100,7 +103,7 @@ def run_batch(args):
         systems = colour_all()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        res = css.css_density_matrix_batched(systems, KT, depth, flags, concurrency=4)
+        res = css.css_density_matrix_batched(systems, KT, depth, flags, concurrency=BATCH_STREAMS)
         torch.cuda.synchronize()
         state.update(systems=systems, res=res, t_colour=t1 - t0, t_density=time.perf_counter() - t1)
 
@@ -136,7 +139,7 @@ def run_batch(args):
         "config": {"workload": f"{BATCH_COUNT} water boxes of {int(sizes.min())}..{int(sizes.max())} molecules "
                                f"({int(sizes.sum())} in all, {sum(int(d['H'].n) for d in systems)} orbitals), "
                                f"fp32 blocks, depth {depth}",
-                   "sizes": [int(x) for x in sizes], "flags": flags, "concurrency": 4},
+                   "sizes": [int(x) for x in sizes], "flags": flags, "concurrency": BATCH_STREAMS},
         "colour_ms_per_step": tc / args.steps * 1e3,
         "batched_density_ms": td / args.steps * 1e3,
         "sequential_density_ms": ts * 1e3,
