@@ -655,13 +655,15 @@ __global__ __launch_bounds__(kPoleThreads) void k_pole_solve(const double* __res
 
 // b <= 96, blocks of 16 (N = 16 NB rows, padded with the identity beyond b):
 // one workgroup per pole, the complex Schur complement S (N x N, row stride
-// N + 1) in LDS. Each S_j is inverted in place by block Gauss-Jordan without
-// pivoting: wave 0 inverts the 16 x 16 diagonal block P = S_kk^-1 in registers,
-// the row block (S_kj <- P S_kj), the trailing blocks (S_ij -= S_ik S_kj) and the
-// column block (S_ik <- -S_ik P) are updated on FP64 MFMA, three barriers per block
-// step, with the next pivot inverted during the trailing update (gj_inverse_blk).
-// G_j (N x N, global) and the forward sweep are as in k_pole_solve_generic.
-constexpr int kBlkThreads = 512;     // 8 waves: 256 registers per lane, no spills
+// N + 1) in LDS. Each S_j (complex symmetric) is inverted in place by block
+// Gauss-Jordan without pivoting: wave 0 inverts the 16 x 16 diagonal block
+// P = S_kk^-1 in registers, the row block (S_kj <- P S_kj) is computed on FP64 MFMA
+// and the column block written as its signed transpose, the upper trailing blocks
+// are updated on FP64 MFMA and mirrored, two barriers per block step, with the next
+// pivot inverted during the trailing update (gj_inverse_blk). The next Schur
+// complement is symmetric too and computed on its upper tiles. G_j (N x N, global)
+// and the forward sweep are as in k_pole_solve_generic.
+constexpr int kBlkThreads = 512;     // 8 waves: at most 256 registers per lane (199 used, no spills)
 constexpr int kBlkWaves = kBlkThreads / 64;
 
 // Wave 0: the 16 x 16 diagonal block at (o, o) of S inverted in registers (Gauss-Jordan
