@@ -902,7 +902,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
         double* Gi = Gr + nn;
         for (int t = wave; t < NTL; t += kBlkWaves) {
             const int m0 = (t / NB) * 16, c0 = (t % NB) * 16;
-            pd4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+            pd4 tr2[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, ti2[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};   // even / odd K steps
             constexpr int H = 8, NH = (N / 4 + H - 1) / H;      // K in chunks of 8 steps of global operands
             const int hmax = (c0 + 16 + 4 * H - 1) / (4 * H);
 #pragma unroll
@@ -919,11 +919,12 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
                     const int s4 = h * H + q;
                     if (s4 >= N / 4) break;
                     const int k = 4 * s4 + lr;
-                    tr = mfma64(Sr[(m0 + lc) * SW + k], bv[q], tr);
-                    ti = mfma64(Si[(m0 + lc) * SW + k], bv[q], ti);
+                    tr2[q & 1] = mfma64(Sr[(m0 + lc) * SW + k], bv[q], tr2[q & 1]);
+                    ti2[q & 1] = mfma64(Si[(m0 + lc) * SW + k], bv[q], ti2[q & 1]);
                 }
                 __builtin_amdgcn_sched_barrier(0);             // one chunk of operands live at a time
             }
+            const pd4 tr = tr2[0] + tr2[1], ti = ti2[0] + ti2[1];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + lr + 4 * r, col = c0 + lc;
@@ -942,7 +943,7 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
             int mb = NB - 1, rem = t;                          // tile rows NB-1, NB-2, ..: NB - mb tiles each
             while (rem >= NB - mb) { rem -= NB - mb; --mb; }
             const int m0 = 16 * mb, c0 = 16 * (mb + rem);
-            pd4 tr = {0, 0, 0, 0}, ti = {0, 0, 0, 0};
+            pd4 tr2[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, ti2[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};   // even / odd K steps
             constexpr int H = 8, NH = (N / 4 + H - 1) / H;      // K in chunks of 8 steps of global operands
             const int hmax = (m0 + 16 + 4 * H - 1) / (4 * H);
 #pragma unroll
@@ -960,11 +961,12 @@ __global__ __launch_bounds__(kBlkThreads) void k_pole_solve_blk(const double* __
                 }
 #pragma unroll
                 for (int q = 0; q < H; ++q) {
-                    tr = mfma64(av[q], zr[q], tr);
-                    ti = mfma64(av[q], zi[q], ti);
+                    tr2[q & 1] = mfma64(av[q], zr[q], tr2[q & 1]);
+                    ti2[q & 1] = mfma64(av[q], zi[q], ti2[q & 1]);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
+            const pd4 tr = tr2[0] + tr2[1], ti = ti2[0] + ti2[1];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + lr + 4 * r, col = c0 + lc;
@@ -1029,29 +1031,37 @@ __global__ __launch_bounds__(64 * NB) void k_pole_forward(int v, int b, const do
     };
     auto step = [&](int j, const double (&g)[2][KS]) {
         const int cur = (j - 1) & 1;
-        pd4 nr[CT], ni[CT];
+        // even and odd K steps in separate accumulators (four independent MFMA chains
+        // per column tile), added at the end
+        pd4 nr[CT][2], ni[CT][2];
 #pragma unroll
-        for (int t = 0; t < CT; ++t) nr[t] = ni[t] = pd4{0, 0, 0, 0};
+        for (int t = 0; t < CT; ++t) nr[t][0] = nr[t][1] = ni[t][0] = ni[t][1] = pd4{0, 0, 0, 0};
 #pragma unroll
         for (int s4 = 0; s4 < KS; ++s4) {
-            const int k = 4 * s4 + lr;
+            const int k = 4 * s4 + lr, h = s4 & 1;
 #pragma unroll
             for (int t = 0; t < CT; ++t) {
                 const double zr = zb[cur][0][k * SC + 16 * t + lc], zi = zb[cur][1][k * SC + 16 * t + lc];
-                nr[t] = mfma64(g[0][s4], zr, nr[t]);
-                nr[t] = mfma64(-g[1][s4], zi, nr[t]);
-                ni[t] = mfma64(g[0][s4], zi, ni[t]);
-                ni[t] = mfma64(g[1][s4], zr, ni[t]);
+                nr[t][h] = mfma64(g[0][s4], zr, nr[t][h]);
+                nr[t][h] = mfma64(-g[1][s4], zi, nr[t][h]);
+                ni[t][h] = mfma64(g[0][s4], zi, ni[t][h]);
+                ni[t][h] = mfma64(g[1][s4], zr, ni[t][h]);
             }
+        }
+        pd4 nrs[CT], nis[CT];
+#pragma unroll
+        for (int t = 0; t < CT; ++t) {
+            nrs[t] = nr[t][0] + nr[t][1];
+            nis[t] = ni[t][0] + ni[t][1];
         }
 #pragma unroll
         for (int t = 0; t < CT; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + lr + 4 * r, col = c0 + 16 * t + lc;
-                zb[cur ^ 1][0][row * SC + 16 * t + lc] = -nr[t][r];
-                zb[cur ^ 1][1][row * SC + 16 * t + lc] = -ni[t][r];
-                if (row < b && col < b) Wp[(int64_t)j * b * b + row * b + col] = -wgt * ni[t][r];
+                zb[cur ^ 1][0][row * SC + 16 * t + lc] = -nrs[t][r];
+                zb[cur ^ 1][1][row * SC + 16 * t + lc] = -nis[t][r];
+                if (row < b && col < b) Wp[(int64_t)j * b * b + row * b + col] = -wgt * nis[t][r];
             }
         lds_barrier();                                    // Z_j complete; Z_{j-1} no longer read
     };
@@ -1202,7 +1212,7 @@ css_status subspace_fermi_poles(const double* A, const double* B, int v, int b, 
         switch (nb16) {
 #define CSS_FWD(NB, CT) \
     case NB: k_pole_forward<NB, CT><<<dim3(np, NB / CT), 64 * NB, 0, s>>>(v, b, wgt, Gbuf, Wout); break;
-            CSS_FWD(1, 1) CSS_FWD(2, 2) CSS_FWD(3, 1) CSS_FWD(4, 2) CSS_FWD(5, 1) CSS_FWD(6, 2)
+            CSS_FWD(1, 1) CSS_FWD(2, 2) CSS_FWD(3, 1) CSS_FWD(4, 2) CSS_FWD(5, 1) CSS_FWD(6, 1)
 #undef CSS_FWD
             default: break;
         }
