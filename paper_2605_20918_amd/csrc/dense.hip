@@ -490,7 +490,7 @@ __global__ void k_frag_s(const double* __restrict__ S, int64_t sstride, int npro
 // addresses are clamped into the block (a clamped value always meets a zero
 // coefficient), so that every wait for a load can leave the later loads in flight.
 template <int MT, int NT, int D, int NPL>
-__global__ __launch_bounds__(256) void k_update_split(float* OUT, const float* IN, double alpha,
+__global__ __launch_bounds__(256, 3) void k_update_split(float* OUT, const float* IN, double alpha,
                                                       const float* __restrict__ X, int64_t xstride, int nprod,
                                                       const bf16x8* __restrict__ frag, int64_t Np, int ld_arg,
                                                       const int* __restrict__ state,
