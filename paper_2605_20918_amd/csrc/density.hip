@@ -382,27 +382,33 @@ __global__ void k_ns_finish(const double* __restrict__ Z, const double* __restri
 
 // Pattern sanity: row pointers monotone from 0 to nnz, columns in range and strictly
 // increasing within each row (the band energy binary-searches the rows).
-__global__ void k_validate_pattern(int n, int64_t nnz, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                   int* __restrict__ bad) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) {
+// One wave per row (grid-stride): row bounds, then every adjacent pair of the row's
+// columns at once (strictly increasing); every thread also range-checks the columns
+// t = global thread index, t + stride, ... One flag for any violation.
+__global__ __launch_bounds__(256) void k_validate_pattern(int n, int64_t nnz, const int64_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ col, int* __restrict__ bad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
+    bool fail = false;
+    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); i < n; i += nwaves) {
         const int64_t a = rp[i], b = rp[i + 1];
-        if (a < 0 || b < a || b > nnz) {
-            atomicOr(bad, 1);
-        } else {
-            for (int64_t t = a + 1; t < b; ++t)
-                if (col[t - 1] >= col[t]) {
-                    atomicOr(bad, 1);
-                    break;
-                }
+        if (a < 0 || b < a || b > nnz || (i == 0 && a != 0) || (i == n - 1 && b != nnz)) {
+            fail = true;
+            continue;
         }
-        if (i == 0 && a != 0) atomicOr(bad, 1);
-        if (i == n - 1 && b != nnz) atomicOr(bad, 1);
+        for (int64_t t = a + 1 + lane; t < b; t += 64)
+            if (col[t - 1] >= col[t]) fail = true;
     }
-    if (i < nnz) {
-        const int32_t c = col[i];
-        if (c < 0 || c >= n) atomicOr(bad, 1);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nnz; t += stride) {
+        const int32_t c = col[t];
+        if (c < 0 || c >= n) fail = true;
     }
+    if (fail) atomicOr(bad, 1);
+}
+void validate_pattern_launch(int n, int64_t nnz, const int64_t* rp, const int32_t* col, int* bad, hipStream_t s) {
+    const unsigned grid = std::max(1u, std::min<unsigned>(grid_for(n, 4), 16384));
+    k_validate_pattern<<<grid, 256, 0, s>>>(n, nnz, rp, col, bad);
 }
 
 // Fpad[j][i][c] = F[j*b + i][c] for i, c < b; zero in the padding.
@@ -687,8 +693,7 @@ css_status dm_run(const css_csr* H, const int32_t* color, const int8_t* sign, in
 
     {
         fill_launch<int>(bf.flags, 0, 16, s);
-        k_validate_pattern<<<grid_for(std::max<int64_t>(lz.n, p_nnz), 256), 256, 0, s>>>(lz.n, p_nnz, p_row_ptr, p_col,
-                                                                                         bf.flags);
+        validate_pattern_launch(lz.n, p_nnz, p_row_ptr, p_col, bf.flags, s);
         int pbad = 0;
         CSS_HIP_TRY(hipMemcpyAsync(&pbad, bf.flags, sizeof(int), hipMemcpyDeviceToHost, s));
         CSS_HIP_TRY(hipStreamSynchronize(s));
@@ -920,8 +925,7 @@ css_status nonorth_run(const css_csr* Hp, const css_csr* Sih, const css_csr* He,
 
     // inputs: the pattern and the sparse S^-1/2 (and H, S for the sums)
     fill_launch<int>(bf.flags, 0, 16, s);
-    k_validate_pattern<<<grid_for(std::max<int64_t>(lz.n, p_nnz), 256), 256, 0, s>>>(lz.n, p_nnz, p_row_ptr, p_col,
-                                                                                     bf.flags);
+    validate_pattern_launch(lz.n, p_nnz, p_row_ptr, p_col, bf.flags, s);
     csr_validate_launch(lz.n, Sih->nnz, Sih->row_ptr, Sih->col, bf.flags + 3, s);
     if (He) csr_validate_launch(lz.n, He->nnz, He->row_ptr, He->col, bf.flags + 5, s);
     if (Se) csr_validate_launch(lz.n, Se->nnz, Se->row_ptr, Se->col, bf.flags + 7, s);

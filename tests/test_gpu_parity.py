@@ -742,6 +742,36 @@ def test_nonorthogonal_entry_errors():
     assert e.value.code == 2
 
 
+def test_density_rejects_bad_pattern():
+    """The P pattern is validated before use: rows must be strictly increasing, row
+    bounds consistent and columns in range (CSS_E_CSR = 2), checked for one row of
+    each kind in the middle of the pattern."""
+    ws, H, rp, col, color, b, sign, mu = water_case(64, 20919)
+    args = (to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, 4)
+    r = ws.n // 2
+    a, e = int(rp[r]), int(rp[r + 1])
+    assert e - a >= 3
+    cases = []
+    unsorted = col.copy()
+    unsorted[a + 1], unsorted[a + 2] = unsorted[a + 2], unsorted[a + 1]
+    cases.append((rp, unsorted))
+    repeated = col.copy()
+    repeated[e - 1] = repeated[e - 2]
+    cases.append((rp, repeated))
+    bad_rp = rp.copy()
+    bad_rp[r] = bad_rp[r + 1] + 1
+    cases.append((bad_rp, col))
+    out_of_range = col.copy()
+    out_of_range[e - 1] = ws.n
+    cases.append((rp, out_of_range))
+    for prp, pcol in cases:
+        with pytest.raises(css.CssError) as err:
+            css.css_density_matrix(*args, dev_i64(prp), dev_i32(pcol), FP64_FLAGS)
+        assert err.value.code == 2
+    # the unchanged pattern is accepted
+    css.css_density_matrix(*args, dev_i64(rp), dev_i32(col), FP64_FLAGS)
+
+
 def test_errors_are_reported():
     ws, H, rp, col, color, b, sign, mu = water_case(64, 20919)
     good = (to_dev(ws), dev_i32(color), dev_i8(sign), b, mu, KT, 4, dev_i64(rp), dev_i32(col), FP64_FLAGS)
