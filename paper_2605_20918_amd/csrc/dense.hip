@@ -600,8 +600,9 @@ __global__ __launch_bounds__(256, 3) void k_update_split(float* OUT, const float
 // FP32 block) and S'_p as one BF16 part: one 16x16x32 BF16 MFMA per tile and K chunk.
 // For coefficient blocks of the size of a loss of orthogonality (the correction of
 // the re-orthogonalisation), each term is within 2^-8 |X||S| of the exact one, far
-// under FP32 rounding of OUT. Structure as k_update_split (X runs of a K chunk fetched
-// D chunks ahead, fragments double buffered in LDS, branch-free loop).
+// under FP32 rounding of OUT. Structure as k_update_split (X runs fetched D chunks
+// ahead, fragments double buffered in LDS, branch-free loop), with two K chunks per
+// stage, so one work-group barrier per two chunks.
 template <int MT, int NT, int D>
 __global__ __launch_bounds__(256) void k_update_bf16x(float* OUT, const float* IN, double alpha,
                                                       const unsigned short* __restrict__ X, int64_t xstride, int nprod,
@@ -612,58 +613,75 @@ __global__ __launch_bounds__(256) void k_update_bf16x(float* OUT, const float* I
     if (state && state[0]) return;
     constexpr int FR = NT * 64;                           // fragments of one K chunk
     constexpr int PER = (FR + 255) / 256;
-    __shared__ bf16x8 sB[2][PER * 256];
+    constexpr int CPS = 2;                                // K chunks per stage (one barrier per stage)
+    __shared__ bf16x8 sB[2][CPS][PER * 256];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, lr = l >> 4, lc = l & 15;
     const int64_t m0 = ((int64_t)blockIdx.x * 4 + w) * (16 * MT);
     const bool active = m0 < Np;
     const int64_t mrow = active ? m0 : 0;
     const int nkc = (ld + kSplitK - 1) / kSplitK;
     const int total = nprod * nkc;
+    const int nstage = (total + CPS - 1) / CPS;
     mf_f4 c[MT][NT];
 #pragma unroll
     for (int a = 0; a < MT; ++a)
 #pragma unroll
         for (int b = 0; b < NT; ++b) c[a][b] = mf_f4{0.f, 0.f, 0.f, 0.f};
-    auto fetch_x = [&](int it, bf16x8 (&x)[MT]) {
-        const int p = it / nkc, k = min((it % nkc) * kSplitK + 8 * lr, ld - 8);
-        const unsigned short* Xp = X + (int64_t)p * xstride + (mrow + lc) * ld + k;
+    // chunk it: X runs clamped to the last chunk (past the end they meet the zero
+    // fragments), fragments clamped to the zero chunk `total`
+    auto fetch_x = [&](int st, bf16x8 (&x)[CPS][MT]) {
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) x[mt] = *reinterpret_cast<const bf16x8*>(Xp + (int64_t)16 * mt * ld);
-    };
-    auto fetch_s = [&](int it, bf16x8 (&reg)[PER]) {
-        const bf16x8* src = frag + (int64_t)it * FR;
+        for (int q = 0; q < CPS; ++q) {
+            const int it = min(CPS * st + q, total - 1);
+            const int p = it / nkc, k = min((it % nkc) * kSplitK + 8 * lr, ld - 8);
+            const unsigned short* Xp = X + (int64_t)p * xstride + (mrow + lc) * ld + k;
 #pragma unroll
-        for (int q = 0; q < PER; ++q) reg[q] = src[min(threadIdx.x + 256 * q, (unsigned)FR - 1)];
-    };
-    auto store_s = [&](int buf, const bf16x8 (&reg)[PER]) {
-#pragma unroll
-        for (int q = 0; q < PER; ++q) sB[buf][threadIdx.x + 256 * q] = reg[q];
-    };
-    auto compute = [&](int buf, const bf16x8 (&x)[MT]) {
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const bf16x8 bp = sB[buf][nt * 64 + l];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[mt], bp, c[mt][nt], 0, 0, 0);
+            for (int mt = 0; mt < MT; ++mt) x[q][mt] = *reinterpret_cast<const bf16x8*>(Xp + (int64_t)16 * mt * ld);
         }
     };
-    bf16x8 xr[D][MT];
+    auto fetch_s = [&](int st, bf16x8 (&reg)[CPS][PER]) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) fetch_x(min(d, total - 1), xr[d]);
-    bf16x8 sreg[PER];
+        for (int q = 0; q < CPS; ++q) {
+            const bf16x8* src = frag + (int64_t)min(CPS * st + q, total) * FR;
+#pragma unroll
+            for (int e = 0; e < PER; ++e) reg[q][e] = src[min(threadIdx.x + 256 * e, (unsigned)FR - 1)];
+        }
+    };
+    auto store_s = [&](int buf, const bf16x8 (&reg)[CPS][PER]) {
+#pragma unroll
+        for (int q = 0; q < CPS; ++q)
+#pragma unroll
+            for (int e = 0; e < PER; ++e) sB[buf][q][threadIdx.x + 256 * e] = reg[q][e];
+    };
+    auto compute = [&](int buf, const bf16x8 (&x)[CPS][MT]) {
+#pragma unroll
+        for (int q = 0; q < CPS; ++q)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const bf16x8 bp = sB[buf][q][nt * 64 + l];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    c[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[q][mt], bp, c[mt][nt], 0, 0, 0);
+            }
+    };
+    // D K chunks in flight: D / CPS stages of X runs ahead, fragments one stage ahead
+    constexpr int DS = D / CPS > 0 ? D / CPS : 1;
+    bf16x8 xr[DS][CPS][MT];
+#pragma unroll
+    for (int d = 0; d < DS; ++d) fetch_x(d, xr[d]);
+    bf16x8 sreg[CPS][PER];
     fetch_s(0, sreg);
     store_s(0, sreg);
-    fetch_s(min(1, total), sreg);
-    for (int it0 = 0; it0 < total; it0 += D) {
+    fetch_s(1, sreg);
+    for (int st0 = 0; st0 < nstage; st0 += DS) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const int it = it0 + d;
-            lds_barrier();                                // sB[it & 1] holds chunk it; chunk it - 1 done
-            compute(it & 1, xr[d]);
-            store_s((it + 1) & 1, sreg);
-            fetch_s(min(it + 2, total), sreg);
-            fetch_x(min(it + D, total - 1), xr[d]);       // D chunks ahead (clamped at the end)
+        for (int d = 0; d < DS; ++d) {
+            const int st = st0 + d;
+            lds_barrier();                                // sB[st & 1] holds stage st; stage st - 1 done
+            compute(st & 1, xr[d]);
+            store_s((st + 1) & 1, sreg);
+            fetch_s(st + 2, sreg);
+            fetch_x(st + DS, xr[d]);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
