@@ -1239,10 +1239,39 @@ __device__ __forceinline__ void chol_inv_blk(const double* __restrict__ G, int b
 #pragma unroll
         for (int r = 0; r < 4; ++r) M[(16 * ib + lr + 4 * r) * W + 16 * jb + lc] = c[r];
     };
+    // block column jb of X = R^-1, tiles upwards: X_ij = -X_ii sum_{k=i+1..j} R_ik X_kj,
+    // X_ij^T stored in the strictly lower block triangle of M (which the factorisation
+    // no longer reads); needs R's block columns <= jb and the X_kk
+    auto inv_column = [&](int jb) {
+        for (int ib = jb - 1; ib >= 0; --ib) {
+            Mf::acc tv = Mf::zero();
+            for (int kb = ib + 1; kb <= jb; ++kb) {
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    const double av = M[(16 * ib + lc) * W + 16 * kb + 4 * s4 + lr];          // R_ik[lc][4s+lr]
+                    const double bv = kb == jb ? XD[jb * 256 + s4 * 64 + l]                    // X_jj[4s+lr][lc]
+                                               : M[(16 * jb + lc) * W + 16 * kb + 4 * s4 + lr];  // X_kj^T
+                    tv = Mf::mma(av, bv, tv);
+                }
+            }
+            Mf::acc c = Mf::zero();
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int li = lc, lj = 4 * s4 + lr;                   // X_ii[lc][4s+lr]
+                const double av = XD[ib * 256 + (li >> 2) * 64 + 16 * (li & 3) + lj];
+                c = Mf::mma(-av, tv[s4], c);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) M[(16 * jb + lc) * W + 16 * ib + lr + 4 * r] = c[r];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+    };
     if (wv == 0) diag_block(0);
     __syncthreads();
     // Look-ahead: in block step kb, after the panel, wave 0 updates the next diagonal
-    // tile and factors it while waves 1..3 update the other trailing tiles.
+    // tile and factors it while waves 1..3 update the other trailing tiles; then one of
+    // them forms block column kb of the inverse (R's block columns <= kb and X_kk are
+    // final by then), so that only the last column is left after the factorisation.
     for (int kb = 0; kb < NB && !sfail; ++kb) {
         const int o = 16 * kb;
         // (d) panel R_kj = X_kk^T A_kj, tiles dealt to the waves
@@ -1270,6 +1299,7 @@ __device__ __forceinline__ void chol_inv_blk(const double* __restrict__ G, int b
                         if (tile++ % 3 != wv - 1) continue;
                         trailing(ib, jb, o);
                     }
+                if (kb >= 1 && wv == 1 + kb % 3) inv_column(kb);
             }
             __syncthreads();
         }
@@ -1280,49 +1310,27 @@ __device__ __forceinline__ void chol_inv_blk(const double* __restrict__ G, int b
         if (t == 0) { state[2] = step; state[0] = 1; }
         return;
     }
-    // blocked inverse: block columns are independent (wave w takes NB-1-w, NB-5-w, ...);
-    // within a column the tiles go upwards
-    for (int jb = NB - 1 - wv; jb >= 1; jb -= 4)
-        for (int ib = jb - 1; ib >= 0; --ib) {
-            Mf::acc tv = Mf::zero();
-            for (int kb = ib + 1; kb <= jb; ++kb) {
-#pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) {
-                    const double av = M[(16 * ib + lc) * W + 16 * kb + 4 * s4 + lr];          // R_ik[lc][4s+lr]
-                    const double bv = kb == jb ? XD[jb * 256 + s4 * 64 + l]                    // X_jj[4s+lr][lc]
-                                               : M[(16 * jb + lc) * W + 16 * kb + 4 * s4 + lr];  // X_kj^T
-                    tv = Mf::mma(av, bv, tv);
-                }
-            }
-            Mf::acc c = Mf::zero();
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-                const int li = lc, lj = 4 * s4 + lr;                   // X_ii[lc][4s+lr]
-                const double av = XD[ib * 256 + (li >> 2) * 64 + 16 * (li & 3) + lj];
-                c = Mf::mma(-av, tv[s4], c);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) M[(16 * jb + lc) * W + 16 * ib + lr + 4 * r] = c[r];
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        }
+    // the last block column of the inverse (the others were formed during the factorisation)
+    if (NB > 1 && wv == 0) inv_column(NB - 1);
     __syncthreads();
-    // ld == N (checked by the launcher): constant index arithmetic
-#pragma unroll 4
-    for (int idx = t; idx < N * N; idx += 256) {
-        const int i = idx / N, j = idx % N;
-        double rv = 0.0, xv = 0.0;
-        if (i < b && j < b && j >= i) {
-            rv = M[i * W + j];
-            const int bi = i >> 4, bj = j >> 4;
-            if (bi == bj) {
-                const int li = i & 15, lj = j & 15;
-                xv = XD[bi * 256 + (li >> 2) * 64 + 16 * (li & 3) + lj];
-            } else {
-                xv = M[j * W + i];
-            }
+    // ld == N (checked by the launcher): constant index arithmetic; two adjacent
+    // elements per thread (one 16-byte store each to R and R^-1), branch-free
+    for (int e2 = t; e2 < N * N / 2; e2 += 256) {
+        const int idx = 2 * e2, i = idx / N, j = idx % N;    // j even: j, j + 1 in one block column
+        const int bi = i >> 4, bj = j >> 4, li = i & 15, lj = j & 15;
+        double rv[2], xv[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int jj = j + q;
+            const double r = M[i * W + jj];
+            const double xd = XD[bi * 256 + (li >> 2) * 64 + 16 * (li & 3) + lj + q];
+            const double xm = M[jj * W + i];
+            const bool in = i < b && jj < b && jj >= i;
+            rv[q] = in ? r : 0.0;
+            xv[q] = in ? (bi == bj ? xd : xm) : 0.0;
         }
-        R[idx] = rv;
-        Rinv[idx] = xv;
+        *reinterpret_cast<double2*>(R + idx) = make_double2(rv[0], rv[1]);
+        *reinterpret_cast<double2*>(Rinv + idx) = make_double2(xv[0], xv[1]);
     }
 }
 
