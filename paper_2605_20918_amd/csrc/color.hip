@@ -439,6 +439,37 @@ __global__ __launch_bounds__(256) void k_fp_sweep(int n, const int64_t* __restri
     if (lane == 0 && nchanged > 0) *changed = 1;
 }
 
+// Exclusive scan of the n cell counts into start[0 .. n] (start[n] = total) by one
+// work-group: each thread adds a contiguous segment, the segment sums are scanned in
+// LDS, then each thread writes its segment's prefixes.
+constexpr int kCellScanThreads = 256;
+__global__ __launch_bounds__(kCellScanThreads) void k_cell_scan(const int* __restrict__ count, int n,
+                                                                int* __restrict__ start) {
+    __shared__ int part[kCellScanThreads];
+    const int t = threadIdx.x;
+    const int per = (n + kCellScanThreads - 1) / kCellScanThreads;
+    const int a = min(n, t * per), e = min(n, a + per);
+    int sum = 0;
+    for (int c = a; c < e; ++c) sum += count[c];
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int q = 0; q < kCellScanThreads; ++q) {
+            const int v = part[q];
+            part[q] = run;
+            run += v;
+        }
+        start[n] = run;
+    }
+    __syncthreads();
+    int run = part[t];
+    for (int c = a; c < e; ++c) {
+        start[c] = run;
+        run += count[c];
+    }
+}
+
 __global__ void k_fill_int(int* __restrict__ p, int64_t cnt, int v) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < cnt) p[i] = v;
@@ -618,17 +649,7 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
     fill_launch<int>(w.cell_count, 0, ncell, s);
     fill_launch<int>(w.cell_fill, 0, ncell, s);
     k_bin<<<grid_for(n, 256), 256, 0, s>>>(xyz, n, g, w.cell_of, w.cell_count);
-    {
-        // cell_start = exclusive scan of cell_count (reuse the row-pointer scan on a temp view)
-        std::vector<int> hc(ncell);
-        CSS_HIP_TRY(hipMemcpyAsync(hc.data(), w.cell_count, sizeof(int) * ncell, hipMemcpyDeviceToHost, s));
-        CSS_HIP_TRY(hipStreamSynchronize(s));
-        std::vector<int> hs(ncell + 1);
-        hs[0] = 0;
-        for (int c = 0; c < ncell; ++c) hs[c + 1] = hs[c] + hc[c];
-        CSS_HIP_TRY(hipMemcpyAsync(w.cell_start, hs.data(), sizeof(int) * (ncell + 1), hipMemcpyHostToDevice, s));
-        CSS_HIP_TRY(hipStreamSynchronize(s));
-    }
+    k_cell_scan<<<1, kCellScanThreads, 0, s>>>(w.cell_count, ncell, w.cell_start);   // cell_start, on the device
     k_place<<<grid_for(n, 256), 256, 0, s>>>(n, w.cell_of, w.cell_start, w.cell_fill, w.cell_list);
 
     // degrees and row pointers
