@@ -659,20 +659,18 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
     k_scan_blocks<<<nblk, kScanBlock, 0, s>>>(w.deg, n, p_row_ptr, w.block_sum);
     k_scan_sums<<<1, kScanBlock, 0, s>>>(w.block_sum, nblk);
     k_scan_add<<<nblk, kScanBlock, 0, s>>>(p_row_ptr, n, w.block_sum);
+    // nnz, and the longest row (it must fit the LDS row sort), in one host round trip
+    fill_launch<int>(w.scalars, 0, 2, s);
+    k_max_color<<<64, 256, 0, s>>>(nullptr, n, w.scalars, w.scalars + 1, p_row_ptr);
     int64_t nnz = 0;
+    int hmax[2];
     CSS_HIP_TRY(hipMemcpyAsync(&nnz, p_row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CSS_HIP_TRY(hipMemcpyAsync(hmax, w.scalars, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     CSS_HIP_TRY(hipStreamSynchronize(s));
     const int64_t capacity = *p_nnz;
     *p_nnz = nnz;
     if (p_col == nullptr) return CSS_OK;                 // size query
     if (capacity < nnz) return CSS_E_CAPACITY;
-
-    // longest row must fit the LDS row sort
-    fill_launch<int>(w.scalars, 0, 2, s);
-    k_max_color<<<64, 256, 0, s>>>(nullptr, n, w.scalars, w.scalars + 1, p_row_ptr);
-    int hmax[2];
-    CSS_HIP_TRY(hipMemcpyAsync(hmax, w.scalars, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-    CSS_HIP_TRY(hipStreamSynchronize(s));
     if (hmax[1] > kMaxRowLds) return CSS_E_UNSUPPORTED;
 
     k_cell_pairs<false><<<ncell, kPairThreads, 0, s>>>(xyz, g, rc2, w.cell_start, w.cell_list, w.deg, p_row_ptr,
