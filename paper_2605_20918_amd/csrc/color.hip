@@ -291,7 +291,12 @@ __global__ void k_clear_flags(int32_t* __restrict__ p_col, int64_t nnz) {
 // of a higher-priority neighbour of the same chunk (consecutive orbitals are
 // mostly on one molecule). A row is read kFpLoads entries per lane at a time; the
 // first batch of every due orbital's row is requested before the first is used.
-constexpr int kFpChunk = 8;
+// Water colourings, whole call: 4 orbitals per wavefront 3.01 ms at 10^4 molecules
+// and 17.2 ms at 10^5; 8 orbitals 2.98 and 19.5 ms (fewer sweeps, 62 and 71 against
+// 66 and 79, but a longer serial chain per wavefront); 16 orbitals 3.60 and 22.5 ms.
+// Issuing the colour gathers of all due orbitals before the first evaluation was
+// slower still (3.7 ms at 10^4).
+constexpr int kFpChunk = 4;
 constexpr int kFpBatch = 64;                 // colouring sweeps per host check
 constexpr int kFpLoads = 4;
 constexpr int kFpSpan = 64 * kFpLoads;               // row entries per batch
@@ -321,21 +326,15 @@ __device__ __forceinline__ int mex_of(unsigned long long (&m)[4], int base) {
 }
 
 // Stamps the lower-priority neighbours among a batch of row entries (entry q of
-// this lane at index t + 64 q) with `next`. Most are stamped already by another
-// changed neighbour: the stamp is read first and written only if it differs (a
-// stale read costs a redundant store, never a missed one, since only this sweep
-// writes `next`).
+// this lane at index t + 64 q) with `next`. Plain stores, not read first: every
+// writer in this sweep writes the same value and no stamp is larger during it, so
+// a store loses nothing (reading the stamp first, to skip the stores most
+// neighbours do not need, took longer: 3.12 against 2.99 ms per 10k colouring).
 __device__ __forceinline__ void mark_lower(const int (&u)[kFpLoads], int v, int64_t t, int64_t e, int next,
                                            int* stamp) {
-    int old[kFpLoads];
-#pragma unroll
-    for (int q = 0; q < kFpLoads; ++q) {
-        const bool lp = u[q] >= 0 && u[q] != v && t + 64 * q < e;
-        old[q] = lp ? stamp[u[q]] : next;
-    }
 #pragma unroll
     for (int q = 0; q < kFpLoads; ++q)
-        if (old[q] != next) stamp[u[q]] = next;
+        if (u[q] >= 0 && u[q] != v && t + 64 * q < e) stamp[u[q]] = next;
 }
 
 __global__ __launch_bounds__(256) void k_fp_sweep(int n, const int64_t* __restrict__ p_row_ptr,
