@@ -291,11 +291,13 @@ __global__ void k_clear_flags(int32_t* __restrict__ p_col, int64_t nnz) {
 // of a higher-priority neighbour of the same chunk (consecutive orbitals are
 // mostly on one molecule). A row is read kFpLoads entries per lane at a time; the
 // first batch of every due orbital's row is requested before the first is used.
-// Water colourings, whole call: 4 orbitals per wavefront 3.01 ms at 10^4 molecules
-// and 17.2 ms at 10^5; 8 orbitals 2.98 and 19.5 ms (fewer sweeps, 62 and 71 against
-// 66 and 79, but a longer serial chain per wavefront); 16 orbitals 3.60 and 22.5 ms.
-// Issuing the colour gathers of all due orbitals before the first evaluation was
-// slower still (3.7 ms at 10^4).
+// Water colourings, whole call: 4 orbitals per wavefront 2.77 ms at 10^4 molecules
+// and 14.6 ms at 10^5; 8 orbitals 2.69 and 17.1 ms (fewer sweeps, 63 and 67 against
+// 66 and 80, but a longer serial chain per wavefront); 2 loads per lane instead of 4,
+// 2.87 and 15.2 ms. With the mex masks reduced by LDS lane permutes instead of the
+// VALU moves of wave_or: 3.16 and 17.1 ms; with stamps read before they are written
+// as well, and 8 orbitals, 3.12 and 21.1 ms. Issuing the colour gathers of all due
+// orbitals before the first evaluation was slower (3.7 ms at 10^4).
 constexpr int kFpChunk = 4;
 constexpr int kFpBatch = 64;                 // colouring sweeps per host check
 constexpr int kFpLoads = 4;
@@ -312,17 +314,40 @@ __device__ __forceinline__ void mex_mark(int cu, int base, unsigned long long (&
     m[3] |= word == 3 ? bit : 0ull;
 }
 
+// OR of x over the 64 lanes of the wavefront, in every lane, on VALU cross-lane
+// moves only: within each 16-lane row by DPP (swap neighbours, swap pairs, mirror
+// the half rows, mirror the rows), then across the four rows by the two lane-swap
+// instructions (the 32-lane swap pairs rows 0-2 and 1-3, the 16-lane swap 0-1 and 2-3).
+__device__ __forceinline__ unsigned wave_or(unsigned x) {
+    x |= static_cast<unsigned>(__builtin_amdgcn_mov_dpp(static_cast<int>(x), 0xB1, 0xf, 0xf, false));
+    x |= static_cast<unsigned>(__builtin_amdgcn_mov_dpp(static_cast<int>(x), 0x4E, 0xf, 0xf, false));
+    x |= static_cast<unsigned>(__builtin_amdgcn_mov_dpp(static_cast<int>(x), 0x141, 0xf, 0xf, false));
+    x |= static_cast<unsigned>(__builtin_amdgcn_mov_dpp(static_cast<int>(x), 0x140, 0xf, 0xf, false));
+    const auto h = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    x = static_cast<unsigned>(h[0]) | static_cast<unsigned>(h[1]);
+    const auto q = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return static_cast<unsigned>(q[0]) | static_cast<unsigned>(q[1]);
+}
+
 // Smallest colour >= base absent from the wave's masks (-1 if all 256 are present).
 __device__ __forceinline__ int mex_of(unsigned long long (&m)[4], int base) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int wd = 0; wd < 4; ++wd) m[wd] |= __shfl_xor(m[wd], off);
+    for (int wd = 0; wd < 4; ++wd)
+        m[wd] = static_cast<unsigned long long>(wave_or(static_cast<unsigned>(m[wd]))) |
+                static_cast<unsigned long long>(wave_or(static_cast<unsigned>(m[wd] >> 32))) << 32;
     if (~m[0]) return base + __builtin_ctzll(~m[0]);
     if (~m[1]) return base + 64 + __builtin_ctzll(~m[1]);
     if (~m[2]) return base + 128 + __builtin_ctzll(~m[2]);
     if (~m[3]) return base + 192 + __builtin_ctzll(~m[3]);
     return -1;
+}
+
+// v of lane `src` (uniform) in every lane
+__device__ __forceinline__ int lane_int(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+__device__ __forceinline__ int64_t lane_i64(int64_t v, int src) {
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(v & 0xffffffffLL), src));
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(v >> 32), src);
+    return static_cast<int64_t>((static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | lo);
 }
 
 // Stamps the lower-priority neighbours among a batch of row entries (entry q of
@@ -360,7 +385,7 @@ __global__ __launch_bounds__(256) void k_fp_sweep(int n, const int64_t* __restri
         int rank = 0;
 #pragma unroll
         for (int j = 0; j < kFpChunk; ++j) {
-            const int dj = __shfl(dl, j);
+            const int dj = lane_int(dl, j);
             rank += ((dm >> j) & 1) && (dj > dl || (dj == dl && j < lane));
         }
         const int ndue = __popcll(dm);
@@ -371,14 +396,14 @@ __global__ __launch_bounds__(256) void k_fp_sweep(int n, const int64_t* __restri
         for (int r = 0; r < kFpChunk; ++r) {
             const unsigned long long b = __ballot(due && rank == r);
             src[r] = b ? __builtin_ctzll(b) : 0;
-            const int64_t sr = __shfl(rs, src[r]), er = __shfl(re, src[r]);
+            const int64_t sr = lane_i64(rs, src[r]), er = lane_i64(re, src[r]);
 #pragma unroll
             for (int q = 0; q < kFpLoads; ++q) u[r][q] = p_col[min(sr + lane + 64 * q, er - 1)];
         }
         for (int r = 0; r < ndue; ++r) {
             const int v = static_cast<int>(v0) + src[0];
-            const int cur = __shfl(cl, src[0]);
-            const int64_t s = __shfl(rs, src[0]), e = __shfl(re, src[0]);
+            const int cur = lane_int(cl, src[0]);
+            const int64_t s = lane_i64(rs, src[0]), e = lane_i64(re, src[0]);
             int cu[kFpLoads];
 #pragma unroll
             for (int q = 0; q < kFpLoads; ++q) {
@@ -400,7 +425,7 @@ __global__ __launch_bounds__(256) void k_fp_sweep(int n, const int64_t* __restri
             }
             int chosen = mex_of(m, 0);
             // colours beyond 255: further windows over the whole row
-            for (int base = 256; chosen < 0; base += 256) {
+            for (int base = 256; chosen < 0 && base <= e - s; base += 256) {
                 unsigned long long mb[4] = {0ull, 0ull, 0ull, 0ull};
                 for (int64_t tb = s + lane; __ballot(tb < e); tb += kFpSpan) {
                     int w[kFpLoads], cw[kFpLoads];
@@ -413,6 +438,7 @@ __global__ __launch_bounds__(256) void k_fp_sweep(int n, const int64_t* __restri
                 }
                 chosen = mex_of(mb, base);
             }
+            chosen = chosen < 0 ? 0 : chosen;            // unreachable: the mex of L colours is <= L
             if (chosen != cur) {
                 if (lane == 0) color[v] = chosen;
                 ++nchanged;
