@@ -225,7 +225,52 @@ __global__ __launch_bounds__(kPairThreads) void k_cell_pairs(const double* __res
     }
 }
 
-// Sort each pattern row ascending by rank (entries are distinct).
+// Sort each pattern row ascending by rank (entries are distinct): one wavefront per
+// row, the row in a per-wavefront LDS slice of kSortWaveRow entries, each lane
+// placing its entries by counting the smaller ones. Used when every row fits; one
+// work-group per row with a kMaxRowLds slice otherwise (k_sort_rows). The row is
+// padded to 16 entries and compared 16 at a time from four 16-byte LDS reads in
+// flight. At 10^4 water molecules (60 000 rows of about 64 entries): 116 us, against
+// 185 us for the work-group-per-row sort (five 32 KB work-groups per compute unit)
+// and 247 us for this one comparing one entry per LDS read and wait.
+constexpr int kSortWaveRow = 512;
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256) void k_sort_rows_wave(int n, const int64_t* __restrict__ p_row_ptr,
+                                                        int32_t* __restrict__ p_col) {
+    static_assert(kSortWaveRow % 16 == 0, "rows are padded to 16 entries");
+    __shared__ int4 rows[4][kSortWaveRow / 4];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    int32_t* row = reinterpret_cast<int32_t*>(rows[w]);
+    for (int m = blockIdx.x * 4 + w; m < n; m += gridDim.x * 4) {
+        const int64_t s = p_row_ptr[m];
+        // <= kSortWaveRow (checked by the host); the padding INT_MAX is never smaller
+        // than an entry (entries are column indices below n)
+        const int len = __builtin_amdgcn_readfirstlane(static_cast<int>(p_row_ptr[m + 1] - s));
+        const int len16 = (len + 15) & ~15;
+        for (int i = lane; i < len16; i += 64) row[i] = i < len ? p_col[s + i] : INT_MAX;
+        wave_sync_lds();
+        for (int i = lane; i < len; i += 64) {
+            const int32_t x = row[i];
+            int r = 0;
+            for (int k = 0; k < len16 / 4; k += 4) {        // 16 entries, four 16-byte reads in flight
+                const int4 a = rows[w][k], b = rows[w][k + 1], c = rows[w][k + 2], d = rows[w][k + 3];
+                r += (a.x < x) + (a.y < x) + (a.z < x) + (a.w < x) + (b.x < x) + (b.y < x) + (b.z < x) +
+                     (b.w < x) + (c.x < x) + (c.y < x) + (c.z < x) + (c.w < x) + (d.x < x) + (d.y < x) +
+                     (d.z < x) + (d.w < x);
+            }
+            p_col[s + r] = x;
+        }
+        wave_sync_lds();                                                // row[] is reused for the next row
+    }
+}
+
 __global__ void k_sort_rows(int n, const int64_t* __restrict__ p_row_ptr, int32_t* __restrict__ p_col) {
     __shared__ int32_t row[kMaxRowLds];
     int m = blockIdx.x;
@@ -700,7 +745,11 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
 
     k_cell_pairs<false><<<ncell, kPairThreads, 0, s>>>(xyz, g, rc2, w.cell_start, w.cell_list, w.deg, p_row_ptr,
                                                        p_col);
-    k_sort_rows<<<n, 256, 0, s>>>(n, p_row_ptr, p_col);
+    if (hmax[1] <= kSortWaveRow)
+        k_sort_rows_wave<<<static_cast<unsigned>(std::min<int64_t>(8192, (n + 3) / 4)), 256, 0, s>>>(n, p_row_ptr,
+                                                                                                    p_col);
+    else
+        k_sort_rows<<<n, 256, 0, s>>>(n, p_row_ptr, p_col);
 
     // fixed-point sweeps, kFpBatch per host check of the change counters; a sweep after
     // one that changed nothing returns at once, so a batch costs one host round trip

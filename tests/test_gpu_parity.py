@@ -97,6 +97,19 @@ def test_colour_large_frontiers_bitexact():
     assert r1 == r2
 
 
+def test_colour_long_rows_bitexact():
+    """Rows longer than the per-wavefront row sort takes (512 entries), so the
+    work-group-per-row sort runs, and more than 256 colours, so the mex looks past
+    its first 256-colour window: a complete graph on 700 centres, and a dense
+    cluster of 600 beside 400 sparse centres (rows of about 600 and of a few)."""
+    rng = np.random.default_rng(13)
+    _colour_case(rng.uniform(0, 1, size=(700, 3)), np.zeros(3), 10.0)
+    dense = rng.uniform(0, 1, size=(600, 3))
+    sparse = rng.uniform(0, 40, size=(400, 3)) + 5.0
+    xyz = np.concatenate([dense, sparse])[rng.permutation(1000)]
+    _colour_case(xyz, np.zeros(3), 2.0)
+
+
 # ---------------------------------------------------------------- probes
 
 @pytest.mark.parametrize("ones", [False, True])
