@@ -341,8 +341,9 @@ __global__ void k_clear_flags(int32_t* __restrict__ p_col, int64_t nnz) {
 // 66 and 80, but a longer serial chain per wavefront); 2 loads per lane instead of 4,
 // 2.87 and 15.2 ms. With the mex masks reduced by LDS lane permutes instead of the
 // VALU moves of wave_or: 3.16 and 17.1 ms; with stamps read before they are written
-// as well, and 8 orbitals, 3.12 and 21.1 ms. Issuing the colour gathers of all due
-// orbitals before the first evaluation was slower (3.7 ms at 10^4).
+// as well, and 8 orbitals, 3.12 and 21.1 ms. Issuing the colour gathers of the due
+// orbitals' first 64 entries before the first evaluation was slower: 3.45 against
+// 2.41 ms at 10^4 (80 sweeps per host check), more sweeps and dearer ones.
 constexpr int kFpChunk = 4;
 // Colouring sweeps per host check. A call whose sweeps run past a batch pays for
 // a whole further batch (launches that return at once, one more host round trip):
