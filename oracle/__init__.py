@@ -1,8 +1,8 @@
 """Plain FP64 CPU oracle of the CSS density-matrix path. TEST INFRASTRUCTURE.
 
 This package is the slow, obviously correct reference that the GPU library is
-checked against. Only the test suite, the smoke check of the graft entry point
-and the CPU-baseline leg of the benchmark may import or run it; the product
+checked against. Only the test suite, smoke() in __graft_entry__.py and the
+CPU-baseline leg of the benchmark may import or run it; the product
 path (the HIP library and its Python binding) never does, and shares no code
 with it. It is written from the paper (arXiv 2605.20918): every function cites
 the equation or passage it follows and states the readings taken where the
