@@ -336,14 +336,15 @@ __global__ void k_clear_flags(int32_t* __restrict__ p_col, int64_t nnz) {
 // of a higher-priority neighbour of the same chunk (consecutive orbitals are
 // mostly on one molecule). A row is read kFpLoads entries per lane at a time; the
 // first batch of every due orbital's row is requested before the first is used.
-// Water colourings, whole call: 4 orbitals per wavefront 2.77 ms at 10^4 molecules
-// and 14.6 ms at 10^5; 8 orbitals 2.69 and 17.1 ms (fewer sweeps, 63 and 67 against
-// 66 and 80, but a longer serial chain per wavefront); 2 loads per lane instead of 4,
-// 2.87 and 15.2 ms. With the mex masks reduced by LDS lane permutes instead of the
-// VALU moves of wave_or: 3.16 and 17.1 ms; with stamps read before they are written
-// as well, and 8 orbitals, 3.12 and 21.1 ms. Issuing the colour gathers of the due
-// orbitals' first 64 entries before the first evaluation was slower: 3.45 against
-// 2.41 ms at 10^4 (80 sweeps per host check), more sweeps and dearer ones.
+// Water colourings, whole call, 64 sweeps per host check: 4 orbitals per
+// wavefront 2.77 ms at 10^4 molecules and 14.6 ms at 10^5; 8 orbitals 2.69 and
+// 17.1 ms (fewer sweeps, 63 and 67 against 66 and 80, but a longer serial chain per
+// wavefront); 2 loads per lane instead of 4, 2.87 and 15.2 ms. With the mex masks
+// reduced by LDS lane permutes instead of the VALU moves of wave_or: 3.16 and
+// 17.1 ms; with stamps read before they are written as well, and 8 orbitals, 3.12
+// and 21.1 ms. Issuing the colour gathers of the due orbitals' first 64 entries
+// before the first evaluation was slower: 3.45 against 2.41 ms at 10^4 (80 sweeps
+// per host check), more sweeps and dearer ones.
 constexpr int kFpChunk = 4;
 // Colouring sweeps per host check. A call whose sweeps run past a batch pays for
 // a whole further batch (launches that return at once, one more host round trip):
