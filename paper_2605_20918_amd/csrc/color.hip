@@ -235,10 +235,12 @@ __global__ __launch_bounds__(kPairThreads) void k_cell_pairs(const double* __res
 // and 247 us for this one comparing one entry per LDS read and wait.
 constexpr int kSortWaveRow = 512;
 
+// Orders the wavefront's LDS accesses across its lanes (fences on LDS only: a
+// wavefront-scope release on all memory would also wait for its global stores).
 __device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
 __global__ __launch_bounds__(256) void k_sort_rows_wave(int n, const int64_t* __restrict__ p_row_ptr,
