@@ -137,9 +137,17 @@ __device__ __forceinline__ double min_image(double dk, double L, double invL) {
 // staged through LDS kCandChunk at a time, the four wavefronts taking every
 // fourth candidate (a broadcast read). Every conflict decision is the plain
 // ((dx*dx + dy*dy) + dz*dz) <= r_cut^2, products and sums rounded separately.
-// COUNT = true: deg[m] = number of conflicting partners (self excluded).
+// COUNT = true: deg[m] = number of conflicting partners (self excluded), and, when
+// rows_tmp is given, the row (self included, unsorted) in the first kRowTmp slots of
+// rows_tmp[m kRowTmp ..]; when every row fits there, the second pass is not run and
+// the sort reads the rows from rows_tmp (water at r_cut = 6 A: rows of 169 entries
+// on average and at most 206 at 10^4 molecules, where the two passes took 214 +
+// 226 us). The slots are kept for up to kRowTmpMaxN orbitals (1 GB), so larger
+// systems take the second pass and no more memory.
 // COUNT = false: write the row (self included) at p_col[p_row_ptr[m] ...] unsorted.
 constexpr int kPairThreads = 256;
+constexpr int kRowTmp = 256;
+constexpr int kRowTmpMaxN = 1 << 20;
 constexpr int kCandChunk = 1024;
 
 template <bool COUNT>
@@ -147,7 +155,7 @@ __global__ __launch_bounds__(kPairThreads) void k_cell_pairs(const double* __res
                                                              const int* __restrict__ cell_start,
                                                              const int* __restrict__ cell_list, int* __restrict__ deg,
                                                              const int64_t* __restrict__ p_row_ptr,
-                                                             int32_t* __restrict__ p_col) {
+                                                             int32_t* __restrict__ p_col, int32_t* __restrict__ rows_tmp) {
 #pragma clang fp contract(off)
     __shared__ double sx[kCandChunk], sy[kCandChunk], sz[kCandChunk];
     __shared__ int sid[kCandChunk];
@@ -216,6 +224,7 @@ __global__ __launch_bounds__(kPairThreads) void k_cell_pairs(const double* __res
                     if (hit) {
                         const int slot = atomicAdd(&cnt[lane], 1);
                         if (!COUNT) p_col[rbase + slot] = nb;
+                        else if (rows_tmp && slot < kRowTmp) rows_tmp[(int64_t)m * kRowTmp + slot] = nb;
                     }
                 }
         }
@@ -244,7 +253,9 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 __global__ __launch_bounds__(256) void k_sort_rows_wave(int n, const int64_t* __restrict__ p_row_ptr,
-                                                        int32_t* __restrict__ p_col) {
+                                                        const int32_t* __restrict__ rows_tmp, int32_t* __restrict__ p_col) {
+    // rows_tmp: the rows in slots of kRowTmp per orbital (every row fits, checked by the
+    // host), or nullptr: the rows are read from p_col in place
     static_assert(kSortWaveRow % 16 == 0, "rows are padded to 16 entries");
     __shared__ int4 rows[4][kSortWaveRow / 4];
     const int lane = threadIdx.x & 63;
@@ -256,7 +267,8 @@ __global__ __launch_bounds__(256) void k_sort_rows_wave(int n, const int64_t* __
         // than an entry (entries are column indices below n)
         const int len = __builtin_amdgcn_readfirstlane(static_cast<int>(p_row_ptr[m + 1] - s));
         const int len16 = (len + 15) & ~15;
-        for (int i = lane; i < len16; i += 64) row[i] = i < len ? p_col[s + i] : INT_MAX;
+        const int32_t* src = rows_tmp ? rows_tmp + (int64_t)m * kRowTmp : p_col + s;
+        for (int i = lane; i < len16; i += 64) row[i] = i < len ? src[i] : INT_MAX;
         wave_sync_lds();
         for (int i = lane; i < len; i += 64) {
             const int32_t x = row[i];
@@ -652,6 +664,7 @@ Grid make_grid(int n, const double box[3], double r_cut, const double bb[6]) {
 
 struct ColorWs {
     int *cell_of, *cell_count, *cell_start, *cell_fill, *cell_list, *deg, *scalars, *stamp;
+    int32_t* rows_tmp;
     int64_t* block_sum;
     double *bbox, *bbox_part;
 };
@@ -666,6 +679,7 @@ ColorWs carve_color(Arena& a, int n) {
     w.cell_list = a.take<int>(n);
     w.deg = a.take<int>(n);
     w.stamp = a.take<int>(n);
+    w.rows_tmp = n <= kRowTmpMaxN ? a.take<int32_t>(static_cast<size_t>(n) * kRowTmp) : nullptr;
     w.scalars = a.take<int>(16 + kFpBatch);
     w.block_sum = a.take<int64_t>((n + kScanBlock - 1) / kScanBlock + 1);
     w.bbox = a.take<double>(8);
@@ -732,7 +746,7 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
 
     // degrees and row pointers
     k_cell_pairs<true><<<ncell, kPairThreads, 0, s>>>(xyz, g, rc2, w.cell_start, w.cell_list, w.deg, nullptr,
-                                                      nullptr);
+                                                      nullptr, n <= kRowTmpMaxN ? w.rows_tmp : nullptr);
     const int nblk = (n + kScanBlock - 1) / kScanBlock;
     k_scan_blocks<<<nblk, kScanBlock, 0, s>>>(w.deg, n, p_row_ptr, w.block_sum);
     k_scan_sums<<<1, kScanBlock, 0, s>>>(w.block_sum, nblk);
@@ -751,11 +765,15 @@ extern "C" css_status css_color(const double* xyz, int32_t n, const double box[3
     if (capacity < nnz) return CSS_E_CAPACITY;
     if (hmax[1] > kMaxRowLds) return CSS_E_UNSUPPORTED;
 
-    k_cell_pairs<false><<<ncell, kPairThreads, 0, s>>>(xyz, g, rc2, w.cell_start, w.cell_list, w.deg, p_row_ptr,
-                                                       p_col);
+    // rows (self included) of at most kRowTmp entries are already in rows_tmp
+    const bool rows_kept = n <= kRowTmpMaxN && hmax[1] <= kRowTmp;
+    if (!rows_kept)
+        k_cell_pairs<false><<<ncell, kPairThreads, 0, s>>>(xyz, g, rc2, w.cell_start, w.cell_list, w.deg, p_row_ptr,
+                                                           p_col, nullptr);
+    static_assert(kRowTmp <= kSortWaveRow, "kept rows go through the wavefront sort");
     if (hmax[1] <= kSortWaveRow)
-        k_sort_rows_wave<<<static_cast<unsigned>(std::min<int64_t>(8192, (n + 3) / 4)), 256, 0, s>>>(n, p_row_ptr,
-                                                                                                    p_col);
+        k_sort_rows_wave<<<static_cast<unsigned>(std::min<int64_t>(8192, (n + 3) / 4)), 256, 0, s>>>(
+            n, p_row_ptr, rows_kept ? w.rows_tmp : nullptr, p_col);
     else
         k_sort_rows<<<n, 256, 0, s>>>(n, p_row_ptr, p_col);
 
