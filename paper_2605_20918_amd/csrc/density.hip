@@ -455,24 +455,52 @@ __global__ __launch_bounds__(256) void k_gather(int n, const int64_t* __restrict
 }
 
 // One wavefront per row: sum over H entries present in the pattern of H_mn P_mn.
+// The pattern row is staged in a per-wavefront LDS slice when it has at most
+// kEnergyLds entries, so each lane's binary search reads LDS instead of making a
+// chain of dependent global loads (found positions and the order of the sums are
+// the same either way).
+constexpr int kEnergyLds = 512;
+
 template <typename V>
 __global__ __launch_bounds__(256) void k_energy(int n, const int32_t* __restrict__ hrp, const int32_t* __restrict__ hcol,
                                                 const V* __restrict__ hval, const int64_t* __restrict__ prp,
                                                 const int32_t* __restrict__ pcol, const double* __restrict__ pval,
                                                 double* __restrict__ row_e) {
+    __shared__ int32_t prow_lds[4][kEnergyLds];
     const int lane = threadIdx.x & 63;
-    const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int64_t m = (int64_t)blockIdx.x * 4 + w;
     if (m >= n) return;
     const int64_t ps = prp[m], pe = prp[m + 1];
+    const bool staged = pe - ps <= kEnergyLds;                      // uniform over the wavefront
+    int32_t* prow = prow_lds[w];
+    if (staged) {
+        for (int64_t i = lane; i < pe - ps; i += 64) prow[i] = pcol[ps + i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    }
     double e = 0.0;
     for (int32_t t = hrp[m] + lane; t < hrp[m + 1]; t += 64) {
         const int nn = hcol[t];
         int64_t lo = ps, hi = pe;          // binary search nn in the sorted pattern row
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (pcol[mid] < nn) lo = mid + 1; else hi = mid;
+        bool hit;
+        if (staged) {
+            int a = 0, b = static_cast<int>(pe - ps);
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (prow[mid] < nn) a = mid + 1; else b = mid;
+            }
+            lo = ps + a;
+            hit = lo < pe && prow[a] == nn;
+        } else {
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (pcol[mid] < nn) lo = mid + 1; else hi = mid;
+            }
+            hit = lo < pe && pcol[lo] == nn;
         }
-        if (lo < pe && pcol[lo] == nn) e += (double)hval[t] * pval[lo];
+        if (hit) e += (double)hval[t] * pval[lo];
     }
     for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
     if (lane == 0) row_e[m] = e;
